@@ -1,0 +1,153 @@
+/*
+ * kmx -- weighted k-means++ seeding and Lloyd iterations on one AMD Instinct
+ * MI355X (gfx950).  Plain C ABI: every array argument is a raw pointer, every
+ * size a plain integer; no C++ or framework types cross this boundary.
+ *
+ * The problem (Sec. 1, definition of k-means; Sec. 1, coreset cost): given n
+ * points x_i in R^d with weights w_i >= 0 and k centers c_j, the cost is
+ *     cost(C) = sum_i w_i * min_j ||x_i - c_j||^2 .
+ * Lloyd's algorithm (Sec. 1) alternates assignment to the closest center and
+ * replacement of each center by the weighted centroid of its points (Sec. 2,
+ * centroid; Sec. 2.1, clustering feature (W, S, Q) = (sum w, sum w x,
+ * sum w x^T x)).  k-means++ (Sec. 1) draws the first center by weight and each
+ * further center with probability proportional to w_i * D2_i, D2_i being the
+ * squared distance to the closest center chosen so far; Sec. 2.2 runs it on
+ * the weighted summary.
+ *
+ * Conventions shared by all calls
+ *   - X is row-major n x d float32 with leading dimension ldx >= d (elements);
+ *     C arrays are row-major k x d float32 with leading dimension d.
+ *   - Array arguments are DEVICE pointers on the context's device, owned by
+ *     the caller, unless marked "host".  Host scalar outputs are written after
+ *     the call synchronizes the context's stream; every other call is
+ *     stream-ordered and asynchronous (results valid once the stream reaches
+ *     that point).
+ *   - w may be NULL (all weights 1).  Weights must be finite and >= 0.
+ *   - Ties in the argmin go to the lowest center index.  An empty cluster
+ *     keeps its previous center.
+ *   - Return codes only; nothing throws or aborts across the ABI.  On failure
+ *     kmx_last_error() describes the cause.  Argument checks run before any
+ *     work is enqueued, so a KMX_EINVAL call leaves outputs untouched.
+ *   - Calls on one context are not thread-safe; use one context per thread.
+ */
+#ifndef KMX_H
+#define KMX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct kmx_ctx kmx_ctx;
+
+typedef enum {
+  KMX_OK = 0,
+  KMX_EINVAL = 1,       /* bad argument (null pointer, size, range)          */
+  KMX_ENOMEM = 2,       /* device workspace allocation failed                */
+  KMX_EDEVICE = 3,      /* a HIP runtime call or kernel launch failed        */
+  KMX_EUNSUPPORTED = 4  /* valid request outside what this build implements  */
+} kmx_status;
+
+/* Arithmetic of the distance GEMM inside assignment.  Labels are exact for
+ * every precision: rows whose top-2 margin lies inside the rigorous error
+ * bound of the chosen precision are re-checked with compensated FP32
+ * direct differences.  Centroid and cost accumulation is always FP64. */
+typedef enum {
+  KMX_FP32 = 0,   /* FP32 MFMA, FP32 accumulate                              */
+  KMX_BF16 = 1    /* BF16 inputs (round to nearest even), FP32 accumulate    */
+} kmx_prec;
+
+/* Context: binds a device and a HIP stream (hip_stream == NULL: the null
+ * stream).  Owns a grow-only device workspace freed by kmx_destroy.  A
+ * quantized copy of X is cached per (pointer, n, d, ldx, precision) until
+ * kmx_invalidate is called for that pointer or a different X is used. */
+kmx_status kmx_create(kmx_ctx** out, int device, void* hip_stream);
+kmx_status kmx_destroy(kmx_ctx* ctx);
+kmx_status kmx_set_stream(kmx_ctx* ctx, void* hip_stream);
+/* Drop cached derived data of X (call after X's contents change). */
+kmx_status kmx_invalidate(kmx_ctx* ctx, const float* X);
+/* Message of the last failed call on ctx ("" if none).  Valid until the next
+ * call on ctx.  kmx_last_error(NULL) reports failures of kmx_create. */
+const char* kmx_last_error(const kmx_ctx* ctx);
+
+/* Weighted k-means++ seeding (Sec. 1 k-means++; Sec. 2.2 on the weighted
+ * summary).  Round 0 draws i_0 with probability w_i / sum w; round r >= 1
+ * draws i_r with probability w_i D2_i / sum_j w_j D2_j, where D2 is the FP64
+ * squared distance to the closest chosen center.  If that mass is zero, round
+ * r draws by weight among rows not chosen yet.  The draws are inverse-CDF
+ * picks (first index whose inclusive prefix strictly exceeds u_r * total)
+ * with u_r = (z_r >> 11) * 2^-53, z_r the r-th SplitMix64 output for state
+ * rng_seed.
+ *   C_out   device, k x d float32: exact copies of the chosen rows.
+ *   idx_out device, k int64, nullable: the chosen row indices.
+ * Requires 1 <= k <= n.  Rows with w_i = 0 are never chosen while rows with
+ * positive weight remain. */
+kmx_status kmx_seed(kmx_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
+                    const float* w, int32_t k, uint64_t rng_seed,
+                    float* C_out, int64_t* idx_out);
+
+/* Assignment step (Sec. 1): label_i = argmin_j ||x_i - c_j||^2, lowest j on
+ * ties.  The distance GEMM runs in `prec`; flagged rows are re-checked.
+ *   label_out device, n int32.
+ *   d1_out    device, n float32, nullable: distance to the assigned center.
+ *   d2_out    device, n float32, nullable: second smallest distance as
+ *             evaluated by the GEMM (within the GEMM's error bound; +inf if
+ *             k == 1).
+ *   n_flagged host, nullable: rows that needed the re-check (synchronizes).
+ */
+kmx_status kmx_assign(kmx_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
+                      const float* C, int32_t k, kmx_prec prec,
+                      int32_t* label_out, float* d1_out, float* d2_out,
+                      int64_t* n_flagged);
+
+/* Update step (Sec. 1; Sec. 2 centroid; Sec. 2.1 clustering features).  For
+ * each j: W_j = sum w_i, S_j = sum w_i x_i over label_i == j, in FP64;
+ * C_out[j] = float32(S_j / W_j) if W_j > 0 else C_prev[j].  C_out may equal
+ * C_prev.  Labels must lie in [0, k).
+ *   W_out             device, k float64, nullable.
+ *   cost_at_centroids host, nullable: sum_j (Q_j - ||S_j||^2 / W_j), the cost
+ *                     of this partition against its own centroids
+ *                     (synchronizes). */
+kmx_status kmx_update(kmx_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
+                      const float* w, const int32_t* label, int32_t k,
+                      const float* C_prev, float* C_out, double* W_out,
+                      double* cost_at_centroids);
+
+/* Weighted cost sum_i w_i min_j ||x_i - c_j||^2 in FP64 (Sec. 1), evaluated
+ * through the clustering-feature identity of Sec. 2.1 over the exact
+ * assignment:  sum_j Q_j - 2 c_j . S_j + W_j ||c_j||^2.  Synchronizes. */
+kmx_status kmx_cost(kmx_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
+                    const float* w, const float* C, int32_t k, kmx_prec prec,
+                    double* cost_out);
+
+/* Lloyd's algorithm (Sec. 1 and its footnote on stopping).  Iteration t
+ * assigns against C_t, records cost_hist[t] = cost(C_t) and replaces the
+ * centers by the weighted centroids.  tol < 0: exactly max_iter iterations.
+ * tol >= 0: stop after iteration t >= 1 when no label changed or when
+ * cost_hist[t-1] - cost_hist[t] <= tol * cost_hist[t-1].  One final
+ * assignment gives cost_hist[iters] = cost(C_iters) and the labels.
+ *   C_inout   device, k x d float32: C_0 in, C_iters out.
+ *   label_out device, n int32, nullable: labels against C_iters.
+ *   cost_hist host, max_iter + 1 doubles (entries past iters untouched).
+ *   iters_done host: number of update steps performed.
+ * Synchronizes once at the end. */
+kmx_status kmx_lloyd(kmx_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
+                     const float* w, float* C_inout, int32_t k, int32_t max_iter,
+                     double tol, kmx_prec prec, int32_t* label_out,
+                     double* cost_hist, int32_t* iters_done);
+
+/* Kernel timing for measurement: while enabled, HIP events bracket every
+ * kernel class on the context's stream.  kmx_timing_read returns the summed
+ * milliseconds and launch counts per class since the last reset:
+ *   class 0 prep (row statistics, quantization), 1 assign GEMM, 2 re-check,
+ *   3 label sort, 4 segmented reduction, 5 finalize, 6 seeding, 7 other.
+ * ms_out and count_out are host arrays of length n_classes (<= 8).
+ * Reading synchronizes.  enable = 0 stops recording; reset clears sums. */
+kmx_status kmx_timing(kmx_ctx* ctx, int enable, int reset);
+kmx_status kmx_timing_read(kmx_ctx* ctx, int n_classes, double* ms_out, int64_t* count_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KMX_H */

@@ -1,0 +1,205 @@
+// Weighted k-means++ seeding (Sec. 1: first center uniformly at random, each
+// further center with probability proportional to the squared distance to the
+// closest chosen center; Sec. 2.2: run on the weighted summary, a weight-w
+// point standing for w copies as in Sec. 2.3.1).
+//
+// One launch per round r.  Every block streams its rows of X once: for r >= 1
+// it lowers D2_i to ||x_i - c_{r-1}||^2 (FP64 direct differences of the FP32
+// inputs, exact up to the final sums) and writes the FP64 block sum of
+// w_i * D2_i (r = 0: of w_i).  The last block to finish (atomic ticket) draws
+// u_r from SplitMix64, finds the first block whose inclusive prefix of block
+// sums strictly exceeds u_r * M, then the first row inside it, copies that row
+// into C and marks it chosen.  If the mass M is zero it draws by weight among
+// the rows not chosen yet.
+#include "kmx_device.h"
+#include "kmx_internal.h"
+
+namespace kmx {
+
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t r) {
+  // state after r + 1 increments of the golden-ratio constant, then the mix
+  uint64_t z = seed + (r + 1ull) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Inclusive scan of doubles over the 256 threads of a block (fixed order).
+// Uses sh[0..3]; contains barriers, so every thread must call it.
+__device__ double block_incl_scan_256(double v, double* sh) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  double x = v;
+#pragma unroll
+  for (int m = 1; m < 64; m <<= 1) {
+    const double y = __shfl_up(x, m, 64);
+    if (lane >= m) x += y;
+  }
+  if (lane == 63) sh[w] = x;
+  __syncthreads();
+  double add = 0.0;
+  for (int q = 0; q < w; ++q) add += sh[q];
+  __syncthreads();
+  return add + x;
+}
+
+// Sum over the 256 threads of a block in a fixed order.  Uses sh[0..3].
+__device__ double block_sum_256(double v, double* sh) {
+  v = wave_sum_f64(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  const double r = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+  __syncthreads();
+  return r;
+}
+
+// First i in [lo, hi) whose inclusive prefix of mass(.) strictly exceeds
+// target (prefixes scanned 256 entries at a time).  If rounding leaves no such
+// i, the last i with positive mass; if there is none, -1.  *excl receives the
+// exclusive prefix at the returned index when it was a strict hit.
+// Uses sh[0..7]; every thread must call it.
+template <typename F>
+__device__ int64_t pick_linear(int64_t lo, int64_t hi, double target, F mass, double* sh,
+                               unsigned long long* red, double* excl) {
+  double carry = 0.0;
+  if (threadIdx.x == 0) {
+    red[0] = ~0ull;
+    red[1] = 0ull;
+  }
+  __syncthreads();
+  for (int64_t s = lo; s < hi; s += 256) {
+    const int64_t i = s + threadIdx.x;
+    const double v = (i < hi) ? mass(i) : 0.0;
+    const double inc = block_incl_scan_256(v, sh) + carry;
+    if (i < hi && inc > target) atomicMin(&red[0], (unsigned long long)i);
+    if (i < hi && v > 0.0) atomicMax(&red[1], (unsigned long long)(i + 1));
+    if (threadIdx.x == 255) sh[4] = inc;
+    __syncthreads();
+    const unsigned long long f = red[0];
+    if (f != ~0ull && (int64_t)f == i) sh[5] = inc - v;
+    carry = sh[4];
+    __syncthreads();
+    if (f != ~0ull) {
+      if (excl) *excl = sh[5];
+      __syncthreads();
+      return (int64_t)f;
+    }
+  }
+  return (int64_t)red[1] - 1;
+}
+
+__global__ __launch_bounds__(256) void seed_round_kernel(
+    const float* __restrict__ X, int64_t n, int d, int64_t ldx, const float* __restrict__ w,
+    int r, uint64_t seed, double* __restrict__ D2, uint8_t* __restrict__ chosen,
+    double* __restrict__ part, unsigned int* __restrict__ ctr, float* __restrict__ C,
+    int64_t* __restrict__ idx_out) {
+  __shared__ double sh[8];
+  __shared__ unsigned long long red[2];
+  __shared__ unsigned int ticket;
+  const int nb = gridDim.x;
+  const int b = blockIdx.x;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t r0 = (int64_t)b * kSeedRows;
+  const int64_t r1 = min(n, r0 + kSeedRows);
+
+  // ---- 1. lower D2 against the previous center; block mass ----
+  double macc = 0.0;
+  if (r == 0) {
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += 256) macc += w ? (double)w[i] : 1.0;
+  } else {
+    const float* c = C + (int64_t)(r - 1) * d;
+    for (int64_t i = r0 + wv; i < r1; i += 4) {
+      const float* x = X + i * ldx;
+      double acc = 0.0;
+      for (int q = lane; q < d; q += 64) {
+        const double df = (double)x[q] - (double)c[q];
+        acc = fma(df, df, acc);
+      }
+      acc = wave_sum_f64(acc);
+      const double dv = (r == 1) ? acc : fmin(D2[i], acc);
+      if (lane == 0) {
+        D2[i] = dv;
+        macc += w ? (double)w[i] * dv : dv;
+      }
+    }
+  }
+  const double bsum = block_sum_256(macc, sh);
+  if (threadIdx.x == 0) {
+    part[b] = bsum;
+    __threadfence();
+    ticket = atomicAdd(ctr, 1u);
+  }
+  __syncthreads();
+  if (ticket != (unsigned)(nb - 1)) return;
+
+  // ---- 2. the last block draws the row ----
+  __threadfence();
+  const volatile double* pv = part;
+  const uint64_t z = splitmix64_at(seed, (uint64_t)r);
+  const double u = (double)(z >> 11) * 0x1.0p-53;
+  double t = 0.0;
+  for (int q = threadIdx.x; q < nb; q += 256) t += pv[q];
+  const double M = block_sum_256(t, sh);
+  int64_t pick = -1;
+  if (M > 0.0) {
+    const double target = u * M;
+    double before = 0.0;
+    int64_t qb = pick_linear(0, nb, target, [&](int64_t q) { return pv[q]; }, sh, red, &before);
+    if (qb >= 0) {
+      const int64_t b0 = qb * kSeedRows;
+      const int64_t b1 = min(n, b0 + kSeedRows);
+      const double tin = target - before;
+      if (r == 0) {
+        pick = pick_linear(b0, b1, tin, [&](int64_t i) { return w ? (double)w[i] : 1.0; }, sh,
+                           red, nullptr);
+      } else {
+        pick = pick_linear(b0, b1, tin,
+                           [&](int64_t i) { return (w ? (double)w[i] : 1.0) * D2[i]; }, sh,
+                           red, nullptr);
+      }
+    }
+  }
+  if (pick < 0) {
+    // zero mass: draw by weight among the rows not chosen yet
+    double tt = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256)
+      tt += chosen[i] ? 0.0 : (w ? (double)w[i] : 1.0);
+    const double M2 = block_sum_256(tt, sh);
+    if (M2 > 0.0) {
+      pick = pick_linear(0, n, u * M2,
+                         [&](int64_t i) { return chosen[i] ? 0.0 : (w ? (double)w[i] : 1.0); },
+                         sh, red, nullptr);
+    }
+    if (pick < 0) {
+      // no positive weight left: the first row not chosen yet (else row 0)
+      if (threadIdx.x == 0) red[0] = ~0ull;
+      __syncthreads();
+      for (int64_t i = threadIdx.x; i < n; i += 256)
+        if (!chosen[i]) atomicMin(&red[0], (unsigned long long)i);
+      __syncthreads();
+      const unsigned long long f = red[0];
+      pick = (f == ~0ull) ? 0 : (int64_t)f;
+    }
+  }
+  __syncthreads();
+  // ---- 3. write the center (an exact copy of the row) ----
+  const float* xs = X + pick * ldx;
+  float* cr = C + (int64_t)r * d;
+  for (int q = threadIdx.x; q < d; q += 256) cr[q] = xs[q];
+  if (threadIdx.x == 0) {
+    chosen[pick] = 1;
+    if (idx_out) idx_out[r] = pick;
+    *ctr = 0u;
+  }
+}
+
+hipError_t launch_seed_round(hipStream_t s, const float* X, int64_t n, int d, int64_t ldx,
+                             const float* w, int r, uint64_t seed, double* D2, uint8_t* chosen,
+                             double* part, unsigned int* ctr, float* C_out, int64_t* idx_out) {
+  const int nb = (int)((n + kSeedRows - 1) / kSeedRows);
+  hipLaunchKernelGGL(seed_round_kernel, dim3(nb), dim3(256), 0, s, X, n, d, ldx, w, r, seed, D2,
+                     chosen, part, ctr, C_out, idx_out);
+  return hipGetLastError();
+}
+
+}  // namespace kmx

@@ -1,0 +1,457 @@
+// Update step of Lloyd's algorithm (Sec. 1: replace each center by the
+// centroid of its subset) as a deterministic, HBM-bound segmented reduction.
+//
+// For every cluster j the kernels form the weighted clustering feature of
+// Sec. 2.1 / Sec. 2.3.1: W_j = sum w_i, S_j = sum w_i x_i, Q_j = sum w_i ||x_i||^2
+// in FP64 (w_i x_i is exact in FP64).  The cost of the partition against any
+// center c follows from the identity of Sec. 2.1:
+//     sum_{i in P_j} w_i ||x_i - c||^2 = Q_j - 2 c.S_j + W_j ||c||^2 .
+//
+// Mechanism: a stable counting sort of row ids by label (block histograms,
+// column scans, in-block ranks from a 64-lane comparison), then one workgroup
+// per chunk of at most kReduceRows rows of one cluster gathers whole rows
+// (coalesced) and accumulates FP64 partial features, and one workgroup per
+// cluster sums its chunks in chunk order.  Every sum has a fixed order, so the
+// results are bitwise reproducible.
+#include "kmx_device.h"
+#include "kmx_internal.h"
+
+namespace kmx {
+
+// ---- 1. block histograms; optional label-change count against lab_prev ----
+__global__ __launch_bounds__(256) void hist_kernel(const int32_t* __restrict__ label,
+                                                   int32_t* __restrict__ lab_prev, int64_t n,
+                                                   int k, int32_t* __restrict__ counts,
+                                                   LoopState* __restrict__ st, int track,
+                                                   const int* __restrict__ gate) {
+  if (gate && *gate) return;
+  extern __shared__ int hsm[];
+  const int b = blockIdx.x;
+  for (int j = threadIdx.x; j < k; j += blockDim.x) hsm[j] = 0;
+  __syncthreads();
+  const int64_t r0 = (int64_t)b * kSortRows;
+  const int64_t r1 = min(n, r0 + kSortRows);
+  unsigned long long ch = 0;
+  for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+    const int lab = label[i];
+    if (lab >= 0 && lab < k) atomicAdd(&hsm[lab], 1);
+    if (track) {
+      ch += (lab_prev[i] != lab);
+      lab_prev[i] = lab;
+    }
+  }
+  __syncthreads();
+  int32_t* out = counts + (int64_t)b * k;
+  for (int j = threadIdx.x; j < k; j += blockDim.x) out[j] = hsm[j];
+  if (track) {
+    for (int m = 32; m >= 1; m >>= 1) ch += __shfl_xor(ch, m, 64);
+    if ((threadIdx.x & 63) == 0 && ch) atomicAdd(&st->changed, ch);
+  }
+}
+
+// ---- 2. per-segment column sums of the count matrix ----
+__global__ __launch_bounds__(256) void scan_seg_kernel(const int32_t* __restrict__ counts,
+                                                       int nb, int k,
+                                                       int32_t* __restrict__ segsum,
+                                                       const int* __restrict__ gate) {
+  if (gate && *gate) return;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = blockIdx.y;
+  if (j >= k) return;
+  const int per = (nb + kScanSegs - 1) / kScanSegs;
+  const int b0 = s * per, b1 = min(nb, b0 + per);
+  int acc = 0;
+  for (int b = b0; b < b1; ++b) acc += counts[(int64_t)b * k + j];
+  segsum[(int64_t)s * k + j] = acc;
+}
+
+// Block-wide exclusive scan of one int per thread (1024 threads).
+__device__ int block_excl_scan_1024(int v, int* sh, int& total) {
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6;
+  int x = v;
+#pragma unroll
+  for (int m = 1; m < 64; m <<= 1) {
+    int y = __shfl_up(x, m, 64);
+    if (lane >= m) x += y;
+  }
+  if (lane == 63) sh[w] = x;
+  __syncthreads();
+  if (tid < 64) {
+    int s = (tid < 16) ? sh[tid] : 0;
+#pragma unroll
+    for (int m = 1; m < 16; m <<= 1) {
+      int y = __shfl_up(s, m, 64);
+      if (lane >= m) s += y;
+    }
+    if (tid < 16) sh[16 + tid] = s;
+  }
+  __syncthreads();
+  const int wexcl = (w == 0) ? 0 : sh[16 + w - 1];
+  total = sh[16 + 15];
+  const int r = wexcl + x - v;
+  __syncthreads();
+  return r;
+}
+
+// ---- 3. exclusive scans: segment offsets per column, cluster bases, chunk bases ----
+// One workgroup of 1024 threads.  base[j] = first sorted position of cluster
+// j (base[k] = number of valid rows); chunk_base likewise for reduction chunks.
+__global__ __launch_bounds__(1024) void scan_top_kernel(int32_t* __restrict__ segsum, int k,
+                                                        int32_t* __restrict__ base,
+                                                        int32_t* __restrict__ chunk_base,
+                                                        const int* __restrict__ gate) {
+  if (gate && *gate) return;
+  __shared__ int sh[64];
+  const int per = (k + 1023) / 1024;  // columns per thread, contiguous
+  const int j0 = threadIdx.x * per;
+  int tot_local = 0, ch_local = 0;
+  for (int q = 0; q < per; ++q) {
+    const int j = j0 + q;
+    if (j < k) {
+      int run = 0;
+      for (int s = 0; s < kScanSegs; ++s) {
+        const int v = segsum[(int64_t)s * k + j];
+        segsum[(int64_t)s * k + j] = run;
+        run += v;
+      }
+      tot_local += run;
+      ch_local += (run + kReduceRows - 1) / kReduceRows;
+      base[j] = run;        // temporarily the column total
+      chunk_base[j] = (run + kReduceRows - 1) / kReduceRows;
+    }
+  }
+  int total_rows, total_chunks;
+  int off = block_excl_scan_1024(tot_local, sh, total_rows);
+  int coff = block_excl_scan_1024(ch_local, sh, total_chunks);
+  for (int q = 0; q < per; ++q) {
+    const int j = j0 + q;
+    if (j < k) {
+      const int t = base[j], c = chunk_base[j];
+      base[j] = off;
+      chunk_base[j] = coff;
+      off += t;
+      coff += c;
+    }
+  }
+  if (threadIdx.x == 0) {
+    base[k] = total_rows;
+    chunk_base[k] = total_chunks;
+  }
+}
+
+// ---- 4. per-block offsets: counts[b][j] <- base[j] + rows of j in earlier blocks ----
+__global__ __launch_bounds__(256) void scan_fill_kernel(int32_t* __restrict__ counts, int nb,
+                                                        int k, const int32_t* __restrict__ segsum,
+                                                        const int32_t* __restrict__ base,
+                                                        const int* __restrict__ gate) {
+  if (gate && *gate) return;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = blockIdx.y;
+  if (j >= k) return;
+  const int per = (nb + kScanSegs - 1) / kScanSegs;
+  const int b0 = s * per, b1 = min(nb, b0 + per);
+  int run = base[j] + segsum[(int64_t)s * k + j];
+  for (int b = b0; b < b1; ++b) {
+    const int64_t o = (int64_t)b * k + j;
+    const int c = counts[o];
+    counts[o] = run;
+    run += c;
+  }
+}
+
+// ---- 5. stable scatter: one wave per block, 64 rows at a time ----
+__global__ __launch_bounds__(64) void scatter_kernel(const int32_t* __restrict__ label, int64_t n,
+                                                     int k, const int32_t* __restrict__ offs,
+                                                     int32_t* __restrict__ perm,
+                                                     const int* __restrict__ gate) {
+  if (gate && *gate) return;
+  extern __shared__ int cnt[];
+  const int b = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int32_t* ob = offs + (int64_t)b * k;
+  for (int j = lane; j < k; j += 64) cnt[j] = ob[j];
+  __syncthreads();
+  const int64_t r0 = (int64_t)b * kSortRows;
+  for (int c = 0; c < kSortRows; c += 64) {
+    const int64_t i = r0 + c + lane;
+    if (r0 + c >= n) break;
+    int lab = (i < n) ? label[i] : -1;
+    if (lab < 0 || lab >= k) lab = -1;
+    int rank = 0, tot = 0;
+#pragma unroll
+    for (int t = 0; t < 64; ++t) {
+      const int lt = __builtin_amdgcn_readlane(lab, t);
+      const int eq = (lt == lab) ? 1 : 0;
+      rank += (t < lane) ? eq : 0;
+      tot += eq;
+    }
+    int pos = 0;
+    if (lab >= 0) pos = cnt[lab] + rank;
+    __syncthreads();
+    if (lab >= 0) {
+      perm[pos] = (int32_t)i;
+      if (rank == tot - 1) cnt[lab] = pos + 1;
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_sort(hipStream_t s, const int32_t* label, int32_t* lab_prev, int64_t n, int k,
+                       int32_t* counts, int32_t* segsum, int32_t* base, int32_t* chunk_base,
+                       int32_t* perm, LoopState* st, int track, const int* gate) {
+  const int nb = (int)((n + kSortRows - 1) / kSortRows);
+  const size_t lds = (size_t)k * sizeof(int);
+  hipLaunchKernelGGL(hist_kernel, dim3(nb), dim3(256), lds, s, label, lab_prev, n, k, counts, st,
+                     track, gate);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  dim3 g2((k + 255) / 256, kScanSegs);
+  hipLaunchKernelGGL(scan_seg_kernel, g2, dim3(256), 0, s, counts, nb, k, segsum, gate);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(scan_top_kernel, dim3(1), dim3(1024), 0, s, segsum, k, base, chunk_base,
+                     gate);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(scan_fill_kernel, g2, dim3(256), 0, s, counts, nb, k, segsum, base, gate);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(scatter_kernel, dim3(nb), dim3(64), lds, s, label, n, k, counts, perm, gate);
+  return hipGetLastError();
+}
+
+// ---- 6. chunk reduction: FP64 (S, Q, W) over at most kReduceRows rows ----
+// Four waves walk the chunk's rows in an interleaved, fixed order; a lane owns
+// VEC consecutive columns in each of M column groups of 64*VEC.
+template <int VEC, int M>
+__global__ __launch_bounds__(256) void reduce_kernel(const float* __restrict__ X, int d,
+                                                     int64_t ldx, const float* __restrict__ w,
+                                                     const int32_t* __restrict__ perm,
+                                                     const int32_t* __restrict__ base,
+                                                     const int32_t* __restrict__ chunk_base,
+                                                     int k, double* __restrict__ partS,
+                                                     double* __restrict__ partQ,
+                                                     double* __restrict__ partW,
+                                                     const int* __restrict__ gate) {
+  if (gate && *gate) return;
+  __shared__ double sh[4][64 * VEC * M];
+  __shared__ double shq[4], shw[4];
+  const int cidx = blockIdx.x;
+  if (cidx >= chunk_base[k]) return;
+  // cluster owning this chunk: last j with chunk_base[j] <= cidx
+  int lo = 0, hi = k;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (chunk_base[mid] <= cidx) lo = mid; else hi = mid;
+  }
+  const int j = lo;
+  const int64_t r0 = (int64_t)base[j] + (int64_t)(cidx - chunk_base[j]) * kReduceRows;
+  const int64_t r1 = min((int64_t)base[j + 1], r0 + kReduceRows);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  constexpr int CB = 64 * VEC * M;  // columns per pass
+  double qacc = 0.0, wacc = 0.0;
+  for (int cb = 0; cb < d; cb += CB) {
+    double S[M][VEC], Q[M][VEC];
+#pragma unroll
+    for (int m = 0; m < M; ++m)
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) S[m][v] = Q[m][v] = 0.0;
+    for (int64_t r = r0 + wv; r < r1; r += 4) {
+      const int64_t i = perm[r];
+      const double wt = w ? (double)w[i] : 1.0;
+      if (cb == 0) wacc += wt;
+      const float* xr = X + i * ldx + cb;
+#pragma unroll
+      for (int m = 0; m < M; ++m) {
+        const int c0 = (m * 64 + lane) * VEC;
+        if (VEC == 4) {
+          if (cb + c0 + 4 <= d) {
+            const float4 v = *(const float4*)(xr + c0);
+            const float vv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const double xd = (double)vv[q];
+              const double wx = wt * xd;
+              S[m][q] += wx;
+              Q[m][q] += wx * xd;
+            }
+          } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              if (cb + c0 + q < d) {
+                const double xd = (double)xr[c0 + q];
+                const double wx = wt * xd;
+                S[m][q] += wx;
+                Q[m][q] += wx * xd;
+              }
+            }
+          }
+        } else {
+#pragma unroll
+          for (int q = 0; q < VEC; ++q) {
+            if (cb + c0 + q < d) {
+              const double xd = (double)xr[c0 + q];
+              const double wx = wt * xd;
+              S[m][q] += wx;
+              Q[m][q] += wx * xd;
+            }
+          }
+        }
+      }
+    }
+    // combine the four waves in a fixed order
+#pragma unroll
+    for (int m = 0; m < M; ++m)
+#pragma unroll
+      for (int q = 0; q < VEC; ++q) {
+        sh[wv][(m * 64 + lane) * VEC + q] = S[m][q];
+        qacc += Q[m][q];
+      }
+    __syncthreads();
+    for (int c = threadIdx.x; c < CB; c += 256) {
+      if (cb + c < d)
+        partS[(int64_t)cidx * d + cb + c] = ((sh[0][c] + sh[1][c]) + sh[2][c]) + sh[3][c];
+    }
+    __syncthreads();
+  }
+  qacc = wave_sum_f64(qacc);
+  if (lane == 0) {
+    shq[wv] = qacc;
+    shw[wv] = wacc;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    partQ[cidx] = ((shq[0] + shq[1]) + shq[2]) + shq[3];
+    partW[cidx] = ((shw[0] + shw[1]) + shw[2]) + shw[3];
+  }
+}
+
+hipError_t launch_reduce(hipStream_t s, const float* X, int64_t n, int d, int64_t ldx,
+                         const float* w, const int32_t* perm, const int32_t* base,
+                         const int32_t* chunk_base, int k, double* partS, double* partQ,
+                         double* partW, const int* gate) {
+  const int64_t maxchunks = (n + kReduceRows - 1) / kReduceRows + k;
+  const bool vec = ((((uintptr_t)X) & 15) == 0) && (ldx % 4 == 0);
+  dim3 g((unsigned)maxchunks);
+  if (vec && d > 256) {
+    hipLaunchKernelGGL((reduce_kernel<4, 2>), g, dim3(256), 0, s, X, d, ldx, w, perm, base,
+                       chunk_base, k, partS, partQ, partW, gate);
+  } else if (vec && d > 64) {
+    hipLaunchKernelGGL((reduce_kernel<4, 1>), g, dim3(256), 0, s, X, d, ldx, w, perm, base,
+                       chunk_base, k, partS, partQ, partW, gate);
+  } else {
+    hipLaunchKernelGGL((reduce_kernel<1, 1>), g, dim3(256), 0, s, X, d, ldx, w, perm, base,
+                       chunk_base, k, partS, partQ, partW, gate);
+  }
+  return hipGetLastError();
+}
+
+// ---- 7. per-cluster finalize: sum chunks, new center, cost terms ----
+__global__ __launch_bounds__(256) void finalize_kernel(
+    const double* __restrict__ partS, const double* __restrict__ partQ,
+    const double* __restrict__ partW, const int32_t* __restrict__ chunk_base, int k, int d,
+    const float* C_prev, float* C_out, double* __restrict__ W_out, double* __restrict__ termC,
+    double* __restrict__ termMu, int write_c, const int* __restrict__ gate) {
+  if (gate && *gate) return;
+  __shared__ double red[3][4];
+  const int j = blockIdx.x;
+  const int c0 = chunk_base[j], c1 = chunk_base[j + 1];
+  double W = 0.0, Q = 0.0;
+  for (int c = c0; c < c1; ++c) {
+    W += partW[c];
+    Q += partQ[c];
+  }
+  double dotCS = 0.0, cn2 = 0.0, s2 = 0.0;
+  for (int col = threadIdx.x; col < d; col += 256) {
+    double S = 0.0;
+    for (int c = c0; c < c1; ++c) S += partS[(int64_t)c * d + col];
+    const float cp = C_prev[(int64_t)j * d + col];
+    const double cpd = (double)cp;
+    dotCS += cpd * S;
+    cn2 += cpd * cpd;
+    s2 += S * S;
+    if (write_c) C_out[(int64_t)j * d + col] = (W > 0.0) ? (float)(S / W) : cp;
+  }
+  dotCS = wave_sum_f64(dotCS);
+  cn2 = wave_sum_f64(cn2);
+  s2 = wave_sum_f64(s2);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) {
+    red[0][wv] = dotCS;
+    red[1][wv] = cn2;
+    red[2][wv] = s2;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double a = ((red[0][0] + red[0][1]) + red[0][2]) + red[0][3];
+    const double b = ((red[1][0] + red[1][1]) + red[1][2]) + red[1][3];
+    const double e = ((red[2][0] + red[2][1]) + red[2][2]) + red[2][3];
+    termC[j] = Q - 2.0 * a + W * b;
+    termMu[j] = (W > 0.0) ? (Q - e / W) : 0.0;
+    if (W_out) W_out[j] = W;
+  }
+}
+
+hipError_t launch_finalize(hipStream_t s, const double* partS, const double* partQ,
+                           const double* partW, const int32_t* chunk_base, int k, int d,
+                           const float* C_prev, float* C_out, double* W_out, double* termC,
+                           double* termMu, int write_c, const int* gate) {
+  hipLaunchKernelGGL(finalize_kernel, dim3(k), dim3(256), 0, s, partS, partQ, partW, chunk_base,
+                     k, d, C_prev, C_out, W_out, termC, termMu, write_c, gate);
+  return hipGetLastError();
+}
+
+// ---- 8. cost sums and loop control (one workgroup) ----
+// mode 0: Lloyd iteration -> cost_hist[iter], stopping rule, iter += 1
+// mode 1: final assignment -> cost_hist[iter]
+// mode 2: store both sums in the state (standalone update / cost)
+__global__ __launch_bounds__(256) void cost_sum_kernel(const double* __restrict__ termC,
+                                                       const double* __restrict__ termMu, int k,
+                                                       LoopState* __restrict__ st,
+                                                       double* __restrict__ cost_hist, int mode,
+                                                       const int* __restrict__ gate) {
+  if (gate && *gate) return;
+  __shared__ double red[2][4];
+  double a = 0.0, b = 0.0;
+  for (int j = threadIdx.x; j < k; j += 256) {
+    a += termC[j];
+    b += termMu[j];
+  }
+  a = wave_sum_f64(a);
+  b = wave_sum_f64(b);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) {
+    red[0][wv] = a;
+    red[1][wv] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double cC = ((red[0][0] + red[0][1]) + red[0][2]) + red[0][3];
+    const double cM = ((red[1][0] + red[1][1]) + red[1][2]) + red[1][3];
+    st->cost_last = cC;
+    st->cost_at_centroids = cM;
+    if (mode == 0) {
+      const int t = st->iter;
+      cost_hist[t] = cC;
+      st->iter = t + 1;
+      if (st->tol >= 0.0 && t >= 1) {
+        const double prev = cost_hist[t - 1];
+        if (st->changed == 0ull || (prev - cC) <= st->tol * prev) st->done = 1;
+      }
+      if (t + 1 >= st->max_iter) st->done = 1;
+      st->changed = 0ull;
+    } else if (mode == 1) {
+      cost_hist[st->iter] = cC;
+    }
+  }
+}
+
+hipError_t launch_cost_sum(hipStream_t s, const double* termC, const double* termMu, int k,
+                           LoopState* st, double* cost_hist, int mode, const int* gate) {
+  hipLaunchKernelGGL(cost_sum_kernel, dim3(1), dim3(256), 0, s, termC, termMu, k, st, cost_hist,
+                     mode, gate);
+  return hipGetLastError();
+}
+
+}  // namespace kmx

@@ -1,0 +1,494 @@
+// Host side of the kmx C ABI: argument checks, the grow-only workspace, the
+// per-dataset cache and the launch sequences of seed / assign / update / cost
+// / lloyd.  All device work is enqueued on the context's stream.
+#include <climits>
+#include <cstdint>
+#include <cstring>
+#include <string>
+
+#include "kmx_internal.h"
+
+using namespace kmx;
+
+namespace {
+
+thread_local std::string g_create_err;
+
+kmx_status fail(kmx_ctx* ctx, kmx_status st, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  else g_create_err = msg;
+  return st;
+}
+
+#define KMX_HIP(ctx, call)                                                          \
+  do {                                                                              \
+    hipError_t e_ = (call);                                                         \
+    if (e_ != hipSuccess) {                                                         \
+      (void)hipGetLastError();                                                      \
+      return fail(ctx, KMX_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    }                                                                               \
+  } while (0)
+
+#define KMX_TRY(expr)               \
+  do {                              \
+    kmx_status s_ = (expr);         \
+    if (s_ != KMX_OK) return s_;    \
+  } while (0)
+
+kmx_status grow(kmx_ctx* ctx, Buf& b, size_t bytes) {
+  if (bytes == 0) bytes = 16;
+  if (b.bytes >= bytes) return KMX_OK;
+  if (b.p) {
+    KMX_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    KMX_HIP(ctx, hipFree(b.p));
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(ctx, KMX_ENOMEM,
+                "hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
+  }
+  b.p = p;
+  b.bytes = bytes;
+  return KMX_OK;
+}
+
+template <typename T>
+T* P(const Buf& b) { return reinterpret_cast<T*>(b.p); }
+
+// ---- timing: HIP events around each kernel class on the context stream ----
+hipEvent_t take_event(kmx_ctx* c) {
+  if (!c->pool.empty()) {
+    hipEvent_t e = c->pool.back();
+    c->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return e;
+}
+
+struct Timed {
+  kmx_ctx* c;
+  int cls;
+  hipEvent_t a = nullptr;
+  Timed(kmx_ctx* c_, int cls_) : c(c_), cls(cls_) {
+    if (c->timing) {
+      a = take_event(c);
+      if (a) (void)hipEventRecord(a, c->stream);
+    }
+  }
+  ~Timed() {
+    if (c->timing && a) {
+      hipEvent_t b = take_event(c);
+      if (b) {
+        (void)hipEventRecord(b, c->stream);
+        c->recs.push_back({cls, a, b});
+      } else {
+        c->pool.push_back(a);
+      }
+    }
+  }
+};
+
+kmx_status set_device(kmx_ctx* ctx) {
+  KMX_HIP(ctx, hipSetDevice(ctx->device));
+  return KMX_OK;
+}
+
+kmx_status check_problem(kmx_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
+                         int32_t k) {
+  if (!X) return fail(ctx, KMX_EINVAL, "X is NULL");
+  if (n < 1 || n > (int64_t)INT32_MAX - 1)
+    return fail(ctx, KMX_EINVAL, "n must lie in [1, 2^31 - 2], got " + std::to_string(n));
+  if (d < 1) return fail(ctx, KMX_EINVAL, "d must be >= 1, got " + std::to_string(d));
+  if (ldx < d) return fail(ctx, KMX_EINVAL, "ldx must be >= d");
+  if (k < 1) return fail(ctx, KMX_EINVAL, "k must be >= 1, got " + std::to_string(k));
+  if ((int64_t)k > n) return fail(ctx, KMX_EINVAL, "k must be <= n");
+  if (k > kMaxK)
+    return fail(ctx, KMX_EUNSUPPORTED, "k above " + std::to_string(kMaxK) + " is not supported");
+  return KMX_OK;
+}
+
+kmx_status check_prec(kmx_ctx* ctx, int prec, int d) {
+  if (prec != KMX_FP32 && prec != KMX_BF16) return fail(ctx, KMX_EINVAL, "unknown precision");
+  const int dmax = (prec == KMX_BF16) ? 1024 : 1024;
+  if (d > dmax)
+    return fail(ctx, KMX_EUNSUPPORTED,
+                "assignment supports d <= " + std::to_string(dmax) + ", got " + std::to_string(d));
+  return KMX_OK;
+}
+
+// Row statistics and (BF16) the quantized copy of X, cached per dataset.
+kmx_status ensure_prep(kmx_ctx* ctx, const float* X, int64_t n, int d, int64_t ldx, int prec) {
+  if (ctx->cache_valid && ctx->cache_X == X && ctx->cache_n == n && ctx->cache_d == d &&
+      ctx->cache_ldx == ldx && ctx->cache_prec == prec)
+    return KMX_OK;
+  ctx->cache_valid = false;
+  KMX_TRY(grow(ctx, ctx->rowstats, (size_t)n * sizeof(RowStats)));
+  uint16_t* xq = nullptr;
+  int dp = assign_dpad(prec, d);
+  if (prec == KMX_BF16) {
+    KMX_TRY(grow(ctx, ctx->xq, (size_t)n * dp * sizeof(uint16_t)));
+    xq = P<uint16_t>(ctx->xq);
+  }
+  {
+    Timed tm(ctx, T_PREP);
+    KMX_HIP(ctx, launch_prep_rows(ctx->stream, X, n, d, ldx, dp, xq, P<RowStats>(ctx->rowstats),
+                                  ctx->num_cus));
+  }
+  ctx->cache_X = X;
+  ctx->cache_n = n;
+  ctx->cache_d = d;
+  ctx->cache_ldx = ldx;
+  ctx->cache_prec = prec;
+  ctx->cache_valid = true;
+  return KMX_OK;
+}
+
+kmx_status ensure_common(kmx_ctx* ctx, int64_t n, int d, int k) {
+  const int64_t nb = (n + kSortRows - 1) / kSortRows;
+  const int64_t maxchunks = (n + kReduceRows - 1) / kReduceRows + k;
+  KMX_TRY(grow(ctx, ctx->state, sizeof(LoopState)));
+  KMX_TRY(grow(ctx, ctx->lab_a, (size_t)n * sizeof(int32_t)));
+  KMX_TRY(grow(ctx, ctx->flags, (size_t)n * sizeof(FlagEntry)));
+  KMX_TRY(grow(ctx, ctx->cstats, sizeof(CenterStats)));
+  KMX_TRY(grow(ctx, ctx->counts, (size_t)nb * k * sizeof(int32_t)));
+  KMX_TRY(grow(ctx, ctx->segsum, (size_t)kScanSegs * k * sizeof(int32_t)));
+  KMX_TRY(grow(ctx, ctx->base, (size_t)(k + 1) * sizeof(int32_t)));
+  KMX_TRY(grow(ctx, ctx->chunk_base, (size_t)(k + 1) * sizeof(int32_t)));
+  KMX_TRY(grow(ctx, ctx->perm, (size_t)n * sizeof(int32_t)));
+  KMX_TRY(grow(ctx, ctx->partS, (size_t)maxchunks * d * sizeof(double)));
+  KMX_TRY(grow(ctx, ctx->partQ, (size_t)maxchunks * sizeof(double)));
+  KMX_TRY(grow(ctx, ctx->partW, (size_t)maxchunks * sizeof(double)));
+  KMX_TRY(grow(ctx, ctx->W, (size_t)k * sizeof(double)));
+  KMX_TRY(grow(ctx, ctx->termC, (size_t)k * sizeof(double)));
+  KMX_TRY(grow(ctx, ctx->termMu, (size_t)k * sizeof(double)));
+  return KMX_OK;
+}
+
+LoopState* ST(kmx_ctx* ctx) { return P<LoopState>(ctx->state); }
+
+kmx_status write_state(kmx_ctx* ctx, int max_iter, double tol) {
+  LoopState h;
+  std::memset(&h, 0, sizeof(h));
+  h.max_iter = max_iter;
+  h.tol = tol;
+  KMX_HIP(ctx, hipMemcpyAsync(ctx->state.p, &h, sizeof(h), hipMemcpyHostToDevice, ctx->stream));
+  KMX_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return KMX_OK;
+}
+
+// prep_centers + GEMM assignment + re-check.  gate: skip when *gate != 0.
+kmx_status run_assign(kmx_ctx* ctx, const float* X, int64_t n, int d, int64_t ldx, const float* C,
+                      int k, int prec, int32_t* label, float* d1, float* d2, const int* gate) {
+  const int dp = assign_dpad(prec, d);
+  const int bn = assign_tile_n(prec, d);
+  const int kpad = (k + bn - 1) / bn * bn;
+  const size_t esz = (prec == KMX_BF16) ? 2 : 4;
+  KMX_TRY(grow(ctx, ctx->cq, (size_t)kpad * dp * esz));
+  KMX_TRY(grow(ctx, ctx->ch, (size_t)kpad * sizeof(float)));
+  LoopState* st = ST(ctx);
+  CenterStats* cs = P<CenterStats>(ctx->cstats);
+  {
+    Timed tm(ctx, T_PREP);
+    KMX_HIP(ctx, launch_reset_small(ctx->stream, cs, nullptr, st, 0));
+    KMX_HIP(ctx, launch_prep_centers(ctx->stream, C, k, d, kpad, dp, prec, ctx->cq.p,
+                                     P<float>(ctx->ch), cs));
+  }
+  {
+    Timed tm(ctx, T_ASSIGN);
+    KMX_HIP(ctx, launch_assign(ctx->stream, prec, X, ldx, P<uint16_t>(ctx->xq), n, d, dp,
+                               P<RowStats>(ctx->rowstats), ctx->cq.p, P<float>(ctx->ch), k, kpad,
+                               cs, label, d1, d2, P<FlagEntry>(ctx->flags), st, gate));
+  }
+  {
+    Timed tm(ctx, T_RECHECK);
+    KMX_HIP(ctx, launch_recheck(ctx->stream, X, n, d, ldx, C, k, label, d1,
+                                P<FlagEntry>(ctx->flags), st, ctx->num_cus, gate));
+  }
+  return KMX_OK;
+}
+
+// sort + segmented reduction + finalize + cost sums.
+kmx_status run_update(kmx_ctx* ctx, const float* X, int64_t n, int d, int64_t ldx, const float* w,
+                      const int32_t* label, int k, const float* C_prev, float* C_out,
+                      double* W_out, int write_c, int32_t* lab_prev, double* hist, int mode,
+                      const int* gate) {
+  LoopState* st = ST(ctx);
+  {
+    Timed tm(ctx, T_SORT);
+    KMX_HIP(ctx, launch_sort(ctx->stream, label, lab_prev, n, k, P<int32_t>(ctx->counts),
+                             P<int32_t>(ctx->segsum), P<int32_t>(ctx->base),
+                             P<int32_t>(ctx->chunk_base), P<int32_t>(ctx->perm), st,
+                             lab_prev ? 1 : 0, gate));
+  }
+  {
+    Timed tm(ctx, T_REDUCE);
+    KMX_HIP(ctx, launch_reduce(ctx->stream, X, n, d, ldx, w, P<int32_t>(ctx->perm),
+                               P<int32_t>(ctx->base), P<int32_t>(ctx->chunk_base), k,
+                               P<double>(ctx->partS), P<double>(ctx->partQ),
+                               P<double>(ctx->partW), gate));
+  }
+  {
+    Timed tm(ctx, T_FINAL);
+    KMX_HIP(ctx, launch_finalize(ctx->stream, P<double>(ctx->partS), P<double>(ctx->partQ),
+                                 P<double>(ctx->partW), P<int32_t>(ctx->chunk_base), k, d, C_prev,
+                                 C_out, W_out ? W_out : P<double>(ctx->W), P<double>(ctx->termC),
+                                 P<double>(ctx->termMu), write_c, gate));
+    KMX_HIP(ctx, launch_cost_sum(ctx->stream, P<double>(ctx->termC), P<double>(ctx->termMu), k,
+                                 st, hist, mode, gate));
+  }
+  return KMX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+kmx_status kmx_create(kmx_ctx** out, int device, void* hip_stream) {
+  if (!out) return fail(nullptr, KMX_EINVAL, "out is NULL");
+  *out = nullptr;
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || ndev < 1) {
+    (void)hipGetLastError();
+    return fail(nullptr, KMX_EDEVICE, "no HIP device available");
+  }
+  if (device < 0 || device >= ndev) return fail(nullptr, KMX_EINVAL, "device index out of range");
+  e = hipSetDevice(device);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(nullptr, KMX_EDEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e));
+  }
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, device);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(nullptr, KMX_EDEVICE, "hipGetDeviceProperties failed");
+  }
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(nullptr, KMX_EUNSUPPORTED,
+                std::string("this build targets gfx950, device is ") + prop.gcnArchName);
+  kmx_ctx* c = new (std::nothrow) kmx_ctx();
+  if (!c) return fail(nullptr, KMX_ENOMEM, "out of host memory");
+  c->device = device;
+  c->stream = (hipStream_t)hip_stream;
+  c->num_cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  *out = c;
+  return KMX_OK;
+}
+
+kmx_status kmx_destroy(kmx_ctx* ctx) {
+  if (!ctx) return KMX_EINVAL;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  kmx::Buf* bufs[] = {&ctx->xq,    &ctx->rowstats, &ctx->cq,     &ctx->ch,         &ctx->cstats,
+                      &ctx->lab_a, &ctx->lab_prev, &ctx->d1,     &ctx->d2,         &ctx->flags,
+                      &ctx->counters, &ctx->counts, &ctx->segsum, &ctx->base,     &ctx->chunk_base,
+                      &ctx->perm,  &ctx->partS,    &ctx->partQ,  &ctx->partW,      &ctx->W,
+                      &ctx->termC, &ctx->termMu,   &ctx->state,  &ctx->D2,         &ctx->chosen,
+                      &ctx->seed_part, &ctx->seed_ctr, &ctx->scratch_c, &ctx->hist};
+  for (kmx::Buf* b : bufs)
+    if (b->p) (void)hipFree(b->p);
+  for (auto& r : ctx->recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
+  delete ctx;
+  return KMX_OK;
+}
+
+kmx_status kmx_set_stream(kmx_ctx* ctx, void* hip_stream) {
+  if (!ctx) return KMX_EINVAL;
+  ctx->stream = (hipStream_t)hip_stream;
+  return KMX_OK;
+}
+
+kmx_status kmx_invalidate(kmx_ctx* ctx, const float* X) {
+  if (!ctx) return KMX_EINVAL;
+  if (X == nullptr || ctx->cache_X == X) ctx->cache_valid = false;
+  return KMX_OK;
+}
+
+const char* kmx_last_error(const kmx_ctx* ctx) {
+  return ctx ? ctx->err.c_str() : g_create_err.c_str();
+}
+
+kmx_status kmx_seed(kmx_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
+                    const float* w, int32_t k, uint64_t rng_seed, float* C_out,
+                    int64_t* idx_out) {
+  if (!ctx) return KMX_EINVAL;
+  ctx->err.clear();
+  KMX_TRY(check_problem(ctx, X, n, d, ldx, k));
+  if (!C_out) return fail(ctx, KMX_EINVAL, "C_out is NULL");
+  KMX_TRY(set_device(ctx));
+  const int64_t nb = (n + kSeedRows - 1) / kSeedRows;
+  KMX_TRY(grow(ctx, ctx->D2, (size_t)n * sizeof(double)));
+  KMX_TRY(grow(ctx, ctx->chosen, (size_t)n));
+  KMX_TRY(grow(ctx, ctx->seed_part, (size_t)nb * sizeof(double)));
+  KMX_TRY(grow(ctx, ctx->seed_ctr, 16));
+  Timed tm(ctx, T_SEED);
+  KMX_HIP(ctx, launch_fill_u8(ctx->stream, P<uint8_t>(ctx->chosen), n, 0));
+  KMX_HIP(ctx, launch_fill_i32(ctx->stream, P<int32_t>(ctx->seed_ctr), 4, 0));
+  for (int r = 0; r < k; ++r) {
+    KMX_HIP(ctx, launch_seed_round(ctx->stream, X, n, d, ldx, w, r, rng_seed, P<double>(ctx->D2),
+                                   P<uint8_t>(ctx->chosen), P<double>(ctx->seed_part),
+                                   P<unsigned int>(ctx->seed_ctr), C_out, idx_out));
+  }
+  return KMX_OK;
+}
+
+kmx_status kmx_assign(kmx_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
+                      const float* C, int32_t k, kmx_prec prec, int32_t* label_out, float* d1_out,
+                      float* d2_out, int64_t* n_flagged) {
+  if (!ctx) return KMX_EINVAL;
+  ctx->err.clear();
+  KMX_TRY(check_problem(ctx, X, n, d, ldx, k));
+  KMX_TRY(check_prec(ctx, prec, d));
+  if (!C) return fail(ctx, KMX_EINVAL, "C is NULL");
+  if (!label_out) return fail(ctx, KMX_EINVAL, "label_out is NULL");
+  KMX_TRY(set_device(ctx));
+  KMX_TRY(ensure_common(ctx, n, d, k));
+  KMX_TRY(ensure_prep(ctx, X, n, d, ldx, prec));
+  KMX_TRY(run_assign(ctx, X, n, d, ldx, C, k, prec, label_out, d1_out, d2_out, nullptr));
+  if (n_flagged) {
+    LoopState h;
+    KMX_HIP(ctx, hipMemcpyAsync(&h, ctx->state.p, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+    KMX_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    *n_flagged = (int64_t)h.flagged;
+  }
+  return KMX_OK;
+}
+
+kmx_status kmx_update(kmx_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
+                      const float* w, const int32_t* label, int32_t k, const float* C_prev,
+                      float* C_out, double* W_out, double* cost_at_centroids) {
+  if (!ctx) return KMX_EINVAL;
+  ctx->err.clear();
+  if (!X) return fail(ctx, KMX_EINVAL, "X is NULL");
+  if (n < 1 || n > (int64_t)INT32_MAX - 1) return fail(ctx, KMX_EINVAL, "n out of range");
+  if (d < 1 || ldx < d) return fail(ctx, KMX_EINVAL, "bad d or ldx");
+  if (k < 1) return fail(ctx, KMX_EINVAL, "k must be >= 1");
+  if (k > kMaxK) return fail(ctx, KMX_EUNSUPPORTED, "k too large");
+  if (!label || !C_prev || !C_out) return fail(ctx, KMX_EINVAL, "NULL label or centers");
+  KMX_TRY(set_device(ctx));
+  KMX_TRY(ensure_common(ctx, n, d, k));
+  KMX_TRY(run_update(ctx, X, n, d, ldx, w, label, k, C_prev, C_out, W_out, 1, nullptr, nullptr, 2,
+                     nullptr));
+  if (cost_at_centroids) {
+    LoopState h;
+    KMX_HIP(ctx, hipMemcpyAsync(&h, ctx->state.p, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+    KMX_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    *cost_at_centroids = h.cost_at_centroids;
+  }
+  return KMX_OK;
+}
+
+kmx_status kmx_cost(kmx_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
+                    const float* w, const float* C, int32_t k, kmx_prec prec, double* cost_out) {
+  if (!ctx) return KMX_EINVAL;
+  ctx->err.clear();
+  KMX_TRY(check_problem(ctx, X, n, d, ldx, k));
+  KMX_TRY(check_prec(ctx, prec, d));
+  if (!C || !cost_out) return fail(ctx, KMX_EINVAL, "NULL C or cost_out");
+  KMX_TRY(set_device(ctx));
+  KMX_TRY(ensure_common(ctx, n, d, k));
+  KMX_TRY(ensure_prep(ctx, X, n, d, ldx, prec));
+  int32_t* lab = P<int32_t>(ctx->lab_a);
+  KMX_TRY(run_assign(ctx, X, n, d, ldx, C, k, prec, lab, nullptr, nullptr, nullptr));
+  KMX_TRY(run_update(ctx, X, n, d, ldx, w, lab, k, C, nullptr, nullptr, 0, nullptr, nullptr, 2,
+                     nullptr));
+  LoopState h;
+  KMX_HIP(ctx, hipMemcpyAsync(&h, ctx->state.p, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+  KMX_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  *cost_out = h.cost_last;
+  return KMX_OK;
+}
+
+kmx_status kmx_lloyd(kmx_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
+                     const float* w, float* C_inout, int32_t k, int32_t max_iter, double tol,
+                     kmx_prec prec, int32_t* label_out, double* cost_hist, int32_t* iters_done) {
+  if (!ctx) return KMX_EINVAL;
+  ctx->err.clear();
+  KMX_TRY(check_problem(ctx, X, n, d, ldx, k));
+  KMX_TRY(check_prec(ctx, prec, d));
+  if (!C_inout || !cost_hist || !iters_done)
+    return fail(ctx, KMX_EINVAL, "NULL C_inout, cost_hist or iters_done");
+  if (max_iter < 0) return fail(ctx, KMX_EINVAL, "max_iter must be >= 0");
+  KMX_TRY(set_device(ctx));
+  KMX_TRY(ensure_common(ctx, n, d, k));
+  KMX_TRY(ensure_prep(ctx, X, n, d, ldx, prec));
+  KMX_TRY(grow(ctx, ctx->lab_prev, (size_t)n * sizeof(int32_t)));
+  KMX_TRY(grow(ctx, ctx->hist, (size_t)(max_iter + 1) * sizeof(double)));
+  KMX_TRY(write_state(ctx, max_iter, tol));
+  int32_t* lab = label_out ? label_out : P<int32_t>(ctx->lab_a);
+  int32_t* prev = P<int32_t>(ctx->lab_prev);
+  double* hist = P<double>(ctx->hist);
+  LoopState* st = ST(ctx);
+  KMX_HIP(ctx, launch_fill_i32(ctx->stream, prev, n, -1));
+  for (int t = 0; t < max_iter; ++t) {
+    KMX_TRY(run_assign(ctx, X, n, d, ldx, C_inout, k, prec, lab, nullptr, nullptr, &st->done));
+    KMX_TRY(run_update(ctx, X, n, d, ldx, w, lab, k, C_inout, C_inout, nullptr, 1, prev, hist, 0,
+                       &st->done));
+  }
+  // final assignment: labels and cost of the returned centers
+  KMX_TRY(run_assign(ctx, X, n, d, ldx, C_inout, k, prec, lab, nullptr, nullptr, nullptr));
+  KMX_TRY(run_update(ctx, X, n, d, ldx, w, lab, k, C_inout, nullptr, nullptr, 0, nullptr, hist, 1,
+                     nullptr));
+  LoopState h;
+  KMX_HIP(ctx, hipMemcpyAsync(&h, ctx->state.p, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+  KMX_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  const int it = h.iter;
+  KMX_HIP(ctx, hipMemcpy(cost_hist, hist, (size_t)(it + 1) * sizeof(double),
+                         hipMemcpyDeviceToHost));
+  *iters_done = it;
+  return KMX_OK;
+}
+
+kmx_status kmx_timing(kmx_ctx* ctx, int enable, int reset) {
+  if (!ctx) return KMX_EINVAL;
+  if (reset) {
+    (void)hipStreamSynchronize(ctx->stream);
+    for (auto& r : ctx->recs) {
+      ctx->pool.push_back(r.a);
+      ctx->pool.push_back(r.b);
+    }
+    ctx->recs.clear();
+    for (int i = 0; i < T_NCLASS; ++i) {
+      ctx->ms_acc[i] = 0.0;
+      ctx->cnt_acc[i] = 0;
+    }
+  }
+  ctx->timing = enable != 0;
+  return KMX_OK;
+}
+
+kmx_status kmx_timing_read(kmx_ctx* ctx, int n_classes, double* ms_out, int64_t* count_out) {
+  if (!ctx) return KMX_EINVAL;
+  if (n_classes < 0 || n_classes > T_NCLASS) return fail(ctx, KMX_EINVAL, "n_classes out of range");
+  KMX_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  for (auto& r : ctx->recs) {
+    float ms = 0.f;
+    KMX_HIP(ctx, hipEventElapsedTime(&ms, r.a, r.b));
+    ctx->ms_acc[r.cls] += ms;
+    ctx->cnt_acc[r.cls] += 1;
+    ctx->pool.push_back(r.a);
+    ctx->pool.push_back(r.b);
+  }
+  ctx->recs.clear();
+  for (int i = 0; i < n_classes; ++i) {
+    if (ms_out) ms_out[i] = ctx->ms_acc[i];
+    if (count_out) count_out[i] = ctx->cnt_acc[i];
+  }
+  return KMX_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,93 @@
+// Device helpers shared by the kmx kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace kmx {
+
+// float -> bfloat16 bits, round to nearest even (finite inputs).
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  uint32_t r = 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)((u + r) >> 16);
+}
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t b) {
+  return __uint_as_float(((uint32_t)b) << 16);
+}
+
+// Non-negative double -> float rounded toward +inf.
+__device__ __forceinline__ float f64_to_f32_up(double x) {
+  float f = (float)x;
+  if ((double)f < x) f = __uint_as_float(__float_as_uint(f) + 1u);
+  return f;
+}
+
+// Butterfly sums over the 64 lanes of a wave.  IEEE addition commutes, so
+// every lane ends with the same bits and the order is fixed.
+__device__ __forceinline__ double wave_sum_f64(double v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+
+__device__ __forceinline__ float wave_sum_f32(float v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+
+// Error-free transformations (Knuth's TwoSum; FMA-based product).
+__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
+  s = a + b;
+  float bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
+__device__ __forceinline__ void two_prod(float a, float b, float& p, float& e) {
+  p = a * b;
+  e = __builtin_fmaf(a, b, -p);
+}
+
+// Accumulates the exact square of (x - c) into the double-float pair (s, e):
+// the difference is split exactly by TwoSum, its square by TwoProd.
+__device__ __forceinline__ void df_acc_sqdiff(float x, float c, float& s, float& e) {
+  float dh, dl;
+  two_sum(x, -c, dh, dl);
+  float p, pe;
+  two_prod(dh, dh, p, pe);
+  pe = __builtin_fmaf(2.0f * dh, dl, pe);
+  float t, te;
+  two_sum(s, p, t, te);
+  s = t;
+  e += te + pe;
+}
+
+// Combines double-float partials across the lanes of a wave (fixed order).
+__device__ __forceinline__ void wave_sum_df(float& s, float& e) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    float so = __shfl_xor(s, m, 64);
+    float eo = __shfl_xor(e, m, 64);
+    // symmetric in (self, other) so both partners hold identical bits
+    float lo_s = fminf(s, so), hi_s = fmaxf(s, so);
+    float t, te;
+    two_sum(hi_s, lo_s, t, te);
+    float el = fminf(e, eo), eh = fmaxf(e, eo);
+    s = t;
+    e = (eh + el) + te;
+  }
+}
+
+// Normalizes a double-float so that (hi, lo) compare lexicographically.
+__device__ __forceinline__ void df_norm(float s, float e, float& hi, float& lo) {
+  hi = s + e;
+  lo = e - (hi - s);
+}
+
+__device__ __forceinline__ bool df_less(float h1, float l1, float h2, float l2) {
+  return h1 < h2 || (h1 == h2 && l1 < l2);
+}
+
+}  // namespace kmx

@@ -1,0 +1,155 @@
+// Internal declarations shared by the kmx translation units.  Not installed;
+// the public contract is include/kmx.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/kmx.h"
+
+namespace kmx {
+
+// Per-row statistics written once per dataset by the prep kernel.
+//   xn2 : ||x||^2 (FP64 sum, rounded to nearest float)
+//   nx  : ||x||, rounded up
+//   nxq : ||x~|| of the quantized row (== nx for FP32), rounded up
+//   rx  : ||x - x~|| (0 for FP32), rounded up
+struct RowStats {
+  float xn2, nx, nxq, rx;
+};
+
+// Per-iteration center statistics (maxima over centers), set by prep_centers
+// through atomicMax on the bit patterns of non-negative floats.
+//   cq_max : max_j ||c~_j||    (rounded up)
+//   rc_max : max_j ||c_j - c~_j|| (rounded up)
+//   cn_max : max_j ||c_j||     (rounded up)
+struct CenterStats {
+  unsigned int cq_max, rc_max, cn_max, pad;
+};
+
+// Device-side Lloyd state, one instance per context.
+struct LoopState {
+  int done;          // set once the stopping rule fired
+  int iter;          // completed update steps
+  int max_iter;
+  int track_changes; // count label changes against the previous labels
+  double tol;        // < 0: fixed iteration count
+  unsigned long long changed;
+  unsigned long long flagged;   // rows that needed the re-check (last assign)
+  unsigned long long flagged_full;
+  double cost_at_centroids;
+  double cost_last;
+};
+
+// Entry of the re-check list: row index (bit 31 set: every center must be
+// re-checked) and the runner-up candidate.
+struct FlagEntry {
+  int row;
+  int cand2;
+};
+
+enum TimingClass {
+  T_PREP = 0, T_ASSIGN = 1, T_RECHECK = 2, T_SORT = 3, T_REDUCE = 4,
+  T_FINAL = 5, T_SEED = 6, T_OTHER = 7, T_NCLASS = 8
+};
+
+// Grow-only device buffer.
+struct Buf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+// Sizes of the row blocks used by the sort and the seeding rounds.
+constexpr int kSortRows = 2048;     // rows per histogram / scatter block
+constexpr int kReduceRows = 512;    // rows per segmented-reduction chunk
+constexpr int kSeedRows = 2048;     // rows per seeding block
+constexpr int kScanSegs = 64;       // column-scan segments
+constexpr int kMaxK = 16384;        // largest k (LDS histograms)
+
+}  // namespace kmx
+
+struct kmx_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int num_cus = 256;
+  std::string err;
+
+  // cached per-dataset data
+  const float* cache_X = nullptr;
+  int64_t cache_n = 0, cache_ldx = 0;
+  int cache_d = 0, cache_prec = -1;
+  bool cache_valid = false;
+
+  kmx::Buf xq, rowstats;
+  kmx::Buf cq, ch, cstats;
+  kmx::Buf lab_a, lab_prev, d1, d2;
+  kmx::Buf flags, counters;
+  kmx::Buf counts, segsum, base, chunk_base, perm;
+  kmx::Buf partS, partQ, partW;
+  kmx::Buf W, termC, termMu;
+  kmx::Buf state;
+  kmx::Buf D2, chosen, seed_part, seed_ctr;
+  kmx::Buf scratch_c, hist;
+
+  // timing
+  bool timing = false;
+  struct Rec { int cls; hipEvent_t a, b; };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  double ms_acc[kmx::T_NCLASS] = {0};
+  int64_t cnt_acc[kmx::T_NCLASS] = {0};
+};
+
+namespace kmx {
+
+// ---- launchers (each returns hipSuccess or the launch error) --------------
+// prep
+hipError_t launch_prep_rows(hipStream_t s, const float* X, int64_t n, int d, int64_t ldx,
+                            int dp, uint16_t* Xq, RowStats* st, int num_cus);
+hipError_t launch_prep_centers(hipStream_t s, const float* C, int k, int d, int kpad, int dp,
+                               int prec, void* Cq, float* ch, CenterStats* cs);
+hipError_t launch_fill_i32(hipStream_t s, int32_t* p, int64_t n, int32_t v);
+hipError_t launch_fill_u8(hipStream_t s, uint8_t* p, int64_t n, uint8_t v);
+hipError_t launch_reset_small(hipStream_t s, CenterStats* cs, unsigned long long* ctr,
+                              LoopState* st, int reset_iter);
+
+// assign
+int assign_tile_n(int prec, int d);   // centers per tile (kpad granularity)
+int assign_dpad(int prec, int d);     // padded row length of quantized data
+hipError_t launch_assign(hipStream_t s, int prec, const float* X, int64_t ldx,
+                         const uint16_t* Xq, int64_t n, int d, int dp,
+                         const RowStats* rs, const void* Cq, const float* ch,
+                         int k, int kpad, const CenterStats* cs, int32_t* label,
+                         float* d1, float* d2, FlagEntry* flags, LoopState* st,
+                         const int* gate);
+hipError_t launch_recheck(hipStream_t s, const float* X, int64_t n, int d, int64_t ldx,
+                          const float* C, int k, int32_t* label, float* d1,
+                          const FlagEntry* flags, const LoopState* st, int num_cus,
+                          const int* gate);
+
+// update
+hipError_t launch_sort(hipStream_t s, const int32_t* label, int32_t* lab_prev, int64_t n,
+                       int k, int32_t* counts, int32_t* segsum, int32_t* base,
+                       int32_t* chunk_base, int32_t* perm, LoopState* st, int track,
+                       const int* gate);
+hipError_t launch_reduce(hipStream_t s, const float* X, int64_t n, int d, int64_t ldx,
+                         const float* w, const int32_t* perm, const int32_t* base,
+                         const int32_t* chunk_base, int k, double* partS, double* partQ,
+                         double* partW, const int* gate);
+hipError_t launch_finalize(hipStream_t s, const double* partS, const double* partQ,
+                           const double* partW, const int32_t* chunk_base, int k, int d,
+                           const float* C_prev, float* C_out, double* W_out,
+                           double* termC, double* termMu, int write_c, const int* gate);
+hipError_t launch_cost_sum(hipStream_t s, const double* termC, const double* termMu, int k,
+                           LoopState* st, double* cost_hist, int mode, const int* gate);
+
+// seeding
+hipError_t launch_seed_round(hipStream_t s, const float* X, int64_t n, int d, int64_t ldx,
+                             const float* w, int r, uint64_t seed, double* D2,
+                             uint8_t* chosen, double* part, unsigned int* ctr,
+                             float* C_out, int64_t* idx_out);
+
+}  // namespace kmx

@@ -1,0 +1,233 @@
+"""ctypes binding of libkmx (include/kmx.h).
+
+Argument marshalling only: every tensor must already live on the GPU; torch
+supplies device memory and the current stream, and every step of the
+computation runs in the library's HIP kernels.  Calls raise ``KmxError`` when
+the library reports a failure, and ``RuntimeError`` when the library is not
+built -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkmx.so")
+
+FP32, BF16 = 0, 1
+_PREC = {"fp32": FP32, "bf16": BF16, FP32: FP32, BF16: BF16}
+
+TIMING_CLASSES = ("prep", "assign", "recheck", "sort", "reduce", "finalize", "seed", "other")
+
+_lib = None
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_i32 = ctypes.c_int32
+
+
+class KmxError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"kmx status {status}: {message}")
+        self.status = status
+
+
+def lib():
+    """Loads libkmx.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_1502_04265_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    sig = {
+        "kmx_create": [ctypes.POINTER(_vp), ctypes.c_int, _vp],
+        "kmx_destroy": [_vp],
+        "kmx_set_stream": [_vp, _vp],
+        "kmx_invalidate": [_vp, _vp],
+        "kmx_seed": [_vp, _vp, _i64, _i32, _i64, _vp, _i32, ctypes.c_uint64, _vp, _vp],
+        "kmx_assign": [_vp, _vp, _i64, _i32, _i64, _vp, _i32, ctypes.c_int, _vp, _vp, _vp, _vp],
+        "kmx_update": [_vp, _vp, _i64, _i32, _i64, _vp, _vp, _i32, _vp, _vp, _vp, _vp],
+        "kmx_cost": [_vp, _vp, _i64, _i32, _i64, _vp, _vp, _i32, ctypes.c_int, _vp],
+        "kmx_lloyd": [_vp, _vp, _i64, _i32, _i64, _vp, _vp, _i32, _i32, ctypes.c_double,
+                      ctypes.c_int, _vp, _vp, _vp],
+        "kmx_timing": [_vp, ctypes.c_int, ctypes.c_int],
+        "kmx_timing_read": [_vp, ctypes.c_int, _vp, _vp],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    L.kmx_last_error.argtypes = [_vp]
+    L.kmx_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _check(status: int, ctx_ptr) -> None:
+    if status != 0:
+        msg = lib().kmx_last_error(ctx_ptr)
+        raise KmxError(status, msg.decode() if msg else "")
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else _vp(t.data_ptr())
+
+
+def _rows(X: torch.Tensor):
+    if not X.is_cuda or X.dtype != torch.float32 or X.dim() != 2 or X.stride(1) != 1:
+        raise ValueError("X must be a 2-D float32 CUDA tensor with unit column stride")
+    return X.shape[0], X.shape[1], X.stride(0)
+
+
+def _vec(w: Optional[torch.Tensor], n: int, dtype=torch.float32):
+    if w is None:
+        return None
+    if not w.is_cuda or w.dtype != dtype or w.numel() != n or not w.is_contiguous():
+        raise ValueError(f"expected a contiguous {dtype} CUDA tensor of {n} elements")
+    return w
+
+
+def _centers(C: torch.Tensor, d: int):
+    if not C.is_cuda or C.dtype != torch.float32 or C.dim() != 2 or C.shape[1] != d \
+            or not C.is_contiguous():
+        raise ValueError("C must be a contiguous k x d float32 CUDA tensor")
+    return C.shape[0]
+
+
+class Context:
+    """Owns a kmx_ctx bound to one device; every call runs on torch's current
+    stream of that device."""
+
+    def __init__(self, device: int = 0):
+        L = lib()
+        self.device = int(device)
+        p = _vp()
+        with torch.cuda.device(self.device):
+            st = torch.cuda.current_stream().cuda_stream
+            _check(L.kmx_create(ctypes.byref(p), self.device, _vp(st)), None)
+        self._p = p
+
+    def close(self):
+        if getattr(self, "_p", None) is not None and self._p.value:
+            lib().kmx_destroy(self._p)
+            self._p = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _sync_stream(self):
+        st = torch.cuda.current_stream(self.device).cuda_stream
+        lib().kmx_set_stream(self._p, _vp(st))
+
+    # ---- the five calls ----------------------------------------------------
+    def seed(self, X, k: int, w=None, rng_seed: int = 0):
+        n, d, ldx = _rows(X)
+        _vec(w, n)
+        C = torch.empty((k, d), dtype=torch.float32, device=X.device)
+        idx = torch.empty(k, dtype=torch.int64, device=X.device)
+        self._sync_stream()
+        _check(lib().kmx_seed(self._p, _ptr(X), n, d, ldx, _ptr(w), k,
+                              ctypes.c_uint64(rng_seed & (2 ** 64 - 1)), _ptr(C), _ptr(idx)),
+               self._p)
+        return C, idx
+
+    def assign(self, X, C, prec="fp32", want_d=True):
+        n, d, ldx = _rows(X)
+        k = _centers(C, d)
+        lab = torch.empty(n, dtype=torch.int32, device=X.device)
+        d1 = torch.empty(n, dtype=torch.float32, device=X.device) if want_d else None
+        d2 = torch.empty(n, dtype=torch.float32, device=X.device) if want_d else None
+        nf = ctypes.c_int64(0)
+        self._sync_stream()
+        _check(lib().kmx_assign(self._p, _ptr(X), n, d, ldx, _ptr(C), k, _PREC[prec], _ptr(lab),
+                                _ptr(d1), _ptr(d2), ctypes.byref(nf)), self._p)
+        return lab, d1, d2, int(nf.value)
+
+    def update(self, X, labels, C_prev, w=None, out=None):
+        n, d, ldx = _rows(X)
+        k = _centers(C_prev, d)
+        _vec(labels, n, torch.int32)
+        _vec(w, n)
+        C_out = torch.empty_like(C_prev) if out is None else out
+        W = torch.empty(k, dtype=torch.float64, device=X.device)
+        cac = ctypes.c_double(0.0)
+        self._sync_stream()
+        _check(lib().kmx_update(self._p, _ptr(X), n, d, ldx, _ptr(w), _ptr(labels), k,
+                                _ptr(C_prev), _ptr(C_out), _ptr(W), ctypes.byref(cac)), self._p)
+        return C_out, W, float(cac.value)
+
+    def cost(self, X, C, w=None, prec="fp32") -> float:
+        n, d, ldx = _rows(X)
+        k = _centers(C, d)
+        _vec(w, n)
+        out = ctypes.c_double(0.0)
+        self._sync_stream()
+        _check(lib().kmx_cost(self._p, _ptr(X), n, d, ldx, _ptr(w), _ptr(C), k, _PREC[prec],
+                              ctypes.byref(out)), self._p)
+        return float(out.value)
+
+    def lloyd(self, X, C0, max_iter: int, w=None, tol: float = -1.0, prec="bf16",
+              labels: bool = True, inplace: bool = False):
+        n, d, ldx = _rows(X)
+        k = _centers(C0, d)
+        _vec(w, n)
+        C = C0 if inplace else C0.clone()
+        lab = torch.empty(n, dtype=torch.int32, device=X.device) if labels else None
+        hist = (ctypes.c_double * (max_iter + 1))()
+        iters = ctypes.c_int32(0)
+        self._sync_stream()
+        _check(lib().kmx_lloyd(self._p, _ptr(X), n, d, ldx, _ptr(w), _ptr(C), k, max_iter,
+                               float(tol), _PREC[prec], _ptr(lab), hist, ctypes.byref(iters)),
+               self._p)
+        it = int(iters.value)
+        return C, lab, [hist[i] for i in range(it + 1)], it
+
+    def invalidate(self, X=None):
+        _check(lib().kmx_invalidate(self._p, _ptr(X)), self._p)
+
+    # ---- measurement -------------------------------------------------------
+    def timing(self, enable: bool = True, reset: bool = True):
+        _check(lib().kmx_timing(self._p, int(enable), int(reset)), self._p)
+
+    def timing_read(self):
+        ms = (ctypes.c_double * 8)()
+        cnt = (ctypes.c_int64 * 8)()
+        _check(lib().kmx_timing_read(self._p, 8, ms, cnt), self._p)
+        return {name: (ms[i], cnt[i]) for i, name in enumerate(TIMING_CLASSES)}
+
+
+_default = {}
+
+
+def context(device: int = 0) -> Context:
+    """A per-process context for ``device`` (created on first use)."""
+    if device not in _default:
+        _default[device] = Context(device)
+    return _default[device]
+
+
+def seed(X, k, w=None, rng_seed=0):
+    return context(X.device.index or 0).seed(X, k, w, rng_seed)
+
+
+def assign(X, C, prec="fp32", want_d=True):
+    return context(X.device.index or 0).assign(X, C, prec, want_d)
+
+
+def update(X, labels, C_prev, w=None, out=None):
+    return context(X.device.index or 0).update(X, labels, C_prev, w, out)
+
+
+def cost(X, C, w=None, prec="fp32"):
+    return context(X.device.index or 0).cost(X, C, w, prec)
+
+
+def lloyd(X, C0, max_iter, w=None, tol=-1.0, prec="bf16", labels=True, inplace=False):
+    return context(X.device.index or 0).lloyd(X, C0, max_iter, w, tol, prec, labels, inplace)

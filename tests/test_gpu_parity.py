@@ -1,0 +1,271 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Bars (fixed by the method's contract):
+  * labels bit-exact, except rows whose oracle top-2 margin is below 1e-6
+    relative: (d2 - d1) < 1e-6 * d2;
+  * centroids within 1e-5 relative per center (norm-wise), compared on the
+    same labels;
+  * cost within 1e-6 relative;
+  * seeding: identical indices (both sides use FP64 distances and the same
+    SplitMix64 stream; a differing pick would need u*M to fall within ~1e-15
+    relative of a prefix boundary).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import kmeans as ok
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+MARGIN = 1e-6
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1502_04265_amd import kmx
+    return kmx.Context(0)
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def _exempt(d1, d2):
+    return (d2 - d1) < MARGIN * d2
+
+
+def _check_labels(lab_gpu, X, C, tag):
+    lab_o, d1, d2 = ok.assign(X, C)
+    ex = _exempt(d1, d2)
+    bad = (lab_gpu != lab_o) & ~ex
+    assert not bad.any(), f"{tag}: {bad.sum()} label mismatches outside the exempt band " \
+                          f"(first rows {np.nonzero(bad)[0][:5]})"
+    return lab_o, d1, d2
+
+
+# ---------------------------------------------------------------------------
+# assignment
+# ---------------------------------------------------------------------------
+ASSIGN_CASES = [
+    # n, d, k  -- several tiles, ragged tails in n, d and k
+    (1000, 64, 10),
+    (3001, 37, 67),
+    (2500, 130, 129),
+    (777, 512, 33),
+    (513, 1000, 50),
+    (200, 3, 1),
+    (64, 16, 2),
+    (50, 8, 50),      # k == n
+]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("n,d,k", ASSIGN_CASES)
+def test_assign_matches_oracle(ctx, prec, n, d, k):
+    say(f"assign prec={prec} n={n} d={d} k={k}")
+    rng = np.random.default_rng(n * 7 + d + k)
+    X, _ = synth.isotropic_mixture(n, d, max(2, k // 2 + 1), seed=n + d)
+    C = X[rng.choice(n, k, replace=False)] + rng.normal(0, 0.1, (k, d)).astype(np.float32)
+    lab, d1, d2, nf = ctx.assign(_dev(X), _dev(C), prec=prec)
+    lab = lab.cpu().numpy()
+    lab_o, od1, od2 = _check_labels(lab, X, C, f"{prec} {n}x{d} k={k}")
+    # d1 within the GEMM's own error for unflagged rows; exact for re-checked rows
+    g1 = d1.cpu().numpy().astype(np.float64)
+    same = lab == lab_o
+    scale = np.sum(X.astype(np.float64) ** 2, 1) + np.max(np.sum(C.astype(np.float64) ** 2, 1))
+    tol = (2e-2 if prec == "bf16" else 1e-3) * scale + 1e-6
+    assert np.all(np.abs(g1[same] - od1[same]) <= tol[same])
+    assert 0 <= nf <= n
+
+
+def test_assign_ties_and_duplicates(ctx):
+    say("assign ties/duplicates")
+    X = np.array([[0, 0], [2, 0], [1, 0], [5, 5], [1, 1]], dtype=np.float32)
+    C = np.array([[1, 0], [1, 0], [0, 0], [2, 0]], dtype=np.float32)  # duplicate centers 0, 1
+    for prec in ("fp32", "bf16"):
+        lab, _, _, _ = ctx.assign(_dev(X), _dev(C), prec=prec)
+        lab_o, _, _ = ok.assign(X, C)
+        assert lab.cpu().numpy().tolist() == lab_o.tolist()
+
+
+def test_assign_near_ties_are_rechecked(ctx):
+    # Points exactly between two centers up to tiny offsets: only the re-check
+    # can resolve them; labels must still be exact outside the exempt band.
+    say("assign near ties")
+    rng = np.random.default_rng(3)
+    n, d = 4000, 96
+    c0 = rng.normal(0, 3, d)
+    c1 = c0 + rng.normal(0, 1, d)
+    mid = 0.5 * (c0 + c1)
+    direction = (c1 - c0) / np.linalg.norm(c1 - c0)
+    eps = rng.uniform(-1e-3, 1e-3, n)
+    X = (mid[None, :] + eps[:, None] * direction[None, :]
+         + 0.5 * rng.normal(size=(n, d)) * (1 - np.abs(direction))[None, :]).astype(np.float32)
+    C = np.stack([c0, c1, c0 + 40.0]).astype(np.float32)
+    for prec in ("fp32", "bf16"):
+        lab, _, _, nf = ctx.assign(_dev(X), _dev(C), prec=prec)
+        _check_labels(lab.cpu().numpy(), X, C, f"near ties {prec}")
+        assert nf > 0
+
+
+# ---------------------------------------------------------------------------
+# update and cost
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n,d,k,weighted", [(5000, 64, 10, False), (3001, 37, 67, True),
+                                            (1200, 700, 5, True), (300, 1, 3, False)])
+def test_update_matches_oracle(ctx, n, d, k, weighted):
+    say(f"update n={n} d={d} k={k} w={weighted}")
+    rng = np.random.default_rng(n + d)
+    X, _ = synth.isotropic_mixture(n, d, k, seed=d)
+    w = synth.lognormal_weights(n, seed=k) if weighted else None
+    lab = rng.integers(0, k, size=n).astype(np.int32)
+    lab[lab == k - 1] = 0          # cluster k-1 empty: keeps its center
+    C_prev = rng.normal(size=(k, d)).astype(np.float32)
+    C_new, W, cac = ctx.update(_dev(X), _dev(lab), _dev(C_prev), w=None if w is None else _dev(w))
+    Co, Wo, So, Qo = ok.update(X, w, lab, C_prev)
+    Cg = C_new.cpu().numpy().astype(np.float64)
+    for j in range(k):
+        ref = np.linalg.norm(Co[j])
+        assert np.linalg.norm(Cg[j] - Co[j]) <= 1e-5 * max(ref, 1e-3)
+    assert np.array_equal(Cg[k - 1], C_prev[k - 1].astype(np.float64))
+    np.testing.assert_allclose(W.cpu().numpy(), Wo, rtol=1e-12)
+    ref_cac = ok.cost_at_centroids(Wo, So, Qo)
+    assert abs(cac - ref_cac) <= 1e-9 * ref_cac
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_cost_matches_oracle(ctx, prec):
+    say(f"cost {prec}")
+    X, _ = synth.isotropic_mixture(4000, 50, 8, seed=2)
+    w = synth.lognormal_weights(4000, seed=3)
+    C = X[:8] + 0.5
+    c = ctx.cost(_dev(X), _dev(C), w=_dev(w), prec=prec)
+    ref = ok.cost(X, w, C)
+    assert abs(c - ref) <= 1e-6 * ref
+
+
+# ---------------------------------------------------------------------------
+# seeding
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n,d,k,weighted,seed", [(3000, 24, 6, False, 7), (10000, 64, 10, False, 0),
+                                                 (5000, 33, 40, True, 11), (2049, 5, 17, True, 3)])
+def test_seed_matches_oracle(ctx, n, d, k, weighted, seed):
+    say(f"seed n={n} d={d} k={k} w={weighted}")
+    X, _ = synth.isotropic_mixture(n, d, k, seed=seed)
+    w = synth.lognormal_weights(n, seed=seed) if weighted else None
+    if w is not None:
+        w[::5] = 0.0
+    C, idx = ctx.seed(_dev(X), k, w=None if w is None else _dev(w), rng_seed=seed)
+    Co, idx_o, _ = ok.seed(X, w, k, seed)
+    assert idx.cpu().numpy().tolist() == idx_o.tolist()
+    assert np.array_equal(C.cpu().numpy(), X[idx_o])
+
+
+def test_seed_zero_mass_fallback(ctx):
+    say("seed duplicates")
+    X = np.repeat(np.array([[1.0, 2.0], [3.0, 4.0]], dtype=np.float32), 50, axis=0)
+    C, idx = ctx.seed(_dev(X), 5, rng_seed=9)
+    Co, idx_o, _ = ok.seed(X, None, 5, 9)
+    assert idx.cpu().numpy().tolist() == idx_o.tolist()
+
+
+# ---------------------------------------------------------------------------
+# Lloyd end to end
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_lloyd_small_workload_end_to_end(ctx, prec):
+    # plain-method workload: n=10,000, d=64, 10 isotropic Gaussians (means in
+    # [-10,10]^64, sigma 1), k-means++ (seed 0) then 20 Lloyd iterations
+    say(f"lloyd small {prec}")
+    X, _ = synth.isotropic_mixture(10000, 64, 10, seed=0)
+    Xg = _dev(X)
+    C0, idx = ctx.seed(Xg, 10, rng_seed=0)
+    Co0, idx_o, _ = ok.seed(X, None, 10, 0)
+    assert idx.cpu().numpy().tolist() == idx_o.tolist()
+    C, lab, hist, it = ctx.lloyd(Xg, C0, 20, prec=prec)
+    ref = ok.lloyd(X, None, Co0, 20)
+    assert it == ref["iters"] == 20
+    _check_labels(lab.cpu().numpy(), X, ref["C"], "final labels")
+    np.testing.assert_allclose(hist, ref["cost"], rtol=1e-6)
+    Cg = C.cpu().numpy().astype(np.float64)
+    for j in range(10):
+        assert np.linalg.norm(Cg[j] - ref["C"][j]) <= 1e-5 * np.linalg.norm(ref["C"][j])
+
+
+def test_lloyd_weighted_ragged_teacher_forced(ctx):
+    # Teacher-forced step check on a weighted, ragged problem: each GPU
+    # iteration starts from the oracle's centers.
+    say("lloyd teacher forced")
+    n, d, k = 7001, 45, 23
+    X, _ = synth.isotropic_mixture(n, d, 15, seed=4)
+    w = synth.lognormal_weights(n, seed=4)
+    C, _, _ = ok.seed(X, w, k, 5)
+    C = C.astype(np.float32).astype(np.float64)
+    for t in range(4):
+        Cg, lab, hist, it = ctx.lloyd(_dev(X), _dev(C.astype(np.float32)), 1, w=_dev(w),
+                                      prec="bf16")
+        ref = ok.lloyd(X, w, C, 1)
+        assert it == 1
+        assert abs(hist[0] - ref["cost"][0]) <= 1e-6 * ref["cost"][0]
+        lab_o, _, _ = ok.assign(X, C)
+        Cn, _, _, _ = ok.update(X, w, lab_o, C)
+        Cn = Cn.astype(np.float32).astype(np.float64)
+        G = Cg.cpu().numpy().astype(np.float64)
+        for j in range(k):
+            assert np.linalg.norm(G[j] - Cn[j]) <= 1e-5 * max(np.linalg.norm(Cn[j]), 1e-3)
+        C = Cn
+
+
+def test_lloyd_early_stop_and_determinism(ctx):
+    say("lloyd early stop")
+    X, _ = synth.isotropic_mixture(6000, 20, 5, seed=8)
+    Xg = _dev(X)
+    C0 = _dev(X[:5])
+    C1, lab1, h1, it1 = ctx.lloyd(Xg, C0, 60, tol=0.0, prec="bf16")
+    ref = ok.lloyd(X, None, X[:5], 60, tol=0.0)
+    assert it1 == ref["iters"] and it1 < 60
+    np.testing.assert_allclose(h1, ref["cost"], rtol=1e-6)
+    C2, lab2, h2, it2 = ctx.lloyd(Xg, C0, 60, tol=0.0, prec="bf16")
+    assert torch.equal(C1, C2) and torch.equal(lab1, lab2) and h1 == h2
+
+
+def test_lloyd_zero_iterations(ctx):
+    X, _ = synth.isotropic_mixture(500, 7, 3, seed=1)
+    C, lab, hist, it = ctx.lloyd(_dev(X), _dev(X[:3]), 0, prec="fp32")
+    assert it == 0 and len(hist) == 1
+    assert abs(hist[0] - ok.cost(X, None, X[:3])) <= 1e-6 * hist[0]
+
+
+# ---------------------------------------------------------------------------
+# full-size workload: sampled rows
+# ---------------------------------------------------------------------------
+def test_assign_full_size_router_workload_sampled(ctx):
+    # n=4,000,000, d=512, k=1000 (means N(0,4I), sigma in [0.5,1.5]); labels of
+    # 2,000 sampled rows against the oracle, both precisions, plus the fraction
+    # of re-checked rows.
+    say("full-size assign n=4e6 d=512 k=1000")
+    n, d, k = 4_000_000, 512, 1000
+    Xg, means, sig = synth.router_mixture_device(n, d, k, seed=0)
+    rng = np.random.default_rng(0)
+    cidx = rng.choice(n, k, replace=False)
+    Cg = Xg[torch.from_numpy(cidx).to("cuda:0")].contiguous()
+    rows = np.sort(rng.choice(n, 2000, replace=False))
+    Xs = Xg[torch.from_numpy(rows).to("cuda:0")].cpu().numpy()
+    C = Cg.cpu().numpy()
+    for prec in ("bf16", "fp32"):
+        lab, _, _, nf = ctx.assign(Xg, Cg, prec=prec, want_d=False)
+        say(f"  {prec}: flagged {nf} of {n}")
+        _check_labels(lab.cpu().numpy()[rows], Xs, C, f"full {prec}")
+        assert nf < n // 2
+    del Xg
+    torch.cuda.empty_cache()

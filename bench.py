@@ -1,0 +1,194 @@
+"""Lloyd iterations per second on one MI355X.
+
+Workload (default): n = 4,000,000 points in d = 512 from a 1,000-component
+Gaussian mixture (means N(0, 4I), sigma_c uniform in [0.5, 1.5], row i in
+component i mod 1000), k = 1000, weighted k-means++ seeding (seed 0), then
+Lloyd iterations.  One step = one Lloyd iteration (assignment with the BF16
+MFMA distance GEMM + re-check of flagged rows, FP64 segmented reduction,
+new centroids, FP64 cost).  The same iterations on the plain FP32 path are
+timed from the same start and must reach the same cost within 1e-6 relative.
+
+Prints ONE JSON line.  Data is synthetic and generated on the device before
+the timed region; the seeding, the one-off BF16 copy of X and the plain-FP32
+comparison run are timed separately and reported as extra fields.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Lloyd iter/s (n=4M,d=512,k=1000) vs plain FP32 GPU, equal cost ±1e-6 rel"
+BF16_PEAK_TFLOPS = 2500.0    # MI355X dense BF16 MFMA
+FP32_PEAK_TFLOPS = 157.3     # MI355X FP32 matrix
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    "router": dict(n=4_000_000, d=512, k=1000, name="gaussian mixture n=4e6 d=512 k=1000 "
+                   "(means N(0,4I), sigma U[0.5,1.5])"),
+    "small": dict(n=10_000, d=64, k=10, name="isotropic mixture n=1e4 d=64 k=10 "
+                  "(means U[-10,10]^64, sigma 1)"),
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(X_host_rows, C_host, n_full, seconds_target=10.0):
+    """Times the FP64 oracle (assignment + update of one Lloyd iteration) on a
+    bounded row sample and scales to the full n."""
+    import numpy as np
+    from oracle import kmeans as ok
+
+    rows = X_host_rows
+    t0 = time.perf_counter()
+    probe = rows[:100]
+    lab, _, _ = ok.assign(probe, C_host)
+    ok.update(probe, None, lab, C_host)
+    t_probe = time.perf_counter() - t0
+    m = int(min(len(rows), max(100, 100 * seconds_target / max(t_probe, 1e-6))))
+    sample = rows[:m]
+    t0 = time.perf_counter()
+    lab, _, _ = ok.assign(sample, C_host)
+    ok.update(sample, None, lab, C_host)
+    t = time.perf_counter() - t0
+    sec_per_iter = t * n_full / m
+    return {"value": 1.0 / sec_per_iter, "unit": "iter/s", "cores": 1, "kind": "oracle",
+            "sample": f"one Lloyd iteration (FP64 assign + update) on {m} of {n_full} rows, "
+                      f"all {C_host.shape[0]} centers; {t:.1f} s measured, scaled by n",
+            "sec_per_iter": sec_per_iter}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="router", choices=sorted(WORKLOADS))
+    ap.add_argument("--fp32-steps", type=int, default=None,
+                    help="iterations of the plain FP32 comparison (default: --steps)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1502_04265_amd import kmx
+
+    wl = WORKLOADS[args.workload]
+    n, d, k = wl["n"], wl["d"], wl["k"]
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    log(f"[bench] generating {n}x{d} on device")
+    if args.workload == "router":
+        X, means, sig = synth.router_mixture_device(n, d, k, seed=0, device=dev)
+    else:
+        Xh, _ = synth.isotropic_mixture(n, d, k, seed=0)
+        X = torch.from_numpy(Xh).to(dev)
+    torch.cuda.synchronize()
+    ctx = kmx.Context(0)
+
+    # ---- seeding (not part of the per-iteration metric) ----
+    log("[bench] k-means++ seeding")
+    t0 = time.perf_counter()
+    C0, idx = ctx.seed(X, k, rng_seed=0)
+    torch.cuda.synchronize()
+    seed_ms = (time.perf_counter() - t0) * 1e3
+    log(f"[bench] seeding {seed_ms:.1f} ms")
+
+    # ---- one-off BF16 copy of X + warmup iterations ----
+    t0 = time.perf_counter()
+    Cw, _, hw, _ = ctx.lloyd(X, C0, args.warmup, prec="bf16", labels=False)
+    torch.cuda.synchronize()
+    warm_ms = (time.perf_counter() - t0) * 1e3
+    log(f"[bench] warmup ({args.warmup} iters incl. BF16 copy of X) {warm_ms:.1f} ms")
+
+    # ---- timed region: K Lloyd iterations on the BF16 path ----
+    ctx.timing(True, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Cb, lab_b, hist_b, it_b = ctx.lloyd(X, Cw, args.steps, prec="bf16", labels=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kt = ctx.timing_read()
+    ctx.timing(False, True)
+    ms_per_step = wall * 1e3 / args.steps
+    value = args.steps / wall
+    log(f"[bench] bf16: {ms_per_step:.3f} ms/iter, {value:.2f} iter/s, cost {hist_b[-1]:.9e}")
+
+    a_ms, a_cnt = kt["assign"]
+    assign_avg_ms = a_ms / max(a_cnt, 1)
+    flops = 2.0 * n * k * d
+    achieved = flops / (assign_avg_ms * 1e-3) / 1e12
+    r_ms, r_cnt = kt["reduce"]
+    reduce_avg_ms = r_ms / max(r_cnt, 1)
+    reduce_bytes = n * d * 4 + n * 4          # rows of X (FP32) + the permutation
+    reduce_gbs = reduce_bytes / (reduce_avg_ms * 1e-3) / 1e9
+
+    # rows needing the re-check at the final centers
+    _, _, _, nflag = ctx.assign(X, Cb, prec="bf16", want_d=False)
+    listed, via_fp32, full = ctx.assign_stats()
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "iter/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": wl["name"], "n": n, "d": d, "k": k,
+                   "assign": "bf16 MFMA GEMM + FP32 re-check", "reduce": "fp64"},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": BF16_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / BF16_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "assign_kernel<bf16>", "avg_ms": assign_avg_ms,
+                     "algorithmic_flops": flops},
+        "update_roofline": {"bound": "hbm", "achieved": reduce_gbs, "peak": HBM_PEAK_GBS,
+                            "unit": "GB/s", "frac": reduce_gbs / HBM_PEAK_GBS,
+                            "kernel": "reduce_kernel", "avg_ms": reduce_avg_ms},
+        "kernel_ms_per_step": {c: (v[0] / args.steps) for c, v in kt.items() if v[1]},
+        "seed_ms": seed_ms, "warmup_ms": warm_ms,
+        "recheck_rows_final": {"listed": listed, "via_fp32_gemm": via_fp32, "all_centers": full,
+                               "n": n},
+        "final_cost": hist_b[-1],
+    }
+
+    # ---- plain FP32 path from the same start ----
+    if not args.no_fp32:
+        ks = args.fp32_steps or args.steps
+        ctx.lloyd(X, Cw, 1, prec="fp32", labels=False)     # FP32 row statistics
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Cf, lab_f, hist_f, it_f = ctx.lloyd(X, Cw, ks, prec="fp32", labels=False)
+        torch.cuda.synchronize()
+        wf = time.perf_counter() - t0
+        log(f"[bench] fp32: {wf * 1e3 / ks:.3f} ms/iter, cost {hist_f[-1]:.9e}")
+        out["fp32_path"] = {"iter_per_s": ks / wf, "ms_per_step": wf * 1e3 / ks, "steps": ks,
+                            "final_cost": hist_f[-1]}
+        out["speedup_vs_fp32"] = value / (ks / wf)
+        if ks == args.steps:
+            rel = abs(hist_f[-1] - hist_b[-1]) / hist_f[-1]
+            out["equal_cost_rel_diff"] = rel
+            out["equal_cost"] = bool(rel <= 1e-6)
+
+    # ---- CPU oracle baseline on a bounded sample ----
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle)")
+        rows = X[:20000].cpu().numpy()
+        out["cpu_baseline"] = cpu_baseline(rows, Cb.cpu().numpy(), n)
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -94,7 +94,9 @@ kmx_status kmx_seed(kmx_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t 
  *   d2_out    device, n float32, nullable: second smallest distance as
  *             evaluated by the GEMM (within the GEMM's error bound; +inf if
  *             k == 1).
- *   n_flagged host, nullable: rows that needed the re-check (synchronizes).
+ *   n_flagged host, nullable: rows the first GEMM pass could not decide, i.e.
+ *             rows that went to the exact re-check or to the FP32 GEMM pass
+ *             (synchronizes).
  */
 kmx_status kmx_assign(kmx_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
                       const float* C, int32_t k, kmx_prec prec,
@@ -136,6 +138,15 @@ kmx_status kmx_lloyd(kmx_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t
                      const float* w, float* C_inout, int32_t k, int32_t max_iter,
                      double tol, kmx_prec prec, int32_t* label_out,
                      double* cost_hist, int32_t* iters_done);
+
+/* Re-check counts of the most recent assignment on ctx (kmx_assign, kmx_cost,
+ * or the final assignment of kmx_lloyd); host outputs, each nullable:
+ *   listed   rows on the exact re-check list (pairs and full rows),
+ *   fp32     rows the BF16 GEMM passed to the FP32 GEMM because three or more
+ *            centers lay within its error bound,
+ *   full     rows re-checked against every center.
+ * Synchronizes. */
+kmx_status kmx_assign_stats(kmx_ctx* ctx, int64_t* listed, int64_t* fp32, int64_t* full);
 
 /* Kernel timing for measurement: while enabled, HIP events bracket every
  * kernel class on the context's stream.  kmx_timing_read returns the summed

@@ -2,33 +2,40 @@
 // closest center), as a distance GEMM on the gfx950 matrix cores with the
 // argmin fused into the epilogue.
 //
-// Ranking.  ||x - c_j||^2 = ||x||^2 - 2 (x.c_j - ||c_j||^2 / 2), so the
-// closest center maximizes tau_j = x.c_j - h_j with h_j = ||c_j||^2 / 2.  The
-// GEMM produces x~.c~_j (BF16 or FP32 operands, FP32 accumulation); the
-// epilogue forms t_j = x~.c~_j - h_j + o_x with a per-row offset o_x that
-// makes every t_j positive, so its float bits order like unsigned integers.
-// The low `ib` bits are replaced by (mask - j): one unsigned max then keeps
-// the best score and, on equal truncated scores, the lowest index.  Each lane
-// keeps the top three keys of the centers it sees; lanes holding the same
-// point merge at the end.
+// Ranking.  ||x - c_j||^2 = ||x||^2 - 2 (x.c_j - h_j) with h_j = ||c_j||^2 / 2,
+// so the closest center maximizes x.c_j - h_j.  The kernel forms the positive
+// score t_j = x~.c~_j - h_j + O (x~, c~ the GEMM operands: BF16 copies, or the
+// FP32 values), whose float bits order like unsigned integers.
+//   BF16: the rows of X carry three extra columns equal to -1 and the centers
+//     carry h_j - O split into three BF16 terms, so the MFMA accumulator *is*
+//     t_j; O is one offset per assignment (max row norm times max center norm
+//     plus max h).
+//   FP32: t_j = (acc - h_j) + o_x with a per-row offset o_x, clamped at 0.
+// The low `ib` bits of t_j are replaced by (mask - j): an unsigned max keeps
+// the best score and, between equal truncated scores, the lowest index.  A
+// lane keeps the three largest keys it has seen (max, med3, med3); the four
+// lanes holding one point merge at the end.
 //
-// Soundness.  For every center |t_j - (tau_j + o_x)| <= E(x), where E bounds
-// the FP32 accumulation (gamma_K ||x~|| ||c~||), the quantization of both
-// operands (||x - x~|| ||c~|| + ||x|| ||c - c~||), the rounding of h_j and of
-// the epilogue, and the key truncation.  If t_1 - t_2 > 2E the GEMM's top-1 is
-// the exact argmin.  Otherwise the row is flagged: when t_1 - t_3 > 2E only
-// the two listed centers can win and the re-check compares those two;
-// otherwise it re-checks every center.  The re-check computes distances as
-// FP32 direct differences with error-free transformations (TwoSum/TwoProd
-// double-float accumulation), so labels agree with exact arithmetic except
-// on ties closer than about 1e-13 relative.
+// Soundness.  For every center |t_j - (x.c_j - h_j + O)| <= E(x), where E
+// covers the FP32 accumulation (gamma_K sum |x~_i c~_ji|), the quantization of
+// both operands (||x - x~|| ||c~|| + ||x|| ||c - c~||), the rounding of h_j and
+// of the epilogue, and the key truncation.  If t_1 - t_2 > 2E the top key's
+// center is the exact argmin.  Otherwise the row is flagged: when
+// t_1 - t_3 > 2E only the two listed centers can win and the re-check compares
+// them exactly; otherwise the row needs every center: the BF16 pass sends it
+// to the FP32 pass (same kernel, FP32 operands, list of rows), whose much
+// tighter bound leaves it as a two-candidate re-check in all but exceptional
+// cases; rows still open after the FP32 pass are re-checked against every
+// center.  The re-check computes FP32 direct differences with error-free
+// transformations (double-float accumulation), so labels agree with exact
+// arithmetic except on ties closer than about 1e-13 relative.
 //
 // Layout.  MFMA 16x16x32 BF16 (or 16x16x4 FP32): A = 16 centers x K (from
-// LDS), B = K x 16 points (held in registers for the whole center loop),
+// LDS), B = K x 16 points (registers, loaded once per block of points),
 // D[center][point]: lane l holds point l%16 and centers 4(l/16)+i.  Each lane
 // reads 16 contiguous bytes of a row per "unit" (8 BF16 or 4 FP32); A and B
-// use the same unit-to-k mapping, so the contraction order inside a unit is
-// irrelevant to the result's definition.
+// use the same unit-to-k mapping, so the contraction order inside a unit does
+// not change what is computed.
 #include "kmx_device.h"
 #include "kmx_internal.h"
 
@@ -38,322 +45,515 @@ typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8_t;
 typedef __attribute__((ext_vector_type(4))) float f32x4_t;
 typedef __attribute__((ext_vector_type(4))) unsigned int u32x4_t;
 
-__device__ __forceinline__ void top3_insert(unsigned key, unsigned& v1, unsigned& v2,
-                                            unsigned& v3) {
-  unsigned a = max(v1, key), b = min(v1, key);
-  v1 = a;
-  unsigned c = max(v2, b), e = min(v2, b);
-  v2 = c;
-  v3 = max(v3, e);
+__device__ __forceinline__ unsigned med3u(unsigned a, unsigned b, unsigned c) {
+  return max(min(a, b), min(max(a, b), c));
 }
 
-template <bool BF16, int NKU, int NCG, int BN, int WAVES>
+// (v1 >= v2 >= v3) <- the three largest of {v1, v2, v3, key}
+__device__ __forceinline__ void top3_insert(unsigned key, unsigned& v1, unsigned& v2,
+                                            unsigned& v3) {
+  const unsigned n1 = max(v1, key);
+  const unsigned n2 = med3u(v1, v2, key);
+  const unsigned n3 = med3u(v2, v3, key);
+  v1 = n1;
+  v2 = n2;
+  v3 = n3;
+}
+
+template <bool BF16, int NKU, int NCG, int BN, int WAVES, int PF = 1>
 __global__ __launch_bounds__(WAVES * 64) void assign_kernel(
-    const void* __restrict__ Xsrc, int64_t xs, int vec_ok, int64_t n, int d, int dp,
+    const void* __restrict__ Xsrc, int64_t xs, int vec_ok, int64_t n, const int* __restrict__ rows,
+    const unsigned long long* __restrict__ row_count, int d, int dp,
     const RowStats* __restrict__ rs, const void* __restrict__ Cq, const float* __restrict__ ch,
     int k, int kpad, int ib, const CenterStats* __restrict__ cs, int32_t* __restrict__ label,
     float* __restrict__ d1o, float* __restrict__ d2o, FlagEntry* __restrict__ flags,
-    LoopState* __restrict__ st, const int* __restrict__ done) {
-  if (done && *done) return;
+    int* __restrict__ full_rows, int* __restrict__ brute, LoopState* __restrict__ st,
+    const int* __restrict__ gate) {
+  if (gate && *gate) return;
   constexpr int NT = WAVES * 64;
   constexpr int RB = BN / 16;
   constexpr int ROWB = NKU * 64;         // bytes of one center row (all units)
-  constexpr int PITCH = ROWB + 16;       // padded LDS row pitch
-  constexpr int UNITS = BN * NKU * 4;    // 16-byte units per tile
-  constexpr int UPT = (UNITS + NT - 1) / NT;
-  __shared__ __attribute__((aligned(16))) unsigned char lds[2][BN * PITCH];
+  constexpr int PITCH = ROWB + 16;       // padded LDS row pitch (16-byte units: NKU*4 + 1)
+  constexpr int UROW = NKU * 4 + 1;      // 16-byte units per LDS row
+  constexpr int CHUNKS = (BN * UROW + 63) / 64;  // 1 KB direct-to-LDS copies per tile
+  constexpr int BUFB = CHUNKS * 1024;    // bytes of one tile buffer
+  constexpr int PPB = WAVES * 16 * NCG;  // points per block
+  __shared__ __attribute__((aligned(1024))) unsigned char lds[2][BUFB];
   __shared__ __attribute__((aligned(16))) float hsh[2][BN];
+  __shared__ int wcnt[3][WAVES];
+  __shared__ unsigned long long wbase[3];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int prow = lane & 15;
   const int grp = lane >> 4;
-  const int64_t p_base = ((int64_t)blockIdx.x * WAVES + wave) * (16 * NCG);
 
-  // ---- point fragments (B operand), loaded once ----
-  u32x4_t xf[NCG][NKU];
-#pragma unroll
-  for (int cg = 0; cg < NCG; ++cg) {
-    const int64_t p = p_base + cg * 16 + prow;
-    const bool pv = p < n;
-#pragma unroll
-    for (int ku = 0; ku < NKU; ++ku) {
-      u32x4_t v = {0u, 0u, 0u, 0u};
-      if (BF16) {
-        if (pv) {
-          const uint16_t* src = (const uint16_t*)Xsrc + p * xs + ku * 32 + grp * 8;
-          v = *(const u32x4_t*)src;
-        }
-      } else {
-        const int e0 = ku * 16 + grp * 4;
-        const float* src = (const float*)Xsrc + p * xs + e0;
-        if (pv) {
-          if (vec_ok && e0 + 4 <= d) {
-            v = *(const u32x4_t*)src;
-          } else {
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-              if (e0 + q < d) v[q] = __float_as_uint(src[q]);
-          }
-        }
-      }
-      xf[cg][ku] = v;
-    }
-  }
+  const int64_t npts = rows ? (int64_t)(*row_count) : n;
+  const int64_t nblk = (npts + PPB - 1) / PPB;
+  const int ntiles = kpad / BN;
+  const unsigned mask = (ib >= 32) ? 0xFFFFFFFFu : ((1u << ib) - 1u);
 
-  // ---- per-point offset o_x so that every score is positive ----
   const float cqm = __uint_as_float(cs->cq_max);
   const float rcm = __uint_as_float(cs->rc_max);
   const float cnm = __uint_as_float(cs->cn_max);
-  float ox[NCG];
-#pragma unroll
-  for (int cg = 0; cg < NCG; ++cg) {
-    const int64_t p = p_base + cg * 16 + prow;
-    float nxq = (p < n) ? rs[p].nxq : 0.0f;
-    ox[cg] = (nxq * cqm + 0.5f * cnm * cnm) * 1.001f + 1.0f;
-  }
+  const float Og = cs->O;
 
-  const unsigned mask = (ib >= 32) ? 0xFFFFFFFFu : ((1u << ib) - 1u);
-  unsigned v1[NCG], v2[NCG], v3[NCG];
-#pragma unroll
-  for (int cg = 0; cg < NCG; ++cg) v1[cg] = v2[cg] = v3[cg] = 0u;
+  for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+    const int64_t p_base = blk * PPB + (int64_t)wave * (16 * NCG);
 
-  const int ntiles = kpad / BN;
-  u32x4_t stage[UPT];
-  float hstage = 0.0f;
-
-  auto gload = [&](int tile) {
+    // ---- point fragments (B operand) for this block ----
+    int64_t src_row[NCG];
+    u32x4_t xf[NCG][NKU];
 #pragma unroll
-    for (int i = 0; i < UPT; ++i) {
-      const int u = tid + NT * i;
-      if (u < UNITS) {
-        const int row = u / (NKU * 4);
-        const int col = u % (NKU * 4);
-        const unsigned char* src = (const unsigned char*)Cq +
-                                   ((int64_t)(tile * BN + row)) * ROWB + col * 16;
-        stage[i] = *(const u32x4_t*)src;
+    for (int cg = 0; cg < NCG; ++cg) {
+      const int64_t p = p_base + cg * 16 + prow;
+      const bool pv = p < npts;
+      const int64_t r = pv ? (rows ? (int64_t)rows[p] : p) : -1;
+      src_row[cg] = r;
+#pragma unroll
+      for (int ku = 0; ku < NKU; ++ku) {
+        u32x4_t v = {0u, 0u, 0u, 0u};
+        if (BF16) {
+          if (pv) v = *(const u32x4_t*)((const uint16_t*)Xsrc + r * xs + ku * 32 + grp * 8);
+        } else {
+          const int e0 = ku * 16 + grp * 4;
+          const float* src = (const float*)Xsrc + r * xs + e0;
+          if (pv) {
+            if (vec_ok && e0 + 4 <= d) {
+              v = *(const u32x4_t*)src;
+            } else {
+#pragma unroll
+              for (int q = 0; q < 4; ++q)
+                if (e0 + q < d) v[q] = __float_as_uint(src[q]);
+            }
+          }
+        }
+        xf[cg][ku] = v;
       }
     }
-    if (tid < BN) hstage = ch[tile * BN + tid];
-  };
-  auto lstore = [&](int buf) {
+
+    // BF16 state: three packed keys per point.  FP32 state: the three best
+    // scores and the indices of the first two, kept exactly.
+    unsigned v1[NCG], v2[NCG], v3[NCG];
+    float f1[NCG], f2[NCG], f3[NCG];
+    int j1[NCG], j2[NCG];
 #pragma unroll
-    for (int i = 0; i < UPT; ++i) {
-      const int u = tid + NT * i;
-      if (u < UNITS) {
-        const int row = u / (NKU * 4);
-        const int col = u % (NKU * 4);
-        *(u32x4_t*)(&lds[buf][row * PITCH + col * 16]) = stage[i];
-      }
+    for (int cg = 0; cg < NCG; ++cg) {
+      v1[cg] = v2[cg] = v3[cg] = 0u;
+      f1[cg] = f2[cg] = f3[cg] = -__builtin_inff();
+      j1[cg] = j2[cg] = 0x7FFFFFFF;
     }
-    if (tid < BN) hsh[buf][tid] = hstage;
-  };
 
-  gload(0);
-  lstore(0);
-  __syncthreads();
+    // Tile copy: LDS chunk c (1 KB) receives the 16-byte units c*64 .. c*64+63
+    // of the padded tile, lane l the unit c*64 + l (the order the direct-to-LDS
+    // load writes them).  Pad units re-load the tile's first unit.
+    float hstage = 0.0f;
+    auto issue_tile = [&](int tile, int buf) {
+      const unsigned char* tbase = (const unsigned char*)Cq + (int64_t)tile * BN * ROWB;
+#pragma unroll
+      for (int c = wave; c < CHUNKS; c += WAVES) {
+        const int q = c * 64 + lane;
+        const int row = q / UROW;
+        const int uc = q - row * UROW;
+        const unsigned char* src =
+            (row < BN && uc < NKU * 4) ? tbase + row * ROWB + uc * 16 : tbase;
+        __builtin_amdgcn_global_load_lds(
+            (const void*)src, (__attribute__((address_space(3))) void*)(&lds[buf][c * 1024]), 16,
+            0, 0);
+      }
+      if (!BF16 && tid < BN) hstage = ch[tile * BN + tid];
+    };
+    auto finish_tile = [&](int buf) {
+      if (!BF16 && tid < BN) hsh[buf][tid] = hstage;
+      __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    };
 
-  for (int t = 0; t < ntiles; ++t) {
-    const int buf = t & 1;
-    if (t + 1 < ntiles) gload(t + 1);
+    issue_tile(0, 0);
+    finish_tile(0);
+    __syncthreads();
 
-    f32x4_t acc[NCG][RB];
-#pragma unroll
-    for (int cg = 0; cg < NCG; ++cg)
-#pragma unroll
-      for (int rb = 0; rb < RB; ++rb) acc[cg][rb] = (f32x4_t){0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < ntiles; ++t) {
+      const int buf = t & 1;
+      if (t + 1 < ntiles) issue_tile(t + 1, buf ^ 1);
 
+      f32x4_t acc[NCG][RB];
 #pragma unroll
-    for (int ku = 0; ku < NKU; ++ku) {
+      for (int cg = 0; cg < NCG; ++cg)
 #pragma unroll
-      for (int rb = 0; rb < RB; ++rb) {
-        const u32x4_t a =
-            *(const u32x4_t*)(&lds[buf][(rb * 16 + prow) * PITCH + ku * 64 + grp * 16]);
+        for (int rb = 0; rb < RB; ++rb) acc[cg][rb] = (f32x4_t){0.f, 0.f, 0.f, 0.f};
+
+      // A fragments run PF units ahead of the MFMAs that use them; the
+      // scheduling barrier keeps the compiler from sinking the reads.
+      constexpr int NB = PF + 1;
+      u32x4_t afr[NB][RB];
+      const unsigned char* abase = &lds[buf][prow * PITCH + grp * 16];
 #pragma unroll
-        for (int cg = 0; cg < NCG; ++cg) {
-          if (BF16) {
-            acc[cg][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                __builtin_bit_cast(bf16x8_t, a), __builtin_bit_cast(bf16x8_t, xf[cg][ku]),
-                acc[cg][rb], 0, 0, 0);
-          } else {
+      for (int q = 0; q < PF; ++q)
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
-              acc[cg][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(
-                  __uint_as_float(a[q]), __uint_as_float(xf[cg][ku][q]), acc[cg][rb], 0, 0, 0);
+        for (int rb = 0; rb < RB; ++rb)
+          if (q < NKU) afr[q][rb] = *(const u32x4_t*)(abase + rb * 16 * PITCH + q * 64);
+#pragma unroll
+      for (int ku = 0; ku < NKU; ++ku) {
+        if (ku + PF < NKU) {
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb)
+            afr[(ku + PF) % NB][rb] =
+                *(const u32x4_t*)(abase + rb * 16 * PITCH + (ku + PF) * 64);
+        }
+        if (PF > 1) __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+          const u32x4_t a = afr[ku % NB][rb];
+#pragma unroll
+          for (int cg = 0; cg < NCG; ++cg) {
+            if (BF16) {
+              acc[cg][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                  __builtin_bit_cast(bf16x8_t, a), __builtin_bit_cast(bf16x8_t, xf[cg][ku]),
+                  acc[cg][rb], 0, 0, 0);
+            } else {
+#pragma unroll
+              for (int q = 0; q < 4; ++q)
+                acc[cg][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                    __uint_as_float(a[q]), __uint_as_float(xf[cg][ku][q]), acc[cg][rb], 0, 0,
+                    0);
+            }
           }
         }
       }
+
+      // ---- epilogue: running top-3 ----
+      if constexpr (BF16) {
+        const unsigned ibase = mask - (unsigned)(t * BN + grp * 4);
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const unsigned idx = ibase - (unsigned)(rb * 16 + i);
+#pragma unroll
+            for (int cg = 0; cg < NCG; ++cg) {
+              const unsigned key = (__float_as_uint(acc[cg][rb][i]) & ~mask) | idx;
+              top3_insert(key, v1[cg], v2[cg], v3[cg]);
+            }
+          }
+        }
+      } else {
+        // centers arrive in increasing index order per lane: a strict '>'
+        // keeps the lower index on ties
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+          const f32x4_t hv = *(const f32x4_t*)(&hsh[buf][rb * 16 + grp * 4]);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int j = t * BN + rb * 16 + grp * 4 + i;
+#pragma unroll
+            for (int cg = 0; cg < NCG; ++cg) {
+              const float tt = acc[cg][rb][i] - hv[i];
+              const bool c1 = tt > f1[cg], c2 = tt > f2[cg], c3 = tt > f3[cg];
+              f3[cg] = c2 ? f2[cg] : (c3 ? tt : f3[cg]);
+              f2[cg] = c1 ? f1[cg] : (c2 ? tt : f2[cg]);
+              j2[cg] = c1 ? j1[cg] : (c2 ? j : j2[cg]);
+              f1[cg] = c1 ? tt : f1[cg];
+              j1[cg] = c1 ? j : j1[cg];
+            }
+          }
+        }
+      }
+
+      if (t + 1 < ntiles) finish_tile(buf ^ 1);
+      __syncthreads();
     }
 
-    // ---- epilogue: scores -> keys -> running top-3 ----
-    const bool last = (t == ntiles - 1);
-    const unsigned ibase = mask - (unsigned)(t * BN + grp * 4);
+    // ---- merge the four lanes that hold the same point ----
 #pragma unroll
-    for (int rb = 0; rb < RB; ++rb) {
-      const f32x4_t hv = *(const f32x4_t*)(&hsh[buf][rb * 16 + grp * 4]);
+    for (int cg = 0; cg < NCG; ++cg) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int jl = rb * 16 + grp * 4 + i;  // center within the tile
-        const bool valid = !last || (t * BN + jl < k);
+      for (int m = 16; m <= 32; m <<= 1) {
+        if constexpr (BF16) {
+          const unsigned o1 = __shfl_xor(v1[cg], m, 64);
+          const unsigned o2 = __shfl_xor(v2[cg], m, 64);
+          const unsigned o3 = __shfl_xor(v3[cg], m, 64);
+          top3_insert(o1, v1[cg], v2[cg], v3[cg]);
+          top3_insert(o2, v1[cg], v2[cg], v3[cg]);
+          top3_insert(o3, v1[cg], v2[cg], v3[cg]);
+        } else {
+          const float g1 = __shfl_xor(f1[cg], m, 64), g2 = __shfl_xor(f2[cg], m, 64);
+          const float g3 = __shfl_xor(f3[cg], m, 64);
+          const int k1 = __shfl_xor(j1[cg], m, 64), k2 = __shfl_xor(j2[cg], m, 64);
+          // insert (g1,k1), (g2,k2) with the index tie-break, then g3 as a value
 #pragma unroll
-        for (int cg = 0; cg < NCG; ++cg) {
-          const float tt = (acc[cg][rb][i] - hv[i]) + ox[cg];
-          unsigned key = (__float_as_uint(tt) & ~mask) | (ibase - (unsigned)(rb * 16 + i));
-          key = valid ? key : 0u;
-          top3_insert(key, v1[cg], v2[cg], v3[cg]);
+          for (int q = 0; q < 2; ++q) {
+            const float tt = q ? g2 : g1;
+            const int jj = q ? k2 : k1;
+            const bool c1 = tt > f1[cg] || (tt == f1[cg] && jj < j1[cg]);
+            const bool c2 = tt > f2[cg] || (tt == f2[cg] && jj < j2[cg]);
+            const bool c3 = tt > f3[cg];
+            f3[cg] = c2 ? f2[cg] : (c3 ? tt : f3[cg]);
+            f2[cg] = c1 ? f1[cg] : (c2 ? tt : f2[cg]);
+            j2[cg] = c1 ? j1[cg] : (c2 ? jj : j2[cg]);
+            f1[cg] = c1 ? tt : f1[cg];
+            j1[cg] = c1 ? jj : j1[cg];
+          }
+          f3[cg] = fmaxf(f3[cg], g3);
         }
       }
     }
 
-    if (t + 1 < ntiles) lstore(buf ^ 1);
+    // ---- decision, outputs, re-check lists ----
+    const float ua = 1.1920929e-7f;  // 2^-23: covers any faithful accumulation rounding
+    const float u = 5.9604645e-8f;   // 2^-24
+    const float Kf = (float)(dp + 1);
+    const float gam = Kf * ua / (1.0f - Kf * ua);
+    unsigned long long fmask[NCG], gmask[NCG], bmask[NCG];
+    int cand2v[NCG];
+    int nf_w = 0, ng_w = 0, nfull_w = 0;
+#pragma unroll
+    for (int cg = 0; cg < NCG; ++cg) {
+      const int64_t r = src_row[cg];
+      const bool writer = (grp == (cg & 3)) && (r >= 0);
+      bool flagged = false, full = false;
+      int cand2 = 0;
+      if (writer) {
+        const RowStats rw = rs[r];
+        float t1, t2 = 0.f, t3 = 0.f, E, off;
+        int i1;
+        bool has2, has3;
+        if constexpr (BF16) {
+          const unsigned hi = ~mask;
+          off = Og;
+          E = gam * (rw.nxq * cqm + Og) + rw.rx * cqm + rw.nx * rcm + 3.0f * u * Og +
+              ldexpf(2.0f * Og, ib - 23);
+          t1 = __uint_as_float(v1[cg] & hi);
+          i1 = (v1[cg] & hi) ? min((int)(mask - (v1[cg] & mask)), k - 1) : 0;
+          has2 = (v2[cg] & hi) != 0u;
+          has3 = (v3[cg] & hi) != 0u;
+          if (has2) {
+            t2 = __uint_as_float(v2[cg] & hi);
+            cand2 = min((int)(mask - (v2[cg] & mask)), k - 1);
+          }
+          if (has3) t3 = __uint_as_float(v3[cg] & hi);
+        } else {
+          off = 0.0f;
+          E = (gam + u) * rw.nx * cnm + 1.5f * u * cnm * cnm;
+          t1 = f1[cg];
+          i1 = min(max(j1[cg], 0), k - 1);
+          has2 = f2[cg] > -__builtin_inff();
+          has3 = f3[cg] > -__builtin_inff();
+          if (has2) {
+            t2 = f2[cg];
+            cand2 = min(max(j2[cg], 0), k - 1);
+          }
+          if (has3) t3 = f3[cg];
+        }
+        E *= 1.0001f;
+        label[r] = i1;
+        if (d1o) d1o[r] = fmaxf(rw.xn2 - 2.0f * (t1 - off), 0.0f);
+        if (has2) {
+          if (d2o) d2o[r] = fmaxf(rw.xn2 - 2.0f * (t2 - off), 0.0f);
+          flagged = (t1 - t2) <= 2.0f * E;
+          if (flagged && has3) full = (t1 - t3) <= 2.0f * E;
+        } else if (d2o) {
+          d2o[r] = __builtin_inff();
+        }
+      }
+      const bool to_full = full && (full_rows != nullptr);
+      const bool to_brute = full && (full_rows == nullptr);
+      const bool to_flags = flagged && !full;
+      fmask[cg] = __ballot(to_flags);
+      gmask[cg] = __ballot(to_full);
+      bmask[cg] = __ballot(to_brute);
+      cand2v[cg] = cand2;
+      nf_w += __popcll(fmask[cg]);
+      ng_w += __popcll(gmask[cg]);
+      nfull_w += __popcll(bmask[cg]);
+    }
+    // one atomic per list and workgroup; waves take consecutive slices
+    if (lane == 0) {
+      wcnt[0][wave] = nf_w;
+      wcnt[1][wave] = ng_w;
+      wcnt[2][wave] = nfull_w;
+    }
     __syncthreads();
-  }
-
-  // ---- merge the four lanes that hold the same point ----
-#pragma unroll
-  for (int cg = 0; cg < NCG; ++cg) {
-#pragma unroll
-    for (int m = 16; m <= 32; m <<= 1) {
-      unsigned o1 = __shfl_xor(v1[cg], m, 64);
-      unsigned o2 = __shfl_xor(v2[cg], m, 64);
-      unsigned o3 = __shfl_xor(v3[cg], m, 64);
-      top3_insert(o1, v1[cg], v2[cg], v3[cg]);
-      top3_insert(o2, v1[cg], v2[cg], v3[cg]);
-      top3_insert(o3, v1[cg], v2[cg], v3[cg]);
-    }
-  }
-
-  // ---- decision, outputs and the re-check list ----
-  const float ua = 1.1920929e-7f;   // 2^-23: covers any faithful accumulation rounding
-  const float u = 5.9604645e-8f;    // 2^-24
-  const float Kf = (float)(dp + 1);
-  const float gam = Kf * ua / (1.0f - Kf * ua);
-#pragma unroll
-  for (int cg = 0; cg < NCG; ++cg) {
-    const int64_t p = p_base + cg * 16 + prow;
-    const bool writer = (grp == (cg & 3)) && (p < n);
-    bool flagged = false, full = false;
-    int cand2 = 0;
-    if (writer) {
-      const RowStats r = rs[p];
-      const float o = ox[cg];
-      float E = gam * r.nxq * cqm + r.rx * cqm + r.nx * rcm + u * 0.5f * cnm * cnm +
-                4.0f * u * o + ldexpf(2.0f * o, ib - 23);
-      E = E * 1.0001f;
-      const float t1 = __uint_as_float(v1[cg] & ~mask);
-      // keys of real centers are never 0; the clamps only guard non-finite input
-      const int i1 = v1[cg] ? min((int)(mask - (v1[cg] & mask)), k - 1) : 0;
-      label[p] = i1;
-      if (d1o) d1o[p] = fmaxf(r.xn2 - 2.0f * (t1 - o), 0.0f);
-      if (v2[cg] != 0u) {
-        const float t2 = __uint_as_float(v2[cg] & ~mask);
-        cand2 = min((int)(mask - (v2[cg] & mask)), k - 1);
-        if (d2o) d2o[p] = fmaxf(r.xn2 - 2.0f * (t2 - o), 0.0f);
-        flagged = (t1 - t2) <= 2.0f * E;
-        if (flagged && v3[cg] != 0u) {
-          const float t3 = __uint_as_float(v3[cg] & ~mask);
-          full = (t1 - t3) <= 2.0f * E;
-        }
-      } else if (d2o) {
-        d2o[p] = __builtin_inff();
+    if (tid == 0) {
+      int sf = 0, sg = 0, sx = 0;
+      for (int w = 0; w < WAVES; ++w) {
+        sf += wcnt[0][w];
+        sg += wcnt[1][w];
+        sx += wcnt[2][w];
       }
+      wbase[0] = sf ? atomicAdd(&st->flagged, (unsigned long long)sf) : 0ull;
+      wbase[1] = sg ? atomicAdd(&st->full_count, (unsigned long long)sg) : 0ull;
+      wbase[2] = sx ? atomicAdd(&st->flagged_full, (unsigned long long)sx) : 0ull;
+      if (!rows && (sf + sg + sx)) atomicAdd(&st->undecided, (unsigned long long)(sf + sg + sx));
     }
-    const unsigned long long fm = __ballot(flagged);
-    if (fm) {
-      const unsigned long long ffm = __ballot(full);
-      unsigned long long basei = 0;
-      if (lane == 0) {
-        basei = atomicAdd(&st->flagged, (unsigned long long)__popcll(fm));
-        if (ffm) atomicAdd(&st->flagged_full, (unsigned long long)__popcll(ffm));
-      }
-      basei = __shfl(basei, 0, 64);
-      if (flagged) {
-        const unsigned long long below = fm & ((1ull << lane) - 1ull);
+    __syncthreads();
+    unsigned long long of = wbase[0], og = wbase[1], ob = wbase[2];
+    for (int w = 0; w < wave; ++w) {
+      of += wcnt[0][w];
+      og += wcnt[1][w];
+      ob += wcnt[2][w];
+    }
+    const unsigned long long below = (1ull << lane) - 1ull;
+#pragma unroll
+    for (int cg = 0; cg < NCG; ++cg) {
+      if ((fmask[cg] >> lane) & 1ull) {
         FlagEntry fe;
-        fe.row = (int)p | (full ? (int)0x80000000 : 0);
-        fe.cand2 = cand2;
-        flags[basei + __popcll(below)] = fe;
+        fe.row = (int)src_row[cg];
+        fe.cand2 = cand2v[cg];
+        flags[of + __popcll(fmask[cg] & below)] = fe;
       }
+      if ((gmask[cg] >> lane) & 1ull) full_rows[og + __popcll(gmask[cg] & below)] = (int)src_row[cg];
+      if ((bmask[cg] >> lane) & 1ull) brute[ob + __popcll(bmask[cg] & below)] = (int)src_row[cg];
+      of += __popcll(fmask[cg]);
+      og += __popcll(gmask[cg]);
+      ob += __popcll(bmask[cg]);
     }
+    __syncthreads();
   }
 }
 
 // ---------------------------------------------------------------------------
-// Kernel configurations.  dp is the padded row length: BF16 rows are padded
-// to a multiple of 32 elements (one 16x16x32 unit), FP32 rows to 16.
+// Kernel configurations.
+// BF16 rows hold d values, zero padding and three -1 columns: dp = 32*NKU with
+// NKU the first entry of kBf16Units covering d + 3.  FP32 rows are padded to
+// 16*NKU, NKU a power of two.
 // ---------------------------------------------------------------------------
+static const int kBf16Units[] = {1, 2, 3, 5, 9, 17, 24, 32, 33};
+
 static int units_for(int prec, int d) {
-  const int kpu = (prec == KMX_BF16) ? 32 : 16;
-  int u = (d + kpu - 1) / kpu;
+  if (prec == KMX_BF16) {
+    const int need = (d + 3 + 31) / 32;
+    for (int u : kBf16Units)
+      if (u >= need) return u;
+    return -1;
+  }
+  const int need = (d + 15) / 16;
   int p = 1;
-  while (p < u) p <<= 1;
-  return p;
+  while (p < need) p <<= 1;
+  return p <= 64 ? p : -1;
 }
 
 int assign_dpad(int prec, int d) {
-  const int kpu = (prec == KMX_BF16) ? 32 : 16;
-  return units_for(prec, d) * kpu;
+  const int u = units_for(prec, d);
+  if (u < 0) return -1;
+  return u * ((prec == KMX_BF16) ? 32 : 16);
 }
 
-// Centers per LDS tile: each of the two tile buffers stays within about 66 KB.
+// Centers per LDS tile: each of the two tile buffers stays within ~72 KB.
 int assign_tile_n(int prec, int d) {
   const int nku = units_for(prec, d);
-  if (prec == KMX_BF16) return (nku <= 16) ? 64 : 32;
+  if (prec == KMX_BF16) {
+    if (nku <= 3 || nku == 9) return 64;
+    if (nku == 17) return 64;   // every d=512 variant tiles kpad in multiples of 64
+    if (nku <= 32) return 32;
+    return 16;
+  }
   if (nku <= 4) return 64;
   if (nku <= 32) return 32;
   return 16;
 }
 
-template <bool BF16, int NKU, int NCG, int BN, int WAVES>
+template <bool BF16, int NKU, int NCG, int BN, int WAVES, int PF = 1>
 static hipError_t run_assign(hipStream_t s, const void* Xsrc, int64_t xs, int vec_ok, int64_t n,
-                             int d, int dp, const RowStats* rs, const void* Cq, const float* ch,
-                             int k, int kpad, int ib, const CenterStats* cs, int32_t* label,
-                             float* d1, float* d2, FlagEntry* flags, LoopState* st,
-                             const int* gate) {
+                             const int* rows, const unsigned long long* row_count, int d, int dp,
+                             const RowStats* rs, const void* Cq, const float* ch, int k, int kpad,
+                             int ib, const CenterStats* cs, int32_t* label, float* d1, float* d2,
+                             FlagEntry* flags, int* full_rows, int* brute, LoopState* st,
+                             const int* gate, int num_cus) {
   const int64_t ppb = (int64_t)WAVES * 16 * NCG;
-  const int64_t blocks = (n + ppb - 1) / ppb;
-  hipLaunchKernelGGL((assign_kernel<BF16, NKU, NCG, BN, WAVES>), dim3((unsigned)blocks),
-                     dim3(WAVES * 64), 0, s, Xsrc, xs, vec_ok, n, d, dp, rs, Cq, ch, k, kpad, ib,
-                     cs, label, d1, d2, flags, st, gate);
+  int64_t blocks = (n + ppb - 1) / ppb;
+  if (rows) {
+    const int64_t cap = (int64_t)num_cus * 2;
+    if (blocks > cap) blocks = cap;
+  }
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL((assign_kernel<BF16, NKU, NCG, BN, WAVES, PF>), dim3((unsigned)blocks),
+                     dim3(WAVES * 64), 0, s, Xsrc, xs, vec_ok, n, rows, row_count, d, dp, rs, Cq,
+                     ch, k, kpad, ib, cs, label, d1, d2, flags, full_rows, brute, st, gate);
   return hipGetLastError();
 }
 
+static int bf16_variant() {
+  static int v = -1;
+  if (v < 0) {
+    const char* e = getenv("KMX_ASSIGN_VARIANT");
+    v = e ? atoi(e) : 0;
+  }
+  return v;
+}
+
+static int fp32_variant() {
+  static int v = -1;
+  if (v < 0) {
+    const char* e = getenv("KMX_ASSIGN_FP32_VARIANT");
+    v = e ? atoi(e) : 0;
+  }
+  return v;
+}
+
 hipError_t launch_assign(hipStream_t s, int prec, const float* X, int64_t ldx, const uint16_t* Xq,
-                         int64_t n, int d, int dp, const RowStats* rs, const void* Cq,
-                         const float* ch, int k, int kpad, const CenterStats* cs, int32_t* label,
-                         float* d1, float* d2, FlagEntry* flags, LoopState* st, const int* gate) {
+                         int64_t n, const int* rows, const unsigned long long* row_count, int d,
+                         int dp, const RowStats* rs, const void* Cq, const float* ch, int k,
+                         int kpad, const CenterStats* cs, int32_t* label, float* d1, float* d2,
+                         FlagEntry* flags, int* full_rows, int* brute, LoopState* st,
+                         const int* gate, int num_cus) {
   int ib = 1;
   while ((1 << ib) < kpad) ++ib;
   const int nku = units_for(prec, d);
   if (prec == KMX_BF16) {
     const void* src = Xq;
     const int64_t xs = dp;
-#define KMX_A(NKU_, NCG_, BN_, W_)                                                              \
-  return run_assign<true, NKU_, NCG_, BN_, W_>(s, src, xs, 1, n, d, dp, rs, Cq, ch, k, kpad, ib, \
-                                               cs, label, d1, d2, flags, st, gate)
+    const int var = bf16_variant();
+#define KMX_A(NKU_, NCG_, BN_, W_)                                                             \
+  return run_assign<true, NKU_, NCG_, BN_, W_>(s, src, xs, 1, n, rows, row_count, d, dp, rs,  \
+                                               Cq, ch, k, kpad, ib, cs, label, d1, d2, flags, \
+                                               full_rows, brute, st, gate, num_cus)
     switch (nku) {
       case 1: KMX_A(1, 4, 64, 8);
       case 2: KMX_A(2, 4, 64, 8);
-      case 4: KMX_A(4, 4, 64, 8);
-      case 8: KMX_A(8, 2, 64, 8);
-      case 16: KMX_A(16, 2, 64, 8);
+      case 3: KMX_A(3, 4, 64, 8);
+      case 5: KMX_A(5, 4, 32, 8);
+      case 9: KMX_A(9, 2, 64, 8);
+      case 17:
+        if (var == 1) KMX_A(17, 4, 32, 4);
+        if (var == 2) KMX_A(17, 2, 64, 8);
+        if (var == 3) KMX_A(17, 4, 64, 4);
+        if (var == 7) KMX_A(17, 2, 32, 4);
+        if (var == 8) KMX_A(17, 2, 64, 4);
+        if (var == 4)
+          return run_assign<true, 17, 2, 32, 8, 2>(s, src, xs, 1, n, rows, row_count, d, dp, rs, Cq,
+                                                   ch, k, kpad, ib, cs, label, d1, d2, flags,
+                                                   full_rows, brute, st, gate, num_cus);
+        if (var == 5)
+          return run_assign<true, 17, 2, 32, 8, 3>(s, src, xs, 1, n, rows, row_count, d, dp, rs, Cq,
+                                                   ch, k, kpad, ib, cs, label, d1, d2, flags,
+                                                   full_rows, brute, st, gate, num_cus);
+        if (var == 6)
+          return run_assign<true, 17, 2, 64, 8, 2>(s, src, xs, 1, n, rows, row_count, d, dp, rs, Cq,
+                                                   ch, k, kpad, ib, cs, label, d1, d2, flags,
+                                                   full_rows, brute, st, gate, num_cus);
+        KMX_A(17, 2, 32, 8);
+      case 24: KMX_A(24, 1, 32, 8);
       case 32: KMX_A(32, 1, 32, 8);
+      case 33: KMX_A(33, 1, 16, 8);
       default: return hipErrorInvalidValue;
     }
 #undef KMX_A
   } else {
     const int vec_ok = ((((uintptr_t)X) & 15) == 0) && (ldx % 4 == 0);
-#define KMX_A(NKU_, NCG_, BN_, W_)                                                               \
-  return run_assign<false, NKU_, NCG_, BN_, W_>(s, X, ldx, vec_ok, n, d, dp, rs, Cq, ch, k, kpad, \
-                                                ib, cs, label, d1, d2, flags, st, gate)
+#define KMX_A(NKU_, NCG_, BN_, W_)                                                                 \
+  return run_assign<false, NKU_, NCG_, BN_, W_>(s, X, ldx, vec_ok, n, rows, row_count, d, dp, rs, \
+                                                Cq, ch, k, kpad, ib, cs, label, d1, d2, flags,    \
+                                                full_rows, brute, st, gate, num_cus)
     switch (nku) {
       case 1: KMX_A(1, 4, 64, 8);
       case 2: KMX_A(2, 4, 64, 8);
       case 4: KMX_A(4, 2, 64, 8);
       case 8: KMX_A(8, 2, 32, 8);
       case 16: KMX_A(16, 2, 32, 8);
-      case 32: KMX_A(32, 1, 32, 8);
+      case 32:
+        if (fp32_variant() == 1) KMX_A(32, 1, 32, 4);
+        KMX_A(32, 1, 32, 8);
       case 64: KMX_A(64, 1, 16, 4);
       default: return hipErrorInvalidValue;
     }
@@ -363,112 +563,152 @@ hipError_t launch_assign(hipStream_t s, int prec, const float* X, int64_t ldx, c
 
 // ---------------------------------------------------------------------------
 // Re-check of flagged rows.  One wave per list entry.
+//   pair entry: exact comparison of the two listed centers;
+//   full entry: plain FP32 distances to every center (lanes split the
+//     coordinates, 64 centers at a time, transposed through LDS), then the
+//     exact comparison among the centers inside the FP32 error band of the
+//     minimum.
+// Exact = FP32 direct differences with TwoSum/TwoProd double-float sums.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void recheck_kernel(const float* __restrict__ X, int64_t n,
-                                                      int d, int64_t ldx,
-                                                      const float* __restrict__ C, int k,
-                                                      int32_t* __restrict__ label,
-                                                      float* __restrict__ d1o,
-                                                      const FlagEntry* __restrict__ flags,
-                                                      const LoopState* __restrict__ st,
-                                                      const int* __restrict__ done) {
-  if (done && *done) return;
+__device__ __forceinline__ void exact_dist(const float* __restrict__ x,
+                                           const float* __restrict__ c, int d, int lane,
+                                           float& hi, float& lo) {
+  float s = 0.f, e = 0.f;
+  for (int q = lane; q < d; q += 64) df_acc_sqdiff(x[q], c[q], s, e);
+  wave_sum_df(s, e);
+  df_norm(s, e, hi, lo);
+}
+
+__global__ __launch_bounds__(256) void recheck_pair_kernel(
+    const float* __restrict__ X, int64_t n, int d, int64_t ldx, const float* __restrict__ C,
+    int k, int32_t* __restrict__ label, float* __restrict__ d1o,
+    const FlagEntry* __restrict__ flags, const LoopState* __restrict__ st,
+    const int* __restrict__ gate) {
+  if (gate && *gate) return;
   const unsigned long long cnt = st->flagged;
   const int lane = threadIdx.x & 63;
   const int64_t gw = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int64_t nw = (int64_t)gridDim.x * 4;
   for (int64_t e = gw; e < (int64_t)cnt; e += nw) {
     const FlagEntry fe = flags[e];
-    const int row = fe.row & 0x7FFFFFFF;
-    const bool full = fe.row < 0;
-    if (row >= n) continue;
+    const int row = fe.row;
+    if (row < 0 || row >= n) continue;
     const float* x = X + (int64_t)row * ldx;
-    int best = label[row];
-    float bh, bl;
-    if (!full) {
-      const int c2 = fe.cand2;
-      float s1 = 0.f, e1 = 0.f, s2 = 0.f, e2 = 0.f;
-      const float* a = C + (int64_t)best * d;
-      const float* b = C + (int64_t)c2 * d;
-      for (int c = lane; c < d; c += 64) {
-        const float xv = x[c];
-        df_acc_sqdiff(xv, a[c], s1, e1);
-        df_acc_sqdiff(xv, b[c], s2, e2);
-      }
-      wave_sum_df(s1, e1);
-      wave_sum_df(s2, e2);
-      float h1, l1, h2, l2;
-      df_norm(s1, e1, h1, l1);
-      df_norm(s2, e2, h2, l2);
-      const bool take2 = df_less(h2, l2, h1, l1) || (h1 == h2 && l1 == l2 && c2 < best);
-      if (take2) { best = c2; bh = h2; bl = l2; } else { bh = h1; bl = l1; }
-    } else {
-      // Pass 1: plain FP32 distances, one center per lane, to find the minimum.
-      const float gam = (float)(d + 3) * 5.9604645e-8f;
-      float m = __builtin_inff();
-      for (int jb = 0; jb < k; jb += 64) {
-        const int j = jb + lane;
-        if (j < k) {
-          const float* cj = C + (int64_t)j * d;
-          float acc = 0.f;
-          for (int c = 0; c < d; ++c) {
-            const float dd = x[c] - cj[c];
-            acc = __builtin_fmaf(dd, dd, acc);
-          }
-          m = fminf(m, acc);
-        }
-      }
-#pragma unroll
-      for (int s = 32; s >= 1; s >>= 1) m = fminf(m, __shfl_xor(m, s, 64));
-      const float thr = m * (1.0f + gam) / (1.0f - gam) * 1.0001f + 1e-30f;
-      // Pass 2: every center within the plain-FP32 error band gets the exact test.
-      bh = __builtin_inff();
-      bl = 0.f;
-      best = -1;
-      for (int jb = 0; jb < k; jb += 64) {
-        const int j = jb + lane;
-        bool cand = false;
-        if (j < k) {
-          const float* cj = C + (int64_t)j * d;
-          float acc = 0.f;
-          for (int c = 0; c < d; ++c) {
-            const float dd = x[c] - cj[c];
-            acc = __builtin_fmaf(dd, dd, acc);
-          }
-          cand = acc <= thr;
-        }
-        unsigned long long cm = __ballot(cand);
-        while (cm) {
-          const int t = __ffsll((long long)cm) - 1;
-          cm &= cm - 1ull;
-          const int jj = jb + t;
-          const float* cj = C + (int64_t)jj * d;
-          float s1 = 0.f, e1 = 0.f;
-          for (int c = lane; c < d; c += 64) df_acc_sqdiff(x[c], cj[c], s1, e1);
-          wave_sum_df(s1, e1);
-          float h1, l1;
-          df_norm(s1, e1, h1, l1);
-          if (best < 0 || df_less(h1, l1, bh, bl)) { bh = h1; bl = l1; best = jj; }
-        }
-      }
-    }
+    const int c1 = min(max(label[row], 0), k - 1), c2 = min(max(fe.cand2, 0), k - 1);
+    float h1, l1, h2, l2;
+    exact_dist(x, C + (int64_t)c1 * d, d, lane, h1, l1);
+    exact_dist(x, C + (int64_t)c2 * d, d, lane, h2, l2);
+    const bool take2 = df_less(h2, l2, h1, l1) || (h1 == h2 && l1 == l2 && c2 < c1);
     if (lane == 0) {
-      label[row] = best;
-      if (d1o) d1o[row] = bh;
+      label[row] = take2 ? c2 : c1;
+      if (d1o) d1o[row] = take2 ? h2 : h1;
     }
+  }
+}
+
+// One workgroup per row that needs every center; thread t handles centers
+// t, t + 256, ...  Pass 1: plain FP32 distances (sequential over the row,
+// relative error <= (d + 3) u) and their minimum m.  Pass 2: exact distances
+// of the centers within the error band of m; lexicographic argmin with the
+// lowest index on ties.
+__device__ __forceinline__ float plain_dist(const float* __restrict__ x,
+                                            const float* __restrict__ c, int d, bool vec) {
+  float acc = 0.f;
+  int q = 0;
+  if (vec) {
+    for (; q + 4 <= d; q += 4) {
+      const float4 a = *(const float4*)(x + q);
+      const float4 b = *(const float4*)(c + q);
+      float df = a.x - b.x; acc = __builtin_fmaf(df, df, acc);
+      df = a.y - b.y; acc = __builtin_fmaf(df, df, acc);
+      df = a.z - b.z; acc = __builtin_fmaf(df, df, acc);
+      df = a.w - b.w; acc = __builtin_fmaf(df, df, acc);
+    }
+  }
+  for (; q < d; ++q) {
+    const float df = x[q] - c[q];
+    acc = __builtin_fmaf(df, df, acc);
+  }
+  return acc;
+}
+
+__global__ __launch_bounds__(256) void recheck_full_kernel(
+    const float* __restrict__ X, int64_t n, int d, int64_t ldx, const float* __restrict__ C,
+    int k, int32_t* __restrict__ label, float* __restrict__ d1o, const int* __restrict__ brute,
+    const LoopState* __restrict__ st, const int* __restrict__ gate) {
+  if (gate && *gate) return;
+  __shared__ float redf[4];
+  __shared__ float redh[4], redl[4];
+  __shared__ int redj[4];
+  const unsigned long long cnt = st->flagged_full;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const float gam = (float)(d + 3) * 5.9604645e-8f;
+  for (int64_t e = blockIdx.x; e < (int64_t)cnt; e += gridDim.x) {
+    const int row = brute[e];
+    if (row < 0 || row >= n) continue;   // uniform across the block
+    const float* x = X + (int64_t)row * ldx;
+    const bool vec = ((((uintptr_t)x) & 15) == 0) && ((((uintptr_t)C) & 15) == 0) && (d % 4 == 0);
+    float m = __builtin_inff();
+    for (int j = tid; j < k; j += 256) m = fminf(m, plain_dist(x, C + (int64_t)j * d, d, vec));
+#pragma unroll
+    for (int s2 = 32; s2 >= 1; s2 >>= 1) m = fminf(m, __shfl_xor(m, s2, 64));
+    if (lane == 0) redf[wv] = m;
+    __syncthreads();
+    m = fminf(fminf(redf[0], redf[1]), fminf(redf[2], redf[3]));
+    const float thr = m * (1.0f + gam) / (1.0f - gam) * 1.0001f + 1e-30f;
+    float bh = __builtin_inff(), bl = 0.f;
+    int best = 0x7FFFFFFF;
+    for (int j = tid; j < k; j += 256) {
+      const float* cj = C + (int64_t)j * d;
+      if (plain_dist(x, cj, d, vec) <= thr) {
+        float s = 0.f, ee = 0.f;
+        for (int q = 0; q < d; ++q) df_acc_sqdiff(x[q], cj[q], s, ee);
+        float h, l;
+        df_norm(s, ee, h, l);
+        if (df_less(h, l, bh, bl) || (h == bh && l == bl && j < best)) { bh = h; bl = l; best = j; }
+      }
+    }
+#pragma unroll
+    for (int s2 = 32; s2 >= 1; s2 >>= 1) {
+      const float oh = __shfl_xor(bh, s2, 64), ol = __shfl_xor(bl, s2, 64);
+      const int oj = __shfl_xor(best, s2, 64);
+      if (df_less(oh, ol, bh, bl) || (oh == bh && ol == bl && oj < best)) { bh = oh; bl = ol; best = oj; }
+    }
+    if (lane == 0) { redh[wv] = bh; redl[wv] = bl; redj[wv] = best; }
+    __syncthreads();
+    if (tid == 0) {
+      for (int w = 1; w < 4; ++w) {
+        if (df_less(redh[w], redl[w], bh, bl) || (redh[w] == bh && redl[w] == bl && redj[w] < best)) {
+          bh = redh[w]; bl = redl[w]; best = redj[w];
+        }
+      }
+      if (best < k) {
+        label[row] = best;
+        if (d1o) d1o[row] = bh;
+      }
+    }
+    __syncthreads();
   }
 }
 
 hipError_t launch_recheck(hipStream_t s, const float* X, int64_t n, int d, int64_t ldx,
                           const float* C, int k, int32_t* label, float* d1,
-                          const FlagEntry* flags, const LoopState* st, int num_cus,
-                          const int* gate) {
+                          const FlagEntry* flags, const int* brute, const LoopState* st,
+                          int num_cus, const int* gate) {
   int64_t blocks = (n + 3) / 4;
-  const int64_t cap = (int64_t)num_cus * 8;
+  int64_t cap = (int64_t)num_cus * 8;
   if (blocks > cap) blocks = cap;
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(recheck_kernel, dim3((unsigned)blocks), dim3(256), 0, s, X, n, d, ldx, C, k,
-                     label, d1, flags, st, gate);
+  hipLaunchKernelGGL(recheck_pair_kernel, dim3((unsigned)blocks), dim3(256), 0, s, X, n, d, ldx,
+                     C, k, label, d1, flags, st, gate);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  cap = (int64_t)num_cus * 2;
+  blocks = n;
+  if (blocks > cap) blocks = cap;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(recheck_full_kernel, dim3((unsigned)blocks), dim3(256), 0, s, X, n, d, ldx,
+                     C, k, label, d1, brute, st, gate);
   return hipGetLastError();
 }
 

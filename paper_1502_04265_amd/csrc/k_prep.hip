@@ -11,28 +11,36 @@
 namespace kmx {
 
 // One wave per row.  Writes RowStats and, when Xq != nullptr, the BF16 row
-// (round to nearest even) zero-padded to dp elements.
+// (round to nearest even) of dp elements: x~ in columns [0, d), zeros, and
+// -1 in the last three columns.  Those three columns multiply the split
+// score offset stored with each center (see k_assign.hip).  xq_max receives
+// max_i ||x~_i||.
 __global__ __launch_bounds__(256) void prep_rows_kernel(const float* __restrict__ X, int64_t n,
                                                         int d, int64_t ldx, int dp,
                                                         uint16_t* __restrict__ Xq,
-                                                        RowStats* __restrict__ st) {
+                                                        RowStats* __restrict__ st,
+                                                        unsigned* __restrict__ xq_max) {
   const int lane = threadIdx.x & 63;
   const int64_t wave0 = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  unsigned local_max = 0u;
   for (int64_t row = wave0; row < n; row += nwaves) {
     const float* x = X + row * ldx;
     double s2 = 0.0, q2 = 0.0, r2 = 0.0;
     const int lim = Xq ? dp : d;
     for (int c = lane; c < lim; c += 64) {
-      float v = (c < d) ? x[c] : 0.0f;
-      double vd = (double)v;
+      const float v = (c < d) ? x[c] : 0.0f;
+      const double vd = (double)v;
       s2 += vd * vd;
       if (Xq) {
         uint16_t b = f32_to_bf16_rne(v);
+        if (c >= dp - 3) b = 0xBF80u;   // -1.0
         Xq[row * dp + c] = b;
-        double qd = (double)bf16_to_f32(b);
-        q2 += qd * qd;
-        r2 += (vd - qd) * (vd - qd);
+        if (c < d) {
+          const double qd = (double)bf16_to_f32(b);
+          q2 += qd * qd;
+          r2 += (vd - qd) * (vd - qd);
+        }
       }
     }
     s2 = wave_sum_f64(s2);
@@ -50,40 +58,46 @@ __global__ __launch_bounds__(256) void prep_rows_kernel(const float* __restrict_
         r.rx = 0.0f;
       }
       st[row] = r;
+      local_max = max(local_max, __float_as_uint(r.nxq));
     }
   }
+  if (lane == 0 && xq_max) atomicMax(xq_max, local_max);
 }
 
 hipError_t launch_prep_rows(hipStream_t s, const float* X, int64_t n, int d, int64_t ldx,
-                            int dp, uint16_t* Xq, RowStats* st, int num_cus) {
-  int64_t waves_needed = n;
-  int64_t blocks = (waves_needed + 3) / 4;
-  int64_t cap = (int64_t)num_cus * 16;
+                            int dp, uint16_t* Xq, RowStats* st, unsigned* xq_max, int num_cus) {
+  int64_t blocks = (n + 3) / 4;
+  const int64_t cap = (int64_t)num_cus * 16;
   if (blocks > cap) blocks = cap;
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(prep_rows_kernel, dim3((unsigned)blocks), dim3(256), 0, s, X, n, d, ldx,
-                     dp, Xq, st);
+                     dp, Xq, st, xq_max);
   return hipGetLastError();
 }
 
-// One wave per (padded) center.  prec 0: FP32 copy; prec 1: BF16 copy.
-// ch[j] = 0.5 ||c_j||^2 rounded to nearest float (0 for padding rows).
+// Pass A, one wave per (padded) center.  prec 0 (FP32): copy of c_j into a
+// row of dp floats, ch[j] = ||c_j||^2 / 2 (+inf for padding rows, whose score
+// is then clamped away).  prec 1 (BF16): c~_j (round to nearest even) in
+// columns [0, d), zeros elsewhere; hd[j] = ||c_j||^2 / 2 in FP64.  Maxima of
+// the norms go to cs.
 __global__ __launch_bounds__(64) void prep_centers_kernel(const float* __restrict__ C, int k,
                                                           int d, int dp, int prec,
                                                           void* __restrict__ Cq,
                                                           float* __restrict__ ch,
+                                                          double* __restrict__ hd,
                                                           CenterStats* __restrict__ cs) {
   const int j = blockIdx.x;
   const int lane = threadIdx.x;
   double s2 = 0.0, q2 = 0.0, r2 = 0.0;
-  for (int c = lane; c < dp; c += 64) {
-    float v = (j < k && c < d) ? C[(int64_t)j * d + c] : 0.0f;
-    double vd = (double)v;
+  const int lim = (prec == 1) ? dp - 3 : dp;
+  for (int c = lane; c < lim; c += 64) {
+    const float v = (j < k && c < d) ? C[(int64_t)j * d + c] : 0.0f;
+    const double vd = (double)v;
     s2 += vd * vd;
     if (prec == 1) {
-      uint16_t b = f32_to_bf16_rne(v);
+      const uint16_t b = f32_to_bf16_rne(v);
       ((uint16_t*)Cq)[(int64_t)j * dp + c] = b;
-      double qd = (double)bf16_to_f32(b);
+      const double qd = (double)bf16_to_f32(b);
       q2 += qd * qd;
       r2 += (vd - qd) * (vd - qd);
     } else {
@@ -94,11 +108,15 @@ __global__ __launch_bounds__(64) void prep_centers_kernel(const float* __restric
   q2 = wave_sum_f64(q2);
   r2 = wave_sum_f64(r2);
   if (lane == 0) {
-    ch[j] = (float)(0.5 * s2);
+    if (prec == 1) {
+      hd[j] = 0.5 * s2;
+    } else {
+      ch[j] = (j < k) ? (float)(0.5 * s2) : __builtin_inff();
+    }
     if (j < k) {
-      float cn = f64_to_f32_up(sqrt(s2));
-      float cq = (prec == 1) ? f64_to_f32_up(sqrt(q2)) : cn;
-      float rc = (prec == 1) ? f64_to_f32_up(sqrt(r2)) : 0.0f;
+      const float cn = f64_to_f32_up(sqrt(s2));
+      const float cq = (prec == 1) ? f64_to_f32_up(sqrt(q2)) : cn;
+      const float rc = (prec == 1) ? f64_to_f32_up(sqrt(r2)) : 0.0f;
       atomicMax(&cs->cq_max, __float_as_uint(cq));
       atomicMax(&cs->rc_max, __float_as_uint(rc));
       atomicMax(&cs->cn_max, __float_as_uint(cn));
@@ -106,10 +124,46 @@ __global__ __launch_bounds__(64) void prep_centers_kernel(const float* __restric
   }
 }
 
+// Pass B (BF16 only), one thread per padded center: the offset
+// O = (max||x~|| max||c~|| + max||c||^2 / 2) * 1.001 + 1 makes every score
+// x~.c~_j - h_j + O positive.  h'_j = h_j - O is stored as three BF16 terms
+// (h1 + h2 + h3 = h'_j to about 2^-24 |h'_j|) in the last three columns, which
+// meet the -1 columns of the rows; padding rows get zeros (score 0).
+__global__ void prep_centers_b_kernel(int k, int kpad, int dp, uint16_t* __restrict__ Cq,
+                                      const double* __restrict__ hd,
+                                      CenterStats* __restrict__ cs,
+                                      const unsigned* __restrict__ xq_max) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const float xm = __uint_as_float(*xq_max);
+  const float cqm = __uint_as_float(cs->cq_max);
+  const float cnm = __uint_as_float(cs->cn_max);
+  const float O = (xm * cqm + 0.5f * cnm * cnm) * 1.001f + 1.0f;
+  if (j == 0) cs->O = O;
+  if (j >= kpad) return;
+  uint16_t h1 = 0, h2 = 0, h3 = 0;
+  if (j < k) {
+    const float hp = (float)(hd[j] - (double)O);
+    h1 = f32_to_bf16_rne(hp);
+    const float r1 = hp - bf16_to_f32(h1);
+    h2 = f32_to_bf16_rne(r1);
+    const float r2 = r1 - bf16_to_f32(h2);
+    h3 = f32_to_bf16_rne(r2);
+  }
+  uint16_t* row = Cq + (int64_t)j * dp + dp - 3;
+  row[0] = h1;
+  row[1] = h2;
+  row[2] = h3;
+}
+
 hipError_t launch_prep_centers(hipStream_t s, const float* C, int k, int d, int kpad, int dp,
-                               int prec, void* Cq, float* ch, CenterStats* cs) {
-  hipLaunchKernelGGL(prep_centers_kernel, dim3(kpad), dim3(64), 0, s, C, k, d, dp, prec, Cq,
-                     ch, cs);
+                               int prec, void* Cq, float* ch, double* hd, CenterStats* cs,
+                               const unsigned* xq_max) {
+  hipLaunchKernelGGL(prep_centers_kernel, dim3(kpad), dim3(64), 0, s, C, k, d, dp, prec, Cq, ch,
+                     hd, cs);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || prec != 1) return e;
+  hipLaunchKernelGGL(prep_centers_b_kernel, dim3((kpad + 255) / 256), dim3(256), 0, s, k, kpad,
+                     dp, (uint16_t*)Cq, hd, cs, xq_max);
   return hipGetLastError();
 }
 
@@ -143,14 +197,16 @@ hipError_t launch_fill_u8(hipStream_t s, uint8_t* p, int64_t n, uint8_t v) {
 
 // Clears the center maxima and the per-assignment counters; with reset_iter
 // also the loop state (done, iter, changed).
-__global__ void reset_small_kernel(CenterStats* cs, unsigned long long* ctr, LoopState* st,
+__global__ void reset_small_kernel(CenterStats* cs, CenterStats* cs2, LoopState* st,
                                    int reset_iter) {
   if (threadIdx.x == 0) {
-    if (cs) { cs->cq_max = 0; cs->rc_max = 0; cs->cn_max = 0; cs->pad = 0; }
-    if (ctr) { ctr[0] = 0; ctr[1] = 0; }
+    if (cs) { cs->cq_max = 0; cs->rc_max = 0; cs->cn_max = 0; cs->O = 0.0f; }
+    if (cs2) { cs2->cq_max = 0; cs2->rc_max = 0; cs2->cn_max = 0; cs2->O = 0.0f; }
     if (st) {
       st->flagged = 0;
+      st->full_count = 0;
       st->flagged_full = 0;
+      st->undecided = 0;
       if (reset_iter) {
         st->done = 0;
         st->iter = 0;
@@ -160,9 +216,9 @@ __global__ void reset_small_kernel(CenterStats* cs, unsigned long long* ctr, Loo
   }
 }
 
-hipError_t launch_reset_small(hipStream_t s, CenterStats* cs, unsigned long long* ctr,
-                              LoopState* st, int reset_iter) {
-  hipLaunchKernelGGL(reset_small_kernel, dim3(1), dim3(64), 0, s, cs, ctr, st, reset_iter);
+hipError_t launch_reset_small(hipStream_t s, CenterStats* cs, CenterStats* cs2, LoopState* st,
+                              int reset_iter) {
+  hipLaunchKernelGGL(reset_small_kernel, dim3(1), dim3(64), 0, s, cs, cs2, st, reset_iter);
   return hipGetLastError();
 }
 

@@ -250,6 +250,7 @@ __global__ __launch_bounds__(256) void reduce_kernel(const float* __restrict__ X
   const int64_t r1 = min((int64_t)base[j + 1], r0 + kReduceRows);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   constexpr int CB = 64 * VEC * M;  // columns per pass
+  constexpr int UR = 4;             // rows in flight per wave
   double qacc = 0.0, wacc = 0.0;
   for (int cb = 0; cb < d; cb += CB) {
     double S[M][VEC], Q[M][VEC];
@@ -257,47 +258,43 @@ __global__ __launch_bounds__(256) void reduce_kernel(const float* __restrict__ X
     for (int m = 0; m < M; ++m)
 #pragma unroll
       for (int v = 0; v < VEC; ++v) S[m][v] = Q[m][v] = 0.0;
-    for (int64_t r = r0 + wv; r < r1; r += 4) {
-      const int64_t i = perm[r];
-      const double wt = w ? (double)w[i] : 1.0;
-      if (cb == 0) wacc += wt;
-      const float* xr = X + i * ldx + cb;
+    // wave wv takes rows r0 + wv, r0 + wv + 4, ...; UR of them per step, in order
+    for (int64_t rb = r0 + wv; rb < r1; rb += 4 * UR) {
+      float xv[UR][M][VEC];
+      double wt[UR];
 #pragma unroll
-      for (int m = 0; m < M; ++m) {
-        const int c0 = (m * 64 + lane) * VEC;
-        if (VEC == 4) {
-          if (cb + c0 + 4 <= d) {
-            const float4 v = *(const float4*)(xr + c0);
-            const float vv[4] = {v.x, v.y, v.z, v.w};
+      for (int u = 0; u < UR; ++u) {
+        const int64_t r = rb + 4 * u;
+        const bool rv = r < r1;
+        const int64_t i = rv ? (int64_t)perm[r] : 0;
+        wt[u] = rv ? (w ? (double)w[i] : 1.0) : 0.0;
+        const float* xr = X + i * ldx + cb;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              const double xd = (double)vv[q];
-              const double wx = wt * xd;
-              S[m][q] += wx;
-              Q[m][q] += wx * xd;
-            }
+        for (int m = 0; m < M; ++m) {
+          const int c0 = (m * 64 + lane) * VEC;
+          if (VEC == 4 && rv && cb + c0 + 4 <= d) {
+            const float4 t4 = *(const float4*)(xr + c0);
+            xv[u][m][0] = t4.x;
+            if (VEC == 4) { xv[u][m][1] = t4.y; xv[u][m][2] = t4.z; xv[u][m][3] = t4.w; }
           } else {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              if (cb + c0 + q < d) {
-                const double xd = (double)xr[c0 + q];
-                const double wx = wt * xd;
-                S[m][q] += wx;
-                Q[m][q] += wx * xd;
-              }
-            }
-          }
-        } else {
-#pragma unroll
-          for (int q = 0; q < VEC; ++q) {
-            if (cb + c0 + q < d) {
-              const double xd = (double)xr[c0 + q];
-              const double wx = wt * xd;
-              S[m][q] += wx;
-              Q[m][q] += wx * xd;
-            }
+            for (int q = 0; q < VEC; ++q)
+              xv[u][m][q] = (rv && cb + c0 + q < d) ? xr[c0 + q] : 0.0f;
           }
         }
+      }
+#pragma unroll
+      for (int u = 0; u < UR; ++u) {
+        if (cb == 0) wacc += wt[u];
+#pragma unroll
+        for (int m = 0; m < M; ++m)
+#pragma unroll
+          for (int q = 0; q < VEC; ++q) {
+            const double xd = (double)xv[u][m][q];
+            const double wx = wt[u] * xd;
+            S[m][q] += wx;
+            Q[m][q] = fma(wx, xd, Q[m][q]);
+          }
       }
     }
     // combine the four waves in a fixed order

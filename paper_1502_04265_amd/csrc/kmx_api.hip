@@ -118,30 +118,33 @@ kmx_status check_problem(kmx_ctx* ctx, const float* X, int64_t n, int32_t d, int
 
 kmx_status check_prec(kmx_ctx* ctx, int prec, int d) {
   if (prec != KMX_FP32 && prec != KMX_BF16) return fail(ctx, KMX_EINVAL, "unknown precision");
-  const int dmax = (prec == KMX_BF16) ? 1024 : 1024;
-  if (d > dmax)
+  const int dmax = (prec == KMX_BF16) ? 1053 : 1024;
+  if (d > dmax || d > 1024)
     return fail(ctx, KMX_EUNSUPPORTED,
                 "assignment supports d <= " + std::to_string(dmax) + ", got " + std::to_string(d));
   return KMX_OK;
 }
 
-// Row statistics and (BF16) the quantized copy of X, cached per dataset.
+// Row statistics and (BF16) the quantized copy of X, cached per dataset.  The
+// BF16 preparation also serves the FP32 path (which only reads ||x||).
 kmx_status ensure_prep(kmx_ctx* ctx, const float* X, int64_t n, int d, int64_t ldx, int prec) {
   if (ctx->cache_valid && ctx->cache_X == X && ctx->cache_n == n && ctx->cache_d == d &&
-      ctx->cache_ldx == ldx && ctx->cache_prec == prec)
+      ctx->cache_ldx == ldx && (ctx->cache_prec == prec || ctx->cache_prec == KMX_BF16))
     return KMX_OK;
   ctx->cache_valid = false;
   KMX_TRY(grow(ctx, ctx->rowstats, (size_t)n * sizeof(RowStats)));
+  KMX_TRY(grow(ctx, ctx->xstats, 16));
   uint16_t* xq = nullptr;
-  int dp = assign_dpad(prec, d);
+  const int dp = assign_dpad(prec, d);
   if (prec == KMX_BF16) {
     KMX_TRY(grow(ctx, ctx->xq, (size_t)n * dp * sizeof(uint16_t)));
     xq = P<uint16_t>(ctx->xq);
   }
   {
     Timed tm(ctx, T_PREP);
+    KMX_HIP(ctx, launch_fill_i32(ctx->stream, P<int32_t>(ctx->xstats), 4, 0));
     KMX_HIP(ctx, launch_prep_rows(ctx->stream, X, n, d, ldx, dp, xq, P<RowStats>(ctx->rowstats),
-                                  ctx->num_cus));
+                                  P<unsigned>(ctx->xstats), ctx->num_cus));
   }
   ctx->cache_X = X;
   ctx->cache_n = n;
@@ -159,6 +162,9 @@ kmx_status ensure_common(kmx_ctx* ctx, int64_t n, int d, int k) {
   KMX_TRY(grow(ctx, ctx->lab_a, (size_t)n * sizeof(int32_t)));
   KMX_TRY(grow(ctx, ctx->flags, (size_t)n * sizeof(FlagEntry)));
   KMX_TRY(grow(ctx, ctx->cstats, sizeof(CenterStats)));
+  KMX_TRY(grow(ctx, ctx->cstats32, sizeof(CenterStats)));
+  KMX_TRY(grow(ctx, ctx->full_rows, (size_t)n * sizeof(int)));
+  KMX_TRY(grow(ctx, ctx->brute, (size_t)n * sizeof(int)));
   KMX_TRY(grow(ctx, ctx->counts, (size_t)nb * k * sizeof(int32_t)));
   KMX_TRY(grow(ctx, ctx->segsum, (size_t)kScanSegs * k * sizeof(int32_t)));
   KMX_TRY(grow(ctx, ctx->base, (size_t)(k + 1) * sizeof(int32_t)));
@@ -186,32 +192,61 @@ kmx_status write_state(kmx_ctx* ctx, int max_iter, double tol) {
 }
 
 // prep_centers + GEMM assignment + re-check.  gate: skip when *gate != 0.
+// BF16: rows whose candidate set the BF16 bound cannot narrow to two centers
+// go through the FP32 GEMM (same kernel, listed rows) before the re-check.
 kmx_status run_assign(kmx_ctx* ctx, const float* X, int64_t n, int d, int64_t ldx, const float* C,
                       int k, int prec, int32_t* label, float* d1, float* d2, const int* gate) {
-  const int dp = assign_dpad(prec, d);
-  const int bn = assign_tile_n(prec, d);
-  const int kpad = (k + bn - 1) / bn * bn;
-  const size_t esz = (prec == KMX_BF16) ? 2 : 4;
-  KMX_TRY(grow(ctx, ctx->cq, (size_t)kpad * dp * esz));
-  KMX_TRY(grow(ctx, ctx->ch, (size_t)kpad * sizeof(float)));
   LoopState* st = ST(ctx);
   CenterStats* cs = P<CenterStats>(ctx->cstats);
+  CenterStats* cs32 = P<CenterStats>(ctx->cstats32);
+  const int dp32 = assign_dpad(KMX_FP32, d);
+  const int bn32 = assign_tile_n(KMX_FP32, d);
+  const int kpad32 = (k + bn32 - 1) / bn32 * bn32;
+  KMX_TRY(grow(ctx, ctx->cq32, (size_t)kpad32 * dp32 * sizeof(float)));
+  KMX_TRY(grow(ctx, ctx->ch32, (size_t)kpad32 * sizeof(float)));
   {
     Timed tm(ctx, T_PREP);
-    KMX_HIP(ctx, launch_reset_small(ctx->stream, cs, nullptr, st, 0));
-    KMX_HIP(ctx, launch_prep_centers(ctx->stream, C, k, d, kpad, dp, prec, ctx->cq.p,
-                                     P<float>(ctx->ch), cs));
+    KMX_HIP(ctx, launch_reset_small(ctx->stream, cs, cs32, st, 0));
+    KMX_HIP(ctx, launch_prep_centers(ctx->stream, C, k, d, kpad32, dp32, KMX_FP32, ctx->cq32.p,
+                                     P<float>(ctx->ch32), nullptr, cs32, nullptr));
   }
-  {
+  const RowStats* rs = P<RowStats>(ctx->rowstats);
+  FlagEntry* flags = P<FlagEntry>(ctx->flags);
+  if (prec == KMX_BF16) {
+    const int dp = assign_dpad(KMX_BF16, d);
+    const int bn = assign_tile_n(KMX_BF16, d);
+    const int kpad = (k + bn - 1) / bn * bn;
+    KMX_TRY(grow(ctx, ctx->cq, (size_t)kpad * dp * sizeof(uint16_t)));
+    KMX_TRY(grow(ctx, ctx->hd, (size_t)kpad * sizeof(double)));
+    {
+      Timed tm(ctx, T_PREP);
+      KMX_HIP(ctx, launch_prep_centers(ctx->stream, C, k, d, kpad, dp, KMX_BF16, ctx->cq.p, nullptr,
+                                       P<double>(ctx->hd), cs, P<unsigned>(ctx->xstats)));
+    }
+    {
+      Timed tm(ctx, T_ASSIGN);
+      KMX_HIP(ctx, launch_assign(ctx->stream, KMX_BF16, X, ldx, P<uint16_t>(ctx->xq), n, nullptr,
+                                 nullptr, d, dp, rs, ctx->cq.p, nullptr, k, kpad, cs, label, d1,
+                                 d2, flags, P<int>(ctx->full_rows), P<int>(ctx->brute), st, gate,
+                                 ctx->num_cus));
+    }
+    {
+      Timed tm(ctx, T_RECHECK);
+      KMX_HIP(ctx, launch_assign(ctx->stream, KMX_FP32, X, ldx, nullptr, n, P<int>(ctx->full_rows),
+                                 &st->full_count, d, dp32, rs, ctx->cq32.p, P<float>(ctx->ch32), k,
+                                 kpad32, cs32, label, d1, d2, flags, nullptr, P<int>(ctx->brute),
+                                 st, gate, ctx->num_cus));
+    }
+  } else {
     Timed tm(ctx, T_ASSIGN);
-    KMX_HIP(ctx, launch_assign(ctx->stream, prec, X, ldx, P<uint16_t>(ctx->xq), n, d, dp,
-                               P<RowStats>(ctx->rowstats), ctx->cq.p, P<float>(ctx->ch), k, kpad,
-                               cs, label, d1, d2, P<FlagEntry>(ctx->flags), st, gate));
+    KMX_HIP(ctx, launch_assign(ctx->stream, KMX_FP32, X, ldx, nullptr, n, nullptr, nullptr, d, dp32,
+                               rs, ctx->cq32.p, P<float>(ctx->ch32), k, kpad32, cs32, label, d1,
+                               d2, flags, nullptr, P<int>(ctx->brute), st, gate, ctx->num_cus));
   }
   {
     Timed tm(ctx, T_RECHECK);
-    KMX_HIP(ctx, launch_recheck(ctx->stream, X, n, d, ldx, C, k, label, d1,
-                                P<FlagEntry>(ctx->flags), st, ctx->num_cus, gate));
+    KMX_HIP(ctx, launch_recheck(ctx->stream, X, n, d, ldx, C, k, label, d1, flags,
+                                P<int>(ctx->brute), st, ctx->num_cus, gate));
   }
   return KMX_OK;
 }
@@ -289,7 +324,8 @@ kmx_status kmx_destroy(kmx_ctx* ctx) {
   if (!ctx) return KMX_EINVAL;
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
-  kmx::Buf* bufs[] = {&ctx->xq,    &ctx->rowstats, &ctx->cq,     &ctx->ch,         &ctx->cstats,
+  kmx::Buf* bufs[] = {&ctx->xq, &ctx->xstats, &ctx->hd, &ctx->cq32, &ctx->ch32, &ctx->cstats32,
+                      &ctx->full_rows, &ctx->brute, &ctx->rowstats, &ctx->cq,     &ctx->ch,         &ctx->cstats,
                       &ctx->lab_a, &ctx->lab_prev, &ctx->d1,     &ctx->d2,         &ctx->flags,
                       &ctx->counters, &ctx->counts, &ctx->segsum, &ctx->base,     &ctx->chunk_base,
                       &ctx->perm,  &ctx->partS,    &ctx->partQ,  &ctx->partW,      &ctx->W,
@@ -363,7 +399,7 @@ kmx_status kmx_assign(kmx_ctx* ctx, const float* X, int64_t n, int32_t d, int64_
     LoopState h;
     KMX_HIP(ctx, hipMemcpyAsync(&h, ctx->state.p, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
     KMX_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    *n_flagged = (int64_t)h.flagged;
+    *n_flagged = (int64_t)h.undecided;
   }
   return KMX_OK;
 }
@@ -450,6 +486,25 @@ kmx_status kmx_lloyd(kmx_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t
   KMX_HIP(ctx, hipMemcpy(cost_hist, hist, (size_t)(it + 1) * sizeof(double),
                          hipMemcpyDeviceToHost));
   *iters_done = it;
+  return KMX_OK;
+}
+
+kmx_status kmx_assign_stats(kmx_ctx* ctx, int64_t* listed, int64_t* fp32, int64_t* full) {
+  if (!ctx) return KMX_EINVAL;
+  ctx->err.clear();
+  if (!ctx->state.p) {
+    if (listed) *listed = 0;
+    if (fp32) *fp32 = 0;
+    if (full) *full = 0;
+    return KMX_OK;
+  }
+  KMX_TRY(set_device(ctx));
+  LoopState h;
+  KMX_HIP(ctx, hipMemcpyAsync(&h, ctx->state.p, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+  KMX_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  if (listed) *listed = (int64_t)h.flagged;
+  if (fp32) *fp32 = (int64_t)h.full_count;
+  if (full) *full = (int64_t)h.flagged_full;
   return KMX_OK;
 }
 

@@ -26,8 +26,10 @@ struct RowStats {
 //   cq_max : max_j ||c~_j||    (rounded up)
 //   rc_max : max_j ||c_j - c~_j|| (rounded up)
 //   cn_max : max_j ||c_j||     (rounded up)
+//   O      : score offset of the BF16 GEMM (see k_assign.hip)
 struct CenterStats {
-  unsigned int cq_max, rc_max, cn_max, pad;
+  unsigned int cq_max, rc_max, cn_max;
+  float O;
 };
 
 // Device-side Lloyd state, one instance per context.
@@ -38,14 +40,16 @@ struct LoopState {
   int track_changes; // count label changes against the previous labels
   double tol;        // < 0: fixed iteration count
   unsigned long long changed;
-  unsigned long long flagged;   // rows that needed the re-check (last assign)
-  unsigned long long flagged_full;
+  unsigned long long flagged;      // entries of the re-check list (last assign)
+  unsigned long long full_count;   // rows sent to the FP32 GEMM pass (BF16 only)
+  unsigned long long flagged_full; // rows re-checked against every center
+  unsigned long long undecided;    // rows the first GEMM pass could not decide
   double cost_at_centroids;
   double cost_last;
 };
 
-// Entry of the re-check list: row index (bit 31 set: every center must be
-// re-checked) and the runner-up candidate.
+// Entry of the two-candidate re-check list: row index and the runner-up
+// candidate (the leader is the row's current label).
 struct FlagEntry {
   int row;
   int cand2;
@@ -83,8 +87,8 @@ struct kmx_ctx {
   int cache_d = 0, cache_prec = -1;
   bool cache_valid = false;
 
-  kmx::Buf xq, rowstats;
-  kmx::Buf cq, ch, cstats;
+  kmx::Buf xq, rowstats, xstats;
+  kmx::Buf cq, ch, hd, cstats, cq32, ch32, cstats32, full_rows, brute;
   kmx::Buf lab_a, lab_prev, d1, d2;
   kmx::Buf flags, counters;
   kmx::Buf counts, segsum, base, chunk_base, perm;
@@ -108,27 +112,29 @@ namespace kmx {
 // ---- launchers (each returns hipSuccess or the launch error) --------------
 // prep
 hipError_t launch_prep_rows(hipStream_t s, const float* X, int64_t n, int d, int64_t ldx,
-                            int dp, uint16_t* Xq, RowStats* st, int num_cus);
+                            int dp, uint16_t* Xq, RowStats* st, unsigned* xq_max, int num_cus);
 hipError_t launch_prep_centers(hipStream_t s, const float* C, int k, int d, int kpad, int dp,
-                               int prec, void* Cq, float* ch, CenterStats* cs);
+                               int prec, void* Cq, float* ch, double* hd, CenterStats* cs,
+                               const unsigned* xq_max);
 hipError_t launch_fill_i32(hipStream_t s, int32_t* p, int64_t n, int32_t v);
 hipError_t launch_fill_u8(hipStream_t s, uint8_t* p, int64_t n, uint8_t v);
-hipError_t launch_reset_small(hipStream_t s, CenterStats* cs, unsigned long long* ctr,
-                              LoopState* st, int reset_iter);
+hipError_t launch_reset_small(hipStream_t s, CenterStats* cs, CenterStats* cs2, LoopState* st,
+                              int reset_iter);
 
 // assign
 int assign_tile_n(int prec, int d);   // centers per tile (kpad granularity)
-int assign_dpad(int prec, int d);     // padded row length of quantized data
+int assign_dpad(int prec, int d);     // padded row length of the GEMM operands
 hipError_t launch_assign(hipStream_t s, int prec, const float* X, int64_t ldx,
-                         const uint16_t* Xq, int64_t n, int d, int dp,
+                         const uint16_t* Xq, int64_t n, const int* rows,
+                         const unsigned long long* row_count, int d, int dp,
                          const RowStats* rs, const void* Cq, const float* ch,
                          int k, int kpad, const CenterStats* cs, int32_t* label,
-                         float* d1, float* d2, FlagEntry* flags, LoopState* st,
-                         const int* gate);
+                         float* d1, float* d2, FlagEntry* flags, int* full_rows, int* brute,
+                         LoopState* st, const int* gate, int num_cus);
 hipError_t launch_recheck(hipStream_t s, const float* X, int64_t n, int d, int64_t ldx,
                           const float* C, int k, int32_t* label, float* d1,
-                          const FlagEntry* flags, const LoopState* st, int num_cus,
-                          const int* gate);
+                          const FlagEntry* flags, const int* brute, const LoopState* st,
+                          int num_cus, const int* gate);
 
 // update
 hipError_t launch_sort(hipStream_t s, const int32_t* label, int32_t* lab_prev, int64_t n,

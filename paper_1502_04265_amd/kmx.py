@@ -55,6 +55,7 @@ def lib():
         "kmx_lloyd": [_vp, _vp, _i64, _i32, _i64, _vp, _vp, _i32, _i32, ctypes.c_double,
                       ctypes.c_int, _vp, _vp, _vp],
         "kmx_timing": [_vp, ctypes.c_int, ctypes.c_int],
+        "kmx_assign_stats": [_vp, _vp, _vp, _vp],
         "kmx_timing_read": [_vp, ctypes.c_int, _vp, _vp],
     }
     for name, args in sig.items():
@@ -193,6 +194,13 @@ class Context:
         _check(lib().kmx_invalidate(self._p, _ptr(X)), self._p)
 
     # ---- measurement -------------------------------------------------------
+    def assign_stats(self):
+        """(listed, fp32, full) re-check counts of the most recent assignment."""
+        a, b, c = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int64(0)
+        _check(lib().kmx_assign_stats(self._p, ctypes.byref(a), ctypes.byref(b),
+                                      ctypes.byref(c)), self._p)
+        return int(a.value), int(b.value), int(c.value)
+
     def timing(self, enable: bool = True, reset: bool = True):
         _check(lib().kmx_timing(self._p, int(enable), int(reset)), self._p)
 

@@ -13,22 +13,23 @@
 //   FP32: t_j = (acc - h_j) + o_x with a per-row offset o_x, clamped at 0.
 // The low `ib` bits of t_j are replaced by (mask - j): an unsigned max keeps
 // the best score and, between equal truncated scores, the lowest index.  A
-// lane keeps the three largest keys it has seen (max, med3, med3); the four
-// lanes holding one point merge at the end.
+// lane keeps the four (BF16) or three (FP32) largest keys it has seen (max
+// and med3 operations); the four lanes holding one point merge at the end.
 //
 // Soundness.  For every center |t_j - (x.c_j - h_j + O)| <= E(x), where E
 // covers the FP32 accumulation (gamma_K sum |x~_i c~_ji|), the quantization of
 // both operands (||x - x~|| ||c~|| + ||x|| ||c - c~||), the rounding of h_j and
 // of the epilogue, and the key truncation.  If t_1 - t_2 > 2E the top key's
-// center is the exact argmin.  Otherwise the row is flagged: when
-// t_1 - t_3 > 2E only the two listed centers can win and the re-check compares
-// them exactly; otherwise the row needs every center: the BF16 pass sends it
-// to the FP32 pass (same kernel, FP32 operands, list of rows), whose much
-// tighter bound leaves it as a two-candidate re-check in all but exceptional
-// cases; rows still open after the FP32 pass are re-checked against every
-// center.  The re-check computes FP32 direct differences with error-free
-// transformations (double-float accumulation), so labels agree with exact
-// arithmetic except on ties closer than about 1e-13 relative.
+// center is the exact argmin.  Otherwise the row is flagged: the centers whose
+// score lies within 2E of the top can win; when they are among the listed two
+// (BF16: three) the short re-check compares them.  Otherwise the row needs
+// every center: the BF16 pass sends it to the FP32 pass (same kernel, FP32
+// operands, list of rows), whose much tighter bound leaves it a short
+// re-check in all but exceptional cases; rows still open after the FP32 pass
+// are re-checked against every center.  The re-check decides with plain FP32
+// direct differences where their error bound allows and otherwise with
+// error-free transformations (double-float accumulation), so labels agree
+// with exact arithmetic except on ties closer than about 1e-13 relative.
 //
 // Layout.  MFMA 16x16x32 BF16 (or 16x16x4 FP32): A = 16 centers x K (from
 // LDS), B = K x 16 points (registers, loaded once per block of points),
@@ -49,15 +50,17 @@ __device__ __forceinline__ unsigned med3u(unsigned a, unsigned b, unsigned c) {
   return max(min(a, b), min(max(a, b), c));
 }
 
-// (v1 >= v2 >= v3) <- the three largest of {v1, v2, v3, key}
-__device__ __forceinline__ void top3_insert(unsigned key, unsigned& v1, unsigned& v2,
-                                            unsigned& v3) {
+// (v1 >= v2 >= v3 >= v4) <- the four largest of {v1, v2, v3, v4, key}
+__device__ __forceinline__ void top4_insert(unsigned key, unsigned& v1, unsigned& v2,
+                                            unsigned& v3, unsigned& v4) {
   const unsigned n1 = max(v1, key);
   const unsigned n2 = med3u(v1, v2, key);
   const unsigned n3 = med3u(v2, v3, key);
+  const unsigned n4 = med3u(v3, v4, key);
   v1 = n1;
   v2 = n2;
   v3 = n3;
+  v4 = n4;
 }
 
 template <bool BF16, int NKU, int NCG, int BN, int WAVES, int PF = 1>
@@ -133,14 +136,14 @@ __global__ __launch_bounds__(WAVES * 64) void assign_kernel(
       }
     }
 
-    // BF16 state: three packed keys per point.  FP32 state: the three best
+    // BF16 state: four packed keys per point.  FP32 state: the three best
     // scores and the indices of the first two, kept exactly.
-    unsigned v1[NCG], v2[NCG], v3[NCG];
+    unsigned v1[NCG], v2[NCG], v3[NCG], v4[NCG];
     float f1[NCG], f2[NCG], f3[NCG];
     int j1[NCG], j2[NCG];
 #pragma unroll
     for (int cg = 0; cg < NCG; ++cg) {
-      v1[cg] = v2[cg] = v3[cg] = 0u;
+      v1[cg] = v2[cg] = v3[cg] = v4[cg] = 0u;
       f1[cg] = f2[cg] = f3[cg] = -__builtin_inff();
       j1[cg] = j2[cg] = 0x7FFFFFFF;
     }
@@ -233,7 +236,7 @@ __global__ __launch_bounds__(WAVES * 64) void assign_kernel(
 #pragma unroll
             for (int cg = 0; cg < NCG; ++cg) {
               const unsigned key = (__float_as_uint(acc[cg][rb][i]) & ~mask) | idx;
-              top3_insert(key, v1[cg], v2[cg], v3[cg]);
+              top4_insert(key, v1[cg], v2[cg], v3[cg], v4[cg]);
             }
           }
         }
@@ -273,9 +276,11 @@ __global__ __launch_bounds__(WAVES * 64) void assign_kernel(
           const unsigned o1 = __shfl_xor(v1[cg], m, 64);
           const unsigned o2 = __shfl_xor(v2[cg], m, 64);
           const unsigned o3 = __shfl_xor(v3[cg], m, 64);
-          top3_insert(o1, v1[cg], v2[cg], v3[cg]);
-          top3_insert(o2, v1[cg], v2[cg], v3[cg]);
-          top3_insert(o3, v1[cg], v2[cg], v3[cg]);
+          const unsigned o4 = __shfl_xor(v4[cg], m, 64);
+          top4_insert(o1, v1[cg], v2[cg], v3[cg], v4[cg]);
+          top4_insert(o2, v1[cg], v2[cg], v3[cg], v4[cg]);
+          top4_insert(o3, v1[cg], v2[cg], v3[cg], v4[cg]);
+          top4_insert(o4, v1[cg], v2[cg], v3[cg], v4[cg]);
         } else {
           const float g1 = __shfl_xor(f1[cg], m, 64), g2 = __shfl_xor(f2[cg], m, 64);
           const float g3 = __shfl_xor(f3[cg], m, 64);
@@ -305,19 +310,19 @@ __global__ __launch_bounds__(WAVES * 64) void assign_kernel(
     const float Kf = (float)(dp + 1);
     const float gam = Kf * ua / (1.0f - Kf * ua);
     unsigned long long fmask[NCG], gmask[NCG], bmask[NCG];
-    int cand2v[NCG];
+    int cand2v[NCG], cand3v[NCG];
     int nf_w = 0, ng_w = 0, nfull_w = 0;
 #pragma unroll
     for (int cg = 0; cg < NCG; ++cg) {
       const int64_t r = src_row[cg];
       const bool writer = (grp == (cg & 3)) && (r >= 0);
       bool flagged = false, full = false;
-      int cand2 = 0;
+      int cand2 = 0, cand3 = -1;
       if (writer) {
         const RowStats rw = rs[r];
-        float t1, t2 = 0.f, t3 = 0.f, E, off;
-        int i1;
-        bool has2, has3;
+        float t1, t2 = 0.f, t3 = 0.f, t4 = 0.f, E, off;
+        int i1, i3 = -1;
+        bool has2, has3, has4 = false;
         if constexpr (BF16) {
           const unsigned hi = ~mask;
           off = Og;
@@ -327,11 +332,16 @@ __global__ __launch_bounds__(WAVES * 64) void assign_kernel(
           i1 = (v1[cg] & hi) ? min((int)(mask - (v1[cg] & mask)), k - 1) : 0;
           has2 = (v2[cg] & hi) != 0u;
           has3 = (v3[cg] & hi) != 0u;
+          has4 = (v4[cg] & hi) != 0u;
           if (has2) {
             t2 = __uint_as_float(v2[cg] & hi);
             cand2 = min((int)(mask - (v2[cg] & mask)), k - 1);
           }
-          if (has3) t3 = __uint_as_float(v3[cg] & hi);
+          if (has3) {
+            t3 = __uint_as_float(v3[cg] & hi);
+            i3 = min((int)(mask - (v3[cg] & mask)), k - 1);
+          }
+          if (has4) t4 = __uint_as_float(v4[cg] & hi);
         } else {
           off = 0.0f;
           E = (gam + u) * rw.nx * cnm + 1.5f * u * cnm * cnm;
@@ -351,7 +361,16 @@ __global__ __launch_bounds__(WAVES * 64) void assign_kernel(
         if (has2) {
           if (d2o) d2o[r] = fmaxf(rw.xn2 - 2.0f * (t2 - off), 0.0f);
           flagged = (t1 - t2) <= 2.0f * E;
-          if (flagged && has3) full = (t1 - t3) <= 2.0f * E;
+          if (flagged && has3 && (t1 - t3) <= 2.0f * E) {
+            // BF16 keeps a fourth key: three listed candidates suffice unless
+            // the fourth is inside the band too
+            if (BF16) {
+              cand3 = i3;
+              full = has4 && (t1 - t4) <= 2.0f * E;
+            } else {
+              full = true;
+            }
+          }
         } else if (d2o) {
           d2o[r] = __builtin_inff();
         }
@@ -363,6 +382,7 @@ __global__ __launch_bounds__(WAVES * 64) void assign_kernel(
       gmask[cg] = __ballot(to_full);
       bmask[cg] = __ballot(to_brute);
       cand2v[cg] = cand2;
+      cand3v[cg] = cand3;
       nf_w += __popcll(fmask[cg]);
       ng_w += __popcll(gmask[cg]);
       nfull_w += __popcll(bmask[cg]);
@@ -400,6 +420,8 @@ __global__ __launch_bounds__(WAVES * 64) void assign_kernel(
         FlagEntry fe;
         fe.row = (int)src_row[cg];
         fe.cand2 = cand2v[cg];
+        fe.cand3 = cand3v[cg];
+        fe.pad = 0;
         flags[of + __popcll(fmask[cg] & below)] = fe;
       }
       if ((gmask[cg] >> lane) & 1ull) full_rows[og + __popcll(gmask[cg] & below)] = (int)src_row[cg];
@@ -579,6 +601,21 @@ __device__ __forceinline__ void exact_dist(const float* __restrict__ x,
   df_norm(s, e, hi, lo);
 }
 
+// Short re-check: the listed 2 or 3 candidates.  Plain FP32 distances first
+// (per-lane sequential sums of ceil(d/64) squares, then a 6-level butterfly:
+// relative error <= (ceil(d/64) + 9) u); when the best plain distance beats
+// every other candidate by more than that bound the result is exact,
+// otherwise the candidates are compared with double-float sums.
+__device__ __forceinline__ float wave_plain_dist(const float* __restrict__ x,
+                                                 const float* __restrict__ c, int d, int lane) {
+  float acc = 0.f;
+  for (int q = lane; q < d; q += 64) {
+    const float df = x[q] - c[q];
+    acc = __builtin_fmaf(df, df, acc);
+  }
+  return wave_sum_f32(acc);
+}
+
 __global__ __launch_bounds__(256) void recheck_pair_kernel(
     const float* __restrict__ X, int64_t n, int d, int64_t ldx, const float* __restrict__ C,
     int k, int32_t* __restrict__ label, float* __restrict__ d1o,
@@ -589,19 +626,41 @@ __global__ __launch_bounds__(256) void recheck_pair_kernel(
   const int lane = threadIdx.x & 63;
   const int64_t gw = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int64_t nw = (int64_t)gridDim.x * 4;
+  const float tol = (float)((d + 63) / 64 + 10) * 5.9604645e-8f;
   for (int64_t e = gw; e < (int64_t)cnt; e += nw) {
     const FlagEntry fe = flags[e];
     const int row = fe.row;
     if (row < 0 || row >= n) continue;
     const float* x = X + (int64_t)row * ldx;
-    const int c1 = min(max(label[row], 0), k - 1), c2 = min(max(fe.cand2, 0), k - 1);
-    float h1, l1, h2, l2;
-    exact_dist(x, C + (int64_t)c1 * d, d, lane, h1, l1);
-    exact_dist(x, C + (int64_t)c2 * d, d, lane, h2, l2);
-    const bool take2 = df_less(h2, l2, h1, l1) || (h1 == h2 && l1 == l2 && c2 < c1);
+    int cj[3];
+    cj[0] = min(max(label[row], 0), k - 1);
+    cj[1] = min(max(fe.cand2, 0), k - 1);
+    cj[2] = fe.cand3 >= 0 ? min(fe.cand3, k - 1) : -1;
+    const int nc = (cj[2] >= 0) ? 3 : 2;
+    float p[3];
+    for (int q = 0; q < nc; ++q) p[q] = wave_plain_dist(x, C + (int64_t)cj[q] * d, d, lane);
+    int b = 0;
+    for (int q = 1; q < nc; ++q)
+      if (p[q] < p[b] || (p[q] == p[b] && cj[q] < cj[b])) b = q;
+    bool sure = true;
+    for (int q = 0; q < nc; ++q)
+      if (q != b && !(p[q] - p[b] > tol * (p[q] + p[b]))) sure = false;
+    int best = cj[b];
+    float bd = p[b];
+    if (!sure) {
+      float bh = 0.f, bl = 0.f;
+      for (int q = 0; q < nc; ++q) {
+        float h, l;
+        exact_dist(x, C + (int64_t)cj[q] * d, d, lane, h, l);
+        if (q == 0 || df_less(h, l, bh, bl) || (h == bh && l == bl && cj[q] < best)) {
+          bh = h; bl = l; best = cj[q];
+        }
+      }
+      bd = bh;
+    }
     if (lane == 0) {
-      label[row] = take2 ? c2 : c1;
-      if (d1o) d1o[row] = take2 ? h2 : h1;
+      label[row] = best;
+      if (d1o) d1o[row] = bd;
     }
   }
 }

@@ -258,7 +258,7 @@ __global__ __launch_bounds__(256) void reduce_kernel(const float* __restrict__ X
     for (int m = 0; m < M; ++m)
 #pragma unroll
       for (int v = 0; v < VEC; ++v) S[m][v] = Q[m][v] = 0.0;
-    // wave wv takes rows r0 + wv, r0 + wv + 4, ...; UR of them per step, in order
+    // wave wv takes rows r0 + wv, r0 + wv + 4, ... in order, UR per step
     for (int64_t rb = r0 + wv; rb < r1; rb += 4 * UR) {
       float xv[UR][M][VEC];
       double wt[UR];

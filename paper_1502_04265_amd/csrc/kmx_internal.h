@@ -48,11 +48,13 @@ struct LoopState {
   double cost_last;
 };
 
-// Entry of the two-candidate re-check list: row index and the runner-up
-// candidate (the leader is the row's current label).
+// Entry of the short re-check list: row index and the other candidates (the
+// leader is the row's current label; cand3 = -1 when there are only two).
 struct FlagEntry {
   int row;
   int cand2;
+  int cand3;
+  int pad;
 };
 
 enum TimingClass {

@@ -118,6 +118,26 @@ def test_assign_near_ties_are_rechecked(ctx):
         assert nf > 0
 
 
+@pytest.mark.parametrize("m", [3, 4, 6])
+def test_assign_multiway_near_ties(ctx, m):
+    # Points close to the center of a regular simplex of m centers: m centers
+    # are nearly equidistant, so the short list (m = 3), the FP32 pass and the
+    # every-center re-check (m >= 4) all run.  Far decoys fill out k.
+    say(f"assign {m}-way near ties")
+    rng = np.random.default_rng(10 + m)
+    n, d = 3000, 40
+    base = rng.normal(0, 2, d)
+    dirs = np.linalg.qr(rng.normal(size=(d, m)))[0].T      # m orthonormal directions
+    C_near = base + 3.0 * dirs
+    C_far = base + 60.0 + rng.normal(size=(20, d))
+    C = np.vstack([C_far[:7], C_near, C_far[7:]]).astype(np.float32)
+    X = (base + 1e-3 * rng.normal(size=(n, d))).astype(np.float32)
+    for prec in ("fp32", "bf16"):
+        lab, _, _, nf = ctx.assign(_dev(X), _dev(C), prec=prec)
+        _check_labels(lab.cpu().numpy(), X, C, f"{m}-way {prec}")
+        assert nf > 0
+
+
 # ---------------------------------------------------------------------------
 # update and cost
 # ---------------------------------------------------------------------------

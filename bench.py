@@ -40,6 +40,22 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measured_traffic(key):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    passes, scaled by the copy-kernel calibration; None once the kernel source
+    no longer matches the hash recorded with the counters."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "assign_traffic_n4m_d512_k1000.json")
+    try:
+        rec = json.load(open(path))
+        src = open(os.path.join(ROOT, rec["kernel_source"]), "rb").read()
+        if hashlib.sha256(src).hexdigest() != rec["kernel_source_sha256"]:
+            return None
+        return rec[key]["hbm_bytes"]
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(X_host_rows, C_host, n_full, seconds_target=10.0):
     """Times the FP64 oracle (assignment + update of one Lloyd iteration) on a
     bounded row sample and scales to the full n."""
@@ -75,6 +91,10 @@ def main():
                     help="iterations of the plain FP32 comparison (default: --steps)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--only", choices=["assign"], default=None,
+                    help="profiling mode: only the assignment on the workload's data (centers = "
+                         "first k rows + noise), plus a plain 1 GiB device copy whose counters "
+                         "calibrate FETCH_SIZE / WRITE_SIZE")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -100,6 +120,24 @@ def main():
         X = torch.from_numpy(Xh).to(dev)
     torch.cuda.synchronize()
     ctx = kmx.Context(0)
+
+    if args.only == "assign":
+        g = torch.Generator(device=dev)
+        g.manual_seed(1)
+        C = X[:k].contiguous() + 0.05 * torch.randn(k, d, device=dev, generator=g)
+        cal = torch.empty(1 << 28, dtype=torch.float32, device=dev)      # 1 GiB
+        dst = torch.empty_like(cal)
+        for prec in ("bf16", "fp32"):
+            ctx.assign(X, C, prec=prec, want_d=False)
+            for _ in range(args.steps):
+                ctx.assign(X, C, prec=prec, want_d=False)
+            log(f"[bench] assign {prec} x{args.steps}")
+        for _ in range(3):
+            dst.copy_(cal)
+        torch.cuda.synchronize()
+        print(json.dumps({"mode": "assign-only", "n": n, "d": d, "k": k, "steps": args.steps,
+                          "copy_bytes_each_way": cal.numel() * 4}), flush=True)
+        return
 
     # ---- seeding (not part of the per-iteration metric) ----
     log("[bench] k-means++ seeding")
@@ -150,7 +188,8 @@ def main():
         "config": {"workload": wl["name"], "n": n, "d": d, "k": k,
                    "assign": "bf16 MFMA GEMM + FP32 re-check", "reduce": "fp64"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": BF16_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / BF16_PEAK_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / BF16_PEAK_TFLOPS,
+                     "traffic": measured_traffic("assign_bf16") if args.workload == "router" else None,
                      "kernel": "assign_kernel<bf16>", "avg_ms": assign_avg_ms,
                      "algorithmic_flops": flops},
         "update_roofline": {"bound": "hbm", "achieved": reduce_gbs, "peak": HBM_PEAK_GBS,

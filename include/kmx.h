@@ -152,11 +152,88 @@ kmx_status kmx_assign_stats(kmx_ctx* ctx, int64_t* listed, int64_t* fp32, int64_
  * kernel class on the context's stream.  kmx_timing_read returns the summed
  * milliseconds and launch counts per class since the last reset:
  *   class 0 prep (row statistics, quantization), 1 assign GEMM, 2 re-check,
- *   3 label sort, 4 segmented reduction, 5 finalize, 6 seeding, 7 other.
- * ms_out and count_out are host arrays of length n_classes (<= 8).
+ *   3 label sort, 4 segmented reduction, 5 finalize, 6 seeding, 7 other,
+ *   8 router forward pass, 9 center table + certificate, 10 router training.
+ * ms_out and count_out are host arrays of length n_classes (<= 11).
  * Reading synchronizes.  enable = 0 stops recording; reset clears sums. */
 kmx_status kmx_timing(kmx_ctx* ctx, int enable, int reset);
 kmx_status kmx_timing_read(kmx_ctx* ctx, int n_classes, double* ms_out, int64_t* count_out);
+
+/* ---------------------------------------------------------------------------
+ * Candidate router with a certificate.
+ *
+ * Not part of the paper's method: an accelerator of its assignment step
+ * (Sec. 1) that leaves every label unchanged.  A two-layer perceptron
+ *     z(x) = W2 relu(W1 x + b1) + b2,   W1: 256 x d, W2: k x 256,
+ * evaluated in BF16 with FP32 accumulation, proposes 16 candidate centers
+ * per point: the four highest logits within each quarter of the centers
+ * (quarter of center j: (j mod 16) div 4), which always contain the four
+ * highest logits overall.  An assignment using the proposals takes the best
+ * proposal b and an upper bound D of ||x - c_b||; a table of lower bounds of
+ * the center distances gives the centers within 2 D of c_b (Elkan's
+ * triangle-inequality lemma: no other center can be closer than c_b).  With
+ * none, c_b is the label; with one or two, all among the candidates, the
+ * exact comparison decides; otherwise the point goes through the GEMM
+ * assignment.  Requirements: 1 <= d <= 1024, 1 <= k <= 4096.
+ * ------------------------------------------------------------------------- */
+typedef struct kmx_router kmx_router;
+
+/* New router for inputs of width d and k centers, on ctx's device.
+ * Initial weights: W1 ~ N(0, 2/d), W2 ~ N(0, 1/256) from a SplitMix64 /
+ * Box-Muller stream seeded by init_seed; zero biases; Adam state cleared. */
+kmx_status kmx_router_create(kmx_ctx* ctx, int32_t d, int32_t k, uint64_t init_seed,
+                             kmx_router** out);
+kmx_status kmx_router_destroy(kmx_ctx* ctx, kmx_router* r);
+
+/* FP32 parameters, device arrays: W1 256 x d, b1 256, W2 k x 256, b2 k (row
+ * major).  set_params also clears the Adam state; get_params outputs are
+ * nullable. */
+kmx_status kmx_router_set_params(kmx_ctx* ctx, kmx_router* r, const float* W1, const float* b1,
+                                 const float* W2, const float* b2);
+kmx_status kmx_router_get_params(kmx_ctx* ctx, kmx_router* r, float* W1, float* b1, float* W2,
+                                 float* b2);
+
+/* Mean softmax cross-entropy of labels (device, n int32 in [0, k)) over the
+ * n rows of X (n <= 65536, one batch) and its gradients (device FP32 arrays
+ * shaped like the parameters, each nullable).  The network runs as in
+ * training: BF16 inputs, weights and activations, FP32 accumulation.
+ *   loss host, nullable (synchronizes). */
+kmx_status kmx_router_loss_grad(kmx_ctx* ctx, kmx_router* r, const float* X, int64_t n, int32_t d,
+                                int64_t ldx, const int32_t* labels, double* loss, float* dW1,
+                                float* db1, float* dW2, float* db2);
+
+/* Adam training (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr) on the
+ * n * n_sets pairs (x_i, labels[s * n + i]), s < n_sets (device int32): each
+ * epoch visits every pair once in batches of `batch` (<= 65536; the last one
+ * may be smaller), in a pseudo-random order drawn from shuffle_seed (0: the
+ * order s-major, i-minor).
+ *   loss_hist  host, nullable: mean loss of every step (epochs * steps per
+ *              epoch entries);
+ *   steps_done host, nullable.
+ * Synchronizes. */
+kmx_status kmx_router_train(kmx_ctx* ctx, kmx_router* r, const float* X, int64_t n, int32_t d,
+                            int64_t ldx, const int32_t* labels, int32_t n_sets, int32_t epochs,
+                            int32_t batch, float lr, uint64_t shuffle_seed, double* loss_hist,
+                            int64_t* steps_done);
+
+/* Proposals for the rows of X: cand_out device n x 16 int32; entries
+ * 4q .. 4q+3 are quarter q's four highest logits in decreasing order (-1
+ * where the quarter has fewer than four centers). */
+kmx_status kmx_router_propose(kmx_ctx* ctx, kmx_router* r, const float* X, int64_t n, int32_t d,
+                              int64_t ldx, int32_t* cand_out);
+
+/* Lloyd's algorithm as kmx_lloyd (same arguments, results and stopping
+ * rule) with the assignment step accelerated by certified proposals.  r
+ * gives the proposals (one forward pass per call: they depend on X only);
+ * r == NULL uses each point's previous label as its only candidate, the
+ * first assignment then running the full GEMM.  prec is the GEMM's
+ * precision for the remaining rows.
+ *   gemm_rows host, nullable, max_iter + 1 entries: rows of each
+ *             assignment (entries 0 .. iters) that went through the GEMM. */
+kmx_status kmx_lloyd_routed(kmx_ctx* ctx, kmx_router* r, const float* X, int64_t n, int32_t d,
+                            int64_t ldx, const float* w, float* C_inout, int32_t k,
+                            int32_t max_iter, double tol, kmx_prec prec, int32_t* label_out,
+                            double* cost_hist, int32_t* iters_done, int64_t* gemm_rows);
 
 #ifdef __cplusplus
 }

@@ -207,6 +207,8 @@ __global__ void reset_small_kernel(CenterStats* cs, CenterStats* cs2, LoopState*
       st->full_count = 0;
       st->flagged_full = 0;
       st->undecided = 0;
+      st->routed_fallback = 0;
+      st->routed_listed = 0;
       if (reset_iter) {
         st->done = 0;
         st->iter = 0;

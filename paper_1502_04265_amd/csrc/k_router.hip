@@ -1,0 +1,679 @@
+// Candidate router and its certificate (inference side).
+//
+// The router is a two-layer perceptron  z = W2 relu(W1 x + b1) + b2  with
+// H = 256 hidden units and one output per center, trained (k_train.hip) on
+// the labels of earlier Lloyd iterations.  It proposes 16 candidate centers
+// per point.  A proposal is used only under a triangle-inequality
+// certificate (Elkan 2003): with b the proposal's best center and D an upper
+// bound of ||x - c_b||, every center c with ||c_b - c|| >= 2 D satisfies
+// ||x - c|| >= ||c_b - c|| - ||x - c_b|| >= D >= ||x - c_b||, so it cannot be
+// closer than c_b.  The centers inside that radius are read from c_b's sorted
+// neighbour list (a k x k table of lower bounds of the center distances,
+// rebuilt for every center set).  No neighbour inside: c_b is the exact
+// closest center.  One or two, all of them candidates: the exact short
+// re-check decides between them and c_b.  Otherwise the row goes through the
+// GEMM assignment.  Labels are therefore those of the assignment step
+// (Sec. 1) whatever the network proposes; only the amount of GEMM work
+// depends on it.
+//
+// Forward pass layout (gfx950 MFMA 16x16x32 BF16, FP32 accumulate).  As in
+// the assignment GEMM, the point fragments stay in registers (B operand) and
+// weight tiles stream through LDS (A operand).  Layer 1 turns 16 hidden
+// units per tile into BF16 relu activations that remain in registers: lane l
+// holds units 4(l/16)..4(l/16)+3 of each 16-unit tile, and two consecutive
+// tiles form exactly the eight BF16 values the lane supplies for one 32-wide
+// K unit of layer 2.  The layer-2 weight columns are stored in that
+// permuted order, so no data moves between lanes.  The biases initialise the
+// accumulators.
+//
+// Proposals.  Each lane keeps the four largest logits of the centers it
+// sees, i.e. of one quarter of the centers (quarter q = (j mod 16) div 4).
+// The 16 proposals of a point are these four per quarter: they contain the
+// exact top four logits and, unless one quarter holds more than four of the
+// top 16, the exact top 16.  Logits are ordered through the monotone map of
+// float bits to unsigned integers; the low ib bits carry the center index.
+#include "kmx_device.h"
+#include "kmx_internal.h"
+
+namespace kmx {
+
+typedef __attribute__((ext_vector_type(8))) __bf16 rbf16x8_t;
+typedef __attribute__((ext_vector_type(2))) __bf16 rbf16x2_t;
+typedef __attribute__((ext_vector_type(4))) float rf32x4_t;
+typedef __attribute__((ext_vector_type(4))) unsigned int ru32x4_t;
+
+__device__ __forceinline__ unsigned r_med3(unsigned a, unsigned b, unsigned c) {
+  return max(min(a, b), min(max(a, b), c));
+}
+
+__device__ __forceinline__ void r_top4(unsigned key, unsigned& v1, unsigned& v2, unsigned& v3,
+                                       unsigned& v4) {
+  const unsigned n1 = max(v1, key);
+  const unsigned n2 = r_med3(v1, v2, key);
+  const unsigned n3 = r_med3(v2, v3, key);
+  const unsigned n4 = r_med3(v3, v4, key);
+  v1 = n1;
+  v2 = n2;
+  v3 = n3;
+  v4 = n4;
+}
+
+// Order-preserving map of float bit patterns onto unsigned integers.
+__device__ __forceinline__ unsigned ordered_bits(float f) {
+  const unsigned u = __float_as_uint(f);
+  return u ^ ((unsigned)((int)u >> 31) | 0x80000000u);
+}
+
+template <int NKU, int NCG, int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void router_fwd_kernel(
+    const uint16_t* __restrict__ Xq, int64_t xs, int64_t n, const uint16_t* __restrict__ W1a,
+    const float* __restrict__ b1, const uint16_t* __restrict__ W2a,
+    const float* __restrict__ b2p, int kpad, int ib, uint32_t* __restrict__ keys,
+    const int* __restrict__ gate) {
+  if (gate && *gate) return;
+  constexpr int ROW1 = NKU * 64;                     // bytes of a W1a row
+  constexpr int UROW1 = NKU * 4 + 1;                 // 16-byte units of a padded LDS row
+  constexpr int PITCH1 = UROW1 * 16;
+  constexpr int CH1 = (kRouterBN1 * UROW1 + 63) / 64;
+  constexpr int ROW2 = kRouterHU * 64;               // bytes of a W2a row
+  constexpr int UROW2 = kRouterHU * 4 + 1;
+  constexpr int PITCH2 = UROW2 * 16;
+  constexpr int CH2 = (kRouterBN2 * UROW2 + 63) / 64;
+  constexpr int CHM = CH1 > CH2 ? CH1 : CH2;
+  constexpr int NT1 = kRouterH / kRouterBN1;
+  constexpr int RB2 = kRouterBN2 / 16;
+  constexpr int PPB = WAVES * 16 * NCG;
+  static_assert(NT1 % 2 == 0, "layer 2 starts on buffer 0");
+  __shared__ __attribute__((aligned(1024))) unsigned char lds[2][CHM * 1024];
+  __shared__ __attribute__((aligned(16))) float sb1[kRouterH];
+  __shared__ __attribute__((aligned(16))) float sb2[kRouterMaxK];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int prow = lane & 15;
+  const int grp = lane >> 4;
+  const int64_t nblk = (n + PPB - 1) / PPB;
+  const int ntiles2 = kpad / kRouterBN2;
+  const unsigned mask = (1u << ib) - 1u;
+
+  for (int i = tid; i < kRouterH; i += WAVES * 64) sb1[i] = b1[i];
+  for (int i = tid; i < kpad; i += WAVES * 64) sb2[i] = b2p[i];
+  __syncthreads();
+
+  // Direct-to-LDS copy of a tile of `nrows` rows (rowb bytes each) into LDS
+  // rows of urow 16-byte units (one pad unit); lane l of chunk c carries the
+  // padded unit c*64 + l.  Pad units re-load the tile's first unit.
+  auto issue = [&](const unsigned char* base, int rowb, int urow, int nrows, int chunks,
+                   int buf) {
+    for (int c = wave; c < chunks; c += WAVES) {
+      const int q = c * 64 + lane;
+      const int row = q / urow;
+      const int uc = q - row * urow;
+      const unsigned char* src = (row < nrows && uc < urow - 1) ? base + row * rowb + uc * 16 : base;
+      __builtin_amdgcn_global_load_lds(
+          (const void*)src, (__attribute__((address_space(3))) void*)(&lds[buf][c * 1024]), 16,
+          0, 0);
+    }
+  };
+
+  for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+    const int64_t p_base = blk * PPB + (int64_t)wave * (16 * NCG);
+    ru32x4_t xf[NCG][NKU];
+#pragma unroll
+    for (int cg = 0; cg < NCG; ++cg) {
+      const int64_t p = p_base + cg * 16 + prow;
+      const bool pv = p < n;
+#pragma unroll
+      for (int ku = 0; ku < NKU; ++ku) {
+        ru32x4_t v = {0u, 0u, 0u, 0u};
+        if (pv) v = *(const ru32x4_t*)(Xq + p * xs + ku * 32 + grp * 8);
+        xf[cg][ku] = v;
+      }
+    }
+
+    // ---- layer 1: hidden activations, kept as layer-2 B fragments ----
+    ru32x4_t hf[NCG][kRouterHU];
+    issue((const unsigned char*)W1a, ROW1, UROW1, kRouterBN1, CH1, 0);
+    __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < NT1; ++t) {
+      const int buf = t & 1;
+      if (t + 1 < NT1)
+        issue((const unsigned char*)W1a + (t + 1) * kRouterBN1 * ROW1, ROW1, UROW1, kRouterBN1,
+              CH1, buf ^ 1);
+      else
+        issue((const unsigned char*)W2a, ROW2, UROW2, kRouterBN2, CH2, buf ^ 1);
+      const rf32x4_t bias = *(const rf32x4_t*)(&sb1[t * kRouterBN1 + grp * 4]);
+      rf32x4_t acc[NCG];
+#pragma unroll
+      for (int cg = 0; cg < NCG; ++cg) acc[cg] = bias;
+      const unsigned char* abase = &lds[buf][prow * PITCH1 + grp * 16];
+#pragma unroll
+      for (int ku = 0; ku < NKU; ++ku) {
+        const ru32x4_t a = *(const ru32x4_t*)(abase + ku * 64);
+#pragma unroll
+        for (int cg = 0; cg < NCG; ++cg)
+          acc[cg] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+              __builtin_bit_cast(rbf16x8_t, a), __builtin_bit_cast(rbf16x8_t, xf[cg][ku]),
+              acc[cg], 0, 0, 0);
+      }
+#pragma unroll
+      for (int cg = 0; cg < NCG; ++cg) {
+        const rbf16x2_t p0 = {(__bf16)fmaxf(acc[cg][0], 0.0f), (__bf16)fmaxf(acc[cg][1], 0.0f)};
+        const rbf16x2_t p1 = {(__bf16)fmaxf(acc[cg][2], 0.0f), (__bf16)fmaxf(acc[cg][3], 0.0f)};
+        hf[cg][t >> 1][(t & 1) * 2] = __builtin_bit_cast(unsigned, p0);
+        hf[cg][t >> 1][(t & 1) * 2 + 1] = __builtin_bit_cast(unsigned, p1);
+      }
+      __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      __syncthreads();
+    }
+
+    // ---- layer 2: logits and the per-quarter top four ----
+    unsigned v1[NCG], v2[NCG], v3[NCG], v4[NCG];
+#pragma unroll
+    for (int cg = 0; cg < NCG; ++cg) v1[cg] = v2[cg] = v3[cg] = v4[cg] = 0u;
+    for (int t2 = 0; t2 < ntiles2; ++t2) {
+      const int buf = t2 & 1;
+      if (t2 + 1 < ntiles2)
+        issue((const unsigned char*)W2a + (int64_t)(t2 + 1) * kRouterBN2 * ROW2, ROW2, UROW2,
+              kRouterBN2, CH2, buf ^ 1);
+      rf32x4_t acc[NCG][RB2];
+#pragma unroll
+      for (int rb = 0; rb < RB2; ++rb) {
+        const rf32x4_t bias = *(const rf32x4_t*)(&sb2[t2 * kRouterBN2 + rb * 16 + grp * 4]);
+#pragma unroll
+        for (int cg = 0; cg < NCG; ++cg) acc[cg][rb] = bias;
+      }
+      const unsigned char* abase = &lds[buf][prow * PITCH2 + grp * 16];
+#pragma unroll
+      for (int u = 0; u < kRouterHU; ++u) {
+#pragma unroll
+        for (int rb = 0; rb < RB2; ++rb) {
+          const ru32x4_t a = *(const ru32x4_t*)(abase + rb * 16 * PITCH2 + u * 64);
+#pragma unroll
+          for (int cg = 0; cg < NCG; ++cg)
+            acc[cg][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                __builtin_bit_cast(rbf16x8_t, a), __builtin_bit_cast(rbf16x8_t, hf[cg][u]),
+                acc[cg][rb], 0, 0, 0);
+        }
+      }
+      const unsigned ibase = mask - (unsigned)(t2 * kRouterBN2 + grp * 4);
+#pragma unroll
+      for (int rb = 0; rb < RB2; ++rb) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const unsigned idx = ibase - (unsigned)(rb * 16 + i);
+#pragma unroll
+          for (int cg = 0; cg < NCG; ++cg) {
+            const unsigned key = (ordered_bits(acc[cg][rb][i]) & ~mask) | (idx & mask);
+            r_top4(key, v1[cg], v2[cg], v3[cg], v4[cg]);
+          }
+        }
+      }
+      __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      __syncthreads();
+    }
+
+#pragma unroll
+    for (int cg = 0; cg < NCG; ++cg) {
+      const int64_t p = p_base + cg * 16 + prow;
+      if (p < n) {
+        const ru32x4_t o = {v1[cg], v2[cg], v3[cg], v4[cg]};
+        *(ru32x4_t*)(keys + p * kRouterM + grp * 4) = o;
+      }
+    }
+  }
+}
+
+// Units of 32 BF16 columns the forward pass reads from each row of the
+// quantized X (dp columns): the smallest instantiated count covering d.
+static const int kRouterUnits[] = {1, 2, 3, 5, 9, 16, 17, 24, 32, 33};
+
+int router_units(int d, int dp) {
+  const int need = (d + 31) / 32;
+  for (int u : kRouterUnits)
+    if (u >= need && u * 32 <= dp) return u;
+  return -1;
+}
+
+template <int NKU, int NCG, int WAVES>
+static hipError_t run_router_fwd(hipStream_t s, const uint16_t* Xq, int64_t xs, int64_t n,
+                                 const uint16_t* W1a, const float* b1, const uint16_t* W2a,
+                                 const float* b2p, int kpad, int ib, uint32_t* keys,
+                                 const int* gate, int num_cus) {
+  const int64_t ppb = (int64_t)WAVES * 16 * NCG;
+  int64_t blocks = (n + ppb - 1) / ppb;
+  const int64_t cap = (int64_t)num_cus * 2;
+  if (blocks > cap) blocks = cap;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL((router_fwd_kernel<NKU, NCG, WAVES>), dim3((unsigned)blocks),
+                     dim3(WAVES * 64), 0, s, Xq, xs, n, W1a, b1, W2a, b2p, kpad, ib, keys, gate);
+  return hipGetLastError();
+}
+
+hipError_t launch_router_fwd(hipStream_t s, const uint16_t* Xq, int64_t dp, int64_t n, int d,
+                             const uint16_t* W1a, const float* b1, const uint16_t* W2a,
+                             const float* b2p, int kpad, uint32_t* keys, const int* gate,
+                             int num_cus) {
+  if (kpad % kRouterBN2 != 0 || kpad > kRouterMaxK) return hipErrorInvalidValue;
+  int ib = 1;
+  while ((1 << ib) < kpad) ++ib;
+  switch (router_units(d, (int)dp)) {
+// Two point groups per wave keep both layers' fragments in registers; for 16
+// and 17 units that needs more than the 256 registers of two waves per SIMD,
+// so those run one wave per SIMD (four waves per workgroup).
+#define KMX_R(U, G, W)                                                                     \
+  case U:                                                                                  \
+    return run_router_fwd<U, G, W>(s, Xq, dp, n, W1a, b1, W2a, b2p, kpad, ib, keys, gate, \
+                                   num_cus)
+    KMX_R(1, 2, 8);
+    KMX_R(2, 2, 8);
+    KMX_R(3, 2, 8);
+    KMX_R(5, 2, 8);
+    KMX_R(9, 2, 8);
+    KMX_R(16, 2, 4);
+    KMX_R(17, 2, 4);
+    KMX_R(24, 1, 8);
+    KMX_R(32, 1, 8);
+    KMX_R(33, 1, 8);
+#undef KMX_R
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Inference layouts of the network from the FP32 parameters.
+//   W1a[h][c] = bf16(W1[h][c]) for c < d, 0 up to the row length r1;
+//   W2a[j][p] = bf16(W2[j][pi(p)]), p = 32u + 8g + e, pi(p) = 32u + 4g + e
+//               for e < 4 and 32u + 16 + 4g + (e - 4) otherwise; zero rows
+//               for padding centers;
+//   b2p[j]    = b2[j], -inf for padding centers.
+// ---------------------------------------------------------------------------
+__global__ void router_layout_kernel(const float* __restrict__ W1, const float* __restrict__ W2,
+                                     const float* __restrict__ b2, int d, int k, int kpad, int r1,
+                                     uint16_t* __restrict__ W1a, uint16_t* __restrict__ W2a,
+                                     float* __restrict__ b2p) {
+  const int64_t n1 = (int64_t)kRouterH * r1;
+  const int64_t n2 = (int64_t)kpad * kRouterH;
+  const int64_t total = n1 + n2 + kpad;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    if (i < n1) {
+      const int h = (int)(i / r1), c = (int)(i % r1);
+      W1a[i] = (c < d) ? f32_to_bf16_rne(W1[(int64_t)h * d + c]) : (uint16_t)0;
+    } else if (i < n1 + n2) {
+      const int64_t e2 = i - n1;
+      const int j = (int)(e2 / kRouterH), p = (int)(e2 % kRouterH);
+      const int u = p >> 5, g = (p >> 3) & 3, e = p & 7;
+      const int h = 32 * u + (e < 4 ? 4 * g + e : 16 + 4 * g + (e - 4));
+      W2a[e2] = (j < k) ? f32_to_bf16_rne(W2[(int64_t)j * kRouterH + h]) : (uint16_t)0;
+    } else {
+      const int j = (int)(i - n1 - n2);
+      b2p[j] = (j < k) ? b2[j] : -__builtin_inff();
+    }
+  }
+}
+
+hipError_t launch_router_layout(hipStream_t s, const float* W1, const float* W2, const float* b2,
+                                int d, int k, int kpad, int r1, uint16_t* W1a, uint16_t* W2a,
+                                float* b2p) {
+  const int64_t total = (int64_t)kRouterH * r1 + (int64_t)kpad * kRouterH + kpad;
+  int64_t blocks = (total + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(router_layout_kernel, dim3((unsigned)blocks), dim3(256), 0, s, W1, W2, b2, d,
+                     k, kpad, r1, W1a, W2a, b2p);
+  return hipGetLastError();
+}
+
+// Proposals as center indices (-1 where a quarter had fewer than four
+// centers): cand[i][4q + r] is the r-th best of quarter q.
+__global__ void router_decode_kernel(const uint32_t* __restrict__ keys, int64_t count, int k,
+                                     int ib, int32_t* __restrict__ cand) {
+  const unsigned mask = (1u << ib) - 1u;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int j = (int)(mask - (keys[i] & mask));
+    cand[i] = (j < k) ? j : -1;
+  }
+}
+
+hipError_t launch_router_decode(hipStream_t s, const uint32_t* keys, int64_t count, int k,
+                                int kpad, int32_t* cand) {
+  int ib = 1;
+  while ((1 << ib) < kpad) ++ib;
+  int64_t blocks = (count + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(router_decode_kernel, dim3((unsigned)blocks), dim3(256), 0, s, keys, count, k,
+                     ib, cand);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Center-distance table.  Pass 1 (tiles of 64 x 64 centers, 4 x 4 per
+// thread): D[b][c] = a lower bound of ||c_b - c_c||.  The FP32 sum of d
+// squared direct differences has relative error below (d + 3) u, u = 2^-24,
+// so sqrt(s (1 - 2 (d + 8) u)) (1 - 4 u) is a lower bound.  Pass 2 (one
+// workgroup per center): the kNbrL nearest other centers sorted by that
+// bound (bitonic sort of (bound, index) keys in LDS), and the bound of the
+// next one (+inf when none).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void center_dist_kernel(const float* __restrict__ C, int k, int d,
+                                                          float* __restrict__ D,
+                                                          const int* __restrict__ gate) {
+  if (gate && *gate) return;
+  __shared__ float Bt[32][65];
+  __shared__ float Ct[32][65];
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  const int b0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
+  float acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0f;
+  for (int k0 = 0; k0 < d; k0 += 32) {
+    for (int e = tid; e < 64 * 32; e += 256) {
+      const int rr = e >> 5, kk = e & 31, kc = k0 + kk;
+      Bt[kk][rr] = (b0 + rr < k && kc < d) ? C[(int64_t)(b0 + rr) * d + kc] : 0.0f;
+      Ct[kk][rr] = (c0 + rr < k && kc < d) ? C[(int64_t)(c0 + rr) * d + kc] : 0.0f;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int kk = 0; kk < 32; ++kk) {
+      float bv[4], cv[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        bv[i] = Bt[kk][ty + 16 * i];
+        cv[i] = Ct[kk][tx + 16 * i];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const float df = bv[i] - cv[j];
+          acc[i][j] = __builtin_fmaf(df, df, acc[i][j]);
+        }
+    }
+    __syncthreads();
+  }
+  const float u = 5.9604645e-8f;
+  const float shrink = 1.0f - 2.0f * (float)(d + 8) * u;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int b = b0 + ty + 16 * i, c = c0 + tx + 16 * j;
+      if (b < k && c < k)
+        D[(int64_t)b * k + c] =
+            (b == c) ? __builtin_inff() : sqrtf(fmaxf(acc[i][j] * shrink, 0.0f)) * (1.0f - 4.0f * u);
+    }
+}
+
+__global__ __launch_bounds__(256) void center_select_kernel(const float* __restrict__ D, int k,
+                                                            int kp2, int32_t* __restrict__ nbr,
+                                                            float* __restrict__ nbd,
+                                                            const int* __restrict__ gate) {
+  if (gate && *gate) return;
+  extern __shared__ unsigned long long sk[];
+  const int b = blockIdx.x;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < kp2; i += 256) {
+    unsigned long long key = ~0ull;
+    if (i < k && i != b)
+      key = ((unsigned long long)__float_as_uint(D[(int64_t)b * k + i]) << 32) | (unsigned)i;
+    sk[i] = key;
+  }
+  __syncthreads();
+  for (int size = 2; size <= kp2; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int t = tid; t < (kp2 >> 1); t += 256) {
+        const int lo = (t / stride) * 2 * stride + (t % stride);
+        const int hi = lo + stride;
+        const bool up = (lo & size) == 0;
+        const unsigned long long a = sk[lo], c = sk[hi];
+        if ((a > c) == up) {
+          sk[lo] = c;
+          sk[hi] = a;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = tid; i <= kNbrL; i += 256) {
+    const unsigned long long key = (i < kp2) ? sk[i] : ~0ull;
+    const bool none = key == ~0ull;
+    if (i < kNbrL) nbr[(int64_t)b * kNbrL + i] = none ? -1 : (int)(key & 0xFFFFFFFFull);
+    nbd[(int64_t)b * (kNbrL + 1) + i] = none ? __builtin_inff() : __uint_as_float((unsigned)(key >> 32));
+  }
+}
+
+hipError_t launch_center_table(hipStream_t s, const float* C, int k, int d, float* D, int32_t* nbr,
+                               float* nbd, const int* gate) {
+  if (k > kRouterMaxK) return hipErrorInvalidValue;
+  const unsigned tiles = (unsigned)((k + 63) / 64);
+  hipLaunchKernelGGL(center_dist_kernel, dim3(tiles, tiles), dim3(256), 0, s, C, k, d, D, gate);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  int kp2 = 2;
+  while (kp2 < k) kp2 <<= 1;
+  hipLaunchKernelGGL(center_select_kernel, dim3((unsigned)k), dim3(256),
+                     (size_t)kp2 * sizeof(unsigned long long), s, D, k, kp2, nbr, nbd, gate);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Certificate.  16 lanes per row, 4 rows per wave; a workgroup decides a
+// chunk of 1024 rows, then appends its list entries with one atomic per list.
+//   D_ub = sqrt(s (1 + (d + 16) u)) (1 + 4 u) + ||x - x~||, s the FP32 sum of
+//          (x~_e - c_e)^2 over the BF16 row x~ (triangle inequality for the
+//          quantization, relative error of the sum below (d/16 + 8) u);
+//   R    = 2 D_ub (1 + 8 u);
+//   m    = number of listed neighbours with lower bound < R.
+// Decision: m = 0 -> label = b; 1 <= m <= 2 with every such neighbour among
+// the candidates -> label = b plus a short re-check entry; otherwise (or the
+// list is exhausted, or no proposal) -> GEMM row list.
+// ROUTED = false takes the previous label as the only candidate.
+// ---------------------------------------------------------------------------
+template <bool ROUTED>
+__global__ __launch_bounds__(256) void router_cert_kernel(
+    const uint16_t* __restrict__ Xq, int64_t xs, int64_t n, int d, const float* __restrict__ C,
+    int k, const RowStats* __restrict__ rs, const uint32_t* __restrict__ keys, int ib,
+    const int32_t* __restrict__ nbr, const float* __restrict__ nbd, int32_t* __restrict__ label,
+    FlagEntry* __restrict__ flags, int* __restrict__ fb_rows, LoopState* __restrict__ st,
+    const int* __restrict__ gate) {
+  if (gate && *gate) return;
+  constexpr int RPW = 256;
+  constexpr int RPB = 4 * RPW;
+  __shared__ unsigned char kind[RPB];  // 0 certified, 1 certified + re-check, 2 GEMM, 3 none
+  __shared__ int rn0[RPB], rn1[RPB];
+  __shared__ int wcnt[2][4];
+  __shared__ unsigned long long wbase[2];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int q = lane & 15, sub = lane >> 4;
+  const unsigned mask = (1u << ib) - 1u;
+  const float u = 5.9604645e-8f;
+  const float gam = (float)(d + 16) * u;
+  const bool vec = ((((uintptr_t)C) & 15) == 0) && (d % 8 == 0);
+  const int64_t nchunks = (n + RPB - 1) / RPB;
+  const unsigned long long below = (1ull << lane) - 1ull;
+
+  for (int64_t chk = blockIdx.x; chk < nchunks; chk += gridDim.x) {
+    const int64_t r0 = chk * RPB + (int64_t)wave * RPW;
+    for (int pass = 0; pass < RPW / 4; ++pass) {
+      const int slot = pass * 4 + sub;
+      const int64_t r = r0 + slot;
+      const bool valid = r < n;
+      int b0 = 0, cand = -1;
+      bool ok = valid;
+      if (ROUTED) {
+        const unsigned key = valid ? keys[r * kRouterM + q] : 0u;
+        const int ci = (int)(mask - (key & mask));
+        cand = (valid && ci < k) ? ci : -1;
+        unsigned best = (cand >= 0) ? key : 0u;
+#pragma unroll
+        for (int m = 8; m >= 1; m >>= 1) best = max(best, (unsigned)__shfl_xor((int)best, m, 64));
+        if (best == 0u) ok = false;
+        b0 = ok ? (int)(mask - (best & mask)) : 0;
+        if (b0 >= k) {
+          ok = false;
+          b0 = 0;
+        }
+      } else {
+        b0 = valid ? label[r] : 0;
+        if (b0 < 0 || b0 >= k) {
+          ok = false;
+          b0 = 0;
+        }
+        cand = (q == 0) ? b0 : -1;
+      }
+
+      // upper bound of ||x - c_b0||
+      const float* c = C + (int64_t)b0 * d;
+      const uint16_t* xr = Xq + (valid ? r : 0) * xs;
+      float s = 0.0f;
+      for (int e0 = q * 8; e0 < d; e0 += 128) {
+        if (vec) {
+          const ru32x4_t xv = *(const ru32x4_t*)(xr + e0);
+          const float4 ca = *(const float4*)(c + e0);
+          const float4 cb = *(const float4*)(c + e0 + 4);
+          const float cc[8] = {ca.x, ca.y, ca.z, ca.w, cb.x, cb.y, cb.z, cb.w};
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const unsigned w2 = xv[e >> 1];
+            const float xe = __uint_as_float((e & 1) ? (w2 & 0xFFFF0000u) : (w2 << 16));
+            const float df = xe - cc[e];
+            s = __builtin_fmaf(df, df, s);
+          }
+        } else {
+          const int e1 = min(e0 + 8, d);
+          for (int e = e0; e < e1; ++e) {
+            const float df = bf16_to_f32(xr[e]) - c[e];
+            s = __builtin_fmaf(df, df, s);
+          }
+        }
+      }
+#pragma unroll
+      for (int m = 8; m >= 1; m >>= 1) s += __shfl_xor(s, m, 64);
+      const float rx = valid ? rs[r].rx : 0.0f;
+      const float dub = sqrtf(s * (1.0f + gam)) * (1.0f + 4.0f * u) + rx;
+      const float R = 2.0f * dub * (1.0f + 8.0f * u);
+
+      // walk b0's sorted neighbour list
+      const float* nd = nbd + (int64_t)b0 * (kNbrL + 1);
+      const unsigned long long bal0 = __ballot(nd[q] < R);
+      const unsigned long long bal1 = __ballot(nd[q + 16] < R);
+      const int m = __popcll((bal0 >> (16 * sub)) & 0xFFFFull) +
+                    __popcll((bal1 >> (16 * sub)) & 0xFFFFull);
+      const bool exhausted = (m == kNbrL) && (nd[kNbrL] < R);
+      const int n0 = (m >= 1) ? nbr[(int64_t)b0 * kNbrL] : -2;
+      const int n1 = (m >= 2) ? nbr[(int64_t)b0 * kNbrL + 1] : -2;
+      const unsigned long long h0 = __ballot(cand >= 0 && cand == n0);
+      const unsigned long long h1 = __ballot(cand >= 0 && cand == n1);
+      const bool has0 = ((h0 >> (16 * sub)) & 0xFFFFull) != 0ull;
+      const bool has1 = ((h1 >> (16 * sub)) & 0xFFFFull) != 0ull;
+      int kd;
+      if (!valid) kd = 3;
+      else if (!ok || exhausted || m > 2) kd = 2;
+      else if (m == 0) kd = 0;
+      else kd = (has0 && (m < 2 || has1)) ? 1 : 2;
+      if (q == 0) {
+        const int rec = wave * RPW + slot;
+        kind[rec] = (unsigned char)kd;
+        rn0[rec] = n0;
+        rn1[rec] = (m == 2) ? n1 : -1;
+        if (kd <= 1) label[r] = b0;
+      }
+    }
+    __syncthreads();
+
+    int nf = 0, nb = 0;
+    for (int i = lane; i < RPW; i += 64) {
+      const int kd = kind[wave * RPW + i];
+      nf += (kd == 1);
+      nb += (kd == 2);
+    }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+      nf += __shfl_xor(nf, m, 64);
+      nb += __shfl_xor(nb, m, 64);
+    }
+    if (lane == 0) {
+      wcnt[0][wave] = nf;
+      wcnt[1][wave] = nb;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      const int sf = wcnt[0][0] + wcnt[0][1] + wcnt[0][2] + wcnt[0][3];
+      const int sb = wcnt[1][0] + wcnt[1][1] + wcnt[1][2] + wcnt[1][3];
+      wbase[0] = sf ? atomicAdd(&st->flagged, (unsigned long long)sf) : 0ull;
+      wbase[1] = sb ? atomicAdd(&st->routed_fallback, (unsigned long long)sb) : 0ull;
+      if (sf) atomicAdd(&st->routed_listed, (unsigned long long)sf);
+    }
+    __syncthreads();
+    unsigned long long of = wbase[0], ob = wbase[1];
+    for (int w = 0; w < wave; ++w) {
+      of += wcnt[0][w];
+      ob += wcnt[1][w];
+    }
+    for (int i0 = 0; i0 < RPW; i0 += 64) {
+      const int rec = wave * RPW + i0 + lane;
+      const int kd = kind[rec];
+      const unsigned long long bf = __ballot(kd == 1);
+      const unsigned long long bb = __ballot(kd == 2);
+      const int row = (int)(r0 + i0 + lane);
+      if (kd == 1) {
+        FlagEntry fe;
+        fe.row = row;
+        fe.cand2 = rn0[rec];
+        fe.cand3 = rn1[rec];
+        fe.pad = 0;
+        flags[of + __popcll(bf & below)] = fe;
+      }
+      if (kd == 2) fb_rows[ob + __popcll(bb & below)] = row;
+      of += __popcll(bf);
+      ob += __popcll(bb);
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_router_cert(hipStream_t s, const uint16_t* Xq, int64_t dp, int64_t n, int d,
+                              const float* C, int k, const RowStats* rs, const uint32_t* keys,
+                              int kpad, const int32_t* nbr, const float* nbd, int32_t* label,
+                              FlagEntry* flags, int* fb_rows, LoopState* st, const int* gate,
+                              int num_cus) {
+  int ib = 1;
+  while ((1 << ib) < kpad) ++ib;
+  int64_t blocks = (n + 1023) / 1024;
+  const int64_t cap = (int64_t)num_cus * 8;
+  if (blocks > cap) blocks = cap;
+  if (blocks < 1) blocks = 1;
+  if (keys)
+    hipLaunchKernelGGL(router_cert_kernel<true>, dim3((unsigned)blocks), dim3(256), 0, s, Xq, dp,
+                       n, d, C, k, rs, keys, ib, nbr, nbd, label, flags, fb_rows, st, gate);
+  else
+    hipLaunchKernelGGL(router_cert_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, s, Xq, dp,
+                       n, d, C, k, rs, keys, ib, nbr, nbd, label, flags, fb_rows, st, gate);
+  return hipGetLastError();
+}
+
+// fbh[slot] = rows sent to the GEMM by the last certificate pass (or `all`
+// when all_rows != 0); skipped once the loop has stopped.
+__global__ void record_fallback_kernel(const LoopState* __restrict__ st, int64_t* __restrict__ fbh,
+                                       int slot, int all_rows, int64_t all,
+                                       const int* __restrict__ gate) {
+  if (gate && *gate) return;
+  if (threadIdx.x == 0) fbh[slot] = all_rows ? all : (int64_t)st->routed_fallback;
+}
+
+hipError_t launch_record_fallback(hipStream_t s, const LoopState* st, int64_t* fbh, int slot,
+                                  int all_rows, int64_t all, const int* gate) {
+  hipLaunchKernelGGL(record_fallback_kernel, dim3(1), dim3(64), 0, s, st, fbh, slot, all_rows, all,
+                     gate);
+  return hipGetLastError();
+}
+
+}  // namespace kmx

@@ -6,101 +6,15 @@
 #include <cstring>
 #include <string>
 
-#include "kmx_internal.h"
+#include "host_util.h"
 
 using namespace kmx;
+using namespace kmx::host;
 
-namespace {
+namespace kmx {
+namespace host {
 
 thread_local std::string g_create_err;
-
-kmx_status fail(kmx_ctx* ctx, kmx_status st, const std::string& msg) {
-  if (ctx) ctx->err = msg;
-  else g_create_err = msg;
-  return st;
-}
-
-#define KMX_HIP(ctx, call)                                                          \
-  do {                                                                              \
-    hipError_t e_ = (call);                                                         \
-    if (e_ != hipSuccess) {                                                         \
-      (void)hipGetLastError();                                                      \
-      return fail(ctx, KMX_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
-    }                                                                               \
-  } while (0)
-
-#define KMX_TRY(expr)               \
-  do {                              \
-    kmx_status s_ = (expr);         \
-    if (s_ != KMX_OK) return s_;    \
-  } while (0)
-
-kmx_status grow(kmx_ctx* ctx, Buf& b, size_t bytes) {
-  if (bytes == 0) bytes = 16;
-  if (b.bytes >= bytes) return KMX_OK;
-  if (b.p) {
-    KMX_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    KMX_HIP(ctx, hipFree(b.p));
-    b.p = nullptr;
-    b.bytes = 0;
-  }
-  void* p = nullptr;
-  hipError_t e = hipMalloc(&p, bytes);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    return fail(ctx, KMX_ENOMEM,
-                "hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
-  }
-  b.p = p;
-  b.bytes = bytes;
-  return KMX_OK;
-}
-
-template <typename T>
-T* P(const Buf& b) { return reinterpret_cast<T*>(b.p); }
-
-// ---- timing: HIP events around each kernel class on the context stream ----
-hipEvent_t take_event(kmx_ctx* c) {
-  if (!c->pool.empty()) {
-    hipEvent_t e = c->pool.back();
-    c->pool.pop_back();
-    return e;
-  }
-  hipEvent_t e = nullptr;
-  if (hipEventCreate(&e) != hipSuccess) {
-    (void)hipGetLastError();
-    return nullptr;
-  }
-  return e;
-}
-
-struct Timed {
-  kmx_ctx* c;
-  int cls;
-  hipEvent_t a = nullptr;
-  Timed(kmx_ctx* c_, int cls_) : c(c_), cls(cls_) {
-    if (c->timing) {
-      a = take_event(c);
-      if (a) (void)hipEventRecord(a, c->stream);
-    }
-  }
-  ~Timed() {
-    if (c->timing && a) {
-      hipEvent_t b = take_event(c);
-      if (b) {
-        (void)hipEventRecord(b, c->stream);
-        c->recs.push_back({cls, a, b});
-      } else {
-        c->pool.push_back(a);
-      }
-    }
-  }
-};
-
-kmx_status set_device(kmx_ctx* ctx) {
-  KMX_HIP(ctx, hipSetDevice(ctx->device));
-  return KMX_OK;
-}
 
 kmx_status check_problem(kmx_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
                          int32_t k) {
@@ -179,8 +93,6 @@ kmx_status ensure_common(kmx_ctx* ctx, int64_t n, int d, int k) {
   return KMX_OK;
 }
 
-LoopState* ST(kmx_ctx* ctx) { return P<LoopState>(ctx->state); }
-
 kmx_status write_state(kmx_ctx* ctx, int max_iter, double tol) {
   LoopState h;
   std::memset(&h, 0, sizeof(h));
@@ -191,11 +103,7 @@ kmx_status write_state(kmx_ctx* ctx, int max_iter, double tol) {
   return KMX_OK;
 }
 
-// prep_centers + GEMM assignment + re-check.  gate: skip when *gate != 0.
-// BF16: rows whose candidate set the BF16 bound cannot narrow to two centers
-// go through the FP32 GEMM (same kernel, listed rows) before the re-check.
-kmx_status run_assign(kmx_ctx* ctx, const float* X, int64_t n, int d, int64_t ldx, const float* C,
-                      int k, int prec, int32_t* label, float* d1, float* d2, const int* gate) {
+kmx_status run_prep_centers(kmx_ctx* ctx, const float* C, int k, int d, int prec) {
   LoopState* st = ST(ctx);
   CenterStats* cs = P<CenterStats>(ctx->cstats);
   CenterStats* cs32 = P<CenterStats>(ctx->cstats32);
@@ -204,29 +112,45 @@ kmx_status run_assign(kmx_ctx* ctx, const float* X, int64_t n, int d, int64_t ld
   const int kpad32 = (k + bn32 - 1) / bn32 * bn32;
   KMX_TRY(grow(ctx, ctx->cq32, (size_t)kpad32 * dp32 * sizeof(float)));
   KMX_TRY(grow(ctx, ctx->ch32, (size_t)kpad32 * sizeof(float)));
-  {
-    Timed tm(ctx, T_PREP);
-    KMX_HIP(ctx, launch_reset_small(ctx->stream, cs, cs32, st, 0));
-    KMX_HIP(ctx, launch_prep_centers(ctx->stream, C, k, d, kpad32, dp32, KMX_FP32, ctx->cq32.p,
-                                     P<float>(ctx->ch32), nullptr, cs32, nullptr));
-  }
-  const RowStats* rs = P<RowStats>(ctx->rowstats);
-  FlagEntry* flags = P<FlagEntry>(ctx->flags);
+  Timed tm(ctx, T_PREP);
+  KMX_HIP(ctx, launch_reset_small(ctx->stream, cs, cs32, st, 0));
+  KMX_HIP(ctx, launch_prep_centers(ctx->stream, C, k, d, kpad32, dp32, KMX_FP32, ctx->cq32.p,
+                                   P<float>(ctx->ch32), nullptr, cs32, nullptr));
   if (prec == KMX_BF16) {
     const int dp = assign_dpad(KMX_BF16, d);
     const int bn = assign_tile_n(KMX_BF16, d);
     const int kpad = (k + bn - 1) / bn * bn;
     KMX_TRY(grow(ctx, ctx->cq, (size_t)kpad * dp * sizeof(uint16_t)));
     KMX_TRY(grow(ctx, ctx->hd, (size_t)kpad * sizeof(double)));
-    {
-      Timed tm(ctx, T_PREP);
-      KMX_HIP(ctx, launch_prep_centers(ctx->stream, C, k, d, kpad, dp, KMX_BF16, ctx->cq.p, nullptr,
-                                       P<double>(ctx->hd), cs, P<unsigned>(ctx->xstats)));
-    }
+    KMX_HIP(ctx, launch_prep_centers(ctx->stream, C, k, d, kpad, dp, KMX_BF16, ctx->cq.p, nullptr,
+                                     P<double>(ctx->hd), cs, P<unsigned>(ctx->xstats)));
+  }
+  return KMX_OK;
+}
+
+// BF16: rows whose candidate set the BF16 bound cannot narrow to three
+// centers go through the FP32 GEMM (same kernel, listed rows) before the
+// re-check.  gate: skip when *gate != 0.
+kmx_status run_assign_gemm(kmx_ctx* ctx, const float* X, int64_t n, int d, int64_t ldx,
+                           const float* C, int k, int prec, int32_t* label, float* d1,
+                           float* d2, const int* rows, const unsigned long long* row_count,
+                           const int* gate) {
+  LoopState* st = ST(ctx);
+  CenterStats* cs = P<CenterStats>(ctx->cstats);
+  CenterStats* cs32 = P<CenterStats>(ctx->cstats32);
+  const int dp32 = assign_dpad(KMX_FP32, d);
+  const int bn32 = assign_tile_n(KMX_FP32, d);
+  const int kpad32 = (k + bn32 - 1) / bn32 * bn32;
+  const RowStats* rs = P<RowStats>(ctx->rowstats);
+  FlagEntry* flags = P<FlagEntry>(ctx->flags);
+  if (prec == KMX_BF16) {
+    const int dp = assign_dpad(KMX_BF16, d);
+    const int bn = assign_tile_n(KMX_BF16, d);
+    const int kpad = (k + bn - 1) / bn * bn;
     {
       Timed tm(ctx, T_ASSIGN);
-      KMX_HIP(ctx, launch_assign(ctx->stream, KMX_BF16, X, ldx, P<uint16_t>(ctx->xq), n, nullptr,
-                                 nullptr, d, dp, rs, ctx->cq.p, nullptr, k, kpad, cs, label, d1,
+      KMX_HIP(ctx, launch_assign(ctx->stream, KMX_BF16, X, ldx, P<uint16_t>(ctx->xq), n, rows,
+                                 row_count, d, dp, rs, ctx->cq.p, nullptr, k, kpad, cs, label, d1,
                                  d2, flags, P<int>(ctx->full_rows), P<int>(ctx->brute), st, gate,
                                  ctx->num_cus));
     }
@@ -239,9 +163,10 @@ kmx_status run_assign(kmx_ctx* ctx, const float* X, int64_t n, int d, int64_t ld
     }
   } else {
     Timed tm(ctx, T_ASSIGN);
-    KMX_HIP(ctx, launch_assign(ctx->stream, KMX_FP32, X, ldx, nullptr, n, nullptr, nullptr, d, dp32,
-                               rs, ctx->cq32.p, P<float>(ctx->ch32), k, kpad32, cs32, label, d1,
-                               d2, flags, nullptr, P<int>(ctx->brute), st, gate, ctx->num_cus));
+    KMX_HIP(ctx, launch_assign(ctx->stream, KMX_FP32, X, ldx, nullptr, n, rows, row_count, d,
+                               dp32, rs, ctx->cq32.p, P<float>(ctx->ch32), k, kpad32, cs32, label,
+                               d1, d2, flags, nullptr, P<int>(ctx->brute), st, gate,
+                               ctx->num_cus));
   }
   {
     Timed tm(ctx, T_RECHECK);
@@ -249,6 +174,12 @@ kmx_status run_assign(kmx_ctx* ctx, const float* X, int64_t n, int d, int64_t ld
                                 P<int>(ctx->brute), st, ctx->num_cus, gate));
   }
   return KMX_OK;
+}
+
+kmx_status run_assign(kmx_ctx* ctx, const float* X, int64_t n, int d, int64_t ldx, const float* C,
+                      int k, int prec, int32_t* label, float* d1, float* d2, const int* gate) {
+  KMX_TRY(run_prep_centers(ctx, C, k, d, prec));
+  return run_assign_gemm(ctx, X, n, d, ldx, C, k, prec, label, d1, d2, nullptr, nullptr, gate);
 }
 
 // sort + segmented reduction + finalize + cost sums.
@@ -283,7 +214,8 @@ kmx_status run_update(kmx_ctx* ctx, const float* X, int64_t n, int d, int64_t ld
   return KMX_OK;
 }
 
-}  // namespace
+}  // namespace host
+}  // namespace kmx
 
 extern "C" {
 
@@ -324,13 +256,16 @@ kmx_status kmx_destroy(kmx_ctx* ctx) {
   if (!ctx) return KMX_EINVAL;
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
-  kmx::Buf* bufs[] = {&ctx->xq, &ctx->xstats, &ctx->hd, &ctx->cq32, &ctx->ch32, &ctx->cstats32,
-                      &ctx->full_rows, &ctx->brute, &ctx->rowstats, &ctx->cq,     &ctx->ch,         &ctx->cstats,
-                      &ctx->lab_a, &ctx->lab_prev, &ctx->d1,     &ctx->d2,         &ctx->flags,
-                      &ctx->counters, &ctx->counts, &ctx->segsum, &ctx->base,     &ctx->chunk_base,
-                      &ctx->perm,  &ctx->partS,    &ctx->partQ,  &ctx->partW,      &ctx->W,
-                      &ctx->termC, &ctx->termMu,   &ctx->state,  &ctx->D2,         &ctx->chosen,
-                      &ctx->seed_part, &ctx->seed_ctr, &ctx->scratch_c, &ctx->hist};
+  kmx::Buf* bufs[] = {
+      &ctx->xq,        &ctx->xstats,   &ctx->hd,         &ctx->cq32,       &ctx->ch32,
+      &ctx->cstats32,  &ctx->full_rows, &ctx->brute,     &ctx->rowstats,   &ctx->cq,
+      &ctx->ch,        &ctx->cstats,   &ctx->lab_a,      &ctx->lab_prev,   &ctx->d1,
+      &ctx->d2,        &ctx->flags,    &ctx->counters,   &ctx->counts,     &ctx->segsum,
+      &ctx->base,      &ctx->chunk_base, &ctx->perm,     &ctx->partS,      &ctx->partQ,
+      &ctx->partW,     &ctx->W,        &ctx->termC,      &ctx->termMu,     &ctx->state,
+      &ctx->D2,        &ctx->chosen,   &ctx->seed_part,  &ctx->seed_ctr,   &ctx->scratch_c,
+      &ctx->hist,      &ctx->fb_rows,  &ctx->keys,       &ctx->cdist,      &ctx->nbr,
+      &ctx->nbd,       &ctx->fbh};
   for (kmx::Buf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   for (auto& r : ctx->recs) {

@@ -46,6 +46,8 @@ struct LoopState {
   unsigned long long undecided;    // rows the first GEMM pass could not decide
   double cost_at_centroids;
   double cost_last;
+  unsigned long long routed_fallback;  // rows the certificate sent to the GEMM (last assign)
+  unsigned long long routed_listed;    // certified rows that needed the short re-check
 };
 
 // Entry of the short re-check list: row index and the other candidates (the
@@ -59,7 +61,8 @@ struct FlagEntry {
 
 enum TimingClass {
   T_PREP = 0, T_ASSIGN = 1, T_RECHECK = 2, T_SORT = 3, T_REDUCE = 4,
-  T_FINAL = 5, T_SEED = 6, T_OTHER = 7, T_NCLASS = 8
+  T_FINAL = 5, T_SEED = 6, T_OTHER = 7, T_ROUTER = 8, T_CERT = 9, T_TRAIN = 10,
+  T_NCLASS = 11
 };
 
 // Grow-only device buffer.
@@ -74,6 +77,62 @@ constexpr int kReduceRows = 512;    // rows per segmented-reduction chunk
 constexpr int kSeedRows = 2048;     // rows per seeding block
 constexpr int kScanSegs = 64;       // column-scan segments
 constexpr int kMaxK = 16384;        // largest k (LDS histograms)
+
+// Candidate router (k_router.hip, k_train.hip).
+constexpr int kRouterH = 256;       // hidden units
+constexpr int kRouterHU = kRouterH / 32;  // layer-2 K units of 32
+constexpr int kRouterBN1 = 16;      // hidden units per layer-1 LDS tile
+constexpr int kRouterBN2 = 64;      // centers per layer-2 LDS tile
+constexpr int kRouterM = 16;        // proposals per point
+constexpr int kRouterMaxK = 4096;   // largest k the router supports
+constexpr int kNbrL = 32;           // sorted neighbours kept per center
+constexpr int kRouterMaxBatch = 65536;  // largest training batch
+
+// router: inference (k_router.hip)
+int router_units(int d, int dp);
+hipError_t launch_router_layout(hipStream_t s, const float* W1, const float* W2, const float* b2,
+                                int d, int k, int kpad, int r1, uint16_t* W1a, uint16_t* W2a,
+                                float* b2p);
+hipError_t launch_router_fwd(hipStream_t s, const uint16_t* Xq, int64_t dp, int64_t n, int d,
+                             const uint16_t* W1a, const float* b1, const uint16_t* W2a,
+                             const float* b2p, int kpad, uint32_t* keys, const int* gate,
+                             int num_cus);
+hipError_t launch_router_decode(hipStream_t s, const uint32_t* keys, int64_t count, int k,
+                                int kpad, int32_t* cand);
+hipError_t launch_center_table(hipStream_t s, const float* C, int k, int d, float* D, int32_t* nbr,
+                               float* nbd, const int* gate);
+hipError_t launch_router_cert(hipStream_t s, const uint16_t* Xq, int64_t dp, int64_t n, int d,
+                              const float* C, int k, const RowStats* rs, const uint32_t* keys,
+                              int kpad, const int32_t* nbr, const float* nbd, int32_t* label,
+                              FlagEntry* flags, int* fb_rows, LoopState* st, const int* gate,
+                              int num_cus);
+hipError_t launch_record_fallback(hipStream_t s, const LoopState* st, int64_t* fbh, int slot,
+                                  int all_rows, int64_t all, const int* gate);
+
+// router: training (k_train.hip)
+hipError_t launch_gather_batch(hipStream_t s, const float* X, int64_t n, int d, int64_t ldx,
+                               const int32_t* labels, uint64_t total, int64_t first, int bsz,
+                               int d8, int shuffle, uint64_t key, int k, uint16_t* Xb,
+                               int32_t* yb);
+int gemm_splits(int M, int N, int K, int num_cus, int* kchunk);
+hipError_t launch_gemm_bf16(hipStream_t s, int M, int N, int K, const uint16_t* A, int64_t lda,
+                            bool ak, const uint16_t* B, int64_t ldb, bool bk, float* Cp, int splits,
+                            int kchunk);
+hipError_t launch_ep_hidden(hipStream_t s, const float* P, int S, int M, int N, const float* bias,
+                            const uint16_t* Hb, uint16_t* out, int mode);
+hipError_t launch_softmax_ce(hipStream_t s, const float* P, int bsz, int k, int k8,
+                             const float* b2, const int32_t* yb, uint16_t* dZ, float* lossrow);
+hipError_t launch_sum_partials(hipStream_t s, const float* P, int S, int64_t zstride, int rows,
+                               int cols, int ldp, float* out);
+int colsum_segments(int rows);
+hipError_t launch_colsum(hipStream_t s, const uint16_t* Mx, int rows, int cols, int ld,
+                         float* part, float* out);
+hipError_t launch_loss_mean(hipStream_t s, const float* lossrow, int bsz, double* out);
+hipError_t launch_adam(hipStream_t s, float* p, const float* g, float* m, float* v, int rows,
+                       int cols, float lr, float beta1, float beta2, float eps, float bc1, float bc2,
+                       uint16_t* bf, int ldb);
+hipError_t launch_to_bf16_pad(hipStream_t s, const float* src, int rows, int cols, int prow,
+                              int ldb, uint16_t* dst);
 
 }  // namespace kmx
 
@@ -99,6 +158,7 @@ struct kmx_ctx {
   kmx::Buf state;
   kmx::Buf D2, chosen, seed_part, seed_ctr;
   kmx::Buf scratch_c, hist;
+  kmx::Buf fb_rows, keys, cdist, nbr, nbd, fbh;   // routed assignment
 
   // timing
   bool timing = false;
@@ -159,5 +219,51 @@ hipError_t launch_seed_round(hipStream_t s, const float* X, int64_t n, int d, in
                              const float* w, int r, uint64_t seed, double* D2,
                              uint8_t* chosen, double* part, unsigned int* ctr,
                              float* C_out, int64_t* idx_out);
+
+// router: inference (k_router.hip)
+int router_units(int d, int dp);
+hipError_t launch_router_layout(hipStream_t s, const float* W1, const float* W2, const float* b2,
+                                int d, int k, int kpad, int r1, uint16_t* W1a, uint16_t* W2a,
+                                float* b2p);
+hipError_t launch_router_fwd(hipStream_t s, const uint16_t* Xq, int64_t dp, int64_t n, int d,
+                             const uint16_t* W1a, const float* b1, const uint16_t* W2a,
+                             const float* b2p, int kpad, uint32_t* keys, const int* gate,
+                             int num_cus);
+hipError_t launch_router_decode(hipStream_t s, const uint32_t* keys, int64_t count, int k,
+                                int kpad, int32_t* cand);
+hipError_t launch_center_table(hipStream_t s, const float* C, int k, int d, float* D, int32_t* nbr,
+                               float* nbd, const int* gate);
+hipError_t launch_router_cert(hipStream_t s, const uint16_t* Xq, int64_t dp, int64_t n, int d,
+                              const float* C, int k, const RowStats* rs, const uint32_t* keys,
+                              int kpad, const int32_t* nbr, const float* nbd, int32_t* label,
+                              FlagEntry* flags, int* fb_rows, LoopState* st, const int* gate,
+                              int num_cus);
+hipError_t launch_record_fallback(hipStream_t s, const LoopState* st, int64_t* fbh, int slot,
+                                  int all_rows, int64_t all, const int* gate);
+
+// router: training (k_train.hip)
+hipError_t launch_gather_batch(hipStream_t s, const float* X, int64_t n, int d, int64_t ldx,
+                               const int32_t* labels, uint64_t total, int64_t first, int bsz,
+                               int d8, int shuffle, uint64_t key, int k, uint16_t* Xb,
+                               int32_t* yb);
+int gemm_splits(int M, int N, int K, int num_cus, int* kchunk);
+hipError_t launch_gemm_bf16(hipStream_t s, int M, int N, int K, const uint16_t* A, int64_t lda,
+                            bool ak, const uint16_t* B, int64_t ldb, bool bk, float* Cp, int splits,
+                            int kchunk);
+hipError_t launch_ep_hidden(hipStream_t s, const float* P, int S, int M, int N, const float* bias,
+                            const uint16_t* Hb, uint16_t* out, int mode);
+hipError_t launch_softmax_ce(hipStream_t s, const float* P, int bsz, int k, int k8,
+                             const float* b2, const int32_t* yb, uint16_t* dZ, float* lossrow);
+hipError_t launch_sum_partials(hipStream_t s, const float* P, int S, int64_t zstride, int rows,
+                               int cols, int ldp, float* out);
+int colsum_segments(int rows);
+hipError_t launch_colsum(hipStream_t s, const uint16_t* Mx, int rows, int cols, int ld,
+                         float* part, float* out);
+hipError_t launch_loss_mean(hipStream_t s, const float* lossrow, int bsz, double* out);
+hipError_t launch_adam(hipStream_t s, float* p, const float* g, float* m, float* v, int rows,
+                       int cols, float lr, float beta1, float beta2, float eps, float bc1, float bc2,
+                       uint16_t* bf, int ldb);
+hipError_t launch_to_bf16_pad(hipStream_t s, const float* src, int rows, int cols, int prow,
+                              int ldb, uint16_t* dst);
 
 }  // namespace kmx

@@ -20,7 +20,10 @@ LIB_PATH = os.path.join(_HERE, "libkmx.so")
 FP32, BF16 = 0, 1
 _PREC = {"fp32": FP32, "bf16": BF16, FP32: FP32, BF16: BF16}
 
-TIMING_CLASSES = ("prep", "assign", "recheck", "sort", "reduce", "finalize", "seed", "other")
+TIMING_CLASSES = ("prep", "assign", "recheck", "sort", "reduce", "finalize", "seed", "other",
+                  "router", "certificate", "train")
+ROUTER_HIDDEN = 256
+ROUTER_M = 16
 
 _lib = None
 _vp = ctypes.c_void_p
@@ -57,6 +60,16 @@ def lib():
         "kmx_timing": [_vp, ctypes.c_int, ctypes.c_int],
         "kmx_assign_stats": [_vp, _vp, _vp, _vp],
         "kmx_timing_read": [_vp, ctypes.c_int, _vp, _vp],
+        "kmx_router_create": [_vp, _i32, _i32, ctypes.c_uint64, ctypes.POINTER(_vp)],
+        "kmx_router_destroy": [_vp, _vp],
+        "kmx_router_set_params": [_vp, _vp, _vp, _vp, _vp, _vp],
+        "kmx_router_get_params": [_vp, _vp, _vp, _vp, _vp, _vp],
+        "kmx_router_loss_grad": [_vp, _vp, _vp, _i64, _i32, _i64, _vp, _vp, _vp, _vp, _vp, _vp],
+        "kmx_router_train": [_vp, _vp, _vp, _i64, _i32, _i64, _vp, _i32, _i32, _i32,
+                             ctypes.c_float, ctypes.c_uint64, _vp, _vp],
+        "kmx_router_propose": [_vp, _vp, _vp, _i64, _i32, _i64, _vp],
+        "kmx_lloyd_routed": [_vp, _vp, _vp, _i64, _i32, _i64, _vp, _vp, _i32, _i32,
+                             ctypes.c_double, ctypes.c_int, _vp, _vp, _vp, _vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -205,10 +218,129 @@ class Context:
         _check(lib().kmx_timing(self._p, int(enable), int(reset)), self._p)
 
     def timing_read(self):
-        ms = (ctypes.c_double * 8)()
-        cnt = (ctypes.c_int64 * 8)()
-        _check(lib().kmx_timing_read(self._p, 8, ms, cnt), self._p)
+        nc = len(TIMING_CLASSES)
+        ms = (ctypes.c_double * nc)()
+        cnt = (ctypes.c_int64 * nc)()
+        _check(lib().kmx_timing_read(self._p, nc, ms, cnt), self._p)
         return {name: (ms[i], cnt[i]) for i, name in enumerate(TIMING_CLASSES)}
+
+    # ---- candidate router ----------------------------------------------------
+    def router(self, d: int, k: int, init_seed: int = 0) -> "Router":
+        return Router(self, d, k, init_seed)
+
+    def lloyd_routed(self, X, C0, max_iter: int, router: Optional["Router"] = None, w=None,
+                     tol: float = -1.0, prec="bf16", labels: bool = True, inplace: bool = False):
+        """kmx_lloyd_routed; returns (C, labels, cost_hist, iters, gemm_rows)."""
+        n, d, ldx = _rows(X)
+        k = _centers(C0, d)
+        _vec(w, n)
+        C = C0 if inplace else C0.clone()
+        lab = torch.empty(n, dtype=torch.int32, device=X.device) if labels else None
+        hist = (ctypes.c_double * (max_iter + 1))()
+        rows = (ctypes.c_int64 * (max_iter + 1))()
+        iters = ctypes.c_int32(0)
+        self._sync_stream()
+        _check(lib().kmx_lloyd_routed(self._p, router._r if router is not None else None,
+                                      _ptr(X), n, d, ldx, _ptr(w), _ptr(C), k, max_iter,
+                                      float(tol), _PREC[prec], _ptr(lab), hist,
+                                      ctypes.byref(iters), rows), self._p)
+        it = int(iters.value)
+        return (C, lab, [hist[i] for i in range(it + 1)], it, [rows[i] for i in range(it + 1)])
+
+
+class Router:
+    """kmx_router: the candidate network (256 hidden units) for inputs of
+    width d and k centers, with its FP32 parameters and Adam state on the
+    device."""
+
+    def __init__(self, ctx: Context, d: int, k: int, init_seed: int = 0):
+        self.ctx = ctx
+        self.d, self.k = int(d), int(k)
+        r = _vp()
+        _check(lib().kmx_router_create(ctx._p, self.d, self.k,
+                                       ctypes.c_uint64(init_seed & (2 ** 64 - 1)),
+                                       ctypes.byref(r)), ctx._p)
+        self._r = r
+
+    def close(self):
+        if getattr(self, "_r", None) is not None and self._r.value:
+            lib().kmx_router_destroy(self.ctx._p, self._r)
+            self._r = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _dev(self):
+        return torch.device("cuda", self.ctx.device)
+
+    def get_params(self):
+        H, d, k = ROUTER_HIDDEN, self.d, self.k
+        dev = self._dev()
+        W1 = torch.empty((H, d), dtype=torch.float32, device=dev)
+        b1 = torch.empty(H, dtype=torch.float32, device=dev)
+        W2 = torch.empty((k, H), dtype=torch.float32, device=dev)
+        b2 = torch.empty(k, dtype=torch.float32, device=dev)
+        self.ctx._sync_stream()
+        _check(lib().kmx_router_get_params(self.ctx._p, self._r, _ptr(W1), _ptr(b1), _ptr(W2),
+                                           _ptr(b2)), self.ctx._p)
+        return W1, b1, W2, b2
+
+    def set_params(self, W1, b1, W2, b2):
+        H, d, k = ROUTER_HIDDEN, self.d, self.k
+        for t, shape in ((W1, (H, d)), (b1, (H,)), (W2, (k, H)), (b2, (k,))):
+            if not t.is_cuda or t.dtype != torch.float32 or tuple(t.shape) != shape \
+                    or not t.is_contiguous():
+                raise ValueError(f"expected a contiguous float32 CUDA tensor of shape {shape}")
+        self.ctx._sync_stream()
+        _check(lib().kmx_router_set_params(self.ctx._p, self._r, _ptr(W1), _ptr(b1), _ptr(W2),
+                                           _ptr(b2)), self.ctx._p)
+
+    def loss_grad(self, X, labels):
+        n, d, ldx = _rows(X)
+        _vec(labels, n, torch.int32)
+        H, k = ROUTER_HIDDEN, self.k
+        dev = self._dev()
+        g = (torch.empty((H, d), dtype=torch.float32, device=dev),
+             torch.empty(H, dtype=torch.float32, device=dev),
+             torch.empty((k, H), dtype=torch.float32, device=dev),
+             torch.empty(k, dtype=torch.float32, device=dev))
+        loss = ctypes.c_double(0.0)
+        self.ctx._sync_stream()
+        _check(lib().kmx_router_loss_grad(self.ctx._p, self._r, _ptr(X), n, d, ldx,
+                                          _ptr(labels), ctypes.byref(loss), *map(_ptr, g)),
+               self.ctx._p)
+        return float(loss.value), g
+
+    def train(self, X, labels, epochs: int = 1, batch: int = 8192, lr: float = 1e-3,
+              shuffle_seed: int = 1):
+        """labels: (n_sets, n) or (n,) int32 CUDA tensor.  Returns per-step losses."""
+        n, d, ldx = _rows(X)
+        lab = labels if labels.dim() == 2 else labels.view(1, -1)
+        if not lab.is_cuda or lab.dtype != torch.int32 or lab.shape[1] != n \
+                or not lab.is_contiguous():
+            raise ValueError("labels must be a contiguous int32 CUDA tensor of shape (sets, n)")
+        sets = lab.shape[0]
+        total = n * sets
+        steps = epochs * ((total + batch - 1) // batch)
+        hist = (ctypes.c_double * max(steps, 1))()
+        done = ctypes.c_int64(0)
+        self.ctx._sync_stream()
+        _check(lib().kmx_router_train(self.ctx._p, self._r, _ptr(X), n, d, ldx, _ptr(lab), sets,
+                                      epochs, batch, float(lr),
+                                      ctypes.c_uint64(shuffle_seed & (2 ** 64 - 1)), hist,
+                                      ctypes.byref(done)), self.ctx._p)
+        return [hist[i] for i in range(int(done.value))]
+
+    def propose(self, X):
+        n, d, ldx = _rows(X)
+        cand = torch.empty((n, ROUTER_M), dtype=torch.int32, device=X.device)
+        self.ctx._sync_stream()
+        _check(lib().kmx_router_propose(self.ctx._p, self._r, _ptr(X), n, d, ldx, _ptr(cand)),
+               self.ctx._p)
+        return cand
 
 
 _default = {}

@@ -1,0 +1,245 @@
+"""Candidate router on the GPU (through the C ABI) against the FP64 oracle.
+
+  * gradients of the mean softmax cross-entropy: relative L2 error <= 1e-2
+    and cosine >= 0.9999 against oracle.mlp on the BF16-rounded inputs and
+    weights the GPU uses (its hidden activations and logit gradients are
+    BF16 as well, which is what the tolerance covers);
+  * one Adam step: the oracle's update of the same gradient;
+  * proposals: every proposal of quarter q is among the four highest oracle
+    logits of that quarter up to the logit resolution of the keys;
+  * routed Lloyd: labels, centers and cost history identical (bitwise) to the
+    plain GEMM path, whatever the proposals; final labels equal the oracle's
+    assignment outside the top-2 margin band;
+  * what training buys: GEMM rows of a trained router against an untrained
+    one and against previous labels as the only candidate.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import kmeans as ok
+from oracle import mlp as om
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+H = 256
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1502_04265_amd import kmx
+    return kmx.Context(0)
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def bf16(a):
+    """Round to the nearest BF16 value (ties to even), returned as float64."""
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000).astype(np.uint32)
+    return r.view(np.float32).astype(np.float64)
+
+
+def _params(rng, d, k, s1=None, s2=None):
+    s1 = s1 or np.sqrt(2.0 / d)
+    s2 = s2 or np.sqrt(1.0 / H)
+    W1 = (s1 * rng.standard_normal((H, d))).astype(np.float32)
+    b1 = (0.1 * rng.standard_normal(H)).astype(np.float32)
+    W2 = (s2 * rng.standard_normal((k, H))).astype(np.float32)
+    b2 = (0.1 * rng.standard_normal(k)).astype(np.float32)
+    return W1, b1, W2, b2
+
+
+def _rel_cos(g, o):
+    g = np.asarray(g, np.float64).ravel()
+    o = np.asarray(o, np.float64).ravel()
+    rel = np.linalg.norm(g - o) / max(np.linalg.norm(o), 1e-300)
+    cos = float(g @ o / max(np.linalg.norm(g) * np.linalg.norm(o), 1e-300))
+    return rel, cos
+
+
+@pytest.mark.parametrize("n,d,k", [(512, 64, 50), (777, 100, 130), (2048, 512, 1000)])
+def test_router_gradients_match_oracle(ctx, n, d, k):
+    say(f"router grad n={n} d={d} k={k}")
+    rng = np.random.default_rng(n + d + k)
+    X, _, _ = synth.router_mixture(n, d, min(k, 64), seed=d)
+    y = rng.integers(0, k, n).astype(np.int32)
+    W1, b1, W2, b2 = _params(rng, d, k)
+    r = ctx.router(d, k)
+    r.set_params(*map(_dev, (W1, b1, W2, b2)))
+    loss, g = r.loss_grad(_dev(X), _dev(y))
+    g = [t.cpu().numpy() for t in g]
+    L, *G = om.gradients(bf16(X), y, bf16(W1), b1, bf16(W2), b2)
+    assert abs(loss - L) <= 1e-2 * abs(L), (loss, L)
+    for name, gg, oo in zip(("dW1", "db1", "dW2", "db2"), g, G):
+        rel, cos = _rel_cos(gg, oo)
+        say(f"  {name}: rel {rel:.2e} cos {cos:.6f}")
+        assert rel <= 1e-2 and cos >= 0.9999, (name, rel, cos)
+
+
+def test_router_adam_step_matches_oracle(ctx):
+    n, d, k = 600, 48, 40
+    rng = np.random.default_rng(3)
+    X, _, _ = synth.router_mixture(n, d, k, seed=3)
+    y = (np.arange(n) % k).astype(np.int32)
+    P0 = _params(rng, d, k)
+    r = ctx.router(d, k)
+    r.set_params(*map(_dev, P0))
+    _, g = r.loss_grad(_dev(X), _dev(y))
+    g = [t.cpu().numpy().astype(np.float64) for t in g]
+    lr = 1e-2
+    hist = r.train(_dev(X), _dev(y), epochs=1, batch=n, lr=lr, shuffle_seed=0)
+    assert len(hist) == 1
+    P1 = [t.cpu().numpy().astype(np.float64) for t in r.get_params()]
+    zero = [np.zeros_like(p, dtype=np.float64) for p in P0]
+    expect, _, _ = om.adam_step([p.astype(np.float64) for p in P0], g, zero, zero, 1, lr=lr)
+    for a, e in zip(P1, expect):
+        tol = 1e-6 * np.abs(e).max() + 1e-4 * lr
+        assert np.abs(a - e).max() <= tol, np.abs(a - e).max()
+
+
+@pytest.mark.parametrize("n,d,k", [(1500, 64, 130), (2048, 512, 1000), (300, 20, 16)])
+def test_router_proposals_match_oracle_logits(ctx, n, d, k):
+    say(f"router proposals n={n} d={d} k={k}")
+    rng = np.random.default_rng(7 * k + d)
+    X, _, _ = synth.router_mixture(n, d, min(k, 64), seed=k)
+    W1, b1, W2, b2 = _params(rng, d, k, s2=3.0 / np.sqrt(H))
+    r = ctx.router(d, k)
+    r.set_params(*map(_dev, (W1, b1, W2, b2)))
+    cand = r.propose(_dev(X)).cpu().numpy()
+    # oracle logits with the BF16 operands and BF16 hidden activations of the GPU
+    A = bf16(X) @ bf16(W1).T + b1
+    Hh = bf16(np.maximum(A, 0.0))
+    Z = Hh @ bf16(W2).T + b2
+    quarter = (np.arange(k) % 16) // 4
+    for q in range(4):
+        Jq = np.nonzero(quarter == q)[0]
+        got = cand[:, 4 * q:4 * q + 4]
+        assert ((got >= 0) == (np.arange(4)[None, :] < len(Jq))).all()
+        ok_rows = got >= 0
+        assert (quarter[np.where(ok_rows, got, 0)][ok_rows] == q).all()
+        m = min(4, len(Jq))
+        zq = Z[:, Jq]
+        fourth = np.sort(zq, axis=1)[:, -m]
+        tol = 1e-3 * (np.abs(Z).max(axis=1) + 1.0)
+        zg = np.take_along_axis(Z, np.where(ok_rows, got, 0), axis=1)
+        bad = ok_rows & (zg < (fourth - tol)[:, None])
+        assert not bad.any(), f"quarter {q}: {bad.sum()} proposals below the quarter's top four"
+        # no duplicates within a quarter
+        srt = np.sort(np.where(ok_rows, got, -1 - np.arange(4)[None, :]), axis=1)
+        assert (np.diff(srt, axis=1) != 0).all()
+
+
+def _plain_and_routed(ctx, X, C0, iters, router, prec="bf16"):
+    Xd, Cd = _dev(X), _dev(C0)
+    Cp, lp, hp, ip = ctx.lloyd(Xd, Cd, iters, prec=prec)
+    Cr, lr_, hr, ir, rows = ctx.lloyd_routed(Xd, Cd, iters, router=router, prec=prec)
+    return (Cp.cpu().numpy(), lp.cpu().numpy(), hp, ip), (Cr.cpu().numpy(), lr_.cpu().numpy(),
+                                                          hr, ir, rows)
+
+
+@pytest.mark.parametrize("mode", ["previous", "untrained", "trained"])
+@pytest.mark.parametrize("prec", ["bf16", "fp32"])
+def test_lloyd_routed_identical_to_plain(ctx, mode, prec):
+    n, d, k, iters = 20000, 64, 50, 6
+    say(f"lloyd routed mode={mode} prec={prec}")
+    X, _, _ = synth.router_mixture(n, d, k, seed=11)
+    Xd = _dev(X)
+    C0, _ = ctx.seed(Xd, k, rng_seed=5)
+    C0 = C0.cpu().numpy()
+    router = None
+    if mode != "previous":
+        router = ctx.router(d, k, init_seed=9)
+        if mode == "trained":
+            # labels of plain iterations 1..3 as training data
+            sets = []
+            C = _dev(C0)
+            for _ in range(3):
+                C, lab, _, _ = ctx.lloyd(Xd, C, 1, prec="bf16")
+                sets.append(lab)
+            router.train(Xd, torch.stack(sets).contiguous(), epochs=3, batch=2048, lr=3e-3)
+    (Cp, lp, hp, ip), (Cr, lr_, hr, ir, rows) = _plain_and_routed(ctx, X, C0, iters, router, prec)
+    say(f"  gemm rows per assignment: {rows}")
+    assert ip == ir == iters
+    assert (lp == lr_).all()
+    assert np.array_equal(Cp.view(np.uint32), Cr.view(np.uint32))
+    assert hp == hr
+    lab_o, d1, d2 = ok.assign(X, Cr)
+    bad = (lr_ != lab_o) & ~((d2 - d1) < 1e-6 * d2)
+    assert not bad.any()
+    if mode == "previous":
+        assert rows[0] == n
+        assert max(rows[1:]) < n
+    if mode == "untrained":
+        assert min(rows) > 0.9 * n
+
+
+def test_trained_router_gain(ctx):
+    """Training is what makes the proposals usable: the trained network sends
+    far fewer rows to the GEMM than the same network untrained, from the first
+    routed assignment on, with identical results."""
+    n, d, k = 40000, 64, 100
+    X, _, _ = synth.router_mixture(n, d, k, seed=21)
+    Xd = _dev(X)
+    C0, _ = ctx.seed(Xd, k, rng_seed=1)
+    sets = []
+    C = C0
+    for _ in range(5):
+        C, lab, _, _ = ctx.lloyd(Xd, C, 1, prec="bf16")
+        sets.append(lab)
+    C5 = C
+    untrained = ctx.router(d, k, init_seed=4)
+    trained = ctx.router(d, k, init_seed=4)
+    losses = trained.train(Xd, torch.stack(sets).contiguous(), epochs=2, batch=4096, lr=3e-3)
+    assert losses[-1] < 0.2 * losses[0]
+    cand = trained.propose(Xd).cpu().numpy()
+    lab5 = sets[-1].cpu().numpy()
+    hit = (cand == lab5[:, None]).any(axis=1).mean()
+    say(f"trained router: label among proposals for {hit:.4f} of the rows; loss "
+        f"{losses[0]:.3f} -> {losses[-1]:.3f}")
+    assert hit > 0.99
+    res = {}
+    for name, r in (("untrained", untrained), ("trained", trained), ("previous", None)):
+        Cr, lr_, hr, ir, rows = ctx.lloyd_routed(Xd, C5, 3, router=r, prec="bf16")
+        res[name] = (Cr.cpu().numpy(), lr_.cpu().numpy(), hr, rows)
+        say(f"  {name}: gemm rows {rows}")
+    for name in ("trained", "previous"):
+        assert np.array_equal(res[name][0], res["untrained"][0])
+        assert (res[name][1] == res["untrained"][1]).all()
+        assert res[name][2] == res["untrained"][2]
+    assert res["trained"][3][0] < 0.5 * res["untrained"][3][0]
+
+
+def test_lloyd_routed_full_size_previous_labels(ctx):
+    """The bench workload (n = 4M, d = 512, k = 1000): routed iterations with
+    previous labels give the plain path's labels and centers."""
+    n, d, k = 4_000_000, 512, 1000
+    say("routed full size")
+    X, _, _ = synth.router_mixture_device(n, d, k, seed=0, device="cuda:0")
+    idx = torch.arange(0, n, n // k, device="cuda:0")[:k]
+    C0 = X[idx].contiguous()
+    Cp, lp, hp, ip = ctx.lloyd(X, C0, 2, prec="bf16")
+    Cr, lr_, hr, ir, rows = ctx.lloyd_routed(X, C0, 2, router=None, prec="bf16")
+    say(f"  gemm rows {rows}")
+    assert torch.equal(lp, lr_)
+    assert torch.equal(Cp, Cr)
+    assert hp == hr
+    assert rows[0] == n and rows[1] < n
+    # sampled rows against the oracle's assignment
+    samp = torch.arange(0, n, 4099, device="cuda:0")
+    Xs = X[samp].cpu().numpy()
+    lab_o, d1, d2 = ok.assign(Xs, Cr.cpu().numpy())
+    got = lr_[samp].cpu().numpy()
+    bad = (got != lab_o) & ~((d2 - d1) < 1e-6 * d2)
+    assert not bad.any()

@@ -2,15 +2,20 @@
 
 Workload (default): n = 4,000,000 points in d = 512 from a 1,000-component
 Gaussian mixture (means N(0, 4I), sigma_c uniform in [0.5, 1.5], row i in
-component i mod 1000), k = 1000, weighted k-means++ seeding (seed 0), then
-Lloyd iterations.  One step = one Lloyd iteration (assignment with the BF16
-MFMA distance GEMM + re-check of flagged rows, FP64 segmented reduction,
-new centroids, FP64 cost).  The same iterations on the plain FP32 path are
-timed from the same start and must reach the same cost within 1e-6 relative.
+component i mod 1000), k = 1000, k-means++ seeding (seed 0), W = 5 plain FP32
+Lloyd iterations whose labels train the candidate router (1 epoch over the
+5 n pairs, batch 8192, Adam lr 1e-3), then K = 15 timed Lloyd iterations
+(iterations 6..20).  One step = one Lloyd iteration: certified router
+proposals, BF16 MFMA distance GEMM + exact re-check for the other rows,
+FP64 segmented reduction, new centroids, FP64 cost; the timed call includes
+the router's forward pass (one per call) and the final assignment.  The
+same iterations run from the same centers on the plain FP32 path, the full
+BF16 path and with previous labels as the only candidates; the results must
+agree (identical labels and centers; FP32 cost within 1e-6 relative).
 
 Prints ONE JSON line.  Data is synthetic and generated on the device before
-the timed region; the seeding, the one-off BF16 copy of X and the plain-FP32
-comparison run are timed separately and reported as extra fields.
+the timed region; seeding, the plain iterations, training and the
+comparison runs are timed separately and reported as extra fields.
 """
 from __future__ import annotations
 
@@ -84,8 +89,12 @@ def cpu_baseline(X_host_rows, C_host, n_full, seconds_target=10.0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=15,
+                    help="timed Lloyd iterations (after the warmup iterations)")
+    ap.add_argument("--warmup", type=int, default=5,
+                    help="plain FP32 iterations whose labels train the router")
+    ap.add_argument("--batch", type=int, default=8192, help="router training batch")
+    ap.add_argument("--lr", type=float, default=1e-3, help="router learning rate (Adam)")
     ap.add_argument("--workload", default="router", choices=sorted(WORKLOADS))
     ap.add_argument("--fp32-steps", type=int, default=None,
                     help="iterations of the plain FP32 comparison (default: --steps)")
@@ -147,38 +156,89 @@ def main():
     seed_ms = (time.perf_counter() - t0) * 1e3
     log(f"[bench] seeding {seed_ms:.1f} ms")
 
-    # ---- one-off BF16 copy of X + warmup iterations ----
+    # ---- warmup = plain FP32 iterations 1..W, labels recorded for training ----
     t0 = time.perf_counter()
-    Cw, _, hw, _ = ctx.lloyd(X, C0, args.warmup, prec="bf16", labels=False)
+    sets = []
+    C = C0
+    for _ in range(args.warmup):
+        C, lab, _, _ = ctx.lloyd(X, C, 1, prec="fp32", labels=True)
+        sets.append(lab)
     torch.cuda.synchronize()
+    Cw = C
     warm_ms = (time.perf_counter() - t0) * 1e3
-    log(f"[bench] warmup ({args.warmup} iters incl. BF16 copy of X) {warm_ms:.1f} ms")
+    log(f"[bench] plain FP32 iterations 1..{args.warmup}: {warm_ms:.1f} ms")
 
-    # ---- timed region: K Lloyd iterations on the BF16 path ----
+    # ---- router training on the recorded (x, label) pairs ----
+    router = ctx.router(d, k, init_seed=0)
+    train = {}
+    if sets:
+        labels = torch.stack(sets).contiguous()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        losses = router.train(X, labels, epochs=1, batch=args.batch, lr=args.lr, shuffle_seed=1)
+        torch.cuda.synchronize()
+        train_ms = (time.perf_counter() - t0) * 1e3
+        del labels
+        pairs = len(sets) * n
+        flops_step = 6.0 * (d * 256 + 256 * k)          # forward + two backward products
+        train = {"ms": train_ms, "steps": len(losses), "batch": args.batch, "lr": args.lr,
+                 "pairs": pairs, "loss_first": losses[0], "loss_last": losses[-1],
+                 "tflops": flops_step * pairs / (train_ms * 1e-3) / 1e12}
+        log(f"[bench] router training: {len(losses)} steps, {train_ms:.1f} ms, loss "
+            f"{losses[0]:.3f} -> {losses[-1]:.4f}")
+    del sets
+
+    # ---- timed region: K routed Lloyd iterations (BF16 GEMM for the rest) ----
     ctx.timing(True, True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    Cb, lab_b, hist_b, it_b = ctx.lloyd(X, Cw, args.steps, prec="bf16", labels=True)
+    Cr, lab_r, hist_r, it_r, rows_r = ctx.lloyd_routed(X, Cw, args.steps, router=router,
+                                                       prec="bf16", labels=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     kt = ctx.timing_read()
     ctx.timing(False, True)
     ms_per_step = wall * 1e3 / args.steps
     value = args.steps / wall
-    log(f"[bench] bf16: {ms_per_step:.3f} ms/iter, {value:.2f} iter/s, cost {hist_b[-1]:.9e}")
+    log(f"[bench] routed: {ms_per_step:.3f} ms/iter, {value:.2f} iter/s, cost {hist_r[-1]:.9e}, "
+        f"GEMM rows {rows_r}")
 
-    a_ms, a_cnt = kt["assign"]
-    assign_avg_ms = a_ms / max(a_cnt, 1)
+    def run_timed(label, fn):
+        ctx.timing(True, True)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        res = fn()
+        torch.cuda.synchronize()
+        w = time.perf_counter() - t
+        kk = ctx.timing_read()
+        ctx.timing(False, True)
+        log(f"[bench] {label}: {w * 1e3 / args.steps:.3f} ms/iter, cost {res[2][-1]:.9e}")
+        return res, w, kk
+
+    # ---- the same iterations without the router: full BF16 GEMM, previous labels ----
+    (Cb, lab_b, hist_b, _), wb, ktb = run_timed(
+        "full bf16", lambda: ctx.lloyd(X, Cw, args.steps, prec="bf16", labels=True))
+    (Cp, lab_p, hist_p, _, rows_p), wp, _ = run_timed(
+        "previous labels", lambda: ctx.lloyd_routed(X, Cw, args.steps, router=None, prec="bf16",
+                                                    labels=True))
+    same = bool(torch.equal(lab_r, lab_b) and torch.equal(Cr, Cb) and torch.equal(lab_p, lab_b))
+
+    # ---- rooflines ----
+    def avg(kk, cls):
+        ms, cnt = kk[cls]
+        return ms / max(cnt, 1), cnt
+
+    a_ms, _ = avg(ktb, "assign")
     flops = 2.0 * n * k * d
-    achieved = flops / (assign_avg_ms * 1e-3) / 1e12
-    r_ms, r_cnt = kt["reduce"]
-    reduce_avg_ms = r_ms / max(r_cnt, 1)
+    achieved = flops / (a_ms * 1e-3) / 1e12
+    r_ms, _ = avg(kt, "reduce")
     reduce_bytes = n * d * 4 + n * 4          # rows of X (FP32) + the permutation
-    reduce_gbs = reduce_bytes / (reduce_avg_ms * 1e-3) / 1e9
-
-    # rows needing the re-check at the final centers
-    _, _, _, nflag = ctx.assign(X, Cb, prec="bf16", want_d=False)
-    listed, via_fp32, full = ctx.assign_stats()
+    reduce_gbs = reduce_bytes / (r_ms * 1e-3) / 1e9
+    f_ms, f_cnt = avg(kt, "router")
+    router_flops = 2.0 * n * (d * 256 + 256 * k)
+    c_ms, c_cnt = avg(kt, "certificate")
+    cert_bytes = n * (2 * d + 64 + 4 + 16)     # BF16 row, 16 proposals, label, row statistics
+    gemm_rows_mean = sum(rows_r) / len(rows_r)
 
     out = {
         "metric": METRIC, "value": value, "unit": "iter/s", "n_gpus": 1,
@@ -186,26 +246,44 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "bf16", "data": "synthetic",
         "config": {"workload": wl["name"], "n": n, "d": d, "k": k,
-                   "assign": "bf16 MFMA GEMM + FP32 re-check", "reduce": "fp64"},
+                   "assign": "router proposals + certificate, bf16 MFMA GEMM + FP32 re-check "
+                             "for the other rows", "reduce": "fp64",
+                   "timed": f"Lloyd iterations {args.warmup + 1}..{args.warmup + args.steps} "
+                            f"from the centers after {args.warmup} plain FP32 iterations"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": BF16_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / BF16_PEAK_TFLOPS,
                      "traffic": measured_traffic("assign_bf16") if args.workload == "router" else None,
-                     "kernel": "assign_kernel<bf16>", "avg_ms": assign_avg_ms,
-                     "algorithmic_flops": flops},
+                     "kernel": "assign_kernel<bf16> (full assignment, same iterations)",
+                     "avg_ms": a_ms, "algorithmic_flops": flops},
         "update_roofline": {"bound": "hbm", "achieved": reduce_gbs, "peak": HBM_PEAK_GBS,
                             "unit": "GB/s", "frac": reduce_gbs / HBM_PEAK_GBS,
-                            "kernel": "reduce_kernel", "avg_ms": reduce_avg_ms},
+                            "kernel": "reduce_kernel", "avg_ms": r_ms},
+        "router_roofline": {"bound": "mfma", "achieved": router_flops / (f_ms * 1e-3) / 1e12,
+                            "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                            "frac": router_flops / (f_ms * 1e-3) / 1e12 / BF16_PEAK_TFLOPS,
+                            "kernel": "router_fwd_kernel", "avg_ms": f_ms, "launches": f_cnt},
+        "certificate_roofline": {"bound": "hbm", "achieved": cert_bytes / (c_ms * 1e-3) / 1e9,
+                                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                 "frac": cert_bytes / (c_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                 "kernel": "center table + router_cert_kernel", "avg_ms": c_ms},
         "kernel_ms_per_step": {c: (v[0] / args.steps) for c, v in kt.items() if v[1]},
+        "gemm_rows_per_assignment": rows_r,
+        "gemm_row_fraction": gemm_rows_mean / n,
+        "full_bf16": {"iter_per_s": args.steps / wb, "ms_per_step": wb * 1e3 / args.steps,
+                      "final_cost": hist_b[-1],
+                      "kernel_ms_per_step": {c: (v[0] / args.steps) for c, v in ktb.items() if v[1]}},
+        "previous_labels": {"iter_per_s": args.steps / wp, "ms_per_step": wp * 1e3 / args.steps,
+                            "gemm_rows_per_assignment": rows_p},
+        "router_vs_full_bf16": value / (args.steps / wb),
+        "identical_to_full_bf16": same,
+        "router_training": train,
         "seed_ms": seed_ms, "warmup_ms": warm_ms,
-        "recheck_rows_final": {"listed": listed, "via_fp32_gemm": via_fp32, "all_centers": full,
-                               "n": n},
-        "final_cost": hist_b[-1],
+        "final_cost": hist_r[-1],
     }
 
     # ---- plain FP32 path from the same start ----
     if not args.no_fp32:
         ks = args.fp32_steps or args.steps
-        ctx.lloyd(X, Cw, 1, prec="fp32", labels=False)     # FP32 row statistics
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         Cf, lab_f, hist_f, it_f = ctx.lloyd(X, Cw, ks, prec="fp32", labels=False)
@@ -216,7 +294,7 @@ def main():
                             "final_cost": hist_f[-1]}
         out["speedup_vs_fp32"] = value / (ks / wf)
         if ks == args.steps:
-            rel = abs(hist_f[-1] - hist_b[-1]) / hist_f[-1]
+            rel = abs(hist_f[-1] - hist_r[-1]) / hist_f[-1]
             out["equal_cost_rel_diff"] = rel
             out["equal_cost"] = bool(rel <= 1e-6)
 
@@ -224,7 +302,7 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         rows = X[:20000].cpu().numpy()
-        out["cpu_baseline"] = cpu_baseline(rows, Cb.cpu().numpy(), n)
+        out["cpu_baseline"] = cpu_baseline(rows, Cr.cpu().numpy(), n)
 
     print(json.dumps(out), flush=True)
 

@@ -54,8 +54,10 @@ typedef enum {
  * bound of the chosen precision are re-checked with compensated FP32
  * direct differences.  Centroid and cost accumulation is always FP64. */
 typedef enum {
-  KMX_FP32 = 0,   /* FP32 MFMA, FP32 accumulate                              */
-  KMX_BF16 = 1    /* BF16 inputs (round to nearest even), FP32 accumulate    */
+  KMX_FP32 = 0,     /* FP32 MFMA, FP32 accumulate                            */
+  KMX_BF16 = 1,     /* BF16 inputs (round to nearest even), FP32 accumulate  */
+  KMX_FP8E4M3 = 2   /* FP8 E4M3 inputs with a power-of-two scale per row of X
+                       and one for all centers, FP32 accumulate; d <= 1024  */
 } kmx_prec;
 
 /* Context: binds a device and a HIP stream (hip_stream == NULL: the null

@@ -155,9 +155,201 @@ __global__ void prep_centers_b_kernel(int k, int kpad, int dp, uint16_t* __restr
   row[2] = h3;
 }
 
+// ---------------------------------------------------------------------------
+// FP8 E4M3 (OCP: bias 7, largest finite 448, subnormals m 2^-9, no
+// infinities).  Round to nearest even; magnitudes above 448 saturate.  The
+// error bounds use the residuals of the stored values, so they hold for any
+// rounding; round-to-nearest only keeps them small.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ unsigned f32_to_e4m3_rne(float v) {
+  const unsigned u = __float_as_uint(v);
+  const unsigned sgn = (u >> 24) & 0x80u;
+  const unsigned a = u & 0x7FFFFFFFu;
+  unsigned r;
+  if (a >= 0x43E00000u) {              // >= 448, inf, NaN
+    r = 0x7Eu;
+  } else if (a < 0x3C800000u) {        // below 2^-6: multiples of 2^-9 (8 -> 2^-6 = 0x08)
+    r = (unsigned)__builtin_rintf(__uint_as_float(a) * 512.0f);
+  } else {                             // keep three mantissa bits, ties to even
+    const unsigned rr = a + 0x7FFFFu + ((a >> 20) & 1u);
+    r = (((rr >> 23) - 120u) << 3) | ((rr >> 20) & 7u);
+    if (r > 0x7Eu) r = 0x7Eu;
+  }
+  return sgn | r;
+}
+
+__device__ __forceinline__ float e4m3_to_f32(unsigned b) {
+  const unsigned e = (b >> 3) & 15u, m = b & 7u;
+  const float v = e ? __uint_as_float(((e + 120u) << 23) | (m << 20)) : (float)m * 0.001953125f;
+  return (b & 0x80u) ? -v : v;
+}
+
+// Exponent e of the power-of-two scale 2^e with amax / 2^e <= 448 (smallest
+// such e, clamped to the E8M0 range).
+__device__ __forceinline__ int e4m3_scale_exp(float amax) {
+  if (!(amax > 0.0f)) return 0;
+  int e;
+  const float f = frexpf(amax / 448.0f, &e);   // amax/448 = f 2^e, f in [0.5, 1)
+  if (f == 0.5f) e -= 1;
+  while (ldexpf(448.0f, e) < amax) ++e;        // guard against the rounding of amax / 448
+  return max(-127, min(127, e));
+}
+
+// One wave per row: FP8 row of dp bytes (q in [0, d), zeros after), its E8M0
+// scale byte sx8[row] = e + 127, and RowStats with nxq = ||2^e q|| and
+// rx = ||x - 2^e q||.  xq_max receives max_i nxq_i.
+__global__ __launch_bounds__(256) void prep_rows_f8_kernel(const float* __restrict__ X, int64_t n,
+                                                           int d, int64_t ldx, int dp,
+                                                           uint8_t* __restrict__ Xq8,
+                                                           uint8_t* __restrict__ sx8,
+                                                           RowStats* __restrict__ st,
+                                                           unsigned* __restrict__ xq_max) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wave0 = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  unsigned local_max = 0u;
+  for (int64_t row = wave0; row < n; row += nwaves) {
+    const float* x = X + row * ldx;
+    float amax = 0.0f;
+    for (int c = lane; c < d; c += 64) amax = fmaxf(amax, fabsf(x[c]));
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) amax = fmaxf(amax, __shfl_xor(amax, m, 64));
+    const int e = e4m3_scale_exp(amax);
+    const float inv = ldexpf(1.0f, -e);
+    const double sc = ldexp(1.0, e);
+    double s2 = 0.0, q2 = 0.0, r2 = 0.0;
+    for (int c0 = 4 * lane; c0 < dp; c0 += 256) {
+      unsigned word = 0u;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int c = c0 + t;
+        const float v = (c < d) ? x[c] : 0.0f;
+        const unsigned q = f32_to_e4m3_rne(v * inv);
+        const double back = (double)e4m3_to_f32(q) * sc;
+        s2 += (double)v * v;
+        q2 += back * back;
+        r2 += ((double)v - back) * ((double)v - back);
+        word |= q << (8 * t);
+      }
+      *(unsigned*)(Xq8 + row * dp + c0) = word;
+    }
+    s2 = wave_sum_f64(s2);
+    q2 = wave_sum_f64(q2);
+    r2 = wave_sum_f64(r2);
+    if (lane == 0) {
+      RowStats r;
+      r.xn2 = (float)s2;
+      r.nx = f64_to_f32_up(sqrt(s2));
+      r.nxq = f64_to_f32_up(sqrt(q2));
+      r.rx = f64_to_f32_up(sqrt(r2));
+      st[row] = r;
+      sx8[row] = (uint8_t)(e + 127);
+      local_max = max(local_max, __float_as_uint(r.nxq));
+    }
+  }
+  if (lane == 0 && xq_max) atomicMax(xq_max, local_max);
+}
+
+hipError_t launch_prep_rows_f8(hipStream_t s, const float* X, int64_t n, int d, int64_t ldx,
+                               int dp, uint8_t* Xq8, uint8_t* sx8, RowStats* st,
+                               unsigned* xq_max, int num_cus) {
+  if (dp % 256 != 0 && dp % 128 != 0) return hipErrorInvalidValue;
+  int64_t blocks = (n + 3) / 4;
+  const int64_t cap = (int64_t)num_cus * 16;
+  if (blocks > cap) blocks = cap;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(prep_rows_f8_kernel, dim3((unsigned)blocks), dim3(256), 0, s, X, n, d, ldx,
+                     dp, Xq8, sx8, st, xq_max);
+  return hipGetLastError();
+}
+
+// Centers, FP8: one scale for all centers.  Pass 1: max |c_ji|.  Pass 2 (one
+// wave per padded center): the FP8 row (zeros for padding), hd = ||c||^2 / 2
+// in FP64 and the norm maxima.  Pass 3: the offset O and the accumulator
+// start values ch[j] = O - hd[j] (0 for padding: score 0, never selected).
+__global__ void center_amax_kernel(const float* __restrict__ C, int64_t total,
+                                   CenterStats* __restrict__ cs) {
+  float m = 0.0f;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x)
+    m = fmaxf(m, fabsf(C[i]));
+#pragma unroll
+  for (int s2 = 32; s2 >= 1; s2 >>= 1) m = fmaxf(m, __shfl_xor(m, s2, 64));
+  if ((threadIdx.x & 63) == 0) atomicMax(&cs->c_amax, __float_as_uint(m));
+}
+
+__global__ __launch_bounds__(64) void prep_centers_f8_kernel(const float* __restrict__ C, int k,
+                                                             int d, int dp,
+                                                             uint8_t* __restrict__ Cq8,
+                                                             double* __restrict__ hd,
+                                                             CenterStats* __restrict__ cs) {
+  const int j = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int e = e4m3_scale_exp(__uint_as_float(cs->c_amax));
+  const float inv = ldexpf(1.0f, -e);
+  const double sc = ldexp(1.0, e);
+  double s2 = 0.0, q2 = 0.0, r2 = 0.0;
+  for (int c0 = 4 * lane; c0 < dp; c0 += 256) {
+    unsigned word = 0u;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int c = c0 + t;
+      const float v = (j < k && c < d) ? C[(int64_t)j * d + c] : 0.0f;
+      const unsigned q = f32_to_e4m3_rne(v * inv);
+      const double back = (double)e4m3_to_f32(q) * sc;
+      s2 += (double)v * v;
+      q2 += back * back;
+      r2 += ((double)v - back) * ((double)v - back);
+      word |= q << (8 * t);
+    }
+    *(unsigned*)(Cq8 + (int64_t)j * dp + c0) = word;
+  }
+  s2 = wave_sum_f64(s2);
+  q2 = wave_sum_f64(q2);
+  r2 = wave_sum_f64(r2);
+  if (lane == 0) {
+    hd[j] = 0.5 * s2;
+    if (j == 0) cs->c_exp = e + 127;
+    if (j < k) {
+      atomicMax(&cs->cq_max, __float_as_uint(f64_to_f32_up(sqrt(q2))));
+      atomicMax(&cs->rc_max, __float_as_uint(f64_to_f32_up(sqrt(r2))));
+      atomicMax(&cs->cn_max, __float_as_uint(f64_to_f32_up(sqrt(s2))));
+    }
+  }
+}
+
+__global__ void prep_centers_f8_b_kernel(int k, int kpad, const double* __restrict__ hd,
+                                         CenterStats* __restrict__ cs,
+                                         const unsigned* __restrict__ xq_max,
+                                         float* __restrict__ ch) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const float xm = __uint_as_float(*xq_max);
+  const float cqm = __uint_as_float(cs->cq_max);
+  const float cnm = __uint_as_float(cs->cn_max);
+  const float O = (xm * cqm + 0.5f * cnm * cnm) * 1.001f + 1.0f;
+  if (j == 0) cs->O = O;
+  if (j >= kpad) return;
+  ch[j] = (j < k) ? (float)((double)O - hd[j]) : 0.0f;
+}
+
 hipError_t launch_prep_centers(hipStream_t s, const float* C, int k, int d, int kpad, int dp,
                                int prec, void* Cq, float* ch, double* hd, CenterStats* cs,
                                const unsigned* xq_max) {
+  if (prec == 2) {
+    const int64_t total = (int64_t)k * d;
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(center_amax_kernel, dim3((unsigned)blocks), dim3(256), 0, s, C, total, cs);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(prep_centers_f8_kernel, dim3(kpad), dim3(64), 0, s, C, k, d, dp,
+                       (uint8_t*)Cq, hd, cs);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(prep_centers_f8_b_kernel, dim3((kpad + 255) / 256), dim3(256), 0, s, k,
+                       kpad, hd, cs, xq_max, ch);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(prep_centers_kernel, dim3(kpad), dim3(64), 0, s, C, k, d, dp, prec, Cq, ch,
                      hd, cs);
   hipError_t e = hipGetLastError();
@@ -200,8 +392,8 @@ hipError_t launch_fill_u8(hipStream_t s, uint8_t* p, int64_t n, uint8_t v) {
 __global__ void reset_small_kernel(CenterStats* cs, CenterStats* cs2, LoopState* st,
                                    int reset_iter) {
   if (threadIdx.x == 0) {
-    if (cs) { cs->cq_max = 0; cs->rc_max = 0; cs->cn_max = 0; cs->O = 0.0f; }
-    if (cs2) { cs2->cq_max = 0; cs2->rc_max = 0; cs2->cn_max = 0; cs2->O = 0.0f; }
+    if (cs) { cs->cq_max = 0; cs->rc_max = 0; cs->cn_max = 0; cs->O = 0.0f; cs->c_amax = 0; cs->c_exp = 127; }
+    if (cs2) { cs2->cq_max = 0; cs2->rc_max = 0; cs2->cn_max = 0; cs2->O = 0.0f; cs2->c_amax = 0; cs2->c_exp = 127; }
     if (st) {
       st->flagged = 0;
       st->full_count = 0;

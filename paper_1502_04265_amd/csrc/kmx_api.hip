@@ -31,7 +31,8 @@ kmx_status check_problem(kmx_ctx* ctx, const float* X, int64_t n, int32_t d, int
 }
 
 kmx_status check_prec(kmx_ctx* ctx, int prec, int d) {
-  if (prec != KMX_FP32 && prec != KMX_BF16) return fail(ctx, KMX_EINVAL, "unknown precision");
+  if (prec != KMX_FP32 && prec != KMX_BF16 && prec != KMX_FP8E4M3)
+    return fail(ctx, KMX_EINVAL, "unknown precision");
   const int dmax = (prec == KMX_BF16) ? 1053 : 1024;
   if (d > dmax || d > 1024)
     return fail(ctx, KMX_EUNSUPPORTED,
@@ -42,6 +43,30 @@ kmx_status check_prec(kmx_ctx* ctx, int prec, int d) {
 // Row statistics and (BF16) the quantized copy of X, cached per dataset.  The
 // BF16 preparation also serves the FP32 path (which only reads ||x||).
 kmx_status ensure_prep(kmx_ctx* ctx, const float* X, int64_t n, int d, int64_t ldx, int prec) {
+  if (prec == KMX_FP8E4M3) {
+    if (ctx->cache8_valid && ctx->cache8_X == X && ctx->cache8_n == n && ctx->cache8_d == d &&
+        ctx->cache8_ldx == ldx)
+      return KMX_OK;
+    ctx->cache8_valid = false;
+    const int dp8 = assign_dpad(KMX_FP8E4M3, d);
+    KMX_TRY(grow(ctx, ctx->rowstats8, (size_t)n * sizeof(RowStats)));
+    KMX_TRY(grow(ctx, ctx->xstats8, 16));
+    KMX_TRY(grow(ctx, ctx->xq8, (size_t)n * dp8));
+    KMX_TRY(grow(ctx, ctx->sx8, (size_t)n));
+    {
+      Timed tm(ctx, T_PREP);
+      KMX_HIP(ctx, launch_fill_i32(ctx->stream, P<int32_t>(ctx->xstats8), 4, 0));
+      KMX_HIP(ctx, launch_prep_rows_f8(ctx->stream, X, n, d, ldx, dp8, P<uint8_t>(ctx->xq8),
+                                       P<uint8_t>(ctx->sx8), P<RowStats>(ctx->rowstats8),
+                                       P<unsigned>(ctx->xstats8), ctx->num_cus));
+    }
+    ctx->cache8_X = X;
+    ctx->cache8_n = n;
+    ctx->cache8_d = d;
+    ctx->cache8_ldx = ldx;
+    ctx->cache8_valid = true;
+    return KMX_OK;
+  }
   if (ctx->cache_valid && ctx->cache_X == X && ctx->cache_n == n && ctx->cache_d == d &&
       ctx->cache_ldx == ldx && (ctx->cache_prec == prec || ctx->cache_prec == KMX_BF16))
     return KMX_OK;
@@ -125,6 +150,17 @@ kmx_status run_prep_centers(kmx_ctx* ctx, const float* C, int k, int d, int prec
     KMX_HIP(ctx, launch_prep_centers(ctx->stream, C, k, d, kpad, dp, KMX_BF16, ctx->cq.p, nullptr,
                                      P<double>(ctx->hd), cs, P<unsigned>(ctx->xstats)));
   }
+  if (prec == KMX_FP8E4M3) {
+    const int dp = assign_dpad(KMX_FP8E4M3, d);
+    const int bn = assign_tile_n(KMX_FP8E4M3, d);
+    const int kpad = (k + bn - 1) / bn * bn;
+    KMX_TRY(grow(ctx, ctx->cq8, (size_t)kpad * dp));
+    KMX_TRY(grow(ctx, ctx->ch8, (size_t)kpad * sizeof(float)));
+    KMX_TRY(grow(ctx, ctx->hd8, (size_t)kpad * sizeof(double)));
+    KMX_HIP(ctx, launch_prep_centers(ctx->stream, C, k, d, kpad, dp, KMX_FP8E4M3, ctx->cq8.p,
+                                     P<float>(ctx->ch8), P<double>(ctx->hd8), cs,
+                                     P<unsigned>(ctx->xstats8)));
+  }
   return KMX_OK;
 }
 
@@ -143,27 +179,32 @@ kmx_status run_assign_gemm(kmx_ctx* ctx, const float* X, int64_t n, int d, int64
   const int kpad32 = (k + bn32 - 1) / bn32 * bn32;
   const RowStats* rs = P<RowStats>(ctx->rowstats);
   FlagEntry* flags = P<FlagEntry>(ctx->flags);
-  if (prec == KMX_BF16) {
-    const int dp = assign_dpad(KMX_BF16, d);
-    const int bn = assign_tile_n(KMX_BF16, d);
+  if (prec == KMX_BF16 || prec == KMX_FP8E4M3) {
+    const bool f8 = prec == KMX_FP8E4M3;
+    const int dp = assign_dpad(prec, d);
+    const int bn = assign_tile_n(prec, d);
     const int kpad = (k + bn - 1) / bn * bn;
+    if (f8) rs = P<RowStats>(ctx->rowstats8);   // its xn2 and nx also serve the FP32 pass
     {
       Timed tm(ctx, T_ASSIGN);
-      KMX_HIP(ctx, launch_assign(ctx->stream, KMX_BF16, X, ldx, P<uint16_t>(ctx->xq), n, rows,
-                                 row_count, d, dp, rs, ctx->cq.p, nullptr, k, kpad, cs, label, d1,
-                                 d2, flags, P<int>(ctx->full_rows), P<int>(ctx->brute), st, gate,
+      KMX_HIP(ctx, launch_assign(ctx->stream, prec, X, ldx,
+                                 f8 ? ctx->xq8.p : ctx->xq.p, f8 ? P<uint8_t>(ctx->sx8) : nullptr,
+                                 n, rows, row_count, d, dp, rs, f8 ? ctx->cq8.p : ctx->cq.p,
+                                 f8 ? P<float>(ctx->ch8) : nullptr, k, kpad, cs, label, d1, d2,
+                                 flags, P<int>(ctx->full_rows), P<int>(ctx->brute), st, gate,
                                  ctx->num_cus));
     }
     {
       Timed tm(ctx, T_RECHECK);
-      KMX_HIP(ctx, launch_assign(ctx->stream, KMX_FP32, X, ldx, nullptr, n, P<int>(ctx->full_rows),
+      KMX_HIP(ctx, launch_assign(ctx->stream, KMX_FP32, X, ldx, nullptr, nullptr, n,
+                                 P<int>(ctx->full_rows),
                                  &st->full_count, d, dp32, rs, ctx->cq32.p, P<float>(ctx->ch32), k,
                                  kpad32, cs32, label, d1, d2, flags, nullptr, P<int>(ctx->brute),
                                  st, gate, ctx->num_cus));
     }
   } else {
     Timed tm(ctx, T_ASSIGN);
-    KMX_HIP(ctx, launch_assign(ctx->stream, KMX_FP32, X, ldx, nullptr, n, rows, row_count, d,
+    KMX_HIP(ctx, launch_assign(ctx->stream, KMX_FP32, X, ldx, nullptr, nullptr, n, rows, row_count, d,
                                dp32, rs, ctx->cq32.p, P<float>(ctx->ch32), k, kpad32, cs32, label,
                                d1, d2, flags, nullptr, P<int>(ctx->brute), st, gate,
                                ctx->num_cus));
@@ -265,7 +306,8 @@ kmx_status kmx_destroy(kmx_ctx* ctx) {
       &ctx->partW,     &ctx->W,        &ctx->termC,      &ctx->termMu,     &ctx->state,
       &ctx->D2,        &ctx->chosen,   &ctx->seed_part,  &ctx->seed_ctr,   &ctx->scratch_c,
       &ctx->hist,      &ctx->fb_rows,  &ctx->keys,       &ctx->cdist,      &ctx->nbr,
-      &ctx->nbd,       &ctx->fbh};
+      &ctx->nbd,       &ctx->fbh,      &ctx->xq8,        &ctx->sx8,        &ctx->rowstats8,
+      &ctx->xstats8,   &ctx->cq8,      &ctx->ch8,        &ctx->hd8};
   for (kmx::Buf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   for (auto& r : ctx->recs) {
@@ -286,6 +328,7 @@ kmx_status kmx_set_stream(kmx_ctx* ctx, void* hip_stream) {
 kmx_status kmx_invalidate(kmx_ctx* ctx, const float* X) {
   if (!ctx) return KMX_EINVAL;
   if (X == nullptr || ctx->cache_X == X) ctx->cache_valid = false;
+  if (X == nullptr || ctx->cache8_X == X) ctx->cache8_valid = false;
   return KMX_OK;
 }
 

@@ -26,10 +26,14 @@ struct RowStats {
 //   cq_max : max_j ||c~_j||    (rounded up)
 //   rc_max : max_j ||c_j - c~_j|| (rounded up)
 //   cn_max : max_j ||c_j||     (rounded up)
-//   O      : score offset of the BF16 GEMM (see k_assign.hip)
+//   O      : score offset of the BF16 / FP8 GEMM (see k_assign.hip)
+//   c_amax : max_j max_i |c_ji| (FP8 only)
+//   c_exp  : E8M0 exponent byte of the FP8 center scale (FP8 only)
 struct CenterStats {
   unsigned int cq_max, rc_max, cn_max;
   float O;
+  unsigned int c_amax;
+  int c_exp;
 };
 
 // Device-side Lloyd state, one instance per context.
@@ -149,6 +153,12 @@ struct kmx_ctx {
   bool cache_valid = false;
 
   kmx::Buf xq, rowstats, xstats;
+  // FP8 copy of X (rows of dp bytes), E8M0 row scales and its row statistics
+  const float* cache8_X = nullptr;
+  int64_t cache8_n = 0, cache8_ldx = 0;
+  int cache8_d = 0;
+  bool cache8_valid = false;
+  kmx::Buf xq8, sx8, rowstats8, xstats8, cq8, ch8, hd8;
   kmx::Buf cq, ch, hd, cstats, cq32, ch32, cstats32, full_rows, brute;
   kmx::Buf lab_a, lab_prev, d1, d2;
   kmx::Buf flags, counters;
@@ -178,6 +188,9 @@ hipError_t launch_prep_rows(hipStream_t s, const float* X, int64_t n, int d, int
 hipError_t launch_prep_centers(hipStream_t s, const float* C, int k, int d, int kpad, int dp,
                                int prec, void* Cq, float* ch, double* hd, CenterStats* cs,
                                const unsigned* xq_max);
+hipError_t launch_prep_rows_f8(hipStream_t s, const float* X, int64_t n, int d, int64_t ldx,
+                               int dp, uint8_t* Xq8, uint8_t* sx8, RowStats* st,
+                               unsigned* xq_max, int num_cus);
 hipError_t launch_fill_i32(hipStream_t s, int32_t* p, int64_t n, int32_t v);
 hipError_t launch_fill_u8(hipStream_t s, uint8_t* p, int64_t n, uint8_t v);
 hipError_t launch_reset_small(hipStream_t s, CenterStats* cs, CenterStats* cs2, LoopState* st,
@@ -187,7 +200,7 @@ hipError_t launch_reset_small(hipStream_t s, CenterStats* cs, CenterStats* cs2, 
 int assign_tile_n(int prec, int d);   // centers per tile (kpad granularity)
 int assign_dpad(int prec, int d);     // padded row length of the GEMM operands
 hipError_t launch_assign(hipStream_t s, int prec, const float* X, int64_t ldx,
-                         const uint16_t* Xq, int64_t n, const int* rows,
+                         const void* Xq, const uint8_t* sx8, int64_t n, const int* rows,
                          const unsigned long long* row_count, int d, int dp,
                          const RowStats* rs, const void* Cq, const float* ch,
                          int k, int kpad, const CenterStats* cs, int32_t* label,

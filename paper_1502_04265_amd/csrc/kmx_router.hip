@@ -432,7 +432,8 @@ kmx_status kmx_lloyd_routed(kmx_ctx* ctx, kmx_router* r, const float* X, int64_t
   if (max_iter < 0) return fail(ctx, KMX_EINVAL, "max_iter must be >= 0");
   KMX_TRY(set_device(ctx));
   KMX_TRY(ensure_common(ctx, n, d, k));
-  KMX_TRY(ensure_prep(ctx, X, n, d, ldx, KMX_BF16));
+  KMX_TRY(ensure_prep(ctx, X, n, d, ldx, KMX_BF16));   // the certificate reads the BF16 rows
+  if (prec == KMX_FP8E4M3) KMX_TRY(ensure_prep(ctx, X, n, d, ldx, KMX_FP8E4M3));
   KMX_TRY(grow(ctx, ctx->lab_prev, (size_t)n * sizeof(int32_t)));
   KMX_TRY(grow(ctx, ctx->hist, (size_t)(max_iter + 1) * sizeof(double)));
   KMX_TRY(grow(ctx, ctx->fb_rows, (size_t)n * sizeof(int)));

@@ -17,8 +17,8 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libkmx.so")
 
-FP32, BF16 = 0, 1
-_PREC = {"fp32": FP32, "bf16": BF16, FP32: FP32, BF16: BF16}
+FP32, BF16, FP8 = 0, 1, 2
+_PREC = {"fp32": FP32, "bf16": BF16, "fp8": FP8, FP32: FP32, BF16: BF16, FP8: FP8}
 
 TIMING_CLASSES = ("prep", "assign", "recheck", "sort", "reduce", "finalize", "seed", "other",
                   "router", "certificate", "train")

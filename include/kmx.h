@@ -141,6 +141,17 @@ kmx_status kmx_lloyd(kmx_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t
                      double tol, kmx_prec prec, int32_t* label_out,
                      double* cost_hist, int32_t* iters_done);
 
+/* Projection onto a subspace (Sec. 3, dimension reduction of each piece: a
+ * row's coordinates in the span of the top right singular vectors, which
+ * keeps squared distances within that span):
+ *     Y[r][j] = sum_i X[r][i] V[i][j],  r < rows, j < d_out,
+ * FP32 MFMA with FP32 accumulation.  X rows x d_in (leading dimension ldx),
+ * V d_in x d_out row-major, Y rows x d_out (leading dimension ldy), all
+ * device.  d_out a multiple of 16 in [16, 128]; Y 16-byte aligned with
+ * ldy % 4 == 0.  Stream-ordered; call once per chunk of rows. */
+kmx_status kmx_project(kmx_ctx* ctx, const float* X, int64_t rows, int32_t d_in, int64_t ldx,
+                       const float* V, int32_t d_out, float* Y, int64_t ldy);
+
 /* Re-check counts of the most recent assignment on ctx (kmx_assign, kmx_cost,
  * or the final assignment of kmx_lloyd); host outputs, each nullable:
  *   listed   rows on the exact re-check list (pairs and full rows),
@@ -155,8 +166,9 @@ kmx_status kmx_assign_stats(kmx_ctx* ctx, int64_t* listed, int64_t* fp32, int64_
  * milliseconds and launch counts per class since the last reset:
  *   class 0 prep (row statistics, quantization), 1 assign GEMM, 2 re-check,
  *   3 label sort, 4 segmented reduction, 5 finalize, 6 seeding, 7 other,
- *   8 router forward pass, 9 center table + certificate, 10 router training.
- * ms_out and count_out are host arrays of length n_classes (<= 11).
+ *   8 router forward pass, 9 center table + certificate, 10 router training,
+ *   11 projection.
+ * ms_out and count_out are host arrays of length n_classes (<= 12).
  * Reading synchronizes.  enable = 0 stops recording; reset clears sums. */
 kmx_status kmx_timing(kmx_ctx* ctx, int enable, int reset);
 kmx_status kmx_timing_read(kmx_ctx* ctx, int n_classes, double* ms_out, int64_t* count_out);

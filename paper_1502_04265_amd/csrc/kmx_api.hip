@@ -467,6 +467,22 @@ kmx_status kmx_lloyd(kmx_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t
   return KMX_OK;
 }
 
+kmx_status kmx_project(kmx_ctx* ctx, const float* X, int64_t rows, int32_t d_in, int64_t ldx,
+                       const float* V, int32_t d_out, float* Y, int64_t ldy) {
+  if (!ctx) return KMX_EINVAL;
+  ctx->err.clear();
+  if (!X || !V || !Y) return fail(ctx, KMX_EINVAL, "NULL X, V or Y");
+  if (rows < 1 || d_in < 1 || ldx < d_in) return fail(ctx, KMX_EINVAL, "bad rows, d_in or ldx");
+  if (d_out < 16 || d_out > 128 || d_out % 16 != 0)
+    return fail(ctx, KMX_EUNSUPPORTED, "d_out must be a multiple of 16 in [16, 128]");
+  if (ldy < d_out || ldy % 4 != 0 || (((uintptr_t)Y) & 15))
+    return fail(ctx, KMX_EINVAL, "Y needs 16-byte alignment and ldy >= d_out, ldy % 4 == 0");
+  KMX_TRY(set_device(ctx));
+  Timed tm(ctx, T_PROJECT);
+  KMX_HIP(ctx, launch_project(ctx->stream, X, rows, d_in, ldx, V, d_out, Y, ldy, ctx->num_cus));
+  return KMX_OK;
+}
+
 kmx_status kmx_assign_stats(kmx_ctx* ctx, int64_t* listed, int64_t* fp32, int64_t* full) {
   if (!ctx) return KMX_EINVAL;
   ctx->err.clear();

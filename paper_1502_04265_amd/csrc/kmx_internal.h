@@ -66,7 +66,7 @@ struct FlagEntry {
 enum TimingClass {
   T_PREP = 0, T_ASSIGN = 1, T_RECHECK = 2, T_SORT = 3, T_REDUCE = 4,
   T_FINAL = 5, T_SEED = 6, T_OTHER = 7, T_ROUTER = 8, T_CERT = 9, T_TRAIN = 10,
-  T_NCLASS = 11
+  T_PROJECT = 11, T_NCLASS = 12
 };
 
 // Grow-only device buffer.
@@ -91,6 +91,10 @@ constexpr int kRouterM = 16;        // proposals per point
 constexpr int kRouterMaxK = 4096;   // largest k the router supports
 constexpr int kNbrL = 32;           // sorted neighbours kept per center
 constexpr int kRouterMaxBatch = 65536;  // largest training batch
+
+// projection (k_project.hip)
+hipError_t launch_project(hipStream_t s, const float* X, int64_t rows, int d_in, int64_t ldx,
+                          const float* V, int d_out, float* Y, int64_t ldy, int num_cus);
 
 // router: inference (k_router.hip)
 int router_units(int d, int dp);
@@ -232,6 +236,10 @@ hipError_t launch_seed_round(hipStream_t s, const float* X, int64_t n, int d, in
                              const float* w, int r, uint64_t seed, double* D2,
                              uint8_t* chosen, double* part, unsigned int* ctr,
                              float* C_out, int64_t* idx_out);
+
+// projection (k_project.hip)
+hipError_t launch_project(hipStream_t s, const float* X, int64_t rows, int d_in, int64_t ldx,
+                          const float* V, int d_out, float* Y, int64_t ldy, int num_cus);
 
 // router: inference (k_router.hip)
 int router_units(int d, int dp);

@@ -21,7 +21,7 @@ FP32, BF16, FP8 = 0, 1, 2
 _PREC = {"fp32": FP32, "bf16": BF16, "fp8": FP8, FP32: FP32, BF16: BF16, FP8: FP8}
 
 TIMING_CLASSES = ("prep", "assign", "recheck", "sort", "reduce", "finalize", "seed", "other",
-                  "router", "certificate", "train")
+                  "router", "certificate", "train", "project")
 ROUTER_HIDDEN = 256
 ROUTER_M = 16
 
@@ -60,6 +60,7 @@ def lib():
         "kmx_timing": [_vp, ctypes.c_int, ctypes.c_int],
         "kmx_assign_stats": [_vp, _vp, _vp, _vp],
         "kmx_timing_read": [_vp, ctypes.c_int, _vp, _vp],
+        "kmx_project": [_vp, _vp, _i64, _i32, _i64, _vp, _i32, _vp, _i64],
         "kmx_router_create": [_vp, _i32, _i32, ctypes.c_uint64, ctypes.POINTER(_vp)],
         "kmx_router_destroy": [_vp, _vp],
         "kmx_router_set_params": [_vp, _vp, _vp, _vp, _vp, _vp],
@@ -223,6 +224,19 @@ class Context:
         cnt = (ctypes.c_int64 * nc)()
         _check(lib().kmx_timing_read(self._p, nc, ms, cnt), self._p)
         return {name: (ms[i], cnt[i]) for i, name in enumerate(TIMING_CLASSES)}
+
+    def project(self, X, V, out=None):
+        """Y = X V for a chunk of rows (kmx_project); V is d_in x d_out float32."""
+        rows, d_in, ldx = _rows(X)
+        if not V.is_cuda or V.dtype != torch.float32 or V.dim() != 2 or V.shape[0] != d_in \
+                or not V.is_contiguous():
+            raise ValueError("V must be a contiguous d_in x d_out float32 CUDA tensor")
+        d_out = V.shape[1]
+        Y = torch.empty((rows, d_out), dtype=torch.float32, device=X.device) if out is None else out
+        self._sync_stream()
+        _check(lib().kmx_project(self._p, _ptr(X), rows, d_in, ldx, _ptr(V), d_out, _ptr(Y),
+                                 Y.stride(0)), self._p)
+        return Y
 
     # ---- candidate router ----------------------------------------------------
     def router(self, d: int, k: int, init_seed: int = 0) -> "Router":

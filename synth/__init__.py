@@ -176,3 +176,31 @@ def instance(desc):
     X = (means[comp] + rng.standard_normal((n, d))).astype(np.float32)
     w = rng.lognormal(0.0, 1.0, size=n).astype(np.float32)
     return X, w
+
+
+def lowrank_factors(d: int, r: int = 64, seed: int = 0):
+    """Gaussian factor matrix F (r x d, float32) of the streamed high-dimensional
+    workload: rows are z F + noise with z ~ N(0, I_r)."""
+    return _rng([seed, 0x10F]).standard_normal((r, d)).astype(np.float32)
+
+
+def lowrank_chunk(rows: int, F, seed: int = 0, chunk: int = 0, noise: float = 0.05):
+    """Chunk ``chunk`` of the streamed workload: rows z F + noise N(0, noise^2 I),
+    z ~ N(0, I_r) (float32)."""
+    rng = _rng([seed, 0xC4, chunk])
+    Z = rng.standard_normal((rows, F.shape[0])).astype(np.float32)
+    return (Z @ F + noise * rng.standard_normal((rows, F.shape[1])).astype(np.float32)
+            ).astype(np.float32)
+
+
+def lowrank_chunk_device(rows: int, F_dev, seed: int = 0, chunk: int = 0, noise: float = 0.05,
+                         device="cuda"):
+    """Same family as ``lowrank_chunk``, drawn on the device by torch's seeded
+    Philox generator (a different stream than the host version)."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed((int(seed) * 1_000_003 + int(chunk)) & 0x7FFFFFFFFFFFFFFF)
+    Z = torch.randn(rows, F_dev.shape[0], generator=g, device=device)
+    X = Z @ F_dev
+    X.add_(torch.randn(rows, F_dev.shape[1], generator=g, device=device), alpha=noise)
+    return X

@@ -1,0 +1,98 @@
+"""Streamed pipeline on the GPU (through the C ABI) against the FP64 oracle.
+
+  * kmx_project: Y = X V within the FP32 accumulation bound
+    |Y - Y*| <= (d_in + 2) 2^-23 (|X| |V|) elementwise (plus 1e-30), over
+    several tiles, ragged rows, d_in and every supported width;
+  * the basis from the randomized SVD of a sample spans the exact top
+    right singular vectors (principal angles);
+  * k-means on the projected rows with the FP8 E4M3 distance GEMM: labels,
+    centers and cost of the oracle's Lloyd on the same projected rows, to
+    the usual bars (labels exact outside the 1e-6 top-2 margin band,
+    centroids 1e-5, cost 1e-6).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import kmeans as ok
+from oracle import project as op
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1502_04265_amd import kmx
+    return kmx.Context(0)
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+@pytest.mark.parametrize("rows,d_in,d_out", [(1000, 4096, 64), (777, 1000, 16), (130, 37, 128),
+                                             (197, 200, 48), (64, 64, 112), (1, 5, 32)])
+def test_project_matches_oracle(ctx, rows, d_in, d_out):
+    say(f"project rows={rows} d_in={d_in} d_out={d_out}")
+    rng = np.random.default_rng(rows + d_in + d_out)
+    X = rng.standard_normal((rows, d_in)).astype(np.float32)
+    V = rng.standard_normal((d_in, d_out)).astype(np.float32)
+    Y = ctx.project(_dev(X), _dev(V)).cpu().numpy().astype(np.float64)
+    Yo = op.project(X, V)
+    bound = (d_in + 2) * 2.0 ** -23 * (np.abs(X.astype(np.float64)) @ np.abs(V.astype(np.float64)))
+    assert np.all(np.abs(Y - Yo) <= bound + 1e-30)
+
+
+def test_project_strided_rows(ctx):
+    # rows inside a wider buffer (leading dimension > d_in) and an odd stride
+    rng = np.random.default_rng(5)
+    big = rng.standard_normal((300, 131)).astype(np.float32)
+    X = _dev(big)[:, :100]
+    V = rng.standard_normal((100, 32)).astype(np.float32)
+    Y = ctx.project(X, _dev(V)).cpu().numpy().astype(np.float64)
+    Yo = op.project(big[:, :100], V)
+    bound = 102 * 2.0 ** -23 * (np.abs(big[:, :100].astype(np.float64)) @ np.abs(V.astype(np.float64)))
+    assert np.all(np.abs(Y - Yo) <= bound + 1e-30)
+
+
+def test_streamed_pipeline_fp8_kmeans(ctx):
+    """rank-64 signal in d=1024 plus N(0, 0.05^2) noise, 4 chunks of 16,384
+    rows, basis from a randomized SVD of an 8,192-row sample, k = 100."""
+    from paper_1502_04265_amd import subspace
+    d_in, r, chunks, rows, k, iters = 1024, 64, 4, 16384, 100, 8
+    F = synth.lowrank_factors(d_in, r, seed=3)
+    sample = synth.lowrank_chunk(8192, F, seed=3, chunk=999)
+    V = subspace.top_right_singular_vectors(sample, r, seed=1)
+    cosines = np.linalg.svd(op.best_fit_basis(sample, r).T @ V.astype(np.float64),
+                            compute_uv=False)
+    assert cosines.min() > 0.9999
+    Vd = _dev(V)
+    Y = torch.empty((chunks * rows, r), dtype=torch.float32, device="cuda:0")
+    for c in range(chunks):
+        Xc = synth.lowrank_chunk(rows, F, seed=3, chunk=c)
+        ctx.project(_dev(Xc), Vd, out=Y[c * rows:(c + 1) * rows])
+    Yh = Y.cpu().numpy()
+    C0, idx = ctx.seed(Y, k, rng_seed=2)
+    Co0, idx_o, _ = ok.seed(Yh, None, k, 2)
+    assert idx.cpu().numpy().tolist() == idx_o.tolist()
+    C, lab, hist, it = ctx.lloyd(Y, C0, iters, prec="fp8")
+    listed, via_fp32, full = ctx.assign_stats()
+    say(f"  fp8 final assignment: listed {listed}, via FP32 GEMM {via_fp32}, all centers {full}")
+    ref = ok.lloyd(Yh, None, Co0, iters)
+    assert it == ref["iters"] == iters
+    lab_o, d1, d2 = ok.assign(Yh, ref["C"])
+    bad = (lab.cpu().numpy() != lab_o) & ~((d2 - d1) < 1e-6 * d2)
+    assert not bad.any()
+    np.testing.assert_allclose(hist, ref["cost"], rtol=1e-6)
+    G = C.cpu().numpy().astype(np.float64)
+    for j in range(k):
+        assert np.linalg.norm(G[j] - ref["C"][j]) <= 1e-5 * np.linalg.norm(ref["C"][j])

@@ -30,8 +30,13 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Lloyd iter/s (n=4M,d=512,k=1000) vs plain FP32 GPU, equal cost ±1e-6 rel"
 BF16_PEAK_TFLOPS = 2500.0    # MI355X dense BF16 MFMA
+FP8_PEAK_TFLOPS = 5000.0     # MI355X dense FP8 MFMA
 FP32_PEAK_TFLOPS = 157.3     # MI355X FP32 matrix
 HBM_PEAK_GBS = 8000.0
+
+STREAMED = dict(n=10_000_000, d_in=4096, r=64, k=100, chunk=65536, sample=100_000,
+                name="rank-64 signal in d=4096 + N(0,0.05^2) noise, n=1e7 in chunks of 65536, "
+                     "projected to 64 dims, k=100")
 
 WORKLOADS = {
     "router": dict(n=4_000_000, d=512, k=1000, name="gaussian mixture n=4e6 d=512 k=1000 "
@@ -86,6 +91,103 @@ def cpu_baseline(X_host_rows, C_host, n_full, seconds_target=10.0):
             "sec_per_iter": sec_per_iter}
 
 
+def streamed_main(args):
+    """Streamed high-dimensional workload: chunks generated on the device,
+    projected onto a basis from a randomized SVD of a sample (host), then
+    k-means++ and Lloyd on the projected rows with the FP8 distance GEMM; the
+    BF16 and FP32 GEMMs run the same iterations from the same centers."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1502_04265_amd import kmx, subspace
+
+    W = STREAMED
+    d_in, r, k, rows = W["d_in"], W["r"], W["k"], W["chunk"]
+    nchunks = args.chunks or (W["n"] + rows - 1) // rows
+    n = nchunks * rows
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    ctx = kmx.Context(0)
+    F = torch.from_numpy(synth.lowrank_factors(d_in, r, seed=0)).to(dev)
+    log(f"[bench] basis from a {W['sample']}-row sample (randomized SVD on the host)")
+    t0 = time.perf_counter()
+    parts = []
+    for c in range((W["sample"] + rows - 1) // rows):
+        parts.append(synth.lowrank_chunk_device(rows, F, seed=0, chunk=1_000_000 + c,
+                                                device=dev).cpu().numpy())
+    sample = np.concatenate(parts)[:W["sample"]]
+    V = subspace.top_right_singular_vectors(sample, r, power_iters=1, seed=0)
+    del parts, sample
+    svd_s = time.perf_counter() - t0
+    Vd = torch.from_numpy(V).to(dev)
+    Y = torch.empty((n, r), dtype=torch.float32, device=dev)
+    ctx.timing(True, True)
+    gen_ms = 0.0
+    for c in range(nchunks):
+        t1 = time.perf_counter()
+        Xc = synth.lowrank_chunk_device(rows, F, seed=0, chunk=c, device=dev)
+        torch.cuda.synchronize()
+        gen_ms += (time.perf_counter() - t1) * 1e3
+        ctx.project(Xc, Vd, out=Y[c * rows:(c + 1) * rows])
+        if c % 32 == 0:
+            log(f"[bench] chunk {c}/{nchunks}")
+    torch.cuda.synchronize()
+    kt = ctx.timing_read()
+    ctx.timing(False, True)
+    del Xc
+    p_ms, p_cnt = kt["project"]
+    p_avg = p_ms / max(p_cnt, 1)
+    p_bytes = rows * d_in * 4 + rows * r * 4 + d_in * r * 4
+    log(f"[bench] projection: {p_avg:.3f} ms per chunk, {p_bytes / (p_avg * 1e-3) / 1e9:.0f} GB/s")
+
+    C0, _ = ctx.seed(Y, k, rng_seed=0)
+    res = {}
+    for prec in ("fp8", "bf16", "fp32"):
+        ctx.lloyd(Y, C0, 1, prec=prec, labels=False)            # per-precision copy of Y
+        ctx.timing(True, True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        Cp, _, hist, it = ctx.lloyd(Y, C0, args.steps, prec=prec, labels=False)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t1
+        kk = ctx.timing_read()
+        ctx.timing(False, True)
+        listed, via_fp32, full = ctx.assign_stats()
+        a_ms, a_cnt = kk["assign"]
+        res[prec] = {"iter_per_s": args.steps / wall, "ms_per_step": wall * 1e3 / args.steps,
+                     "final_cost": hist[-1], "assign_ms": a_ms / max(a_cnt, 1),
+                     "recheck_ms_per_step": kk["recheck"][0] / args.steps,
+                     "final_listed": listed, "final_via_fp32_gemm": via_fp32,
+                     "final_all_centers": full}
+        log(f"[bench] {prec}: {wall * 1e3 / args.steps:.3f} ms/iter, cost {hist[-1]:.9e}, "
+            f"listed {listed}, via FP32 {via_fp32}")
+    base = res["fp32"]["final_cost"]
+    flops = 2.0 * n * k * r
+    a8 = res["fp8"]["assign_ms"]
+    out = {
+        "metric": "streamed pipeline: projected rows/s and Lloyd iter/s (FP8 distance GEMM)",
+        "value": res["fp8"]["iter_per_s"], "unit": "iter/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": 1, "ms_per_step": res["fp8"]["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "fp8e4m3", "data": "synthetic",
+        "config": {"workload": W["name"], "n": n, "d_in": d_in, "d": r, "k": k,
+                   "chunks": nchunks},
+        "projection": {"ms_per_chunk": p_avg, "rows_per_s": rows / (p_avg * 1e-3),
+                       "roofline": {"bound": "hbm", "achieved": p_bytes / (p_avg * 1e-3) / 1e9,
+                                    "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                    "frac": p_bytes / (p_avg * 1e-3) / 1e9 / HBM_PEAK_GBS},
+                       "tflops": 2.0 * rows * d_in * r / (p_avg * 1e-3) / 1e12,
+                       "generation_ms_per_chunk": gen_ms / nchunks, "svd_s": svd_s},
+        "roofline": {"bound": "mfma", "achieved": flops / (a8 * 1e-3) / 1e12,
+                     "peak": FP8_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": flops / (a8 * 1e-3) / 1e12 / FP8_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "assign_kernel<fp8>", "avg_ms": a8},
+        "paths": res,
+        "equal_cost_rel_diff": {p: abs(res[p]["final_cost"] - base) / base for p in res},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -95,7 +197,9 @@ def main():
                     help="plain FP32 iterations whose labels train the router")
     ap.add_argument("--batch", type=int, default=8192, help="router training batch")
     ap.add_argument("--lr", type=float, default=1e-3, help="router learning rate (Adam)")
-    ap.add_argument("--workload", default="router", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="router", choices=sorted(WORKLOADS) + ["streamed"])
+    ap.add_argument("--chunks", type=int, default=None,
+                    help="streamed workload: number of chunks (default: all of n)")
     ap.add_argument("--fp32-steps", type=int, default=None,
                     help="iterations of the plain FP32 comparison (default: --steps)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -117,6 +221,8 @@ def main():
     import synth
     from paper_1502_04265_amd import kmx
 
+    if args.workload == "streamed":
+        return streamed_main(args)
     wl = WORKLOADS[args.workload]
     n, d, k = wl["n"], wl["d"], wl["k"]
     dev = "cuda:0"
@@ -221,7 +327,11 @@ def main():
     (Cp, lab_p, hist_p, _, rows_p), wp, _ = run_timed(
         "previous labels", lambda: ctx.lloyd_routed(X, Cw, args.steps, router=None, prec="bf16",
                                                     labels=True))
-    same = bool(torch.equal(lab_r, lab_b) and torch.equal(Cr, Cb) and torch.equal(lab_p, lab_b))
+    (C8, lab_8, hist_8, _), w8, kt8 = run_timed(
+        "full fp8", lambda: ctx.lloyd(X, Cw, args.steps, prec="fp8", labels=True))
+    fp8_stats = ctx.assign_stats()
+    same = bool(torch.equal(lab_r, lab_b) and torch.equal(Cr, Cb) and torch.equal(lab_p, lab_b)
+                and torch.equal(lab_8, lab_b) and torch.equal(C8, Cb))
 
     # ---- rooflines ----
     def avg(kk, cls):
@@ -274,6 +384,10 @@ def main():
                       "kernel_ms_per_step": {c: (v[0] / args.steps) for c, v in ktb.items() if v[1]}},
         "previous_labels": {"iter_per_s": args.steps / wp, "ms_per_step": wp * 1e3 / args.steps,
                             "gemm_rows_per_assignment": rows_p},
+        "full_fp8": {"iter_per_s": args.steps / w8, "ms_per_step": w8 * 1e3 / args.steps,
+                     "final_cost": hist_8[-1],
+                     "final_listed_via_fp32_all": list(fp8_stats),
+                     "kernel_ms_per_step": {c: (v[0] / args.steps) for c, v in kt8.items() if v[1]}},
         "router_vs_full_bf16": value / (args.steps / wb),
         "identical_to_full_bf16": same,
         "router_training": train,

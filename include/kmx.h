@@ -57,7 +57,9 @@ typedef enum {
   KMX_FP32 = 0,     /* FP32 MFMA, FP32 accumulate                            */
   KMX_BF16 = 1,     /* BF16 inputs (round to nearest even), FP32 accumulate  */
   KMX_FP8E4M3 = 2   /* FP8 E4M3 inputs with a power-of-two scale per row of X
-                       and one for all centers, FP32 accumulate; d <= 1024  */
+                       and one for all centers, FP32 accumulate; rows the
+                       FP8 bound cannot decide go through the BF16 GEMM;
+                       d <= 1024 */
 } kmx_prec;
 
 /* Context: binds a device and a HIP stream (hip_stream == NULL: the null
@@ -155,8 +157,10 @@ kmx_status kmx_project(kmx_ctx* ctx, const float* X, int64_t rows, int32_t d_in,
 /* Re-check counts of the most recent assignment on ctx (kmx_assign, kmx_cost,
  * or the final assignment of kmx_lloyd); host outputs, each nullable:
  *   listed   rows on the exact re-check list (pairs and full rows),
- *   fp32     rows the BF16 GEMM passed to the FP32 GEMM because three or more
- *            centers lay within its error bound,
+ *   fp32     rows the BF16 GEMM passed to the FP32 GEMM because more than
+ *            three centers lay within its error bound (with KMX_FP8E4M3 the
+ *            FP8 pass first hands every row it cannot decide to the BF16
+ *            pass),
  *   full     rows re-checked against every center.
  * Synchronizes. */
 kmx_status kmx_assign_stats(kmx_ctx* ctx, int64_t* listed, int64_t* fp32, int64_t* full);

@@ -81,8 +81,8 @@ __global__ __launch_bounds__(WAVES * 64) void assign_kernel(
     const RowStats* __restrict__ rs, const void* __restrict__ Cq, const float* __restrict__ ch,
     int k, int kpad, int ib, const CenterStats* __restrict__ cs, int32_t* __restrict__ label,
     float* __restrict__ d1o, float* __restrict__ d2o, FlagEntry* __restrict__ flags,
-    int* __restrict__ full_rows, int* __restrict__ brute, LoopState* __restrict__ st,
-    const int* __restrict__ gate) {
+    int* __restrict__ full_rows, unsigned long long* __restrict__ full_ctr, int cascade_all,
+    int* __restrict__ brute, LoopState* __restrict__ st, const int* __restrict__ gate) {
   if (gate && *gate) return;
   constexpr bool BF16 = (MODE == 1);
   constexpr bool F8 = (MODE == 2);
@@ -433,9 +433,10 @@ __global__ __launch_bounds__(WAVES * 64) void assign_kernel(
           d2o[r] = __builtin_inff();
         }
       }
-      const bool to_full = full && (full_rows != nullptr);
+      // cascade_all: every undecided row goes to the next GEMM pass
+      const bool to_full = (full || (cascade_all && flagged)) && (full_rows != nullptr);
       const bool to_brute = full && (full_rows == nullptr);
-      const bool to_flags = flagged && !full;
+      const bool to_flags = flagged && !full && !to_full;
       fmask[cg] = __ballot(to_flags);
       gmask[cg] = __ballot(to_full);
       bmask[cg] = __ballot(to_brute);
@@ -460,7 +461,7 @@ __global__ __launch_bounds__(WAVES * 64) void assign_kernel(
         sx += wcnt[2][w];
       }
       wbase[0] = sf ? atomicAdd(&st->flagged, (unsigned long long)sf) : 0ull;
-      wbase[1] = sg ? atomicAdd(&st->full_count, (unsigned long long)sg) : 0ull;
+      wbase[1] = sg ? atomicAdd(full_ctr, (unsigned long long)sg) : 0ull;
       wbase[2] = sx ? atomicAdd(&st->flagged_full, (unsigned long long)sx) : 0ull;
       if (!rows && (sf + sg + sx)) atomicAdd(&st->undecided, (unsigned long long)(sf + sg + sx));
     }
@@ -547,8 +548,9 @@ static hipError_t run_assign(hipStream_t s, const void* Xsrc, int64_t xs, int ve
                              const int* rows, const unsigned long long* row_count, int d, int dp,
                              const RowStats* rs, const void* Cq, const float* ch, int k, int kpad,
                              int ib, const CenterStats* cs, int32_t* label, float* d1, float* d2,
-                             FlagEntry* flags, int* full_rows, int* brute, LoopState* st,
-                             const int* gate, int num_cus) {
+                             FlagEntry* flags, int* full_rows, unsigned long long* full_ctr,
+                             int cascade_all, int* brute, LoopState* st, const int* gate,
+                             int num_cus) {
   const int64_t ppb = (int64_t)WAVES * 16 * NCG;
   int64_t blocks = (n + ppb - 1) / ppb;
   if (rows) {
@@ -558,7 +560,8 @@ static hipError_t run_assign(hipStream_t s, const void* Xsrc, int64_t xs, int ve
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL((assign_kernel<MODE, NKU, NCG, BN, WAVES, PF>), dim3((unsigned)blocks),
                      dim3(WAVES * 64), 0, s, Xsrc, xs, vec_ok, sx8, n, rows, row_count, d, dp, rs, Cq,
-                     ch, k, kpad, ib, cs, label, d1, d2, flags, full_rows, brute, st, gate);
+                     ch, k, kpad, ib, cs, label, d1, d2, flags, full_rows, full_ctr, cascade_all,
+                     brute, st, gate);
   return hipGetLastError();
 }
 
@@ -567,7 +570,8 @@ hipError_t launch_assign(hipStream_t s, int prec, const float* X, int64_t ldx, c
                          const unsigned long long* row_count, int d, int dp, const RowStats* rs,
                          const void* Cq, const float* ch, int k, int kpad, const CenterStats* cs,
                          int32_t* label, float* d1, float* d2, FlagEntry* flags, int* full_rows,
-                         int* brute, LoopState* st, const int* gate, int num_cus) {
+                         unsigned long long* full_ctr, int cascade_all, int* brute, LoopState* st,
+                         const int* gate, int num_cus) {
   int ib = 1;
   while ((1 << ib) < kpad) ++ib;
   const int nku = units_for(prec, d);
@@ -575,7 +579,7 @@ hipError_t launch_assign(hipStream_t s, int prec, const float* X, int64_t ldx, c
 #define KMX_A(NKU_, NCG_, BN_, W_)                                                               \
   return run_assign<1, NKU_, NCG_, BN_, W_>(s, Xq, dp, 1, nullptr, n, rows, row_count, d, dp, rs, \
                                             Cq, ch, k, kpad, ib, cs, label, d1, d2, flags,      \
-                                            full_rows, brute, st, gate, num_cus)
+                                            full_rows, full_ctr, cascade_all, brute, st, gate, num_cus)
     switch (nku) {
       case 1: KMX_A(1, 4, 64, 8);
       case 2: KMX_A(2, 4, 64, 8);
@@ -595,7 +599,7 @@ hipError_t launch_assign(hipStream_t s, int prec, const float* X, int64_t ldx, c
 #define KMX_A(NKU_, NCG_, BN_, W_)                                                           \
   return run_assign<2, NKU_, NCG_, BN_, W_>(s, Xq, dp, 1, sx8, n, rows, row_count, d, dp, rs, \
                                             Cq, ch, k, kpad, ib, cs, label, d1, d2, flags,  \
-                                            full_rows, brute, st, gate, num_cus)
+                                            full_rows, full_ctr, cascade_all, brute, st, gate, num_cus)
     switch (nku) {
       case 1: KMX_A(1, 4, 64, 8);
       case 2: KMX_A(2, 4, 64, 8);
@@ -611,7 +615,7 @@ hipError_t launch_assign(hipStream_t s, int prec, const float* X, int64_t ldx, c
 #define KMX_A(NKU_, NCG_, BN_, W_)                                                               \
   return run_assign<0, NKU_, NCG_, BN_, W_>(s, X, ldx, vec_ok, nullptr, n, rows, row_count, d, \
                                             dp, rs, Cq, ch, k, kpad, ib, cs, label, d1, d2,     \
-                                            flags, full_rows, brute, st, gate, num_cus)
+                                            flags, full_rows, full_ctr, cascade_all, brute, st, gate, num_cus)
   switch (nku) {
     case 1: KMX_A(1, 4, 64, 8);
     case 2: KMX_A(2, 4, 64, 8);

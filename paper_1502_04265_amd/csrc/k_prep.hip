@@ -389,14 +389,16 @@ hipError_t launch_fill_u8(hipStream_t s, uint8_t* p, int64_t n, uint8_t v) {
 
 // Clears the center maxima and the per-assignment counters; with reset_iter
 // also the loop state (done, iter, changed).
-__global__ void reset_small_kernel(CenterStats* cs, CenterStats* cs2, LoopState* st,
-                                   int reset_iter) {
+__global__ void reset_small_kernel(CenterStats* cs, CenterStats* cs2, CenterStats* cs3,
+                                   LoopState* st, int reset_iter) {
   if (threadIdx.x == 0) {
+    if (cs3) { cs3->cq_max = 0; cs3->rc_max = 0; cs3->cn_max = 0; cs3->O = 0.0f; cs3->c_amax = 0; cs3->c_exp = 127; }
     if (cs) { cs->cq_max = 0; cs->rc_max = 0; cs->cn_max = 0; cs->O = 0.0f; cs->c_amax = 0; cs->c_exp = 127; }
     if (cs2) { cs2->cq_max = 0; cs2->rc_max = 0; cs2->cn_max = 0; cs2->O = 0.0f; cs2->c_amax = 0; cs2->c_exp = 127; }
     if (st) {
       st->flagged = 0;
       st->full_count = 0;
+      st->full_count2 = 0;
       st->flagged_full = 0;
       st->undecided = 0;
       st->routed_fallback = 0;
@@ -410,9 +412,9 @@ __global__ void reset_small_kernel(CenterStats* cs, CenterStats* cs2, LoopState*
   }
 }
 
-hipError_t launch_reset_small(hipStream_t s, CenterStats* cs, CenterStats* cs2, LoopState* st,
-                              int reset_iter) {
-  hipLaunchKernelGGL(reset_small_kernel, dim3(1), dim3(64), 0, s, cs, cs2, st, reset_iter);
+hipError_t launch_reset_small(hipStream_t s, CenterStats* cs, CenterStats* cs2, CenterStats* cs3,
+                              LoopState* st, int reset_iter) {
+  hipLaunchKernelGGL(reset_small_kernel, dim3(1), dim3(64), 0, s, cs, cs2, cs3, st, reset_iter);
   return hipGetLastError();
 }
 

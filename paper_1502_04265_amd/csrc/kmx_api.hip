@@ -44,6 +44,7 @@ kmx_status check_prec(kmx_ctx* ctx, int prec, int d) {
 // BF16 preparation also serves the FP32 path (which only reads ||x||).
 kmx_status ensure_prep(kmx_ctx* ctx, const float* X, int64_t n, int d, int64_t ldx, int prec) {
   if (prec == KMX_FP8E4M3) {
+    KMX_TRY(ensure_prep(ctx, X, n, d, ldx, KMX_BF16));   // the cascade's BF16 pass
     if (ctx->cache8_valid && ctx->cache8_X == X && ctx->cache8_n == n && ctx->cache8_d == d &&
         ctx->cache8_ldx == ldx)
       return KMX_OK;
@@ -103,6 +104,8 @@ kmx_status ensure_common(kmx_ctx* ctx, int64_t n, int d, int k) {
   KMX_TRY(grow(ctx, ctx->cstats, sizeof(CenterStats)));
   KMX_TRY(grow(ctx, ctx->cstats32, sizeof(CenterStats)));
   KMX_TRY(grow(ctx, ctx->full_rows, (size_t)n * sizeof(int)));
+  KMX_TRY(grow(ctx, ctx->full_rows2, (size_t)n * sizeof(int)));
+  KMX_TRY(grow(ctx, ctx->cstats8, sizeof(CenterStats)));
   KMX_TRY(grow(ctx, ctx->brute, (size_t)n * sizeof(int)));
   KMX_TRY(grow(ctx, ctx->counts, (size_t)nb * k * sizeof(int32_t)));
   KMX_TRY(grow(ctx, ctx->segsum, (size_t)kScanSegs * k * sizeof(int32_t)));
@@ -132,16 +135,17 @@ kmx_status run_prep_centers(kmx_ctx* ctx, const float* C, int k, int d, int prec
   LoopState* st = ST(ctx);
   CenterStats* cs = P<CenterStats>(ctx->cstats);
   CenterStats* cs32 = P<CenterStats>(ctx->cstats32);
+  CenterStats* cs8 = P<CenterStats>(ctx->cstats8);
   const int dp32 = assign_dpad(KMX_FP32, d);
   const int bn32 = assign_tile_n(KMX_FP32, d);
   const int kpad32 = (k + bn32 - 1) / bn32 * bn32;
   KMX_TRY(grow(ctx, ctx->cq32, (size_t)kpad32 * dp32 * sizeof(float)));
   KMX_TRY(grow(ctx, ctx->ch32, (size_t)kpad32 * sizeof(float)));
   Timed tm(ctx, T_PREP);
-  KMX_HIP(ctx, launch_reset_small(ctx->stream, cs, cs32, st, 0));
+  KMX_HIP(ctx, launch_reset_small(ctx->stream, cs, cs32, cs8, st, 0));
   KMX_HIP(ctx, launch_prep_centers(ctx->stream, C, k, d, kpad32, dp32, KMX_FP32, ctx->cq32.p,
                                    P<float>(ctx->ch32), nullptr, cs32, nullptr));
-  if (prec == KMX_BF16) {
+  if (prec == KMX_BF16 || prec == KMX_FP8E4M3) {   // FP8 cascades into BF16
     const int dp = assign_dpad(KMX_BF16, d);
     const int bn = assign_tile_n(KMX_BF16, d);
     const int kpad = (k + bn - 1) / bn * bn;
@@ -158,15 +162,16 @@ kmx_status run_prep_centers(kmx_ctx* ctx, const float* C, int k, int d, int prec
     KMX_TRY(grow(ctx, ctx->ch8, (size_t)kpad * sizeof(float)));
     KMX_TRY(grow(ctx, ctx->hd8, (size_t)kpad * sizeof(double)));
     KMX_HIP(ctx, launch_prep_centers(ctx->stream, C, k, d, kpad, dp, KMX_FP8E4M3, ctx->cq8.p,
-                                     P<float>(ctx->ch8), P<double>(ctx->hd8), cs,
+                                     P<float>(ctx->ch8), P<double>(ctx->hd8), cs8,
                                      P<unsigned>(ctx->xstats8)));
   }
   return KMX_OK;
 }
 
-// BF16: rows whose candidate set the BF16 bound cannot narrow to three
-// centers go through the FP32 GEMM (same kernel, listed rows) before the
-// re-check.  gate: skip when *gate != 0.
+// GEMM passes: FP8 (every undecided row to the BF16 pass), BF16 (rows with
+// more than three centers inside its bound to the FP32 pass), FP32 (rows still
+// open to the every-center re-check); then the re-check.  gate: skip when
+// *gate != 0.
 kmx_status run_assign_gemm(kmx_ctx* ctx, const float* X, int64_t n, int d, int64_t ldx,
                            const float* C, int k, int prec, int32_t* label, float* d1,
                            float* d2, const int* rows, const unsigned long long* row_count,
@@ -174,45 +179,62 @@ kmx_status run_assign_gemm(kmx_ctx* ctx, const float* X, int64_t n, int d, int64
   LoopState* st = ST(ctx);
   CenterStats* cs = P<CenterStats>(ctx->cstats);
   CenterStats* cs32 = P<CenterStats>(ctx->cstats32);
+  CenterStats* cs8 = P<CenterStats>(ctx->cstats8);
   const int dp32 = assign_dpad(KMX_FP32, d);
   const int bn32 = assign_tile_n(KMX_FP32, d);
   const int kpad32 = (k + bn32 - 1) / bn32 * bn32;
   const RowStats* rs = P<RowStats>(ctx->rowstats);
   FlagEntry* flags = P<FlagEntry>(ctx->flags);
-  if (prec == KMX_BF16 || prec == KMX_FP8E4M3) {
-    const bool f8 = prec == KMX_FP8E4M3;
-    const int dp = assign_dpad(prec, d);
-    const int bn = assign_tile_n(prec, d);
+  int* brute = P<int>(ctx->brute);
+  ctx->last_prec = prec;
+  if (prec == KMX_FP32) {
+    Timed tm(ctx, T_ASSIGN);
+    KMX_HIP(ctx, launch_assign(ctx->stream, KMX_FP32, X, ldx, nullptr, nullptr, n, rows,
+                               row_count, d, dp32, rs, ctx->cq32.p, P<float>(ctx->ch32), k,
+                               kpad32, cs32, label, d1, d2, flags, nullptr, nullptr, 0, brute,
+                               st, gate, ctx->num_cus));
+  } else {
+    const int dp = assign_dpad(KMX_BF16, d);
+    const int bn = assign_tile_n(KMX_BF16, d);
     const int kpad = (k + bn - 1) / bn * bn;
-    if (f8) rs = P<RowStats>(ctx->rowstats8);   // its xn2 and nx also serve the FP32 pass
-    {
+    // rows the BF16 pass covers, and where it sends rows for the FP32 pass
+    const int* rows16 = rows;
+    const unsigned long long* cnt16 = row_count;
+    int* next16 = P<int>(ctx->full_rows);
+    unsigned long long* ctr16 = &st->full_count;
+    if (prec == KMX_FP8E4M3) {
+      const int dp8 = assign_dpad(KMX_FP8E4M3, d);
+      const int bn8 = assign_tile_n(KMX_FP8E4M3, d);
+      const int kpad8 = (k + bn8 - 1) / bn8 * bn8;
       Timed tm(ctx, T_ASSIGN);
-      KMX_HIP(ctx, launch_assign(ctx->stream, prec, X, ldx,
-                                 f8 ? ctx->xq8.p : ctx->xq.p, f8 ? P<uint8_t>(ctx->sx8) : nullptr,
-                                 n, rows, row_count, d, dp, rs, f8 ? ctx->cq8.p : ctx->cq.p,
-                                 f8 ? P<float>(ctx->ch8) : nullptr, k, kpad, cs, label, d1, d2,
-                                 flags, P<int>(ctx->full_rows), P<int>(ctx->brute), st, gate,
-                                 ctx->num_cus));
+      KMX_HIP(ctx, launch_assign(ctx->stream, KMX_FP8E4M3, X, ldx, ctx->xq8.p,
+                                 P<uint8_t>(ctx->sx8), n, rows, row_count, d, dp8,
+                                 P<RowStats>(ctx->rowstats8), ctx->cq8.p, P<float>(ctx->ch8), k,
+                                 kpad8, cs8, label, d1, d2, flags, P<int>(ctx->full_rows),
+                                 &st->full_count, 1, brute, st, gate, ctx->num_cus));
+      rows16 = P<int>(ctx->full_rows);
+      cnt16 = &st->full_count;
+      next16 = P<int>(ctx->full_rows2);
+      ctr16 = &st->full_count2;
+    }
+    {
+      Timed tm(ctx, prec == KMX_FP8E4M3 ? T_RECHECK : T_ASSIGN);
+      KMX_HIP(ctx, launch_assign(ctx->stream, KMX_BF16, X, ldx, ctx->xq.p, nullptr, n, rows16,
+                                 cnt16, d, dp, rs, ctx->cq.p, nullptr, k, kpad, cs, label, d1, d2,
+                                 flags, next16, ctr16, 0, brute, st, gate, ctx->num_cus));
     }
     {
       Timed tm(ctx, T_RECHECK);
-      KMX_HIP(ctx, launch_assign(ctx->stream, KMX_FP32, X, ldx, nullptr, nullptr, n,
-                                 P<int>(ctx->full_rows),
-                                 &st->full_count, d, dp32, rs, ctx->cq32.p, P<float>(ctx->ch32), k,
-                                 kpad32, cs32, label, d1, d2, flags, nullptr, P<int>(ctx->brute),
-                                 st, gate, ctx->num_cus));
+      KMX_HIP(ctx, launch_assign(ctx->stream, KMX_FP32, X, ldx, nullptr, nullptr, n, next16,
+                                 ctr16, d, dp32, rs, ctx->cq32.p, P<float>(ctx->ch32), k, kpad32,
+                                 cs32, label, d1, d2, flags, nullptr, nullptr, 0, brute, st, gate,
+                                 ctx->num_cus));
     }
-  } else {
-    Timed tm(ctx, T_ASSIGN);
-    KMX_HIP(ctx, launch_assign(ctx->stream, KMX_FP32, X, ldx, nullptr, nullptr, n, rows, row_count, d,
-                               dp32, rs, ctx->cq32.p, P<float>(ctx->ch32), k, kpad32, cs32, label,
-                               d1, d2, flags, nullptr, P<int>(ctx->brute), st, gate,
-                               ctx->num_cus));
   }
   {
     Timed tm(ctx, T_RECHECK);
-    KMX_HIP(ctx, launch_recheck(ctx->stream, X, n, d, ldx, C, k, label, d1, flags,
-                                P<int>(ctx->brute), st, ctx->num_cus, gate));
+    KMX_HIP(ctx, launch_recheck(ctx->stream, X, n, d, ldx, C, k, label, d1, flags, brute, st,
+                                ctx->num_cus, gate));
   }
   return KMX_OK;
 }
@@ -307,7 +329,8 @@ kmx_status kmx_destroy(kmx_ctx* ctx) {
       &ctx->D2,        &ctx->chosen,   &ctx->seed_part,  &ctx->seed_ctr,   &ctx->scratch_c,
       &ctx->hist,      &ctx->fb_rows,  &ctx->keys,       &ctx->cdist,      &ctx->nbr,
       &ctx->nbd,       &ctx->fbh,      &ctx->xq8,        &ctx->sx8,        &ctx->rowstats8,
-      &ctx->xstats8,   &ctx->cq8,      &ctx->ch8,        &ctx->hd8};
+      &ctx->xstats8,   &ctx->cq8,      &ctx->ch8,        &ctx->hd8,        &ctx->cstats8,
+      &ctx->full_rows2};
   for (kmx::Buf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   for (auto& r : ctx->recs) {
@@ -497,7 +520,7 @@ kmx_status kmx_assign_stats(kmx_ctx* ctx, int64_t* listed, int64_t* fp32, int64_
   KMX_HIP(ctx, hipMemcpyAsync(&h, ctx->state.p, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
   KMX_HIP(ctx, hipStreamSynchronize(ctx->stream));
   if (listed) *listed = (int64_t)h.flagged;
-  if (fp32) *fp32 = (int64_t)h.full_count;
+  if (fp32) *fp32 = (int64_t)(ctx->last_prec == KMX_FP8E4M3 ? h.full_count2 : h.full_count);
   if (full) *full = (int64_t)h.flagged_full;
   return KMX_OK;
 }

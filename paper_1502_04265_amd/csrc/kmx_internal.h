@@ -50,6 +50,7 @@ struct LoopState {
   unsigned long long undecided;    // rows the first GEMM pass could not decide
   double cost_at_centroids;
   double cost_last;
+  unsigned long long full_count2;      // rows the BF16 pass of an FP8 cascade sent to FP32
   unsigned long long routed_fallback;  // rows the certificate sent to the GEMM (last assign)
   unsigned long long routed_listed;    // certified rows that needed the short re-check
 };
@@ -162,7 +163,8 @@ struct kmx_ctx {
   int64_t cache8_n = 0, cache8_ldx = 0;
   int cache8_d = 0;
   bool cache8_valid = false;
-  kmx::Buf xq8, sx8, rowstats8, xstats8, cq8, ch8, hd8;
+  int last_prec = -1;   // precision of the most recent assignment
+  kmx::Buf xq8, sx8, rowstats8, xstats8, cq8, ch8, hd8, cstats8, full_rows2;
   kmx::Buf cq, ch, hd, cstats, cq32, ch32, cstats32, full_rows, brute;
   kmx::Buf lab_a, lab_prev, d1, d2;
   kmx::Buf flags, counters;
@@ -197,8 +199,8 @@ hipError_t launch_prep_rows_f8(hipStream_t s, const float* X, int64_t n, int d, 
                                unsigned* xq_max, int num_cus);
 hipError_t launch_fill_i32(hipStream_t s, int32_t* p, int64_t n, int32_t v);
 hipError_t launch_fill_u8(hipStream_t s, uint8_t* p, int64_t n, uint8_t v);
-hipError_t launch_reset_small(hipStream_t s, CenterStats* cs, CenterStats* cs2, LoopState* st,
-                              int reset_iter);
+hipError_t launch_reset_small(hipStream_t s, CenterStats* cs, CenterStats* cs2, CenterStats* cs3,
+                              LoopState* st, int reset_iter);
 
 // assign
 int assign_tile_n(int prec, int d);   // centers per tile (kpad granularity)
@@ -208,7 +210,8 @@ hipError_t launch_assign(hipStream_t s, int prec, const float* X, int64_t ldx,
                          const unsigned long long* row_count, int d, int dp,
                          const RowStats* rs, const void* Cq, const float* ch,
                          int k, int kpad, const CenterStats* cs, int32_t* label,
-                         float* d1, float* d2, FlagEntry* flags, int* full_rows, int* brute,
+                         float* d1, float* d2, FlagEntry* flags, int* full_rows,
+                         unsigned long long* full_ctr, int cascade_all, int* brute,
                          LoopState* st, const int* gate, int num_cus);
 hipError_t launch_recheck(hipStream_t s, const float* X, int64_t n, int d, int64_t ldx,
                           const float* C, int k, int32_t* label, float* d1,

@@ -178,6 +178,50 @@ kmx_status kmx_timing(kmx_ctx* ctx, int enable, int reset);
 kmx_status kmx_timing_read(kmx_ctx* ctx, int n_classes, double* ms_out, int64_t* count_out);
 
 /* ---------------------------------------------------------------------------
+ * Batched Lloyd: many independent weighted problems at once (Sec. 2.2 runs
+ * k-means++ and Lloyd on weighted summaries; pieces and restarts give many
+ * such problems).  Every iteration assigns all problems with one persistent
+ * launch per width group (d rounded to the BF16 tile width: up to six
+ * groups; BF16 distance GEMM, exact labels as for kmx_assign), updates each
+ * problem's centroids in FP64 and records its cost; the iteration is
+ * captured once as a HIP graph and replayed.  The tile shape used for each
+ * (d, k class) is the autotuner's choice when kmx_batched_autotune ran on
+ * the context, otherwise a default.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  const float* X;   /* device, n x d, leading dimension ldx                  */
+  int64_t n;
+  int32_t d;        /* 1 <= d <= 512                                        */
+  int64_t ldx;
+  const float* w;   /* device, n weights, nullable (all 1)                   */
+  float* C;         /* device, k x d: C_0 in, C_iters out                    */
+  int32_t k;        /* 1 <= k <= n                                           */
+  int32_t* label;   /* device, n, nullable: labels against C_iters           */
+} kmx_problem;
+
+/* iters Lloyd iterations of every problem (no early stop), then one
+ * assignment for the final cost and labels.
+ *   prec      KMX_BF16.
+ *   cost_hist host, count x (iters + 1) doubles, row i = problem i:
+ *             cost_hist[i][t] = cost of problem i at C_t.
+ * Synchronizes.  Inputs are copied once per call into a grouped layout. */
+kmx_status kmx_lloyd_batched(kmx_ctx* ctx, const kmx_problem* probs, int32_t count,
+                             int32_t iters, kmx_prec prec, double* cost_hist);
+
+/* Autotuner: for each (d, k class) present in probs (k classes: k <= 24,
+ * k <= 96, larger), times the batched assignment of those problems under
+ * each tile shape and keeps the fastest on ctx.  cache_path (nullable): a
+ * file of JSON lines; entries for this device are loaded instead of tuning
+ * when present (*loaded = 1), new results are appended otherwise. */
+kmx_status kmx_batched_autotune(kmx_ctx* ctx, const kmx_problem* probs, int32_t count,
+                                kmx_prec prec, const char* cache_path, int32_t* loaded);
+
+/* Tile shape the batched assignment uses for (d, k) on ctx: centers per LDS
+ * tile and points per workgroup (host outputs, nullable). */
+kmx_status kmx_batched_tiles(kmx_ctx* ctx, int32_t d, int32_t k, int32_t* tile,
+                             int32_t* points_per_block);
+
+/* ---------------------------------------------------------------------------
  * Candidate router with a certificate.
  *
  * Not part of the paper's method: an accelerator of its assignment step

@@ -72,55 +72,81 @@ __device__ __forceinline__ void top4_insert(unsigned key, unsigned& v1, unsigned
   v4 = n4;
 }
 
-// MODE: 0 FP32, 1 BF16, 2 FP8 E4M3.
-template <int MODE, int NKU, int NCG, int BN, int WAVES, int PF = 1>
-__global__ __launch_bounds__(WAVES * 64) void assign_kernel(
-    const void* __restrict__ Xsrc, int64_t xs, int vec_ok, const uint8_t* __restrict__ sx8,
-    int64_t n, const int* __restrict__ rows,
-    const unsigned long long* __restrict__ row_count, int d, int dp,
-    const RowStats* __restrict__ rs, const void* __restrict__ Cq, const float* __restrict__ ch,
-    int k, int kpad, int ib, const CenterStats* __restrict__ cs, int32_t* __restrict__ label,
-    float* __restrict__ d1o, float* __restrict__ d2o, FlagEntry* __restrict__ flags,
-    int* __restrict__ full_rows, unsigned long long* __restrict__ full_ctr, int cascade_all,
-    int* __restrict__ brute, LoopState* __restrict__ st, const int* __restrict__ gate) {
-  if (gate && *gate) return;
+// Arguments of one assignment pass as seen by a block.
+struct AssignArgs {
+  const void* Xsrc;            // rows of the GEMM operand (FP32 X, BF16 or FP8 copy)
+  int64_t xs;                  // row stride (elements of the operand; bytes for FP8)
+  int vec_ok;                  // FP32 rows allow 16-byte loads
+  const uint8_t* sx8;          // FP8 row scales (E8M0)
+  int64_t npts;                // points: rows[0 .. npts) or 0 .. npts
+  const int* rows;             // optional row list
+  int d, dp;
+  const RowStats* rs;
+  const void* Cq;              // padded center rows
+  const float* ch;             // per-center values (FP32: h_j; FP8: O - h_j)
+  int k, kpad, ib;
+  const CenterStats* cs;
+  int32_t* label;
+  float* d1o;
+  float* d2o;
+  int koff;                    // added to every center index written
+  int64_t list_off;            // added to every row index written into a list
+  FlagEntry* flags;
+  int* full_rows;
+  unsigned long long* full_ctr;
+  int cascade_all;
+  int* brute;
+  LoopState* st;
+  int count_undecided;
+};
+
+template <int MODE, int NKU, int NCG, int BN, int WAVES>
+struct AssignShape {
+  static constexpr int UB = (MODE == 2) ? 32 : 16;     // bytes per lane and unit
+  static constexpr int ROWB = NKU * UB * 4;            // bytes of one center row
+  static constexpr int UROW = ROWB / 16 + 1;           // 16-byte units per LDS row
+  static constexpr int CHUNKS = (BN * UROW + 63) / 64; // 1 KB direct-to-LDS copies per tile
+  static constexpr int BUFB = CHUNKS * 1024;           // bytes of one tile buffer
+  static constexpr int PPB = WAVES * 16 * NCG;         // points per block
+};
+
+// One block of PPB points starting at point blk * PPB: point fragments, the
+// loop over every center tile, the merge of the four lanes of a point, the
+// decision and the re-check list entries.  lds holds two tile buffers, hsh
+// two rows of BN per-center values, wcnt 3 * WAVES counters, wbase 3 bases.
+template <int MODE, int NKU, int NCG, int BN, int WAVES, int PF>
+__device__ __forceinline__ void assign_block(const AssignArgs& A, int64_t blk,
+                                             unsigned char* lds, float* hsh, int* wcnt,
+                                             unsigned long long* wbase) {
   constexpr bool BF16 = (MODE == 1);
   constexpr bool F8 = (MODE == 2);
   constexpr bool PK = (MODE != 0);       // packed keys (BF16, FP8)
   constexpr bool HS = (MODE != 1);       // per-center values staged with each tile
-  constexpr int UB = F8 ? 32 : 16;       // bytes per lane and unit
   constexpr int NF = F8 ? 2 : 1;         // 16-byte fragments per lane and unit
   constexpr int NT = WAVES * 64;
   constexpr int RB = BN / 16;
-  constexpr int ROWB = NKU * UB * 4;     // bytes of one center row (all units)
+  using S = AssignShape<MODE, NKU, NCG, BN, WAVES>;
+  constexpr int ROWB = S::ROWB;
   constexpr int PITCH = ROWB + 16;       // padded LDS row pitch
-  constexpr int UROW = ROWB / 16 + 1;    // 16-byte units per LDS row
-  constexpr int CHUNKS = (BN * UROW + 63) / 64;  // 1 KB direct-to-LDS copies per tile
-  constexpr int BUFB = CHUNKS * 1024;    // bytes of one tile buffer
-  constexpr int PPB = WAVES * 16 * NCG;  // points per block
-  __shared__ __attribute__((aligned(1024))) unsigned char lds[2][BUFB];
-  __shared__ __attribute__((aligned(16))) float hsh[2][BN];
-  __shared__ int wcnt[3][WAVES];
-  __shared__ unsigned long long wbase[3];
+  constexpr int UROW = S::UROW;
+  constexpr int CHUNKS = S::CHUNKS;
+  constexpr int BUFB = S::BUFB;
+  constexpr int PPB = S::PPB;
+  (void)NT;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int prow = lane & 15;
   const int grp = lane >> 4;
-
-  const int64_t npts = rows ? (int64_t)(*row_count) : n;
-  const int64_t nblk = (npts + PPB - 1) / PPB;
-  const int ntiles = kpad / BN;
-  const unsigned mask = (ib >= 32) ? 0xFFFFFFFFu : ((1u << ib) - 1u);
-
-  const float cqm = __uint_as_float(cs->cq_max);
-  const float rcm = __uint_as_float(cs->rc_max);
-  const float cnm = __uint_as_float(cs->cn_max);
-  const float Og = cs->O;
-  const int cexp = cs->c_exp;
-
-  for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+  const int ntiles = A.kpad / BN;
+  const unsigned mask = (A.ib >= 32) ? 0xFFFFFFFFu : ((1u << A.ib) - 1u);
+  const float cqm = __uint_as_float(A.cs->cq_max);
+  const float rcm = __uint_as_float(A.cs->rc_max);
+  const float cnm = __uint_as_float(A.cs->cn_max);
+  const float Og = A.cs->O;
+  const int cexp = A.cs->c_exp;
+  {
     const int64_t p_base = blk * PPB + (int64_t)wave * (16 * NCG);
 
     // ---- point fragments (B operand) for this block ----
@@ -130,30 +156,30 @@ __global__ __launch_bounds__(WAVES * 64) void assign_kernel(
 #pragma unroll
     for (int cg = 0; cg < NCG; ++cg) {
       const int64_t p = p_base + cg * 16 + prow;
-      const bool pv = p < npts;
-      const int64_t r = pv ? (rows ? (int64_t)rows[p] : p) : -1;
+      const bool pv = p < A.npts;
+      const int64_t r = pv ? (A.rows ? (int64_t)A.rows[p] : p) : -1;
       src_row[cg] = r;
       sxe[cg] = 127;
-      if (F8 && pv) sxe[cg] = (int)sx8[r];
+      if (F8 && pv) sxe[cg] = (int)A.sx8[r];
 #pragma unroll
       for (int ku = 0; ku < NKU * NF; ++ku) {
         u32x4_t v = {0u, 0u, 0u, 0u};
         if (F8) {
           if (pv)
-            v = *(const u32x4_t*)((const uint8_t*)Xsrc + r * xs + (ku >> 1) * 128 + grp * 32 +
+            v = *(const u32x4_t*)((const uint8_t*)A.Xsrc + r * A.xs + (ku >> 1) * 128 + grp * 32 +
                                   (ku & 1) * 16);
         } else if (BF16) {
-          if (pv) v = *(const u32x4_t*)((const uint16_t*)Xsrc + r * xs + ku * 32 + grp * 8);
+          if (pv) v = *(const u32x4_t*)((const uint16_t*)A.Xsrc + r * A.xs + ku * 32 + grp * 8);
         } else {
           const int e0 = ku * 16 + grp * 4;
-          const float* src = (const float*)Xsrc + r * xs + e0;
+          const float* src = (const float*)A.Xsrc + r * A.xs + e0;
           if (pv) {
-            if (vec_ok && e0 + 4 <= d) {
+            if (A.vec_ok && e0 + 4 <= A.d) {
               v = *(const u32x4_t*)src;
             } else {
 #pragma unroll
               for (int q = 0; q < 4; ++q)
-                if (e0 + q < d) v[q] = __float_as_uint(src[q]);
+                if (e0 + q < A.d) v[q] = __float_as_uint(src[q]);
             }
           }
         }
@@ -178,7 +204,7 @@ __global__ __launch_bounds__(WAVES * 64) void assign_kernel(
     // load writes them).  Pad units re-load the tile's first unit.
     float hstage = 0.0f;
     auto issue_tile = [&](int tile, int buf) {
-      const unsigned char* tbase = (const unsigned char*)Cq + (int64_t)tile * BN * ROWB;
+      const unsigned char* tbase = (const unsigned char*)A.Cq + (int64_t)tile * BN * ROWB;
 #pragma unroll
       for (int c = wave; c < CHUNKS; c += WAVES) {
         const int q = c * 64 + lane;
@@ -187,13 +213,13 @@ __global__ __launch_bounds__(WAVES * 64) void assign_kernel(
         const unsigned char* src =
             (row < BN && uc < UROW - 1) ? tbase + row * ROWB + uc * 16 : tbase;
         __builtin_amdgcn_global_load_lds(
-            (const void*)src, (__attribute__((address_space(3))) void*)(&lds[buf][c * 1024]), 16,
+            (const void*)src, (__attribute__((address_space(3))) void*)(&lds[buf * BUFB + c * 1024]), 16,
             0, 0);
       }
-      if (HS && tid < BN) hstage = ch[tile * BN + tid];
+      if (HS && tid < BN) hstage = A.ch[tile * BN + tid];
     };
     auto finish_tile = [&](int buf) {
-      if (HS && tid < BN) hsh[buf][tid] = hstage;
+      if (HS && tid < BN) hsh[buf * BN + tid] = hstage;
       __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
     };
 
@@ -209,13 +235,13 @@ __global__ __launch_bounds__(WAVES * 64) void assign_kernel(
 #pragma unroll
       for (int rb = 0; rb < RB; ++rb) {
         f32x4_t a0 = {0.f, 0.f, 0.f, 0.f};
-        if (F8) a0 = *(const f32x4_t*)(&hsh[buf][rb * 16 + grp * 4]);
+        if (F8) a0 = *(const f32x4_t*)(&hsh[buf * BN + rb * 16 + grp * 4]);
 #pragma unroll
         for (int cg = 0; cg < NCG; ++cg) acc[cg][rb] = a0;
       }
 
       if constexpr (F8) {
-        const unsigned char* abase = &lds[buf][prow * PITCH + grp * 32];
+        const unsigned char* abase = &lds[buf * BUFB + prow * PITCH + grp * 32];
 #pragma unroll
         for (int ku = 0; ku < NKU; ++ku) {
 #pragma unroll
@@ -239,7 +265,7 @@ __global__ __launch_bounds__(WAVES * 64) void assign_kernel(
       // scheduling barrier keeps the compiler from sinking the reads.
       constexpr int NB = PF + 1;
       u32x4_t afr[NB][RB];
-      const unsigned char* abase = &lds[buf][prow * PITCH + grp * 16];
+      const unsigned char* abase = &lds[buf * BUFB + prow * PITCH + grp * 16];
 #pragma unroll
       for (int q = 0; q < PF; ++q)
 #pragma unroll
@@ -295,7 +321,7 @@ __global__ __launch_bounds__(WAVES * 64) void assign_kernel(
         // keeps the lower index on ties
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
-          const f32x4_t hv = *(const f32x4_t*)(&hsh[buf][rb * 16 + grp * 4]);
+          const f32x4_t hv = *(const f32x4_t*)(&hsh[buf * BN + rb * 16 + grp * 4]);
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const int j = t * BN + rb * 16 + grp * 4 + i;
@@ -357,7 +383,7 @@ __global__ __launch_bounds__(WAVES * 64) void assign_kernel(
     // ---- decision, outputs, re-check lists ----
     const float ua = 1.1920929e-7f;  // 2^-23: covers any faithful accumulation rounding
     const float u = 5.9604645e-8f;   // 2^-24
-    const float Kf = (float)(dp + 1);
+    const float Kf = (float)(A.dp + 1);
     const float gam = Kf * ua / (1.0f - Kf * ua);
     unsigned long long fmask[NCG], gmask[NCG], bmask[NCG];
     int cand2v[NCG], cand3v[NCG];
@@ -369,7 +395,7 @@ __global__ __launch_bounds__(WAVES * 64) void assign_kernel(
       bool flagged = false, full = false;
       int cand2 = 0, cand3 = -1;
       if (writer) {
-        const RowStats rw = rs[r];
+        const RowStats rw = A.rs[r];
         float t1, t2 = 0.f, t3 = 0.f, t4 = 0.f, E, off;
         int i1, i3 = -1;
         bool has2, has3, has4 = false;
@@ -378,46 +404,46 @@ __global__ __launch_bounds__(WAVES * 64) void assign_kernel(
           off = Og;
           if constexpr (BF16) {
             E = gam * (rw.nxq * cqm + Og) + rw.rx * cqm + rw.nx * rcm + 3.0f * u * Og +
-                ldexpf(2.0f * Og, ib - 23);
+                ldexpf(2.0f * Og, A.ib - 23);
           } else {
             // NKU accumulation steps of FP32 rounding, the FP8 instruction's
             // internal summation (2^-10 sum |x~ c~|), the rounding of O - h_j
             const float gk = (float)NKU * ua;
             E = (9.765625e-4f + gk) * rw.nxq * cqm + gk * Og + rw.rx * cqm + rw.nx * rcm +
-                u * Og + ldexpf(2.0f * Og, ib - 23);
+                u * Og + ldexpf(2.0f * Og, A.ib - 23);
           }
           t1 = __uint_as_float(v1[cg] & hi);
-          i1 = (v1[cg] & hi) ? min((int)(mask - (v1[cg] & mask)), k - 1) : 0;
+          i1 = (v1[cg] & hi) ? min((int)(mask - (v1[cg] & mask)), A.k - 1) : 0;
           has2 = (v2[cg] & hi) != 0u;
           has3 = (v3[cg] & hi) != 0u;
           has4 = (v4[cg] & hi) != 0u;
           if (has2) {
             t2 = __uint_as_float(v2[cg] & hi);
-            cand2 = min((int)(mask - (v2[cg] & mask)), k - 1);
+            cand2 = min((int)(mask - (v2[cg] & mask)), A.k - 1);
           }
           if (has3) {
             t3 = __uint_as_float(v3[cg] & hi);
-            i3 = min((int)(mask - (v3[cg] & mask)), k - 1);
+            i3 = min((int)(mask - (v3[cg] & mask)), A.k - 1);
           }
           if (has4) t4 = __uint_as_float(v4[cg] & hi);
         } else {
           off = 0.0f;
           E = (gam + u) * rw.nx * cnm + 1.5f * u * cnm * cnm;
           t1 = f1[cg];
-          i1 = min(max(j1[cg], 0), k - 1);
+          i1 = min(max(j1[cg], 0), A.k - 1);
           has2 = f2[cg] > -__builtin_inff();
           has3 = f3[cg] > -__builtin_inff();
           if (has2) {
             t2 = f2[cg];
-            cand2 = min(max(j2[cg], 0), k - 1);
+            cand2 = min(max(j2[cg], 0), A.k - 1);
           }
           if (has3) t3 = f3[cg];
         }
         E *= 1.0001f;
-        label[r] = i1;
-        if (d1o) d1o[r] = fmaxf(rw.xn2 - 2.0f * (t1 - off), 0.0f);
+        A.label[r] = A.koff + i1;
+        if (A.d1o) A.d1o[r] = fmaxf(rw.xn2 - 2.0f * (t1 - off), 0.0f);
         if (has2) {
-          if (d2o) d2o[r] = fmaxf(rw.xn2 - 2.0f * (t2 - off), 0.0f);
+          if (A.d2o) A.d2o[r] = fmaxf(rw.xn2 - 2.0f * (t2 - off), 0.0f);
           flagged = (t1 - t2) <= 2.0f * E;
           if (flagged && has3 && (t1 - t3) <= 2.0f * E) {
             // BF16 keeps a fourth key: three listed candidates suffice unless
@@ -429,13 +455,13 @@ __global__ __launch_bounds__(WAVES * 64) void assign_kernel(
               full = true;
             }
           }
-        } else if (d2o) {
-          d2o[r] = __builtin_inff();
+        } else if (A.d2o) {
+          A.d2o[r] = __builtin_inff();
         }
       }
       // cascade_all: every undecided row goes to the next GEMM pass
-      const bool to_full = (full || (cascade_all && flagged)) && (full_rows != nullptr);
-      const bool to_brute = full && (full_rows == nullptr);
+      const bool to_full = (full || (A.cascade_all && flagged)) && (A.full_rows != nullptr);
+      const bool to_brute = full && (A.full_rows == nullptr);
       const bool to_flags = flagged && !full && !to_full;
       fmask[cg] = __ballot(to_flags);
       gmask[cg] = __ballot(to_full);
@@ -448,49 +474,69 @@ __global__ __launch_bounds__(WAVES * 64) void assign_kernel(
     }
     // one atomic per list and workgroup; waves take consecutive slices
     if (lane == 0) {
-      wcnt[0][wave] = nf_w;
-      wcnt[1][wave] = ng_w;
-      wcnt[2][wave] = nfull_w;
+      wcnt[0 * WAVES + wave] = nf_w;
+      wcnt[1 * WAVES + wave] = ng_w;
+      wcnt[2 * WAVES + wave] = nfull_w;
     }
     __syncthreads();
     if (tid == 0) {
       int sf = 0, sg = 0, sx = 0;
       for (int w = 0; w < WAVES; ++w) {
-        sf += wcnt[0][w];
-        sg += wcnt[1][w];
-        sx += wcnt[2][w];
+        sf += wcnt[0 * WAVES + w];
+        sg += wcnt[1 * WAVES + w];
+        sx += wcnt[2 * WAVES + w];
       }
-      wbase[0] = sf ? atomicAdd(&st->flagged, (unsigned long long)sf) : 0ull;
-      wbase[1] = sg ? atomicAdd(full_ctr, (unsigned long long)sg) : 0ull;
-      wbase[2] = sx ? atomicAdd(&st->flagged_full, (unsigned long long)sx) : 0ull;
-      if (!rows && (sf + sg + sx)) atomicAdd(&st->undecided, (unsigned long long)(sf + sg + sx));
+      wbase[0] = sf ? atomicAdd(&A.st->flagged, (unsigned long long)sf) : 0ull;
+      wbase[1] = sg ? atomicAdd(A.full_ctr, (unsigned long long)sg) : 0ull;
+      wbase[2] = sx ? atomicAdd(&A.st->flagged_full, (unsigned long long)sx) : 0ull;
+      if (A.count_undecided && (sf + sg + sx))
+        atomicAdd(&A.st->undecided, (unsigned long long)(sf + sg + sx));
     }
     __syncthreads();
     unsigned long long of = wbase[0], og = wbase[1], ob = wbase[2];
     for (int w = 0; w < wave; ++w) {
-      of += wcnt[0][w];
-      og += wcnt[1][w];
-      ob += wcnt[2][w];
+      of += wcnt[0 * WAVES + w];
+      og += wcnt[1 * WAVES + w];
+      ob += wcnt[2 * WAVES + w];
     }
     const unsigned long long below = (1ull << lane) - 1ull;
 #pragma unroll
     for (int cg = 0; cg < NCG; ++cg) {
       if ((fmask[cg] >> lane) & 1ull) {
         FlagEntry fe;
-        fe.row = (int)src_row[cg];
-        fe.cand2 = cand2v[cg];
-        fe.cand3 = cand3v[cg];
+        fe.row = (int)(src_row[cg] + A.list_off);
+        fe.cand2 = A.koff + cand2v[cg];
+        fe.cand3 = cand3v[cg] >= 0 ? A.koff + cand3v[cg] : -1;
         fe.pad = 0;
-        flags[of + __popcll(fmask[cg] & below)] = fe;
+        A.flags[of + __popcll(fmask[cg] & below)] = fe;
       }
-      if ((gmask[cg] >> lane) & 1ull) full_rows[og + __popcll(gmask[cg] & below)] = (int)src_row[cg];
-      if ((bmask[cg] >> lane) & 1ull) brute[ob + __popcll(bmask[cg] & below)] = (int)src_row[cg];
+      if ((gmask[cg] >> lane) & 1ull) A.full_rows[og + __popcll(gmask[cg] & below)] =
+          (int)(src_row[cg] + A.list_off);
+      if ((bmask[cg] >> lane) & 1ull) A.brute[ob + __popcll(bmask[cg] & below)] =
+          (int)(src_row[cg] + A.list_off);
       of += __popcll(fmask[cg]);
       og += __popcll(gmask[cg]);
       ob += __popcll(bmask[cg]);
     }
     __syncthreads();
   }
+}
+
+// MODE: 0 FP32, 1 BF16, 2 FP8 E4M3.  Persistent over the blocks of points.
+template <int MODE, int NKU, int NCG, int BN, int WAVES, int PF = 1>
+__global__ __launch_bounds__(WAVES * 64) void assign_kernel(AssignArgs A,
+                                                            const unsigned long long* row_count,
+                                                            const int* __restrict__ gate) {
+  if (gate && *gate) return;
+  using S = AssignShape<MODE, NKU, NCG, BN, WAVES>;
+  __shared__ __attribute__((aligned(1024))) unsigned char lds[2 * S::BUFB];
+  __shared__ __attribute__((aligned(16))) float hsh[2 * BN];
+  __shared__ int wcnt[3 * WAVES];
+  __shared__ unsigned long long wbase[3];
+  if (A.rows) A.npts = (int64_t)(*row_count);
+  const int64_t nblk = (A.npts + S::PPB - 1) / S::PPB;
+  for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x)
+    assign_block<MODE, NKU, NCG, BN, WAVES, PF>(A, blk, lds, hsh, wcnt, wbase);
 }
 
 // ---------------------------------------------------------------------------
@@ -544,13 +590,41 @@ int assign_tile_n(int prec, int d) {
 
 template <int MODE, int NKU, int NCG, int BN, int WAVES, int PF = 1>
 static hipError_t run_assign(hipStream_t s, const void* Xsrc, int64_t xs, int vec_ok,
-                             const uint8_t* sx8, int64_t n,
-                             const int* rows, const unsigned long long* row_count, int d, int dp,
+                             const uint8_t* sx8, int64_t n, const int* rows,
+                             const unsigned long long* row_count, int d, int dp,
                              const RowStats* rs, const void* Cq, const float* ch, int k, int kpad,
                              int ib, const CenterStats* cs, int32_t* label, float* d1, float* d2,
                              FlagEntry* flags, int* full_rows, unsigned long long* full_ctr,
                              int cascade_all, int* brute, LoopState* st, const int* gate,
                              int num_cus) {
+  AssignArgs A;
+  A.Xsrc = Xsrc;
+  A.xs = xs;
+  A.vec_ok = vec_ok;
+  A.sx8 = sx8;
+  A.npts = n;
+  A.rows = rows;
+  A.d = d;
+  A.dp = dp;
+  A.rs = rs;
+  A.Cq = Cq;
+  A.ch = ch;
+  A.k = k;
+  A.kpad = kpad;
+  A.ib = ib;
+  A.cs = cs;
+  A.label = label;
+  A.d1o = d1;
+  A.d2o = d2;
+  A.koff = 0;
+  A.list_off = 0;
+  A.flags = flags;
+  A.full_rows = full_rows;
+  A.full_ctr = full_ctr;
+  A.cascade_all = cascade_all;
+  A.brute = brute;
+  A.st = st;
+  A.count_undecided = rows == nullptr;
   const int64_t ppb = (int64_t)WAVES * 16 * NCG;
   int64_t blocks = (n + ppb - 1) / ppb;
   if (rows) {
@@ -559,9 +633,7 @@ static hipError_t run_assign(hipStream_t s, const void* Xsrc, int64_t xs, int ve
   }
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL((assign_kernel<MODE, NKU, NCG, BN, WAVES, PF>), dim3((unsigned)blocks),
-                     dim3(WAVES * 64), 0, s, Xsrc, xs, vec_ok, sx8, n, rows, row_count, d, dp, rs, Cq,
-                     ch, k, kpad, ib, cs, label, d1, d2, flags, full_rows, full_ctr, cascade_all,
-                     brute, st, gate);
+                     dim3(WAVES * 64), 0, s, A, row_count, gate);
   return hipGetLastError();
 }
 
@@ -814,6 +886,323 @@ hipError_t launch_recheck(hipStream_t s, const float* X, int64_t n, int d, int64
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(recheck_full_kernel, dim3((unsigned)blocks), dim3(256), 0, s, X, n, d, ldx,
                      C, k, label, d1, brute, st, gate);
+  return hipGetLastError();
+}
+
+}  // namespace kmx
+
+namespace kmx {
+
+// ---------------------------------------------------------------------------
+// Batched assignment: the instances of a batched Lloyd call, one persistent
+// launch per width group.  A work item is one block of points of one
+// instance; the instance's variant selects the tile shape (point groups per
+// wave, centers per tile), its own centers and statistics.  Items are ordered
+// by decreasing cost and taken round-robin by the workgroups.
+// ---------------------------------------------------------------------------
+constexpr int kBatchWaves = 8;
+// (variant id, BF16 units, point groups per wave, centers per tile); three
+// shapes per width group (BF16 units 1, 2, 3, 5, 9, 17).
+#define KMX_BG0(X) X(0, 1, 4, 64) X(1, 1, 4, 16) X(2, 1, 2, 32)
+#define KMX_BG1(X) X(3, 2, 4, 64) X(4, 2, 4, 16) X(5, 2, 2, 32)
+#define KMX_BG2(X) X(6, 3, 4, 64) X(7, 3, 4, 16) X(8, 3, 2, 32)
+#define KMX_BG3(X) X(9, 5, 4, 32) X(10, 5, 2, 16) X(11, 5, 2, 64)
+#define KMX_BG4(X) X(12, 9, 2, 64) X(13, 9, 2, 16) X(14, 9, 2, 32)
+#define KMX_BG5(X) X(15, 17, 2, 32) X(16, 17, 2, 16) X(17, 17, 1, 32)
+#define KMX_BVARIANTS(X) KMX_BG0(X) KMX_BG1(X) KMX_BG2(X) KMX_BG3(X) KMX_BG4(X) KMX_BG5(X)
+
+constexpr int bmax(int a, int b) { return a > b ? a : b; }
+template <int NKU, int NCG, int BN>
+constexpr int bbuf() {
+  return AssignShape<1, NKU, NCG, BN, kBatchWaves>::BUFB;
+}
+#define KMX_BUFMAX(ID, NKU, NCG, BN) bmax(bbuf<NKU, NCG, BN>(),
+#define KMX_CLOSE(ID, NKU, NCG, BN) )
+constexpr int kGroupBuf[6] = {
+    KMX_BG0(KMX_BUFMAX) 0 KMX_BG0(KMX_CLOSE), KMX_BG1(KMX_BUFMAX) 0 KMX_BG1(KMX_CLOSE),
+    KMX_BG2(KMX_BUFMAX) 0 KMX_BG2(KMX_CLOSE), KMX_BG3(KMX_BUFMAX) 0 KMX_BG3(KMX_CLOSE),
+    KMX_BG4(KMX_BUFMAX) 0 KMX_BG4(KMX_CLOSE), KMX_BG5(KMX_BUFMAX) 0 KMX_BG5(KMX_CLOSE)};
+#undef KMX_BUFMAX
+#undef KMX_CLOSE
+
+struct BVariant {
+  int nku, ncg, bn;
+};
+#define KMX_BV(ID, NKU, NCG, BN) {NKU, NCG, BN},
+static const BVariant kBVariants[] = {KMX_BVARIANTS(KMX_BV)};
+#undef KMX_BV
+
+static int batch_group(int d) {
+  const int u = units_for(KMX_BF16, d);
+  switch (u) {
+    case 1: return 0;
+    case 2: return 1;
+    case 3: return 2;
+    case 5: return 3;
+    case 9: return 4;
+    case 17: return 5;
+    default: return -1;
+  }
+}
+
+int batched_variants(int d) { return batch_group(d) < 0 ? 0 : 3; }
+int batched_variant_id(int d, int v) { return 3 * batch_group(d) + v; }
+int batched_variant_tile(int d, int v) { return kBVariants[batched_variant_id(d, v)].bn; }
+int batched_variant_ppb(int d, int v) {
+  return kBatchWaves * 16 * kBVariants[batched_variant_id(d, v)].ncg;
+}
+
+// One item of the batched assignment: the instance's rows and centers as
+// assign_block arguments.
+template <int NKU, int NCG, int BN>
+__device__ __forceinline__ void batched_block(const BatchInst& I, int blk,
+                                              FlagEntry* __restrict__ flags,
+                                              int* __restrict__ brute, LoopState* __restrict__ st,
+                                              int32_t* __restrict__ label, unsigned char* lds,
+                                              float* hsh, int* wcnt, unsigned long long* wbase) {
+  AssignArgs A;
+  A.Xsrc = I.xq + I.row0 * I.dp;
+  A.xs = I.dp;
+  A.vec_ok = 1;
+  A.sx8 = nullptr;
+  A.npts = I.n;
+  A.rows = nullptr;
+  A.d = I.d;
+  A.dp = I.dp;
+  A.rs = I.rs + I.row0;
+  A.Cq = I.cq + (int64_t)I.cpad0 * I.dp;
+  A.ch = nullptr;
+  A.k = I.k;
+  A.kpad = I.kpad;
+  A.ib = I.ib;
+  A.cs = I.cs;
+  A.label = label + I.grow0;
+  A.d1o = nullptr;
+  A.d2o = nullptr;
+  A.koff = I.koff;
+  A.list_off = I.grow0;
+  A.flags = flags;
+  A.full_rows = nullptr;
+  A.full_ctr = nullptr;
+  A.cascade_all = 0;
+  A.brute = brute;
+  A.st = st;
+  A.count_undecided = 1;
+  assign_block<1, NKU, NCG, BN, kBatchWaves, 1>(A, blk, lds, hsh, wcnt, wbase);
+}
+
+// Persistent over the items [begin, end) of one width group; each item's
+// instance selects one of the group's three tile shapes.  (Calls to
+// out-of-line per-shape functions gave wrong labels on gfx950; every shape
+// is inlined here.)
+template <int G>
+__global__ __launch_bounds__(kBatchWaves * 64) void assign_batched_kernel(
+    const BatchItem* __restrict__ items, int begin, int end, const BatchInst* __restrict__ insts,
+    FlagEntry* __restrict__ flags, int* __restrict__ brute, LoopState* __restrict__ st,
+    int32_t* __restrict__ label) {
+  __shared__ __attribute__((aligned(1024))) unsigned char lds[2 * kGroupBuf[G]];
+  __shared__ __attribute__((aligned(16))) float hsh[2 * 64];
+  __shared__ int wcnt[3 * kBatchWaves];
+  __shared__ unsigned long long wbase[3];
+  for (int it = begin + (int)blockIdx.x; it < end; it += (int)gridDim.x) {
+    const BatchItem item = items[it];
+    const BatchInst& I = insts[item.inst];
+#define KMX_BCASE(ID, NKU, NCG, BN)                                                           \
+  case ID:                                                                                    \
+    batched_block<NKU, NCG, BN>(I, item.blk, flags, brute, st, label, lds, hsh, wcnt, wbase); \
+    break;
+#define KMX_GROUP_CASES(GG, LIST)                         \
+  if constexpr (G == GG) {                                \
+    switch (I.variant) { LIST(KMX_BCASE) default: break; } \
+  }
+    KMX_GROUP_CASES(0, KMX_BG0)
+    KMX_GROUP_CASES(1, KMX_BG1)
+    KMX_GROUP_CASES(2, KMX_BG2)
+    KMX_GROUP_CASES(3, KMX_BG3)
+    KMX_GROUP_CASES(4, KMX_BG4)
+    KMX_GROUP_CASES(5, KMX_BG5)
+#undef KMX_GROUP_CASES
+#undef KMX_BCASE
+  }
+}
+
+int batched_group(int d) { return batch_group(d); }
+
+hipError_t launch_assign_batched(hipStream_t s, int group, const BatchItem* items, int begin,
+                                 int end, const BatchInst* insts, FlagEntry* flags, int* brute,
+                                 LoopState* st, int32_t* label, int grid) {
+  const int nitems = end - begin;
+  if (nitems <= 0) return hipSuccess;
+  if (grid < 1) grid = 1;
+  if (grid > nitems) grid = nitems;
+  switch (group) {
+#define KMX_G(G)                                                                                \
+  case G:                                                                                       \
+    hipLaunchKernelGGL(assign_batched_kernel<G>, dim3((unsigned)grid), dim3(kBatchWaves * 64), \
+                       0, s, items, begin, end, insts, flags, brute, st, label);               \
+    return hipGetLastError();
+    KMX_G(0)
+    KMX_G(1)
+    KMX_G(2)
+    KMX_G(3)
+    KMX_G(4)
+    KMX_G(5)
+#undef KMX_G
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+// Re-check of a batched assignment: list rows are global; the bucket (pair
+// entries) or the instance (every-center entries) is found by binary search.
+__device__ __forceinline__ int find_bucket(const BatchBucket* __restrict__ b, int nb, int64_t g) {
+  int lo = 0, hi = nb - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (b[mid].grow0 <= g) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ int find_inst(const BatchInst* __restrict__ in, int ni, int64_t g) {
+  int lo = 0, hi = ni - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (in[mid].grow0 <= g) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(256) void recheck_pair_batched_kernel(
+    const BatchBucket* __restrict__ buckets, int nb, int32_t* __restrict__ label,
+    const FlagEntry* __restrict__ flags, const LoopState* __restrict__ st, int64_t nrows) {
+  const unsigned long long cnt = st->flagged;
+  const int lane = threadIdx.x & 63;
+  const int64_t gw = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t nw = (int64_t)gridDim.x * 4;
+  for (int64_t e = gw; e < (int64_t)cnt; e += nw) {
+    const FlagEntry fe = flags[e];
+    const int64_t row = fe.row;
+    if (row < 0 || row >= nrows) continue;
+    const BatchBucket B = buckets[find_bucket(buckets, nb, row)];
+    const int d = B.d;
+    const float tol = (float)((d + 63) / 64 + 10) * 5.9604645e-8f;
+    const float* x = B.X + (row - B.grow0) * d;
+    int cj[3];
+    cj[0] = min(max(label[row], 0), B.K - 1);
+    cj[1] = min(max(fe.cand2, 0), B.K - 1);
+    cj[2] = fe.cand3 >= 0 ? min(fe.cand3, B.K - 1) : -1;
+    const int nc = (cj[2] >= 0) ? 3 : 2;
+    float p[3];
+    for (int q = 0; q < nc; ++q) p[q] = wave_plain_dist(x, B.C + (int64_t)cj[q] * d, d, lane);
+    int b = 0;
+    for (int q = 1; q < nc; ++q)
+      if (p[q] < p[b] || (p[q] == p[b] && cj[q] < cj[b])) b = q;
+    bool sure = true;
+    for (int q = 0; q < nc; ++q)
+      if (q != b && !(p[q] - p[b] > tol * (p[q] + p[b]))) sure = false;
+    int best = cj[b];
+    if (!sure) {
+      float bh = 0.f, bl = 0.f;
+      for (int q = 0; q < nc; ++q) {
+        float h, l;
+        exact_dist(x, B.C + (int64_t)cj[q] * d, d, lane, h, l);
+        if (q == 0 || df_less(h, l, bh, bl) || (h == bh && l == bl && cj[q] < best)) {
+          bh = h;
+          bl = l;
+          best = cj[q];
+        }
+      }
+    }
+    if (lane == 0) label[row] = best;
+  }
+}
+
+// One workgroup per row needing every center of its instance.
+__global__ __launch_bounds__(256) void recheck_full_batched_kernel(
+    const BatchInst* __restrict__ insts, int ni, int32_t* __restrict__ label,
+    const int* __restrict__ brute, const LoopState* __restrict__ st, int64_t nrows) {
+  __shared__ float redf[4];
+  __shared__ float redh[4], redl[4];
+  __shared__ int redj[4];
+  const unsigned long long cnt = st->flagged_full;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int64_t e = blockIdx.x; e < (int64_t)cnt; e += gridDim.x) {
+    const int64_t row = brute[e];
+    if (row < 0 || row >= nrows) continue;   // uniform across the block
+    const BatchInst& I = insts[find_inst(insts, ni, row)];
+    const int d = I.d;
+    const float gam = (float)(d + 3) * 5.9604645e-8f;
+    const float* x = I.X + (I.row0 + (row - I.grow0)) * d;
+    const float* C = I.C + (int64_t)I.koff * d;
+    const bool vec = ((((uintptr_t)x) & 15) == 0) && ((((uintptr_t)C) & 15) == 0) && (d % 4 == 0);
+    float m = __builtin_inff();
+    for (int j = tid; j < I.k; j += 256) m = fminf(m, plain_dist(x, C + (int64_t)j * d, d, vec));
+#pragma unroll
+    for (int s2 = 32; s2 >= 1; s2 >>= 1) m = fminf(m, __shfl_xor(m, s2, 64));
+    if (lane == 0) redf[wv] = m;
+    __syncthreads();
+    m = fminf(fminf(redf[0], redf[1]), fminf(redf[2], redf[3]));
+    const float thr = m * (1.0f + gam) / (1.0f - gam) * 1.0001f + 1e-30f;
+    float bh = __builtin_inff(), bl = 0.f;
+    int best = 0x7FFFFFFF;
+    for (int j = tid; j < I.k; j += 256) {
+      const float* cj = C + (int64_t)j * d;
+      if (plain_dist(x, cj, d, vec) <= thr) {
+        float s = 0.f, ee = 0.f;
+        for (int q = 0; q < d; ++q) df_acc_sqdiff(x[q], cj[q], s, ee);
+        float h, l;
+        df_norm(s, ee, h, l);
+        if (df_less(h, l, bh, bl) || (h == bh && l == bl && j < best)) {
+          bh = h;
+          bl = l;
+          best = j;
+        }
+      }
+    }
+#pragma unroll
+    for (int s2 = 32; s2 >= 1; s2 >>= 1) {
+      const float oh = __shfl_xor(bh, s2, 64), ol = __shfl_xor(bl, s2, 64);
+      const int oj = __shfl_xor(best, s2, 64);
+      if (df_less(oh, ol, bh, bl) || (oh == bh && ol == bl && oj < best)) {
+        bh = oh;
+        bl = ol;
+        best = oj;
+      }
+    }
+    if (lane == 0) {
+      redh[wv] = bh;
+      redl[wv] = bl;
+      redj[wv] = best;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      for (int w = 1; w < 4; ++w) {
+        if (df_less(redh[w], redl[w], bh, bl) ||
+            (redh[w] == bh && redl[w] == bl && redj[w] < best)) {
+          bh = redh[w];
+          bl = redl[w];
+          best = redj[w];
+        }
+      }
+      if (best < I.k) label[row] = I.koff + best;
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_recheck_batched(hipStream_t s, const BatchBucket* buckets, int nbuckets,
+                                  const BatchInst* insts, int ninst, int32_t* label,
+                                  const FlagEntry* flags, const int* brute, const LoopState* st,
+                                  int64_t nrows, int num_cus) {
+  hipLaunchKernelGGL(recheck_pair_batched_kernel, dim3((unsigned)(num_cus * 8)), dim3(256), 0, s,
+                     buckets, nbuckets, label, flags, st, nrows);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(recheck_full_batched_kernel, dim3((unsigned)(num_cus * 2)), dim3(256), 0, s,
+                     insts, ninst, label, brute, st, nrows);
   return hipGetLastError();
 }
 

@@ -330,9 +330,13 @@ kmx_status kmx_destroy(kmx_ctx* ctx) {
       &ctx->hist,      &ctx->fb_rows,  &ctx->keys,       &ctx->cdist,      &ctx->nbr,
       &ctx->nbd,       &ctx->fbh,      &ctx->xq8,        &ctx->sx8,        &ctx->rowstats8,
       &ctx->xstats8,   &ctx->cq8,      &ctx->ch8,        &ctx->hd8,        &ctx->cstats8,
-      &ctx->full_rows2};
+      &ctx->full_rows2, &ctx->bX,       &ctx->bXq,        &ctx->brs,        &ctx->bw,
+      &ctx->bC,        &ctx->bCq,      &ctx->bhd,        &ctx->bcs,        &ctx->blab,
+      &ctx->bitems,    &ctx->binsts,   &ctx->bbuckets,   &ctx->bcinst,     &ctx->bxstats,
+      &ctx->btermC,    &ctx->btermMu,  &ctx->bW,         &ctx->bcost};
   for (kmx::Buf* b : bufs)
     if (b->p) (void)hipFree(b->p);
+  if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   for (auto& r : ctx->recs) {
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);

@@ -5,7 +5,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/kmx.h"
@@ -64,6 +66,46 @@ struct FlagEntry {
   int pad;
 };
 
+// Batched assignment (many independent instances, one launch).  Instances of
+// equal d form a bucket whose rows, centers and labels are concatenated;
+// labels and list entries use bucket-global center indices and global rows.
+struct BatchInst {
+  int64_t row0;        // first row of the instance in its bucket
+  int64_t grow0;       // first row in the global numbering (all buckets)
+  int n, d, dp, k;
+  int kpad;            // padded center count (multiple of the variant's tile)
+  int koff;            // first center of the instance in its bucket
+  int kg0;             // first center in the global numbering (all buckets)
+  int cpad0;           // first padded center row in the bucket's quantized centers
+  int variant;         // tile shape, index into the batched kernel's variant list
+  int ib;              // index bits of the packed keys
+  int bucket;
+  int pad_;
+  const uint16_t* xq;  // bucket BF16 rows (dp per row)
+  const RowStats* rs;  // bucket row statistics
+  uint16_t* cq;        // bucket quantized centers (dp per padded center)
+  double* hd;          // per padded center (global numbering of padded centers)
+  CenterStats* cs;     // this instance's statistics
+  const float* X;      // bucket FP32 rows (d per row)
+  const float* C;      // bucket FP32 centers (d per center)
+  const unsigned* xq_max;  // bucket max ||x~||
+  int hd0;             // first padded center in the global numbering of padded centers
+  int pad2_;
+};
+
+struct BatchItem {
+  int inst;
+  int blk;             // block of points within the instance
+};
+
+struct BatchBucket {
+  int64_t grow0;       // first global row
+  int64_t n;
+  int d, K;            // width, centers of all its instances
+  const float* X;      // FP32 rows (d per row)
+  const float* C;      // FP32 centers (d per center)
+};
+
 enum TimingClass {
   T_PREP = 0, T_ASSIGN = 1, T_RECHECK = 2, T_SORT = 3, T_REDUCE = 4,
   T_FINAL = 5, T_SEED = 6, T_OTHER = 7, T_ROUTER = 8, T_CERT = 9, T_TRAIN = 10,
@@ -92,6 +134,29 @@ constexpr int kRouterM = 16;        // proposals per point
 constexpr int kRouterMaxK = 4096;   // largest k the router supports
 constexpr int kNbrL = 32;           // sorted neighbours kept per center
 constexpr int kRouterMaxBatch = 65536;  // largest training batch
+
+// batched (k_assign.hip, k_batch.hip)
+int batched_variants(int d);                  // number of tile shapes for width d
+int batched_variant_tile(int d, int v);       // centers per tile of variant v
+int batched_variant_ppb(int d, int v);        // points per block of variant v
+int batched_variant_id(int d, int v);         // variant index over all groups
+int batched_group(int d);                     // width group (one kernel per group)
+hipError_t launch_assign_batched(hipStream_t s, int group, const BatchItem* items, int begin,
+                                 int end, const BatchInst* insts, FlagEntry* flags, int* brute,
+                                 LoopState* st, int32_t* label, int grid);
+hipError_t launch_recheck_batched(hipStream_t s, const BatchBucket* buckets, int nbuckets,
+                                  const BatchInst* insts, int ninst, int32_t* label,
+                                  const FlagEntry* flags, const int* brute, const LoopState* st,
+                                  int64_t nrows, int num_cus);
+hipError_t launch_batch_reset(hipStream_t s, const BatchInst* insts, int ninst, LoopState* st,
+                              unsigned* work_ctr);
+hipError_t launch_batch_prep_centers(hipStream_t s, const BatchInst* insts, const int* cinst,
+                                     int npad);
+hipError_t launch_batch_cost(hipStream_t s, const BatchInst* insts, int ninst,
+                             const double* termC, double* cost, int stride, LoopState* st,
+                             int advance);
+hipError_t launch_batch_labels(hipStream_t s, const int32_t* glabel, int64_t grow0, int n,
+                               int koff, int32_t* out);
 
 // projection (k_project.hip)
 hipError_t launch_project(hipStream_t s, const float* X, int64_t rows, int d_in, int64_t ldx,
@@ -175,6 +240,11 @@ struct kmx_ctx {
   kmx::Buf D2, chosen, seed_part, seed_ctr;
   kmx::Buf scratch_c, hist;
   kmx::Buf fb_rows, keys, cdist, nbr, nbd, fbh;   // routed assignment
+  // batched Lloyd: concatenated instances and their descriptors
+  kmx::Buf bX, bXq, brs, bw, bC, bCq, bhd, bcs, blab, bitems, binsts, bbuckets, bcinst, bxstats;
+  kmx::Buf btermC, btermMu, bW, bcost;
+  hipStream_t cap_stream = nullptr;                // stream the batched iteration is captured on
+  std::map<std::pair<int, int>, int> tune;         // (d, k class) -> tile-shape variant
 
   // timing
   bool timing = false;
@@ -239,6 +309,29 @@ hipError_t launch_seed_round(hipStream_t s, const float* X, int64_t n, int d, in
                              const float* w, int r, uint64_t seed, double* D2,
                              uint8_t* chosen, double* part, unsigned int* ctr,
                              float* C_out, int64_t* idx_out);
+
+// batched (k_assign.hip, k_batch.hip)
+int batched_variants(int d);                  // number of tile shapes for width d
+int batched_variant_tile(int d, int v);       // centers per tile of variant v
+int batched_variant_ppb(int d, int v);        // points per block of variant v
+int batched_variant_id(int d, int v);         // variant index over all groups
+int batched_group(int d);                     // width group (one kernel per group)
+hipError_t launch_assign_batched(hipStream_t s, int group, const BatchItem* items, int begin,
+                                 int end, const BatchInst* insts, FlagEntry* flags, int* brute,
+                                 LoopState* st, int32_t* label, int grid);
+hipError_t launch_recheck_batched(hipStream_t s, const BatchBucket* buckets, int nbuckets,
+                                  const BatchInst* insts, int ninst, int32_t* label,
+                                  const FlagEntry* flags, const int* brute, const LoopState* st,
+                                  int64_t nrows, int num_cus);
+hipError_t launch_batch_reset(hipStream_t s, const BatchInst* insts, int ninst, LoopState* st,
+                              unsigned* work_ctr);
+hipError_t launch_batch_prep_centers(hipStream_t s, const BatchInst* insts, const int* cinst,
+                                     int npad);
+hipError_t launch_batch_cost(hipStream_t s, const BatchInst* insts, int ninst,
+                             const double* termC, double* cost, int stride, LoopState* st,
+                             int advance);
+hipError_t launch_batch_labels(hipStream_t s, const int32_t* glabel, int64_t grow0, int n,
+                               int koff, int32_t* out);
 
 // projection (k_project.hip)
 hipError_t launch_project(hipStream_t s, const float* X, int64_t rows, int d_in, int64_t ldx,

@@ -31,6 +31,13 @@ _i64 = ctypes.c_int64
 _i32 = ctypes.c_int32
 
 
+class Problem(ctypes.Structure):
+    """kmx_problem: one instance of a batched call (device pointers)."""
+    _fields_ = [("X", ctypes.c_void_p), ("n", ctypes.c_int64), ("d", ctypes.c_int32),
+                ("ldx", ctypes.c_int64), ("w", ctypes.c_void_p), ("C", ctypes.c_void_p),
+                ("k", ctypes.c_int32), ("label", ctypes.c_void_p)]
+
+
 class KmxError(RuntimeError):
     def __init__(self, status: int, message: str):
         super().__init__(f"kmx status {status}: {message}")
@@ -60,6 +67,9 @@ def lib():
         "kmx_timing": [_vp, ctypes.c_int, ctypes.c_int],
         "kmx_assign_stats": [_vp, _vp, _vp, _vp],
         "kmx_timing_read": [_vp, ctypes.c_int, _vp, _vp],
+        "kmx_lloyd_batched": [_vp, _vp, _i32, _i32, ctypes.c_int, _vp],
+        "kmx_batched_autotune": [_vp, _vp, _i32, ctypes.c_int, ctypes.c_char_p, _vp],
+        "kmx_batched_tiles": [_vp, _i32, _i32, _vp, _vp],
         "kmx_project": [_vp, _vp, _i64, _i32, _i64, _vp, _i32, _vp, _i64],
         "kmx_router_create": [_vp, _i32, _i32, ctypes.c_uint64, ctypes.POINTER(_vp)],
         "kmx_router_destroy": [_vp, _vp],
@@ -224,6 +234,51 @@ class Context:
         cnt = (ctypes.c_int64 * nc)()
         _check(lib().kmx_timing_read(self._p, nc, ms, cnt), self._p)
         return {name: (ms[i], cnt[i]) for i, name in enumerate(TIMING_CLASSES)}
+
+    # ---- batched instances ----------------------------------------------------
+    def _problems(self, problems, labels=True, inplace=False):
+        arr = (Problem * len(problems))()
+        keep = []
+        for i, p in enumerate(problems):
+            X, C0 = p["X"], p["C"]
+            w = p.get("w")
+            n, d, ldx = _rows(X)
+            k = _centers(C0, d)
+            _vec(w, n)
+            C = C0 if inplace else C0.clone()
+            lab = torch.empty(n, dtype=torch.int32, device=X.device) if labels else None
+            keep.append((C, lab))
+            arr[i] = Problem(X.data_ptr(), n, d, ldx, w.data_ptr() if w is not None else None,
+                             C.data_ptr(), k, lab.data_ptr() if lab is not None else None)
+        return arr, keep
+
+    def lloyd_batched(self, problems, iters: int, prec="bf16", labels: bool = True,
+                      inplace: bool = False):
+        """problems: list of dicts with X (n x d), C (k x d initial centers), optional w.
+        Returns [(C, labels, cost_hist)] in the same order."""
+        arr, keep = self._problems(problems, labels, inplace)
+        hist = (ctypes.c_double * (len(problems) * (iters + 1)))()
+        self._sync_stream()
+        _check(lib().kmx_lloyd_batched(self._p, arr, len(problems), iters, _PREC[prec], hist),
+               self._p)
+        s = iters + 1
+        return [(keep[i][0], keep[i][1], [hist[i * s + t] for t in range(s)])
+                for i in range(len(problems))]
+
+    def batched_autotune(self, problems, cache_path=None, prec="bf16"):
+        """Tile shapes for the batched assignment; returns True when read from the cache."""
+        arr, _ = self._problems(problems, labels=False)
+        loaded = ctypes.c_int32(0)
+        self._sync_stream()
+        _check(lib().kmx_batched_autotune(self._p, arr, len(problems), _PREC[prec],
+                                          cache_path.encode() if cache_path else None,
+                                          ctypes.byref(loaded)), self._p)
+        return bool(loaded.value)
+
+    def batched_tiles(self, d: int, k: int):
+        t, p = ctypes.c_int32(0), ctypes.c_int32(0)
+        _check(lib().kmx_batched_tiles(self._p, d, k, ctypes.byref(t), ctypes.byref(p)), self._p)
+        return int(t.value), int(p.value)
 
     def project(self, X, V, out=None):
         """Y = X V for a chunk of rows (kmx_project); V is d_in x d_out float32."""

@@ -204,3 +204,18 @@ def lowrank_chunk_device(rows: int, F_dev, seed: int = 0, chunk: int = 0, noise:
     X = Z @ F_dev
     X.add_(torch.randn(rows, F_dev.shape[1], generator=g, device=device), alpha=noise)
     return X
+
+
+def instance_device(desc, device="cuda"):
+    """Same family as ``instance`` with the noise and the weights drawn on the
+    device by torch's seeded Philox generator (means from the host RNG)."""
+    import torch
+    rng = _rng(list(desc["seed"]))
+    n, d, k = desc["n"], desc["d"], desc["k"]
+    means = torch.from_numpy(rng.uniform(-10, 10, size=(k, d)).astype(np.float32)).to(device)
+    g = torch.Generator(device=device)
+    g.manual_seed(int(rng.integers(0, 2 ** 62)))
+    comp = torch.arange(n, device=device) % k
+    X = means[comp] + torch.randn(n, d, generator=g, device=device)
+    w = torch.exp(torch.randn(n, generator=g, device=device))
+    return X.contiguous(), w.contiguous()

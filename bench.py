@@ -91,6 +91,76 @@ def cpu_baseline(X_host_rows, C_host, n_full, seconds_target=10.0):
             "sec_per_iter": sec_per_iter}
 
 
+def batched_main(args):
+    """Many uneven weighted instances: n ~ U[1e3, 2e5], d in {16..512}, k ~ U[5, 200],
+    log-normal(0,1) weights, Gaussian-mixture points; weighted k-means++ per
+    instance, tile shapes from the autotuner, then the batched Lloyd loop (one
+    assignment launch per width group, iteration replayed as a graph) against
+    the same iterations run instance by instance."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1502_04265_amd import kmx
+
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    ctx = kmx.Context(0)
+    descs = synth.uneven_instances(args.instances, seed=0)
+    log(f"[bench] generating {len(descs)} instances, sum n = {sum(d['n'] for d in descs)}")
+    probs = []
+    t0 = time.perf_counter()
+    for i, desc in enumerate(descs):
+        X, w = synth.instance_device(desc, device=dev)
+        C0, _ = ctx.seed(X, desc["k"], w=w, rng_seed=i)
+        probs.append({"X": X, "C": C0, "w": w})
+    torch.cuda.synchronize()
+    seed_s = time.perf_counter() - t0
+    cache = os.path.join(ROOT, "gpurun_out", "batched_tiles.jsonl")
+    os.makedirs(os.path.dirname(cache), exist_ok=True)
+    t0 = time.perf_counter()
+    loaded = ctx.batched_autotune(probs, cache)
+    tune_s = time.perf_counter() - t0
+    log(f"[bench] seeding {seed_s:.2f} s, autotune {tune_s:.2f} s (cache {'hit' if loaded else 'written'})")
+    ctx.lloyd_batched(probs, 1, labels=False)                   # warmup (graph, buffers)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = ctx.lloyd_batched(probs, args.steps, labels=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    log(f"[bench] batched: {wall * 1e3 / args.steps:.3f} ms per iteration of all instances")
+    t0 = time.perf_counter()
+    seq = []
+    for p in probs:
+        seq.append(ctx.lloyd(p["X"], p["C"], args.steps, w=p["w"], prec="bf16", labels=True))
+    torch.cuda.synchronize()
+    wseq = time.perf_counter() - t0
+    log(f"[bench] one by one: {wseq * 1e3 / args.steps:.3f} ms per iteration of all instances")
+    same = all(torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]) for a, b in zip(res, seq))
+    rel = max(abs(a[2][-1] - b[2][-1]) / max(b[2][-1], 1e-300) for a, b in zip(res, seq))
+    flops = sum(2.0 * d["n"] * d["k"] * d["d"] for d in descs)
+    tiles = {}
+    for d in descs:
+        t, ppb = ctx.batched_tiles(d["d"], d["k"])
+        tiles[f"d={d['d']},k<={24 if d['k'] <= 24 else (96 if d['k'] <= 96 else 200)}"] = [t, ppb]
+    out = {
+        "metric": "batched Lloyd: iterations/s of all instances together",
+        "value": args.steps / wall, "unit": "iter/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": 1, "ms_per_step": wall * 1e3 / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": f"{len(descs)} weighted instances, n U[1e3,2e5], d in "
+                               f"{{16..512}}, k U[5,200], log-normal weights",
+                   "sum_n": sum(d["n"] for d in descs), "sum_k": sum(d["k"] for d in descs)},
+        "one_by_one": {"iter_per_s": args.steps / wseq, "ms_per_step": wseq * 1e3 / args.steps},
+        "speedup_vs_one_by_one": wseq / wall,
+        "identical_to_one_by_one": bool(same), "max_final_cost_rel_diff": rel,
+        "assign_flops_per_iteration": flops,
+        "whole_iteration_tflops": flops / (wall / args.steps) / 1e12,
+        "tiles": tiles, "seed_s": seed_s, "autotune_s": tune_s,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def streamed_main(args):
     """Streamed high-dimensional workload: chunks generated on the device,
     projected onto a basis from a randomized SVD of a sample (host), then
@@ -197,7 +267,10 @@ def main():
                     help="plain FP32 iterations whose labels train the router")
     ap.add_argument("--batch", type=int, default=8192, help="router training batch")
     ap.add_argument("--lr", type=float, default=1e-3, help="router learning rate (Adam)")
-    ap.add_argument("--workload", default="router", choices=sorted(WORKLOADS) + ["streamed"])
+    ap.add_argument("--workload", default="router",
+                    choices=sorted(WORKLOADS) + ["streamed", "batched"])
+    ap.add_argument("--instances", type=int, default=256,
+                    help="batched workload: number of instances")
     ap.add_argument("--chunks", type=int, default=None,
                     help="streamed workload: number of chunks (default: all of n)")
     ap.add_argument("--fp32-steps", type=int, default=None,
@@ -223,6 +296,8 @@ def main():
 
     if args.workload == "streamed":
         return streamed_main(args)
+    if args.workload == "batched":
+        return batched_main(args)
     wl = WORKLOADS[args.workload]
     n, d, k = wl["n"], wl["d"], wl["k"]
     dev = "cuda:0"
@@ -242,7 +317,7 @@ def main():
         C = X[:k].contiguous() + 0.05 * torch.randn(k, d, device=dev, generator=g)
         cal = torch.empty(1 << 28, dtype=torch.float32, device=dev)      # 1 GiB
         dst = torch.empty_like(cal)
-        for prec in ("bf16", "fp32"):
+        for prec in ("bf16", "fp8", "fp32"):
             ctx.assign(X, C, prec=prec, want_d=False)
             for _ in range(args.steps):
                 ctx.assign(X, C, prec=prec, want_d=False)

@@ -6,10 +6,9 @@
 // so the closest center maximizes x.c_j - h_j.  The kernel forms the positive
 // score t_j = x~.c~_j - h_j + O (x~, c~ the GEMM operands: BF16 copies, or the
 // FP32 values), whose float bits order like unsigned integers.
-//   BF16: the rows of X carry three extra columns equal to -1 and the centers
-//     carry h_j - O split into three BF16 terms, so the MFMA accumulator *is*
-//     t_j; O is one offset per assignment (max row norm times max center norm
-//     plus max h).
+//   BF16: the accumulator starts at O - h_j (rounded to FP32) and the MFMAs
+//     add x~.c~_j, so it ends at t_j; O is one offset per assignment (max row
+//     norm times max center norm plus max h).
 //   FP32: t_j = (acc - h_j) + o_x with a per-row offset o_x, clamped at 0.
 //   FP8 (E4M3, per-row power-of-two scales 2^e_x, one scale 2^e_c for all
 //     centers): the scaled MFMA applies 2^(e_x + e_c) to each product, so the
@@ -21,8 +20,8 @@
 //
 // Soundness.  For every center |t_j - (x.c_j - h_j + O)| <= E(x), where E
 // covers the FP32 accumulation (gamma_K sum |x~_i c~_ji|), the quantization of
-// both operands (||x - x~|| ||c~|| + ||x|| ||c - c~||), the rounding of h_j and
-// of the epilogue, and the key truncation.  If t_1 - t_2 > 2E the top key's
+// both operands (||x - x~|| ||c~|| + ||x|| ||c - c~||), the rounding of the
+// start value O - h_j and of the epilogue, and the key truncation.  If t_1 - t_2 > 2E the top key's
 // center is the exact argmin.  Otherwise the row is flagged: the centers whose
 // score lies within 2E of the top can win; when they are among the listed two
 // (BF16: three) the short re-check compares them.  Otherwise the row needs
@@ -114,14 +113,13 @@ struct AssignShape {
 // loop over every center tile, the merge of the four lanes of a point, the
 // decision and the re-check list entries.  lds holds two tile buffers, hsh
 // two rows of BN per-center values, wcnt 3 * WAVES counters, wbase 3 bases.
-template <int MODE, int NKU, int NCG, int BN, int WAVES, int PF>
+template <int MODE, int NKU, int NCG, int BN, int WAVES, int PF, bool EP>
 __device__ __forceinline__ void assign_block(const AssignArgs& A, int64_t blk,
                                              unsigned char* lds, float* hsh, int* wcnt,
                                              unsigned long long* wbase) {
   constexpr bool BF16 = (MODE == 1);
   constexpr bool F8 = (MODE == 2);
   constexpr bool PK = (MODE != 0);       // packed keys (BF16, FP8)
-  constexpr bool HS = (MODE != 1);       // per-center values staged with each tile
   constexpr int NF = F8 ? 2 : 1;         // 16-byte fragments per lane and unit
   constexpr int NT = WAVES * 64;
   constexpr int RB = BN / 16;
@@ -161,15 +159,19 @@ __device__ __forceinline__ void assign_block(const AssignArgs& A, int64_t blk,
       src_row[cg] = r;
       sxe[cg] = 127;
       if (F8 && pv) sxe[cg] = (int)A.sx8[r];
+      // packed operands: invalid points read row 0 (always present) and are
+      // zeroed afterwards, so the loads issue without branches
+      const int64_t rl = pv ? r : 0;
 #pragma unroll
       for (int ku = 0; ku < NKU * NF; ++ku) {
         u32x4_t v = {0u, 0u, 0u, 0u};
         if (F8) {
-          if (pv)
-            v = *(const u32x4_t*)((const uint8_t*)A.Xsrc + r * A.xs + (ku >> 1) * 128 + grp * 32 +
-                                  (ku & 1) * 16);
+          v = *(const u32x4_t*)((const uint8_t*)A.Xsrc + rl * A.xs + (ku >> 1) * 128 + grp * 32 +
+                                (ku & 1) * 16);
+          if (!pv) v = (u32x4_t){0u, 0u, 0u, 0u};
         } else if (BF16) {
-          if (pv) v = *(const u32x4_t*)((const uint16_t*)A.Xsrc + r * A.xs + ku * 32 + grp * 8);
+          v = *(const u32x4_t*)((const uint16_t*)A.Xsrc + rl * A.xs + ku * 32 + grp * 8);
+          if (!pv) v = (u32x4_t){0u, 0u, 0u, 0u};
         } else {
           const int e0 = ku * 16 + grp * 4;
           const float* src = (const float*)A.Xsrc + r * A.xs + e0;
@@ -216,10 +218,10 @@ __device__ __forceinline__ void assign_block(const AssignArgs& A, int64_t blk,
             (const void*)src, (__attribute__((address_space(3))) void*)(&lds[buf * BUFB + c * 1024]), 16,
             0, 0);
       }
-      if (HS && tid < BN) hstage = A.ch[tile * BN + tid];
+      if (tid < BN) hstage = A.ch[tile * BN + tid];
     };
     auto finish_tile = [&](int buf) {
-      if (HS && tid < BN) hsh[buf * BN + tid] = hstage;
+      if (tid < BN) hsh[buf * BN + tid] = hstage;
       __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
     };
 
@@ -227,15 +229,35 @@ __device__ __forceinline__ void assign_block(const AssignArgs& A, int64_t blk,
     finish_tile(0);
     __syncthreads();
 
+    // EP (packed keys only): the keys of tile t - 1 are inserted while the
+    // MFMAs of tile t run, a slice after each unit, so the matrix core and
+    // the vector ALU overlap within a wave.  Inserting key 0 changes nothing
+    // (every kept key is >= 0), which disables the slices of the first tile.
+    constexpr bool PIPE = EP && PK;
+    constexpr int NSC = NCG * RB * 4;    // keys per lane and tile
+    f32x4_t accp[NCG][RB];
+#pragma unroll
+    for (int cg = 0; cg < NCG; ++cg)
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) accp[cg][rb] = (f32x4_t){0.f, 0.f, 0.f, 0.f};
+    auto insert_prev = [&](int sidx, unsigned ibase_p, unsigned pm) {
+      const int rb = sidx / (4 * NCG), i = (sidx / NCG) % 4, cg = sidx % NCG;
+      const unsigned idx = ibase_p - (unsigned)(rb * 16 + i);
+      const unsigned key = ((__float_as_uint(accp[cg][rb][i]) & ~mask) | idx) & pm;
+      top4_insert(key, v1[cg], v2[cg], v3[cg], v4[cg]);
+    };
+
     for (int t = 0; t < ntiles; ++t) {
       const int buf = t & 1;
       if (t + 1 < ntiles) issue_tile(t + 1, buf ^ 1);
+      const unsigned ibase_p = mask - (unsigned)((t - 1) * BN + grp * 4);
+      const unsigned pm = (t > 0) ? 0xFFFFFFFFu : 0u;
 
       f32x4_t acc[NCG][RB];
 #pragma unroll
       for (int rb = 0; rb < RB; ++rb) {
         f32x4_t a0 = {0.f, 0.f, 0.f, 0.f};
-        if (F8) a0 = *(const f32x4_t*)(&hsh[buf * BN + rb * 16 + grp * 4]);
+        if (PK) a0 = *(const f32x4_t*)(&hsh[buf * BN + rb * 16 + grp * 4]);
 #pragma unroll
         for (int cg = 0; cg < NCG; ++cg) acc[cg][rb] = a0;
       }
@@ -258,6 +280,11 @@ __device__ __forceinline__ void assign_block(const AssignArgs& A, int64_t blk,
               acc[cg][rb] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
                   a, b, acc[cg][rb], 0, 0, 0, cexp, 0, sxe[cg]);
             }
+          }
+          if constexpr (PIPE) {
+#pragma unroll
+            for (int sidx = 0; sidx < NSC; ++sidx)
+              if (sidx * NKU / NSC == ku) insert_prev(sidx, ibase_p, pm);
           }
         }
       } else {
@@ -298,11 +325,21 @@ __device__ __forceinline__ void assign_block(const AssignArgs& A, int64_t blk,
             }
           }
         }
+        if constexpr (PIPE) {
+#pragma unroll
+          for (int sidx = 0; sidx < NSC; ++sidx)
+            if (sidx * NKU / NSC == ku) insert_prev(sidx, ibase_p, pm);
+        }
       }
       }
 
-      // ---- epilogue: running top-3 ----
-      if constexpr (PK) {
+      // ---- epilogue: running top-4 (BF16, FP8) or top-3 ----
+      if constexpr (PIPE) {
+#pragma unroll
+        for (int cg = 0; cg < NCG; ++cg)
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb) accp[cg][rb] = acc[cg][rb];
+      } else if constexpr (PK) {
         const unsigned ibase = mask - (unsigned)(t * BN + grp * 4);
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
@@ -341,6 +378,11 @@ __device__ __forceinline__ void assign_block(const AssignArgs& A, int64_t blk,
 
       if (t + 1 < ntiles) finish_tile(buf ^ 1);
       __syncthreads();
+    }
+    if constexpr (PIPE) {
+      const unsigned ibase_p = mask - (unsigned)((ntiles - 1) * BN + grp * 4);
+#pragma unroll
+      for (int sidx = 0; sidx < NSC; ++sidx) insert_prev(sidx, ibase_p, 0xFFFFFFFFu);
     }
 
     // ---- merge the four lanes that hold the same point ----
@@ -403,7 +445,9 @@ __device__ __forceinline__ void assign_block(const AssignArgs& A, int64_t blk,
           const unsigned hi = ~mask;
           off = Og;
           if constexpr (BF16) {
-            E = gam * (rw.nxq * cqm + Og) + rw.rx * cqm + rw.nx * rcm + 3.0f * u * Og +
+            // dp + 1 accumulation steps (the products and the start value),
+            // both quantizations, the rounding of O - h_j, the key truncation
+            E = gam * (rw.nxq * cqm + Og) + rw.rx * cqm + rw.nx * rcm + u * Og +
                 ldexpf(2.0f * Og, A.ib - 23);
           } else {
             // NKU accumulation steps of FP32 rounding, the FP8 instruction's
@@ -523,7 +567,7 @@ __device__ __forceinline__ void assign_block(const AssignArgs& A, int64_t blk,
 }
 
 // MODE: 0 FP32, 1 BF16, 2 FP8 E4M3.  Persistent over the blocks of points.
-template <int MODE, int NKU, int NCG, int BN, int WAVES, int PF = 1>
+template <int MODE, int NKU, int NCG, int BN, int WAVES, int PF = 1, bool EP = false>
 __global__ __launch_bounds__(WAVES * 64) void assign_kernel(AssignArgs A,
                                                             const unsigned long long* row_count,
                                                             const int* __restrict__ gate) {
@@ -536,22 +580,21 @@ __global__ __launch_bounds__(WAVES * 64) void assign_kernel(AssignArgs A,
   if (A.rows) A.npts = (int64_t)(*row_count);
   const int64_t nblk = (A.npts + S::PPB - 1) / S::PPB;
   for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x)
-    assign_block<MODE, NKU, NCG, BN, WAVES, PF>(A, blk, lds, hsh, wcnt, wbase);
+    assign_block<MODE, NKU, NCG, BN, WAVES, PF, EP>(A, blk, lds, hsh, wcnt, wbase);
 }
 
 // ---------------------------------------------------------------------------
 // Kernel configurations.
-// BF16 rows hold d values, zero padding and three -1 columns: dp = 32*NKU with
-// NKU the first entry of kBf16Units covering d + 3.  FP8 rows hold d values
-// and zero padding: dp = 128*NKU bytes.  FP32 rows are padded to 16*NKU, NKU
-// a power of two.
+// BF16 rows hold d values and zero padding: dp = 32*NKU with NKU the first
+// entry of kBf16Units covering d.  FP8 rows hold d values and zero padding:
+// dp = 128*NKU bytes.  FP32 rows are padded to 16*NKU, NKU a power of two.
 // ---------------------------------------------------------------------------
-static const int kBf16Units[] = {1, 2, 3, 5, 9, 17, 24, 32, 33};
+static const int kBf16Units[] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32};
 static const int kF8Units[] = {1, 2, 3, 4, 6, 8};
 
 static int units_for(int prec, int d) {
   if (prec == KMX_BF16) {
-    const int need = (d + 3 + 31) / 32;
+    const int need = (d + 31) / 32;
     for (int u : kBf16Units)
       if (u >= need) return u;
     return -1;
@@ -578,17 +621,13 @@ int assign_dpad(int prec, int d) {
 int assign_tile_n(int prec, int d) {
   const int nku = units_for(prec, d);
   if (prec == KMX_FP8E4M3) return nku <= 3 ? 64 : (nku <= 6 ? 32 : 16);
-  if (prec == KMX_BF16) {
-    if (nku <= 3 || nku == 9) return 64;
-    if (nku <= 32) return 32;
-    return 16;
-  }
+  if (prec == KMX_BF16) return (nku <= 3 || nku == 6 || nku == 8) ? 64 : 32;
   if (nku <= 4) return 64;
   if (nku <= 32) return 32;
   return 16;
 }
 
-template <int MODE, int NKU, int NCG, int BN, int WAVES, int PF = 1>
+template <int MODE, int NKU, int NCG, int BN, int WAVES, int PF = 1, bool EP = false>
 static hipError_t run_assign(hipStream_t s, const void* Xsrc, int64_t xs, int vec_ok,
                              const uint8_t* sx8, int64_t n, const int* rows,
                              const unsigned long long* row_count, int d, int dp,
@@ -632,7 +671,7 @@ static hipError_t run_assign(hipStream_t s, const void* Xsrc, int64_t xs, int ve
     if (blocks > cap) blocks = cap;
   }
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL((assign_kernel<MODE, NKU, NCG, BN, WAVES, PF>), dim3((unsigned)blocks),
+  hipLaunchKernelGGL((assign_kernel<MODE, NKU, NCG, BN, WAVES, PF, EP>), dim3((unsigned)blocks),
                      dim3(WAVES * 64), 0, s, A, row_count, gate);
   return hipGetLastError();
 }
@@ -648,37 +687,38 @@ hipError_t launch_assign(hipStream_t s, int prec, const float* X, int64_t ldx, c
   while ((1 << ib) < kpad) ++ib;
   const int nku = units_for(prec, d);
   if (prec == KMX_BF16) {
-#define KMX_A(NKU_, NCG_, BN_, W_)                                                               \
-  return run_assign<1, NKU_, NCG_, BN_, W_>(s, Xq, dp, 1, nullptr, n, rows, row_count, d, dp, rs, \
+#define KMX_A(NKU_, NCG_, BN_, W_, EP_)                                                          \
+  return run_assign<1, NKU_, NCG_, BN_, W_, 1, EP_>(s, Xq, dp, 1, nullptr, n, rows, row_count, d, dp, rs, \
                                             Cq, ch, k, kpad, ib, cs, label, d1, d2, flags,      \
                                             full_rows, full_ctr, cascade_all, brute, st, gate, num_cus)
     switch (nku) {
-      case 1: KMX_A(1, 4, 64, 8);
-      case 2: KMX_A(2, 4, 64, 8);
-      case 3: KMX_A(3, 4, 64, 8);
-      case 5: KMX_A(5, 4, 32, 8);
-      case 9: KMX_A(9, 2, 64, 8);
-      case 17: KMX_A(17, 2, 32, 8);
-      case 24: KMX_A(24, 1, 32, 8);
-      case 32: KMX_A(32, 1, 32, 8);
-      case 33: KMX_A(33, 1, 16, 8);
+      case 1: KMX_A(1, 4, 64, 8, false);
+      case 2: KMX_A(2, 4, 64, 8, false);
+      case 3: KMX_A(3, 4, 64, 8, false);
+      case 4: KMX_A(4, 4, 32, 8, false);
+      case 6: KMX_A(6, 2, 64, 8, false);
+      case 8: KMX_A(8, 2, 64, 8, false);
+      case 12: KMX_A(12, 2, 32, 8, false);
+      case 16: KMX_A(16, 2, 32, 8, false);
+      case 24: KMX_A(24, 1, 32, 8, false);
+      case 32: KMX_A(32, 1, 32, 8, false);
       default: return hipErrorInvalidValue;
     }
 #undef KMX_A
   }
   if (prec == KMX_FP8E4M3) {
     if (!sx8) return hipErrorInvalidValue;
-#define KMX_A(NKU_, NCG_, BN_, W_)                                                           \
-  return run_assign<2, NKU_, NCG_, BN_, W_>(s, Xq, dp, 1, sx8, n, rows, row_count, d, dp, rs, \
+#define KMX_A(NKU_, NCG_, BN_, W_, EP_)                                                      \
+  return run_assign<2, NKU_, NCG_, BN_, W_, 1, EP_>(s, Xq, dp, 1, sx8, n, rows, row_count, d, dp, rs, \
                                             Cq, ch, k, kpad, ib, cs, label, d1, d2, flags,  \
                                             full_rows, full_ctr, cascade_all, brute, st, gate, num_cus)
     switch (nku) {
-      case 1: KMX_A(1, 4, 64, 8);
-      case 2: KMX_A(2, 4, 64, 8);
-      case 3: KMX_A(3, 2, 64, 8);
-      case 4: KMX_A(4, 2, 32, 8);
-      case 6: KMX_A(6, 1, 32, 8);
-      case 8: KMX_A(8, 1, 16, 8);
+      case 1: KMX_A(1, 4, 64, 8, true);
+      case 2: KMX_A(2, 4, 64, 8, false);
+      case 3: KMX_A(3, 2, 64, 8, false);
+      case 4: KMX_A(4, 2, 32, 8, true);
+      case 6: KMX_A(6, 1, 32, 8, true);
+      case 8: KMX_A(8, 1, 16, 8, true);
       default: return hipErrorInvalidValue;
     }
 #undef KMX_A
@@ -719,19 +759,60 @@ __device__ __forceinline__ void exact_dist(const float* __restrict__ x,
   df_norm(s, e, hi, lo);
 }
 
-// Short re-check: the listed 2 or 3 candidates.  Plain FP32 distances first
-// (per-lane sequential sums of ceil(d/64) squares, then a 6-level butterfly:
-// relative error <= (ceil(d/64) + 9) u); when the best plain distance beats
-// every other candidate by more than that bound the result is exact,
-// otherwise the candidates are compared with double-float sums.
-__device__ __forceinline__ float wave_plain_dist(const float* __restrict__ x,
-                                                 const float* __restrict__ c, int d, int lane) {
-  float acc = 0.f;
-  for (int q = lane; q < d; q += 64) {
-    const float df = x[q] - c[q];
-    acc = __builtin_fmaf(df, df, acc);
+// Short re-check: the listed 2 or 3 candidates, one wave per entry.  Plain
+// FP32 distances first: each lane sums the squares of its own coordinates
+// (four consecutive ones per 256-column step, or one per 64-column step when
+// rows are not 16-byte aligned: at most ceil(d/64) + 3 terms), then a 6-level
+// butterfly, so the relative error is below (ceil(d/64) + 13) u.  When the
+// best plain distance beats every other candidate by more than that bound the
+// result is exact; otherwise the candidates are compared with double-float
+// sums.  The next entry and its current label are fetched one entry ahead.
+__device__ __forceinline__ void plain_dist3(const float* __restrict__ x,
+                                            const float* __restrict__ c0,
+                                            const float* __restrict__ c1,
+                                            const float* __restrict__ c2, int d, int lane,
+                                            bool vec, float& p0, float& p1, float& p2) {
+  float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+  if (vec) {
+    for (int q = lane * 4; q < d; q += 256) {
+      const float4 xv = *(const float4*)(x + q);
+      const float4 u0 = *(const float4*)(c0 + q);
+      const float4 u1 = *(const float4*)(c1 + q);
+      const float4 u2 = *(const float4*)(c2 + q);
+      const float xs[4] = {xv.x, xv.y, xv.z, xv.w};
+      const float v0[4] = {u0.x, u0.y, u0.z, u0.w};
+      const float v1[4] = {u1.x, u1.y, u1.z, u1.w};
+      const float v2[4] = {u2.x, u2.y, u2.z, u2.w};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        float df = xs[e] - v0[e];
+        a0 = __builtin_fmaf(df, df, a0);
+        df = xs[e] - v1[e];
+        a1 = __builtin_fmaf(df, df, a1);
+        df = xs[e] - v2[e];
+        a2 = __builtin_fmaf(df, df, a2);
+      }
+    }
+  } else {
+    for (int q = lane; q < d; q += 64) {
+      const float xq = x[q];
+      float df = xq - c0[q];
+      a0 = __builtin_fmaf(df, df, a0);
+      df = xq - c1[q];
+      a1 = __builtin_fmaf(df, df, a1);
+      df = xq - c2[q];
+      a2 = __builtin_fmaf(df, df, a2);
+    }
   }
-  return wave_sum_f32(acc);
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    a0 += __shfl_xor(a0, m, 64);
+    a1 += __shfl_xor(a1, m, 64);
+    a2 += __shfl_xor(a2, m, 64);
+  }
+  p0 = a0;
+  p1 = a1;
+  p2 = a2;
 }
 
 __global__ __launch_bounds__(256) void recheck_pair_kernel(
@@ -740,23 +821,39 @@ __global__ __launch_bounds__(256) void recheck_pair_kernel(
     const FlagEntry* __restrict__ flags, const LoopState* __restrict__ st,
     const int* __restrict__ gate) {
   if (gate && *gate) return;
-  const unsigned long long cnt = st->flagged;
+  const int64_t cnt = (int64_t)st->flagged;
   const int lane = threadIdx.x & 63;
   const int64_t gw = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int64_t nw = (int64_t)gridDim.x * 4;
-  const float tol = (float)((d + 63) / 64 + 10) * 5.9604645e-8f;
-  for (int64_t e = gw; e < (int64_t)cnt; e += nw) {
-    const FlagEntry fe = flags[e];
+  const float tol = (float)((d + 63) / 64 + 13) * 5.9604645e-8f;
+  const bool vec = ((((uintptr_t)X) & 15) == 0) && (ldx % 4 == 0) &&
+                   ((((uintptr_t)C) & 15) == 0) && (d % 4 == 0);
+  // entries each row appears in at most once, so a label fetched ahead is
+  // never one this kernel writes before reading it
+  FlagEntry fe_n = {-1, -1, -1, 0};
+  int lab_n = 0;
+  if (gw < cnt) {
+    fe_n = flags[gw];
+    lab_n = (fe_n.row >= 0 && fe_n.row < n) ? label[fe_n.row] : 0;
+  }
+  for (int64_t e = gw; e < cnt; e += nw) {
+    const FlagEntry fe = fe_n;
+    const int lab = lab_n;
+    if (e + nw < cnt) {
+      fe_n = flags[e + nw];
+      lab_n = (fe_n.row >= 0 && fe_n.row < n) ? label[fe_n.row] : 0;
+    }
     const int row = fe.row;
     if (row < 0 || row >= n) continue;
     const float* x = X + (int64_t)row * ldx;
     int cj[3];
-    cj[0] = min(max(label[row], 0), k - 1);
+    cj[0] = min(max(lab, 0), k - 1);
     cj[1] = min(max(fe.cand2, 0), k - 1);
     cj[2] = fe.cand3 >= 0 ? min(fe.cand3, k - 1) : -1;
     const int nc = (cj[2] >= 0) ? 3 : 2;
     float p[3];
-    for (int q = 0; q < nc; ++q) p[q] = wave_plain_dist(x, C + (int64_t)cj[q] * d, d, lane);
+    plain_dist3(x, C + (int64_t)cj[0] * d, C + (int64_t)cj[1] * d,
+                C + (int64_t)(nc == 3 ? cj[2] : cj[1]) * d, d, lane, vec, p[0], p[1], p[2]);
     int b = 0;
     for (int q = 1; q < nc; ++q)
       if (p[q] < p[b] || (p[q] == p[b] && cj[q] < cj[b])) b = q;
@@ -783,30 +880,53 @@ __global__ __launch_bounds__(256) void recheck_pair_kernel(
   }
 }
 
-// One workgroup per row that needs every center; thread t handles centers
-// t, t + 256, ...  Pass 1: plain FP32 distances (sequential over the row,
-// relative error <= (d + 3) u) and their minimum m.  Pass 2: exact distances
-// of the centers within the error band of m; lexicographic argmin with the
-// lowest index on ties.
-__device__ __forceinline__ float plain_dist(const float* __restrict__ x,
-                                            const float* __restrict__ c, int d, bool vec) {
-  float acc = 0.f;
-  int q = 0;
+// One workgroup per row that needs every center.  Each wave takes four
+// centers at a time (centers 16i + 4w + 0..3 for wave w), its lanes splitting
+// the coordinates as in the short re-check, so every plain distance has
+// relative error below gamma = (ceil(d/64) + 13) u.  Pass 1: the minimum m
+// of the plain distances.  Pass 2: the same plain distances again (same
+// operations, same bits); exact double-float distances for the centers at
+// most m (1 + gamma) / (1 - gamma) (the only ones that can be the minimum);
+// lexicographic argmin with the lowest index on ties.
+__device__ __forceinline__ void plain_dist4(const float* __restrict__ x,
+                                            const float* __restrict__ C, int j0, int k, int d,
+                                            int lane, bool vec, float* p) {
+  const float* c[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) c[t] = C + (int64_t)min(j0 + t, k - 1) * d;
+  float a[4] = {0.f, 0.f, 0.f, 0.f};
   if (vec) {
-    for (; q + 4 <= d; q += 4) {
-      const float4 a = *(const float4*)(x + q);
-      const float4 b = *(const float4*)(c + q);
-      float df = a.x - b.x; acc = __builtin_fmaf(df, df, acc);
-      df = a.y - b.y; acc = __builtin_fmaf(df, df, acc);
-      df = a.z - b.z; acc = __builtin_fmaf(df, df, acc);
-      df = a.w - b.w; acc = __builtin_fmaf(df, df, acc);
+    for (int q = lane * 4; q < d; q += 256) {
+      const float4 xv = *(const float4*)(x + q);
+      const float xs[4] = {xv.x, xv.y, xv.z, xv.w};
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const float4 u = *(const float4*)(c[t] + q);
+        const float v[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const float df = xs[e] - v[e];
+          a[t] = __builtin_fmaf(df, df, a[t]);
+        }
+      }
+    }
+  } else {
+    for (int q = lane; q < d; q += 64) {
+      const float xq = x[q];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const float df = xq - c[t][q];
+        a[t] = __builtin_fmaf(df, df, a[t]);
+      }
     }
   }
-  for (; q < d; ++q) {
-    const float df = x[q] - c[q];
-    acc = __builtin_fmaf(df, df, acc);
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) a[t] += __shfl_xor(a[t], m, 64);
   }
-  return acc;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) p[t] = (j0 + t < k) ? a[t] : __builtin_inff();
 }
 
 __global__ __launch_bounds__(256) void recheck_full_kernel(
@@ -817,39 +937,40 @@ __global__ __launch_bounds__(256) void recheck_full_kernel(
   __shared__ float redf[4];
   __shared__ float redh[4], redl[4];
   __shared__ int redj[4];
-  const unsigned long long cnt = st->flagged_full;
+  const int64_t cnt = (int64_t)st->flagged_full;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const float gam = (float)(d + 3) * 5.9604645e-8f;
-  for (int64_t e = blockIdx.x; e < (int64_t)cnt; e += gridDim.x) {
+  const float gam = (float)((d + 63) / 64 + 13) * 5.9604645e-8f;
+  const bool vec = ((((uintptr_t)X) & 15) == 0) && (ldx % 4 == 0) &&
+                   ((((uintptr_t)C) & 15) == 0) && (d % 4 == 0);
+  for (int64_t e = blockIdx.x; e < cnt; e += gridDim.x) {
     const int row = brute[e];
     if (row < 0 || row >= n) continue;   // uniform across the block
     const float* x = X + (int64_t)row * ldx;
-    const bool vec = ((((uintptr_t)x) & 15) == 0) && ((((uintptr_t)C) & 15) == 0) && (d % 4 == 0);
     float m = __builtin_inff();
-    for (int j = tid; j < k; j += 256) m = fminf(m, plain_dist(x, C + (int64_t)j * d, d, vec));
-#pragma unroll
-    for (int s2 = 32; s2 >= 1; s2 >>= 1) m = fminf(m, __shfl_xor(m, s2, 64));
+    for (int j0 = 4 * wv; j0 < k; j0 += 16) {
+      float p[4];
+      plain_dist4(x, C, j0, k, d, lane, vec, p);
+      m = fminf(m, fminf(fminf(p[0], p[1]), fminf(p[2], p[3])));
+    }
     if (lane == 0) redf[wv] = m;
     __syncthreads();
     m = fminf(fminf(redf[0], redf[1]), fminf(redf[2], redf[3]));
     const float thr = m * (1.0f + gam) / (1.0f - gam) * 1.0001f + 1e-30f;
     float bh = __builtin_inff(), bl = 0.f;
     int best = 0x7FFFFFFF;
-    for (int j = tid; j < k; j += 256) {
-      const float* cj = C + (int64_t)j * d;
-      if (plain_dist(x, cj, d, vec) <= thr) {
-        float s = 0.f, ee = 0.f;
-        for (int q = 0; q < d; ++q) df_acc_sqdiff(x[q], cj[q], s, ee);
-        float h, l;
-        df_norm(s, ee, h, l);
-        if (df_less(h, l, bh, bl) || (h == bh && l == bl && j < best)) { bh = h; bl = l; best = j; }
-      }
-    }
+    for (int j0 = 4 * wv; j0 < k; j0 += 16) {
+      float p[4];
+      plain_dist4(x, C, j0, k, d, lane, vec, p);
 #pragma unroll
-    for (int s2 = 32; s2 >= 1; s2 >>= 1) {
-      const float oh = __shfl_xor(bh, s2, 64), ol = __shfl_xor(bl, s2, 64);
-      const int oj = __shfl_xor(best, s2, 64);
-      if (df_less(oh, ol, bh, bl) || (oh == bh && ol == bl && oj < best)) { bh = oh; bl = ol; best = oj; }
+      for (int t = 0; t < 4; ++t) {
+        if (p[t] <= thr) {   // wave-uniform
+          float h, l;
+          exact_dist(x, C + (int64_t)(j0 + t) * d, d, lane, h, l);
+          if (df_less(h, l, bh, bl) || (h == bh && l == bl && j0 + t < best)) {
+            bh = h; bl = l; best = j0 + t;
+          }
+        }
+      }
     }
     if (lane == 0) { redh[wv] = bh; redl[wv] = bl; redj[wv] = best; }
     __syncthreads();
@@ -880,7 +1001,7 @@ hipError_t launch_recheck(hipStream_t s, const float* X, int64_t n, int d, int64
                      C, k, label, d1, flags, st, gate);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  cap = (int64_t)num_cus * 2;
+  cap = (int64_t)num_cus * 4;
   blocks = n;
   if (blocks > cap) blocks = cap;
   if (blocks < 1) blocks = 1;
@@ -902,13 +1023,13 @@ namespace kmx {
 // ---------------------------------------------------------------------------
 constexpr int kBatchWaves = 8;
 // (variant id, BF16 units, point groups per wave, centers per tile); three
-// shapes per width group (BF16 units 1, 2, 3, 5, 9, 17).
+// shapes per width group (BF16 units 1, 2, 4, 8, 12, 16).
 #define KMX_BG0(X) X(0, 1, 4, 64) X(1, 1, 4, 16) X(2, 1, 2, 32)
 #define KMX_BG1(X) X(3, 2, 4, 64) X(4, 2, 4, 16) X(5, 2, 2, 32)
-#define KMX_BG2(X) X(6, 3, 4, 64) X(7, 3, 4, 16) X(8, 3, 2, 32)
-#define KMX_BG3(X) X(9, 5, 4, 32) X(10, 5, 2, 16) X(11, 5, 2, 64)
-#define KMX_BG4(X) X(12, 9, 2, 64) X(13, 9, 2, 16) X(14, 9, 2, 32)
-#define KMX_BG5(X) X(15, 17, 2, 32) X(16, 17, 2, 16) X(17, 17, 1, 32)
+#define KMX_BG2(X) X(6, 4, 4, 32) X(7, 4, 4, 16) X(8, 4, 2, 64)
+#define KMX_BG3(X) X(9, 8, 2, 64) X(10, 8, 2, 16) X(11, 8, 2, 32)
+#define KMX_BG4(X) X(12, 12, 2, 32) X(13, 12, 2, 16) X(14, 12, 1, 32)
+#define KMX_BG5(X) X(15, 16, 2, 32) X(16, 16, 2, 16) X(17, 16, 1, 32)
 #define KMX_BVARIANTS(X) KMX_BG0(X) KMX_BG1(X) KMX_BG2(X) KMX_BG3(X) KMX_BG4(X) KMX_BG5(X)
 
 constexpr int bmax(int a, int b) { return a > b ? a : b; }
@@ -932,17 +1053,18 @@ struct BVariant {
 static const BVariant kBVariants[] = {KMX_BVARIANTS(KMX_BV)};
 #undef KMX_BV
 
+static const int kBatchGroupUnits[6] = {1, 2, 4, 8, 12, 16};
+
 static int batch_group(int d) {
-  const int u = units_for(KMX_BF16, d);
-  switch (u) {
-    case 1: return 0;
-    case 2: return 1;
-    case 3: return 2;
-    case 5: return 3;
-    case 9: return 4;
-    case 17: return 5;
-    default: return -1;
-  }
+  const int need = (d + 31) / 32;
+  for (int g = 0; g < 6; ++g)
+    if (d >= 1 && kBatchGroupUnits[g] >= need) return g;
+  return -1;
+}
+
+int batched_dpad(int d) {
+  const int g = batch_group(d);
+  return g < 0 ? -1 : 32 * kBatchGroupUnits[g];
 }
 
 int batched_variants(int d) { return batch_group(d) < 0 ? 0 : 3; }
@@ -971,7 +1093,7 @@ __device__ __forceinline__ void batched_block(const BatchInst& I, int blk,
   A.dp = I.dp;
   A.rs = I.rs + I.row0;
   A.Cq = I.cq + (int64_t)I.cpad0 * I.dp;
-  A.ch = nullptr;
+  A.ch = I.ch + I.hd0;
   A.k = I.k;
   A.kpad = I.kpad;
   A.ib = I.ib;
@@ -988,7 +1110,7 @@ __device__ __forceinline__ void batched_block(const BatchInst& I, int blk,
   A.brute = brute;
   A.st = st;
   A.count_undecided = 1;
-  assign_block<1, NKU, NCG, BN, kBatchWaves, 1>(A, blk, lds, hsh, wcnt, wbase);
+  assign_block<1, NKU, NCG, BN, kBatchWaves, 1, false>(A, blk, lds, hsh, wcnt, wbase);
 }
 
 // Persistent over the items [begin, end) of one width group; each item's
@@ -1088,15 +1210,18 @@ __global__ __launch_bounds__(256) void recheck_pair_batched_kernel(
     if (row < 0 || row >= nrows) continue;
     const BatchBucket B = buckets[find_bucket(buckets, nb, row)];
     const int d = B.d;
-    const float tol = (float)((d + 63) / 64 + 10) * 5.9604645e-8f;
+    const float tol = (float)((d + 63) / 64 + 13) * 5.9604645e-8f;
     const float* x = B.X + (row - B.grow0) * d;
+    const bool vec = ((((uintptr_t)B.X) & 15) == 0) && ((((uintptr_t)B.C) & 15) == 0) &&
+                     (d % 4 == 0);
     int cj[3];
     cj[0] = min(max(label[row], 0), B.K - 1);
     cj[1] = min(max(fe.cand2, 0), B.K - 1);
     cj[2] = fe.cand3 >= 0 ? min(fe.cand3, B.K - 1) : -1;
     const int nc = (cj[2] >= 0) ? 3 : 2;
     float p[3];
-    for (int q = 0; q < nc; ++q) p[q] = wave_plain_dist(x, B.C + (int64_t)cj[q] * d, d, lane);
+    plain_dist3(x, B.C + (int64_t)cj[0] * d, B.C + (int64_t)cj[1] * d,
+                B.C + (int64_t)(nc == 3 ? cj[2] : cj[1]) * d, d, lane, vec, p[0], p[1], p[2]);
     int b = 0;
     for (int q = 1; q < nc; ++q)
       if (p[q] < p[b] || (p[q] == p[b] && cj[q] < cj[b])) b = q;
@@ -1134,42 +1259,36 @@ __global__ __launch_bounds__(256) void recheck_full_batched_kernel(
     if (row < 0 || row >= nrows) continue;   // uniform across the block
     const BatchInst& I = insts[find_inst(insts, ni, row)];
     const int d = I.d;
-    const float gam = (float)(d + 3) * 5.9604645e-8f;
+    const float gam = (float)((d + 63) / 64 + 13) * 5.9604645e-8f;
     const float* x = I.X + (I.row0 + (row - I.grow0)) * d;
     const float* C = I.C + (int64_t)I.koff * d;
     const bool vec = ((((uintptr_t)x) & 15) == 0) && ((((uintptr_t)C) & 15) == 0) && (d % 4 == 0);
     float m = __builtin_inff();
-    for (int j = tid; j < I.k; j += 256) m = fminf(m, plain_dist(x, C + (int64_t)j * d, d, vec));
-#pragma unroll
-    for (int s2 = 32; s2 >= 1; s2 >>= 1) m = fminf(m, __shfl_xor(m, s2, 64));
+    for (int j0 = 4 * wv; j0 < I.k; j0 += 16) {
+      float p[4];
+      plain_dist4(x, C, j0, I.k, d, lane, vec, p);
+      m = fminf(m, fminf(fminf(p[0], p[1]), fminf(p[2], p[3])));
+    }
     if (lane == 0) redf[wv] = m;
     __syncthreads();
     m = fminf(fminf(redf[0], redf[1]), fminf(redf[2], redf[3]));
     const float thr = m * (1.0f + gam) / (1.0f - gam) * 1.0001f + 1e-30f;
     float bh = __builtin_inff(), bl = 0.f;
     int best = 0x7FFFFFFF;
-    for (int j = tid; j < I.k; j += 256) {
-      const float* cj = C + (int64_t)j * d;
-      if (plain_dist(x, cj, d, vec) <= thr) {
-        float s = 0.f, ee = 0.f;
-        for (int q = 0; q < d; ++q) df_acc_sqdiff(x[q], cj[q], s, ee);
-        float h, l;
-        df_norm(s, ee, h, l);
-        if (df_less(h, l, bh, bl) || (h == bh && l == bl && j < best)) {
-          bh = h;
-          bl = l;
-          best = j;
-        }
-      }
-    }
+    for (int j0 = 4 * wv; j0 < I.k; j0 += 16) {
+      float p[4];
+      plain_dist4(x, C, j0, I.k, d, lane, vec, p);
 #pragma unroll
-    for (int s2 = 32; s2 >= 1; s2 >>= 1) {
-      const float oh = __shfl_xor(bh, s2, 64), ol = __shfl_xor(bl, s2, 64);
-      const int oj = __shfl_xor(best, s2, 64);
-      if (df_less(oh, ol, bh, bl) || (oh == bh && ol == bl && oj < best)) {
-        bh = oh;
-        bl = ol;
-        best = oj;
+      for (int t = 0; t < 4; ++t) {
+        if (p[t] <= thr) {   // wave-uniform
+          float h, l;
+          exact_dist(x, C + (int64_t)(j0 + t) * d, d, lane, h, l);
+          if (df_less(h, l, bh, bl) || (h == bh && l == bl && j0 + t < best)) {
+            bh = h;
+            bl = l;
+            best = j0 + t;
+          }
+        }
       }
     }
     if (lane == 0) {
@@ -1201,7 +1320,7 @@ hipError_t launch_recheck_batched(hipStream_t s, const BatchBucket* buckets, int
                      buckets, nbuckets, label, flags, st, nrows);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(recheck_full_batched_kernel, dim3((unsigned)(num_cus * 2)), dim3(256), 0, s,
+  hipLaunchKernelGGL(recheck_full_batched_kernel, dim3((unsigned)(num_cus * 4)), dim3(256), 0, s,
                      insts, ninst, label, brute, st, nrows);
   return hipGetLastError();
 }

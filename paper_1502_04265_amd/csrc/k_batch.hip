@@ -50,7 +50,7 @@ __global__ __launch_bounds__(64) void batch_centers_a_kernel(const BatchInst* __
   const float* c = I.C + (int64_t)(I.koff + (real ? j : 0)) * I.d;
   uint16_t* q = I.cq + (int64_t)(I.cpad0 + j) * I.dp;
   double s2 = 0.0, q2 = 0.0, r2 = 0.0;
-  for (int col = lane; col < I.dp - 3; col += 64) {
+  for (int col = lane; col < I.dp; col += 64) {
     const float v = (real && col < I.d) ? c[col] : 0.0f;
     const uint16_t b = f32_to_bf16_rne(v);
     q[col] = b;
@@ -73,8 +73,8 @@ __global__ __launch_bounds__(64) void batch_centers_a_kernel(const BatchInst* __
 }
 
 // Pass B, one thread per padded center: the instance's score offset O (as for
-// a single problem, with the bucket's largest ||x~||) and h_j - O split into
-// three BF16 terms in the last three columns (zeros for padding).
+// a single problem, with the bucket's largest ||x~||) and the accumulator
+// start values ch[g] = O - h_j in FP32 (zeros for padding).
 __global__ void batch_centers_b_kernel(const BatchInst* __restrict__ insts,
                                        const int* __restrict__ cinst, int npad) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
@@ -86,19 +86,7 @@ __global__ void batch_centers_b_kernel(const BatchInst* __restrict__ insts,
   const float cnm = __uint_as_float(I.cs->cn_max);
   const float O = (xm * cqm + 0.5f * cnm * cnm) * 1.001f + 1.0f;
   if (j == 0) I.cs->O = O;
-  uint16_t h1 = 0, h2 = 0, h3 = 0;
-  if (j < I.k) {
-    const float hp = (float)(I.hd[g] - (double)O);
-    h1 = f32_to_bf16_rne(hp);
-    const float r1 = hp - bf16_to_f32(h1);
-    h2 = f32_to_bf16_rne(r1);
-    const float r2 = r1 - bf16_to_f32(h2);
-    h3 = f32_to_bf16_rne(r2);
-  }
-  uint16_t* row = I.cq + (int64_t)(I.cpad0 + j) * I.dp + I.dp - 3;
-  row[0] = h1;
-  row[1] = h2;
-  row[2] = h3;
+  I.ch[g] = (j < I.k) ? (float)((double)O - I.hd[g]) : 0.0f;
 }
 
 hipError_t launch_batch_prep_centers(hipStream_t s, const BatchInst* insts, const int* cinst,

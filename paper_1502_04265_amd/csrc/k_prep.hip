@@ -11,10 +11,8 @@
 namespace kmx {
 
 // One wave per row.  Writes RowStats and, when Xq != nullptr, the BF16 row
-// (round to nearest even) of dp elements: x~ in columns [0, d), zeros, and
-// -1 in the last three columns.  Those three columns multiply the split
-// score offset stored with each center (see k_assign.hip).  xq_max receives
-// max_i ||x~_i||.
+// (round to nearest even) of dp elements: x~ in columns [0, d), zeros after.
+// xq_max receives max_i ||x~_i||.
 __global__ __launch_bounds__(256) void prep_rows_kernel(const float* __restrict__ X, int64_t n,
                                                         int d, int64_t ldx, int dp,
                                                         uint16_t* __restrict__ Xq,
@@ -33,8 +31,7 @@ __global__ __launch_bounds__(256) void prep_rows_kernel(const float* __restrict_
       const double vd = (double)v;
       s2 += vd * vd;
       if (Xq) {
-        uint16_t b = f32_to_bf16_rne(v);
-        if (c >= dp - 3) b = 0xBF80u;   // -1.0
+        const uint16_t b = f32_to_bf16_rne(v);
         Xq[row * dp + c] = b;
         if (c < d) {
           const double qd = (double)bf16_to_f32(b);
@@ -89,8 +86,7 @@ __global__ __launch_bounds__(64) void prep_centers_kernel(const float* __restric
   const int j = blockIdx.x;
   const int lane = threadIdx.x;
   double s2 = 0.0, q2 = 0.0, r2 = 0.0;
-  const int lim = (prec == 1) ? dp - 3 : dp;
-  for (int c = lane; c < lim; c += 64) {
+  for (int c = lane; c < dp; c += 64) {
     const float v = (j < k && c < d) ? C[(int64_t)j * d + c] : 0.0f;
     const double vd = (double)v;
     s2 += vd * vd;
@@ -122,37 +118,6 @@ __global__ __launch_bounds__(64) void prep_centers_kernel(const float* __restric
       atomicMax(&cs->cn_max, __float_as_uint(cn));
     }
   }
-}
-
-// Pass B (BF16 only), one thread per padded center: the offset
-// O = (max||x~|| max||c~|| + max||c||^2 / 2) * 1.001 + 1 makes every score
-// x~.c~_j - h_j + O positive.  h'_j = h_j - O is stored as three BF16 terms
-// (h1 + h2 + h3 = h'_j to about 2^-24 |h'_j|) in the last three columns, which
-// meet the -1 columns of the rows; padding rows get zeros (score 0).
-__global__ void prep_centers_b_kernel(int k, int kpad, int dp, uint16_t* __restrict__ Cq,
-                                      const double* __restrict__ hd,
-                                      CenterStats* __restrict__ cs,
-                                      const unsigned* __restrict__ xq_max) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  const float xm = __uint_as_float(*xq_max);
-  const float cqm = __uint_as_float(cs->cq_max);
-  const float cnm = __uint_as_float(cs->cn_max);
-  const float O = (xm * cqm + 0.5f * cnm * cnm) * 1.001f + 1.0f;
-  if (j == 0) cs->O = O;
-  if (j >= kpad) return;
-  uint16_t h1 = 0, h2 = 0, h3 = 0;
-  if (j < k) {
-    const float hp = (float)(hd[j] - (double)O);
-    h1 = f32_to_bf16_rne(hp);
-    const float r1 = hp - bf16_to_f32(h1);
-    h2 = f32_to_bf16_rne(r1);
-    const float r2 = r1 - bf16_to_f32(h2);
-    h3 = f32_to_bf16_rne(r2);
-  }
-  uint16_t* row = Cq + (int64_t)j * dp + dp - 3;
-  row[0] = h1;
-  row[1] = h2;
-  row[2] = h3;
 }
 
 // ---------------------------------------------------------------------------
@@ -265,8 +230,7 @@ hipError_t launch_prep_rows_f8(hipStream_t s, const float* X, int64_t n, int d, 
 
 // Centers, FP8: one scale for all centers.  Pass 1: max |c_ji|.  Pass 2 (one
 // wave per padded center): the FP8 row (zeros for padding), hd = ||c||^2 / 2
-// in FP64 and the norm maxima.  Pass 3: the offset O and the accumulator
-// start values ch[j] = O - hd[j] (0 for padding: score 0, never selected).
+// in FP64 and the norm maxima.  Then the offsets (prep_offsets_kernel).
 __global__ void center_amax_kernel(const float* __restrict__ C, int64_t total,
                                    CenterStats* __restrict__ cs) {
   float m = 0.0f;
@@ -318,10 +282,13 @@ __global__ __launch_bounds__(64) void prep_centers_f8_kernel(const float* __rest
   }
 }
 
-__global__ void prep_centers_f8_b_kernel(int k, int kpad, const double* __restrict__ hd,
-                                         CenterStats* __restrict__ cs,
-                                         const unsigned* __restrict__ xq_max,
-                                         float* __restrict__ ch) {
+// BF16 and FP8, one thread per padded center: the offset
+// O = (max||x~|| max||c~|| + max||c||^2 / 2) * 1.001 + 1, which makes every
+// score x~.c~_j - h_j + O positive, and the accumulator start values
+// ch[j] = O - hd[j] rounded to FP32 (0 for padding: score 0, never selected).
+__global__ void prep_offsets_kernel(int k, int kpad, const double* __restrict__ hd,
+                                    CenterStats* __restrict__ cs,
+                                    const unsigned* __restrict__ xq_max, float* __restrict__ ch) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   const float xm = __uint_as_float(*xq_max);
   const float cqm = __uint_as_float(cs->cq_max);
@@ -346,16 +313,16 @@ hipError_t launch_prep_centers(hipStream_t s, const float* C, int k, int d, int 
                        (uint8_t*)Cq, hd, cs);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(prep_centers_f8_b_kernel, dim3((kpad + 255) / 256), dim3(256), 0, s, k,
-                       kpad, hd, cs, xq_max, ch);
+    hipLaunchKernelGGL(prep_offsets_kernel, dim3((kpad + 255) / 256), dim3(256), 0, s, k, kpad,
+                       hd, cs, xq_max, ch);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(prep_centers_kernel, dim3(kpad), dim3(64), 0, s, C, k, d, dp, prec, Cq, ch,
                      hd, cs);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || prec != 1) return e;
-  hipLaunchKernelGGL(prep_centers_b_kernel, dim3((kpad + 255) / 256), dim3(256), 0, s, k, kpad,
-                     dp, (uint16_t*)Cq, hd, cs, xq_max);
+  hipLaunchKernelGGL(prep_offsets_kernel, dim3((kpad + 255) / 256), dim3(256), 0, s, k, kpad, hd,
+                     cs, xq_max, ch);
   return hipGetLastError();
 }
 

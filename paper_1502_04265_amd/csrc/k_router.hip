@@ -229,7 +229,7 @@ __global__ __launch_bounds__(WAVES * 64) void router_fwd_kernel(
 
 // Units of 32 BF16 columns the forward pass reads from each row of the
 // quantized X (dp columns): the smallest instantiated count covering d.
-static const int kRouterUnits[] = {1, 2, 3, 5, 9, 16, 17, 24, 32, 33};
+static const int kRouterUnits[] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32};
 
 int router_units(int d, int dp) {
   const int need = (d + 31) / 32;
@@ -261,8 +261,8 @@ hipError_t launch_router_fwd(hipStream_t s, const uint16_t* Xq, int64_t dp, int6
   int ib = 1;
   while ((1 << ib) < kpad) ++ib;
   switch (router_units(d, (int)dp)) {
-// Two point groups per wave keep both layers' fragments in registers; for 16
-// and 17 units that needs more than the 256 registers of two waves per SIMD,
+// Two point groups per wave keep both layers' fragments in registers; for 8
+// and 16 units that needs more than the 256 registers of two waves per SIMD,
 // so those run one wave per SIMD (four waves per workgroup).
 #define KMX_R(U, G, W)                                                                     \
   case U:                                                                                  \
@@ -271,13 +271,13 @@ hipError_t launch_router_fwd(hipStream_t s, const uint16_t* Xq, int64_t dp, int6
     KMX_R(1, 2, 8);
     KMX_R(2, 2, 8);
     KMX_R(3, 2, 8);
-    KMX_R(5, 2, 8);
-    KMX_R(9, 2, 8);
+    KMX_R(4, 2, 8);
+    KMX_R(6, 2, 8);
+    KMX_R(8, 2, 4);
+    KMX_R(12, 2, 8);
     KMX_R(16, 2, 4);
-    KMX_R(17, 2, 4);
     KMX_R(24, 1, 8);
     KMX_R(32, 1, 8);
-    KMX_R(33, 1, 8);
 #undef KMX_R
     default:
       return hipErrorInvalidValue;
@@ -477,7 +477,7 @@ hipError_t launch_center_table(hipStream_t s, const float* C, int k, int d, floa
 // list is exhausted, or no proposal) -> GEMM row list.
 // ROUTED = false takes the previous label as the only candidate.
 // ---------------------------------------------------------------------------
-template <bool ROUTED>
+template <bool ROUTED, int NX>
 __global__ __launch_bounds__(256) void router_cert_kernel(
     const uint16_t* __restrict__ Xq, int64_t xs, int64_t n, int d, const float* __restrict__ C,
     int k, const RowStats* __restrict__ rs, const uint32_t* __restrict__ keys, int ib,
@@ -496,23 +496,33 @@ __global__ __launch_bounds__(256) void router_cert_kernel(
   const unsigned mask = (1u << ib) - 1u;
   const float u = 5.9604645e-8f;
   const float gam = (float)(d + 16) * u;
-  const bool vec = ((((uintptr_t)C) & 15) == 0) && (d % 8 == 0);
   const int64_t nchunks = (n + RPB - 1) / RPB;
   const unsigned long long below = (1ull << lane) - 1ull;
 
   for (int64_t chk = blockIdx.x; chk < nchunks; chk += gridDim.x) {
     const int64_t r0 = chk * RPB + (int64_t)wave * RPW;
+    // The selection input of the next pass (proposal keys, or the previous
+    // label) is fetched one pass ahead, and everything that depends on the
+    // selected center (its row, neighbour bounds and ids) is issued together
+    // with the point's own row: one memory round trip per pass.
+    auto fetch_sel = [&](int pass) -> unsigned {
+      const int64_t rr = r0 + pass * 4 + sub;
+      if (rr >= n) return 0u;
+      return ROUTED ? keys[rr * kRouterM + q] : (unsigned)label[rr];
+    };
+    unsigned sel_next = fetch_sel(0);
     for (int pass = 0; pass < RPW / 4; ++pass) {
       const int slot = pass * 4 + sub;
       const int64_t r = r0 + slot;
       const bool valid = r < n;
+      const unsigned sel = sel_next;
+      if (pass + 1 < RPW / 4) sel_next = fetch_sel(pass + 1);
       int b0 = 0, cand = -1;
       bool ok = valid;
       if (ROUTED) {
-        const unsigned key = valid ? keys[r * kRouterM + q] : 0u;
-        const int ci = (int)(mask - (key & mask));
+        const int ci = (int)(mask - (sel & mask));
         cand = (valid && ci < k) ? ci : -1;
-        unsigned best = (cand >= 0) ? key : 0u;
+        unsigned best = (cand >= 0) ? sel : 0u;
 #pragma unroll
         for (int m = 8; m >= 1; m >>= 1) best = max(best, (unsigned)__shfl_xor((int)best, m, 64));
         if (best == 0u) ok = false;
@@ -522,7 +532,7 @@ __global__ __launch_bounds__(256) void router_cert_kernel(
           b0 = 0;
         }
       } else {
-        b0 = valid ? label[r] : 0;
+        b0 = valid ? (int)sel : 0;
         if (b0 < 0 || b0 >= k) {
           ok = false;
           b0 = 0;
@@ -530,24 +540,43 @@ __global__ __launch_bounds__(256) void router_cert_kernel(
         cand = (q == 0) ? b0 : -1;
       }
 
+      const float* nd = nbd + (int64_t)b0 * (kNbrL + 1);
+      const float nd0 = nd[q], nd1 = nd[q + 16], ndl = nd[kNbrL];
+      const int nb0 = nbr[(int64_t)b0 * kNbrL], nb1 = nbr[(int64_t)b0 * kNbrL + 1];
+      const float rx = valid ? rs[r].rx : 0.0f;
+
       // upper bound of ||x - c_b0||
       const float* c = C + (int64_t)b0 * d;
       const uint16_t* xr = Xq + (valid ? r : 0) * xs;
       float s = 0.0f;
-      for (int e0 = q * 8; e0 < d; e0 += 128) {
-        if (vec) {
-          const ru32x4_t xv = *(const ru32x4_t*)(xr + e0);
-          const float4 ca = *(const float4*)(c + e0);
-          const float4 cb = *(const float4*)(c + e0 + 4);
-          const float cc[8] = {ca.x, ca.y, ca.z, ca.w, cb.x, cb.y, cb.z, cb.w};
+      if (NX > 0) {
+        ru32x4_t xv[NX > 0 ? NX : 1];
+        float4 ca[NX > 0 ? NX : 1], cb[NX > 0 ? NX : 1];
 #pragma unroll
-          for (int e = 0; e < 8; ++e) {
-            const unsigned w2 = xv[e >> 1];
-            const float xe = __uint_as_float((e & 1) ? (w2 & 0xFFFF0000u) : (w2 << 16));
-            const float df = xe - cc[e];
-            s = __builtin_fmaf(df, df, s);
+        for (int i = 0; i < NX; ++i) {
+          const int e0 = q * 8 + 128 * i;
+          if (e0 < d) {
+            xv[i] = *(const ru32x4_t*)(xr + e0);
+            ca[i] = *(const float4*)(c + e0);
+            cb[i] = *(const float4*)(c + e0 + 4);
           }
-        } else {
+        }
+#pragma unroll
+        for (int i = 0; i < NX; ++i) {
+          if (q * 8 + 128 * i < d) {
+            const float cc[8] = {ca[i].x, ca[i].y, ca[i].z, ca[i].w,
+                                 cb[i].x, cb[i].y, cb[i].z, cb[i].w};
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+              const unsigned w2 = xv[i][e >> 1];
+              const float xe = __uint_as_float((e & 1) ? (w2 & 0xFFFF0000u) : (w2 << 16));
+              const float df = xe - cc[e];
+              s = __builtin_fmaf(df, df, s);
+            }
+          }
+        }
+      } else {
+        for (int e0 = q * 8; e0 < d; e0 += 128) {
           const int e1 = min(e0 + 8, d);
           for (int e = e0; e < e1; ++e) {
             const float df = bf16_to_f32(xr[e]) - c[e];
@@ -557,19 +586,17 @@ __global__ __launch_bounds__(256) void router_cert_kernel(
       }
 #pragma unroll
       for (int m = 8; m >= 1; m >>= 1) s += __shfl_xor(s, m, 64);
-      const float rx = valid ? rs[r].rx : 0.0f;
       const float dub = sqrtf(s * (1.0f + gam)) * (1.0f + 4.0f * u) + rx;
       const float R = 2.0f * dub * (1.0f + 8.0f * u);
 
-      // walk b0's sorted neighbour list
-      const float* nd = nbd + (int64_t)b0 * (kNbrL + 1);
-      const unsigned long long bal0 = __ballot(nd[q] < R);
-      const unsigned long long bal1 = __ballot(nd[q + 16] < R);
+      // b0's sorted neighbour list: m neighbours have a lower bound below R
+      const unsigned long long bal0 = __ballot(nd0 < R);
+      const unsigned long long bal1 = __ballot(nd1 < R);
       const int m = __popcll((bal0 >> (16 * sub)) & 0xFFFFull) +
                     __popcll((bal1 >> (16 * sub)) & 0xFFFFull);
-      const bool exhausted = (m == kNbrL) && (nd[kNbrL] < R);
-      const int n0 = (m >= 1) ? nbr[(int64_t)b0 * kNbrL] : -2;
-      const int n1 = (m >= 2) ? nbr[(int64_t)b0 * kNbrL + 1] : -2;
+      const bool exhausted = (m == kNbrL) && (ndl < R);
+      const int n0 = (m >= 1) ? nb0 : -2;
+      const int n1 = (m >= 2) ? nb1 : -2;
       const unsigned long long h0 = __ballot(cand >= 0 && cand == n0);
       const unsigned long long h1 = __ballot(cand >= 0 && cand == n1);
       const bool has0 = ((h0 >> (16 * sub)) & 0xFFFFull) != 0ull;
@@ -647,16 +674,34 @@ hipError_t launch_router_cert(hipStream_t s, const uint16_t* Xq, int64_t dp, int
                               int num_cus) {
   int ib = 1;
   while ((1 << ib) < kpad) ++ib;
+  // one 1024-row chunk per workgroup up to 32 per CU
   int64_t blocks = (n + 1023) / 1024;
-  const int64_t cap = (int64_t)num_cus * 8;
+  const int64_t cap = (int64_t)num_cus * 32;
   if (blocks > cap) blocks = cap;
   if (blocks < 1) blocks = 1;
-  if (keys)
-    hipLaunchKernelGGL(router_cert_kernel<true>, dim3((unsigned)blocks), dim3(256), 0, s, Xq, dp,
-                       n, d, C, k, rs, keys, ib, nbr, nbd, label, flags, fb_rows, st, gate);
-  else
-    hipLaunchKernelGGL(router_cert_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, s, Xq, dp,
-                       n, d, C, k, rs, keys, ib, nbr, nbd, label, flags, fb_rows, st, gate);
+  // the distance pass keeps the row in registers (NX 128-column pieces per
+  // 16 lanes) when both rows are 16-byte aligned in whole 8-column pieces
+  const bool vec = ((((uintptr_t)C) & 15) == 0) && (((uintptr_t)Xq & 15) == 0) && (d % 8 == 0) &&
+                   (dp % 8 == 0);
+  const int nx = !vec ? 0 : d <= 128 ? 1 : d <= 256 ? 2 : d <= 512 ? 4 : d <= 1024 ? 8 : 0;
+#define KMX_C(R_, NX_)                                                                           \
+  hipLaunchKernelGGL((router_cert_kernel<R_, NX_>), dim3((unsigned)blocks), dim3(256), 0, s, Xq, \
+                     dp, n, d, C, k, rs, keys, ib, nbr, nbd, label, flags, fb_rows, st, gate)
+#define KMX_CN(R_)         \
+  switch (nx) {            \
+    case 1: KMX_C(R_, 1); break; \
+    case 2: KMX_C(R_, 2); break; \
+    case 4: KMX_C(R_, 4); break; \
+    case 8: KMX_C(R_, 8); break; \
+    default: KMX_C(R_, 0); break; \
+  }
+  if (keys) {
+    KMX_CN(true)
+  } else {
+    KMX_CN(false)
+  }
+#undef KMX_CN
+#undef KMX_C
   return hipGetLastError();
 }
 

@@ -150,9 +150,11 @@ kmx_status run_prep_centers(kmx_ctx* ctx, const float* C, int k, int d, int prec
     const int bn = assign_tile_n(KMX_BF16, d);
     const int kpad = (k + bn - 1) / bn * bn;
     KMX_TRY(grow(ctx, ctx->cq, (size_t)kpad * dp * sizeof(uint16_t)));
+    KMX_TRY(grow(ctx, ctx->ch, (size_t)kpad * sizeof(float)));
     KMX_TRY(grow(ctx, ctx->hd, (size_t)kpad * sizeof(double)));
-    KMX_HIP(ctx, launch_prep_centers(ctx->stream, C, k, d, kpad, dp, KMX_BF16, ctx->cq.p, nullptr,
-                                     P<double>(ctx->hd), cs, P<unsigned>(ctx->xstats)));
+    KMX_HIP(ctx, launch_prep_centers(ctx->stream, C, k, d, kpad, dp, KMX_BF16, ctx->cq.p,
+                                     P<float>(ctx->ch), P<double>(ctx->hd), cs,
+                                     P<unsigned>(ctx->xstats)));
   }
   if (prec == KMX_FP8E4M3) {
     const int dp = assign_dpad(KMX_FP8E4M3, d);
@@ -220,7 +222,8 @@ kmx_status run_assign_gemm(kmx_ctx* ctx, const float* X, int64_t n, int d, int64
     {
       Timed tm(ctx, prec == KMX_FP8E4M3 ? T_RECHECK : T_ASSIGN);
       KMX_HIP(ctx, launch_assign(ctx->stream, KMX_BF16, X, ldx, ctx->xq.p, nullptr, n, rows16,
-                                 cnt16, d, dp, rs, ctx->cq.p, nullptr, k, kpad, cs, label, d1, d2,
+                                 cnt16, d, dp, rs, ctx->cq.p, P<float>(ctx->ch), k, kpad, cs,
+                                 label, d1, d2,
                                  flags, next16, ctr16, 0, brute, st, gate, ctx->num_cus));
     }
     {
@@ -331,7 +334,7 @@ kmx_status kmx_destroy(kmx_ctx* ctx) {
       &ctx->nbd,       &ctx->fbh,      &ctx->xq8,        &ctx->sx8,        &ctx->rowstats8,
       &ctx->xstats8,   &ctx->cq8,      &ctx->ch8,        &ctx->hd8,        &ctx->cstats8,
       &ctx->full_rows2, &ctx->bX,       &ctx->bXq,        &ctx->brs,        &ctx->bw,
-      &ctx->bC,        &ctx->bCq,      &ctx->bhd,        &ctx->bcs,        &ctx->blab,
+      &ctx->bC,        &ctx->bCq,      &ctx->bhd,        &ctx->bch,        &ctx->bcs,        &ctx->blab,
       &ctx->bitems,    &ctx->binsts,   &ctx->bbuckets,   &ctx->bcinst,     &ctx->bxstats,
       &ctx->btermC,    &ctx->btermMu,  &ctx->bW,         &ctx->bcost};
   for (kmx::Buf* b : bufs)

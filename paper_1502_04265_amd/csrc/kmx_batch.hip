@@ -84,7 +84,7 @@ void build_plan(const kmx_ctx* ctx, const kmx_problem* probs, int count,
     while (a < e) {
       BucketPlan B;
       B.d = d;
-      B.dp = assign_dpad(KMX_BF16, d);
+      B.dp = batched_dpad(d);
       B.grow0 = pl.N;
       B.xoff = pl.xsz;
       B.xqoff = pl.xqsz;
@@ -182,6 +182,7 @@ kmx_status setup(kmx_ctx* ctx, const kmx_problem* probs, Plan& pl, int stride) {
   KMX_TRY(grow(ctx, ctx->bC, (size_t)pl.csz * sizeof(float)));
   KMX_TRY(grow(ctx, ctx->bCq, (size_t)pl.cqsz * sizeof(uint16_t)));
   KMX_TRY(grow(ctx, ctx->bhd, (size_t)pl.Ptot * sizeof(double)));
+  KMX_TRY(grow(ctx, ctx->bch, (size_t)pl.Ptot * sizeof(float)));
   KMX_TRY(grow(ctx, ctx->bcs, (size_t)ni * sizeof(CenterStats)));
   KMX_TRY(grow(ctx, ctx->blab, (size_t)pl.N * sizeof(int32_t)));
   KMX_TRY(grow(ctx, ctx->bitems, pl.items.size() * sizeof(BatchItem)));
@@ -229,6 +230,7 @@ kmx_status setup(kmx_ctx* ctx, const kmx_problem* probs, Plan& pl, int stride) {
     I.rs = P<RowStats>(ctx->brs) + B.grow0;
     I.cq = bCq + B.cqoff;
     I.hd = P<double>(ctx->bhd);
+    I.ch = P<float>(ctx->bch);
     I.cs = P<CenterStats>(ctx->bcs) + i;
     I.X = bX + B.xoff;
     I.C = bC + B.coff;

@@ -91,6 +91,7 @@ struct BatchInst {
   const unsigned* xq_max;  // bucket max ||x~||
   int hd0;             // first padded center in the global numbering of padded centers
   int pad2_;
+  float* ch;           // per padded center (global numbering): O - h_j, the GEMM start value
 };
 
 struct BatchItem {
@@ -136,10 +137,6 @@ constexpr int kNbrL = 32;           // sorted neighbours kept per center
 constexpr int kRouterMaxBatch = 65536;  // largest training batch
 
 // batched (k_assign.hip, k_batch.hip)
-int batched_variants(int d);                  // number of tile shapes for width d
-int batched_variant_tile(int d, int v);       // centers per tile of variant v
-int batched_variant_ppb(int d, int v);        // points per block of variant v
-int batched_variant_id(int d, int v);         // variant index over all groups
 int batched_group(int d);                     // width group (one kernel per group)
 hipError_t launch_assign_batched(hipStream_t s, int group, const BatchItem* items, int begin,
                                  int end, const BatchInst* insts, FlagEntry* flags, int* brute,
@@ -241,7 +238,7 @@ struct kmx_ctx {
   kmx::Buf scratch_c, hist;
   kmx::Buf fb_rows, keys, cdist, nbr, nbd, fbh;   // routed assignment
   // batched Lloyd: concatenated instances and their descriptors
-  kmx::Buf bX, bXq, brs, bw, bC, bCq, bhd, bcs, blab, bitems, binsts, bbuckets, bcinst, bxstats;
+  kmx::Buf bX, bXq, brs, bw, bC, bCq, bhd, bch, bcs, blab, bitems, binsts, bbuckets, bcinst, bxstats;
   kmx::Buf btermC, btermMu, bW, bcost;
   hipStream_t cap_stream = nullptr;                // stream the batched iteration is captured on
   std::map<std::pair<int, int>, int> tune;         // (d, k class) -> tile-shape variant
@@ -315,6 +312,7 @@ int batched_variants(int d);                  // number of tile shapes for width
 int batched_variant_tile(int d, int v);       // centers per tile of variant v
 int batched_variant_ppb(int d, int v);        // points per block of variant v
 int batched_variant_id(int d, int v);         // variant index over all groups
+int batched_dpad(int d);                      // BF16 row length of a bucket of width d
 int batched_group(int d);                     // width group (one kernel per group)
 hipError_t launch_assign_batched(hipStream_t s, int group, const BatchItem* items, int begin,
                                  int end, const BatchInst* insts, FlagEntry* flags, int* brute,

@@ -185,6 +185,25 @@ def test_lloyd_routed_identical_to_plain(ctx, mode, prec):
         assert min(rows) > 0.9 * n
 
 
+@pytest.mark.parametrize("n,d,k", [(5000, 37, 20), (6000, 200, 40), (3000, 1000, 30)])
+def test_lloyd_routed_identical_other_widths(ctx, n, d, k):
+    """The certificate's distance pass for other row widths (a generic loop
+    for d not a multiple of 8, rows held in 2 or 8 register pieces): routed
+    iterations with previous labels reproduce the plain ones bit for bit."""
+    say(f"lloyd routed widths n={n} d={d} k={k}")
+    X, _, _ = synth.router_mixture(n, d, k, seed=d)
+    Xd = _dev(X)
+    C0, _ = ctx.seed(Xd, k, rng_seed=3)
+    (Cp, lp, hp, ip), (Cr, lr_, hr, ir, rows) = _plain_and_routed(ctx, X, C0.cpu().numpy(), 4,
+                                                                  None)
+    say(f"  gemm rows per assignment: {rows}")
+    assert ip == ir == 4
+    assert (lp == lr_).all()
+    assert np.array_equal(Cp.view(np.uint32), Cr.view(np.uint32))
+    assert hp == hr
+    assert rows[0] == n and max(rows[1:]) < n
+
+
 def test_trained_router_gain(ctx):
     """Training is what makes the proposals usable: the trained network sends
     far fewer rows to the GEMM than the same network untrained, from the first

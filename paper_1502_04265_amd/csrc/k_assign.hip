@@ -247,6 +247,28 @@ __device__ __forceinline__ void assign_block(const AssignArgs& A, int64_t blk,
       top4_insert(key, v1[cg], v2[cg], v3[cg], v4[cg]);
     };
 
+    // Packed keys of one tile into the running top-4.  With eight waves the
+    // second half inserts its keys after the tile's barrier instead of
+    // before it: the two waves sharing a SIMD then run their vector epilogue
+    // while the other one issues matrix instructions.  (The keys live in
+    // registers only, so the barrier does not order them.)
+    const bool late = (WAVES == 8) && (wave >= WAVES / 2);
+    auto insert_tile = [&](const f32x4_t (&a)[NCG][RB], int tt) {
+      const unsigned ibase = mask - (unsigned)(tt * BN + grp * 4);
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const unsigned idx = ibase - (unsigned)(rb * 16 + i);
+#pragma unroll
+          for (int cg = 0; cg < NCG; ++cg) {
+            const unsigned key = (__float_as_uint(a[cg][rb][i]) & ~mask) | idx;
+            top4_insert(key, v1[cg], v2[cg], v3[cg], v4[cg]);
+          }
+        }
+      }
+    };
+
     for (int t = 0; t < ntiles; ++t) {
       const int buf = t & 1;
       if (t + 1 < ntiles) issue_tile(t + 1, buf ^ 1);
@@ -263,15 +285,26 @@ __device__ __forceinline__ void assign_block(const AssignArgs& A, int64_t blk,
       }
 
       if constexpr (F8) {
+        // A fragments one unit ahead, as for BF16 below
         const unsigned char* abase = &lds[buf * BUFB + prow * PITCH + grp * 32];
-#pragma unroll
-        for (int ku = 0; ku < NKU; ++ku) {
+        u32x4_t af8[2][RB][2];
+        auto load_a8 = [&](int q, int slot) {
 #pragma unroll
           for (int rb = 0; rb < RB; ++rb) {
-            const u32x4_t a0 = *(const u32x4_t*)(abase + rb * 16 * PITCH + ku * 128);
-            const u32x4_t a1 = *(const u32x4_t*)(abase + rb * 16 * PITCH + ku * 128 + 16);
+            af8[slot][rb][0] = *(const u32x4_t*)(abase + rb * 16 * PITCH + q * 128);
+            af8[slot][rb][1] = *(const u32x4_t*)(abase + rb * 16 * PITCH + q * 128 + 16);
+          }
+        };
+        load_a8(0, 0);
+#pragma unroll
+        for (int ku = 0; ku < NKU; ++ku) {
+          if (ku + 1 < NKU) load_a8(ku + 1, (ku + 1) & 1);
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb) {
             const i32x8_t a = __builtin_bit_cast(
-                i32x8_t, __builtin_shufflevector(a0, a1, 0, 1, 2, 3, 4, 5, 6, 7));
+                i32x8_t, __builtin_shufflevector(af8[ku & 1][rb][0], af8[ku & 1][rb][1], 0, 1, 2,
+                                                 3, 4, 5, 6, 7));
 #pragma unroll
             for (int cg = 0; cg < NCG; ++cg) {
               const i32x8_t b = __builtin_bit_cast(
@@ -289,7 +322,8 @@ __device__ __forceinline__ void assign_block(const AssignArgs& A, int64_t blk,
         }
       } else {
       // A fragments run PF units ahead of the MFMAs that use them; the
-      // scheduling barrier keeps the compiler from sinking the reads.
+      // scheduling barrier keeps the compiler from sinking the reads next to
+      // their use (which would expose the LDS latency at every unit).
       constexpr int NB = PF + 1;
       u32x4_t afr[NB][RB];
       const unsigned char* abase = &lds[buf * BUFB + prow * PITCH + grp * 16];
@@ -306,7 +340,7 @@ __device__ __forceinline__ void assign_block(const AssignArgs& A, int64_t blk,
             afr[(ku + PF) % NB][rb] =
                 *(const u32x4_t*)(abase + rb * 16 * PITCH + (ku + PF) * 64);
         }
-        if (PF > 1) __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
           const u32x4_t a = afr[ku % NB][rb];
@@ -340,19 +374,7 @@ __device__ __forceinline__ void assign_block(const AssignArgs& A, int64_t blk,
 #pragma unroll
           for (int rb = 0; rb < RB; ++rb) accp[cg][rb] = acc[cg][rb];
       } else if constexpr (PK) {
-        const unsigned ibase = mask - (unsigned)(t * BN + grp * 4);
-#pragma unroll
-        for (int rb = 0; rb < RB; ++rb) {
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const unsigned idx = ibase - (unsigned)(rb * 16 + i);
-#pragma unroll
-            for (int cg = 0; cg < NCG; ++cg) {
-              const unsigned key = (__float_as_uint(acc[cg][rb][i]) & ~mask) | idx;
-              top4_insert(key, v1[cg], v2[cg], v3[cg], v4[cg]);
-            }
-          }
-        }
+        if (!late) insert_tile(acc, t);
       } else {
         // centers arrive in increasing index order per lane: a strict '>'
         // keeps the lower index on ties
@@ -378,6 +400,9 @@ __device__ __forceinline__ void assign_block(const AssignArgs& A, int64_t blk,
 
       if (t + 1 < ntiles) finish_tile(buf ^ 1);
       __syncthreads();
+      if constexpr (PK && !PIPE) {
+        if (late) insert_tile(acc, t);
+      }
     }
     if constexpr (PIPE) {
       const unsigned ibase_p = mask - (unsigned)((ntiles - 1) * BN + grp * 4);
@@ -716,7 +741,7 @@ hipError_t launch_assign(hipStream_t s, int prec, const float* X, int64_t ldx, c
       case 1: KMX_A(1, 4, 64, 8, true);
       case 2: KMX_A(2, 4, 64, 8, false);
       case 3: KMX_A(3, 2, 64, 8, false);
-      case 4: KMX_A(4, 2, 32, 8, true);
+      case 4: KMX_A(4, 2, 32, 4, true);
       case 6: KMX_A(6, 1, 32, 8, true);
       case 8: KMX_A(8, 1, 16, 8, true);
       default: return hipErrorInvalidValue;

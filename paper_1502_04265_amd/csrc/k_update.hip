@@ -109,11 +109,15 @@ __global__ __launch_bounds__(1024) void scan_top_kernel(int32_t* __restrict__ se
   for (int q = 0; q < per; ++q) {
     const int j = j0 + q;
     if (j < k) {
+      // all segment sums of the column in flight at once
+      int v[kScanSegs];
+#pragma unroll
+      for (int s = 0; s < kScanSegs; ++s) v[s] = segsum[(int64_t)s * k + j];
       int run = 0;
+#pragma unroll
       for (int s = 0; s < kScanSegs; ++s) {
-        const int v = segsum[(int64_t)s * k + j];
         segsum[(int64_t)s * k + j] = run;
-        run += v;
+        run += v[s];
       }
       tot_local += run;
       ch_local += (run + kReduceRows - 1) / kReduceRows;
@@ -222,9 +226,15 @@ hipError_t launch_sort(hipStream_t s, const int32_t* label, int32_t* lab_prev, i
 }
 
 // ---- 6. chunk reduction: FP64 (S, Q, W) over at most kReduceRows rows ----
-// Four waves walk the chunk's rows in an interleaved, fixed order; a lane owns
-// VEC consecutive columns in each of M column groups of 64*VEC.
-template <int VEC, int M>
+// The chunk's row ids and weights are staged in LDS first.  Four waves walk
+// the chunk's rows in an interleaved, fixed order (wave v: rows v, v + 4,
+// ...).  A wave is split into SUB = 64 / LPR sub-waves of LPR lanes, each on
+// its own row, so short rows still occupy every lane; a lane owns VEC
+// consecutive columns in each of M column groups of LPR*VEC.  Each step takes
+// UR rows per sub-wave; the next step's rows are loaded while the current
+// step is summed.  The sub-waves' partial sums are combined by a butterfly
+// (same bits on every lane), the waves in a fixed order.
+template <int VEC, int M, int LPR>
 __global__ __launch_bounds__(256) void reduce_kernel(const float* __restrict__ X, int d,
                                                      int64_t ldx, const float* __restrict__ w,
                                                      const int32_t* __restrict__ perm,
@@ -235,8 +245,14 @@ __global__ __launch_bounds__(256) void reduce_kernel(const float* __restrict__ X
                                                      double* __restrict__ partW,
                                                      const int* __restrict__ gate) {
   if (gate && *gate) return;
-  __shared__ double sh[4][64 * VEC * M];
+  constexpr int SUB = 64 / LPR;     // rows side by side in a wave
+  constexpr int CB = LPR * VEC * M; // columns per pass
+  constexpr int UR = 4;             // rows per sub-wave and step
+  constexpr int RS = 4 * SUB;       // row stride between a sub-wave's rows
+  __shared__ double sh[4][CB];
   __shared__ double shq[4], shw[4];
+  __shared__ int srow[kReduceRows];
+  __shared__ float swt[kReduceRows];
   const int cidx = blockIdx.x;
   if (cidx >= chunk_base[k]) return;
   // cluster owning this chunk: last j with chunk_base[j] <= cidx
@@ -248,9 +264,16 @@ __global__ __launch_bounds__(256) void reduce_kernel(const float* __restrict__ X
   const int j = lo;
   const int64_t r0 = (int64_t)base[j] + (int64_t)(cidx - chunk_base[j]) * kReduceRows;
   const int64_t r1 = min((int64_t)base[j + 1], r0 + kReduceRows);
+  const int nr = (int)(r1 - r0);
+  for (int t = threadIdx.x; t < nr; t += 256) {
+    const int i = perm[r0 + t];
+    srow[t] = i;
+    swt[t] = w ? w[i] : 1.0f;
+  }
+  __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  constexpr int CB = 64 * VEC * M;  // columns per pass
-  constexpr int UR = 4;             // rows in flight per wave
+  const int sub = lane / LPR, sl = lane % LPR;
+  const int first = wv + 4 * sub;   // this sub-wave's rows: first, first + RS, ...
   double qacc = 0.0, wacc = 0.0;
   for (int cb = 0; cb < d; cb += CB) {
     double S[M][VEC], Q[M][VEC];
@@ -258,20 +281,16 @@ __global__ __launch_bounds__(256) void reduce_kernel(const float* __restrict__ X
     for (int m = 0; m < M; ++m)
 #pragma unroll
       for (int v = 0; v < VEC; ++v) S[m][v] = Q[m][v] = 0.0;
-    // wave wv takes rows r0 + wv, r0 + wv + 4, ... in order, UR per step
-    for (int64_t rb = r0 + wv; rb < r1; rb += 4 * UR) {
-      float xv[UR][M][VEC];
-      double wt[UR];
+    // rows t0 + RS u of one step, zeros past the chunk
+    auto load_step = [&](int t0, float (&xv)[UR][M][VEC]) {
 #pragma unroll
       for (int u = 0; u < UR; ++u) {
-        const int64_t r = rb + 4 * u;
-        const bool rv = r < r1;
-        const int64_t i = rv ? (int64_t)perm[r] : 0;
-        wt[u] = rv ? (w ? (double)w[i] : 1.0) : 0.0;
-        const float* xr = X + i * ldx + cb;
+        const int t = t0 + RS * u;
+        const bool rv = t < nr;
+        const float* xr = X + (int64_t)(rv ? srow[t] : 0) * ldx + cb;
 #pragma unroll
         for (int m = 0; m < M; ++m) {
-          const int c0 = (m * 64 + lane) * VEC;
+          const int c0 = (m * LPR + sl) * VEC;
           if (VEC == 4 && rv && cb + c0 + 4 <= d) {
             const float4 t4 = *(const float4*)(xr + c0);
             xv[u][m][0] = t4.x;
@@ -283,26 +302,45 @@ __global__ __launch_bounds__(256) void reduce_kernel(const float* __restrict__ X
           }
         }
       }
+    };
+    float xa[UR][M][VEC], xb[UR][M][VEC];
+    load_step(first, xa);
+    for (int t0 = first; t0 < nr; t0 += RS * UR) {
+      const bool more = t0 + RS * UR < nr;
+      if (more) load_step(t0 + RS * UR, xb);
 #pragma unroll
       for (int u = 0; u < UR; ++u) {
-        if (cb == 0) wacc += wt[u];
+        const int t = t0 + RS * u;
+        const double wt = (t < nr) ? (double)swt[t] : 0.0;
+        if (cb == 0) wacc += wt;
 #pragma unroll
         for (int m = 0; m < M; ++m)
 #pragma unroll
           for (int q = 0; q < VEC; ++q) {
-            const double xd = (double)xv[u][m][q];
-            const double wx = wt[u] * xd;
+            const double xd = (double)xa[u][m][q];
+            const double wx = wt * xd;
             S[m][q] += wx;
             Q[m][q] = fma(wx, xd, Q[m][q]);
           }
       }
+      if (more) {
+#pragma unroll
+        for (int u = 0; u < UR; ++u)
+#pragma unroll
+          for (int m = 0; m < M; ++m)
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) xa[u][m][q] = xb[u][m][q];
+      }
     }
-    // combine the four waves in a fixed order
+    // sub-waves, then waves, in a fixed order
 #pragma unroll
     for (int m = 0; m < M; ++m)
 #pragma unroll
       for (int q = 0; q < VEC; ++q) {
-        sh[wv][(m * 64 + lane) * VEC + q] = S[m][q];
+        double v = S[m][q];
+#pragma unroll
+        for (int o = LPR; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
+        if (sub == 0) sh[wv][(m * LPR + sl) * VEC + q] = v;
         qacc += Q[m][q];
       }
     __syncthreads();
@@ -313,6 +351,8 @@ __global__ __launch_bounds__(256) void reduce_kernel(const float* __restrict__ X
     __syncthreads();
   }
   qacc = wave_sum_f64(qacc);
+#pragma unroll
+  for (int o = LPR; o < 64; o <<= 1) wacc += __shfl_xor(wacc, o, 64);
   if (lane == 0) {
     shq[wv] = qacc;
     shw[wv] = wacc;
@@ -331,16 +371,22 @@ hipError_t launch_reduce(hipStream_t s, const float* X, int64_t n, int d, int64_
   const int64_t maxchunks = (n + kReduceRows - 1) / kReduceRows + k;
   const bool vec = ((((uintptr_t)X) & 15) == 0) && (ldx % 4 == 0);
   dim3 g((unsigned)maxchunks);
-  if (vec && d > 256) {
-    hipLaunchKernelGGL((reduce_kernel<4, 2>), g, dim3(256), 0, s, X, d, ldx, w, perm, base,
-                       chunk_base, k, partS, partQ, partW, gate);
-  } else if (vec && d > 64) {
-    hipLaunchKernelGGL((reduce_kernel<4, 1>), g, dim3(256), 0, s, X, d, ldx, w, perm, base,
-                       chunk_base, k, partS, partQ, partW, gate);
+#define KMX_R(V, M, L)                                                                         \
+  hipLaunchKernelGGL((reduce_kernel<V, M, L>), g, dim3(256), 0, s, X, d, ldx, w, perm, base, \
+                     chunk_base, k, partS, partQ, partW, gate)
+  // columns per pass: LPR * VEC * M, the smallest shape covering d (or 512)
+  if (vec) {
+    if (d > 256) KMX_R(4, 2, 64);
+    else if (d > 128) KMX_R(4, 1, 64);
+    else if (d > 64) KMX_R(4, 1, 32);
+    else if (d > 32) KMX_R(4, 1, 16);
+    else KMX_R(4, 1, 8);
   } else {
-    hipLaunchKernelGGL((reduce_kernel<1, 1>), g, dim3(256), 0, s, X, d, ldx, w, perm, base,
-                       chunk_base, k, partS, partQ, partW, gate);
+    if (d > 32) KMX_R(1, 1, 64);
+    else if (d > 16) KMX_R(1, 1, 32);
+    else KMX_R(1, 1, 16);
   }
+#undef KMX_R
   return hipGetLastError();
 }
 

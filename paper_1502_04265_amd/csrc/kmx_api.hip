@@ -334,7 +334,7 @@ kmx_status kmx_destroy(kmx_ctx* ctx) {
       &ctx->nbd,       &ctx->fbh,      &ctx->xq8,        &ctx->sx8,        &ctx->rowstats8,
       &ctx->xstats8,   &ctx->cq8,      &ctx->ch8,        &ctx->hd8,        &ctx->cstats8,
       &ctx->full_rows2, &ctx->bX,       &ctx->bXq,        &ctx->brs,        &ctx->bw,
-      &ctx->bC,        &ctx->bCq,      &ctx->bhd,        &ctx->bch,        &ctx->bcs,        &ctx->blab,
+      &ctx->bC,        &ctx->bCq,      &ctx->bhd,        &ctx->bch,        &ctx->vt,        &ctx->bcs,        &ctx->blab,
       &ctx->bitems,    &ctx->binsts,   &ctx->bbuckets,   &ctx->bcinst,     &ctx->bxstats,
       &ctx->btermC,    &ctx->btermMu,  &ctx->bW,         &ctx->bcost};
   for (kmx::Buf* b : bufs)
@@ -508,8 +508,10 @@ kmx_status kmx_project(kmx_ctx* ctx, const float* X, int64_t rows, int32_t d_in,
   if (ldy < d_out || ldy % 4 != 0 || (((uintptr_t)Y) & 15))
     return fail(ctx, KMX_EINVAL, "Y needs 16-byte alignment and ldy >= d_out, ldy % 4 == 0");
   KMX_TRY(set_device(ctx));
+  KMX_TRY(grow(ctx, ctx->vt, (size_t)d_out * project_dpad(d_in) * sizeof(float)));
   Timed tm(ctx, T_PROJECT);
-  KMX_HIP(ctx, launch_project(ctx->stream, X, rows, d_in, ldx, V, d_out, Y, ldy, ctx->num_cus));
+  KMX_HIP(ctx, launch_project(ctx->stream, X, rows, d_in, ldx, V, d_out, Y, ldy, P<float>(ctx->vt),
+                              ctx->num_cus));
   return KMX_OK;
 }
 

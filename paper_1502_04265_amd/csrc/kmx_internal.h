@@ -136,75 +136,6 @@ constexpr int kRouterMaxK = 4096;   // largest k the router supports
 constexpr int kNbrL = 32;           // sorted neighbours kept per center
 constexpr int kRouterMaxBatch = 65536;  // largest training batch
 
-// batched (k_assign.hip, k_batch.hip)
-int batched_group(int d);                     // width group (one kernel per group)
-hipError_t launch_assign_batched(hipStream_t s, int group, const BatchItem* items, int begin,
-                                 int end, const BatchInst* insts, FlagEntry* flags, int* brute,
-                                 LoopState* st, int32_t* label, int grid);
-hipError_t launch_recheck_batched(hipStream_t s, const BatchBucket* buckets, int nbuckets,
-                                  const BatchInst* insts, int ninst, int32_t* label,
-                                  const FlagEntry* flags, const int* brute, const LoopState* st,
-                                  int64_t nrows, int num_cus);
-hipError_t launch_batch_reset(hipStream_t s, const BatchInst* insts, int ninst, LoopState* st,
-                              unsigned* work_ctr);
-hipError_t launch_batch_prep_centers(hipStream_t s, const BatchInst* insts, const int* cinst,
-                                     int npad);
-hipError_t launch_batch_cost(hipStream_t s, const BatchInst* insts, int ninst,
-                             const double* termC, double* cost, int stride, LoopState* st,
-                             int advance);
-hipError_t launch_batch_labels(hipStream_t s, const int32_t* glabel, int64_t grow0, int n,
-                               int koff, int32_t* out);
-
-// projection (k_project.hip)
-hipError_t launch_project(hipStream_t s, const float* X, int64_t rows, int d_in, int64_t ldx,
-                          const float* V, int d_out, float* Y, int64_t ldy, int num_cus);
-
-// router: inference (k_router.hip)
-int router_units(int d, int dp);
-hipError_t launch_router_layout(hipStream_t s, const float* W1, const float* W2, const float* b2,
-                                int d, int k, int kpad, int r1, uint16_t* W1a, uint16_t* W2a,
-                                float* b2p);
-hipError_t launch_router_fwd(hipStream_t s, const uint16_t* Xq, int64_t dp, int64_t n, int d,
-                             const uint16_t* W1a, const float* b1, const uint16_t* W2a,
-                             const float* b2p, int kpad, uint32_t* keys, const int* gate,
-                             int num_cus);
-hipError_t launch_router_decode(hipStream_t s, const uint32_t* keys, int64_t count, int k,
-                                int kpad, int32_t* cand);
-hipError_t launch_center_table(hipStream_t s, const float* C, int k, int d, float* D, int32_t* nbr,
-                               float* nbd, const int* gate);
-hipError_t launch_router_cert(hipStream_t s, const uint16_t* Xq, int64_t dp, int64_t n, int d,
-                              const float* C, int k, const RowStats* rs, const uint32_t* keys,
-                              int kpad, const int32_t* nbr, const float* nbd, int32_t* label,
-                              FlagEntry* flags, int* fb_rows, LoopState* st, const int* gate,
-                              int num_cus);
-hipError_t launch_record_fallback(hipStream_t s, const LoopState* st, int64_t* fbh, int slot,
-                                  int all_rows, int64_t all, const int* gate);
-
-// router: training (k_train.hip)
-hipError_t launch_gather_batch(hipStream_t s, const float* X, int64_t n, int d, int64_t ldx,
-                               const int32_t* labels, uint64_t total, int64_t first, int bsz,
-                               int d8, int shuffle, uint64_t key, int k, uint16_t* Xb,
-                               int32_t* yb);
-int gemm_splits(int M, int N, int K, int num_cus, int* kchunk);
-hipError_t launch_gemm_bf16(hipStream_t s, int M, int N, int K, const uint16_t* A, int64_t lda,
-                            bool ak, const uint16_t* B, int64_t ldb, bool bk, float* Cp, int splits,
-                            int kchunk);
-hipError_t launch_ep_hidden(hipStream_t s, const float* P, int S, int M, int N, const float* bias,
-                            const uint16_t* Hb, uint16_t* out, int mode);
-hipError_t launch_softmax_ce(hipStream_t s, const float* P, int bsz, int k, int k8,
-                             const float* b2, const int32_t* yb, uint16_t* dZ, float* lossrow);
-hipError_t launch_sum_partials(hipStream_t s, const float* P, int S, int64_t zstride, int rows,
-                               int cols, int ldp, float* out);
-int colsum_segments(int rows);
-hipError_t launch_colsum(hipStream_t s, const uint16_t* Mx, int rows, int cols, int ld,
-                         float* part, float* out);
-hipError_t launch_loss_mean(hipStream_t s, const float* lossrow, int bsz, double* out);
-hipError_t launch_adam(hipStream_t s, float* p, const float* g, float* m, float* v, int rows,
-                       int cols, float lr, float beta1, float beta2, float eps, float bc1, float bc2,
-                       uint16_t* bf, int ldb);
-hipError_t launch_to_bf16_pad(hipStream_t s, const float* src, int rows, int cols, int prow,
-                              int ldb, uint16_t* dst);
-
 }  // namespace kmx
 
 struct kmx_ctx {
@@ -238,6 +169,7 @@ struct kmx_ctx {
   kmx::Buf scratch_c, hist;
   kmx::Buf fb_rows, keys, cdist, nbr, nbd, fbh;   // routed assignment
   // batched Lloyd: concatenated instances and their descriptors
+  kmx::Buf vt;                          // transposed projection basis
   kmx::Buf bX, bXq, brs, bw, bC, bCq, bhd, bch, bcs, blab, bitems, binsts, bbuckets, bcinst, bxstats;
   kmx::Buf btermC, btermMu, bW, bcost;
   hipStream_t cap_stream = nullptr;                // stream the batched iteration is captured on
@@ -333,7 +265,9 @@ hipError_t launch_batch_labels(hipStream_t s, const int32_t* glabel, int64_t gro
 
 // projection (k_project.hip)
 hipError_t launch_project(hipStream_t s, const float* X, int64_t rows, int d_in, int64_t ldx,
-                          const float* V, int d_out, float* Y, int64_t ldy, int num_cus);
+                          const float* V, int d_out, float* Y, int64_t ldy, float* Vt,
+                          int num_cus);
+int project_dpad(int d_in);            // row length of the transposed basis workspace
 
 // router: inference (k_router.hip)
 int router_units(int d, int dp);

@@ -142,7 +142,10 @@ def test_assign_multiway_near_ties(ctx, m):
 # update and cost
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("n,d,k,weighted", [(5000, 64, 10, False), (3001, 37, 67, True),
-                                            (1200, 700, 5, True), (300, 1, 3, False)])
+                                            (1200, 700, 5, True), (300, 1, 3, False),
+                                            (4000, 16, 7, True), (2500, 30, 9, False),
+                                            (3000, 100, 12, True), (2000, 200, 6, False),
+                                            (1500, 7, 4, True), (20000, 24, 3, True)])
 def test_update_matches_oracle(ctx, n, d, k, weighted):
     say(f"update n={n} d={d} k={k} w={weighted}")
     rng = np.random.default_rng(n + d)

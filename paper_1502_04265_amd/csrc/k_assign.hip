@@ -766,275 +766,6 @@ hipError_t launch_assign(hipStream_t s, int prec, const float* X, int64_t ldx, c
 #undef KMX_A
 }
 
-// ---------------------------------------------------------------------------
-// Re-check of flagged rows.  One wave per list entry.
-//   pair entry: exact comparison of the two listed centers;
-//   full entry: plain FP32 distances to every center (lanes split the
-//     coordinates, 64 centers at a time, transposed through LDS), then the
-//     exact comparison among the centers inside the FP32 error band of the
-//     minimum.
-// Exact = FP32 direct differences with TwoSum/TwoProd double-float sums.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ void exact_dist(const float* __restrict__ x,
-                                           const float* __restrict__ c, int d, int lane,
-                                           float& hi, float& lo) {
-  float s = 0.f, e = 0.f;
-  for (int q = lane; q < d; q += 64) df_acc_sqdiff(x[q], c[q], s, e);
-  wave_sum_df(s, e);
-  df_norm(s, e, hi, lo);
-}
-
-// Short re-check: the listed 2 or 3 candidates, one wave per entry.  Plain
-// FP32 distances first: each lane sums the squares of its own coordinates
-// (four consecutive ones per 256-column step, or one per 64-column step when
-// rows are not 16-byte aligned: at most ceil(d/64) + 3 terms), then a 6-level
-// butterfly, so the relative error is below (ceil(d/64) + 13) u.  When the
-// best plain distance beats every other candidate by more than that bound the
-// result is exact; otherwise the candidates are compared with double-float
-// sums.  The next entry and its current label are fetched one entry ahead.
-__device__ __forceinline__ void plain_dist3(const float* __restrict__ x,
-                                            const float* __restrict__ c0,
-                                            const float* __restrict__ c1,
-                                            const float* __restrict__ c2, int d, int lane,
-                                            bool vec, float& p0, float& p1, float& p2) {
-  float a0 = 0.f, a1 = 0.f, a2 = 0.f;
-  if (vec) {
-    for (int q = lane * 4; q < d; q += 256) {
-      const float4 xv = *(const float4*)(x + q);
-      const float4 u0 = *(const float4*)(c0 + q);
-      const float4 u1 = *(const float4*)(c1 + q);
-      const float4 u2 = *(const float4*)(c2 + q);
-      const float xs[4] = {xv.x, xv.y, xv.z, xv.w};
-      const float v0[4] = {u0.x, u0.y, u0.z, u0.w};
-      const float v1[4] = {u1.x, u1.y, u1.z, u1.w};
-      const float v2[4] = {u2.x, u2.y, u2.z, u2.w};
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        float df = xs[e] - v0[e];
-        a0 = __builtin_fmaf(df, df, a0);
-        df = xs[e] - v1[e];
-        a1 = __builtin_fmaf(df, df, a1);
-        df = xs[e] - v2[e];
-        a2 = __builtin_fmaf(df, df, a2);
-      }
-    }
-  } else {
-    for (int q = lane; q < d; q += 64) {
-      const float xq = x[q];
-      float df = xq - c0[q];
-      a0 = __builtin_fmaf(df, df, a0);
-      df = xq - c1[q];
-      a1 = __builtin_fmaf(df, df, a1);
-      df = xq - c2[q];
-      a2 = __builtin_fmaf(df, df, a2);
-    }
-  }
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) {
-    a0 += __shfl_xor(a0, m, 64);
-    a1 += __shfl_xor(a1, m, 64);
-    a2 += __shfl_xor(a2, m, 64);
-  }
-  p0 = a0;
-  p1 = a1;
-  p2 = a2;
-}
-
-__global__ __launch_bounds__(256) void recheck_pair_kernel(
-    const float* __restrict__ X, int64_t n, int d, int64_t ldx, const float* __restrict__ C,
-    int k, int32_t* __restrict__ label, float* __restrict__ d1o,
-    const FlagEntry* __restrict__ flags, const LoopState* __restrict__ st,
-    const int* __restrict__ gate) {
-  if (gate && *gate) return;
-  const int64_t cnt = (int64_t)st->flagged;
-  const int lane = threadIdx.x & 63;
-  const int64_t gw = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int64_t nw = (int64_t)gridDim.x * 4;
-  const float tol = (float)((d + 63) / 64 + 13) * 5.9604645e-8f;
-  const bool vec = ((((uintptr_t)X) & 15) == 0) && (ldx % 4 == 0) &&
-                   ((((uintptr_t)C) & 15) == 0) && (d % 4 == 0);
-  // entries each row appears in at most once, so a label fetched ahead is
-  // never one this kernel writes before reading it
-  FlagEntry fe_n = {-1, -1, -1, 0};
-  int lab_n = 0;
-  if (gw < cnt) {
-    fe_n = flags[gw];
-    lab_n = (fe_n.row >= 0 && fe_n.row < n) ? label[fe_n.row] : 0;
-  }
-  for (int64_t e = gw; e < cnt; e += nw) {
-    const FlagEntry fe = fe_n;
-    const int lab = lab_n;
-    if (e + nw < cnt) {
-      fe_n = flags[e + nw];
-      lab_n = (fe_n.row >= 0 && fe_n.row < n) ? label[fe_n.row] : 0;
-    }
-    const int row = fe.row;
-    if (row < 0 || row >= n) continue;
-    const float* x = X + (int64_t)row * ldx;
-    int cj[3];
-    cj[0] = min(max(lab, 0), k - 1);
-    cj[1] = min(max(fe.cand2, 0), k - 1);
-    cj[2] = fe.cand3 >= 0 ? min(fe.cand3, k - 1) : -1;
-    const int nc = (cj[2] >= 0) ? 3 : 2;
-    float p[3];
-    plain_dist3(x, C + (int64_t)cj[0] * d, C + (int64_t)cj[1] * d,
-                C + (int64_t)(nc == 3 ? cj[2] : cj[1]) * d, d, lane, vec, p[0], p[1], p[2]);
-    int b = 0;
-    for (int q = 1; q < nc; ++q)
-      if (p[q] < p[b] || (p[q] == p[b] && cj[q] < cj[b])) b = q;
-    bool sure = true;
-    for (int q = 0; q < nc; ++q)
-      if (q != b && !(p[q] - p[b] > tol * (p[q] + p[b]))) sure = false;
-    int best = cj[b];
-    float bd = p[b];
-    if (!sure) {
-      float bh = 0.f, bl = 0.f;
-      for (int q = 0; q < nc; ++q) {
-        float h, l;
-        exact_dist(x, C + (int64_t)cj[q] * d, d, lane, h, l);
-        if (q == 0 || df_less(h, l, bh, bl) || (h == bh && l == bl && cj[q] < best)) {
-          bh = h; bl = l; best = cj[q];
-        }
-      }
-      bd = bh;
-    }
-    if (lane == 0) {
-      label[row] = best;
-      if (d1o) d1o[row] = bd;
-    }
-  }
-}
-
-// One workgroup per row that needs every center.  Each wave takes four
-// centers at a time (centers 16i + 4w + 0..3 for wave w), its lanes splitting
-// the coordinates as in the short re-check, so every plain distance has
-// relative error below gamma = (ceil(d/64) + 13) u.  Pass 1: the minimum m
-// of the plain distances.  Pass 2: the same plain distances again (same
-// operations, same bits); exact double-float distances for the centers at
-// most m (1 + gamma) / (1 - gamma) (the only ones that can be the minimum);
-// lexicographic argmin with the lowest index on ties.
-__device__ __forceinline__ void plain_dist4(const float* __restrict__ x,
-                                            const float* __restrict__ C, int j0, int k, int d,
-                                            int lane, bool vec, float* p) {
-  const float* c[4];
-#pragma unroll
-  for (int t = 0; t < 4; ++t) c[t] = C + (int64_t)min(j0 + t, k - 1) * d;
-  float a[4] = {0.f, 0.f, 0.f, 0.f};
-  if (vec) {
-    for (int q = lane * 4; q < d; q += 256) {
-      const float4 xv = *(const float4*)(x + q);
-      const float xs[4] = {xv.x, xv.y, xv.z, xv.w};
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const float4 u = *(const float4*)(c[t] + q);
-        const float v[4] = {u.x, u.y, u.z, u.w};
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const float df = xs[e] - v[e];
-          a[t] = __builtin_fmaf(df, df, a[t]);
-        }
-      }
-    }
-  } else {
-    for (int q = lane; q < d; q += 64) {
-      const float xq = x[q];
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const float df = xq - c[t][q];
-        a[t] = __builtin_fmaf(df, df, a[t]);
-      }
-    }
-  }
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) {
-#pragma unroll
-    for (int t = 0; t < 4; ++t) a[t] += __shfl_xor(a[t], m, 64);
-  }
-#pragma unroll
-  for (int t = 0; t < 4; ++t) p[t] = (j0 + t < k) ? a[t] : __builtin_inff();
-}
-
-__global__ __launch_bounds__(256) void recheck_full_kernel(
-    const float* __restrict__ X, int64_t n, int d, int64_t ldx, const float* __restrict__ C,
-    int k, int32_t* __restrict__ label, float* __restrict__ d1o, const int* __restrict__ brute,
-    const LoopState* __restrict__ st, const int* __restrict__ gate) {
-  if (gate && *gate) return;
-  __shared__ float redf[4];
-  __shared__ float redh[4], redl[4];
-  __shared__ int redj[4];
-  const int64_t cnt = (int64_t)st->flagged_full;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const float gam = (float)((d + 63) / 64 + 13) * 5.9604645e-8f;
-  const bool vec = ((((uintptr_t)X) & 15) == 0) && (ldx % 4 == 0) &&
-                   ((((uintptr_t)C) & 15) == 0) && (d % 4 == 0);
-  for (int64_t e = blockIdx.x; e < cnt; e += gridDim.x) {
-    const int row = brute[e];
-    if (row < 0 || row >= n) continue;   // uniform across the block
-    const float* x = X + (int64_t)row * ldx;
-    float m = __builtin_inff();
-    for (int j0 = 4 * wv; j0 < k; j0 += 16) {
-      float p[4];
-      plain_dist4(x, C, j0, k, d, lane, vec, p);
-      m = fminf(m, fminf(fminf(p[0], p[1]), fminf(p[2], p[3])));
-    }
-    if (lane == 0) redf[wv] = m;
-    __syncthreads();
-    m = fminf(fminf(redf[0], redf[1]), fminf(redf[2], redf[3]));
-    const float thr = m * (1.0f + gam) / (1.0f - gam) * 1.0001f + 1e-30f;
-    float bh = __builtin_inff(), bl = 0.f;
-    int best = 0x7FFFFFFF;
-    for (int j0 = 4 * wv; j0 < k; j0 += 16) {
-      float p[4];
-      plain_dist4(x, C, j0, k, d, lane, vec, p);
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        if (p[t] <= thr) {   // wave-uniform
-          float h, l;
-          exact_dist(x, C + (int64_t)(j0 + t) * d, d, lane, h, l);
-          if (df_less(h, l, bh, bl) || (h == bh && l == bl && j0 + t < best)) {
-            bh = h; bl = l; best = j0 + t;
-          }
-        }
-      }
-    }
-    if (lane == 0) { redh[wv] = bh; redl[wv] = bl; redj[wv] = best; }
-    __syncthreads();
-    if (tid == 0) {
-      for (int w = 1; w < 4; ++w) {
-        if (df_less(redh[w], redl[w], bh, bl) || (redh[w] == bh && redl[w] == bl && redj[w] < best)) {
-          bh = redh[w]; bl = redl[w]; best = redj[w];
-        }
-      }
-      if (best < k) {
-        label[row] = best;
-        if (d1o) d1o[row] = bh;
-      }
-    }
-    __syncthreads();
-  }
-}
-
-hipError_t launch_recheck(hipStream_t s, const float* X, int64_t n, int d, int64_t ldx,
-                          const float* C, int k, int32_t* label, float* d1,
-                          const FlagEntry* flags, const int* brute, const LoopState* st,
-                          int num_cus, const int* gate) {
-  int64_t blocks = (n + 3) / 4;
-  int64_t cap = (int64_t)num_cus * 8;
-  if (blocks > cap) blocks = cap;
-  if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(recheck_pair_kernel, dim3((unsigned)blocks), dim3(256), 0, s, X, n, d, ldx,
-                     C, k, label, d1, flags, st, gate);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  cap = (int64_t)num_cus * 4;
-  blocks = n;
-  if (blocks > cap) blocks = cap;
-  if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(recheck_full_kernel, dim3((unsigned)blocks), dim3(256), 0, s, X, n, d, ldx,
-                     C, k, label, d1, brute, st, gate);
-  return hipGetLastError();
-}
-
 }  // namespace kmx
 
 namespace kmx {
@@ -1198,156 +929,6 @@ hipError_t launch_assign_batched(hipStream_t s, int group, const BatchItem* item
     default:
       return hipErrorInvalidValue;
   }
-}
-
-// Re-check of a batched assignment: list rows are global; the bucket (pair
-// entries) or the instance (every-center entries) is found by binary search.
-__device__ __forceinline__ int find_bucket(const BatchBucket* __restrict__ b, int nb, int64_t g) {
-  int lo = 0, hi = nb - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (b[mid].grow0 <= g) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
-}
-
-__device__ __forceinline__ int find_inst(const BatchInst* __restrict__ in, int ni, int64_t g) {
-  int lo = 0, hi = ni - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (in[mid].grow0 <= g) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
-}
-
-__global__ __launch_bounds__(256) void recheck_pair_batched_kernel(
-    const BatchBucket* __restrict__ buckets, int nb, int32_t* __restrict__ label,
-    const FlagEntry* __restrict__ flags, const LoopState* __restrict__ st, int64_t nrows) {
-  const unsigned long long cnt = st->flagged;
-  const int lane = threadIdx.x & 63;
-  const int64_t gw = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int64_t nw = (int64_t)gridDim.x * 4;
-  for (int64_t e = gw; e < (int64_t)cnt; e += nw) {
-    const FlagEntry fe = flags[e];
-    const int64_t row = fe.row;
-    if (row < 0 || row >= nrows) continue;
-    const BatchBucket B = buckets[find_bucket(buckets, nb, row)];
-    const int d = B.d;
-    const float tol = (float)((d + 63) / 64 + 13) * 5.9604645e-8f;
-    const float* x = B.X + (row - B.grow0) * d;
-    const bool vec = ((((uintptr_t)B.X) & 15) == 0) && ((((uintptr_t)B.C) & 15) == 0) &&
-                     (d % 4 == 0);
-    int cj[3];
-    cj[0] = min(max(label[row], 0), B.K - 1);
-    cj[1] = min(max(fe.cand2, 0), B.K - 1);
-    cj[2] = fe.cand3 >= 0 ? min(fe.cand3, B.K - 1) : -1;
-    const int nc = (cj[2] >= 0) ? 3 : 2;
-    float p[3];
-    plain_dist3(x, B.C + (int64_t)cj[0] * d, B.C + (int64_t)cj[1] * d,
-                B.C + (int64_t)(nc == 3 ? cj[2] : cj[1]) * d, d, lane, vec, p[0], p[1], p[2]);
-    int b = 0;
-    for (int q = 1; q < nc; ++q)
-      if (p[q] < p[b] || (p[q] == p[b] && cj[q] < cj[b])) b = q;
-    bool sure = true;
-    for (int q = 0; q < nc; ++q)
-      if (q != b && !(p[q] - p[b] > tol * (p[q] + p[b]))) sure = false;
-    int best = cj[b];
-    if (!sure) {
-      float bh = 0.f, bl = 0.f;
-      for (int q = 0; q < nc; ++q) {
-        float h, l;
-        exact_dist(x, B.C + (int64_t)cj[q] * d, d, lane, h, l);
-        if (q == 0 || df_less(h, l, bh, bl) || (h == bh && l == bl && cj[q] < best)) {
-          bh = h;
-          bl = l;
-          best = cj[q];
-        }
-      }
-    }
-    if (lane == 0) label[row] = best;
-  }
-}
-
-// One workgroup per row needing every center of its instance.
-__global__ __launch_bounds__(256) void recheck_full_batched_kernel(
-    const BatchInst* __restrict__ insts, int ni, int32_t* __restrict__ label,
-    const int* __restrict__ brute, const LoopState* __restrict__ st, int64_t nrows) {
-  __shared__ float redf[4];
-  __shared__ float redh[4], redl[4];
-  __shared__ int redj[4];
-  const unsigned long long cnt = st->flagged_full;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  for (int64_t e = blockIdx.x; e < (int64_t)cnt; e += gridDim.x) {
-    const int64_t row = brute[e];
-    if (row < 0 || row >= nrows) continue;   // uniform across the block
-    const BatchInst& I = insts[find_inst(insts, ni, row)];
-    const int d = I.d;
-    const float gam = (float)((d + 63) / 64 + 13) * 5.9604645e-8f;
-    const float* x = I.X + (I.row0 + (row - I.grow0)) * d;
-    const float* C = I.C + (int64_t)I.koff * d;
-    const bool vec = ((((uintptr_t)x) & 15) == 0) && ((((uintptr_t)C) & 15) == 0) && (d % 4 == 0);
-    float m = __builtin_inff();
-    for (int j0 = 4 * wv; j0 < I.k; j0 += 16) {
-      float p[4];
-      plain_dist4(x, C, j0, I.k, d, lane, vec, p);
-      m = fminf(m, fminf(fminf(p[0], p[1]), fminf(p[2], p[3])));
-    }
-    if (lane == 0) redf[wv] = m;
-    __syncthreads();
-    m = fminf(fminf(redf[0], redf[1]), fminf(redf[2], redf[3]));
-    const float thr = m * (1.0f + gam) / (1.0f - gam) * 1.0001f + 1e-30f;
-    float bh = __builtin_inff(), bl = 0.f;
-    int best = 0x7FFFFFFF;
-    for (int j0 = 4 * wv; j0 < I.k; j0 += 16) {
-      float p[4];
-      plain_dist4(x, C, j0, I.k, d, lane, vec, p);
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        if (p[t] <= thr) {   // wave-uniform
-          float h, l;
-          exact_dist(x, C + (int64_t)(j0 + t) * d, d, lane, h, l);
-          if (df_less(h, l, bh, bl) || (h == bh && l == bl && j0 + t < best)) {
-            bh = h;
-            bl = l;
-            best = j0 + t;
-          }
-        }
-      }
-    }
-    if (lane == 0) {
-      redh[wv] = bh;
-      redl[wv] = bl;
-      redj[wv] = best;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      for (int w = 1; w < 4; ++w) {
-        if (df_less(redh[w], redl[w], bh, bl) ||
-            (redh[w] == bh && redl[w] == bl && redj[w] < best)) {
-          bh = redh[w];
-          bl = redl[w];
-          best = redj[w];
-        }
-      }
-      if (best < I.k) label[row] = I.koff + best;
-    }
-    __syncthreads();
-  }
-}
-
-hipError_t launch_recheck_batched(hipStream_t s, const BatchBucket* buckets, int nbuckets,
-                                  const BatchInst* insts, int ninst, int32_t* label,
-                                  const FlagEntry* flags, const int* brute, const LoopState* st,
-                                  int64_t nrows, int num_cus) {
-  hipLaunchKernelGGL(recheck_pair_batched_kernel, dim3((unsigned)(num_cus * 8)), dim3(256), 0, s,
-                     buckets, nbuckets, label, flags, st, nrows);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(recheck_full_batched_kernel, dim3((unsigned)(num_cus * 4)), dim3(256), 0, s,
-                     insts, ninst, label, brute, st, nrows);
-  return hipGetLastError();
 }
 
 }  // namespace kmx

@@ -477,7 +477,7 @@ hipError_t launch_center_table(hipStream_t s, const float* C, int k, int d, floa
 // list is exhausted, or no proposal) -> GEMM row list.
 // ROUTED = false takes the previous label as the only candidate.
 // ---------------------------------------------------------------------------
-template <bool ROUTED, int NX>
+template <bool ROUTED, int NX, bool FULL>
 __global__ __launch_bounds__(256) void router_cert_kernel(
     const uint16_t* __restrict__ Xq, int64_t xs, int64_t n, int d, const float* __restrict__ C,
     int k, const RowStats* __restrict__ rs, const uint32_t* __restrict__ keys, int ib,
@@ -522,9 +522,7 @@ __global__ __launch_bounds__(256) void router_cert_kernel(
       if (ROUTED) {
         const int ci = (int)(mask - (sel & mask));
         cand = (valid && ci < k) ? ci : -1;
-        unsigned best = (cand >= 0) ? sel : 0u;
-#pragma unroll
-        for (int m = 8; m >= 1; m >>= 1) best = max(best, (unsigned)__shfl_xor((int)best, m, 64));
+        const unsigned best = row16_max((cand >= 0) ? sel : 0u);
         if (best == 0u) ok = false;
         b0 = ok ? (int)(mask - (best & mask)) : 0;
         if (b0 >= k) {
@@ -555,7 +553,7 @@ __global__ __launch_bounds__(256) void router_cert_kernel(
 #pragma unroll
         for (int i = 0; i < NX; ++i) {
           const int e0 = q * 8 + 128 * i;
-          if (e0 < d) {
+          if (FULL || e0 < d) {
             xv[i] = *(const ru32x4_t*)(xr + e0);
             ca[i] = *(const float4*)(c + e0);
             cb[i] = *(const float4*)(c + e0 + 4);
@@ -563,7 +561,7 @@ __global__ __launch_bounds__(256) void router_cert_kernel(
         }
 #pragma unroll
         for (int i = 0; i < NX; ++i) {
-          if (q * 8 + 128 * i < d) {
+          if (FULL || q * 8 + 128 * i < d) {
             const float cc[8] = {ca[i].x, ca[i].y, ca[i].z, ca[i].w,
                                  cb[i].x, cb[i].y, cb[i].z, cb[i].w};
 #pragma unroll
@@ -584,8 +582,7 @@ __global__ __launch_bounds__(256) void router_cert_kernel(
           }
         }
       }
-#pragma unroll
-      for (int m = 8; m >= 1; m >>= 1) s += __shfl_xor(s, m, 64);
+      s = row16_sum(s);
       const float dub = sqrtf(s * (1.0f + gam)) * (1.0f + 4.0f * u) + rx;
       const float R = 2.0f * dub * (1.0f + 8.0f * u);
 
@@ -684,16 +681,19 @@ hipError_t launch_router_cert(hipStream_t s, const uint16_t* Xq, int64_t dp, int
   const bool vec = ((((uintptr_t)C) & 15) == 0) && (((uintptr_t)Xq & 15) == 0) && (d % 8 == 0) &&
                    (dp % 8 == 0);
   const int nx = !vec ? 0 : d <= 128 ? 1 : d <= 256 ? 2 : d <= 512 ? 4 : d <= 1024 ? 8 : 0;
-#define KMX_C(R_, NX_)                                                                           \
-  hipLaunchKernelGGL((router_cert_kernel<R_, NX_>), dim3((unsigned)blocks), dim3(256), 0, s, Xq, \
-                     dp, n, d, C, k, rs, keys, ib, nbr, nbd, label, flags, fb_rows, st, gate)
-#define KMX_CN(R_)         \
-  switch (nx) {            \
-    case 1: KMX_C(R_, 1); break; \
-    case 2: KMX_C(R_, 2); break; \
-    case 4: KMX_C(R_, 4); break; \
-    case 8: KMX_C(R_, 8); break; \
-    default: KMX_C(R_, 0); break; \
+  // FULL: every 128-column piece lies inside the row (d = 128 NX)
+  const bool full = nx > 0 && d == 128 * nx;
+#define KMX_C(R_, NX_, F_)                                                                    \
+  hipLaunchKernelGGL((router_cert_kernel<R_, NX_, F_>), dim3((unsigned)blocks), dim3(256), 0, \
+                     s, Xq, dp, n, d, C, k, rs, keys, ib, nbr, nbd, label, flags, fb_rows, st, \
+                     gate)
+#define KMX_CN(R_)                                                 \
+  switch (nx) {                                                    \
+    case 1: if (full) KMX_C(R_, 1, true); else KMX_C(R_, 1, false); break; \
+    case 2: if (full) KMX_C(R_, 2, true); else KMX_C(R_, 2, false); break; \
+    case 4: if (full) KMX_C(R_, 4, true); else KMX_C(R_, 4, false); break; \
+    case 8: if (full) KMX_C(R_, 8, true); else KMX_C(R_, 8, false); break; \
+    default: KMX_C(R_, 0, false); break;                           \
   }
   if (keys) {
     KMX_CN(true)

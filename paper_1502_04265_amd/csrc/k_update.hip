@@ -95,10 +95,30 @@ __device__ int block_excl_scan_1024(int v, int* sh, int& total) {
 }
 
 // ---- 3. exclusive scans: segment offsets per column, cluster bases, chunk bases ----
-// One workgroup of 1024 threads.  base[j] = first sorted position of cluster
-// j (base[k] = number of valid rows); chunk_base likewise for reduction chunks.
-__global__ __launch_bounds__(1024) void scan_top_kernel(int32_t* __restrict__ segsum, int k,
-                                                        int32_t* __restrict__ base,
+// 3a. One thread per column: exclusive scan of the column over the segments
+// (in place); base[j] and chunk_base[j] temporarily hold the column's rows
+// and reduction chunks.
+__global__ __launch_bounds__(256) void scan_col_kernel(int32_t* __restrict__ segsum, int k,
+                                                       int32_t* __restrict__ base,
+                                                       int32_t* __restrict__ chunk_base,
+                                                       const int* __restrict__ gate) {
+  if (gate && *gate) return;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= k) return;
+  int run = 0;
+  for (int s = 0; s < kScanSegs; ++s) {
+    const int v = segsum[(int64_t)s * k + j];
+    segsum[(int64_t)s * k + j] = run;
+    run += v;
+  }
+  base[j] = run;
+  chunk_base[j] = (run + kReduceRows - 1) / kReduceRows;
+}
+
+// 3b. One workgroup of 1024 threads: exclusive scans of the column totals.
+// base[j] = first sorted position of cluster j (base[k] = number of valid
+// rows); chunk_base likewise for reduction chunks.
+__global__ __launch_bounds__(1024) void scan_top_kernel(int k, int32_t* __restrict__ base,
                                                         int32_t* __restrict__ chunk_base,
                                                         const int* __restrict__ gate) {
   if (gate && *gate) return;
@@ -109,20 +129,8 @@ __global__ __launch_bounds__(1024) void scan_top_kernel(int32_t* __restrict__ se
   for (int q = 0; q < per; ++q) {
     const int j = j0 + q;
     if (j < k) {
-      // all segment sums of the column in flight at once
-      int v[kScanSegs];
-#pragma unroll
-      for (int s = 0; s < kScanSegs; ++s) v[s] = segsum[(int64_t)s * k + j];
-      int run = 0;
-#pragma unroll
-      for (int s = 0; s < kScanSegs; ++s) {
-        segsum[(int64_t)s * k + j] = run;
-        run += v[s];
-      }
-      tot_local += run;
-      ch_local += (run + kReduceRows - 1) / kReduceRows;
-      base[j] = run;        // temporarily the column total
-      chunk_base[j] = (run + kReduceRows - 1) / kReduceRows;
+      tot_local += base[j];
+      ch_local += chunk_base[j];
     }
   }
   int total_rows, total_chunks;
@@ -214,8 +222,11 @@ hipError_t launch_sort(hipStream_t s, const int32_t* label, int32_t* lab_prev, i
   hipLaunchKernelGGL(scan_seg_kernel, g2, dim3(256), 0, s, counts, nb, k, segsum, gate);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(scan_top_kernel, dim3(1), dim3(1024), 0, s, segsum, k, base, chunk_base,
-                     gate);
+  hipLaunchKernelGGL(scan_col_kernel, dim3((unsigned)((k + 255) / 256)), dim3(256), 0, s, segsum,
+                     k, base, chunk_base, gate);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(scan_top_kernel, dim3(1), dim3(1024), 0, s, k, base, chunk_base, gate);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(scan_fill_kernel, g2, dim3(256), 0, s, counts, nb, k, segsum, base, gate);

@@ -38,6 +38,38 @@ __device__ __forceinline__ float wave_sum_f32(float v) {
   return v;
 }
 
+// Reductions over the 16 lanes of a DPP row (lanes 16r .. 16r + 15) with
+// data-parallel-primitive moves: swaps of neighbours (quad permutations
+// [1,0,3,2] and [2,3,0,1]), then the half-row and row mirrors.  Every lane
+// of the row ends with the same bits (each step adds a value to its partner's
+// value; addition and max are commutative).
+__device__ __forceinline__ int dpp_xor1(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);
+}
+__device__ __forceinline__ int dpp_xor2(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);
+}
+__device__ __forceinline__ int dpp_half_mirror(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, false);
+}
+__device__ __forceinline__ int dpp_mirror(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, false);
+}
+__device__ __forceinline__ float row16_sum(float v) {
+  v += __int_as_float(dpp_xor1(__float_as_int(v)));
+  v += __int_as_float(dpp_xor2(__float_as_int(v)));
+  v += __int_as_float(dpp_half_mirror(__float_as_int(v)));
+  v += __int_as_float(dpp_mirror(__float_as_int(v)));
+  return v;
+}
+__device__ __forceinline__ unsigned row16_max(unsigned v) {
+  v = max(v, (unsigned)dpp_xor1((int)v));
+  v = max(v, (unsigned)dpp_xor2((int)v));
+  v = max(v, (unsigned)dpp_half_mirror((int)v));
+  v = max(v, (unsigned)dpp_mirror((int)v));
+  return v;
+}
+
 // Error-free transformations (Knuth's TwoSum; FMA-based product).
 __device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
   s = a + b;

@@ -185,11 +185,13 @@ def test_lloyd_routed_identical_to_plain(ctx, mode, prec):
         assert min(rows) > 0.9 * n
 
 
-@pytest.mark.parametrize("n,d,k", [(5000, 37, 20), (6000, 200, 40), (3000, 1000, 30)])
+@pytest.mark.parametrize("n,d,k", [(5000, 37, 20), (6000, 200, 40), (3000, 1000, 30),
+                                   (4000, 128, 16), (4000, 256, 24)])
 def test_lloyd_routed_identical_other_widths(ctx, n, d, k):
     """The certificate's distance pass for other row widths (a generic loop
-    for d not a multiple of 8, rows held in 2 or 8 register pieces): routed
-    iterations with previous labels reproduce the plain ones bit for bit."""
+    for d not a multiple of 8, rows held in 1, 2 or 8 register pieces, with
+    and without a partial last piece): routed iterations with previous labels
+    reproduce the plain ones bit for bit."""
     say(f"lloyd routed widths n={n} d={d} k={k}")
     X, _, _ = synth.router_mixture(n, d, k, seed=d)
     Xd = _dev(X)

@@ -645,7 +645,7 @@ int assign_dpad(int prec, int d) {
 // Centers per LDS tile: each of the two tile buffers stays within ~72 KB.
 int assign_tile_n(int prec, int d) {
   const int nku = units_for(prec, d);
-  if (prec == KMX_FP8E4M3) return nku <= 3 ? 64 : (nku <= 6 ? 32 : 16);
+  if (prec == KMX_FP8E4M3) return nku <= 4 ? 64 : (nku <= 6 ? 32 : 16);
   if (prec == KMX_BF16) return (nku <= 3 || nku == 6 || nku == 8) ? 64 : 32;
   if (nku <= 4) return 64;
   if (nku <= 32) return 32;
@@ -661,6 +661,7 @@ static hipError_t run_assign(hipStream_t s, const void* Xsrc, int64_t xs, int ve
                              FlagEntry* flags, int* full_rows, unsigned long long* full_ctr,
                              int cascade_all, int* brute, LoopState* st, const int* gate,
                              int num_cus) {
+  if (kpad % BN != 0) return hipErrorInvalidValue;   // center padding must match the tile
   AssignArgs A;
   A.Xsrc = Xsrc;
   A.xs = xs;
@@ -741,7 +742,7 @@ hipError_t launch_assign(hipStream_t s, int prec, const float* X, int64_t ldx, c
       case 1: KMX_A(1, 4, 64, 8, true);
       case 2: KMX_A(2, 4, 64, 8, false);
       case 3: KMX_A(3, 2, 64, 8, false);
-      case 4: KMX_A(4, 2, 32, 4, true);
+      case 4: KMX_A(4, 2, 64, 8, false);
       case 6: KMX_A(6, 1, 32, 8, true);
       case 8: KMX_A(8, 1, 16, 8, true);
       default: return hipErrorInvalidValue;

@@ -70,6 +70,30 @@ def rotated_mixture(n: int, d: int, K: int, seed: int = 0, lo: float = -5.0,
     return X, means
 
 
+def rotated_mixture_device(n: int, d: int, K: int, seed: int = 0, lo: float = -5.0,
+                           hi: float = 5.0, log10_eig=(-2.0, 0.0), device="cuda"):
+    """Same family as ``rotated_mixture`` (means, rotations and eigenvalues
+    from the host RNG in the same order) with the N(0, I) draws made on the
+    device by torch's seeded Philox generator.  Returns (X device float32,
+    means)."""
+    import torch
+    rng = _rng(seed)
+    means = rng.uniform(lo, hi, size=(K, d))
+    X = torch.empty((n, d), dtype=torch.float32, device=device)
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed) + 0x7A7E)
+    for c in range(K):
+        R = haar_rotation(d, rng)
+        lam = 10.0 ** rng.uniform(log10_eig[0], log10_eig[1], size=d)
+        Ft = torch.from_numpy((R * np.sqrt(lam)[None, :]).T.astype(np.float32)).to(device)
+        m = (n - c + K - 1) // K if c < n else 0
+        if m == 0:
+            continue
+        Z = torch.randn(m, d, generator=g, device=device)
+        X[c::K] = torch.from_numpy(means[c].astype(np.float32)).to(device) + Z @ Ft
+    return X, means
+
+
 def router_mixture(n: int, d: int, K: int, seed: int = 0, mean_std: float = 2.0,
                    sig_lo: float = 0.5, sig_hi: float = 1.5):
     """Rows mu_c + sigma_c N(0, I), c = i mod K; mu_c ~ N(0, mean_std^2 I),

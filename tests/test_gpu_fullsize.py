@@ -1,0 +1,156 @@
+"""The larger workloads at their full sizes, through the C ABI, in the launch
+configurations bench.py times:
+
+  * rotated mixture (n = 1,000,000, d = 1000, k = 50): k-means++ and three
+    Lloyd iterations in FP32, BF16 and FP8; every precision returns the same
+    labels, centers and cost history; sampled rows against the oracle's
+    assignment, three clusters' centroids against the oracle's update on
+    their rows;
+  * streamed (10,000,000 rows of d = 4096 in 153 chunks of 65,536 -> 64):
+    sampled projected rows against the oracle's projection within the FP32
+    accumulation bound, then the same cross-precision identity and sampled
+    labels;
+  * 256 uneven weighted instances (sum n = 26.7 M): two batched iterations
+    against independent single-instance runs (identical labels, bitwise
+    identical centers) and sampled labels of three instances against the
+    oracle.
+
+Labels are compared with the oracle outside its 1e-6 relative top-2 margin
+band, centroids to 1e-5 relative.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import kmeans as ok
+from oracle import project as op
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1502_04265_amd import kmx
+    return kmx.Context(0)
+
+
+def _check_sampled(lab_rows, Xs, C, what):
+    lab_o, d1, d2 = ok.assign(Xs, C)
+    bad = (lab_rows != lab_o) & ~((d2 - d1) < 1e-6 * d2)
+    assert not bad.any(), f"{what}: {int(bad.sum())} sampled rows differ"
+
+
+def _three_precisions(ctx, X, C0, iters):
+    out = {}
+    for prec in ("fp32", "bf16", "fp8"):
+        C, lab, hist, it = ctx.lloyd(X, C0, iters, prec=prec, labels=True)
+        say(f"  {prec}: cost {hist[-1]:.9e}, re-check {ctx.assign_stats()}")
+        out[prec] = (C, lab, hist, it)
+    C32, l32, h32, _ = out["fp32"]
+    for prec in ("bf16", "fp8"):
+        C, lab, hist, _ = out[prec]
+        assert torch.equal(lab, l32), prec
+        assert torch.equal(C, C32), prec
+        assert hist == h32, prec
+    return out["fp32"]
+
+
+def test_rotated_mixture_full_size(ctx):
+    n, d, k, iters = 1_000_000, 1000, 50, 3
+    say("rotated mixture n=1e6 d=1000 k=50")
+    X, _ = synth.rotated_mixture_device(n, d, k, seed=0, device="cuda:0")
+    C0, _ = ctx.seed(X, k, rng_seed=0)
+    C, lab, hist, it = _three_precisions(ctx, X, C0, iters)
+    assert it == iters
+    assert all(hist[t + 1] <= hist[t] * (1 + 1e-12) for t in range(len(hist) - 1))
+    rng = np.random.default_rng(1)
+    rows = np.sort(rng.choice(n, 2000, replace=False))
+    ridx = torch.from_numpy(rows).to("cuda:0")
+    Ch = C.cpu().numpy()
+    _check_sampled(lab[ridx].cpu().numpy(), X[ridx].cpu().numpy(), Ch, "rotated labels")
+    # the update of C_T on the final labels, three clusters against the oracle
+    Cn, W, _ = ctx.update(X, lab, C)
+    labh = lab.cpu().numpy()
+    for j in (0, k // 2, k - 1):
+        members = np.nonzero(labh == j)[0]
+        Xj = X[torch.from_numpy(members).to("cuda:0")].cpu().numpy()
+        ref = Xj.astype(np.float64).mean(axis=0)
+        got = Cn[j].cpu().numpy().astype(np.float64)
+        assert np.linalg.norm(got - ref) <= 1e-5 * max(np.linalg.norm(ref), 1e-3), j
+        assert float(W[j].item()) == float(len(members))
+    del X
+    torch.cuda.empty_cache()
+
+
+def test_streamed_full_size(ctx):
+    from paper_1502_04265_amd import subspace
+    d_in, r, k, rows, n, iters = 4096, 64, 100, 65536, 10_000_000, 3
+    nchunks = (n + rows - 1) // rows
+    say(f"streamed {nchunks} chunks of {rows} x {d_in} -> {r}")
+    dev = "cuda:0"
+    F = torch.from_numpy(synth.lowrank_factors(d_in, r, seed=0)).to(dev)
+    sample = torch.cat([synth.lowrank_chunk_device(rows, F, seed=0, chunk=1_000_000 + c,
+                                                   device=dev) for c in range(2)])[:100_000]
+    V = subspace.top_right_singular_vectors(sample.cpu().numpy(), r, power_iters=1, seed=0)
+    del sample
+    Vd = torch.from_numpy(V).to(dev)
+    Y = torch.empty((nchunks * rows, r), dtype=torch.float32, device=dev)
+    rng = np.random.default_rng(3)
+    worst = 0.0
+    for c in range(nchunks):
+        Xc = synth.lowrank_chunk_device(rows, F, seed=0, chunk=c, device=dev)
+        ctx.project(Xc, Vd, out=Y[c * rows:(c + 1) * rows])
+        if c % 16 == 0:
+            pick = np.sort(rng.choice(rows, 16, replace=False))
+            Xs = Xc[torch.from_numpy(pick).to(dev)].cpu().numpy()
+            Ys = Y[c * rows + torch.from_numpy(pick).to(dev)].cpu().numpy().astype(np.float64)
+            Yo = op.project(Xs, V)
+            bound = (d_in + 2) * 2.0 ** -23 * (np.abs(Xs.astype(np.float64)) @ np.abs(V.astype(np.float64)))
+            assert np.all(np.abs(Ys - Yo) <= bound + 1e-30), c
+            worst = max(worst, float(np.max(np.abs(Ys - Yo) / (bound + 1e-30))))
+    say(f"  projection: worst sampled error {worst:.3f} of its bound")
+    del Xc
+    C0, _ = ctx.seed(Y, k, rng_seed=0)
+    C, lab, hist, it = _three_precisions(ctx, Y, C0, iters)
+    pick = torch.from_numpy(np.sort(rng.choice(Y.shape[0], 2000, replace=False))).to(dev)
+    _check_sampled(lab[pick].cpu().numpy(), Y[pick].cpu().numpy(), C.cpu().numpy(),
+                   "streamed labels")
+    del Y
+    torch.cuda.empty_cache()
+
+
+def test_batched_full_size(ctx):
+    iters = 2
+    descs = synth.uneven_instances(256, seed=0)
+    say(f"batched 256 instances, sum n = {sum(d['n'] for d in descs)}")
+    probs = []
+    for desc in descs:
+        X, w = synth.instance_device(desc, device="cuda:0")
+        C0 = X[:desc["k"]].contiguous()           # first k rows as the start
+        probs.append({"X": X, "C": C0, "w": w})
+    res = ctx.lloyd_batched(probs, iters)
+    for i, p in enumerate(probs):
+        C, lab, hist, _ = ctx.lloyd(p["X"], p["C"], iters, w=p["w"], prec="bf16")
+        Cb, labb, histb = res[i]
+        assert torch.equal(lab, labb), i
+        assert torch.equal(C, Cb), i
+        np.testing.assert_allclose(histb, hist, rtol=1e-12)
+    rng = np.random.default_rng(5)
+    for i in (0, 127, 255):
+        Cb, labb, _ = res[i]
+        X = probs[i]["X"]
+        pick = torch.from_numpy(np.sort(rng.choice(X.shape[0], min(1000, X.shape[0]),
+                                                   replace=False))).to("cuda:0")
+        _check_sampled(labb[pick].cpu().numpy(), X[pick].cpu().numpy(), Cb.cpu().numpy(),
+                       f"instance {i}")
+    del probs, res
+    torch.cuda.empty_cache()

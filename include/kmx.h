@@ -159,8 +159,8 @@ kmx_status kmx_project(kmx_ctx* ctx, const float* X, int64_t rows, int32_t d_in,
  *   listed   rows on the exact re-check list (pairs and full rows),
  *   fp32     rows the BF16 GEMM passed to the FP32 GEMM because more than
  *            three centers lay within its error bound (with KMX_FP8E4M3 the
- *            FP8 pass first hands every row it cannot decide to the BF16
- *            pass),
+ *            FP8 pass first hands the rows with more than three centers
+ *            inside its bound to the BF16 pass),
  *   full     rows re-checked against every center.
  * Synchronizes. */
 kmx_status kmx_assign_stats(kmx_ctx* ctx, int64_t* listed, int64_t* fp32, int64_t* full);

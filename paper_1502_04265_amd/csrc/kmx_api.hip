@@ -170,10 +170,10 @@ kmx_status run_prep_centers(kmx_ctx* ctx, const float* C, int k, int d, int prec
   return KMX_OK;
 }
 
-// GEMM passes: FP8 (every undecided row to the BF16 pass), BF16 (rows with
-// more than three centers inside its bound to the FP32 pass), FP32 (rows still
-// open to the every-center re-check); then the re-check.  gate: skip when
-// *gate != 0.
+// GEMM passes: FP8 (rows with more than three centers inside its bound to
+// the BF16 pass), BF16 (likewise to the FP32 pass), FP32 (rows still open to
+// the every-center re-check); rows with two or three candidates inside a
+// pass's bound go to the short re-check.  gate: skip when *gate != 0.
 kmx_status run_assign_gemm(kmx_ctx* ctx, const float* X, int64_t n, int d, int64_t ldx,
                            const float* C, int k, int prec, int32_t* label, float* d1,
                            float* d2, const int* rows, const unsigned long long* row_count,
@@ -213,7 +213,7 @@ kmx_status run_assign_gemm(kmx_ctx* ctx, const float* X, int64_t n, int d, int64
                                  P<uint8_t>(ctx->sx8), n, rows, row_count, d, dp8,
                                  P<RowStats>(ctx->rowstats8), ctx->cq8.p, P<float>(ctx->ch8), k,
                                  kpad8, cs8, label, d1, d2, flags, P<int>(ctx->full_rows),
-                                 &st->full_count, 1, brute, st, gate, ctx->num_cus));
+                                 &st->full_count, 0, brute, st, gate, ctx->num_cus));
       rows16 = P<int>(ctx->full_rows);
       cnt16 = &st->full_count;
       next16 = P<int>(ctx->full_rows2);

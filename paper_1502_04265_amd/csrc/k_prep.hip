@@ -86,6 +86,8 @@ __global__ __launch_bounds__(64) void prep_centers_kernel(const float* __restric
   const int j = blockIdx.x;
   const int lane = threadIdx.x;
   double s2 = 0.0, q2 = 0.0, r2 = 0.0;
+  // unrolled so the loads of a row are in flight together
+#pragma unroll 8
   for (int c = lane; c < dp; c += 64) {
     const float v = (j < k && c < d) ? C[(int64_t)j * d + c] : 0.0f;
     const double vd = (double)v;
@@ -253,6 +255,7 @@ __global__ __launch_bounds__(64) void prep_centers_f8_kernel(const float* __rest
   const float inv = ldexpf(1.0f, -e);
   const double sc = ldexp(1.0, e);
   double s2 = 0.0, q2 = 0.0, r2 = 0.0;
+#pragma unroll 4
   for (int c0 = 4 * lane; c0 < dp; c0 += 256) {
     unsigned word = 0u;
 #pragma unroll

@@ -12,25 +12,28 @@
 
 namespace kmx {
 
-// Exact distance of one row pair with double-float sums, lanes splitting the
-// coordinates.
+// Exact distance of one row pair with double-float sums, the G lanes of a
+// group (lane = index within the group) splitting the coordinates.
+template <int G = 64>
 __device__ __forceinline__ void exact_dist(const float* __restrict__ x,
                                            const float* __restrict__ c, int d, int lane,
                                            float& hi, float& lo) {
   float s = 0.f, e = 0.f;
-  for (int q = lane; q < d; q += 64) df_acc_sqdiff(x[q], c[q], s, e);
-  wave_sum_df(s, e);
+  for (int q = lane; q < d; q += G) df_acc_sqdiff(x[q], c[q], s, e);
+  wave_sum_df<G>(s, e);
   df_norm(s, e, hi, lo);
 }
 
-// Short re-check: the listed 2 or 3 candidates, one wave per entry.  Plain
-// FP32 distances first: each lane sums the squares of its own coordinates
-// (four consecutive ones per 256-column step, or one per 64-column step when
-// rows are not 16-byte aligned: at most ceil(d/64) + 3 terms), then a 6-level
-// butterfly, so the relative error is below (ceil(d/64) + 13) u.  When the
-// best plain distance beats every other candidate by more than that bound the
-// result is exact; otherwise the candidates are compared with double-float
-// sums.  The next entry and its current label are fetched one entry ahead.
+// Short re-check: the listed 2 or 3 candidates, one group of G lanes per
+// entry (64 / G entries per wave at once).  Plain FP32 distances first: each
+// lane sums the squares of its own coordinates (four consecutive ones per
+// 4G-column step, or one per G-column step when rows are not 16-byte aligned:
+// at most ceil(d/G) + 3 terms), then a log2(G)-level butterfly, so the
+// relative error is below (ceil(d/G) + 13) u.  When the best plain distance
+// beats every other candidate by more than that bound the result is exact;
+// otherwise the candidates are compared with double-float sums.  The next
+// entry and its current label are fetched one entry ahead.
+template <int G = 64>
 __device__ __forceinline__ void plain_dist3(const float* __restrict__ x,
                                             const float* __restrict__ c0,
                                             const float* __restrict__ c1,
@@ -38,7 +41,8 @@ __device__ __forceinline__ void plain_dist3(const float* __restrict__ x,
                                             bool vec, float& p0, float& p1, float& p2) {
   float a0 = 0.f, a1 = 0.f, a2 = 0.f;
   if (vec) {
-    for (int q = lane * 4; q < d; q += 256) {
+#pragma unroll 4
+    for (int q = lane * 4; q < d; q += 4 * G) {
       const float4 xv = *(const float4*)(x + q);
       const float4 u0 = *(const float4*)(c0 + q);
       const float4 u1 = *(const float4*)(c1 + q);
@@ -58,7 +62,7 @@ __device__ __forceinline__ void plain_dist3(const float* __restrict__ x,
       }
     }
   } else {
-    for (int q = lane; q < d; q += 64) {
+    for (int q = lane; q < d; q += G) {
       const float xq = x[q];
       float df = xq - c0[q];
       a0 = __builtin_fmaf(df, df, a0);
@@ -69,7 +73,7 @@ __device__ __forceinline__ void plain_dist3(const float* __restrict__ x,
     }
   }
 #pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) {
+  for (int m = G / 2; m >= 1; m >>= 1) {
     a0 += __shfl_xor(a0, m, 64);
     a1 += __shfl_xor(a1, m, 64);
     a2 += __shfl_xor(a2, m, 64);
@@ -79,17 +83,19 @@ __device__ __forceinline__ void plain_dist3(const float* __restrict__ x,
   p2 = a2;
 }
 
+template <int G>
 __global__ __launch_bounds__(256) void recheck_pair_kernel(
     const float* __restrict__ X, int64_t n, int d, int64_t ldx, const float* __restrict__ C,
     int k, int32_t* __restrict__ label, float* __restrict__ d1o,
     const FlagEntry* __restrict__ flags, const LoopState* __restrict__ st,
     const int* __restrict__ gate) {
   if (gate && *gate) return;
+  constexpr int SPW = 64 / G;          // entries per wave at once
   const int64_t cnt = (int64_t)st->flagged;
-  const int lane = threadIdx.x & 63;
-  const int64_t gw = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int64_t nw = (int64_t)gridDim.x * 4;
-  const float tol = (float)((d + 63) / 64 + 13) * 5.9604645e-8f;
+  const int lane = threadIdx.x & 63, gl = lane % G, grp = lane / G;
+  const int64_t gw = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * SPW + grp;
+  const int64_t nw = (int64_t)gridDim.x * 4 * SPW;
+  const float tol = (float)((d + G - 1) / G + 13) * 5.9604645e-8f;
   const bool vec = ((((uintptr_t)X) & 15) == 0) && (ldx % 4 == 0) &&
                    ((((uintptr_t)C) & 15) == 0) && (d % 4 == 0);
   // entries each row appears in at most once, so a label fetched ahead is
@@ -100,7 +106,7 @@ __global__ __launch_bounds__(256) void recheck_pair_kernel(
     fe_n = flags[gw];
     lab_n = (fe_n.row >= 0 && fe_n.row < n) ? label[fe_n.row] : 0;
   }
-  for (int64_t e = gw; e < cnt; e += nw) {
+  for (int64_t e = gw; e < cnt; e += nw) {   // uniform within a group
     const FlagEntry fe = fe_n;
     const int lab = lab_n;
     if (e + nw < cnt) {
@@ -116,8 +122,8 @@ __global__ __launch_bounds__(256) void recheck_pair_kernel(
     cj[2] = fe.cand3 >= 0 ? min(fe.cand3, k - 1) : -1;
     const int nc = (cj[2] >= 0) ? 3 : 2;
     float p[3];
-    plain_dist3(x, C + (int64_t)cj[0] * d, C + (int64_t)cj[1] * d,
-                C + (int64_t)(nc == 3 ? cj[2] : cj[1]) * d, d, lane, vec, p[0], p[1], p[2]);
+    plain_dist3<G>(x, C + (int64_t)cj[0] * d, C + (int64_t)cj[1] * d,
+                   C + (int64_t)(nc == 3 ? cj[2] : cj[1]) * d, d, gl, vec, p[0], p[1], p[2]);
     int b = 0;
     for (int q = 1; q < nc; ++q)
       if (p[q] < p[b] || (p[q] == p[b] && cj[q] < cj[b])) b = q;
@@ -130,14 +136,14 @@ __global__ __launch_bounds__(256) void recheck_pair_kernel(
       float bh = 0.f, bl = 0.f;
       for (int q = 0; q < nc; ++q) {
         float h, l;
-        exact_dist(x, C + (int64_t)cj[q] * d, d, lane, h, l);
+        exact_dist<G>(x, C + (int64_t)cj[q] * d, d, gl, h, l);
         if (q == 0 || df_less(h, l, bh, bl) || (h == bh && l == bl && cj[q] < best)) {
           bh = h; bl = l; best = cj[q];
         }
       }
       bd = bh;
     }
-    if (lane == 0) {
+    if (gl == 0) {
       label[row] = best;
       if (d1o) d1o[row] = bd;
     }
@@ -264,8 +270,17 @@ hipError_t launch_recheck(hipStream_t s, const float* X, int64_t n, int d, int64
   int64_t cap = (int64_t)num_cus * 8;
   if (blocks > cap) blocks = cap;
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(recheck_pair_kernel, dim3((unsigned)blocks), dim3(256), 0, s, X, n, d, ldx,
-                     C, k, label, d1, flags, st, gate);
+  // lanes per entry: enough to cover a row in a few 16-byte steps, more
+  // entries in flight per wave for short rows
+  if (d <= 256)
+    hipLaunchKernelGGL(recheck_pair_kernel<16>, dim3((unsigned)blocks), dim3(256), 0, s, X, n,
+                       d, ldx, C, k, label, d1, flags, st, gate);
+  else if (d <= 1024)
+    hipLaunchKernelGGL(recheck_pair_kernel<32>, dim3((unsigned)blocks), dim3(256), 0, s, X, n,
+                       d, ldx, C, k, label, d1, flags, st, gate);
+  else
+    hipLaunchKernelGGL(recheck_pair_kernel<64>, dim3((unsigned)blocks), dim3(256), 0, s, X, n,
+                       d, ldx, C, k, label, d1, flags, st, gate);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   cap = (int64_t)num_cus * 4;

@@ -96,10 +96,12 @@ __device__ __forceinline__ void df_acc_sqdiff(float x, float c, float& s, float&
   e += te + pe;
 }
 
-// Combines double-float partials across the lanes of a wave (fixed order).
+// Combines double-float partials across groups of G lanes (G = 64: the whole
+// wave), fixed order, the same bits on every lane of a group.
+template <int G = 64>
 __device__ __forceinline__ void wave_sum_df(float& s, float& e) {
 #pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) {
+  for (int m = G / 2; m >= 1; m >>= 1) {
     float so = __shfl_xor(s, m, 64);
     float eo = __shfl_xor(e, m, 64);
     // symmetric in (self, other) so both partners hold identical bits

@@ -54,6 +54,23 @@ typedef __attribute__((ext_vector_type(4))) float f32x4_t;
 typedef __attribute__((ext_vector_type(4))) unsigned int u32x4_t;
 typedef __attribute__((ext_vector_type(8))) int i32x8_t;
 
+// FP8 x FP8 MFMA with E8M0 block scales: sa for A, byte SEL of sb for B.
+template <int SEL>
+__device__ __forceinline__ f32x4_t mfma_f8_sel(const i32x8_t& a, const i32x8_t& b, f32x4_t c,
+                                               int sa, int sb) {
+  return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b, c, 0, 0, 0, sa, SEL, sb);
+}
+// sel is a constant after unrolling, so the switch folds away.
+__device__ __forceinline__ f32x4_t mfma_f8_scaled(int sel, const i32x8_t& a, const i32x8_t& b,
+                                                  f32x4_t c, int sa, int sb) {
+  switch (sel & 3) {
+    case 0: return mfma_f8_sel<0>(a, b, c, sa, sb);
+    case 1: return mfma_f8_sel<1>(a, b, c, sa, sb);
+    case 2: return mfma_f8_sel<2>(a, b, c, sa, sb);
+    default: return mfma_f8_sel<3>(a, b, c, sa, sb);
+  }
+}
+
 __device__ __forceinline__ unsigned med3u(unsigned a, unsigned b, unsigned c) {
   return max(min(a, b), min(max(a, b), c));
 }
@@ -148,17 +165,18 @@ __device__ __forceinline__ void assign_block(const AssignArgs& A, int64_t blk,
     const int64_t p_base = blk * PPB + (int64_t)wave * (16 * NCG);
 
     // ---- point fragments (B operand) for this block ----
-    int64_t src_row[NCG];
+    int src_row[NCG];                  // n <= 2^31 - 2: row ids fit 32 bits
     u32x4_t xf[NCG][NKU * NF];
-    int sxe[NCG];
+    // E8M0 scale of point group cg in byte cg (FP8; the MFMA selects the byte)
+    static_assert(!F8 || NCG <= 4, "four point-group scales per register");
+    unsigned sxp = 0u;
 #pragma unroll
     for (int cg = 0; cg < NCG; ++cg) {
       const int64_t p = p_base + cg * 16 + prow;
       const bool pv = p < A.npts;
       const int64_t r = pv ? (A.rows ? (int64_t)A.rows[p] : p) : -1;
-      src_row[cg] = r;
-      sxe[cg] = 127;
-      if (F8 && pv) sxe[cg] = (int)A.sx8[r];
+      src_row[cg] = (int)r;
+      if (F8) sxp |= (pv ? (unsigned)A.sx8[r] : 127u) << (8 * (cg & 3));
       // packed operands: invalid points read row 0 (always present) and are
       // zeroed afterwards, so the loads issue without branches
       const int64_t rl = pv ? r : 0;
@@ -310,8 +328,7 @@ __device__ __forceinline__ void assign_block(const AssignArgs& A, int64_t blk,
               const i32x8_t b = __builtin_bit_cast(
                   i32x8_t, __builtin_shufflevector(xf[cg][2 * ku], xf[cg][2 * ku + 1], 0, 1, 2, 3,
                                                    4, 5, 6, 7));
-              acc[cg][rb] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
-                  a, b, acc[cg][rb], 0, 0, 0, cexp, 0, sxe[cg]);
+              acc[cg][rb] = mfma_f8_scaled(cg, a, b, acc[cg][rb], cexp, (int)sxp);
             }
           }
           if constexpr (PIPE) {
@@ -645,7 +662,7 @@ int assign_dpad(int prec, int d) {
 // Centers per LDS tile: each of the two tile buffers stays within ~72 KB.
 int assign_tile_n(int prec, int d) {
   const int nku = units_for(prec, d);
-  if (prec == KMX_FP8E4M3) return nku <= 4 ? 64 : (nku <= 6 ? 32 : 16);
+  if (prec == KMX_FP8E4M3) return nku <= 3 ? 64 : (nku <= 6 ? 32 : 16);
   if (prec == KMX_BF16) return (nku <= 3 || nku == 6 || nku == 8) ? 64 : 32;
   if (nku <= 4) return 64;
   if (nku <= 32) return 32;
@@ -742,7 +759,7 @@ hipError_t launch_assign(hipStream_t s, int prec, const float* X, int64_t ldx, c
       case 1: KMX_A(1, 4, 64, 8, true);
       case 2: KMX_A(2, 4, 64, 8, false);
       case 3: KMX_A(3, 2, 64, 8, false);
-      case 4: KMX_A(4, 2, 64, 8, false);
+      case 4: KMX_A(4, 4, 32, 8, false);
       case 6: KMX_A(6, 1, 32, 8, true);
       case 8: KMX_A(8, 1, 16, 8, true);
       default: return hipErrorInvalidValue;

@@ -6,11 +6,15 @@
 // One launch per round r.  Every block streams its rows of X once: for r >= 1
 // it lowers D2_i to ||x_i - c_{r-1}||^2 (FP64 direct differences of the FP32
 // inputs, exact up to the final sums) and writes the FP64 block sum of
-// w_i * D2_i (r = 0: of w_i).  The last block to finish (atomic ticket) draws
-// u_r from SplitMix64, finds the first block whose inclusive prefix of block
-// sums strictly exceeds u_r * M, then the first row inside it, copies that row
-// into C and marks it chosen.  If the mass M is zero it draws by weight among
-// the rows not chosen yet.
+// w_i * D2_i (r = 0: of w_i).  A row is read by a group of G lanes, lane s
+// taking the 16-byte chunks s, s + G, ... of the row, so each lane has up to
+// NV independent loads in flight; the previous center's chunks stay in
+// registers as FP64 for the whole block (NV = 0: rows wider than NV * G
+// chunks, center re-read from the cache).  The last block to finish (atomic
+// ticket) draws u_r from SplitMix64, finds the first block whose inclusive
+// prefix of block sums strictly exceeds u_r * M, then the first row inside it,
+// copies that row into C and marks it chosen.  If the mass M is zero it draws
+// by weight among the rows not chosen yet.
 #include "kmx_device.h"
 #include "kmx_internal.h"
 
@@ -88,6 +92,21 @@ __device__ int64_t pick_linear(int64_t lo, int64_t hi, double target, F mass, do
   return (int64_t)red[1] - 1;
 }
 
+typedef __attribute__((ext_vector_type(4))) float sf32x4_t;
+
+// Chunk q (elements 4q .. 4q + 3) of a row of length d; zeros past the row.
+template <bool VEC>
+__device__ __forceinline__ sf32x4_t load_chunk(const float* p, int q, int d, bool valid) {
+  sf32x4_t v = {0.f, 0.f, 0.f, 0.f};
+  if (!valid) return v;
+  if (VEC) return *(const sf32x4_t*)(p + 4 * q);
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+    if (4 * q + e < d) v[e] = p[4 * q + e];
+  return v;
+}
+
+template <int G, int NV, bool VEC>
 __global__ __launch_bounds__(256) void seed_round_kernel(
     const float* __restrict__ X, int64_t n, int d, int64_t ldx, const float* __restrict__ w,
     int r, uint64_t seed, double* __restrict__ D2, uint8_t* __restrict__ chosen,
@@ -96,11 +115,13 @@ __global__ __launch_bounds__(256) void seed_round_kernel(
   __shared__ double sh[8];
   __shared__ unsigned long long red[2];
   __shared__ unsigned int ticket;
+  constexpr int NG = 256 / G;          // lane groups (rows in flight) per block
   const int nb = gridDim.x;
   const int b = blockIdx.x;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int sub = threadIdx.x & (G - 1), grp = threadIdx.x / G;
   const int64_t r0 = (int64_t)b * kSeedRows;
   const int64_t r1 = min(n, r0 + kSeedRows);
+  const int nch = (d + 3) >> 2;
 
   // ---- 1. lower D2 against the previous center; block mass ----
   double macc = 0.0;
@@ -108,16 +129,63 @@ __global__ __launch_bounds__(256) void seed_round_kernel(
     for (int64_t i = r0 + threadIdx.x; i < r1; i += 256) macc += w ? (double)w[i] : 1.0;
   } else {
     const float* c = C + (int64_t)(r - 1) * d;
-    for (int64_t i = r0 + wv; i < r1; i += 4) {
+    double cd[NV > 0 ? NV : 1][4];
+    if constexpr (NV > 0) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const sf32x4_t cv = load_chunk<false>(c, sub + G * v, d, sub + G * v < nch);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) cd[v][e] = (double)cv[e];
+      }
+    }
+    // NV > 0: the chunks of the group's next row are loaded while the
+    // current one is reduced
+    sf32x4_t xn[NV > 0 ? NV : 1];
+    if constexpr (NV > 0) {
+      const int64_t i0 = r0 + grp;
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+        xn[v] = load_chunk<VEC>(X + (i0 < r1 ? i0 : 0) * ldx, sub + G * v, d,
+                                i0 < r1 && sub + G * v < nch);
+    }
+    for (int64_t i = r0 + grp; i < r1; i += NG) {
       const float* x = X + i * ldx;
       double acc = 0.0;
-      for (int q = lane; q < d; q += 64) {
-        const double df = (double)x[q] - (double)c[q];
-        acc = fma(df, df, acc);
+      if constexpr (NV > 0) {
+        sf32x4_t xv[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) xv[v] = xn[v];
+        const int64_t inx = i + NG;
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+          xn[v] = load_chunk<VEC>(X + (inx < r1 ? inx : 0) * ldx, sub + G * v, d,
+                                  inx < r1 && sub + G * v < nch);
+        double a4[4] = {0.0, 0.0, 0.0, 0.0};   // four independent FMA chains
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const double df = (double)xv[v][e] - cd[v][e];
+            a4[e] = fma(df, df, a4[e]);
+          }
+        acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
+      } else {
+#pragma unroll 4
+        for (int q = sub; q < nch; q += G) {
+          const sf32x4_t xv = load_chunk<VEC>(x, q, d, true);
+          const sf32x4_t cv = load_chunk<VEC>(c, q, d, true);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const double df = (double)xv[e] - (double)cv[e];
+            acc = fma(df, df, acc);
+          }
+        }
       }
-      acc = wave_sum_f64(acc);
-      const double dv = (r == 1) ? acc : fmin(D2[i], acc);
-      if (lane == 0) {
+      // butterfly over the group: every lane of it ends with the same bits
+#pragma unroll
+      for (int m = G / 2; m >= 1; m >>= 1) acc += __shfl_xor(acc, m, 64);
+      if (sub == 0) {
+        const double dv = (r == 1) ? acc : fmin(D2[i], acc);
         D2[i] = dv;
         macc += w ? (double)w[i] * dv : dv;
       }
@@ -197,9 +265,28 @@ hipError_t launch_seed_round(hipStream_t s, const float* X, int64_t n, int d, in
                              const float* w, int r, uint64_t seed, double* D2, uint8_t* chosen,
                              double* part, unsigned int* ctr, float* C_out, int64_t* idx_out) {
   const int nb = (int)((n + kSeedRows - 1) / kSeedRows);
-  hipLaunchKernelGGL(seed_round_kernel, dim3(nb), dim3(256), 0, s, X, n, d, ldx, w, r, seed, D2,
-                     chosen, part, ctr, C_out, idx_out);
-  return hipGetLastError();
+  const int nch = (d + 3) / 4;
+  // whole 16-byte chunks: rows of X and of C start 16-byte aligned
+  const bool vec = (d % 4 == 0) && (ldx % 4 == 0) && ((((uintptr_t)X) & 15) == 0) &&
+                   ((((uintptr_t)C_out) & 15) == 0);
+#define KMX_S(G_, NV_)                                                                           \
+  do {                                                                                           \
+    if (vec)                                                                                     \
+      hipLaunchKernelGGL((seed_round_kernel<G_, NV_, true>), dim3(nb), dim3(256), 0, s, X, n, d, \
+                         ldx, w, r, seed, D2, chosen, part, ctr, C_out, idx_out);                \
+    else                                                                                         \
+      hipLaunchKernelGGL((seed_round_kernel<G_, NV_, false>), dim3(nb), dim3(256), 0, s, X, n,   \
+                         d, ldx, w, r, seed, D2, chosen, part, ctr, C_out, idx_out);             \
+    return hipGetLastError();                                                                    \
+  } while (0)
+  if (nch <= 16) KMX_S(4, 4);
+  if (nch <= 32) KMX_S(8, 4);
+  if (nch <= 64) KMX_S(16, 4);
+  if (nch <= 128) KMX_S(16, 8);
+  if (nch <= 256) KMX_S(32, 8);
+  if (nch <= 512) KMX_S(64, 8);
+  KMX_S(64, 0);
+#undef KMX_S
 }
 
 }  // namespace kmx

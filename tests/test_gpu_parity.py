@@ -180,8 +180,15 @@ def test_cost_matches_oracle(ctx, prec):
 # ---------------------------------------------------------------------------
 # seeding
 # ---------------------------------------------------------------------------
+# row widths cover every lane-group shape of the D2 pass (4 .. 64 lanes per
+# row, center chunks in registers or re-read), 16-byte and scalar loads, and
+# several 2048-row blocks
 @pytest.mark.parametrize("n,d,k,weighted,seed", [(3000, 24, 6, False, 7), (10000, 64, 10, False, 0),
-                                                 (5000, 33, 40, True, 11), (2049, 5, 17, True, 3)])
+                                                 (5000, 33, 40, True, 11), (2049, 5, 17, True, 3),
+                                                 (3000, 100, 5, False, 1), (2500, 200, 6, True, 2),
+                                                 (4100, 512, 5, False, 4), (2100, 1000, 4, True, 5),
+                                                 (2000, 1500, 3, False, 6), (2000, 2050, 3, True, 8),
+                                                 (2000, 3000, 3, False, 9)])
 def test_seed_matches_oracle(ctx, n, d, k, weighted, seed):
     say(f"seed n={n} d={d} k={k} w={weighted}")
     X, _ = synth.isotropic_mixture(n, d, k, seed=seed)

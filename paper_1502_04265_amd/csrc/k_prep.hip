@@ -77,48 +77,74 @@ hipError_t launch_prep_rows(hipStream_t s, const float* X, int64_t n, int d, int
 // is then clamped away).  prec 1 (BF16): c~_j (round to nearest even) in
 // columns [0, d), zeros elsewhere; hd[j] = ||c_j||^2 / 2 in FP64.  Maxima of
 // the norms go to cs.
-__global__ __launch_bounds__(64) void prep_centers_kernel(const float* __restrict__ C, int k,
-                                                          int d, int dp, int prec,
-                                                          void* __restrict__ Cq,
-                                                          float* __restrict__ ch,
-                                                          double* __restrict__ hd,
-                                                          CenterStats* __restrict__ cs) {
-  const int j = blockIdx.x;
-  const int lane = threadIdx.x;
-  double s2 = 0.0, q2 = 0.0, r2 = 0.0;
-  // unrolled so the loads of a row are in flight together
+__device__ __forceinline__ unsigned block_max_u32(unsigned v, unsigned* sh) {
+  // maxima of non-negative float bits over a 256-thread block (valid in thread 0)
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v = max(v, (unsigned)__shfl_xor((int)v, m, 64));
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  v = max(max(sh[0], sh[1]), max(sh[2], sh[3]));
+  __syncthreads();
+  return v;
+}
+
+// Each wave takes padded centers wave_id, wave_id + total_waves, ...; the
+// norm maxima are reduced over the block and reach cs with one atomic per
+// block and statistic (same-address atomics from every XCD serialize).
+__global__ __launch_bounds__(256) void prep_centers_kernel(const float* __restrict__ C, int k,
+                                                           int d, int dp, int kpad, int prec,
+                                                           void* __restrict__ Cq,
+                                                           float* __restrict__ ch,
+                                                           double* __restrict__ hd,
+                                                           CenterStats* __restrict__ cs) {
+  __shared__ unsigned shm[4];
+  const int lane = threadIdx.x & 63;
+  const int wave = blockIdx.x * 4 + (threadIdx.x >> 6), nwaves = gridDim.x * 4;
+  unsigned cqm = 0u, rcm = 0u, cnm = 0u;
+  for (int j = wave; j < kpad; j += nwaves) {
+    double s2 = 0.0, q2 = 0.0, r2 = 0.0;
+    // unrolled so the loads of a row are in flight together
 #pragma unroll 8
-  for (int c = lane; c < dp; c += 64) {
-    const float v = (j < k && c < d) ? C[(int64_t)j * d + c] : 0.0f;
-    const double vd = (double)v;
-    s2 += vd * vd;
-    if (prec == 1) {
-      const uint16_t b = f32_to_bf16_rne(v);
-      ((uint16_t*)Cq)[(int64_t)j * dp + c] = b;
-      const double qd = (double)bf16_to_f32(b);
-      q2 += qd * qd;
-      r2 += (vd - qd) * (vd - qd);
-    } else {
-      ((float*)Cq)[(int64_t)j * dp + c] = v;
+    for (int c = lane; c < dp; c += 64) {
+      const float v = (j < k && c < d) ? C[(int64_t)j * d + c] : 0.0f;
+      const double vd = (double)v;
+      s2 += vd * vd;
+      if (prec == 1) {
+        const uint16_t b = f32_to_bf16_rne(v);
+        ((uint16_t*)Cq)[(int64_t)j * dp + c] = b;
+        const double qd = (double)bf16_to_f32(b);
+        q2 += qd * qd;
+        r2 += (vd - qd) * (vd - qd);
+      } else {
+        ((float*)Cq)[(int64_t)j * dp + c] = v;
+      }
     }
-  }
-  s2 = wave_sum_f64(s2);
-  q2 = wave_sum_f64(q2);
-  r2 = wave_sum_f64(r2);
-  if (lane == 0) {
-    if (prec == 1) {
-      hd[j] = 0.5 * s2;
-    } else {
-      ch[j] = (j < k) ? (float)(0.5 * s2) : __builtin_inff();
+    s2 = wave_sum_f64(s2);
+    q2 = wave_sum_f64(q2);
+    r2 = wave_sum_f64(r2);
+    if (lane == 0) {
+      if (prec == 1) {
+        hd[j] = 0.5 * s2;
+      } else {
+        ch[j] = (j < k) ? (float)(0.5 * s2) : __builtin_inff();
+      }
     }
     if (j < k) {
       const float cn = f64_to_f32_up(sqrt(s2));
       const float cq = (prec == 1) ? f64_to_f32_up(sqrt(q2)) : cn;
       const float rc = (prec == 1) ? f64_to_f32_up(sqrt(r2)) : 0.0f;
-      atomicMax(&cs->cq_max, __float_as_uint(cq));
-      atomicMax(&cs->rc_max, __float_as_uint(rc));
-      atomicMax(&cs->cn_max, __float_as_uint(cn));
+      cqm = max(cqm, __float_as_uint(cq));
+      rcm = max(rcm, __float_as_uint(rc));
+      cnm = max(cnm, __float_as_uint(cn));
     }
+  }
+  cqm = block_max_u32(cqm, shm);
+  rcm = block_max_u32(rcm, shm);
+  cnm = block_max_u32(cnm, shm);
+  if (threadIdx.x == 0) {
+    atomicMax(&cs->cq_max, cqm);
+    atomicMax(&cs->rc_max, rcm);
+    atomicMax(&cs->cn_max, cnm);
   }
 }
 
@@ -233,55 +259,66 @@ hipError_t launch_prep_rows_f8(hipStream_t s, const float* X, int64_t n, int d, 
 // Centers, FP8: one scale for all centers.  Pass 1: max |c_ji|.  Pass 2 (one
 // wave per padded center): the FP8 row (zeros for padding), hd = ||c||^2 / 2
 // in FP64 and the norm maxima.  Then the offsets (prep_offsets_kernel).
-__global__ void center_amax_kernel(const float* __restrict__ C, int64_t total,
-                                   CenterStats* __restrict__ cs) {
+__global__ __launch_bounds__(256) void center_amax_kernel(const float* __restrict__ C,
+                                                          int64_t total,
+                                                          CenterStats* __restrict__ cs) {
+  __shared__ unsigned shm[4];
   float m = 0.0f;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
        i += (int64_t)gridDim.x * blockDim.x)
     m = fmaxf(m, fabsf(C[i]));
-#pragma unroll
-  for (int s2 = 32; s2 >= 1; s2 >>= 1) m = fmaxf(m, __shfl_xor(m, s2, 64));
-  if ((threadIdx.x & 63) == 0) atomicMax(&cs->c_amax, __float_as_uint(m));
+  const unsigned bm = block_max_u32(__float_as_uint(m), shm);
+  if (threadIdx.x == 0) atomicMax(&cs->c_amax, bm);
 }
 
-__global__ __launch_bounds__(64) void prep_centers_f8_kernel(const float* __restrict__ C, int k,
-                                                             int d, int dp,
-                                                             uint8_t* __restrict__ Cq8,
-                                                             double* __restrict__ hd,
-                                                             CenterStats* __restrict__ cs) {
-  const int j = blockIdx.x;
-  const int lane = threadIdx.x;
+__global__ __launch_bounds__(256) void prep_centers_f8_kernel(const float* __restrict__ C, int k,
+                                                              int d, int dp, int kpad,
+                                                              uint8_t* __restrict__ Cq8,
+                                                              double* __restrict__ hd,
+                                                              CenterStats* __restrict__ cs) {
+  __shared__ unsigned shm[4];
+  const int lane = threadIdx.x & 63;
+  const int wave = blockIdx.x * 4 + (threadIdx.x >> 6), nwaves = gridDim.x * 4;
   const int e = e4m3_scale_exp(__uint_as_float(cs->c_amax));
   const float inv = ldexpf(1.0f, -e);
   const double sc = ldexp(1.0, e);
-  double s2 = 0.0, q2 = 0.0, r2 = 0.0;
+  unsigned cqm = 0u, rcm = 0u, cnm = 0u;
+  for (int j = wave; j < kpad; j += nwaves) {
+    double s2 = 0.0, q2 = 0.0, r2 = 0.0;
 #pragma unroll 4
-  for (int c0 = 4 * lane; c0 < dp; c0 += 256) {
-    unsigned word = 0u;
+    for (int c0 = 4 * lane; c0 < dp; c0 += 256) {
+      unsigned word = 0u;
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int c = c0 + t;
-      const float v = (j < k && c < d) ? C[(int64_t)j * d + c] : 0.0f;
-      const unsigned q = f32_to_e4m3_rne(v * inv);
-      const double back = (double)e4m3_to_f32(q) * sc;
-      s2 += (double)v * v;
-      q2 += back * back;
-      r2 += ((double)v - back) * ((double)v - back);
-      word |= q << (8 * t);
+      for (int t = 0; t < 4; ++t) {
+        const int c = c0 + t;
+        const float v = (j < k && c < d) ? C[(int64_t)j * d + c] : 0.0f;
+        const unsigned q = f32_to_e4m3_rne(v * inv);
+        const double back = (double)e4m3_to_f32(q) * sc;
+        s2 += (double)v * v;
+        q2 += back * back;
+        r2 += ((double)v - back) * ((double)v - back);
+        word |= q << (8 * t);
+      }
+      *(unsigned*)(Cq8 + (int64_t)j * dp + c0) = word;
     }
-    *(unsigned*)(Cq8 + (int64_t)j * dp + c0) = word;
-  }
-  s2 = wave_sum_f64(s2);
-  q2 = wave_sum_f64(q2);
-  r2 = wave_sum_f64(r2);
-  if (lane == 0) {
-    hd[j] = 0.5 * s2;
-    if (j == 0) cs->c_exp = e + 127;
+    s2 = wave_sum_f64(s2);
+    q2 = wave_sum_f64(q2);
+    r2 = wave_sum_f64(r2);
+    if (lane == 0) hd[j] = 0.5 * s2;
     if (j < k) {
-      atomicMax(&cs->cq_max, __float_as_uint(f64_to_f32_up(sqrt(q2))));
-      atomicMax(&cs->rc_max, __float_as_uint(f64_to_f32_up(sqrt(r2))));
-      atomicMax(&cs->cn_max, __float_as_uint(f64_to_f32_up(sqrt(s2))));
+      cqm = max(cqm, __float_as_uint(f64_to_f32_up(sqrt(q2))));
+      rcm = max(rcm, __float_as_uint(f64_to_f32_up(sqrt(r2))));
+      cnm = max(cnm, __float_as_uint(f64_to_f32_up(sqrt(s2))));
     }
+  }
+  cqm = block_max_u32(cqm, shm);
+  rcm = block_max_u32(rcm, shm);
+  cnm = block_max_u32(cnm, shm);
+  if (threadIdx.x == 0) {
+    if (blockIdx.x == 0) cs->c_exp = e + 127;
+    atomicMax(&cs->cq_max, cqm);
+    atomicMax(&cs->rc_max, rcm);
+    atomicMax(&cs->cn_max, cnm);
   }
 }
 
@@ -305,14 +342,16 @@ __global__ void prep_offsets_kernel(int k, int kpad, const double* __restrict__ 
 hipError_t launch_prep_centers(hipStream_t s, const float* C, int k, int d, int kpad, int dp,
                                int prec, void* Cq, float* ch, double* hd, CenterStats* cs,
                                const unsigned* xq_max) {
+  // four waves per block, a few centers per wave: few blocks, few atomics
+  const int cblocks = min((kpad + 7) / 8, 128);
   if (prec == 2) {
     const int64_t total = (int64_t)k * d;
-    int64_t blocks = (total + 255) / 256;
-    if (blocks > 1024) blocks = 1024;
+    int64_t blocks = (total + 4095) / 4096;
+    if (blocks > 128) blocks = 128;
     hipLaunchKernelGGL(center_amax_kernel, dim3((unsigned)blocks), dim3(256), 0, s, C, total, cs);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(prep_centers_f8_kernel, dim3(kpad), dim3(64), 0, s, C, k, d, dp,
+    hipLaunchKernelGGL(prep_centers_f8_kernel, dim3(cblocks), dim3(256), 0, s, C, k, d, dp, kpad,
                        (uint8_t*)Cq, hd, cs);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -320,8 +359,8 @@ hipError_t launch_prep_centers(hipStream_t s, const float* C, int k, int d, int 
                        hd, cs, xq_max, ch);
     return hipGetLastError();
   }
-  hipLaunchKernelGGL(prep_centers_kernel, dim3(kpad), dim3(64), 0, s, C, k, d, dp, prec, Cq, ch,
-                     hd, cs);
+  hipLaunchKernelGGL(prep_centers_kernel, dim3(cblocks), dim3(256), 0, s, C, k, d, dp, kpad, prec,
+                     Cq, ch, hd, cs);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || prec != 1) return e;
   hipLaunchKernelGGL(prep_offsets_kernel, dim3((kpad + 255) / 256), dim3(256), 0, s, k, kpad, hd,

@@ -262,6 +262,36 @@ __global__ __launch_bounds__(kFullWaves * 64) void recheck_full_kernel(
   }
 }
 
+// A short list for the FP32 GEMM pass goes to the every-center re-check
+// instead: that pass costs one workgroup's walk over all k centers however
+// few rows it has, while the re-check runs hundreds of rows side by side.
+// Moves the list onto the every-center list and empties it (the pass then
+// finds no rows); longer lists are left to the pass.
+__global__ __launch_bounds__(1024) void route_small_kernel(unsigned long long* __restrict__ ctr,
+                                                           const int* __restrict__ list,
+                                                           int* __restrict__ brute,
+                                                           LoopState* __restrict__ st,
+                                                           unsigned long long limit,
+                                                           const int* __restrict__ gate) {
+  if (gate && *gate) return;
+  const unsigned long long cnt = *ctr;
+  if (cnt == 0ull || cnt > limit) return;
+  const unsigned long long base = st->flagged_full;
+  for (unsigned long long i = threadIdx.x; i < cnt; i += blockDim.x) brute[base + i] = list[i];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    st->flagged_full = base + cnt;
+    *ctr = 0ull;
+  }
+}
+
+hipError_t launch_route_small(hipStream_t s, unsigned long long* ctr, const int* list, int* brute,
+                              LoopState* st, const int* gate) {
+  hipLaunchKernelGGL(route_small_kernel, dim3(1), dim3(1024), 0, s, ctr, list, brute, st,
+                     (unsigned long long)kShortFp32List, gate);
+  return hipGetLastError();
+}
+
 hipError_t launch_recheck(hipStream_t s, const float* X, int64_t n, int d, int64_t ldx,
                           const float* C, int k, int32_t* label, float* d1,
                           const FlagEntry* flags, const int* brute, const LoopState* st,

@@ -22,30 +22,42 @@ namespace kmx {
 __global__ __launch_bounds__(256) void hist_kernel(const int32_t* __restrict__ label,
                                                    int32_t* __restrict__ lab_prev, int64_t n,
                                                    int k, int32_t* __restrict__ counts,
-                                                   LoopState* __restrict__ st, int track,
+                                                   int32_t* __restrict__ chg, int track,
                                                    const int* __restrict__ gate) {
   if (gate && *gate) return;
   extern __shared__ int hsm[];
+  constexpr int PER = kSortRows / 256;
   const int b = blockIdx.x;
-  for (int j = threadIdx.x; j < k; j += blockDim.x) hsm[j] = 0;
-  __syncthreads();
   const int64_t r0 = (int64_t)b * kSortRows;
   const int64_t r1 = min(n, r0 + kSortRows);
-  unsigned long long ch = 0;
-  for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
-    const int lab = label[i];
-    if (lab >= 0 && lab < k) atomicAdd(&hsm[lab], 1);
-    if (track) {
-      ch += (lab_prev[i] != lab);
-      lab_prev[i] = lab;
+  // the block's labels (and previous labels) are in flight together
+  int lab[PER], prev[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int64_t i = r0 + threadIdx.x + 256 * q;
+    lab[q] = (i < r1) ? label[i] : -1;
+    prev[q] = (track && i < r1) ? lab_prev[i] : -1;
+  }
+  for (int j = threadIdx.x; j < k; j += blockDim.x) hsm[j] = 0;
+  __syncthreads();
+  int ch = 0;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int64_t i = r0 + threadIdx.x + 256 * q;
+    if (lab[q] >= 0 && lab[q] < k) atomicAdd(&hsm[lab[q]], 1);
+    if (track && i < r1) {
+      ch += (prev[q] != lab[q]);
+      lab_prev[i] = lab[q];
     }
   }
   __syncthreads();
   int32_t* out = counts + (int64_t)b * k;
   for (int j = threadIdx.x; j < k; j += blockDim.x) out[j] = hsm[j];
   if (track) {
+    // changed labels per wave, summed by scan_top_kernel (no global atomics)
+#pragma unroll
     for (int m = 32; m >= 1; m >>= 1) ch += __shfl_xor(ch, m, 64);
-    if ((threadIdx.x & 63) == 0 && ch) atomicAdd(&st->changed, ch);
+    if ((threadIdx.x & 63) == 0) chg[4 * b + (threadIdx.x >> 6)] = ch;
   }
 }
 
@@ -120,9 +132,19 @@ __global__ __launch_bounds__(256) void scan_col_kernel(int32_t* __restrict__ seg
 // rows); chunk_base likewise for reduction chunks.
 __global__ __launch_bounds__(1024) void scan_top_kernel(int k, int32_t* __restrict__ base,
                                                         int32_t* __restrict__ chunk_base,
+                                                        const int32_t* __restrict__ chg, int nb,
+                                                        LoopState* __restrict__ st,
                                                         const int* __restrict__ gate) {
   if (gate && *gate) return;
   __shared__ int sh[64];
+  if (chg) {
+    // labels changed in this sort: the hist blocks' counts
+    int c = 0;
+    for (int b = threadIdx.x; b < 4 * nb; b += 1024) c += chg[b];
+    int total_changed;
+    block_excl_scan_1024(c, sh, total_changed);
+    if (threadIdx.x == 0) st->changed += (unsigned long long)total_changed;
+  }
   const int per = (k + 1023) / 1024;  // columns per thread, contiguous
   const int j0 = threadIdx.x * per;
   int tot_local = 0, ch_local = 0;
@@ -172,7 +194,9 @@ __global__ __launch_bounds__(256) void scan_fill_kernel(int32_t* __restrict__ co
   }
 }
 
-// ---- 5. stable scatter: one wave per block, 64 rows at a time ----
+// ---- 5. stable scatter: one wave per block, 64 rows at a time; a row's
+// rank among the step's rows of its cluster comes from the lanes below it
+// whose label matches bit for bit ----
 __global__ __launch_bounds__(64) void scatter_kernel(const int32_t* __restrict__ label, int64_t n,
                                                      int k, const int32_t* __restrict__ offs,
                                                      int32_t* __restrict__ perm,
@@ -185,27 +209,41 @@ __global__ __launch_bounds__(64) void scatter_kernel(const int32_t* __restrict__
   for (int j = lane; j < k; j += 64) cnt[j] = ob[j];
   __syncthreads();
   const int64_t r0 = (int64_t)b * kSortRows;
-  for (int c = 0; c < kSortRows; c += 64) {
-    const int64_t i = r0 + c + lane;
-    if (r0 + c >= n) break;
-    int lab = (i < n) ? label[i] : -1;
-    if (lab < 0 || lab >= k) lab = -1;
-    int rank = 0, tot = 0;
+  const int nbits = 32 - __clz(k);
+  const unsigned long long below = (1ull << lane) - 1ull;
+  constexpr int STEPS = kSortRows / 64, GRP = 8;
+  for (int g = 0; g < STEPS; g += GRP) {
+    if (r0 + 64 * g >= n) break;
+    int labs[GRP];                     // eight steps' labels in flight together
 #pragma unroll
-    for (int t = 0; t < 64; ++t) {
-      const int lt = __builtin_amdgcn_readlane(lab, t);
-      const int eq = (lt == lab) ? 1 : 0;
-      rank += (t < lane) ? eq : 0;
-      tot += eq;
+    for (int c = 0; c < GRP; ++c) {
+      const int64_t i = r0 + 64 * (g + c) + lane;
+      labs[c] = (i < n) ? label[i] : -1;
     }
-    int pos = 0;
-    if (lab >= 0) pos = cnt[lab] + rank;
-    __syncthreads();
-    if (lab >= 0) {
-      perm[pos] = (int32_t)i;
-      if (rank == tot - 1) cnt[lab] = pos + 1;
+#pragma unroll
+    for (int c = 0; c < GRP; ++c) {
+      const int64_t i = r0 + 64 * (g + c) + lane;
+      if (r0 + 64 * (g + c) >= n) break;
+      int lab = labs[c];
+      if (lab < 0 || lab >= k) lab = -1;
+      // lanes holding the same label: one ballot per label bit (labels and
+      // -1 differ in their low nbits bits, since k < 2^nbits)
+      unsigned long long same = ~0ull;
+      for (int bit = 0; bit < nbits; ++bit) {
+        const bool on = (lab >> bit) & 1;
+        const unsigned long long bal = __ballot(on);
+        same &= on ? bal : ~bal;
+      }
+      const int rank = __popcll(same & below), tot = __popcll(same);
+      int pos = 0;
+      if (lab >= 0) pos = cnt[lab] + rank;
+      __syncthreads();
+      if (lab >= 0) {
+        perm[pos] = (int32_t)i;
+        if (rank == tot - 1) cnt[lab] = pos + 1;
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
 }
 
@@ -214,7 +252,10 @@ hipError_t launch_sort(hipStream_t s, const int32_t* label, int32_t* lab_prev, i
                        int32_t* perm, LoopState* st, int track, const int* gate) {
   const int nb = (int)((n + kSortRows - 1) / kSortRows);
   const size_t lds = (size_t)k * sizeof(int);
-  hipLaunchKernelGGL(hist_kernel, dim3(nb), dim3(256), lds, s, label, lab_prev, n, k, counts, st,
+  // with track, counts has 4 nb more entries after the nb x k matrix: the
+  // numbers of changed labels per hist wave
+  int32_t* chg = track ? counts + (int64_t)nb * k : nullptr;
+  hipLaunchKernelGGL(hist_kernel, dim3(nb), dim3(256), lds, s, label, lab_prev, n, k, counts, chg,
                      track, gate);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -226,7 +267,8 @@ hipError_t launch_sort(hipStream_t s, const int32_t* label, int32_t* lab_prev, i
                      k, base, chunk_base, gate);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(scan_top_kernel, dim3(1), dim3(1024), 0, s, k, base, chunk_base, gate);
+  hipLaunchKernelGGL(scan_top_kernel, dim3(1), dim3(1024), 0, s, k, base, chunk_base, chg, nb, st,
+                     gate);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(scan_fill_kernel, g2, dim3(256), 0, s, counts, nb, k, segsum, base, gate);
@@ -411,7 +453,9 @@ __global__ __launch_bounds__(256) void finalize_kernel(
   __shared__ double red[3][4];
   const int j = blockIdx.x;
   const int c0 = chunk_base[j], c1 = chunk_base[j + 1];
+  // chunk sums in chunk order; unrolled so that the loads issue together
   double W = 0.0, Q = 0.0;
+#pragma unroll 8
   for (int c = c0; c < c1; ++c) {
     W += partW[c];
     Q += partQ[c];
@@ -419,6 +463,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(
   double dotCS = 0.0, cn2 = 0.0, s2 = 0.0;
   for (int col = threadIdx.x; col < d; col += 256) {
     double S = 0.0;
+#pragma unroll 8
     for (int c = c0; c < c1; ++c) S += partS[(int64_t)c * d + col];
     const float cp = C_prev[(int64_t)j * d + col];
     const double cpd = (double)cp;

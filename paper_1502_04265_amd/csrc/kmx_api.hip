@@ -107,7 +107,8 @@ kmx_status ensure_common(kmx_ctx* ctx, int64_t n, int d, int k) {
   KMX_TRY(grow(ctx, ctx->full_rows2, (size_t)n * sizeof(int)));
   KMX_TRY(grow(ctx, ctx->cstats8, sizeof(CenterStats)));
   KMX_TRY(grow(ctx, ctx->brute, (size_t)n * sizeof(int)));
-  KMX_TRY(grow(ctx, ctx->counts, (size_t)nb * k * sizeof(int32_t)));
+  // nb x k block counts, then the changed labels of each of the 4 nb hist waves
+  KMX_TRY(grow(ctx, ctx->counts, ((size_t)nb * k + 4 * nb) * sizeof(int32_t)));
   KMX_TRY(grow(ctx, ctx->segsum, (size_t)kScanSegs * k * sizeof(int32_t)));
   KMX_TRY(grow(ctx, ctx->base, (size_t)(k + 1) * sizeof(int32_t)));
   KMX_TRY(grow(ctx, ctx->chunk_base, (size_t)(k + 1) * sizeof(int32_t)));
@@ -171,9 +172,10 @@ kmx_status run_prep_centers(kmx_ctx* ctx, const float* C, int k, int d, int prec
 }
 
 // GEMM passes: FP8 (rows with more than three centers inside its bound to
-// the BF16 pass), BF16 (likewise to the FP32 pass), FP32 (rows still open to
-// the every-center re-check); rows with two or three candidates inside a
-// pass's bound go to the short re-check.  gate: skip when *gate != 0.
+// the BF16 pass), BF16 (likewise to the FP32 pass; a list of at most
+// kShortFp32List rows goes to the every-center re-check instead), FP32 (rows
+// still open to the every-center re-check); rows with two or three candidates
+// inside a pass's bound go to the short re-check.  gate: skip when *gate != 0.
 kmx_status run_assign_gemm(kmx_ctx* ctx, const float* X, int64_t n, int d, int64_t ldx,
                            const float* C, int k, int prec, int32_t* label, float* d1,
                            float* d2, const int* rows, const unsigned long long* row_count,
@@ -228,6 +230,7 @@ kmx_status run_assign_gemm(kmx_ctx* ctx, const float* X, int64_t n, int d, int64
     }
     {
       Timed tm(ctx, T_RECHECK);
+      KMX_HIP(ctx, launch_route_small(ctx->stream, ctr16, next16, brute, st, gate));
       KMX_HIP(ctx, launch_assign(ctx->stream, KMX_FP32, X, ldx, nullptr, nullptr, n, next16,
                                  ctr16, d, dp32, rs, ctx->cq32.p, P<float>(ctx->ch32), k, kpad32,
                                  cs32, label, d1, d2, flags, nullptr, nullptr, 0, brute, st, gate,

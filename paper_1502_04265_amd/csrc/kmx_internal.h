@@ -125,6 +125,7 @@ constexpr int kReduceRows = 512;    // rows per segmented-reduction chunk
 constexpr int kSeedRows = 2048;     // rows per seeding block
 constexpr int kScanSegs = 64;       // column-scan segments
 constexpr int kMaxK = 16384;        // largest k (LDS histograms)
+constexpr int kShortFp32List = 4096;  // FP32-pass lists up to this length: every-center re-check
 
 // Candidate router (k_router.hip, k_train.hip).
 constexpr int kRouterH = 256;       // hidden units
@@ -216,8 +217,15 @@ hipError_t launch_recheck(hipStream_t s, const float* X, int64_t n, int d, int64
                           const float* C, int k, int32_t* label, float* d1,
                           const FlagEntry* flags, const int* brute, const LoopState* st,
                           int num_cus, const int* gate);
+// Moves a list of at most kShortFp32List rows meant for the FP32 GEMM pass
+// onto the every-center re-check list (one workgroup; gate as above).
+hipError_t launch_route_small(hipStream_t s, unsigned long long* ctr, const int* list, int* brute,
+                              LoopState* st, const int* gate);
 
 // update
+// Stable counting sort of rows by label.  counts holds nb x k entries
+// (nb = ceil(n / kSortRows)); with track, 4 nb more after them, and the number
+// of labels that differ from lab_prev is added to st->changed.
 hipError_t launch_sort(hipStream_t s, const int32_t* label, int32_t* lab_prev, int64_t n,
                        int k, int32_t* counts, int32_t* segsum, int32_t* base,
                        int32_t* chunk_base, int32_t* perm, LoopState* st, int track,

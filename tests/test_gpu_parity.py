@@ -118,14 +118,15 @@ def test_assign_near_ties_are_rechecked(ctx):
         assert nf > 0
 
 
-@pytest.mark.parametrize("m", [3, 4, 6])
-def test_assign_multiway_near_ties(ctx, m):
+@pytest.mark.parametrize("m,n", [(3, 3000), (4, 3000), (6, 3000), (6, 10000)])
+def test_assign_multiway_near_ties(ctx, m, n):
     # Points close to the center of a regular simplex of m centers: m centers
-    # are nearly equidistant, so the short list (m = 3), the FP32 pass and the
-    # every-center re-check (m >= 4) all run.  Far decoys fill out k.
-    say(f"assign {m}-way near ties")
+    # are nearly equidistant, so the short list (m = 3) and the every-center
+    # re-check (m >= 4) run; with n = 10,000 the BF16 pass hands more than
+    # 4096 rows on, which the FP32 GEMM pass then takes.  Far decoys fill out k.
+    say(f"assign {m}-way near ties, n={n}")
     rng = np.random.default_rng(10 + m)
-    n, d = 3000, 40
+    d = 40
     base = rng.normal(0, 2, d)
     dirs = np.linalg.qr(rng.normal(size=(d, m)))[0].T      # m orthonormal directions
     C_near = base + 3.0 * dirs
@@ -136,6 +137,9 @@ def test_assign_multiway_near_ties(ctx, m):
         lab, _, _, nf = ctx.assign(_dev(X), _dev(C), prec=prec)
         _check_labels(lab.cpu().numpy(), X, C, f"{m}-way {prec}")
         assert nf > 0
+        if prec == "bf16" and m >= 4:
+            _, via_fp32, _ = ctx.assign_stats()
+            assert (via_fp32 > 4096) if n > 4096 else (via_fp32 == 0), via_fp32
 
 
 # ---------------------------------------------------------------------------

@@ -75,6 +75,17 @@ __device__ __forceinline__ unsigned med3u(unsigned a, unsigned b, unsigned c) {
   return max(min(a, b), min(max(a, b), c));
 }
 
+// (v1 >= v2 >= v3) <- the three largest of {v1, v2, v3, key}
+__device__ __forceinline__ void top3_insert(unsigned key, unsigned& v1, unsigned& v2,
+                                            unsigned& v3) {
+  const unsigned n1 = max(v1, key);
+  const unsigned n2 = med3u(v1, v2, key);
+  const unsigned n3 = med3u(v2, v3, key);
+  v1 = n1;
+  v2 = n2;
+  v3 = n3;
+}
+
 // (v1 >= v2 >= v3 >= v4) <- the four largest of {v1, v2, v3, v4, key}
 __device__ __forceinline__ void top4_insert(unsigned key, unsigned& v1, unsigned& v2,
                                             unsigned& v3, unsigned& v4) {
@@ -137,6 +148,10 @@ __device__ __forceinline__ void assign_block(const AssignArgs& A, int64_t blk,
   constexpr bool BF16 = (MODE == 1);
   constexpr bool F8 = (MODE == 2);
   constexpr bool PK = (MODE != 0);       // packed keys (BF16, FP8)
+  // FP8: each lane keeps its three best keys during the tile loop (a vector
+  // operation less per key); the decision then treats a row whose lane-wise
+  // third best lies inside the bound as having more than three candidates
+  constexpr bool T3 = F8;
   constexpr int NF = F8 ? 2 : 1;         // 16-byte fragments per lane and unit
   constexpr int NT = WAVES * 64;
   constexpr int RB = BN / 16;
@@ -262,7 +277,8 @@ __device__ __forceinline__ void assign_block(const AssignArgs& A, int64_t blk,
       const int rb = sidx / (4 * NCG), i = (sidx / NCG) % 4, cg = sidx % NCG;
       const unsigned idx = ibase_p - (unsigned)(rb * 16 + i);
       const unsigned key = ((__float_as_uint(accp[cg][rb][i]) & ~mask) | idx) & pm;
-      top4_insert(key, v1[cg], v2[cg], v3[cg], v4[cg]);
+      if constexpr (T3) top3_insert(key, v1[cg], v2[cg], v3[cg]);
+      else top4_insert(key, v1[cg], v2[cg], v3[cg], v4[cg]);
     };
 
     // Packed keys of one tile into the running top-4.  With eight waves the
@@ -281,7 +297,8 @@ __device__ __forceinline__ void assign_block(const AssignArgs& A, int64_t blk,
 #pragma unroll
           for (int cg = 0; cg < NCG; ++cg) {
             const unsigned key = (__float_as_uint(a[cg][rb][i]) & ~mask) | idx;
-            top4_insert(key, v1[cg], v2[cg], v3[cg], v4[cg]);
+            if constexpr (T3) top3_insert(key, v1[cg], v2[cg], v3[cg]);
+            else top4_insert(key, v1[cg], v2[cg], v3[cg], v4[cg]);
           }
         }
       }
@@ -428,6 +445,18 @@ __device__ __forceinline__ void assign_block(const AssignArgs& A, int64_t blk,
     }
 
     // ---- merge the four lanes that hold the same point ----
+    // w3: the largest lane-wise third best (T3); a lane whose third best is
+    // inside the bound may hold further candidates that no lane kept
+    unsigned w3[NCG];
+#pragma unroll
+    for (int cg = 0; cg < NCG; ++cg) {
+      w3[cg] = 0u;
+      if constexpr (T3) {
+        w3[cg] = v3[cg];
+        w3[cg] = max(w3[cg], (unsigned)__shfl_xor((int)w3[cg], 16, 64));
+        w3[cg] = max(w3[cg], (unsigned)__shfl_xor((int)w3[cg], 32, 64));
+      }
+    }
 #pragma unroll
     for (int cg = 0; cg < NCG; ++cg) {
 #pragma unroll
@@ -531,7 +560,10 @@ __device__ __forceinline__ void assign_block(const AssignArgs& A, int64_t blk,
         if (has2) {
           if (A.d2o) A.d2o[r] = fmaxf(rw.xn2 - 2.0f * (t2 - off), 0.0f);
           flagged = (t1 - t2) <= 2.0f * E;
-          if (flagged && has3 && (t1 - t3) <= 2.0f * E) {
+          if (T3 && flagged && (w3[cg] & ~mask) &&
+              (t1 - __uint_as_float(w3[cg] & ~mask)) <= 2.0f * E) {
+            full = true;
+          } else if (flagged && has3 && (t1 - t3) <= 2.0f * E) {
             // BF16 keeps a fourth key: three listed candidates suffice unless
             // the fourth is inside the band too
             if (PK) {

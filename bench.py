@@ -350,11 +350,17 @@ def main():
 
     # ---- seeding (not part of the per-iteration metric) ----
     log("[bench] k-means++ seeding")
+    ctx.timing(True, True)
     t0 = time.perf_counter()
     C0, idx = ctx.seed(X, k, rng_seed=0)
     torch.cuda.synchronize()
     seed_ms = (time.perf_counter() - t0) * 1e3
-    log(f"[bench] seeding {seed_ms:.1f} ms")
+    seed_ev_ms = ctx.timing_read()["seed"][0]      # HIP events around the k rounds
+    ctx.timing(False, True)
+    # one round streams X once (4d bytes per row) and reads + writes D2 (16 bytes per row)
+    seed_bytes = float(k) * n * (4 * d + 16)
+    seed_gbs = seed_bytes / (seed_ev_ms * 1e-3) / 1e9
+    log(f"[bench] seeding {seed_ms:.1f} ms ({seed_ev_ms / k:.3f} ms per round, {seed_gbs:.0f} GB/s)")
 
     # ---- warmup = plain FP32 iterations 1..W, labels recorded for training ----
     t0 = time.perf_counter()
@@ -509,6 +515,9 @@ def main():
         "roofline": fp8_roof if best == "full_fp8" else bf16_roof,
         "bf16_gemm_roofline": bf16_roof,
         "fp8_gemm_roofline": fp8_roof,
+        "seed_roofline": {"bound": "hbm", "achieved": seed_gbs, "peak": HBM_PEAK_GBS,
+                          "unit": "GB/s", "frac": seed_gbs / HBM_PEAK_GBS,
+                          "kernel": "seed_round_kernel", "avg_ms": seed_ev_ms / k, "rounds": k},
         "update_roofline": {"bound": "hbm", "achieved": reduce_gbs, "peak": HBM_PEAK_GBS,
                             "unit": "GB/s", "frac": reduce_gbs / HBM_PEAK_GBS,
                             "kernel": "reduce_kernel", "avg_ms": r_ms},

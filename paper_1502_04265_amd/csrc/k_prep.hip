@@ -13,6 +13,17 @@ namespace kmx {
 // One wave per row.  Writes RowStats and, when Xq != nullptr, the BF16 row
 // (round to nearest even) of dp elements: x~ in columns [0, d), zeros after.
 // xq_max receives max_i ||x~_i||.
+__device__ __forceinline__ unsigned block_max_u32(unsigned v, unsigned* sh) {
+  // maxima of non-negative float bits over a 256-thread block (valid in thread 0)
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v = max(v, (unsigned)__shfl_xor((int)v, m, 64));
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  v = max(max(sh[0], sh[1]), max(sh[2], sh[3]));
+  __syncthreads();
+  return v;
+}
+
 __global__ __launch_bounds__(256) void prep_rows_kernel(const float* __restrict__ X, int64_t n,
                                                         int d, int64_t ldx, int dp,
                                                         uint16_t* __restrict__ Xq,
@@ -58,7 +69,10 @@ __global__ __launch_bounds__(256) void prep_rows_kernel(const float* __restrict_
       local_max = max(local_max, __float_as_uint(r.nxq));
     }
   }
-  if (lane == 0 && xq_max) atomicMax(xq_max, local_max);
+  // one atomic per block (same-address atomics from every XCD serialize)
+  __shared__ unsigned shm[4];
+  local_max = block_max_u32(local_max, shm);
+  if (threadIdx.x == 0 && xq_max) atomicMax(xq_max, local_max);
 }
 
 hipError_t launch_prep_rows(hipStream_t s, const float* X, int64_t n, int d, int64_t ldx,
@@ -77,16 +91,6 @@ hipError_t launch_prep_rows(hipStream_t s, const float* X, int64_t n, int d, int
 // is then clamped away).  prec 1 (BF16): c~_j (round to nearest even) in
 // columns [0, d), zeros elsewhere; hd[j] = ||c_j||^2 / 2 in FP64.  Maxima of
 // the norms go to cs.
-__device__ __forceinline__ unsigned block_max_u32(unsigned v, unsigned* sh) {
-  // maxima of non-negative float bits over a 256-thread block (valid in thread 0)
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) v = max(v, (unsigned)__shfl_xor((int)v, m, 64));
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
-  __syncthreads();
-  v = max(max(sh[0], sh[1]), max(sh[2], sh[3]));
-  __syncthreads();
-  return v;
-}
 
 // Each wave takes padded centers wave_id, wave_id + total_waves, ...; the
 // norm maxima are reduced over the block and reach cs with one atomic per
@@ -240,7 +244,9 @@ __global__ __launch_bounds__(256) void prep_rows_f8_kernel(const float* __restri
       local_max = max(local_max, __float_as_uint(r.nxq));
     }
   }
-  if (lane == 0 && xq_max) atomicMax(xq_max, local_max);
+  __shared__ unsigned shm[4];
+  local_max = block_max_u32(local_max, shm);
+  if (threadIdx.x == 0 && xq_max) atomicMax(xq_max, local_max);
 }
 
 hipError_t launch_prep_rows_f8(hipStream_t s, const float* X, int64_t n, int d, int64_t ldx,

@@ -345,20 +345,48 @@ __device__ __forceinline__ int find_inst(const BatchInst* __restrict__ in, int n
   return lo;
 }
 
+// Batched short re-check: G lanes per entry (64 / G entries per wave), the
+// next list entry fetched one ahead; the bucket of a row is found by binary
+// search over the buckets' first rows, staged in LDS when there are at most
+// kBucketLds buckets.
+constexpr int kBucketLds = 256;
+
+template <int G>
 __global__ __launch_bounds__(256) void recheck_pair_batched_kernel(
     const BatchBucket* __restrict__ buckets, int nb, int32_t* __restrict__ label,
     const FlagEntry* __restrict__ flags, const LoopState* __restrict__ st, int64_t nrows) {
-  const unsigned long long cnt = st->flagged;
-  const int lane = threadIdx.x & 63;
-  const int64_t gw = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int64_t nw = (int64_t)gridDim.x * 4;
-  for (int64_t e = gw; e < (int64_t)cnt; e += nw) {
-    const FlagEntry fe = flags[e];
+  __shared__ int64_t sg0[kBucketLds];
+  const bool staged = nb <= kBucketLds;
+  if (staged)
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) sg0[i] = buckets[i].grow0;
+  __syncthreads();
+  constexpr int SPW = 64 / G;
+  const int64_t cnt = (int64_t)st->flagged;
+  const int lane = threadIdx.x & 63, gl = lane % G, grp = lane / G;
+  const int64_t gw = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * SPW + grp;
+  const int64_t nw = (int64_t)gridDim.x * 4 * SPW;
+  const FlagEntry none = {-1, -1, -1, 0};
+  FlagEntry fe_n = (gw < cnt) ? flags[gw] : none;
+  for (int64_t e = gw; e < cnt; e += nw) {   // uniform within a group
+    const FlagEntry fe = fe_n;
+    if (e + nw < cnt) fe_n = flags[e + nw];
     const int64_t row = fe.row;
     if (row < 0 || row >= nrows) continue;
-    const BatchBucket B = buckets[find_bucket(buckets, nb, row)];
+    int bi;
+    if (staged) {
+      int lo = 0, hi = nb - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (sg0[mid] <= row) lo = mid;
+        else hi = mid - 1;
+      }
+      bi = lo;
+    } else {
+      bi = find_bucket(buckets, nb, row);
+    }
+    const BatchBucket B = buckets[bi];
     const int d = B.d;
-    const float tol = (float)((d + 63) / 64 + 13) * 5.9604645e-8f;
+    const float tol = (float)((d + G - 1) / G + 13) * 5.9604645e-8f;
     const float* x = B.X + (row - B.grow0) * d;
     const bool vec = ((((uintptr_t)B.X) & 15) == 0) && ((((uintptr_t)B.C) & 15) == 0) &&
                      (d % 4 == 0);
@@ -368,8 +396,8 @@ __global__ __launch_bounds__(256) void recheck_pair_batched_kernel(
     cj[2] = fe.cand3 >= 0 ? min(fe.cand3, B.K - 1) : -1;
     const int nc = (cj[2] >= 0) ? 3 : 2;
     float p[3];
-    plain_dist3(x, B.C + (int64_t)cj[0] * d, B.C + (int64_t)cj[1] * d,
-                B.C + (int64_t)(nc == 3 ? cj[2] : cj[1]) * d, d, lane, vec, p[0], p[1], p[2]);
+    plain_dist3<G>(x, B.C + (int64_t)cj[0] * d, B.C + (int64_t)cj[1] * d,
+                   B.C + (int64_t)(nc == 3 ? cj[2] : cj[1]) * d, d, gl, vec, p[0], p[1], p[2]);
     int b = 0;
     for (int q = 1; q < nc; ++q)
       if (p[q] < p[b] || (p[q] == p[b] && cj[q] < cj[b])) b = q;
@@ -381,7 +409,7 @@ __global__ __launch_bounds__(256) void recheck_pair_batched_kernel(
       float bh = 0.f, bl = 0.f;
       for (int q = 0; q < nc; ++q) {
         float h, l;
-        exact_dist(x, B.C + (int64_t)cj[q] * d, d, lane, h, l);
+        exact_dist<G>(x, B.C + (int64_t)cj[q] * d, d, gl, h, l);
         if (q == 0 || df_less(h, l, bh, bl) || (h == bh && l == bl && cj[q] < best)) {
           bh = h;
           bl = l;
@@ -389,7 +417,7 @@ __global__ __launch_bounds__(256) void recheck_pair_batched_kernel(
         }
       }
     }
-    if (lane == 0) label[row] = best;
+    if (gl == 0) label[row] = best;
   }
 }
 
@@ -465,8 +493,9 @@ hipError_t launch_recheck_batched(hipStream_t s, const BatchBucket* buckets, int
                                   const BatchInst* insts, int ninst, int32_t* label,
                                   const FlagEntry* flags, const int* brute, const LoopState* st,
                                   int64_t nrows, int num_cus) {
-  hipLaunchKernelGGL(recheck_pair_batched_kernel, dim3((unsigned)(num_cus * 8)), dim3(256), 0, s,
-                     buckets, nbuckets, label, flags, st, nrows);
+  // 16 lanes per entry: bucket widths are at most 512 (8 steps of 16 bytes)
+  hipLaunchKernelGGL(recheck_pair_batched_kernel<16>, dim3((unsigned)(num_cus * 8)), dim3(256), 0,
+                     s, buckets, nbuckets, label, flags, st, nrows);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(recheck_full_batched_kernel, dim3((unsigned)(num_cus * 4)), dim3(kFullWaves * 64), 0, s,

@@ -7,10 +7,11 @@
 // it lowers D2_i to ||x_i - c_{r-1}||^2 (FP64 direct differences of the FP32
 // inputs, exact up to the final sums) and writes the FP64 block sum of
 // w_i * D2_i (r = 0: of w_i).  A row is read by a group of G lanes, lane s
-// taking the 16-byte chunks s, s + G, ... of the row, so each lane has up to
-// NV independent loads in flight; the previous center's chunks stay in
-// registers as FP64 for the whole block (NV = 0: rows wider than NV * G
-// chunks, center re-read from the cache).  The last block to finish (atomic
+// taking the 16-byte chunks s, s + G, ... of the row; a lane keeps the NV
+// loads of its group's next row in flight while it reduces the current row,
+// and the previous center's chunks stay in registers as FP64 for the whole
+// block (NV = 0: rows wider than 512 chunks, one row at a time, the center
+// re-read from the cache).  The last block to finish (atomic
 // ticket) draws u_r from SplitMix64, finds the first block whose inclusive
 // prefix of block sums strictly exceeds u_r * M, then the first row inside it,
 // copies that row into C and marks it chosen.  If the mass M is zero it draws
@@ -149,7 +150,6 @@ __global__ __launch_bounds__(256) void seed_round_kernel(
                                 i0 < r1 && sub + G * v < nch);
     }
     for (int64_t i = r0 + grp; i < r1; i += NG) {
-      const float* x = X + i * ldx;
       double acc = 0.0;
       if constexpr (NV > 0) {
         sf32x4_t xv[NV];
@@ -170,6 +170,7 @@ __global__ __launch_bounds__(256) void seed_round_kernel(
           }
         acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
       } else {
+        const float* x = X + i * ldx;
 #pragma unroll 4
         for (int q = sub; q < nch; q += G) {
           const sf32x4_t xv = load_chunk<VEC>(x, q, d, true);

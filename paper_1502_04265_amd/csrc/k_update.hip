@@ -8,7 +8,7 @@
 //     sum_{i in P_j} w_i ||x_i - c||^2 = Q_j - 2 c.S_j + W_j ||c||^2 .
 //
 // Mechanism: a stable counting sort of row ids by label (block histograms,
-// column scans, in-block ranks from a 64-lane comparison), then one workgroup
+// column scans, in-block ranks from one ballot per label bit), then one workgroup
 // per chunk of at most kReduceRows rows of one cluster gathers whole rows
 // (coalesced) and accumulates FP64 partial features, and one workgroup per
 // cluster sums its chunks in chunk order.  Every sum has a fixed order, so the

@@ -170,6 +170,24 @@ def test_update_matches_oracle(ctx, n, d, k, weighted):
     assert abs(cac - ref_cac) <= 1e-9 * ref_cac
 
 
+@pytest.mark.parametrize("n,d,k", [(2049, 3, 1), (5000, 8, 16), (6001, 4, 1024)])
+def test_update_sort_label_widths(ctx, n, d, k):
+    # the counting sort ranks a step's rows by one ballot per label bit: one
+    # cluster (a single bit), powers of two, and a ragged last step of rows
+    say(f"update label widths n={n} d={d} k={k}")
+    rng = np.random.default_rng(k)
+    X = rng.normal(size=(n, d)).astype(np.float32)
+    lab = rng.integers(0, k, size=n).astype(np.int32)
+    C_prev = rng.normal(size=(k, d)).astype(np.float32)
+    C_new, W, _ = ctx.update(_dev(X), _dev(lab), _dev(C_prev))
+    Co, Wo, _, _ = ok.update(X, None, lab, C_prev)
+    Cg = C_new.cpu().numpy().astype(np.float64)
+    for j in range(k):
+        ref = np.linalg.norm(Co[j])
+        assert np.linalg.norm(Cg[j] - Co[j]) <= 1e-5 * max(ref, 1e-3), j
+    np.testing.assert_array_equal(W.cpu().numpy(), Wo)
+
+
 @pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
 def test_cost_matches_oracle(ctx, prec):
     say(f"cost {prec}")
@@ -203,6 +221,14 @@ def test_seed_matches_oracle(ctx, n, d, k, weighted, seed):
     Co, idx_o, _ = ok.seed(X, w, k, seed)
     assert idx.cpu().numpy().tolist() == idx_o.tolist()
     assert np.array_equal(C.cpu().numpy(), X[idx_o])
+
+
+def test_seed_single_row(ctx):
+    say("seed one row")
+    X = np.array([[3.0]], dtype=np.float32)
+    C, idx = ctx.seed(_dev(X), 1, rng_seed=4)
+    assert idx.cpu().numpy().tolist() == [0]
+    assert np.array_equal(C.cpu().numpy(), X)
 
 
 def test_seed_zero_mass_fallback(ctx):

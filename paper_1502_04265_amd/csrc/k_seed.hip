@@ -13,9 +13,11 @@
 // block (NV = 0: rows wider than 512 chunks, one row at a time, the center
 // re-read from the cache).  The last block to finish (atomic
 // ticket) draws u_r from SplitMix64, finds the first block whose inclusive
-// prefix of block sums strictly exceeds u_r * M, then the first row inside it,
-// copies that row into C and marks it chosen.  If the mass M is zero it draws
-// by weight among the rows not chosen yet.
+// prefix of block sums strictly exceeds u_r * M, then the first row inside it
+// (each search: every thread sums a contiguous slice, one block scan, one
+// thread walks the slice that crosses), copies that row into C and marks it
+// chosen.  If the mass M is zero it draws by weight among the rows not chosen
+// yet.
 #include "kmx_device.h"
 #include "kmx_internal.h"
 
@@ -93,6 +95,65 @@ __device__ int64_t pick_linear(int64_t lo, int64_t hi, double target, F mass, do
   return (int64_t)red[1] - 1;
 }
 
+// The same search in two levels: thread t sums the contiguous slice
+// [lo + t per, lo + (t + 1) per) in index order, one block scan gives the
+// slices' prefixes, and the first thread whose inclusive prefix exceeds
+// target walks its slice again from its exclusive prefix.  If the walk finds
+// no crossing (the scan and the walk round differently), the last index with
+// positive mass in that slice; with no crossing anywhere, the last index with
+// positive mass; if there is none, -1.  Uses sh[0..3]; every thread must
+// call it.
+template <typename F>
+__device__ int64_t pick_sliced(int64_t lo, int64_t hi, double target, F mass, double* sh,
+                               unsigned long long* red, double* excl) {
+  __shared__ double sinc[256];
+  __shared__ long long spick;
+  __shared__ double sbefore;
+  const int t = threadIdx.x;
+  const int64_t per = (hi - lo + 255) / 256;
+  const int64_t a = min(hi, lo + (int64_t)t * per), b = min(hi, a + per);
+  double loc = 0.0;
+  int64_t lastpos = -1;
+  for (int64_t i = a; i < b; ++i) {
+    const double v = mass(i);
+    loc += v;
+    if (v > 0.0) lastpos = i;
+  }
+  if (t == 0) {
+    red[0] = ~0ull;
+    red[1] = 0ull;
+    spick = -1;
+  }
+  const double inc = block_incl_scan_256(loc, sh);   // barriers order the resets above
+  sinc[t] = inc;
+  if (b > a && inc > target) atomicMin(&red[0], (unsigned long long)t);
+  if (lastpos >= 0) atomicMax(&red[1], (unsigned long long)(lastpos + 1));
+  __syncthreads();
+  const unsigned long long ts = red[0];
+  if (ts != ~0ull && (unsigned long long)t == ts) {
+    double run = (t > 0) ? sinc[t - 1] : 0.0;
+    int64_t found = -1;
+    for (int64_t i = a; i < b; ++i) {
+      const double nr = run + mass(i);
+      if (nr > target) {
+        found = i;
+        break;
+      }
+      run = nr;
+    }
+    if (found < 0) found = lastpos;
+    spick = found;
+    sbefore = run;
+  }
+  __syncthreads();
+  int64_t pick = spick;
+  const bool hit = ts != ~0ull && pick >= 0;
+  if (!hit) pick = (int64_t)red[1] - 1;
+  if (excl && hit) *excl = sbefore;
+  __syncthreads();
+  return pick;
+}
+
 typedef __attribute__((ext_vector_type(4))) float sf32x4_t;
 
 // Chunk q (elements 4q .. 4q + 3) of a row of length d; zeros past the row.
@@ -112,7 +173,7 @@ __global__ __launch_bounds__(256) void seed_round_kernel(
     const float* __restrict__ X, int64_t n, int d, int64_t ldx, const float* __restrict__ w,
     int r, uint64_t seed, double* __restrict__ D2, uint8_t* __restrict__ chosen,
     double* __restrict__ part, unsigned int* __restrict__ ctr, float* __restrict__ C,
-    int64_t* __restrict__ idx_out) {
+    int64_t* __restrict__ idx_out, int64_t rpb) {
   __shared__ double sh[8];
   __shared__ unsigned long long red[2];
   __shared__ unsigned int ticket;
@@ -120,8 +181,8 @@ __global__ __launch_bounds__(256) void seed_round_kernel(
   const int nb = gridDim.x;
   const int b = blockIdx.x;
   const int sub = threadIdx.x & (G - 1), grp = threadIdx.x / G;
-  const int64_t r0 = (int64_t)b * kSeedRows;
-  const int64_t r1 = min(n, r0 + kSeedRows);
+  const int64_t r0 = (int64_t)b * rpb;
+  const int64_t r1 = min(n, r0 + rpb);
   const int nch = (d + 3) >> 2;
 
   // ---- 1. lower D2 against the previous center; block mass ----
@@ -213,16 +274,16 @@ __global__ __launch_bounds__(256) void seed_round_kernel(
   if (M > 0.0) {
     const double target = u * M;
     double before = 0.0;
-    int64_t qb = pick_linear(0, nb, target, [&](int64_t q) { return pv[q]; }, sh, red, &before);
+    int64_t qb = pick_sliced(0, nb, target, [&](int64_t q) { return pv[q]; }, sh, red, &before);
     if (qb >= 0) {
-      const int64_t b0 = qb * kSeedRows;
-      const int64_t b1 = min(n, b0 + kSeedRows);
+      const int64_t b0 = qb * rpb;
+      const int64_t b1 = min(n, b0 + rpb);
       const double tin = target - before;
       if (r == 0) {
-        pick = pick_linear(b0, b1, tin, [&](int64_t i) { return w ? (double)w[i] : 1.0; }, sh,
+        pick = pick_sliced(b0, b1, tin, [&](int64_t i) { return w ? (double)w[i] : 1.0; }, sh,
                            red, nullptr);
       } else {
-        pick = pick_linear(b0, b1, tin,
+        pick = pick_sliced(b0, b1, tin,
                            [&](int64_t i) { return (w ? (double)w[i] : 1.0) * D2[i]; }, sh,
                            red, nullptr);
       }
@@ -265,7 +326,8 @@ __global__ __launch_bounds__(256) void seed_round_kernel(
 hipError_t launch_seed_round(hipStream_t s, const float* X, int64_t n, int d, int64_t ldx,
                              const float* w, int r, uint64_t seed, double* D2, uint8_t* chosen,
                              double* part, unsigned int* ctr, float* C_out, int64_t* idx_out) {
-  const int nb = (int)((n + kSeedRows - 1) / kSeedRows);
+  const int64_t rpb = kSeedRows;
+  const int nb = (int)((n + rpb - 1) / rpb);
   const int nch = (d + 3) / 4;
   // whole 16-byte chunks: rows of X and of C start 16-byte aligned
   const bool vec = (d % 4 == 0) && (ldx % 4 == 0) && ((((uintptr_t)X) & 15) == 0) &&
@@ -274,10 +336,10 @@ hipError_t launch_seed_round(hipStream_t s, const float* X, int64_t n, int d, in
   do {                                                                                           \
     if (vec)                                                                                     \
       hipLaunchKernelGGL((seed_round_kernel<G_, NV_, true>), dim3(nb), dim3(256), 0, s, X, n, d, \
-                         ldx, w, r, seed, D2, chosen, part, ctr, C_out, idx_out);                \
+                         ldx, w, r, seed, D2, chosen, part, ctr, C_out, idx_out, rpb);           \
     else                                                                                         \
       hipLaunchKernelGGL((seed_round_kernel<G_, NV_, false>), dim3(nb), dim3(256), 0, s, X, n,   \
-                         d, ldx, w, r, seed, D2, chosen, part, ctr, C_out, idx_out);             \
+                         d, ldx, w, r, seed, D2, chosen, part, ctr, C_out, idx_out, rpb);        \
     return hipGetLastError();                                                                    \
   } while (0)
   if (nch <= 16) KMX_S(4, 4);

@@ -172,8 +172,8 @@ kmx_status run_prep_centers(kmx_ctx* ctx, const float* C, int k, int d, int prec
 }
 
 // GEMM passes: FP8 (rows with more than three centers inside its bound to
-// the BF16 pass), BF16 (likewise to the FP32 pass; a list of at most
-// kShortFp32List rows goes to the every-center re-check instead), FP32 (rows
+// the BF16 pass), BF16 (likewise to the FP32 pass; a short list, see
+// kShortListWork, goes to the every-center re-check instead), FP32 (rows
 // still open to the every-center re-check); rows with two or three candidates
 // inside a pass's bound go to the short re-check.  gate: skip when *gate != 0.
 kmx_status run_assign_gemm(kmx_ctx* ctx, const float* X, int64_t n, int d, int64_t ldx,
@@ -230,7 +230,7 @@ kmx_status run_assign_gemm(kmx_ctx* ctx, const float* X, int64_t n, int d, int64
     }
     {
       Timed tm(ctx, T_RECHECK);
-      KMX_HIP(ctx, launch_route_small(ctx->stream, ctr16, next16, brute, st, gate));
+      KMX_HIP(ctx, launch_route_small(ctx->stream, ctr16, next16, brute, st, k, d, gate));
       KMX_HIP(ctx, launch_assign(ctx->stream, KMX_FP32, X, ldx, nullptr, nullptr, n, next16,
                                  ctr16, d, dp32, rs, ctx->cq32.p, P<float>(ctx->ch32), k, kpad32,
                                  cs32, label, d1, d2, flags, nullptr, nullptr, 0, brute, st, gate,

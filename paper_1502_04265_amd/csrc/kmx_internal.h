@@ -125,7 +125,9 @@ constexpr int kReduceRows = 512;    // rows per segmented-reduction chunk
 constexpr int kSeedRows = 2048;     // rows per seeding block
 constexpr int kScanSegs = 64;       // column-scan segments
 constexpr int kMaxK = 16384;        // largest k (LDS histograms)
-constexpr int kShortFp32List = 4096;  // FP32-pass lists up to this length: every-center re-check
+// FP32-pass lists of at most kShortListWork / (k d) rows (at least 4096) go
+// to the every-center re-check instead (4096 rows at k = 1000, d = 512)
+constexpr double kShortListWork = 4096.0 * 1000.0 * 512.0;
 
 // Candidate router (k_router.hip, k_train.hip).
 constexpr int kRouterH = 256;       // hidden units
@@ -217,10 +219,11 @@ hipError_t launch_recheck(hipStream_t s, const float* X, int64_t n, int d, int64
                           const float* C, int k, int32_t* label, float* d1,
                           const FlagEntry* flags, const int* brute, const LoopState* st,
                           int num_cus, const int* gate);
-// Moves a list of at most kShortFp32List rows meant for the FP32 GEMM pass
-// onto the every-center re-check list (one workgroup; gate as above).
+// Moves a list meant for the FP32 GEMM pass onto the every-center re-check
+// list when it holds at most max(4096, kShortListWork / (k d)) rows (one
+// workgroup; gate as above).
 hipError_t launch_route_small(hipStream_t s, unsigned long long* ctr, const int* list, int* brute,
-                              LoopState* st, const int* gate);
+                              LoopState* st, int k, int d, const int* gate);
 
 // update
 // Stable counting sort of rows by label.  counts holds nb x k entries

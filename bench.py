@@ -357,10 +357,14 @@ def main():
     seed_ms = (time.perf_counter() - t0) * 1e3
     seed_ev_ms = ctx.timing_read()["seed"][0]      # HIP events around the k rounds
     ctx.timing(False, True)
-    # one round streams X once (4d bytes per row) and reads + writes D2 (16 bytes per row)
-    seed_bytes = float(k) * n * (4 * d + 16)
+    seed_rows = ctx.seed_stats()                    # rows whose distance a round computed
+    # rounds 1 .. k-1: every row's D2 and closest-center index (12 bytes), and
+    # for the rows read the row itself plus the D2 / index writes (4d + 12 bytes)
+    seed_bytes = 12.0 * n * (k - 1) + float(seed_rows) * (4 * d + 12)
     seed_gbs = seed_bytes / (seed_ev_ms * 1e-3) / 1e9
-    log(f"[bench] seeding {seed_ms:.1f} ms ({seed_ev_ms / k:.3f} ms per round, {seed_gbs:.0f} GB/s)")
+    seed_frac_read = seed_rows / float(n * max(k - 1, 1))
+    log(f"[bench] seeding {seed_ms:.1f} ms ({seed_ev_ms / k:.3f} ms per round, {seed_gbs:.0f} GB/s, "
+        f"{100 * seed_frac_read:.1f}% of the rows read per round)")
 
     # ---- warmup = plain FP32 iterations 1..W, labels recorded for training ----
     t0 = time.perf_counter()
@@ -517,7 +521,8 @@ def main():
         "fp8_gemm_roofline": fp8_roof,
         "seed_roofline": {"bound": "hbm", "achieved": seed_gbs, "peak": HBM_PEAK_GBS,
                           "unit": "GB/s", "frac": seed_gbs / HBM_PEAK_GBS,
-                          "kernel": "seed_round_kernel", "avg_ms": seed_ev_ms / k, "rounds": k},
+                          "kernel": "seed_round_kernel", "avg_ms": seed_ev_ms / k, "rounds": k,
+                          "rows_read_fraction": seed_frac_read},
         "update_roofline": {"bound": "hbm", "achieved": reduce_gbs, "peak": HBM_PEAK_GBS,
                             "unit": "GB/s", "frac": reduce_gbs / HBM_PEAK_GBS,
                             "kernel": "reduce_kernel", "avg_ms": r_ms},

@@ -86,10 +86,17 @@ const char* kmx_last_error(const kmx_ctx* ctx);
  *   C_out   device, k x d float32: exact copies of the chosen rows.
  *   idx_out device, k int64, nullable: the chosen row indices.
  * Requires 1 <= k <= n.  Rows with w_i = 0 are never chosen while rows with
- * positive weight remain. */
+ * positive weight remain.  A round skips the rows whose D2 provably cannot
+ * drop (the new center is at least twice as far from the row's closest
+ * chosen center as the row is), so D2 is the same as with every row read. */
 kmx_status kmx_seed(kmx_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
                     const float* w, int32_t k, uint64_t rng_seed,
                     float* C_out, int64_t* idx_out);
+
+/* Rows whose distance to the new center the most recent kmx_seed on ctx
+ * computed, summed over its rounds 1 .. k-1 (the other rows kept their D2 by
+ * the triangle-inequality test).  rows_read: host output.  Synchronizes. */
+kmx_status kmx_seed_stats(kmx_ctx* ctx, int64_t* rows_read);
 
 /* Assignment step (Sec. 1): label_i = argmin_j ||x_i - c_j||^2, lowest j on
  * ties.  The distance GEMM runs in `prec`; flagged rows are re-checked.

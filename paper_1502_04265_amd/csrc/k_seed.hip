@@ -173,7 +173,9 @@ __global__ __launch_bounds__(256) void seed_round_kernel(
     const float* __restrict__ X, int64_t n, int d, int64_t ldx, const float* __restrict__ w,
     int r, uint64_t seed, double* __restrict__ D2, uint8_t* __restrict__ chosen,
     double* __restrict__ part, unsigned int* __restrict__ ctr, float* __restrict__ C,
-    int64_t* __restrict__ idx_out, int64_t rpb) {
+    int64_t* __restrict__ idx_out, int64_t rpb, int32_t* __restrict__ sa,
+    const double* __restrict__ cc2, int* __restrict__ nread,
+    unsigned long long* __restrict__ rows_read) {
   __shared__ double sh[8];
   __shared__ unsigned long long red[2];
   __shared__ unsigned int ticket;
@@ -190,6 +192,39 @@ __global__ __launch_bounds__(256) void seed_round_kernel(
   if (r == 0) {
     for (int64_t i = r0 + threadIdx.x; i < r1; i += 256) macc += w ? (double)w[i] : 1.0;
   } else {
+    // Rows that need the distance to c = c_{r-1}: all of them in round 1;
+    // afterwards a row whose nearest chosen center c_a (index sa) satisfies
+    // ||c - c_a||^2 >= 4 D2 (1 + 1e-8) keeps its D2 (triangle inequality:
+    // ||x - c|| >= ||c - c_a|| - ||x - c_a|| >= ||x - c_a||, with room for the
+    // FP64 rounding of both distances; cc2 is rounded down), so its row is
+    // not read.  The rows that need it are listed in row order (ballots), so
+    // every sum keeps a fixed order.
+    __shared__ int slist[kSeedRows];
+    __shared__ int wtot[4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int cnt = 0;
+    for (int64_t s0 = r0; s0 < r1; s0 += 256) {
+      const int64_t i = s0 + threadIdx.x;
+      bool need = false;
+      if (i < r1) {
+        need = true;
+        if (r >= 2) {
+          const double dv = D2[i];
+          if (cc2[sa[i]] >= 4.0 * dv * (1.0 + 1e-8)) {
+            need = false;
+            macc += w ? (double)w[i] * dv : dv;
+          }
+        }
+      }
+      const unsigned long long bal = __ballot(need);
+      if (lane == 0) wtot[wv] = __popcll(bal);
+      __syncthreads();
+      int off = cnt;
+      for (int q = 0; q < wv; ++q) off += wtot[q];
+      if (need) slist[off + __popcll(bal & ((1ull << lane) - 1ull))] = (int)(i - r0);
+      cnt += (wtot[0] + wtot[1]) + (wtot[2] + wtot[3]);
+      __syncthreads();
+    }
     const float* c = C + (int64_t)(r - 1) * d;
     double cd[NV > 0 ? NV : 1][4];
     if constexpr (NV > 0) {
@@ -200,27 +235,28 @@ __global__ __launch_bounds__(256) void seed_round_kernel(
         for (int e = 0; e < 4; ++e) cd[v][e] = (double)cv[e];
       }
     }
-    // NV > 0: the chunks of the group's next row are loaded while the
+    // NV > 0: the chunks of the group's next listed row are loaded while the
     // current one is reduced
     sf32x4_t xn[NV > 0 ? NV : 1];
     if constexpr (NV > 0) {
-      const int64_t i0 = r0 + grp;
+      const bool ok = grp < cnt;
+      const int64_t i0 = ok ? r0 + slist[grp] : 0;
 #pragma unroll
       for (int v = 0; v < NV; ++v)
-        xn[v] = load_chunk<VEC>(X + (i0 < r1 ? i0 : 0) * ldx, sub + G * v, d,
-                                i0 < r1 && sub + G * v < nch);
+        xn[v] = load_chunk<VEC>(X + i0 * ldx, sub + G * v, d, ok && sub + G * v < nch);
     }
-    for (int64_t i = r0 + grp; i < r1; i += NG) {
+    for (int jl = grp; jl < cnt; jl += NG) {
+      const int64_t i = r0 + slist[jl];
       double acc = 0.0;
       if constexpr (NV > 0) {
         sf32x4_t xv[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) xv[v] = xn[v];
-        const int64_t inx = i + NG;
+        const bool ok = jl + NG < cnt;
+        const int64_t inx = ok ? r0 + slist[jl + NG] : 0;
 #pragma unroll
         for (int v = 0; v < NV; ++v)
-          xn[v] = load_chunk<VEC>(X + (inx < r1 ? inx : 0) * ldx, sub + G * v, d,
-                                  inx < r1 && sub + G * v < nch);
+          xn[v] = load_chunk<VEC>(X + inx * ldx, sub + G * v, d, ok && sub + G * v < nch);
         double a4[4] = {0.0, 0.0, 0.0, 0.0};   // four independent FMA chains
 #pragma unroll
         for (int v = 0; v < NV; ++v)
@@ -247,11 +283,15 @@ __global__ __launch_bounds__(256) void seed_round_kernel(
 #pragma unroll
       for (int m = G / 2; m >= 1; m >>= 1) acc += __shfl_xor(acc, m, 64);
       if (sub == 0) {
-        const double dv = (r == 1) ? acc : fmin(D2[i], acc);
+        const double old = (r == 1) ? 0.0 : D2[i];
+        const bool closer = (r == 1) || acc < old;
+        const double dv = closer ? acc : old;
+        if (closer) sa[i] = r - 1;
         D2[i] = dv;
         macc += w ? (double)w[i] * dv : dv;
       }
     }
+    if (threadIdx.x == 0) nread[b] = cnt;
   }
   const double bsum = block_sum_256(macc, sh);
   if (threadIdx.x == 0) {
@@ -265,6 +305,13 @@ __global__ __launch_bounds__(256) void seed_round_kernel(
   // ---- 2. the last block draws the row ----
   __threadfence();
   const volatile double* pv = part;
+  if (r >= 1 && rows_read) {
+    const volatile int* nv = nread;
+    long long t_read = 0;
+    for (int q = threadIdx.x; q < nb; q += 256) t_read += nv[q];
+    const double tr = block_sum_256((double)t_read, sh);
+    if (threadIdx.x == 0) *rows_read += (unsigned long long)tr;
+  }
   const uint64_t z = splitmix64_at(seed, (uint64_t)r);
   const double u = (double)(z >> 11) * 0x1.0p-53;
   double t = 0.0;
@@ -323,9 +370,36 @@ __global__ __launch_bounds__(256) void seed_round_kernel(
   }
 }
 
+// Squared distances from the newest center c_{r-1} to the earlier centers,
+// FP64 sums of the FP32 differences rounded down by 1e-12 relative (a lower
+// bound on the exact value); one wave per earlier center.
+__global__ __launch_bounds__(256) void center_gap_kernel(const float* __restrict__ C, int r,
+                                                         int d, double* __restrict__ cc2) {
+  const int lane = threadIdx.x & 63;
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j >= r - 1) return;   // uniform per wave
+  const float* c = C + (int64_t)(r - 1) * d;
+  const float* cj = C + (int64_t)j * d;
+  double acc = 0.0;
+  for (int q = lane; q < d; q += 64) {
+    const double df = (double)c[q] - (double)cj[q];
+    acc = fma(df, df, acc);
+  }
+  acc = wave_sum_f64(acc);
+  if (lane == 0) cc2[j] = acc * (1.0 - 1e-12);
+}
+
 hipError_t launch_seed_round(hipStream_t s, const float* X, int64_t n, int d, int64_t ldx,
                              const float* w, int r, uint64_t seed, double* D2, uint8_t* chosen,
-                             double* part, unsigned int* ctr, float* C_out, int64_t* idx_out) {
+                             double* part, unsigned int* ctr, float* C_out, int64_t* idx_out,
+                             int32_t* sa, double* cc2, int* nread,
+                             unsigned long long* rows_read) {
+  if (r >= 2) {
+    hipLaunchKernelGGL(center_gap_kernel, dim3((unsigned)((r - 1 + 3) / 4)), dim3(256), 0, s,
+                       C_out, r, d, cc2);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   const int64_t rpb = kSeedRows;
   const int nb = (int)((n + rpb - 1) / rpb);
   const int nch = (d + 3) / 4;
@@ -336,10 +410,12 @@ hipError_t launch_seed_round(hipStream_t s, const float* X, int64_t n, int d, in
   do {                                                                                           \
     if (vec)                                                                                     \
       hipLaunchKernelGGL((seed_round_kernel<G_, NV_, true>), dim3(nb), dim3(256), 0, s, X, n, d, \
-                         ldx, w, r, seed, D2, chosen, part, ctr, C_out, idx_out, rpb);           \
+                         ldx, w, r, seed, D2, chosen, part, ctr, C_out, idx_out, rpb, sa, cc2,    \
+                         nread, rows_read);                                                     \
     else                                                                                         \
       hipLaunchKernelGGL((seed_round_kernel<G_, NV_, false>), dim3(nb), dim3(256), 0, s, X, n,   \
-                         d, ldx, w, r, seed, D2, chosen, part, ctr, C_out, idx_out, rpb);        \
+                         d, ldx, w, r, seed, D2, chosen, part, ctr, C_out, idx_out, rpb, sa,     \
+                         cc2, nread, rows_read);                                                \
     return hipGetLastError();                                                                    \
   } while (0)
   if (nch <= 16) KMX_S(4, 4);

@@ -333,6 +333,7 @@ kmx_status kmx_destroy(kmx_ctx* ctx) {
       &ctx->base,      &ctx->chunk_base, &ctx->perm,     &ctx->partS,      &ctx->partQ,
       &ctx->partW,     &ctx->W,        &ctx->termC,      &ctx->termMu,     &ctx->state,
       &ctx->D2,        &ctx->chosen,   &ctx->seed_part,  &ctx->seed_ctr,   &ctx->scratch_c,
+      &ctx->seed_a,    &ctx->seed_cc,  &ctx->seed_nread,
       &ctx->hist,      &ctx->fb_rows,  &ctx->keys,       &ctx->cdist,      &ctx->nbr,
       &ctx->nbd,       &ctx->fbh,      &ctx->xq8,        &ctx->sx8,        &ctx->rowstats8,
       &ctx->xstats8,   &ctx->cq8,      &ctx->ch8,        &ctx->hd8,        &ctx->cstats8,
@@ -381,15 +382,36 @@ kmx_status kmx_seed(kmx_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t 
   KMX_TRY(grow(ctx, ctx->D2, (size_t)n * sizeof(double)));
   KMX_TRY(grow(ctx, ctx->chosen, (size_t)n));
   KMX_TRY(grow(ctx, ctx->seed_part, (size_t)nb * sizeof(double)));
-  KMX_TRY(grow(ctx, ctx->seed_ctr, 16));
+  KMX_TRY(grow(ctx, ctx->seed_ctr, 16));   // ticket (4 bytes), rows read (8 bytes at 8)
+  KMX_TRY(grow(ctx, ctx->seed_a, (size_t)n * sizeof(int32_t)));
+  KMX_TRY(grow(ctx, ctx->seed_cc, (size_t)k * sizeof(double)));
+  KMX_TRY(grow(ctx, ctx->seed_nread, (size_t)nb * sizeof(int)));
   Timed tm(ctx, T_SEED);
   KMX_HIP(ctx, launch_fill_u8(ctx->stream, P<uint8_t>(ctx->chosen), n, 0));
   KMX_HIP(ctx, launch_fill_i32(ctx->stream, P<int32_t>(ctx->seed_ctr), 4, 0));
   for (int r = 0; r < k; ++r) {
     KMX_HIP(ctx, launch_seed_round(ctx->stream, X, n, d, ldx, w, r, rng_seed, P<double>(ctx->D2),
                                    P<uint8_t>(ctx->chosen), P<double>(ctx->seed_part),
-                                   P<unsigned int>(ctx->seed_ctr), C_out, idx_out));
+                                   P<unsigned int>(ctx->seed_ctr), C_out, idx_out,
+                                   P<int32_t>(ctx->seed_a), P<double>(ctx->seed_cc),
+                                   P<int>(ctx->seed_nread),
+                                   (unsigned long long*)(P<unsigned char>(ctx->seed_ctr) + 8)));
   }
+  return KMX_OK;
+}
+
+kmx_status kmx_seed_stats(kmx_ctx* ctx, int64_t* rows_read) {
+  if (!ctx) return KMX_EINVAL;
+  ctx->err.clear();
+  if (!rows_read) return fail(ctx, KMX_EINVAL, "rows_read is NULL");
+  *rows_read = 0;
+  if (!ctx->seed_ctr.p) return KMX_OK;
+  KMX_TRY(set_device(ctx));
+  unsigned long long h = 0;
+  KMX_HIP(ctx, hipMemcpyAsync(&h, P<unsigned char>(ctx->seed_ctr) + 8, sizeof(h),
+                              hipMemcpyDeviceToHost, ctx->stream));
+  KMX_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  *rows_read = (int64_t)h;
   return KMX_OK;
 }
 

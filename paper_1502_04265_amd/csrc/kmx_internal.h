@@ -168,7 +168,7 @@ struct kmx_ctx {
   kmx::Buf partS, partQ, partW;
   kmx::Buf W, termC, termMu;
   kmx::Buf state;
-  kmx::Buf D2, chosen, seed_part, seed_ctr;
+  kmx::Buf D2, chosen, seed_part, seed_ctr, seed_a, seed_cc, seed_nread;
   kmx::Buf scratch_c, hist;
   kmx::Buf fb_rows, keys, cdist, nbr, nbd, fbh;   // routed assignment
   // batched Lloyd: concatenated instances and their descriptors
@@ -244,11 +244,15 @@ hipError_t launch_finalize(hipStream_t s, const double* partS, const double* par
 hipError_t launch_cost_sum(hipStream_t s, const double* termC, const double* termMu, int k,
                            LoopState* st, double* cost_hist, int mode, const int* gate);
 
-// seeding
+// seeding: one round r (r >= 2 first fills cc2 with the squared distances of
+// c_{r-1} to the earlier centers).  sa: n ints, the index of each row's
+// closest chosen center; cc2: k doubles; nread: one int per 2048-row block;
+// rows_read: adds the rows whose distance was computed.
 hipError_t launch_seed_round(hipStream_t s, const float* X, int64_t n, int d, int64_t ldx,
                              const float* w, int r, uint64_t seed, double* D2,
                              uint8_t* chosen, double* part, unsigned int* ctr,
-                             float* C_out, int64_t* idx_out);
+                             float* C_out, int64_t* idx_out, int32_t* sa, double* cc2,
+                             int* nread, unsigned long long* rows_read);
 
 // batched (k_assign.hip, k_batch.hip)
 int batched_variants(int d);                  // number of tile shapes for width d

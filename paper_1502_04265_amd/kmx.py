@@ -66,6 +66,7 @@ def lib():
                       ctypes.c_int, _vp, _vp, _vp],
         "kmx_timing": [_vp, ctypes.c_int, ctypes.c_int],
         "kmx_assign_stats": [_vp, _vp, _vp, _vp],
+        "kmx_seed_stats": [_vp, _vp],
         "kmx_timing_read": [_vp, ctypes.c_int, _vp, _vp],
         "kmx_lloyd_batched": [_vp, _vp, _i32, _i32, ctypes.c_int, _vp],
         "kmx_batched_autotune": [_vp, _vp, _i32, ctypes.c_int, ctypes.c_char_p, _vp],
@@ -218,6 +219,12 @@ class Context:
         _check(lib().kmx_invalidate(self._p, _ptr(X)), self._p)
 
     # ---- measurement -------------------------------------------------------
+    def seed_stats(self):
+        """Rows whose distance the most recent seed() computed (rounds 1 .. k-1)."""
+        a = ctypes.c_int64(0)
+        _check(lib().kmx_seed_stats(self._p, ctypes.byref(a)), self._p)
+        return int(a.value)
+
     def assign_stats(self):
         """(listed, fp32, full) re-check counts of the most recent assignment."""
         a, b, c = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int64(0)

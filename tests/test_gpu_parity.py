@@ -225,6 +225,9 @@ def test_seed_matches_oracle(ctx, n, d, k, weighted, seed):
     Co, idx_o, _ = ok.seed(X, w, k, seed)
     assert idx.cpu().numpy().tolist() == idx_o.tolist()
     assert np.array_equal(C.cpu().numpy(), X[idx_o])
+    # round 1 reads every row; later rounds skip rows whose D2 cannot drop
+    rows_read = ctx.seed_stats()
+    assert n <= rows_read <= n * (k - 1), rows_read
 
 
 def test_seed_single_row(ctx):

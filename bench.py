@@ -23,6 +23,7 @@ import argparse
 import json
 import os
 import sys
+import tempfile
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -116,8 +117,10 @@ def batched_main(args):
         probs.append({"X": X, "C": C0, "w": w})
     torch.cuda.synchronize()
     seed_s = time.perf_counter() - t0
-    cache = os.path.join(ROOT, "gpurun_out", "batched_tiles.jsonl")
-    os.makedirs(os.path.dirname(cache), exist_ok=True)
+    # autotuner cache (JSON lines keyed by device); KMX_TILE_CACHE overrides
+    cache = os.environ.get("KMX_TILE_CACHE",
+                           os.path.join(tempfile.gettempdir(), "kmx_batched_tiles.jsonl"))
+    os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)
     t0 = time.perf_counter()
     loaded = ctx.batched_autotune(probs, cache)
     tune_s = time.perf_counter() - t0
@@ -303,8 +306,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
+              "(run it with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

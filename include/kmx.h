@@ -46,7 +46,7 @@ typedef enum {
   KMX_EINVAL = 1,       /* bad argument (null pointer, size, range)          */
   KMX_ENOMEM = 2,       /* device workspace allocation failed                */
   KMX_EDEVICE = 3,      /* a HIP runtime call or kernel launch failed        */
-  KMX_EUNSUPPORTED = 4  /* valid request outside what this build implements  */
+  KMX_EUNSUPPORTED = 4  /* valid request outside what the library implements */
 } kmx_status;
 
 /* Arithmetic of the distance GEMM inside assignment.  Labels are exact for

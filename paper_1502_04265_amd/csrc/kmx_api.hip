@@ -311,7 +311,7 @@ kmx_status kmx_create(kmx_ctx** out, int device, void* hip_stream) {
   }
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
     return fail(nullptr, KMX_EUNSUPPORTED,
-                std::string("this build targets gfx950, device is ") + prop.gcnArchName);
+                std::string("the library is compiled for gfx950, device is ") + prop.gcnArchName);
   kmx_ctx* c = new (std::nothrow) kmx_ctx();
   if (!c) return fail(nullptr, KMX_ENOMEM, "out of host memory");
   c->device = device;

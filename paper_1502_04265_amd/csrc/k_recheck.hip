@@ -150,7 +150,140 @@ __global__ __launch_bounds__(256) void recheck_pair_kernel(
   }
 }
 
+// Pipelined short re-check for short, 16-byte aligned rows (at most 4 G NX
+// columns): while entry e is decided, the label and the row of entry e + 1
+// and the list entry e + 2 are in flight (a lane holds its NX row chunks of
+// the next entry in registers).  Same per-lane summation order as
+// plain_dist3, so the same plain distances.  Short rows make the plain
+// re-check latency-bound; long ones are bandwidth-bound and use
+// recheck_pair_kernel.
+template <int G, int NX>
+__device__ __forceinline__ void load_row_chunks(const float* __restrict__ x, int d, int lane,
+                                                float4 (&xv)[NX]) {
+#pragma unroll
+  for (int i = 0; i < NX; ++i) {
+    const int q = lane * 4 + 4 * G * i;
+    xv[i] = (q < d) ? *(const float4*)(x + q) : make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+}
+
+template <int G, int NX>
+__device__ __forceinline__ void plain_dist3_rows(const float4 (&xv)[NX],
+                                                 const float* __restrict__ c0,
+                                                 const float* __restrict__ c1,
+                                                 const float* __restrict__ c2, int d, int lane,
+                                                 float& p0, float& p1, float& p2) {
+  float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+#pragma unroll
+  for (int i = 0; i < NX; ++i) {
+    const int q = lane * 4 + 4 * G * i;
+    if (q < d) {
+      const float4 u0 = *(const float4*)(c0 + q);
+      const float4 u1 = *(const float4*)(c1 + q);
+      const float4 u2 = *(const float4*)(c2 + q);
+      const float xs[4] = {xv[i].x, xv[i].y, xv[i].z, xv[i].w};
+      const float v0[4] = {u0.x, u0.y, u0.z, u0.w};
+      const float v1[4] = {u1.x, u1.y, u1.z, u1.w};
+      const float v2[4] = {u2.x, u2.y, u2.z, u2.w};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        float df = xs[e] - v0[e];
+        a0 = __builtin_fmaf(df, df, a0);
+        df = xs[e] - v1[e];
+        a1 = __builtin_fmaf(df, df, a1);
+        df = xs[e] - v2[e];
+        a2 = __builtin_fmaf(df, df, a2);
+      }
+    }
+  }
+#pragma unroll
+  for (int m = G / 2; m >= 1; m >>= 1) {
+    a0 += __shfl_xor(a0, m, 64);
+    a1 += __shfl_xor(a1, m, 64);
+    a2 += __shfl_xor(a2, m, 64);
+  }
+  p0 = a0;
+  p1 = a1;
+  p2 = a2;
+}
+
+template <int G, int NX>
+__global__ __launch_bounds__(256) void recheck_pair_pipe_kernel(
+    const float* __restrict__ X, int64_t n, int d, int64_t ldx, const float* __restrict__ C,
+    int k, int32_t* __restrict__ label, float* __restrict__ d1o,
+    const FlagEntry* __restrict__ flags, const LoopState* __restrict__ st,
+    const int* __restrict__ gate) {
+  if (gate && *gate) return;
+  constexpr int SPW = 64 / G;          // entries per wave at once
+  const int64_t cnt = (int64_t)st->flagged;
+  const int lane = threadIdx.x & 63, gl = lane % G, grp = lane / G;
+  const int64_t gw = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * SPW + grp;
+  const int64_t nw = (int64_t)gridDim.x * 4 * SPW;
+  const float tol = (float)((d + G - 1) / G + 13) * 5.9604645e-8f;
+  const FlagEntry none = {-1, -1, -1, 0};
+  auto valid = [&](const FlagEntry& f) { return f.row >= 0 && f.row < n; };
+  // entries each row appears in at most once, so a label fetched ahead is
+  // never one this kernel writes before reading it
+  FlagEntry fe_c = (gw < cnt) ? flags[gw] : none;
+  FlagEntry fe_n = (gw + nw < cnt) ? flags[gw + nw] : none;
+  int lab_c = valid(fe_c) ? label[fe_c.row] : 0;
+  float4 xc[NX];
+  load_row_chunks<G, NX>(X + (int64_t)(valid(fe_c) ? fe_c.row : 0) * ldx, valid(fe_c) ? d : 0,
+                         gl, xc);
+  for (int64_t e = gw; e < cnt; e += nw) {   // uniform within a group
+    // stage 1: list entry e + 2; stage 2: label and row of entry e + 1
+    const FlagEntry fe_nn = (e + 2 * nw < cnt) ? flags[e + 2 * nw] : none;
+    const bool vn = valid(fe_n);
+    const int lab_n = vn ? label[fe_n.row] : 0;
+    float4 xn[NX];
+    load_row_chunks<G, NX>(X + (int64_t)(vn ? fe_n.row : 0) * ldx, vn ? d : 0, gl, xn);
+    // stage 3: decide entry e
+    if (valid(fe_c)) {
+      const int row = fe_c.row;
+      int cj[3];
+      cj[0] = min(max(lab_c, 0), k - 1);
+      cj[1] = min(max(fe_c.cand2, 0), k - 1);
+      cj[2] = fe_c.cand3 >= 0 ? min(fe_c.cand3, k - 1) : -1;
+      const int nc = (cj[2] >= 0) ? 3 : 2;
+      float p[3];
+      plain_dist3_rows<G, NX>(xc, C + (int64_t)cj[0] * d, C + (int64_t)cj[1] * d,
+                              C + (int64_t)(nc == 3 ? cj[2] : cj[1]) * d, d, gl, p[0], p[1],
+                              p[2]);
+      int b = 0;
+      for (int q = 1; q < nc; ++q)
+        if (p[q] < p[b] || (p[q] == p[b] && cj[q] < cj[b])) b = q;
+      bool sure = true;
+      for (int q = 0; q < nc; ++q)
+        if (q != b && !(p[q] - p[b] > tol * (p[q] + p[b]))) sure = false;
+      int best = cj[b];
+      float bd = p[b];
+      if (!sure) {
+        const float* x = X + (int64_t)row * ldx;
+        float bh = 0.f, bl = 0.f;
+        for (int q = 0; q < nc; ++q) {
+          float h, l;
+          exact_dist<G>(x, C + (int64_t)cj[q] * d, d, gl, h, l);
+          if (q == 0 || df_less(h, l, bh, bl) || (h == bh && l == bl && cj[q] < best)) {
+            bh = h; bl = l; best = cj[q];
+          }
+        }
+        bd = bh;
+      }
+      if (gl == 0) {
+        label[row] = best;
+        if (d1o) d1o[row] = bd;
+      }
+    }
+    fe_c = fe_n;
+    lab_c = lab_n;
+#pragma unroll
+    for (int i = 0; i < NX; ++i) xc[i] = xn[i];
+    fe_n = fe_nn;
+  }
+}
+
 constexpr int kFullWaves = 16;   // waves per row of the every-center re-check
+constexpr bool kRecheckPipe = true;   // pipelined short re-check for rows of d <= 128
 
 // One workgroup per row that needs every center.  Each wave takes four
 // centers at a time (centers 4(kFullWaves i + w) + 0..3 for wave w), its lanes splitting
@@ -305,8 +438,16 @@ hipError_t launch_recheck(hipStream_t s, const float* X, int64_t n, int d, int64
   if (blocks > cap) blocks = cap;
   if (blocks < 1) blocks = 1;
   // lanes per entry: enough to cover a row in a few 16-byte steps, more
-  // entries in flight per wave for short rows
-  if (d <= 256)
+  // entries in flight per wave for short rows; short aligned rows pipelined
+  const bool vec = ((((uintptr_t)X) & 15) == 0) && (ldx % 4 == 0) &&
+                   ((((uintptr_t)C) & 15) == 0) && (d % 4 == 0);
+  if (kRecheckPipe && vec && d <= 64)
+    hipLaunchKernelGGL((recheck_pair_pipe_kernel<16, 1>), dim3((unsigned)blocks), dim3(256), 0, s,
+                       X, n, d, ldx, C, k, label, d1, flags, st, gate);
+  else if (kRecheckPipe && vec && d <= 128)
+    hipLaunchKernelGGL((recheck_pair_pipe_kernel<16, 2>), dim3((unsigned)blocks), dim3(256), 0, s,
+                       X, n, d, ldx, C, k, label, d1, flags, st, gate);
+  else if (d <= 256)
     hipLaunchKernelGGL(recheck_pair_kernel<16>, dim3((unsigned)blocks), dim3(256), 0, s, X, n,
                        d, ldx, C, k, label, d1, flags, st, gate);
   else if (d <= 1024)

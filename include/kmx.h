@@ -167,8 +167,8 @@ kmx_status kmx_project(kmx_ctx* ctx, const float* X, int64_t rows, int32_t d_in,
  *   fp32     rows the BF16 GEMM passed to the FP32 GEMM because more than
  *            three centers lay within its error bound (with KMX_FP8E4M3 the
  *            FP8 pass first hands the rows with more than three centers
- *            inside its bound to the BF16 pass); 0 when there were few such
- *            rows (at most max(4096, 2.1e9 / (k d))), which then go to the
+ *            inside its bound to the BF16 pass); 0 when there were at most
+ *            4096 such rows and k d >= 65536, which then go to the
  *            every-center re-check,
  *   full     rows re-checked against every center.
  * Synchronizes. */

@@ -420,12 +420,10 @@ __global__ __launch_bounds__(1024) void route_small_kernel(unsigned long long* _
 
 hipError_t launch_route_small(hipStream_t s, unsigned long long* ctr, const int* list, int* brute,
                               LoopState* st, int k, int d, const int* gate) {
-  // every-center work of the list against the FP32 pass's fixed latency
-  double lim = kShortListWork / ((double)k * (double)d);
-  if (lim < 4096.0) lim = 4096.0;
-  if (lim > 1e15) lim = 1e15;
-  hipLaunchKernelGGL(route_small_kernel, dim3(1), dim3(1024), 0, s, ctr, list, brute, st,
-                     (unsigned long long)lim, gate);
+  const unsigned long long lim =
+      ((int64_t)k * d >= kShortListMinKD) ? (unsigned long long)kShortList : 0ull;
+  hipLaunchKernelGGL(route_small_kernel, dim3(1), dim3(1024), 0, s, ctr, list, brute, st, lim,
+                     gate);
   return hipGetLastError();
 }
 

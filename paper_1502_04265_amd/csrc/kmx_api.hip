@@ -172,8 +172,8 @@ kmx_status run_prep_centers(kmx_ctx* ctx, const float* C, int k, int d, int prec
 }
 
 // GEMM passes: FP8 (rows with more than three centers inside its bound to
-// the BF16 pass), BF16 (likewise to the FP32 pass; a short list, see
-// kShortListWork, goes to the every-center re-check instead), FP32 (rows
+// the BF16 pass), BF16 (likewise to the FP32 pass; a short list with long
+// centers, see kShortList, goes to the every-center re-check instead), FP32 (rows
 // still open to the every-center re-check); rows with two or three candidates
 // inside a pass's bound go to the short re-check.  gate: skip when *gate != 0.
 kmx_status run_assign_gemm(kmx_ctx* ctx, const float* X, int64_t n, int d, int64_t ldx,

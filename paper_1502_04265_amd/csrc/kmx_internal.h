@@ -125,9 +125,13 @@ constexpr int kReduceRows = 512;    // rows per segmented-reduction chunk
 constexpr int kSeedRows = 2048;     // rows per seeding block
 constexpr int kScanSegs = 64;       // column-scan segments
 constexpr int kMaxK = 16384;        // largest k (LDS histograms)
-// FP32-pass lists of at most kShortListWork / (k d) rows (at least 4096) go
-// to the every-center re-check instead (4096 rows at k = 1000, d = 512)
-constexpr double kShortListWork = 4096.0 * 1000.0 * 512.0;
+// FP32-pass lists of at most kShortList rows go to the every-center re-check
+// instead when k d >= kShortListMinKD: the pass then costs one workgroup's
+// walk over many long centers however few rows it has, while for small k d
+// the pass is short and the every-center re-check (a workgroup per row) is
+// the slower one
+constexpr int kShortList = 4096;
+constexpr int64_t kShortListMinKD = 65536;
 
 // Candidate router (k_router.hip, k_train.hip).
 constexpr int kRouterH = 256;       // hidden units
@@ -220,7 +224,7 @@ hipError_t launch_recheck(hipStream_t s, const float* X, int64_t n, int d, int64
                           const FlagEntry* flags, const int* brute, const LoopState* st,
                           int num_cus, const int* gate);
 // Moves a list meant for the FP32 GEMM pass onto the every-center re-check
-// list when it holds at most max(4096, kShortListWork / (k d)) rows (one
+// list when it holds at most kShortList rows and k d >= kShortListMinKD (one
 // workgroup; gate as above).
 hipError_t launch_route_small(hipStream_t s, unsigned long long* ctr, const int* list, int* brute,
                               LoopState* st, int k, int d, const int* gate);

@@ -119,14 +119,14 @@ def test_assign_near_ties_are_rechecked(ctx):
 
 
 @pytest.mark.parametrize("m,n,d,nfar", [(3, 3000, 40, 20), (4, 3000, 40, 20), (6, 3000, 40, 20),
-                                          (6, 10000, 512, 994)])
+                                          (6, 3000, 512, 994), (6, 10000, 512, 994)])
 def test_assign_multiway_near_ties(ctx, m, n, d, nfar):
     # Points close to the center of a regular simplex of m centers: m centers
     # are nearly equidistant, so the short list (m = 3) and the every-center
-    # re-check (m >= 4) run.  The BF16 pass hands every row on when m >= 4: a
-    # list of at most max(4096, 4096 * 1000 * 512 / (k d)) rows goes to the
-    # every-center re-check, a longer one (n = 10,000 at k = 1000, d = 512) to
-    # the FP32 GEMM pass.  Far decoys fill out k.
+    # re-check run.  The BF16 pass hands every row on when m >= 4: a list of
+    # at most 4096 rows with k d >= 65536 goes to the every-center re-check,
+    # otherwise (short centers, or n = 10,000) to the FP32 GEMM pass.  Far
+    # decoys fill out k.
     say(f"assign {m}-way near ties, n={n} d={d} k={m + nfar}")
     rng = np.random.default_rng(10 + m)
     base = rng.normal(0, 2, d)
@@ -136,14 +136,14 @@ def test_assign_multiway_near_ties(ctx, m, n, d, nfar):
     C = np.vstack([C_far[:7], C_near, C_far[7:]]).astype(np.float32)
     X = (base + 1e-3 * rng.normal(size=(n, d))).astype(np.float32)
     k = C.shape[0]
-    limit = max(4096, int(4096.0 * 1000.0 * 512.0 / (k * d)))
+    routed = n <= 4096 and k * d >= 65536
     for prec in ("fp32", "bf16", "fp8"):
         lab, _, _, nf = ctx.assign(_dev(X), _dev(C), prec=prec)
         _check_labels(lab.cpu().numpy(), X, C, f"{m}-way {prec}")
         assert nf > 0
         if prec == "bf16" and m >= 4:
             _, via_fp32, _ = ctx.assign_stats()
-            assert (via_fp32 > limit) if n > limit else (via_fp32 == 0), (via_fp32, limit)
+            assert (via_fp32 == 0) if routed else (via_fp32 > 0.9 * n), (via_fp32, n)
 
 
 # ---------------------------------------------------------------------------

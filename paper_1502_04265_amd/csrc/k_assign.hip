@@ -141,7 +141,7 @@ struct AssignShape {
 // loop over every center tile, the merge of the four lanes of a point, the
 // decision and the re-check list entries.  lds holds two tile buffers, hsh
 // two rows of BN per-center values, wcnt 3 * WAVES counters, wbase 3 bases.
-template <int MODE, int NKU, int NCG, int BN, int WAVES, int PF, bool EP>
+template <int MODE, int NKU, int NCG, int BN, int WAVES, int PF, bool EP, int SUBT>
 __device__ __forceinline__ void assign_block(const AssignArgs& A, int64_t blk,
                                              unsigned char* lds, float* hsh, int* wcnt,
                                              unsigned long long* wbase) {
@@ -154,7 +154,13 @@ __device__ __forceinline__ void assign_block(const AssignArgs& A, int64_t blk,
   constexpr bool T3 = F8;
   constexpr int NF = F8 ? 2 : 1;         // 16-byte fragments per lane and unit
   constexpr int NT = WAVES * 64;
-  constexpr int RB = BN / 16;
+  // SUBT sub-tiles per LDS tile: the keys of each BN / SUBT centers are
+  // inserted before the next ones are computed, so the accumulators stay
+  // those of one sub-tile while the tile barrier is paid once per BN centers
+  static_assert(BN % SUBT == 0 && (BN / SUBT) % 16 == 0, "sub-tiles of whole 16-center blocks");
+  static_assert(SUBT == 1 || (MODE == 2 && !EP), "sub-tiles: FP8 without the pipelined epilogue");
+  constexpr int BNS = BN / SUBT;
+  constexpr int RB = BNS / 16;
   using S = AssignShape<MODE, NKU, NCG, BN, WAVES>;
   constexpr int ROWB = S::ROWB;
   constexpr int PITCH = ROWB + 16;       // padded LDS row pitch
@@ -287,8 +293,8 @@ __device__ __forceinline__ void assign_block(const AssignArgs& A, int64_t blk,
     // while the other one issues matrix instructions.  (The keys live in
     // registers only, so the barrier does not order them.)
     const bool late = (WAVES == 8) && (wave >= WAVES / 2);
-    auto insert_tile = [&](const f32x4_t (&a)[NCG][RB], int tt) {
-      const unsigned ibase = mask - (unsigned)(tt * BN + grp * 4);
+    auto insert_tile = [&](const f32x4_t (&a)[NCG][RB], int c0) {   // c0: first center
+      const unsigned ibase = mask - (unsigned)(c0 + grp * 4);
 #pragma unroll
       for (int rb = 0; rb < RB; ++rb) {
 #pragma unroll
@@ -312,16 +318,18 @@ __device__ __forceinline__ void assign_block(const AssignArgs& A, int64_t blk,
 
       f32x4_t acc[NCG][RB];
 #pragma unroll
+      for (int st = 0; st < SUBT; ++st) {
+#pragma unroll
       for (int rb = 0; rb < RB; ++rb) {
         f32x4_t a0 = {0.f, 0.f, 0.f, 0.f};
-        if (PK) a0 = *(const f32x4_t*)(&hsh[buf * BN + rb * 16 + grp * 4]);
+        if (PK) a0 = *(const f32x4_t*)(&hsh[buf * BN + st * BNS + rb * 16 + grp * 4]);
 #pragma unroll
         for (int cg = 0; cg < NCG; ++cg) acc[cg][rb] = a0;
       }
 
       if constexpr (F8) {
         // A fragments one unit ahead, as for BF16 below
-        const unsigned char* abase = &lds[buf * BUFB + prow * PITCH + grp * 32];
+        const unsigned char* abase = &lds[buf * BUFB + (st * BNS + prow) * PITCH + grp * 32];
         u32x4_t af8[2][RB][2];
         auto load_a8 = [&](int q, int slot) {
 #pragma unroll
@@ -360,7 +368,7 @@ __device__ __forceinline__ void assign_block(const AssignArgs& A, int64_t blk,
       // their use (which would expose the LDS latency at every unit).
       constexpr int NB = PF + 1;
       u32x4_t afr[NB][RB];
-      const unsigned char* abase = &lds[buf * BUFB + prow * PITCH + grp * 16];
+      const unsigned char* abase = &lds[buf * BUFB + (st * BNS + prow) * PITCH + grp * 16];
 #pragma unroll
       for (int q = 0; q < PF; ++q)
 #pragma unroll
@@ -408,16 +416,16 @@ __device__ __forceinline__ void assign_block(const AssignArgs& A, int64_t blk,
 #pragma unroll
           for (int rb = 0; rb < RB; ++rb) accp[cg][rb] = acc[cg][rb];
       } else if constexpr (PK) {
-        if (!late) insert_tile(acc, t);
+        if (!late || st + 1 < SUBT) insert_tile(acc, t * BN + st * BNS);
       } else {
         // centers arrive in increasing index order per lane: a strict '>'
         // keeps the lower index on ties
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
-          const f32x4_t hv = *(const f32x4_t*)(&hsh[buf * BN + rb * 16 + grp * 4]);
+          const f32x4_t hv = *(const f32x4_t*)(&hsh[buf * BN + st * BNS + rb * 16 + grp * 4]);
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
-            const int j = t * BN + rb * 16 + grp * 4 + i;
+            const int j = t * BN + st * BNS + rb * 16 + grp * 4 + i;
 #pragma unroll
             for (int cg = 0; cg < NCG; ++cg) {
               const float tt = acc[cg][rb][i] - hv[i];
@@ -432,10 +440,12 @@ __device__ __forceinline__ void assign_block(const AssignArgs& A, int64_t blk,
         }
       }
 
+      }   // sub-tiles
+
       if (t + 1 < ntiles) finish_tile(buf ^ 1);
       __syncthreads();
       if constexpr (PK && !PIPE) {
-        if (late) insert_tile(acc, t);
+        if (late) insert_tile(acc, t * BN + (SUBT - 1) * BNS);
       }
     }
     if constexpr (PIPE) {
@@ -641,7 +651,8 @@ __device__ __forceinline__ void assign_block(const AssignArgs& A, int64_t blk,
 }
 
 // MODE: 0 FP32, 1 BF16, 2 FP8 E4M3.  Persistent over the blocks of points.
-template <int MODE, int NKU, int NCG, int BN, int WAVES, int PF = 1, bool EP = false>
+template <int MODE, int NKU, int NCG, int BN, int WAVES, int PF = 1, bool EP = false,
+          int SUBT = 1>
 __global__ __launch_bounds__(WAVES * 64) void assign_kernel(AssignArgs A,
                                                             const unsigned long long* row_count,
                                                             const int* __restrict__ gate) {
@@ -654,7 +665,7 @@ __global__ __launch_bounds__(WAVES * 64) void assign_kernel(AssignArgs A,
   if (A.rows) A.npts = (int64_t)(*row_count);
   const int64_t nblk = (A.npts + S::PPB - 1) / S::PPB;
   for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x)
-    assign_block<MODE, NKU, NCG, BN, WAVES, PF, EP>(A, blk, lds, hsh, wcnt, wbase);
+    assign_block<MODE, NKU, NCG, BN, WAVES, PF, EP, SUBT>(A, blk, lds, hsh, wcnt, wbase);
 }
 
 // ---------------------------------------------------------------------------
@@ -691,17 +702,24 @@ int assign_dpad(int prec, int d) {
   return u * ((prec == KMX_BF16) ? 32 : (prec == KMX_FP8E4M3) ? 128 : 16);
 }
 
+// FP8 rows of 4 units (d <= 512) with many centers: LDS tiles of 64 centers
+// taken as two sub-tiles of 32 (one tile barrier per 64 centers); with few
+// centers, tiles of 32 (less padding).
+static bool f8_wide_tiles(int k) { return k > 256; }
+
 // Centers per LDS tile: each of the two tile buffers stays within ~72 KB.
-int assign_tile_n(int prec, int d) {
+int assign_tile_n(int prec, int d, int k) {
   const int nku = units_for(prec, d);
-  if (prec == KMX_FP8E4M3) return nku <= 3 ? 64 : (nku <= 6 ? 32 : 16);
+  if (prec == KMX_FP8E4M3)
+    return nku <= 3 ? 64 : (nku == 4 ? (f8_wide_tiles(k) ? 64 : 32) : (nku <= 6 ? 32 : 16));
   if (prec == KMX_BF16) return (nku <= 3 || nku == 6 || nku == 8) ? 64 : 32;
   if (nku <= 4) return 64;
   if (nku <= 32) return 32;
   return 16;
 }
 
-template <int MODE, int NKU, int NCG, int BN, int WAVES, int PF = 1, bool EP = false>
+template <int MODE, int NKU, int NCG, int BN, int WAVES, int PF = 1, bool EP = false,
+          int SUBT = 1>
 static hipError_t run_assign(hipStream_t s, const void* Xsrc, int64_t xs, int vec_ok,
                              const uint8_t* sx8, int64_t n, const int* rows,
                              const unsigned long long* row_count, int d, int dp,
@@ -746,7 +764,7 @@ static hipError_t run_assign(hipStream_t s, const void* Xsrc, int64_t xs, int ve
     if (blocks > cap) blocks = cap;
   }
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL((assign_kernel<MODE, NKU, NCG, BN, WAVES, PF, EP>), dim3((unsigned)blocks),
+  hipLaunchKernelGGL((assign_kernel<MODE, NKU, NCG, BN, WAVES, PF, EP, SUBT>), dim3((unsigned)blocks),
                      dim3(WAVES * 64), 0, s, A, row_count, gate);
   return hipGetLastError();
 }
@@ -783,17 +801,19 @@ hipError_t launch_assign(hipStream_t s, int prec, const float* X, int64_t ldx, c
   }
   if (prec == KMX_FP8E4M3) {
     if (!sx8) return hipErrorInvalidValue;
-#define KMX_A(NKU_, NCG_, BN_, W_, EP_)                                                      \
-  return run_assign<2, NKU_, NCG_, BN_, W_, 1, EP_>(s, Xq, dp, 1, sx8, n, rows, row_count, d, dp, rs, \
+#define KMX_A(NKU_, NCG_, BN_, W_, EP_, SUB_)                                                \
+  return run_assign<2, NKU_, NCG_, BN_, W_, 1, EP_, SUB_>(s, Xq, dp, 1, sx8, n, rows, row_count, d, dp, rs, \
                                             Cq, ch, k, kpad, ib, cs, label, d1, d2, flags,  \
                                             full_rows, full_ctr, cascade_all, brute, st, gate, num_cus)
     switch (nku) {
-      case 1: KMX_A(1, 4, 64, 8, true);
-      case 2: KMX_A(2, 4, 64, 8, false);
-      case 3: KMX_A(3, 2, 64, 8, false);
-      case 4: KMX_A(4, 4, 32, 8, false);
-      case 6: KMX_A(6, 1, 32, 8, true);
-      case 8: KMX_A(8, 1, 16, 8, true);
+      case 1: KMX_A(1, 4, 64, 8, true, 1);
+      case 2: KMX_A(2, 4, 64, 8, false, 1);
+      case 3: KMX_A(3, 2, 64, 8, false, 1);
+      case 4:
+        if (f8_wide_tiles(k)) KMX_A(4, 4, 64, 8, false, 2);
+        KMX_A(4, 4, 32, 8, false, 1);
+      case 6: KMX_A(6, 1, 32, 8, true, 1);
+      case 8: KMX_A(8, 1, 16, 8, true, 1);
       default: return hipErrorInvalidValue;
     }
 #undef KMX_A
@@ -916,7 +936,7 @@ __device__ __forceinline__ void batched_block(const BatchInst& I, int blk,
   A.brute = brute;
   A.st = st;
   A.count_undecided = 1;
-  assign_block<1, NKU, NCG, BN, kBatchWaves, 1, false>(A, blk, lds, hsh, wcnt, wbase);
+  assign_block<1, NKU, NCG, BN, kBatchWaves, 1, false, 1>(A, blk, lds, hsh, wcnt, wbase);
 }
 
 // Persistent over the items [begin, end) of one width group; each item's

@@ -138,7 +138,7 @@ kmx_status run_prep_centers(kmx_ctx* ctx, const float* C, int k, int d, int prec
   CenterStats* cs32 = P<CenterStats>(ctx->cstats32);
   CenterStats* cs8 = P<CenterStats>(ctx->cstats8);
   const int dp32 = assign_dpad(KMX_FP32, d);
-  const int bn32 = assign_tile_n(KMX_FP32, d);
+  const int bn32 = assign_tile_n(KMX_FP32, d, k);
   const int kpad32 = (k + bn32 - 1) / bn32 * bn32;
   KMX_TRY(grow(ctx, ctx->cq32, (size_t)kpad32 * dp32 * sizeof(float)));
   KMX_TRY(grow(ctx, ctx->ch32, (size_t)kpad32 * sizeof(float)));
@@ -148,7 +148,7 @@ kmx_status run_prep_centers(kmx_ctx* ctx, const float* C, int k, int d, int prec
                                    P<float>(ctx->ch32), nullptr, cs32, nullptr));
   if (prec == KMX_BF16 || prec == KMX_FP8E4M3) {   // FP8 cascades into BF16
     const int dp = assign_dpad(KMX_BF16, d);
-    const int bn = assign_tile_n(KMX_BF16, d);
+    const int bn = assign_tile_n(KMX_BF16, d, k);
     const int kpad = (k + bn - 1) / bn * bn;
     KMX_TRY(grow(ctx, ctx->cq, (size_t)kpad * dp * sizeof(uint16_t)));
     KMX_TRY(grow(ctx, ctx->ch, (size_t)kpad * sizeof(float)));
@@ -159,7 +159,7 @@ kmx_status run_prep_centers(kmx_ctx* ctx, const float* C, int k, int d, int prec
   }
   if (prec == KMX_FP8E4M3) {
     const int dp = assign_dpad(KMX_FP8E4M3, d);
-    const int bn = assign_tile_n(KMX_FP8E4M3, d);
+    const int bn = assign_tile_n(KMX_FP8E4M3, d, k);
     const int kpad = (k + bn - 1) / bn * bn;
     KMX_TRY(grow(ctx, ctx->cq8, (size_t)kpad * dp));
     KMX_TRY(grow(ctx, ctx->ch8, (size_t)kpad * sizeof(float)));
@@ -185,7 +185,7 @@ kmx_status run_assign_gemm(kmx_ctx* ctx, const float* X, int64_t n, int d, int64
   CenterStats* cs32 = P<CenterStats>(ctx->cstats32);
   CenterStats* cs8 = P<CenterStats>(ctx->cstats8);
   const int dp32 = assign_dpad(KMX_FP32, d);
-  const int bn32 = assign_tile_n(KMX_FP32, d);
+  const int bn32 = assign_tile_n(KMX_FP32, d, k);
   const int kpad32 = (k + bn32 - 1) / bn32 * bn32;
   const RowStats* rs = P<RowStats>(ctx->rowstats);
   FlagEntry* flags = P<FlagEntry>(ctx->flags);
@@ -199,7 +199,7 @@ kmx_status run_assign_gemm(kmx_ctx* ctx, const float* X, int64_t n, int d, int64
                                st, gate, ctx->num_cus));
   } else {
     const int dp = assign_dpad(KMX_BF16, d);
-    const int bn = assign_tile_n(KMX_BF16, d);
+    const int bn = assign_tile_n(KMX_BF16, d, k);
     const int kpad = (k + bn - 1) / bn * bn;
     // rows the BF16 pass covers, and where it sends rows for the FP32 pass
     const int* rows16 = rows;
@@ -208,7 +208,7 @@ kmx_status run_assign_gemm(kmx_ctx* ctx, const float* X, int64_t n, int d, int64
     unsigned long long* ctr16 = &st->full_count;
     if (prec == KMX_FP8E4M3) {
       const int dp8 = assign_dpad(KMX_FP8E4M3, d);
-      const int bn8 = assign_tile_n(KMX_FP8E4M3, d);
+      const int bn8 = assign_tile_n(KMX_FP8E4M3, d, k);
       const int kpad8 = (k + bn8 - 1) / bn8 * bn8;
       Timed tm(ctx, T_ASSIGN);
       KMX_HIP(ctx, launch_assign(ctx->stream, KMX_FP8E4M3, X, ldx, ctx->xq8.p,

@@ -209,7 +209,7 @@ hipError_t launch_reset_small(hipStream_t s, CenterStats* cs, CenterStats* cs2, 
                               LoopState* st, int reset_iter);
 
 // assign
-int assign_tile_n(int prec, int d);   // centers per tile (kpad granularity)
+int assign_tile_n(int prec, int d, int k);   // centers per tile (kpad granularity)
 int assign_dpad(int prec, int d);     // padded row length of the GEMM operands
 hipError_t launch_assign(hipStream_t s, int prec, const float* X, int64_t ldx,
                          const void* Xq, const uint8_t* sx8, int64_t n, const int* rows,

@@ -67,9 +67,79 @@ def measured_traffic(key):
         return None
 
 
-def cpu_baseline(X_host_rows, C_host, n_full, seconds_target=10.0):
+def host_cpu():
+    """Host CPU model and the threads the process may use."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count()
+    return {"model": model, "nproc": usable}
+
+
+def library_reference():
+    """What plain library work reaches on this part, timed once: a streaming
+    read (torch sum) and a copy of 4 GiB, and square 8192 GEMMs in BF16 and
+    FP8 E4M3 through torch (hipBLASLt).  Context beside the datasheet peaks
+    the rooflines use, not a ceiling: the reduction here reads faster than
+    torch's sum."""
+    import torch
+    dev = "cuda:0"
+    out = {}
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e-3
+
+    x = torch.ones(1 << 30, dtype=torch.float32, device=dev)      # 4 GiB
+    y = torch.empty_like(x)
+    nb = x.numel() * 4
+    out["hbm_read_gbs"] = nb / timed(lambda: x.sum(), 5) / 1e9
+    out["hbm_copy_gbs"] = 2 * nb / timed(lambda: y.copy_(x), 5) / 1e9
+    del x, y
+    m = 8192
+    g = torch.Generator(device=dev).manual_seed(0)
+    a = torch.randn(m, m, device=dev, generator=g).to(torch.bfloat16)
+    b = torch.randn(m, m, device=dev, generator=g).to(torch.bfloat16)
+    out["bf16_gemm_tflops"] = 2 * m ** 3 / timed(lambda: torch.mm(a, b), 10) / 1e12
+    try:
+        f8 = torch.float8_e4m3fn
+        a8 = a.to(f8)
+        b8 = b.to(f8)                   # rows of b8 are the columns of the product
+        one = torch.ones((), device=dev)
+        out["fp8_gemm_tflops"] = 2 * m ** 3 / timed(
+            lambda: torch._scaled_mm(a8, b8.t(), scale_a=one, scale_b=one,
+                                     out_dtype=torch.bfloat16), 10) / 1e12
+    except (RuntimeError, AttributeError, TypeError) as e:
+        out["fp8_gemm_tflops"] = None
+        out["fp8_note"] = str(e)[:120]
+    del a, b
+    torch.cuda.empty_cache()
+    out["what"] = ("torch sum / copy of 4 GiB FP32; 8192^3 torch.mm (BF16) and _scaled_mm "
+                   "(FP8 E4M3) through hipBLASLt")
+    return out
+
+
+def cpu_baseline(X_host_rows, C_host, n_full, seconds_target=10.0, gpu_labels=None):
     """Times the FP64 oracle (assignment + update of one Lloyd iteration) on a
-    bounded row sample and scales to the full n."""
+    bounded row sample and scales to the full n.  With gpu_labels (the path's
+    labels of the same rows against the same centers), also counts the rows
+    whose label differs from the oracle's outside its 1e-6 relative top-2
+    margin."""
     import numpy as np
     from oracle import kmeans as ok
 
@@ -82,14 +152,20 @@ def cpu_baseline(X_host_rows, C_host, n_full, seconds_target=10.0):
     m = int(min(len(rows), max(100, 100 * seconds_target / max(t_probe, 1e-6))))
     sample = rows[:m]
     t0 = time.perf_counter()
-    lab, _, _ = ok.assign(sample, C_host)
+    lab, d1, d2 = ok.assign(sample, C_host)
     ok.update(sample, None, lab, C_host)
     t = time.perf_counter() - t0
     sec_per_iter = t * n_full / m
-    return {"value": 1.0 / sec_per_iter, "unit": "iter/s", "cores": 1, "kind": "oracle",
-            "sample": f"one Lloyd iteration (FP64 assign + update) on {m} of {n_full} rows, "
-                      f"all {C_host.shape[0]} centers; {t:.1f} s measured, scaled by n",
-            "sec_per_iter": sec_per_iter}
+    res = {"value": 1.0 / sec_per_iter, "unit": "iter/s", "cores": 1, "kind": "oracle",
+           "sample": f"one Lloyd iteration (FP64 assign + update) on {m} of {n_full} rows, "
+                     f"all {C_host.shape[0]} centers; {t:.1f} s measured, scaled by n",
+           "sec_per_iter": sec_per_iter, "host": host_cpu()}
+    if gpu_labels is not None:
+        g = np.asarray(gpu_labels[:m])
+        bad = (g != lab) & ~((d2 - d1) < 1e-6 * d2)
+        res["label_check"] = {"rows": m, "differ_outside_margin": int(bad.sum()),
+                              "inside_margin": int(((d2 - d1) < 1e-6 * d2).sum())}
+    return res
 
 
 def batched_main(args):
@@ -307,6 +383,8 @@ def main():
                     help="iterations of the plain FP32 comparison (default: --steps)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-library-reference", action="store_true",
+                    help="skip timing torch's read / copy / GEMMs for context")
     ap.add_argument("--only", choices=["assign"], default=None,
                     help="profiling mode: only the assignment on the workload's data (centers = "
                          "first k rows + noise), plus a plain 1 GiB device copy whose counters "
@@ -571,11 +649,17 @@ def main():
             out["equal_cost_rel_diff"] = rel
             out["equal_cost"] = bool(rel <= 1e-6)
 
+    # ---- plain library work on the same part, for context ----
+    if not args.no_library_reference:
+        out["library_reference"] = library_reference()
+        log(f"[bench] library reference {out['library_reference']}")
+
     # ---- CPU oracle baseline on a bounded sample ----
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         rows = X[:20000].cpu().numpy()
-        out["cpu_baseline"] = cpu_baseline(rows, Cr.cpu().numpy(), n)
+        out["cpu_baseline"] = cpu_baseline(rows, Cr.cpu().numpy(), n,
+                                           gpu_labels=lab_r[:20000].cpu().numpy())
 
     print(json.dumps(out), flush=True)
 

@@ -702,16 +702,16 @@ int assign_dpad(int prec, int d) {
   return u * ((prec == KMX_BF16) ? 32 : (prec == KMX_FP8E4M3) ? 128 : 16);
 }
 
-// FP8 rows of 4 units (d <= 512) with many centers: LDS tiles of 64 centers
-// taken as two sub-tiles of 32 (one tile barrier per 64 centers); with few
+// FP8 rows of 4 units (d <= 512) with many centers: LDS tiles of 64 or 128
+// centers taken as sub-tiles of 32 (one tile barrier per tile); with few
 // centers, tiles of 32 (less padding).
-static bool f8_wide_tiles(int k) { return k > 256; }
+static int f8_tile4(int k) { return k > 512 ? 128 : (k > 256 ? 64 : 32); }
 
 // Centers per LDS tile: each of the two tile buffers stays within ~72 KB.
 int assign_tile_n(int prec, int d, int k) {
   const int nku = units_for(prec, d);
   if (prec == KMX_FP8E4M3)
-    return nku <= 3 ? 64 : (nku == 4 ? (f8_wide_tiles(k) ? 64 : 32) : (nku <= 6 ? 32 : 16));
+    return nku <= 3 ? 64 : (nku == 4 ? f8_tile4(k) : (nku <= 6 ? 32 : 16));
   if (prec == KMX_BF16) return (nku <= 3 || nku == 6 || nku == 8) ? 64 : 32;
   if (nku <= 4) return 64;
   if (nku <= 32) return 32;
@@ -810,7 +810,8 @@ hipError_t launch_assign(hipStream_t s, int prec, const float* X, int64_t ldx, c
       case 2: KMX_A(2, 4, 64, 8, false, 1);
       case 3: KMX_A(3, 2, 64, 8, false, 1);
       case 4:
-        if (f8_wide_tiles(k)) KMX_A(4, 4, 64, 8, false, 2);
+        if (f8_tile4(k) == 128) KMX_A(4, 4, 128, 8, false, 4);
+        if (f8_tile4(k) == 64) KMX_A(4, 4, 64, 8, false, 2);
         KMX_A(4, 4, 32, 8, false, 1);
       case 6: KMX_A(6, 1, 32, 8, true, 1);
       case 8: KMX_A(8, 1, 16, 8, true, 1);

@@ -62,6 +62,8 @@ ASSIGN_CASES = [
     (3001, 37, 67),
     (2500, 130, 129),
     (777, 512, 33),
+    (1500, 500, 300),
+    (2000, 512, 700),
     (513, 1000, 50),
     (200, 3, 1),
     (64, 16, 2),

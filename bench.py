@@ -534,8 +534,12 @@ def main():
     (C8, lab_8, hist_8, _), w8, kt8 = run_timed(
         "full fp8", lambda: ctx.lloyd(X, Cw, args.steps, prec="fp8", labels=True))
     fp8_stats = ctx.assign_stats()
+    (Cr8, lab_r8, hist_r8, _, rows_r8), wr8, ktr8 = run_timed(
+        "routed fp8", lambda: ctx.lloyd_routed(X, Cw, args.steps, router=router, prec="fp8",
+                                               labels=True))
     same = bool(torch.equal(lab_r, lab_b) and torch.equal(Cr, Cb) and torch.equal(lab_p, lab_b)
-                and torch.equal(lab_8, lab_b) and torch.equal(C8, Cb))
+                and torch.equal(lab_8, lab_b) and torch.equal(C8, Cb)
+                and torch.equal(lab_r8, lab_b) and torch.equal(Cr8, Cb))
 
     # ---- rooflines ----
     def avg(kk, cls):
@@ -574,6 +578,11 @@ def main():
                       "final_cost": hist_b[-1], "kernel_ms_per_step": per_step(ktb),
                       "assign": "bf16 MFMA GEMM with fused top-4, FP32 GEMM pass and exact "
                                 "re-check of undecided rows"},
+        "routed_fp8": {"iter_per_s": args.steps / wr8, "ms_per_step": wr8 * 1e3 / args.steps,
+                       "final_cost": hist_r8[-1], "kernel_ms_per_step": per_step(ktr8),
+                       "gemm_rows_per_assignment": rows_r8,
+                       "assign": "router proposals + certificate, fp8 e4m3 MFMA GEMM cascade "
+                                 "for the other rows"},
         "full_fp8": {"iter_per_s": args.steps / w8, "ms_per_step": w8 * 1e3 / args.steps,
                      "final_cost": hist_8[-1], "kernel_ms_per_step": per_step(kt8),
                      "final_listed_via_fp32_all": list(fp8_stats),
@@ -598,14 +607,14 @@ def main():
         "metric": METRIC, "value": value, "unit": "iter/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "fp8e4m3" if best == "full_fp8" else "bf16", "data": "synthetic",
+        "dtype": "fp8e4m3" if best in ("full_fp8", "routed_fp8") else "bf16", "data": "synthetic",
         "config": {"workload": wl["name"], "n": n, "d": d, "k": k, "path": best,
                    "assign": paths[best]["assign"], "reduce": "fp64",
                    "timed": f"Lloyd iterations {args.warmup + 1}..{args.warmup + args.steps} "
                             f"from the centers after {args.warmup} plain FP32 iterations",
                    "value_is": "the fastest of the exact paths below (identical labels and "
                                "centers)"},
-        "roofline": fp8_roof if best == "full_fp8" else bf16_roof,
+        "roofline": fp8_roof if best in ("full_fp8", "routed_fp8") else bf16_roof,
         "bf16_gemm_roofline": bf16_roof,
         "fp8_gemm_roofline": fp8_roof,
         "seed_roofline": {"bound": "hbm", "achieved": seed_gbs, "peak": HBM_PEAK_GBS,

@@ -150,7 +150,7 @@ def _plain_and_routed(ctx, X, C0, iters, router, prec="bf16"):
 
 
 @pytest.mark.parametrize("mode", ["previous", "untrained", "trained"])
-@pytest.mark.parametrize("prec", ["bf16", "fp32"])
+@pytest.mark.parametrize("prec", ["bf16", "fp32", "fp8"])
 def test_lloyd_routed_identical_to_plain(ctx, mode, prec):
     n, d, k, iters = 20000, 64, 50, 6
     say(f"lloyd routed mode={mode} prec={prec}")

@@ -150,6 +150,19 @@ kmx_status kmx_lloyd(kmx_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t
                      double tol, kmx_prec prec, int32_t* label_out,
                      double* cost_hist, int32_t* iters_done);
 
+/* kmx_lloyd with the iteration launched as a graph (Sec. 1, as kmx_lloyd):
+ * one iteration's launches are captured once on the context's capture
+ * stream, which waits for the context stream first, and replayed max_iter
+ * times; the stop rule is evaluated on the device, so iterations after the
+ * stop do nothing, as in kmx_lloyd.  Same arguments, results (bitwise) and
+ * errors as kmx_lloyd, plus KMX_EDEVICE when capture or replay fails.  For
+ * small problems, where launch overhead dominates.  Synchronizes once at
+ * the end. */
+kmx_status kmx_lloyd_graph(kmx_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
+                           const float* w, float* C_inout, int32_t k, int32_t max_iter,
+                           double tol, kmx_prec prec, int32_t* label_out,
+                           double* cost_hist, int32_t* iters_done);
+
 /* Projection onto a subspace (Sec. 3, dimension reduction of each piece: a
  * row's coordinates in the span of the top right singular vectors, which
  * keeps squared distances within that span):

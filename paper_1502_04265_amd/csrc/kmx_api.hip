@@ -482,9 +482,14 @@ kmx_status kmx_cost(kmx_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t 
   return KMX_OK;
 }
 
-kmx_status kmx_lloyd(kmx_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
-                     const float* w, float* C_inout, int32_t k, int32_t max_iter, double tol,
-                     kmx_prec prec, int32_t* label_out, double* cost_hist, int32_t* iters_done) {
+// The Lloyd loop; with graph != 0 one iteration is captured as a HIP graph on
+// the context's capture stream and replayed max_iter times (the iterations
+// are gated on the device by the stop flag, so the host never waits inside
+// the loop either way).
+static kmx_status lloyd_impl(kmx_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
+                             const float* w, float* C_inout, int32_t k, int32_t max_iter,
+                             double tol, kmx_prec prec, int32_t* label_out, double* cost_hist,
+                             int32_t* iters_done, int graph) {
   if (!ctx) return KMX_EINVAL;
   ctx->err.clear();
   KMX_TRY(check_problem(ctx, X, n, d, ldx, k));
@@ -503,10 +508,55 @@ kmx_status kmx_lloyd(kmx_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t
   double* hist = P<double>(ctx->hist);
   LoopState* st = ST(ctx);
   KMX_HIP(ctx, launch_fill_i32(ctx->stream, prev, n, -1));
-  for (int t = 0; t < max_iter; ++t) {
-    KMX_TRY(run_assign(ctx, X, n, d, ldx, C_inout, k, prec, lab, nullptr, nullptr, &st->done));
-    KMX_TRY(run_update(ctx, X, n, d, ldx, w, lab, k, C_inout, C_inout, nullptr, 1, prev, hist, 0,
-                       &st->done));
+  if (graph && max_iter > 0) {
+    // every buffer an iteration touches exists before the capture starts
+    KMX_TRY(run_prep_centers(ctx, C_inout, k, d, prec));
+    if (!ctx->cap_stream)
+      KMX_HIP(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+    hipStream_t cs = ctx->cap_stream;
+    hipEvent_t ev = nullptr;
+    KMX_HIP(ctx, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    KMX_HIP(ctx, hipEventRecord(ev, ctx->stream));
+    KMX_HIP(ctx, hipStreamWaitEvent(cs, ev, 0));
+    // the iteration's launches go to the capture stream; no event timing inside
+    const hipStream_t saved = ctx->stream;
+    const int saved_timing = ctx->timing;
+    ctx->stream = cs;
+    ctx->timing = 0;
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    kmx_status ks = KMX_OK;
+    hipError_t he = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (he == hipSuccess) {
+      ks = run_assign(ctx, X, n, d, ldx, C_inout, k, prec, lab, nullptr, nullptr, &st->done);
+      if (ks == KMX_OK)
+        ks = run_update(ctx, X, n, d, ldx, w, lab, k, C_inout, C_inout, nullptr, 1, prev, hist,
+                        0, &st->done);
+      he = hipStreamEndCapture(cs, &g);
+    }
+    ctx->stream = saved;
+    ctx->timing = saved_timing;
+    if (he == hipSuccess && ks == KMX_OK) he = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    for (int t = 0; he == hipSuccess && ks == KMX_OK && t < max_iter; ++t)
+      he = hipGraphLaunch(ge, cs);
+    if (he == hipSuccess && ks == KMX_OK) he = hipEventRecord(ev, cs);
+    if (he == hipSuccess && ks == KMX_OK) he = hipStreamWaitEvent(ctx->stream, ev, 0);
+    if (he == hipSuccess && ks == KMX_OK) he = hipStreamSynchronize(cs);
+    if (ge) (void)hipGraphExecDestroy(ge);
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipEventDestroy(ev);
+    if (ks != KMX_OK) return ks;
+    if (he != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(ctx, KMX_EDEVICE,
+                  std::string("graph of the Lloyd iteration: ") + hipGetErrorString(he));
+    }
+  } else {
+    for (int t = 0; t < max_iter; ++t) {
+      KMX_TRY(run_assign(ctx, X, n, d, ldx, C_inout, k, prec, lab, nullptr, nullptr, &st->done));
+      KMX_TRY(run_update(ctx, X, n, d, ldx, w, lab, k, C_inout, C_inout, nullptr, 1, prev, hist,
+                         0, &st->done));
+    }
   }
   // final assignment: labels and cost of the returned centers
   KMX_TRY(run_assign(ctx, X, n, d, ldx, C_inout, k, prec, lab, nullptr, nullptr, nullptr));
@@ -520,6 +570,21 @@ kmx_status kmx_lloyd(kmx_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t
                          hipMemcpyDeviceToHost));
   *iters_done = it;
   return KMX_OK;
+}
+
+kmx_status kmx_lloyd(kmx_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
+                     const float* w, float* C_inout, int32_t k, int32_t max_iter, double tol,
+                     kmx_prec prec, int32_t* label_out, double* cost_hist, int32_t* iters_done) {
+  return lloyd_impl(ctx, X, n, d, ldx, w, C_inout, k, max_iter, tol, prec, label_out, cost_hist,
+                    iters_done, 0);
+}
+
+kmx_status kmx_lloyd_graph(kmx_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
+                           const float* w, float* C_inout, int32_t k, int32_t max_iter,
+                           double tol, kmx_prec prec, int32_t* label_out, double* cost_hist,
+                           int32_t* iters_done) {
+  return lloyd_impl(ctx, X, n, d, ldx, w, C_inout, k, max_iter, tol, prec, label_out, cost_hist,
+                    iters_done, 1);
 }
 
 kmx_status kmx_project(kmx_ctx* ctx, const float* X, int64_t rows, int32_t d_in, int64_t ldx,

@@ -179,7 +179,7 @@ struct kmx_ctx {
   kmx::Buf vt;                          // transposed projection basis
   kmx::Buf bX, bXq, brs, bw, bC, bCq, bhd, bch, bcs, blab, bitems, binsts, bbuckets, bcinst, bxstats;
   kmx::Buf btermC, btermMu, bW, bcost;
-  hipStream_t cap_stream = nullptr;                // stream the batched iteration is captured on
+  hipStream_t cap_stream = nullptr;                // stream graphs are captured on (batched, graphed Lloyd)
   std::map<std::pair<int, int>, int> tune;         // (d, k class) -> tile-shape variant
 
   // timing

@@ -64,6 +64,8 @@ def lib():
         "kmx_cost": [_vp, _vp, _i64, _i32, _i64, _vp, _vp, _i32, ctypes.c_int, _vp],
         "kmx_lloyd": [_vp, _vp, _i64, _i32, _i64, _vp, _vp, _i32, _i32, ctypes.c_double,
                       ctypes.c_int, _vp, _vp, _vp],
+        "kmx_lloyd_graph": [_vp, _vp, _i64, _i32, _i64, _vp, _vp, _i32, _i32, ctypes.c_double,
+                            ctypes.c_int, _vp, _vp, _vp],
         "kmx_timing": [_vp, ctypes.c_int, ctypes.c_int],
         "kmx_assign_stats": [_vp, _vp, _vp, _vp],
         "kmx_seed_stats": [_vp, _vp],
@@ -200,7 +202,9 @@ class Context:
         return float(out.value)
 
     def lloyd(self, X, C0, max_iter: int, w=None, tol: float = -1.0, prec="bf16",
-              labels: bool = True, inplace: bool = False):
+              labels: bool = True, inplace: bool = False, graph: bool = False):
+        """kmx_lloyd, or kmx_lloyd_graph with graph=True (one captured
+        iteration replayed); returns (C, labels, cost_hist, iters)."""
         n, d, ldx = _rows(X)
         k = _centers(C0, d)
         _vec(w, n)
@@ -209,9 +213,9 @@ class Context:
         hist = (ctypes.c_double * (max_iter + 1))()
         iters = ctypes.c_int32(0)
         self._sync_stream()
-        _check(lib().kmx_lloyd(self._p, _ptr(X), n, d, ldx, _ptr(w), _ptr(C), k, max_iter,
-                               float(tol), _PREC[prec], _ptr(lab), hist, ctypes.byref(iters)),
-               self._p)
+        fn = lib().kmx_lloyd_graph if graph else lib().kmx_lloyd
+        _check(fn(self._p, _ptr(X), n, d, ldx, _ptr(w), _ptr(C), k, max_iter, float(tol),
+                  _PREC[prec], _ptr(lab), hist, ctypes.byref(iters)), self._p)
         it = int(iters.value)
         return C, lab, [hist[i] for i in range(it + 1)], it
 

@@ -341,3 +341,33 @@ def test_assign_full_size_router_workload_sampled(ctx):
             assert nf < n // 2
     del Xg
     torch.cuda.empty_cache()
+
+
+# ---------------------------------------------------------------------------
+# Lloyd with the iteration launched as a graph (kmx_lloyd_graph)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
+@pytest.mark.parametrize("n,d,k,tol", [(10000, 64, 10, -1.0), (10000, 64, 10, 1e-4),
+                                       (3000, 512, 300, -1.0)])
+def test_lloyd_graph_identical_to_eager(ctx, prec, n, d, k, tol):
+    # The captured iteration is replayed max_iter times; every replay's cost is
+    # recorded, so the whole history is compared with the eager loop.  Two
+    # graph calls in a row (the second shorter), with eager work between.
+    say(f"lloyd graph {prec} n={n} d={d} k={k} tol={tol}")
+    X, _ = synth.isotropic_mixture(n, d, k, seed=21)
+    Xd = _dev(X)
+    C0, _ = ctx.seed(Xd, k, rng_seed=3)
+    for iters in (12, 5):
+        Ce, le, he, ie = ctx.lloyd(Xd, C0, iters, tol=tol, prec=prec)
+        torch.cuda.synchronize()
+        Cg, lg, hg, ig = ctx.lloyd(Xd, C0, iters, tol=tol, prec=prec, graph=True)
+        assert ig == ie, (ig, ie)
+        assert hg == he
+        assert torch.equal(lg, le)
+        assert torch.equal(Cg, Ce)
+        if tol >= 0 and iters == 12:
+            assert ie < iters, "the stop rule should end this run early"
+    # and against the oracle on the last run
+    ref = ok.lloyd(X, None, C0.cpu().numpy(), 5, tol=tol)
+    assert ig == ref["iters"]
+    np.testing.assert_allclose(hg, ref["cost"], rtol=1e-6)

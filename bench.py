@@ -537,9 +537,21 @@ def main():
     (Cr8, lab_r8, hist_r8, _, rows_r8), wr8, ktr8 = run_timed(
         "routed fp8", lambda: ctx.lloyd_routed(X, Cw, args.steps, router=router, prec="fp8",
                                                labels=True))
+    # the same full paths with the iteration replayed as a graph (kmx_lloyd_graph);
+    # one untimed call each first (the first capture on a context pays one-off costs)
+    for prec in ("bf16", "fp8"):
+        ctx.lloyd(X, Cw, 1, prec=prec, labels=False, graph=True)
+    (Cgb, lab_gb, hist_gb, _), wgb, _ = run_timed(
+        "full bf16 graph", lambda: ctx.lloyd(X, Cw, args.steps, prec="bf16", labels=True,
+                                             graph=True))
+    (Cg8, lab_g8, hist_g8, _), wg8, _ = run_timed(
+        "full fp8 graph", lambda: ctx.lloyd(X, Cw, args.steps, prec="fp8", labels=True,
+                                            graph=True))
     same = bool(torch.equal(lab_r, lab_b) and torch.equal(Cr, Cb) and torch.equal(lab_p, lab_b)
                 and torch.equal(lab_8, lab_b) and torch.equal(C8, Cb)
-                and torch.equal(lab_r8, lab_b) and torch.equal(Cr8, Cb))
+                and torch.equal(lab_r8, lab_b) and torch.equal(Cr8, Cb)
+                and torch.equal(lab_gb, lab_b) and torch.equal(Cgb, Cb)
+                and torch.equal(lab_g8, lab_b) and torch.equal(Cg8, Cb))
 
     # ---- rooflines ----
     def avg(kk, cls):
@@ -583,6 +595,12 @@ def main():
                        "gemm_rows_per_assignment": rows_r8,
                        "assign": "router proposals + certificate, fp8 e4m3 MFMA GEMM cascade "
                                  "for the other rows"},
+        "full_bf16_graph": {"iter_per_s": args.steps / wgb, "ms_per_step": wgb * 1e3 / args.steps,
+                            "final_cost": hist_gb[-1],
+                            "assign": "as full_bf16, the iteration replayed as a HIP graph"},
+        "full_fp8_graph": {"iter_per_s": args.steps / wg8, "ms_per_step": wg8 * 1e3 / args.steps,
+                           "final_cost": hist_g8[-1],
+                           "assign": "as full_fp8, the iteration replayed as a HIP graph"},
         "full_fp8": {"iter_per_s": args.steps / w8, "ms_per_step": w8 * 1e3 / args.steps,
                      "final_cost": hist_8[-1], "kernel_ms_per_step": per_step(kt8),
                      "final_listed_via_fp32_all": list(fp8_stats),
@@ -607,14 +625,14 @@ def main():
         "metric": METRIC, "value": value, "unit": "iter/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "fp8e4m3" if best in ("full_fp8", "routed_fp8") else "bf16", "data": "synthetic",
+        "dtype": "fp8e4m3" if best in ("full_fp8", "routed_fp8", "full_fp8_graph") else "bf16", "data": "synthetic",
         "config": {"workload": wl["name"], "n": n, "d": d, "k": k, "path": best,
                    "assign": paths[best]["assign"], "reduce": "fp64",
                    "timed": f"Lloyd iterations {args.warmup + 1}..{args.warmup + args.steps} "
                             f"from the centers after {args.warmup} plain FP32 iterations",
                    "value_is": "the fastest of the exact paths below (identical labels and "
                                "centers)"},
-        "roofline": fp8_roof if best in ("full_fp8", "routed_fp8") else bf16_roof,
+        "roofline": fp8_roof if best in ("full_fp8", "routed_fp8", "full_fp8_graph") else bf16_roof,
         "bf16_gemm_roofline": bf16_roof,
         "fp8_gemm_roofline": fp8_roof,
         "seed_roofline": {"bound": "hbm", "achieved": seed_gbs, "peak": HBM_PEAK_GBS,
@@ -652,6 +670,17 @@ def main():
         log(f"[bench] fp32: {wf * 1e3 / ks:.3f} ms/iter, cost {hist_f[-1]:.9e}")
         out["fp32_path"] = {"iter_per_s": ks / wf, "ms_per_step": wf * 1e3 / ks, "steps": ks,
                             "final_cost": hist_f[-1]}
+        if n <= 1_000_000:
+            # small problems are launch-bound: the same iterations replayed as a graph
+            ctx.lloyd(X, Cw, 1, prec="fp32", labels=False, graph=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            Cfg, _, hist_fg, _ = ctx.lloyd(X, Cw, ks, prec="fp32", labels=False, graph=True)
+            torch.cuda.synchronize()
+            wfg = time.perf_counter() - t0
+            log(f"[bench] fp32 graph: {wfg * 1e3 / ks:.3f} ms/iter, cost {hist_fg[-1]:.9e}")
+            out["fp32_path"]["graph_ms_per_step"] = wfg * 1e3 / ks
+            out["fp32_path"]["graph_identical"] = bool(torch.equal(Cfg, Cf) and hist_fg == hist_f)
         out["speedup_vs_fp32"] = value / (ks / wf)
         if ks == args.steps:
             rel = abs(hist_f[-1] - paths[best]["final_cost"]) / hist_f[-1]

@@ -192,10 +192,13 @@ def cost_at_centroids(W, S, Q) -> float:
 # ----------------------------------------------------------------------------
 def _inverse_cdf(mass: np.ndarray, u: float) -> int:
     """First index whose inclusive prefix of ``mass`` strictly exceeds u * total
-    (reading S5).  The prefix is accumulated sequentially in index order."""
+    (reading S5).  The prefix is accumulated sequentially in index order.
+    A draw from zero total mass is undefined and raises."""
     total = 0.0
     for v in mass:
         total += v
+    if not total > 0.0:
+        raise ValueError("inverse CDF of zero total mass")
     target = u * total
     run = 0.0
     last_positive = -1
@@ -217,10 +220,20 @@ def seed(X, w, k: int, rng_seed: int):
     D2_i is the squared distance of x_i to its closest chosen center; if that
     mass is zero, it draws by weight among the points not chosen yet (S4).
     The draws use u_r from SplitMix64 (S6) through the inverse CDF (S5).
+
+    A weight-w point stands for w copies (Sec. 2.3.1), so a zero-weight point
+    stands for none and k-means++ can only draw k centers from at least k
+    points of positive weight: k > #{w_i > 0}, or a negative or non-finite
+    weight, raises ValueError.
     """
     X = _f64(X)
     n = X.shape[0]
     w = _weights(w, n)
+    if not np.all(np.isfinite(w)) or np.any(w < 0):
+        raise ValueError("weights must be finite and >= 0")
+    if not 1 <= k <= int(np.count_nonzero(w > 0)):
+        raise ValueError(f"k = {k} needs 1 <= k <= #points of positive weight "
+                         f"({int(np.count_nonzero(w > 0))})")
     u = uniforms(rng_seed, k)
     chosen = np.zeros(n, dtype=bool)
     idx = np.empty(k, dtype=np.int64)

@@ -303,6 +303,28 @@ def test_kmeanspp_zero_weight_never_chosen():
         assert np.all(w[idx] > 0)
 
 
+def test_kmeanspp_all_positive_weights_used_then_raises():
+    # Sec. 2.3.1: a weight-w point stands for w copies, so zero-weight points
+    # stand for nothing.  With exactly k positive weights (duplicates, zero D2
+    # mass after a few rounds) every positive row is drawn; one more center
+    # has no point left to be drawn from and must be refused, not invented.
+    X = np.array([[1, 1], [1, 1], [4, 0], [1, 1], [9, 9]], dtype=np.float32)
+    w = np.array([1, 0, 2, 3, 0], dtype=np.float32)
+    for s in range(10):
+        _, idx, _ = ok.seed(X, w, 3, s)
+        assert sorted(idx.tolist()) == [0, 2, 3]
+    with pytest.raises(ValueError):
+        ok.seed(X, w, 4, 0)
+    with pytest.raises(ValueError):
+        ok.seed(X, np.zeros(5, np.float32), 1, 0)
+    with pytest.raises(ValueError):
+        ok.seed(X, np.array([1, -1, 1, 1, 1], np.float32), 2, 0)
+    with pytest.raises(ValueError):
+        ok.seed(X, np.array([1, np.nan, 1, 1, 1], np.float32), 2, 0)
+    with pytest.raises(ValueError):
+        ok.seed(X, None, 6, 0)
+
+
 def test_kmeanspp_sampling_law_chi_square():
     # P(i0, i1) = w_i0 / sum w * w_i1 D2(i1, i0) / sum_j w_j D2(j, i0)
     X = np.array([[0, 0], [1, 0], [0, 2], [3, 3], [-2, 1], [5, -1]], dtype=np.float32)

@@ -22,7 +22,14 @@
  *     the call synchronizes the context's stream; every other call is
  *     stream-ordered and asynchronous (results valid once the stream reaches
  *     that point).
- *   - w may be NULL (all weights 1).  Weights must be finite and >= 0.
+ *   - w may be NULL (all weights 1).  Weights must be finite and >= 0: the
+ *     calls that synchronize anyway (kmx_seed, kmx_cost, kmx_lloyd,
+ *     kmx_lloyd_graph, kmx_lloyd_routed, kmx_lloyd_batched) read w once
+ *     before any other work and return KMX_EINVAL otherwise; kmx_update, which
+ *     does not wait, checks w only under KMX_VALIDATE.
+ *   - KMX_VALIDATE=1 (read when the context is created): calls that take X
+ *     and centers also scan them for values that are not finite first (one
+ *     extra read of X; the call synchronizes), KMX_EINVAL if one is found.
  *   - Ties in the argmin go to the lowest center index.  An empty cluster
  *     keeps its previous center.
  *   - Return codes only; nothing throws or aborts across the ABI.  On failure
@@ -85,10 +92,12 @@ const char* kmx_last_error(const kmx_ctx* ctx);
  * rng_seed.
  *   C_out   device, k x d float32: exact copies of the chosen rows.
  *   idx_out device, k int64, nullable: the chosen row indices.
- * Requires 1 <= k <= n.  Rows with w_i = 0 are never chosen while rows with
- * positive weight remain.  A round skips the rows whose D2 provably cannot
- * drop (the new center is at least twice as far from the row's closest
- * chosen center as the row is), so D2 is the same as with every row read. */
+ * Requires 1 <= k <= #{i : w_i > 0} (= n when w is NULL; a weight-w point
+ * stands for w copies, Sec. 2.3.1, so a zero-weight row stands for none and
+ * is never chosen): KMX_EINVAL otherwise.  A round skips the rows whose D2
+ * provably cannot drop (the new center is at least twice as far from the
+ * row's closest chosen center as the row is), so D2 is the same as with every
+ * row read. */
 kmx_status kmx_seed(kmx_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
                     const float* w, int32_t k, uint64_t rng_seed,
                     float* C_out, int64_t* idx_out);
@@ -163,7 +172,8 @@ kmx_status kmx_lloyd_graph(kmx_ctx* ctx, const float* X, int64_t n, int32_t d, i
                            double tol, kmx_prec prec, int32_t* label_out,
                            double* cost_hist, int32_t* iters_done);
 
-/* Projection onto a subspace (Sec. 3, dimension reduction of each piece: a
+/* Projection onto a subspace (Sec. 2.2, "Using SVD to project to the best
+ * fit subspace": dimension reduction of each piece, a
  * row's coordinates in the span of the top right singular vectors, which
  * keeps squared distances within that span):
  *     Y[r][j] = sum_i X[r][i] V[i][j],  r < rows, j < d_out,

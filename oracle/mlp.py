@@ -69,6 +69,33 @@ def adam_step(params, grads, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8)
     return out_p, out_m, out_v
 
 
+def propose(Z, per_quarter: int = 4):
+    """Candidate proposals from logits Z (rows x k): for each quarter q of the
+    centers (center j belongs to quarter (j mod 16) div 4), its per_quarter
+    highest logits in decreasing order, ties to the lower index; -1 where a
+    quarter has fewer centers.  Returns an int array rows x (4 per_quarter),
+    quarter q in columns [q per_quarter, (q + 1) per_quarter).  Written as a
+    plain repeated selection of the largest remaining logit of each quarter.
+    """
+    Z = np.asarray(Z, np.float64)
+    rows, k = Z.shape
+    out = np.full((rows, 4 * per_quarter), -1, dtype=np.int64)
+    for r in range(rows):
+        for q in range(4):
+            members = [j for j in range(k) if (j % 16) // 4 == q]
+            taken = []
+            for slot in range(min(per_quarter, len(members))):
+                best = -1
+                for j in members:
+                    if j in taken:
+                        continue
+                    if best < 0 or Z[r, j] > Z[r, best]:
+                        best = j            # strict '>' keeps the lower index on ties
+                taken.append(best)
+                out[r, q * per_quarter + slot] = best
+    return out
+
+
 def predict(X, W1, b1, W2, b2):
     """Highest-logit class (lowest index on ties)."""
     _, _, Z = forward(X, W1, b1, W2, b2)

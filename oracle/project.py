@@ -1,7 +1,8 @@
 """FP64 reference of the dimension reduction of the streamed pipeline (test
 infrastructure only).
 
-Sec. 3 replaces each piece by its best-fit low-dimensional approximation:
+Sec. 2.2 ("Using SVD to project to the best fit subspace") replaces each
+piece by its best-fit low-dimensional approximation:
 with A = U D V^T, keeping the top m singular values gives A_m, whose rows lie
 in the span of the top m right singular vectors V_m.  A row's coordinates in
 that span, y = x V_m, keep every squared distance between rows of A_m, so

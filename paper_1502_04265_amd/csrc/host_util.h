@@ -110,6 +110,10 @@ inline LoopState* ST(kmx_ctx* ctx) { return P<LoopState>(ctx->state); }
 kmx_status check_problem(kmx_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
                          int32_t k);
 kmx_status check_prec(kmx_ctx* ctx, int prec, int d);
+// Weights finite and >= 0 with at least min_pos positive; with KMX_VALIDATE
+// also X and C finite.  Synchronizes when it checks anything.
+kmx_status check_data(kmx_ctx* ctx, const float* X, int64_t n, int d, int64_t ldx, const float* w,
+                      int64_t min_pos, const float* C, int k);
 kmx_status ensure_prep(kmx_ctx* ctx, const float* X, int64_t n, int d, int64_t ldx, int prec);
 kmx_status ensure_common(kmx_ctx* ctx, int64_t n, int d, int k);
 kmx_status write_state(kmx_ctx* ctx, int max_iter, double tol);

@@ -402,6 +402,66 @@ hipError_t launch_fill_u8(hipStream_t s, uint8_t* p, int64_t n, uint8_t v) {
   return hipGetLastError();
 }
 
+// Argument checks that need the data (run before any work of a call):
+// out[0] += rows with w_i > 0, out[1] += entries that are not finite or are
+// negative (weights) / not finite (any other array).  One atomic per block.
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += (unsigned long long)__shfl_xor((long long)v, m, 64);
+  return v;
+}
+
+__global__ __launch_bounds__(256) void check_weights_kernel(const float* __restrict__ w, int64_t n,
+                                                            unsigned long long* out) {
+  unsigned long long pos = 0, bad = 0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const float v = w[i];
+    pos += (v > 0.0f) ? 1u : 0u;
+    bad += (!(v >= 0.0f) || !isfinite(v)) ? 1u : 0u;   // NaN, negative, +inf
+  }
+  pos = wave_sum_u64(pos);
+  bad = wave_sum_u64(bad);
+  if ((threadIdx.x & 63) == 0 && (pos | bad)) {
+    atomicAdd(&out[0], pos);
+    atomicAdd(&out[1], bad);
+  }
+}
+
+__global__ __launch_bounds__(256) void scan_finite_kernel(const float* __restrict__ A, int64_t rows,
+                                                          int cols, int64_t ld,
+                                                          unsigned long long* out) {
+  unsigned long long bad = 0;
+  const int64_t total = rows * (int64_t)cols;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+    const int64_t r = i / cols;
+    const float v = A[r * ld + (i - r * cols)];
+    bad += isfinite(v) ? 0u : 1u;
+  }
+  bad = wave_sum_u64(bad);
+  if ((threadIdx.x & 63) == 0 && bad) atomicAdd(&out[1], bad);
+}
+
+hipError_t launch_check_weights(hipStream_t s, const float* w, int64_t n, unsigned long long* out,
+                                int num_cus) {
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > (int64_t)num_cus * 8) blocks = (int64_t)num_cus * 8;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(check_weights_kernel, dim3((unsigned)blocks), dim3(256), 0, s, w, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan_finite(hipStream_t s, const float* A, int64_t rows, int cols, int64_t ld,
+                              unsigned long long* out, int num_cus) {
+  int64_t blocks = (rows * (int64_t)cols + 255) / 256;
+  if (blocks > (int64_t)num_cus * 8) blocks = (int64_t)num_cus * 8;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(scan_finite_kernel, dim3((unsigned)blocks), dim3(256), 0, s, A, rows, cols,
+                     ld, out);
+  return hipGetLastError();
+}
+
 // Clears the center maxima and the per-assignment counters; with reset_iter
 // also the loop state (done, iter, changed).
 __global__ void reset_small_kernel(CenterStats* cs, CenterStats* cs2, CenterStats* cs3,

@@ -1,5 +1,6 @@
 // Projection of a chunk of rows onto a low-dimensional subspace (the
-// dimension reduction of the streamed pipeline, Sec. 3: each row is replaced
+// dimension reduction of the streamed pipeline, Sec. 2.2 "Using SVD to project
+// to the best fit subspace": each row is replaced
 // by its coordinates in the span of the top right singular vectors V, so
 // that squared distances inside that span are preserved).
 //

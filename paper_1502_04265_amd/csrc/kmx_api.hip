@@ -2,6 +2,7 @@
 // per-dataset cache and the launch sequences of seed / assign / update / cost
 // / lloyd.  All device work is enqueued on the context's stream.
 #include <climits>
+#include <cstdlib>
 #include <cstdint>
 #include <cstring>
 #include <string>
@@ -37,6 +38,42 @@ kmx_status check_prec(kmx_ctx* ctx, int prec, int d) {
   if (d > dmax || d > 1024)
     return fail(ctx, KMX_EUNSUPPORTED,
                 "assignment supports d <= " + std::to_string(dmax) + ", got " + std::to_string(d));
+  return KMX_OK;
+}
+
+// Checks that need the data, before any work of the call is enqueued: the
+// weights (when given) must be finite and >= 0, and at least min_pos of them
+// positive; with KMX_VALIDATE=1 set when the context was created, X (n x d)
+// and C (k x d, when given) must be finite too.  Synchronizes the context's
+// stream when it launches anything; does nothing when w == NULL and the scan
+// is off.
+kmx_status check_data(kmx_ctx* ctx, const float* X, int64_t n, int d, int64_t ldx, const float* w,
+                      int64_t min_pos, const float* C, int k) {
+  const bool scan = ctx->validate;
+  if (!w && !scan) return KMX_OK;
+  KMX_TRY(grow(ctx, ctx->vcheck, 6 * sizeof(unsigned long long)));
+  unsigned long long* v = P<unsigned long long>(ctx->vcheck);
+  KMX_HIP(ctx, launch_fill_i32(ctx->stream, P<int32_t>(ctx->vcheck), 12, 0));
+  if (w) KMX_HIP(ctx, launch_check_weights(ctx->stream, w, n, v, ctx->num_cus));
+  if (scan) {
+    KMX_HIP(ctx, launch_scan_finite(ctx->stream, X, n, d, ldx, v + 2, ctx->num_cus));
+    if (C) KMX_HIP(ctx, launch_scan_finite(ctx->stream, C, k, d, d, v + 4, ctx->num_cus));
+  }
+  unsigned long long h[6];
+  KMX_HIP(ctx, hipMemcpyAsync(h, v, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+  KMX_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  if (w && h[1] != 0)
+    return fail(ctx, KMX_EINVAL, "w holds " + std::to_string(h[1]) +
+                                     " entries that are negative or not finite");
+  if (w && (int64_t)h[0] < min_pos)
+    return fail(ctx, KMX_EINVAL, "k = " + std::to_string(min_pos) + " exceeds the number of rows "
+                                 "with positive weight (" + std::to_string(h[0]) + ")");
+  if (scan && h[3] != 0)
+    return fail(ctx, KMX_EINVAL,
+                "X holds " + std::to_string(h[3]) + " entries that are not finite (KMX_VALIDATE)");
+  if (scan && C && h[5] != 0)
+    return fail(ctx, KMX_EINVAL, "the centers hold " + std::to_string(h[5]) +
+                                     " entries that are not finite (KMX_VALIDATE)");
   return KMX_OK;
 }
 
@@ -317,6 +354,8 @@ kmx_status kmx_create(kmx_ctx** out, int device, void* hip_stream) {
   c->device = device;
   c->stream = (hipStream_t)hip_stream;
   c->num_cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  const char* val = std::getenv("KMX_VALIDATE");
+  c->validate = val && val[0] && std::strcmp(val, "0") != 0;
   *out = c;
   return KMX_OK;
 }
@@ -331,7 +370,7 @@ kmx_status kmx_destroy(kmx_ctx* ctx) {
       &ctx->ch,        &ctx->cstats,   &ctx->lab_a,      &ctx->lab_prev,   &ctx->d1,
       &ctx->d2,        &ctx->flags,    &ctx->counters,   &ctx->counts,     &ctx->segsum,
       &ctx->base,      &ctx->chunk_base, &ctx->perm,     &ctx->partS,      &ctx->partQ,
-      &ctx->partW,     &ctx->W,        &ctx->termC,      &ctx->termMu,     &ctx->state,
+      &ctx->partW,     &ctx->W,        &ctx->termC,      &ctx->termMu,     &ctx->state,     &ctx->vcheck,
       &ctx->D2,        &ctx->chosen,   &ctx->seed_part,  &ctx->seed_ctr,   &ctx->scratch_c,
       &ctx->seed_a,    &ctx->seed_cc,  &ctx->seed_nread,
       &ctx->hist,      &ctx->fb_rows,  &ctx->keys,       &ctx->cdist,      &ctx->nbr,
@@ -378,6 +417,7 @@ kmx_status kmx_seed(kmx_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t 
   KMX_TRY(check_problem(ctx, X, n, d, ldx, k));
   if (!C_out) return fail(ctx, KMX_EINVAL, "C_out is NULL");
   KMX_TRY(set_device(ctx));
+  KMX_TRY(check_data(ctx, X, n, d, ldx, w, k, nullptr, 0));
   const int64_t nb = (n + kSeedRows - 1) / kSeedRows;
   KMX_TRY(grow(ctx, ctx->D2, (size_t)n * sizeof(double)));
   KMX_TRY(grow(ctx, ctx->chosen, (size_t)n));
@@ -425,6 +465,7 @@ kmx_status kmx_assign(kmx_ctx* ctx, const float* X, int64_t n, int32_t d, int64_
   if (!C) return fail(ctx, KMX_EINVAL, "C is NULL");
   if (!label_out) return fail(ctx, KMX_EINVAL, "label_out is NULL");
   KMX_TRY(set_device(ctx));
+  KMX_TRY(check_data(ctx, X, n, d, ldx, nullptr, 0, C, k));
   KMX_TRY(ensure_common(ctx, n, d, k));
   KMX_TRY(ensure_prep(ctx, X, n, d, ldx, prec));
   KMX_TRY(run_assign(ctx, X, n, d, ldx, C, k, prec, label_out, d1_out, d2_out, nullptr));
@@ -449,6 +490,7 @@ kmx_status kmx_update(kmx_ctx* ctx, const float* X, int64_t n, int32_t d, int64_
   if (k > kMaxK) return fail(ctx, KMX_EUNSUPPORTED, "k too large");
   if (!label || !C_prev || !C_out) return fail(ctx, KMX_EINVAL, "NULL label or centers");
   KMX_TRY(set_device(ctx));
+  if (ctx->validate) KMX_TRY(check_data(ctx, X, n, d, ldx, w, 0, C_prev, k));
   KMX_TRY(ensure_common(ctx, n, d, k));
   KMX_TRY(run_update(ctx, X, n, d, ldx, w, label, k, C_prev, C_out, W_out, 1, nullptr, nullptr, 2,
                      nullptr));
@@ -469,6 +511,7 @@ kmx_status kmx_cost(kmx_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t 
   KMX_TRY(check_prec(ctx, prec, d));
   if (!C || !cost_out) return fail(ctx, KMX_EINVAL, "NULL C or cost_out");
   KMX_TRY(set_device(ctx));
+  KMX_TRY(check_data(ctx, X, n, d, ldx, w, 0, C, k));
   KMX_TRY(ensure_common(ctx, n, d, k));
   KMX_TRY(ensure_prep(ctx, X, n, d, ldx, prec));
   int32_t* lab = P<int32_t>(ctx->lab_a);
@@ -498,6 +541,7 @@ static kmx_status lloyd_impl(kmx_ctx* ctx, const float* X, int64_t n, int32_t d,
     return fail(ctx, KMX_EINVAL, "NULL C_inout, cost_hist or iters_done");
   if (max_iter < 0) return fail(ctx, KMX_EINVAL, "max_iter must be >= 0");
   KMX_TRY(set_device(ctx));
+  KMX_TRY(check_data(ctx, X, n, d, ldx, w, 0, C_inout, k));
   KMX_TRY(ensure_common(ctx, n, d, k));
   KMX_TRY(ensure_prep(ctx, X, n, d, ldx, prec));
   KMX_TRY(grow(ctx, ctx->lab_prev, (size_t)n * sizeof(int32_t)));

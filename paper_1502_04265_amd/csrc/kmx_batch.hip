@@ -60,6 +60,40 @@ kmx_status check_problems(kmx_ctx* ctx, const kmx_problem* probs, int count) {
   return KMX_OK;
 }
 
+// Data checks of every problem (weights finite and >= 0; with KMX_VALIDATE,
+// X and C finite): all launched, then one synchronization.
+kmx_status check_problem_data(kmx_ctx* ctx, const kmx_problem* probs, int count) {
+  bool any = ctx->validate;
+  for (int i = 0; i < count && !any; ++i) any = probs[i].w != nullptr;
+  if (!any) return KMX_OK;
+  KMX_TRY(grow(ctx, ctx->vcheck, (size_t)count * 6 * sizeof(unsigned long long)));
+  unsigned long long* v = P<unsigned long long>(ctx->vcheck);
+  KMX_HIP(ctx, launch_fill_i32(ctx->stream, P<int32_t>(ctx->vcheck), (int64_t)count * 12, 0));
+  for (int i = 0; i < count; ++i) {
+    const kmx_problem& q = probs[i];
+    if (q.w) KMX_HIP(ctx, launch_check_weights(ctx->stream, q.w, q.n, v + 6 * i, ctx->num_cus));
+    if (ctx->validate) {
+      KMX_HIP(ctx, launch_scan_finite(ctx->stream, q.X, q.n, q.d, q.ldx, v + 6 * i + 2,
+                                      ctx->num_cus));
+      KMX_HIP(ctx, launch_scan_finite(ctx->stream, q.C, q.k, q.d, q.d, v + 6 * i + 4,
+                                      ctx->num_cus));
+    }
+  }
+  std::vector<unsigned long long> h((size_t)count * 6);
+  KMX_HIP(ctx, hipMemcpyAsync(h.data(), v, h.size() * sizeof(unsigned long long),
+                              hipMemcpyDeviceToHost, ctx->stream));
+  KMX_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  for (int i = 0; i < count; ++i) {
+    const std::string at = " (problem " + std::to_string(i) + ")";
+    if (h[6 * i + 1] != 0)
+      return fail(ctx, KMX_EINVAL, "w holds " + std::to_string(h[6 * i + 1]) +
+                                       " entries that are negative or not finite" + at);
+    if (h[6 * i + 3] != 0 || h[6 * i + 5] != 0)
+      return fail(ctx, KMX_EINVAL, "X or C holds entries that are not finite (KMX_VALIDATE)" + at);
+  }
+  return KMX_OK;
+}
+
 int variant_for(const kmx_ctx* ctx, int d, int k) {
   auto it = ctx->tune.find({d, kclass_of(k)});
   return it == ctx->tune.end() ? 0 : it->second;
@@ -340,6 +374,7 @@ kmx_status kmx_lloyd_batched(kmx_ctx* ctx, const kmx_problem* probs, int32_t cou
   if (iters < 0) return fail(ctx, KMX_EINVAL, "iters must be >= 0");
   if (!cost_hist) return fail(ctx, KMX_EINVAL, "cost_hist is NULL");
   KMX_TRY(set_device(ctx));
+  KMX_TRY(check_problem_data(ctx, probs, count));
   Plan pl;
   build_plan(ctx, probs, count, {}, -1, pl);
   const int stride = iters + 1;

@@ -149,6 +149,7 @@ struct kmx_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   int num_cus = 256;
+  bool validate = false;   // KMX_VALIDATE=1: scan X and C for non-finite values
   std::string err;
 
   // cached per-dataset data
@@ -172,6 +173,7 @@ struct kmx_ctx {
   kmx::Buf partS, partQ, partW;
   kmx::Buf W, termC, termMu;
   kmx::Buf state;
+  kmx::Buf vcheck;   // argument-check counters
   kmx::Buf D2, chosen, seed_part, seed_ctr, seed_a, seed_cc, seed_nread;
   kmx::Buf scratch_c, hist;
   kmx::Buf fb_rows, keys, cdist, nbr, nbd, fbh;   // routed assignment
@@ -203,6 +205,12 @@ hipError_t launch_prep_centers(hipStream_t s, const float* C, int k, int d, int 
 hipError_t launch_prep_rows_f8(hipStream_t s, const float* X, int64_t n, int d, int64_t ldx,
                                int dp, uint8_t* Xq8, uint8_t* sx8, RowStats* st,
                                unsigned* xq_max, int num_cus);
+// argument checks: out[0] += rows with w > 0, out[1] += bad entries (not
+// finite, or negative weights); out must be cleared first
+hipError_t launch_check_weights(hipStream_t s, const float* w, int64_t n, unsigned long long* out,
+                                int num_cus);
+hipError_t launch_scan_finite(hipStream_t s, const float* A, int64_t rows, int cols, int64_t ld,
+                              unsigned long long* out, int num_cus);
 hipError_t launch_fill_i32(hipStream_t s, int32_t* p, int64_t n, int32_t v);
 hipError_t launch_fill_u8(hipStream_t s, uint8_t* p, int64_t n, uint8_t v);
 hipError_t launch_reset_small(hipStream_t s, CenterStats* cs, CenterStats* cs2, CenterStats* cs3,

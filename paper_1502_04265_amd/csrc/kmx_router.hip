@@ -431,6 +431,7 @@ kmx_status kmx_lloyd_routed(kmx_ctx* ctx, kmx_router* r, const float* X, int64_t
     return fail(ctx, KMX_EINVAL, "NULL C_inout, cost_hist or iters_done");
   if (max_iter < 0) return fail(ctx, KMX_EINVAL, "max_iter must be >= 0");
   KMX_TRY(set_device(ctx));
+  KMX_TRY(check_data(ctx, X, n, d, ldx, w, 0, C_inout, k));
   KMX_TRY(ensure_common(ctx, n, d, k));
   KMX_TRY(ensure_prep(ctx, X, n, d, ldx, KMX_BF16));   // the certificate reads the BF16 rows
   if (prec == KMX_FP8E4M3) KMX_TRY(ensure_prep(ctx, X, n, d, ldx, KMX_FP8E4M3));

@@ -1,5 +1,5 @@
-"""Host-side basis for the streamed pipeline's dimension reduction (Sec. 3:
-each piece is replaced by its projection onto the top right singular vectors;
+"""Host-side basis for the streamed pipeline's dimension reduction (Sec. 2.2,
+"Using SVD to project to the best fit subspace": each piece is replaced by its projection onto the top right singular vectors;
 the paper computes them with a randomized SVD).
 
 ``top_right_singular_vectors`` is the randomized range finder with subspace

@@ -139,6 +139,21 @@ def test_router_proposals_match_oracle_logits(ctx, n, d, k):
         # no duplicates within a quarter
         srt = np.sort(np.where(ok_rows, got, -1 - np.arange(4)[None, :]), axis=1)
         assert (np.diff(srt, axis=1) != 0).all()
+    # rows whose five highest logits of every quarter are separated by more
+    # than the resolution: the proposals are exactly the oracle's, in order
+    ref = om.propose(Z[:200])
+    quarter_tol = 1e-3 * (np.abs(Z[:200]).max(axis=1) + 1.0)
+    checked = 0
+    for r in range(200):
+        sep = True
+        for q in range(4):
+            zq = np.sort(Z[r, quarter == q])[::-1][:5]
+            if len(zq) > 1 and np.min(-np.diff(zq)) <= quarter_tol[r]:
+                sep = False
+        if sep:
+            checked += 1
+            assert cand[r].tolist() == ref[r].tolist(), r
+    say(f"  {checked} of 200 rows compared exactly with the oracle's proposals")
 
 
 def _plain_and_routed(ctx, X, C0, iters, router, prec="bf16"):

@@ -93,3 +93,36 @@ def test_planted_gradient_mistake_is_caught(monkeypatch):
     monkeypatch.setattr(mlp, "gradients", no_relu_mask)
     with pytest.raises(AssertionError):
         test_gradients_match_central_differences()
+
+
+def test_propose_hand_worked():
+    # k = 20: quarter of j is (j mod 16) div 4 -> quarter 0 = {0..3, 16..19},
+    # quarter 1 = {4..7}, quarter 2 = {8..11}, quarter 3 = {12..15}
+    z = np.zeros((1, 20))
+    z[0, [17, 2, 0, 19]] = [9.0, 8.0, 7.0, 7.0]      # 0 and 19 tie: 0 first
+    z[0, 5] = 3.0
+    z[0, 13] = -1.0
+    got = mlp.propose(z)[0]
+    assert got[:4].tolist() == [17, 2, 0, 19]
+    assert got[4:8].tolist() == [5, 4, 6, 7]            # ties among zeros: index order
+    assert got[12:16].tolist() == [12, 14, 15, 13]
+    # a quarter with fewer than four centers pads with -1 (k = 6: quarter 1 = {4, 5})
+    g6 = mlp.propose(np.arange(6, dtype=float)[None, :])[0]
+    assert g6[4:8].tolist() == [5, 4, -1, -1] and g6[8:].tolist() == [-1] * 8
+
+
+def test_propose_against_sorting_and_global_top_four():
+    rng = np.random.default_rng(3)
+    for k in (1, 7, 16, 37, 64):
+        Z = rng.integers(-3, 4, size=(25, k)).astype(float)   # many ties
+        P = mlp.propose(Z)
+        quarter = (np.arange(k) % 16) // 4
+        for r in range(Z.shape[0]):
+            for q in range(4):
+                J = np.nonzero(quarter == q)[0]
+                # brute force: sort by (-logit, index)
+                order = sorted(J.tolist(), key=lambda j: (-Z[r, j], j))[:4]
+                assert P[r, 4 * q:4 * q + len(order)].tolist() == order
+                assert (P[r, 4 * q + len(order):4 * q + 4] == -1).all()
+            top4 = sorted(range(k), key=lambda j: (-Z[r, j], j))[:4]
+            assert set(top4) <= set(P[r][P[r] >= 0].tolist())

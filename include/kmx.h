@@ -184,6 +184,23 @@ kmx_status kmx_lloyd_graph(kmx_ctx* ctx, const float* X, int64_t n, int32_t d, i
 kmx_status kmx_project(kmx_ctx* ctx, const float* X, int64_t rows, int32_t d_in, int64_t ldx,
                        const float* V, int32_t d_out, float* Y, int64_t ldy);
 
+/* kmx_assign with KMX_FP32 that allocates nothing, for callers that cannot
+ * allocate device memory (code under graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same labels, d1 and d2 bit for bit as
+ * kmx_assign(..., KMX_FP32, ...); n_flagged and kmx_assign_stats are not
+ * reported.  Its working memory is one static device array per GPU of 32 MiB,
+ * held until the process ends: rows are taken in chunks of 262,144, and the
+ * padded FP32 centers must fit the rest of the array, about 22 MB (k * d up to
+ * roughly 5.5 million floats after padding); larger k * d returns KMX_EINVAL
+ * with the sizes in the message.  Every call on one GPU shares that GPU's
+ * array, whichever context it comes through: calls that overlap on one GPU
+ * (other streams, other threads) race and must be serialized by the caller.
+ * The call clears what it needs at its start.  No KMX_VALIDATE scan.
+ * Stream-ordered and asynchronous; d <= 1024. */
+kmx_status kmx_assign_noalloc(kmx_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
+                              const float* C, int32_t k, int32_t* label_out, float* d1_out,
+                              float* d2_out);
+
 /* Re-check counts of the most recent assignment on ctx (kmx_assign, kmx_cost,
  * or the final assignment of kmx_lloyd); host outputs, each nullable:
  *   listed   rows on the exact re-check list (pairs and full rows),

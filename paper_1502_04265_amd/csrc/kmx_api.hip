@@ -349,8 +349,16 @@ kmx_status kmx_create(kmx_ctx** out, int device, void* hip_stream) {
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
     return fail(nullptr, KMX_EUNSUPPORTED,
                 std::string("the library is compiled for gfx950, device is ") + prop.gcnArchName);
+  void* na = nullptr;
+  e = noalloc_init(device, &na);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(nullptr, KMX_EDEVICE,
+                std::string("address of the static scratch array: ") + hipGetErrorString(e));
+  }
   kmx_ctx* c = new (std::nothrow) kmx_ctx();
   if (!c) return fail(nullptr, KMX_ENOMEM, "out of host memory");
+  c->na_scratch = na;
   c->device = device;
   c->stream = (hipStream_t)hip_stream;
   c->num_cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;

@@ -150,6 +150,7 @@ struct kmx_ctx {
   hipStream_t stream = nullptr;
   int num_cus = 256;
   bool validate = false;   // KMX_VALIDATE=1: scan X and C for non-finite values
+  void* na_scratch = nullptr;   // device address of this device's static scratch array
   std::string err;
 
   // cached per-dataset data
@@ -194,6 +195,10 @@ struct kmx_ctx {
 };
 
 namespace kmx {
+
+// Device address of the calling device's static scratch array of
+// kmx_assign_noalloc (looked up once per device; the device must be current).
+hipError_t noalloc_init(int device, void** ptr);
 
 // ---- launchers (each returns hipSuccess or the launch error) --------------
 // prep

@@ -60,6 +60,7 @@ def lib():
         "kmx_invalidate": [_vp, _vp],
         "kmx_seed": [_vp, _vp, _i64, _i32, _i64, _vp, _i32, ctypes.c_uint64, _vp, _vp],
         "kmx_assign": [_vp, _vp, _i64, _i32, _i64, _vp, _i32, ctypes.c_int, _vp, _vp, _vp, _vp],
+        "kmx_assign_noalloc": [_vp, _vp, _i64, _i32, _i64, _vp, _i32, _vp, _vp, _vp],
         "kmx_update": [_vp, _vp, _i64, _i32, _i64, _vp, _vp, _i32, _vp, _vp, _vp, _vp],
         "kmx_cost": [_vp, _vp, _i64, _i32, _i64, _vp, _vp, _i32, ctypes.c_int, _vp],
         "kmx_lloyd": [_vp, _vp, _i64, _i32, _i64, _vp, _vp, _i32, _i32, ctypes.c_double,
@@ -177,6 +178,18 @@ class Context:
         _check(lib().kmx_assign(self._p, _ptr(X), n, d, ldx, _ptr(C), k, _PREC[prec], _ptr(lab),
                                 _ptr(d1), _ptr(d2), ctypes.byref(nf)), self._p)
         return lab, d1, d2, int(nf.value)
+
+    def assign_noalloc(self, X, C, label, d1=None, d2=None):
+        """kmx_assign_noalloc: the FP32 assignment into caller-provided outputs,
+        with no device allocation inside the library."""
+        n, d, ldx = _rows(X)
+        k = _centers(C, d)
+        _vec(label, n, torch.int32)
+        _vec(d1, n)
+        _vec(d2, n)
+        self._sync_stream()
+        _check(lib().kmx_assign_noalloc(self._p, _ptr(X), n, d, ldx, _ptr(C), k, _ptr(label),
+                                        _ptr(d1), _ptr(d2)), self._p)
 
     def update(self, X, labels, C_prev, w=None, out=None):
         n, d, ldx = _rows(X)

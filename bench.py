@@ -5,21 +5,30 @@ Gaussian mixture (means N(0, 4I), sigma_c uniform in [0.5, 1.5], row i in
 component i mod 1000), k = 1000, k-means++ seeding (seed 0), W = 5 plain FP32
 Lloyd iterations whose labels train the candidate router (1 epoch over the
 5 n pairs, batch 8192, Adam lr 1e-3), then K = 15 timed Lloyd iterations
-(iterations 6..20).  One step = one Lloyd iteration: certified router
-proposals, BF16 MFMA distance GEMM + exact re-check for the other rows,
-FP64 segmented reduction, new centroids, FP64 cost; the timed call includes
-the router's forward pass (one per call) and the final assignment.  The
-same iterations run from the same centers on the plain FP32 path, the full
-BF16 path and with previous labels as the only candidates; the results must
-agree (identical labels and centers; FP32 cost within 1e-6 relative).
+(iterations 6..20) from the same centers on every exact path: router
+proposals + certificate (BF16 or FP8 GEMM for the other rows), the same with
+bounds carried across iterations, the non-learned forms (bounds + previous
+label, previous label alone), the full BF16 / FP8 / FP32 GEMM paths, eager and
+replayed as a graph.  Each path is timed --repeats times (median reported);
+each timed call includes the router's forward pass (one per call) and the
+final assignment.  `value` is the fastest path that uses the router (the
+method's router + mixed-precision form), reported only when every path
+returned identical labels and centers and its final cost equals the FP32
+path's within 1e-6 relative; the fastest path overall is reported beside it.
 
 Prints ONE JSON line.  Data is synthetic and generated on the device before
-the timed region; seeding, the plain iterations, training and the
-comparison runs are timed separately and reported as extra fields.
+the timed region; seeding, the plain iterations, training and the oracle
+(FP64 CPU timing and the FP64 errors of the reported results) are outside it.
+--workload rotated|streamed|batched|small prints the other workloads' lines;
+--only assign and --traffic are the counter-collection modes.
 """
 from __future__ import annotations
 
 import argparse
+import re
+import hashlib
+import glob
+import csv
 import json
 import os
 import sys
@@ -65,6 +74,68 @@ def measured_traffic(key):
         return rec[key]["hbm_bytes"]
     except (OSError, KeyError, ValueError):
         return None
+
+
+# ---------------------------------------------------------------------------
+# HBM traffic of the assignment GEMMs from two rocprofv3 counter passes over
+# `bench.py --only assign` (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch):
+#   python bench.py --traffic <fetch_dir> <write_dir> <out.json>
+# The three plain 1 GiB device copies at the end of that mode calibrate both
+# counters (bytes moved / counter value); for each precision the full-size
+# GEMM dispatches (largest grid of that kernel) are averaged.  The record
+# carries the sha256 of the kernel source, so the headline stops reporting the
+# traffic once the kernel changes.
+# ---------------------------------------------------------------------------
+TRAFFIC_SOURCE = "paper_1502_04265_amd/csrc/k_assign.hip"
+TRAFFIC_MODES = {0: "assign_fp32", 1: "assign_bf16", 2: "assign_fp8"}
+
+
+def _traffic_rows(d):
+    out = []
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        out.extend(csv.DictReader(open(f)))
+    return out
+
+
+def _traffic_by_kernel(rows):
+    gemm, copies = {}, []
+    for r in rows:
+        name, val, grid = r["Kernel_Name"], float(r["Counter_Value"]), int(r["Grid_Size"])
+        m = re.search(r"assign_kernel<(\d+),", name)
+        if m:
+            gemm.setdefault(int(m.group(1)), []).append((grid, val))
+        elif "copyBuffer" in name or "copy" in name.lower():
+            copies.append((int(r["Dispatch_Id"]), grid, val))
+    return gemm, copies
+
+
+def traffic_convert(fetch_dir, write_dir):
+    fg, fc = _traffic_by_kernel(_traffic_rows(fetch_dir))
+    wg, wc = _traffic_by_kernel(_traffic_rows(write_dir))
+    gib_kib = 1 << 20
+
+    def calib(copies, full):
+        # the three 1 GiB copies are the last copies of the largest grid
+        big = max(g for _, g, _ in copies)
+        vals = [v for _, g, v in sorted(copies) if g == big][-3:]
+        return full / (sum(vals) / len(vals)), sum(vals) / len(vals)
+
+    ff, fcopy = calib(fc, gib_kib)
+    wf, wcopy = calib(wc, gib_kib)
+    rec = {"kernel_source": TRAFFIC_SOURCE,
+           "kernel_source_sha256": hashlib.sha256(open(os.path.join(ROOT, TRAFFIC_SOURCE), "rb").read()).hexdigest(),
+           "fetch_factor": ff, "write_factor": wf,
+           "copy_1GiB": {"fetch_kib": fcopy, "write_kib": wcopy}}
+    for mode, key in TRAFFIC_MODES.items():
+        if mode not in fg or mode not in wg:
+            continue
+        def full_mean(v):
+            g = max(x for x, _ in v)
+            sel = [y for x, y in v if x == g]
+            return sum(sel) / len(sel)
+        fk, wk = full_mean(fg[mode]), full_mean(wg[mode])
+        rec[key] = {"fetch_kib": fk, "write_kib": wk, "hbm_bytes": (fk * ff + wk * wf) * 1024.0}
+    return rec
 
 
 def host_cpu():
@@ -134,12 +205,24 @@ def library_reference():
     return out
 
 
+def _oracle_chunk(args):
+    """One worker of the all-core oracle timing: assignment + clustering
+    features of a block of rows (plain oracle calls)."""
+    rows, C = args
+    from oracle import kmeans as ok
+    lab, _, _ = ok.assign(rows, C)
+    ok.clustering_features(rows, None, lab, C.shape[0])
+    return len(rows)
+
+
 def cpu_baseline(X_host_rows, C_host, n_full, seconds_target=10.0, gpu_labels=None):
     """Times the FP64 oracle (assignment + update of one Lloyd iteration) on a
-    bounded row sample and scales to the full n.  With gpu_labels (the path's
-    labels of the same rows against the same centers), also counts the rows
-    whose label differs from the oracle's outside its 1e-6 relative top-2
-    margin."""
+    bounded row sample, on one core and on every usable core (a process per
+    core, each running the oracle on its share of the rows), and scales to the
+    full n.  With gpu_labels (the path's labels of the same rows against the
+    same centers), also counts the rows whose label differs from the oracle's
+    outside its 1e-6 relative top-2 margin."""
+    import multiprocessing as mp
     import numpy as np
     from oracle import kmeans as ok
 
@@ -156,16 +239,52 @@ def cpu_baseline(X_host_rows, C_host, n_full, seconds_target=10.0, gpu_labels=No
     ok.update(sample, None, lab, C_host)
     t = time.perf_counter() - t0
     sec_per_iter = t * n_full / m
+    host = host_cpu()
     res = {"value": 1.0 / sec_per_iter, "unit": "iter/s", "cores": 1, "kind": "oracle",
            "sample": f"one Lloyd iteration (FP64 assign + update) on {m} of {n_full} rows, "
-                     f"all {C_host.shape[0]} centers; {t:.1f} s measured, scaled by n",
-           "sec_per_iter": sec_per_iter, "host": host_cpu()}
+                     f"all {C_host.shape[0]} centers; {t:.1f} s measured on one core, scaled by n",
+           "sec_per_iter": sec_per_iter, "host": host}
+    # every usable core: one process per core on equal shares of a larger sample
+    # (at most 16: the CPU share of one GPU on the boxes this runs on)
+    cores = max(1, min(16, int(host["nproc"] or 1)))
+    if cores > 1:
+        m_all = int(min(len(rows), m * cores))
+        step = (m_all + cores - 1) // cores
+        shares = [(rows[a:min(a + step, m_all)], C_host) for a in range(0, m_all, step)]
+        # fresh interpreters: the workers import only NumPy and the oracle
+        ctx = mp.get_context("spawn")
+        with ctx.Pool(processes=cores) as pool:
+            pool.map(_oracle_chunk, [(r[:50], c) for r, c in shares])   # warm the workers
+            t0 = time.perf_counter()
+            done = sum(pool.map(_oracle_chunk, shares))
+            t_all = time.perf_counter() - t0
+        res["all_cores"] = {"value": done / (t_all * n_full), "unit": "iter/s", "cores": cores,
+                            "sample": f"{done} rows in {cores} processes, {t_all:.1f} s wall, "
+                                      f"scaled by n"}
     if gpu_labels is not None:
         g = np.asarray(gpu_labels[:m])
         bad = (g != lab) & ~((d2 - d1) < 1e-6 * d2)
         res["label_check"] = {"rows": m, "differ_outside_margin": int(bad.sum()),
                               "inside_margin": int(((d2 - d1) < 1e-6 * d2).sum())}
     return res
+
+
+def fp64_errors(X_host, labels, C_T, cost_T, C_next, k):
+    """Errors of a path's results against the FP64 oracle on the same
+    partition: cost(C_T) from the clustering features of the final labels
+    (Sec. 2.1), and the centroids of that partition (the next update)."""
+    import numpy as np
+    from oracle import kmeans as ok
+
+    Cn, W, S, Q = ok.update(X_host, None, labels, C_T)
+    cost_o = ok.cost_from_features(W, S, Q, C_T)
+    G = np.asarray(C_next, dtype=np.float64)
+    rel = [float(np.linalg.norm(G[j] - Cn[j]) / max(np.linalg.norm(Cn[j]), 1e-3))
+           for j in range(k)]
+    return {"cost_rel_err": abs(cost_T - cost_o) / cost_o, "cost_oracle": cost_o,
+            "centroid_rel_err_max": max(rel), "centroid_rel_err_mean": float(np.mean(rel)),
+            "what": "final cost and the centroids of the final labels against the FP64 oracle "
+                    "(clustering features of the same partition, all rows)"}
 
 
 def batched_main(args):
@@ -245,6 +364,112 @@ def batched_main(args):
         "whole_iteration_tflops": flops / (wall / args.steps) / 1e12,
         "tiles": tiles, "seed_s": seed_s, "autotune_s": tune_s,
     }
+    print(json.dumps(out), flush=True)
+
+
+def rotated_main(args):
+    """Plain vs mixed precision on the largest SWN / Random shape of the
+    paper's experiments (n = 1,000,000 points in d = 1000, k = 50): a
+    50-component mixture with a random rotation and log-uniform eigenvalues per
+    component, k-means++ (seed 0), then --steps Lloyd iterations (default 50)
+    from the same centers on the plain FP32 path and on the BF16 / FP8 paths
+    with the exact re-check (and with carried bounds).  `value` is the BF16
+    path, valid only when every path returns the same labels, centers and
+    cost."""
+    import torch
+
+    import synth
+    from paper_1502_04265_amd import kmx
+
+    n, d, k = 1_000_000, 1000, 50
+    steps = args.steps if args.steps_given else 50
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    ctx = kmx.Context(0)
+    log(f"[bench] generating rotated mixture {n}x{d}, {k} components")
+    X, _ = synth.rotated_mixture_device(n, d, k, seed=0, device=dev)
+    torch.cuda.synchronize()
+    C0, _ = ctx.seed(X, k, rng_seed=0)
+    for prec in ("bf16", "fp8", "fp32"):
+        ctx.lloyd(X, C0, 1, prec=prec, labels=False)           # quantized copies, buffers
+    res, paths = {}, {}
+
+    def run(name, fn, dtype):
+        walls, kts, out = [], [], None
+        for _ in range(args.repeats):
+            ctx.timing(True, True)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            out = fn()
+            torch.cuda.synchronize()
+            walls.append(time.perf_counter() - t)
+            kts.append(ctx.timing_read())
+            ctx.timing(False, True)
+        order = sorted(range(len(walls)), key=lambda q: walls[q])
+        med = order[len(order) // 2]
+        res[name] = out
+        kk = kts[med]
+        paths[name] = {"iter_per_s": steps / walls[med], "ms_per_step": walls[med] * 1e3 / steps,
+                       "ms_per_step_runs": [w * 1e3 / steps for w in walls],
+                       "final_cost": out[2][-1], "dtype": dtype,
+                       "kernel_ms_per_step": {c: v[0] / steps for c, v in kk.items() if v[1]},
+                       "assign_avg_ms": kk["assign"][0] / max(kk["assign"][1], 1),
+                       "reduce_avg_ms": kk["reduce"][0] / max(kk["reduce"][1], 1)}
+        log(f"[bench] {name}: {walls[med] * 1e3 / steps:.3f} ms/iter, cost {out[2][-1]:.9e}")
+
+    run("fp32", lambda: ctx.lloyd(X, C0, steps, prec="fp32"), "f32")
+    run("bf16", lambda: ctx.lloyd(X, C0, steps, prec="bf16"), "bf16")
+    run("fp8", lambda: ctx.lloyd(X, C0, steps, prec="fp8"), "fp8e4m3")
+    run("bounded_bf16", lambda: ctx.lloyd_bounded(X, C0, steps, prec="bf16"), "bf16")
+    ctx.lloyd(X, C0, 1, prec="bf16", labels=False, graph=True)
+    run("bf16_graph", lambda: ctx.lloyd(X, C0, steps, prec="bf16", graph=True), "bf16")
+    same = all(torch.equal(r[1], res["fp32"][1]) and torch.equal(r[0], res["fp32"][0])
+               for r in res.values())
+    base = paths["fp32"]["final_cost"]
+    for p in paths.values():
+        p["equal_cost_rel_diff"] = abs(p["final_cost"] - base) / base
+    best = "bf16"
+    valid = bool(same and paths[best]["equal_cost_rel_diff"] <= 1e-6)
+    dp = (d + 31) // 32 * 32
+    a_ms = paths["bf16"]["assign_avg_ms"]
+    a_bytes = n * (2.0 * dp + 16 + 4)          # BF16 rows, row statistics, labels
+    r_ms = paths["bf16"]["reduce_avg_ms"]
+    r_bytes = n * (4.0 * d + 4)
+    out = {
+        "metric": "Lloyd iter/s (n=1e6,d=1000,k=50), BF16 MFMA + exact re-check vs plain FP32, "
+                  "equal cost",
+        "value": paths[best]["iter_per_s"] if valid else 0.0, "unit": "iter/s", "n_gpus": 1,
+        "steps": steps, "warmup": 1, "ms_per_step": paths[best]["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": "rotated gaussian mixture n=1e6 d=1000 k=50 (means U[-5,5]^d, "
+                               "Haar rotation, eigenvalues 10^U[-2,0])", "n": n, "d": d, "k": k,
+                   "path": best, "timed": f"{steps} Lloyd iterations from the k-means++ centers, "
+                                          f"median of {args.repeats} runs"},
+        "valid": valid, "identical_paths": bool(same),
+        "roofline": {"bound": "hbm", "achieved": a_bytes / (a_ms * 1e-3) / 1e9,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": a_bytes / (a_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "assign_kernel<bf16> (2 k flop per BF16 row byte: HBM-bound)",
+                     "avg_ms": a_ms, "algorithmic_bytes": a_bytes},
+        "update_roofline": {"bound": "hbm", "achieved": r_bytes / (r_ms * 1e-3) / 1e9,
+                            "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                            "frac": r_bytes / (r_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                            "kernel": "reduce_kernel", "avg_ms": r_ms},
+        "paths": paths,
+        "speedup_vs_fp32": paths[best]["iter_per_s"] / paths["fp32"]["iter_per_s"],
+        "fastest_path": max(paths, key=lambda q: paths[q]["iter_per_s"]),
+    }
+    if not args.no_cpu_baseline:
+        lab_b, Cb_ = res[best][1], res[best][0]
+        rows = X[:200000].cpu().numpy()
+        out["cpu_baseline"] = cpu_baseline(rows, Cb_.cpu().numpy(), n,
+                                           gpu_labels=lab_b[:200000].cpu().numpy())
+        del rows
+        C_next, _, _ = ctx.update(X, lab_b, Cb_)
+        out["fp64_error"] = fp64_errors(X.cpu().numpy(), lab_b.cpu().numpy(),
+                                        Cb_.cpu().numpy().astype("float64"),
+                                        paths[best]["final_cost"], C_next.cpu().numpy(), k)
     print(json.dumps(out), flush=True)
 
 
@@ -374,13 +599,16 @@ def main():
     ap.add_argument("--batch", type=int, default=8192, help="router training batch")
     ap.add_argument("--lr", type=float, default=1e-3, help="router learning rate (Adam)")
     ap.add_argument("--workload", default="router",
-                    choices=sorted(WORKLOADS) + ["streamed", "batched"])
+                    choices=sorted(WORKLOADS) + ["streamed", "batched", "rotated"])
     ap.add_argument("--instances", type=int, default=256,
                     help="batched workload: number of instances")
     ap.add_argument("--chunks", type=int, default=None,
                     help="streamed workload: number of chunks (default: all of n)")
-    ap.add_argument("--fp32-steps", type=int, default=None,
-                    help="iterations of the plain FP32 comparison (default: --steps)")
+    ap.add_argument("--traffic", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT_JSON"),
+                    help="convert two rocprofv3 counter passes of --only assign into the traffic "
+                         "record (no GPU)")
+    ap.add_argument("--repeats", type=int, default=3,
+                    help="timed runs per path (the median is reported)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-library-reference", action="store_true",
@@ -390,7 +618,13 @@ def main():
                          "first k rows + noise), plus a plain 1 GiB device copy whose counters "
                          "calibrate FETCH_SIZE / WRITE_SIZE")
     args = ap.parse_args()
+    args.steps_given = any(a == "--steps" or a.startswith("--steps=") for a in sys.argv[1:])
 
+    if args.traffic:
+        rec = traffic_convert(args.traffic[0], args.traffic[1])
+        json.dump(rec, open(args.traffic[2], "w"), indent=1)
+        print(json.dumps(rec, indent=1))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
               "(run it with --gpus 1)", file=sys.stderr)
@@ -406,6 +640,8 @@ def main():
         return streamed_main(args)
     if args.workload == "batched":
         return batched_main(args)
+    if args.workload == "rotated":
+        return rotated_main(args)
     wl = WORKLOADS[args.workload]
     n, d, k = wl["n"], wl["d"], wl["k"]
     dev = "cuda:0"
@@ -498,60 +734,85 @@ def main():
         prep_once[prec] = (time.perf_counter() - t0) * 1e3
     log(f"[bench] quantized copies of X (one-off, with one assignment each): {prep_once}")
 
-    # ---- timed region: K routed Lloyd iterations (BF16 GEMM for the rest) ----
-    ctx.timing(True, True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    Cr, lab_r, hist_r, it_r, rows_r = ctx.lloyd_routed(X, Cw, args.steps, router=router,
-                                                       prec="bf16", labels=True)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    kt = ctx.timing_read()
-    ctx.timing(False, True)
-    ms_per_step = wall * 1e3 / args.steps
-    value = args.steps / wall
-    log(f"[bench] routed: {ms_per_step:.3f} ms/iter, {value:.2f} iter/s, cost {hist_r[-1]:.9e}, "
-        f"GEMM rows {rows_r}")
-
+    # ---- timed region: K Lloyd iterations from the same centers on every
+    # exact path, each timed REPEATS times (the median is reported) ----
     def run_timed(label, fn):
-        ctx.timing(True, True)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        res = fn()
-        torch.cuda.synchronize()
-        w = time.perf_counter() - t
-        kk = ctx.timing_read()
-        ctx.timing(False, True)
-        log(f"[bench] {label}: {w * 1e3 / args.steps:.3f} ms/iter, cost {res[2][-1]:.9e}")
-        return res, w, kk
+        walls, kts, res = [], [], None
+        for _ in range(args.repeats):
+            ctx.timing(True, True)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            res = fn()
+            torch.cuda.synchronize()
+            walls.append(time.perf_counter() - t)
+            kts.append(ctx.timing_read())
+            ctx.timing(False, True)
+        order = sorted(range(len(walls)), key=lambda q: walls[q])
+        med = order[len(order) // 2]
+        w = walls[med]
+        log(f"[bench] {label}: {w * 1e3 / args.steps:.3f} ms/iter (median of {len(walls)}: "
+            f"{', '.join(f'{x * 1e3 / args.steps:.3f}' for x in walls)}), cost {res[2][-1]:.9e}")
+        return res, w, kts[med], walls
 
-    # ---- the same iterations without the router: full BF16 GEMM, previous labels ----
-    (Cb, lab_b, hist_b, _), wb, ktb = run_timed(
-        "full bf16", lambda: ctx.lloyd(X, Cw, args.steps, prec="bf16", labels=True))
-    (Cp, lab_p, hist_p, _, rows_p), wp, _ = run_timed(
-        "previous labels", lambda: ctx.lloyd_routed(X, Cw, args.steps, router=None, prec="bf16",
-                                                    labels=True))
-    (C8, lab_8, hist_8, _), w8, kt8 = run_timed(
-        "full fp8", lambda: ctx.lloyd(X, Cw, args.steps, prec="fp8", labels=True))
+    def per_step(kk):
+        return {c: (v[0] / args.steps) for c, v in kk.items() if v[1]}
+
+    paths, results = {}, {}
+
+    def add(name, fn, assign, uses_router, dtype):
+        res, w, kk, walls = run_timed(name, fn)
+        results[name] = res
+        paths[name] = {"iter_per_s": args.steps / w, "ms_per_step": w * 1e3 / args.steps,
+                       "ms_per_step_runs": [x * 1e3 / args.steps for x in walls],
+                       "final_cost": res[2][-1], "kernel_ms_per_step": per_step(kk),
+                       "assign": assign, "router": uses_router, "dtype": dtype}
+        if len(res) > 4:
+            paths[name]["gemm_rows_per_assignment"] = res[4]
+        if len(res) > 5:
+            paths[name]["bound_kept_rows_per_assignment"] = res[5]
+        return kk
+
+    S = args.steps
+    kt = add("routed_bf16", lambda: ctx.lloyd_routed(X, Cw, S, router=router, prec="bf16"),
+             "router proposals + Elkan certificate, BF16 MFMA GEMM + exact re-check for the "
+             "other rows", True, "bf16")
+    add("routed_fp8", lambda: ctx.lloyd_routed(X, Cw, S, router=router, prec="fp8"),
+        "router proposals + certificate, FP8 E4M3 GEMM cascade for the other rows", True,
+        "fp8e4m3")
+    kb8r = add("bounded_routed_fp8",
+               lambda: ctx.lloyd_bounded(X, Cw, S, router=router, prec="fp8"),
+               "bounds carried across iterations; rows they cannot keep: router proposals + "
+               "certificate, then the FP8 E4M3 GEMM cascade", True, "fp8e4m3")
+    kb8 = add("bounded_fp8", lambda: ctx.lloyd_bounded(X, Cw, S, router=None, prec="fp8"),
+              "bounds carried across iterations; rows they cannot keep: previous-label "
+              "certificate, then the FP8 E4M3 GEMM cascade", False, "fp8e4m3")
+    add("previous_labels", lambda: ctx.lloyd_routed(X, Cw, S, router=None, prec="bf16"),
+        "previous label + certificate, BF16 GEMM for the other rows", False, "bf16")
+    ktb = add("full_bf16", lambda: ctx.lloyd(X, Cw, S, prec="bf16"),
+              "BF16 MFMA GEMM with fused top-4, FP32 GEMM pass and exact re-check of undecided "
+              "rows", False, "bf16")
+    kt8 = add("full_fp8", lambda: ctx.lloyd(X, Cw, S, prec="fp8"),
+              "FP8 E4M3 MFMA GEMM (per-row scales) with fused top-3, BF16 then FP32 GEMM passes "
+              "and exact re-check of undecided rows", False, "fp8e4m3")
     fp8_stats = ctx.assign_stats()
-    (Cr8, lab_r8, hist_r8, _, rows_r8), wr8, ktr8 = run_timed(
-        "routed fp8", lambda: ctx.lloyd_routed(X, Cw, args.steps, router=router, prec="fp8",
-                                               labels=True))
-    # the same full paths with the iteration replayed as a graph (kmx_lloyd_graph);
-    # one untimed call each first (the first capture on a context pays one-off costs)
-    for prec in ("bf16", "fp8"):
+    paths["full_fp8"]["final_listed_via_fp32_all"] = list(fp8_stats)
+    for prec in ("bf16", "fp8"):     # the first capture on a context pays one-off costs
         ctx.lloyd(X, Cw, 1, prec=prec, labels=False, graph=True)
-    (Cgb, lab_gb, hist_gb, _), wgb, _ = run_timed(
-        "full bf16 graph", lambda: ctx.lloyd(X, Cw, args.steps, prec="bf16", labels=True,
-                                             graph=True))
-    (Cg8, lab_g8, hist_g8, _), wg8, _ = run_timed(
-        "full fp8 graph", lambda: ctx.lloyd(X, Cw, args.steps, prec="fp8", labels=True,
-                                            graph=True))
-    same = bool(torch.equal(lab_r, lab_b) and torch.equal(Cr, Cb) and torch.equal(lab_p, lab_b)
-                and torch.equal(lab_8, lab_b) and torch.equal(C8, Cb)
-                and torch.equal(lab_r8, lab_b) and torch.equal(Cr8, Cb)
-                and torch.equal(lab_gb, lab_b) and torch.equal(Cgb, Cb)
-                and torch.equal(lab_g8, lab_b) and torch.equal(Cg8, Cb))
+    add("full_bf16_graph", lambda: ctx.lloyd(X, Cw, S, prec="bf16", graph=True),
+        "as full_bf16, the iteration replayed as a HIP graph", False, "bf16")
+    add("full_fp8_graph", lambda: ctx.lloyd(X, Cw, S, prec="fp8", graph=True),
+        "as full_fp8, the iteration replayed as a HIP graph", False, "fp8e4m3")
+    ktf = None
+    if not args.no_fp32:
+        ktf = add("fp32", lambda: ctx.lloyd(X, Cw, S, prec="fp32"),
+                  "plain FP32 MFMA GEMM with fused top-3 and exact re-check (the reference path "
+                  "of the metric)", False, "f32")
+
+    base_lab, base_C = results["full_bf16"][1], results["full_bf16"][0]
+    same = all(torch.equal(r[1], base_lab) and torch.equal(r[0], base_C) for r in results.values())
+    cost_ref = paths["fp32"]["final_cost"] if "fp32" in paths else paths["full_bf16"]["final_cost"]
+    for p in paths.values():
+        p["equal_cost_rel_diff"] = abs(p["final_cost"] - cost_ref) / cost_ref
 
     # ---- rooflines ----
     def avg(kk, cls):
@@ -563,51 +824,25 @@ def main():
     achieved = flops / (a_ms * 1e-3) / 1e12
     a8_ms, _ = avg(kt8, "assign")           # the FP8 pass (its BF16 cascade is timed as re-check)
     achieved8 = flops / (a8_ms * 1e-3) / 1e12
-    r_ms, _ = avg(kt, "reduce")
+    r_ms, _ = avg(kb8r, "reduce")
     reduce_bytes = n * d * 4 + n * 4          # rows of X (FP32) + the permutation
     reduce_gbs = reduce_bytes / (r_ms * 1e-3) / 1e9
     f_ms, f_cnt = avg(kt, "router")
     router_flops = 2.0 * n * (d * 256 + 256 * k)
     c_ms, c_cnt = avg(kt, "certificate")
     cert_bytes = n * (2 * d + 64 + 4 + 16)     # BF16 row, 16 proposals, label, row statistics
-    gemm_rows_mean = sum(rows_r) / len(rows_r)
+    bd_ms, bd_cnt = avg(kb8, "bounds")
 
-    def per_step(kk):
-        return {c: (v[0] / args.steps) for c, v in kk.items() if v[1]}
-
-    # every path returns the same labels and centers; `value` is the fastest
-    paths = {
-        "routed": {"iter_per_s": value, "ms_per_step": ms_per_step, "final_cost": hist_r[-1],
-                   "kernel_ms_per_step": per_step(kt), "gemm_rows_per_assignment": rows_r,
-                   "gemm_row_fraction": gemm_rows_mean / n,
-                   "assign": "router proposals + certificate, bf16 MFMA GEMM + FP32 re-check "
-                             "for the other rows"},
-        "previous_labels": {"iter_per_s": args.steps / wp, "ms_per_step": wp * 1e3 / args.steps,
-                            "final_cost": hist_p[-1], "gemm_rows_per_assignment": rows_p,
-                            "assign": "previous label + certificate, bf16 MFMA GEMM for the "
-                                      "other rows"},
-        "full_bf16": {"iter_per_s": args.steps / wb, "ms_per_step": wb * 1e3 / args.steps,
-                      "final_cost": hist_b[-1], "kernel_ms_per_step": per_step(ktb),
-                      "assign": "bf16 MFMA GEMM with fused top-4, FP32 GEMM pass and exact "
-                                "re-check of undecided rows"},
-        "routed_fp8": {"iter_per_s": args.steps / wr8, "ms_per_step": wr8 * 1e3 / args.steps,
-                       "final_cost": hist_r8[-1], "kernel_ms_per_step": per_step(ktr8),
-                       "gemm_rows_per_assignment": rows_r8,
-                       "assign": "router proposals + certificate, fp8 e4m3 MFMA GEMM cascade "
-                                 "for the other rows"},
-        "full_bf16_graph": {"iter_per_s": args.steps / wgb, "ms_per_step": wgb * 1e3 / args.steps,
-                            "final_cost": hist_gb[-1],
-                            "assign": "as full_bf16, the iteration replayed as a HIP graph"},
-        "full_fp8_graph": {"iter_per_s": args.steps / wg8, "ms_per_step": wg8 * 1e3 / args.steps,
-                           "final_cost": hist_g8[-1],
-                           "assign": "as full_fp8, the iteration replayed as a HIP graph"},
-        "full_fp8": {"iter_per_s": args.steps / w8, "ms_per_step": w8 * 1e3 / args.steps,
-                     "final_cost": hist_8[-1], "kernel_ms_per_step": per_step(kt8),
-                     "final_listed_via_fp32_all": list(fp8_stats),
-                     "assign": "fp8 e4m3 MFMA GEMM (per-row scales) with fused top-4, bf16 "
-                               "then FP32 GEMM passes and exact re-check of undecided rows"},
-    }
-    best = max(paths, key=lambda q: paths[q]["iter_per_s"])
+    # `value`: the router form of the method (router proposals + mixed precision,
+    # with or without carried bounds), valid only when every path returned the
+    # same labels and centers and the same final cost as the FP32 path
+    routed = [p for p in paths if paths[p]["router"]]
+    best = max(routed, key=lambda q: paths[q]["iter_per_s"])
+    fastest = max(paths, key=lambda q: paths[q]["iter_per_s"])
+    equal_cost = paths[best]["equal_cost_rel_diff"] <= 1e-6
+    valid = bool(same and equal_cost)
+    value = paths[best]["iter_per_s"] if valid else 0.0
+    ms_per_step = paths[best]["ms_per_step"]
     bf16_roof = {"bound": "mfma", "achieved": achieved, "peak": BF16_PEAK_TFLOPS,
                  "unit": "TFLOP/s", "frac": achieved / BF16_PEAK_TFLOPS,
                  "traffic": measured_traffic("assign_bf16") if args.workload == "router" else None,
@@ -618,30 +853,40 @@ def main():
                 "traffic": measured_traffic("assign_fp8") if args.workload == "router" else None,
                 "kernel": "assign_kernel<fp8> (full assignment)", "avg_ms": a8_ms,
                 "algorithmic_flops": flops}
-    value = paths[best]["iter_per_s"]
-    ms_per_step = paths[best]["ms_per_step"]
+    update_roof = {"bound": "hbm", "achieved": reduce_gbs, "peak": HBM_PEAK_GBS,
+                   "unit": "GB/s", "frac": reduce_gbs / HBM_PEAK_GBS,
+                   "traffic": measured_traffic("reduce") if args.workload == "router" else None,
+                   "kernel": "reduce_kernel (FP64 segmented reduction)", "avg_ms": r_ms,
+                   "algorithmic_bytes": reduce_bytes}
+    # the dominant kernel of the reported path
+    kms = paths[best]["kernel_ms_per_step"]
+    dom = max(kms, key=lambda c: kms[c]) if kms else "assign"
+    roofline = update_roof if dom == "reduce" else fp8_roof
 
     out = {
         "metric": METRIC, "value": value, "unit": "iter/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "fp8e4m3" if best in ("full_fp8", "routed_fp8", "full_fp8_graph") else "bf16", "data": "synthetic",
+        "dtype": paths[best]["dtype"], "data": "synthetic",
         "config": {"workload": wl["name"], "n": n, "d": d, "k": k, "path": best,
                    "assign": paths[best]["assign"], "reduce": "fp64",
                    "timed": f"Lloyd iterations {args.warmup + 1}..{args.warmup + args.steps} "
-                            f"from the centers after {args.warmup} plain FP32 iterations",
-                   "value_is": "the fastest of the exact paths below (identical labels and "
-                               "centers)"},
-        "roofline": fp8_roof if best in ("full_fp8", "routed_fp8", "full_fp8_graph") else bf16_roof,
+                            f"from the centers after {args.warmup} plain FP32 iterations, "
+                            f"median of {args.repeats} runs",
+                   "value_is": "the fastest path that uses the router (router proposals + "
+                               "mixed precision); reported only when every path returned "
+                               "identical labels and centers and its final cost equals the "
+                               "FP32 path's within 1e-6 relative"},
+        "valid": valid,
+        "roofline": roofline,
+        "roofline_dominant_kernel_class": dom,
         "bf16_gemm_roofline": bf16_roof,
         "fp8_gemm_roofline": fp8_roof,
+        "update_roofline": update_roof,
         "seed_roofline": {"bound": "hbm", "achieved": seed_gbs, "peak": HBM_PEAK_GBS,
                           "unit": "GB/s", "frac": seed_gbs / HBM_PEAK_GBS,
                           "kernel": "seed_round_kernel", "avg_ms": seed_ev_ms / k, "rounds": k,
                           "rows_read_fraction": seed_frac_read},
-        "update_roofline": {"bound": "hbm", "achieved": reduce_gbs, "peak": HBM_PEAK_GBS,
-                            "unit": "GB/s", "frac": reduce_gbs / HBM_PEAK_GBS,
-                            "kernel": "reduce_kernel", "avg_ms": r_ms},
         "router_roofline": {"bound": "mfma", "achieved": router_flops / (f_ms * 1e-3) / 1e12,
                             "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
                             "frac": router_flops / (f_ms * 1e-3) / 1e12 / BF16_PEAK_TFLOPS,
@@ -650,54 +895,59 @@ def main():
                                  "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                  "frac": cert_bytes / (c_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                                  "kernel": "center table + router_cert_kernel", "avg_ms": c_ms},
+        "bound_test_ms": bd_ms,
         "paths": paths,
-        "router_vs_full_bf16": paths["routed"]["iter_per_s"] / paths["full_bf16"]["iter_per_s"],
-        "identical_paths": same,
+        "fastest_path": {"path": fastest, "iter_per_s": paths[fastest]["iter_per_s"]},
+        "router_gain": {
+            "routed_fp8_vs_full_fp8": paths["routed_fp8"]["iter_per_s"]
+            / paths["full_fp8"]["iter_per_s"],
+            "bounded_routed_fp8_vs_bounded_fp8": paths["bounded_routed_fp8"]["iter_per_s"]
+            / paths["bounded_fp8"]["iter_per_s"]},
+        "identical_paths": bool(same),
+        "equal_cost": bool(equal_cost),
         "router_training": train,
         "seed_ms": seed_ms, "warmup_ms": warm_ms,
         "quantized_copies_once_ms": prep_once,
         "final_cost": paths[best]["final_cost"],
     }
-
-    # ---- plain FP32 path from the same start ----
-    if not args.no_fp32:
-        ks = args.fp32_steps or args.steps
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        Cf, lab_f, hist_f, it_f = ctx.lloyd(X, Cw, ks, prec="fp32", labels=False)
-        torch.cuda.synchronize()
-        wf = time.perf_counter() - t0
-        log(f"[bench] fp32: {wf * 1e3 / ks:.3f} ms/iter, cost {hist_f[-1]:.9e}")
-        out["fp32_path"] = {"iter_per_s": ks / wf, "ms_per_step": wf * 1e3 / ks, "steps": ks,
-                            "final_cost": hist_f[-1]}
+    if "fp32" in paths:
+        out["fp32_path"] = {"iter_per_s": paths["fp32"]["iter_per_s"],
+                            "ms_per_step": paths["fp32"]["ms_per_step"],
+                            "final_cost": paths["fp32"]["final_cost"]}
+        out["speedup_vs_fp32"] = paths[best]["iter_per_s"] / paths["fp32"]["iter_per_s"]
+        out["equal_cost_rel_diff"] = paths[best]["equal_cost_rel_diff"]
         if n <= 1_000_000:
             # small problems are launch-bound: the same iterations replayed as a graph
             ctx.lloyd(X, Cw, 1, prec="fp32", labels=False, graph=True)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            Cfg, _, hist_fg, _ = ctx.lloyd(X, Cw, ks, prec="fp32", labels=False, graph=True)
-            torch.cuda.synchronize()
-            wfg = time.perf_counter() - t0
-            log(f"[bench] fp32 graph: {wfg * 1e3 / ks:.3f} ms/iter, cost {hist_fg[-1]:.9e}")
-            out["fp32_path"]["graph_ms_per_step"] = wfg * 1e3 / ks
-            out["fp32_path"]["graph_identical"] = bool(torch.equal(Cfg, Cf) and hist_fg == hist_f)
-        out["speedup_vs_fp32"] = value / (ks / wf)
-        if ks == args.steps:
-            rel = abs(hist_f[-1] - paths[best]["final_cost"]) / hist_f[-1]
-            out["equal_cost_rel_diff"] = rel
-            out["equal_cost"] = bool(rel <= 1e-6)
+            res, wfg, _, _ = run_timed("fp32 graph",
+                                       lambda: ctx.lloyd(X, Cw, S, prec="fp32", graph=True))
+            out["fp32_path"]["graph_ms_per_step"] = wfg * 1e3 / S
+            out["fp32_path"]["graph_identical"] = bool(torch.equal(res[0], results["fp32"][0])
+                                                       and res[2] == results["fp32"][2])
+    if not valid:
+        out["invalid_reason"] = ("paths differ" if not same else "final cost differs from the "
+                                 "FP32 path by more than 1e-6 relative")
 
     # ---- plain library work on the same part, for context ----
     if not args.no_library_reference:
         out["library_reference"] = library_reference()
         log(f"[bench] library reference {out['library_reference']}")
 
-    # ---- CPU oracle baseline on a bounded sample ----
+    # ---- the FP64 oracle: timed on the host's cores, and the error of the
+    # reported path's results against it ----
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
-        rows = X[:20000].cpu().numpy()
-        out["cpu_baseline"] = cpu_baseline(rows, Cr.cpu().numpy(), n,
-                                           gpu_labels=lab_r[:20000].cpu().numpy())
+        Cb_, lab_b = results[best][0], results[best][1]
+        rows = X[:min(n, 320000)].cpu().numpy()
+        out["cpu_baseline"] = cpu_baseline(rows, Cb_.cpu().numpy(), n,
+                                           gpu_labels=lab_b[:min(n, 320000)].cpu().numpy())
+        del rows
+        log("[bench] FP64 errors of the results")
+        C_next, _, _ = ctx.update(X, lab_b, Cb_)
+        out["fp64_error"] = fp64_errors(X.cpu().numpy(), lab_b.cpu().numpy(),
+                                        Cb_.cpu().numpy().astype("float64"),
+                                        paths[best]["final_cost"], C_next.cpu().numpy(), k)
+        log(f"[bench] fp64 errors {out['fp64_error']}")
 
     print(json.dumps(out), flush=True)
 

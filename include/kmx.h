@@ -214,14 +214,35 @@ kmx_status kmx_assign_noalloc(kmx_ctx* ctx, const float* X, int64_t n, int32_t d
  * Synchronizes. */
 kmx_status kmx_assign_stats(kmx_ctx* ctx, int64_t* listed, int64_t* fp32, int64_t* full);
 
+/* Measurement of the arithmetic the assignment's error bounds rely on:
+ * instance q < count runs one matrix instruction of the distance GEMM of
+ * `prec`, exactly as the assignment issues it, on A_q and B_q (device,
+ * instance after instance, 16 rows each, row-major) starting from C (device,
+ * count x 16 x 16 float32, nullable: zero), and stores
+ *     D[q][i][j] = C[q][i][j] + sum_t A_q[i][t] B_q[j][t]
+ * as the matrix core rounds it (device, count x 16 x 16 float32):
+ *   KMX_FP8E4M3: 16 x 128 E4M3 bytes per row; every row of A_q is scaled by
+ *     2^(scale_a[q] - 127) and row j of B_q by 2^(scale_b[16 q + j] - 127)
+ *     (E8M0 bytes, device);
+ *   KMX_BF16: 16 x 32 BF16 values (bit patterns) per row; scales unused;
+ *   KMX_FP32: 16 x 4 floats per row; scales unused.
+ * The FP8 bound takes an instruction's error to be at most
+ * 2^-10 sum |a_t b_t| + 2^-19 (|C| + sum |a_t b_t|) plus the FP32 rounding of
+ * the result; the BF16 and FP32 bounds take K faithful FP32 steps (K = 32 or
+ * 4 products).  This call lets a test check that on the device at hand.
+ * Stream-ordered. */
+kmx_status kmx_mfma_probe(kmx_ctx* ctx, kmx_prec prec, const void* A, const void* B,
+                          const uint8_t* scale_a, const uint8_t* scale_b, const float* C, float* D,
+                          int32_t count);
+
 /* Kernel timing for measurement: while enabled, HIP events bracket every
  * kernel class on the context's stream.  kmx_timing_read returns the summed
  * milliseconds and launch counts per class since the last reset:
  *   class 0 prep (row statistics, quantization), 1 assign GEMM, 2 re-check,
  *   3 label sort, 4 segmented reduction, 5 finalize, 6 seeding, 7 other,
  *   8 router forward pass, 9 center table + certificate, 10 router training,
- *   11 projection.
- * ms_out and count_out are host arrays of length n_classes (<= 12).
+ *   11 projection, 12 carried bounds (bound test, center drift).
+ * ms_out and count_out are host arrays of length n_classes (<= 13).
  * Reading synchronizes.  enable = 0 stops recording; reset clears sums. */
 kmx_status kmx_timing(kmx_ctx* ctx, int enable, int reset);
 kmx_status kmx_timing_read(kmx_ctx* ctx, int n_classes, double* ms_out, int64_t* count_out);
@@ -345,6 +366,30 @@ kmx_status kmx_lloyd_routed(kmx_ctx* ctx, kmx_router* r, const float* X, int64_t
                             int64_t ldx, const float* w, float* C_inout, int32_t k,
                             int32_t max_iter, double tol, kmx_prec prec, int32_t* label_out,
                             double* cost_hist, int32_t* iters_done, int64_t* gemm_rows);
+
+/* Lloyd's algorithm as kmx_lloyd (same arguments, results and stopping rule)
+ * with bounds carried across iterations (Hamerly's form of Elkan's
+ * triangle-inequality filtering; not in the paper, an exact accelerator of the
+ * Sec. 1 assignment step).  Every row keeps an upper bound of the distance to
+ * its center and a lower bound of the distance to every other center, set by
+ * the assignment that decided it (rounded outward from that pass's rigorous
+ * error bound or from the exact re-check).  After each update the centers'
+ * drifts (FP64 norms of the moves, rounded up) loosen the bounds by the
+ * triangle inequality; a row whose upper bound stays strictly below its lower
+ * bound keeps its label without its data being read.  The other rows go
+ * through the certificate of kmx_lloyd_routed (the router's proposals when r
+ * is given, else the previous label) and then the GEMM cascade of `prec`.
+ * The first assignment runs the GEMM on every row.
+ *   gemm_rows host, nullable, max_iter + 1 entries: rows of each assignment
+ *             that went through the GEMM.
+ *   kept_rows host, nullable, max_iter + 1 entries: rows of each assignment
+ *             the bounds kept (0 for the first).
+ * Requirements as kmx_lloyd_routed (k <= 4096, d <= 1024). */
+kmx_status kmx_lloyd_bounded(kmx_ctx* ctx, kmx_router* r, const float* X, int64_t n, int32_t d,
+                             int64_t ldx, const float* w, float* C_inout, int32_t k,
+                             int32_t max_iter, double tol, kmx_prec prec, int32_t* label_out,
+                             double* cost_hist, int32_t* iters_done, int64_t* gemm_rows,
+                             int64_t* kept_rows);
 
 #ifdef __cplusplus
 }

@@ -54,6 +54,7 @@ inline kmx_status grow(kmx_ctx* ctx, Buf& b, size_t bytes) {
   }
   b.p = p;
   b.bytes = bytes;
+  ctx->ws_gen++;   // captured graphs that used the old buffer are stale
   return KMX_OK;
 }
 
@@ -100,6 +101,22 @@ struct Timed {
   }
 };
 
+// Owners of a graph, its executable and an event: released on every return.
+struct GraphGuard {
+  hipGraph_t g = nullptr;
+  hipGraphExec_t e = nullptr;
+  ~GraphGuard() {
+    if (e) (void)hipGraphExecDestroy(e);
+    if (g) (void)hipGraphDestroy(g);
+  }
+};
+struct EventGuard {
+  hipEvent_t e = nullptr;
+  ~EventGuard() {
+    if (e) (void)hipEventDestroy(e);
+  }
+};
+
 inline kmx_status set_device(kmx_ctx* ctx) {
   KMX_HIP(ctx, hipSetDevice(ctx->device));
   return KMX_OK;
@@ -123,10 +140,11 @@ kmx_status write_state(kmx_ctx* ctx, int max_iter, double tol);
 kmx_status run_prep_centers(kmx_ctx* ctx, const float* C, int k, int d, int prec);
 // GEMM assignment over all rows (rows == nullptr) or over the rows listed in
 // rows[0 .. *row_count), then the FP32 pass and the re-check.
+// hub / hlb (nullable): carried bounds written for the rows decided here.
 kmx_status run_assign_gemm(kmx_ctx* ctx, const float* X, int64_t n, int d, int64_t ldx,
                            const float* C, int k, int prec, int32_t* label, float* d1,
                            float* d2, const int* rows, const unsigned long long* row_count,
-                           const int* gate);
+                           const int* gate, float* hub = nullptr, float* hlb = nullptr);
 // run_prep_centers + run_assign_gemm over all rows.
 kmx_status run_assign(kmx_ctx* ctx, const float* X, int64_t n, int d, int64_t ldx, const float* C,
                       int k, int prec, int32_t* label, float* d1, float* d2, const int* gate);

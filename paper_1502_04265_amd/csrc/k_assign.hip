@@ -34,9 +34,13 @@
 // with exact arithmetic except on ties closer than about 1e-13 relative.
 //
 // The FP8 MFMA's internal summation is not IEEE round-to-nearest: its error
-// is bounded here by 2^-10 sum |x~_i c~_ji| per instruction (measured worst
-// case on adversarial inputs: 2^-12.6 of that sum), on top of the FP32
-// rounding of each accumulation step.
+// is bounded here per instruction by 2^-10 sum |x~_i c~_ji| (the products'
+// own summation; worst case measured on adversarial inputs 2^-12.0 of that
+// sum) plus 2^-19 (|acc in| + sum |x~_i c~_ji|) (the alignment of the
+// products to a large accumulator: up to 13.5 units in the last place of it
+// measured, 16 allowed), on top of the FP32 rounding of each step.  No
+// published accumulation rule of the instruction backs these constants;
+// kmx_mfma_probe lets a test check them on the device at hand.
 //
 // Layout.  MFMA 16x16x32 BF16, 16x16x128 FP8 or 16x16x4 FP32: A = 16 centers
 // x K (from LDS), B = K x 16 points (registers, loaded once per block of
@@ -69,6 +73,71 @@ __device__ __forceinline__ f32x4_t mfma_f8_scaled(int sel, const i32x8_t& a, con
     case 2: return mfma_f8_sel<2>(a, b, c, sa, sb);
     default: return mfma_f8_sel<3>(a, b, c, sa, sb);
   }
+}
+
+// Measurement of the matrix instructions exactly as the assignment issues
+// them, from start values C (zero when C == nullptr): instance q computes
+// D_q = C_q + A_q B_q^T, D_q and C_q 16 x 16 FP32, D[i][j] = row i of A_q with
+// row j of B_q, one wave per instance, lane l holding rows l % 16 of both
+// operands at the same K positions (the assignment's layout):
+//   prec 2: scaled FP8 E4M3 16x16x128, A_q, B_q 16 x 128 bytes, E8M0 scale
+//           sa[q] for every row of A_q and sb[16 q + j] for row j of B_q;
+//   prec 1: BF16 16x16x32, A_q, B_q 16 x 32 BF16 values;
+//   prec 0: FP32 16x16x4, A_q, B_q 16 x 4 floats.
+template <int PREC>
+__global__ __launch_bounds__(64) void mfma_probe_kernel(const uint8_t* __restrict__ A,
+                                                        const uint8_t* __restrict__ B,
+                                                        const uint8_t* __restrict__ sa,
+                                                        const uint8_t* __restrict__ sb,
+                                                        const float* __restrict__ C,
+                                                        float* __restrict__ D) {
+  constexpr int ROWB = PREC == 2 ? 128 : (PREC == 1 ? 64 : 16);   // bytes per operand row
+  const int q = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int r = lane & 15, g = lane >> 4;
+  const uint8_t* a = A + (int64_t)q * 16 * ROWB + r * ROWB;
+  const uint8_t* b = B + (int64_t)q * 16 * ROWB + r * ROWB;
+  f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
+  if (C) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc[i] = C[(int64_t)q * 256 + (4 * g + i) * 16 + r];
+  }
+  if constexpr (PREC == 2) {
+    i32x8_t av, bv;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      av[i] = ((const int*)(a + g * 32))[i];
+      bv[i] = ((const int*)(b + g * 32))[i];
+    }
+    acc = mfma_f8_sel<0>(av, bv, acc, (int)sa[q], (int)sb[q * 16 + r]);
+  } else if constexpr (PREC == 1) {
+    const u32x4_t av = *(const u32x4_t*)(a + g * 16);
+    const u32x4_t bv = *(const u32x4_t*)(b + g * 16);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, av),
+                                                  __builtin_bit_cast(bf16x8_t, bv), acc, 0, 0, 0);
+  } else {
+    const float av = ((const float*)a)[g];
+    const float bv = ((const float*)b)[g];
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
+  }
+  // lane l holds column (B row) l % 16 and rows (A rows) 4 (l / 16) + i
+#pragma unroll
+  for (int i = 0; i < 4; ++i) D[(int64_t)q * 256 + (4 * g + i) * 16 + r] = acc[i];
+}
+
+hipError_t launch_mfma_probe(hipStream_t s, int prec, const uint8_t* A, const uint8_t* B,
+                             const uint8_t* sa, const uint8_t* sb, const float* C, float* D,
+                             int count) {
+  if (prec == KMX_FP8E4M3)
+    hipLaunchKernelGGL(mfma_probe_kernel<2>, dim3((unsigned)count), dim3(64), 0, s, A, B, sa, sb,
+                       C, D);
+  else if (prec == KMX_BF16)
+    hipLaunchKernelGGL(mfma_probe_kernel<1>, dim3((unsigned)count), dim3(64), 0, s, A, B, sa, sb,
+                       C, D);
+  else
+    hipLaunchKernelGGL(mfma_probe_kernel<0>, dim3((unsigned)count), dim3(64), 0, s, A, B, sa, sb,
+                       C, D);
+  return hipGetLastError();
 }
 
 __device__ __forceinline__ unsigned med3u(unsigned a, unsigned b, unsigned c) {
@@ -125,6 +194,12 @@ struct AssignArgs {
   int* brute;
   LoopState* st;
   int count_undecided;
+  // carried bounds (nullable): upper bound of ||x - c_label|| and lower bound
+  // of every other center's distance, written for the rows this pass decides
+  // (for listed rows the lower bound covers the centers not listed; the
+  // re-check completes both)
+  float* hub;
+  float* hlb;
 };
 
 template <int MODE, int NKU, int NCG, int BN, int WAVES>
@@ -532,10 +607,13 @@ __device__ __forceinline__ void assign_block(const AssignArgs& A, int64_t blk,
                 ldexpf(2.0f * Og, A.ib - 23);
           } else {
             // NKU accumulation steps of FP32 rounding, the FP8 instruction's
-            // internal summation (2^-10 sum |x~ c~|), the rounding of O - h_j
+            // internal summation (2^-10 sum |x~ c~|) and its alignment to the
+            // accumulator (2^-19 of |acc in| + sum |x~ c~|, |acc in| <= 2 O), the
+            // rounding of O - h_j
             const float gk = (float)NKU * ua;
-            E = (9.765625e-4f + gk) * rw.nxq * cqm + gk * Og + rw.rx * cqm + rw.nx * rcm +
-                u * Og + ldexpf(2.0f * Og, A.ib - 23);
+            const float ga = (float)NKU * 1.9073486e-6f;   // NKU * 2^-19
+            E = (9.765625e-4f + gk + ga) * rw.nxq * cqm + (gk + 2.0f * ga) * Og + rw.rx * cqm +
+                rw.nx * rcm + u * Og + ldexpf(2.0f * Og, A.ib - 23);
           }
           t1 = __uint_as_float(v1[cg] & hi);
           i1 = (v1[cg] & hi) ? min((int)(mask - (v1[cg] & mask)), A.k - 1) : 0;
@@ -567,6 +645,13 @@ __device__ __forceinline__ void assign_block(const AssignArgs& A, int64_t blk,
         E *= 1.0001f;
         A.label[r] = A.koff + i1;
         if (A.d1o) A.d1o[r] = fmaxf(rw.xn2 - 2.0f * (t1 - off), 0.0f);
+        // squared distance = ||x||^2 - 2 (true score - off); every true score
+        // lies within E of its computed (truncated) key; ||x||^2 itself is an
+        // FP32 rounding (relative 2^-24)
+        const double xhi = (double)rw.xn2 * (1.0 + 0x1p-23), xlo = (double)rw.xn2 * (1.0 - 0x1p-23);
+        auto lb_of = [&](float tn) {   // every center whose computed key is <= tn
+          return dist_down(xlo - 2.0 * ((double)tn + (double)E - (double)off));
+        };
         if (has2) {
           if (A.d2o) A.d2o[r] = fmaxf(rw.xn2 - 2.0f * (t2 - off), 0.0f);
           flagged = (t1 - t2) <= 2.0f * E;
@@ -583,8 +668,33 @@ __device__ __forceinline__ void assign_block(const AssignArgs& A, int64_t blk,
               full = true;
             }
           }
-        } else if (A.d2o) {
-          A.d2o[r] = __builtin_inff();
+          if (A.hub && !full) {
+            if (!flagged) {
+              // decided here: the label's distance and every other center's
+              A.hub[r] = dist_up(xhi - 2.0 * ((double)t1 - (double)E - (double)off));
+              A.hlb[r] = lb_of(t2);
+            } else {
+              // listed: the re-check sets the upper bound and completes the
+              // lower bound with the listed runner-up; here the centers not
+              // listed (below the next kept key, or a lane-wise third best
+              // that dropped further keys)
+              bool hasn = cand3 >= 0 ? has4 : has3;
+              float tn = cand3 >= 0 ? t4 : t3;
+              if (T3 && (w3[cg] & ~mask)) {
+                const float tw = __uint_as_float(w3[cg] & ~mask);
+                tn = hasn ? fmaxf(tn, tw) : tw;
+                hasn = true;
+              }
+              A.hub[r] = __builtin_inff();
+              A.hlb[r] = hasn ? lb_of(tn) : __builtin_inff();
+            }
+          }
+        } else {
+          if (A.d2o) A.d2o[r] = __builtin_inff();
+          if (A.hub) {   // a single center
+            A.hub[r] = dist_up(xhi - 2.0 * ((double)t1 - (double)E - (double)off));
+            A.hlb[r] = __builtin_inff();
+          }
         }
       }
       // cascade_all: every undecided row goes to the next GEMM pass
@@ -727,7 +837,7 @@ static hipError_t run_assign(hipStream_t s, const void* Xsrc, int64_t xs, int ve
                              int ib, const CenterStats* cs, int32_t* label, float* d1, float* d2,
                              FlagEntry* flags, int* full_rows, unsigned long long* full_ctr,
                              int cascade_all, int* brute, LoopState* st, const int* gate,
-                             int num_cus) {
+                             int num_cus, float* hub, float* hlb) {
   if (kpad % BN != 0) return hipErrorInvalidValue;   // center padding must match the tile
   AssignArgs A;
   A.Xsrc = Xsrc;
@@ -757,6 +867,8 @@ static hipError_t run_assign(hipStream_t s, const void* Xsrc, int64_t xs, int ve
   A.brute = brute;
   A.st = st;
   A.count_undecided = rows == nullptr;
+  A.hub = hub;
+  A.hlb = hlb;
   const int64_t ppb = (int64_t)WAVES * 16 * NCG;
   int64_t blocks = (n + ppb - 1) / ppb;
   if (rows) {
@@ -775,7 +887,7 @@ hipError_t launch_assign(hipStream_t s, int prec, const float* X, int64_t ldx, c
                          const void* Cq, const float* ch, int k, int kpad, const CenterStats* cs,
                          int32_t* label, float* d1, float* d2, FlagEntry* flags, int* full_rows,
                          unsigned long long* full_ctr, int cascade_all, int* brute, LoopState* st,
-                         const int* gate, int num_cus) {
+                         const int* gate, int num_cus, float* hub, float* hlb) {
   int ib = 1;
   while ((1 << ib) < kpad) ++ib;
   const int nku = units_for(prec, d);
@@ -783,7 +895,7 @@ hipError_t launch_assign(hipStream_t s, int prec, const float* X, int64_t ldx, c
 #define KMX_A(NKU_, NCG_, BN_, W_, EP_)                                                          \
   return run_assign<1, NKU_, NCG_, BN_, W_, 1, EP_>(s, Xq, dp, 1, nullptr, n, rows, row_count, d, dp, rs, \
                                             Cq, ch, k, kpad, ib, cs, label, d1, d2, flags,      \
-                                            full_rows, full_ctr, cascade_all, brute, st, gate, num_cus)
+                                            full_rows, full_ctr, cascade_all, brute, st, gate, num_cus, hub, hlb)
     switch (nku) {
       case 1: KMX_A(1, 4, 64, 8, false);
       case 2: KMX_A(2, 4, 64, 8, false);
@@ -804,7 +916,7 @@ hipError_t launch_assign(hipStream_t s, int prec, const float* X, int64_t ldx, c
 #define KMX_A(NKU_, NCG_, BN_, W_, EP_, SUB_)                                                \
   return run_assign<2, NKU_, NCG_, BN_, W_, 1, EP_, SUB_>(s, Xq, dp, 1, sx8, n, rows, row_count, d, dp, rs, \
                                             Cq, ch, k, kpad, ib, cs, label, d1, d2, flags,  \
-                                            full_rows, full_ctr, cascade_all, brute, st, gate, num_cus)
+                                            full_rows, full_ctr, cascade_all, brute, st, gate, num_cus, hub, hlb)
     switch (nku) {
       case 1: KMX_A(1, 4, 64, 8, true, 1);
       case 2: KMX_A(2, 4, 64, 8, false, 1);
@@ -823,7 +935,7 @@ hipError_t launch_assign(hipStream_t s, int prec, const float* X, int64_t ldx, c
 #define KMX_A(NKU_, NCG_, BN_, W_)                                                               \
   return run_assign<0, NKU_, NCG_, BN_, W_>(s, X, ldx, vec_ok, nullptr, n, rows, row_count, d, \
                                             dp, rs, Cq, ch, k, kpad, ib, cs, label, d1, d2,     \
-                                            flags, full_rows, full_ctr, cascade_all, brute, st, gate, num_cus)
+                                            flags, full_rows, full_ctr, cascade_all, brute, st, gate, num_cus, hub, hlb)
   switch (nku) {
     case 1: KMX_A(1, 4, 64, 8);
     case 2: KMX_A(2, 4, 64, 8);
@@ -937,6 +1049,8 @@ __device__ __forceinline__ void batched_block(const BatchInst& I, int blk,
   A.brute = brute;
   A.st = st;
   A.count_undecided = 1;
+  A.hub = nullptr;
+  A.hlb = nullptr;
   assign_block<1, NKU, NCG, BN, kBatchWaves, 1, false, 1>(A, blk, lds, hsh, wcnt, wbase);
 }
 

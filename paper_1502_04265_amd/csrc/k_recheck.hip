@@ -83,12 +83,30 @@ __device__ __forceinline__ void plain_dist3(const float* __restrict__ x,
   p2 = a2;
 }
 
+// Carried bounds of a re-checked row (when kept): the upper bound of the
+// winner's distance and the lower bound of every other center's, from the
+// plain distances (relative error below tol each, taken twice); the lower
+// bound the listing pass stored for the centers not listed is kept when
+// smaller.
+__device__ __forceinline__ void pair_bounds(float* __restrict__ hub, float* __restrict__ hlb,
+                                            int row, const float* p, const int* cj, int nc,
+                                            int best, float tol) {
+  const double t2 = 2.0 * (double)tol;
+  double ub2 = 0.0, ru2 = 1e308;
+  for (int q = 0; q < nc; ++q) {
+    if (cj[q] == best) ub2 = (double)p[q];
+    else ru2 = fmin(ru2, (double)p[q]);
+  }
+  hub[row] = dist_up(ub2 * (1.0 + t2));
+  hlb[row] = fminf(hlb[row], dist_down(ru2 * (1.0 - t2)));
+}
+
 template <int G>
 __global__ __launch_bounds__(256) void recheck_pair_kernel(
     const float* __restrict__ X, int64_t n, int d, int64_t ldx, const float* __restrict__ C,
     int k, int32_t* __restrict__ label, float* __restrict__ d1o,
     const FlagEntry* __restrict__ flags, const LoopState* __restrict__ st,
-    const int* __restrict__ gate) {
+    const int* __restrict__ gate, float* __restrict__ hub, float* __restrict__ hlb) {
   if (gate && *gate) return;
   constexpr int SPW = 64 / G;          // entries per wave at once
   const int64_t cnt = (int64_t)st->flagged;
@@ -146,6 +164,7 @@ __global__ __launch_bounds__(256) void recheck_pair_kernel(
     if (gl == 0) {
       label[row] = best;
       if (d1o) d1o[row] = bd;
+      if (hub) pair_bounds(hub, hlb, row, p, cj, nc, best, tol);
     }
   }
 }
@@ -212,7 +231,7 @@ __global__ __launch_bounds__(256) void recheck_pair_pipe_kernel(
     const float* __restrict__ X, int64_t n, int d, int64_t ldx, const float* __restrict__ C,
     int k, int32_t* __restrict__ label, float* __restrict__ d1o,
     const FlagEntry* __restrict__ flags, const LoopState* __restrict__ st,
-    const int* __restrict__ gate) {
+    const int* __restrict__ gate, float* __restrict__ hub, float* __restrict__ hlb) {
   if (gate && *gate) return;
   constexpr int SPW = 64 / G;          // entries per wave at once
   const int64_t cnt = (int64_t)st->flagged;
@@ -272,6 +291,7 @@ __global__ __launch_bounds__(256) void recheck_pair_pipe_kernel(
       if (gl == 0) {
         label[row] = best;
         if (d1o) d1o[row] = bd;
+        if (hub) pair_bounds(hub, hlb, row, p, cj, nc, best, tol);
       }
     }
     fe_c = fe_n;
@@ -337,9 +357,11 @@ __device__ __forceinline__ void plain_dist4(const float* __restrict__ x,
 __global__ __launch_bounds__(kFullWaves * 64) void recheck_full_kernel(
     const float* __restrict__ X, int64_t n, int d, int64_t ldx, const float* __restrict__ C,
     int k, int32_t* __restrict__ label, float* __restrict__ d1o, const int* __restrict__ brute,
-    const LoopState* __restrict__ st, const int* __restrict__ gate) {
+    const LoopState* __restrict__ st, const int* __restrict__ gate, float* __restrict__ hub,
+    float* __restrict__ hlb) {
   if (gate && *gate) return;
-  __shared__ float redf[kFullWaves];
+  __shared__ float redf[kFullWaves], redf2[kFullWaves];
+  __shared__ int redfj[kFullWaves];
   __shared__ float redh[kFullWaves], redl[kFullWaves];
   __shared__ int redj[kFullWaves];
   const int64_t cnt = (int64_t)st->flagged_full;
@@ -351,16 +373,28 @@ __global__ __launch_bounds__(kFullWaves * 64) void recheck_full_kernel(
     const int row = brute[e];
     if (row < 0 || row >= n) continue;   // uniform across the block
     const float* x = X + (int64_t)row * ldx;
-    float m = __builtin_inff();
+    // pass 1: the smallest plain distance m (center jm) and the second
+    // smallest m2 (for the carried lower bound)
+    float m = __builtin_inff(), m2 = __builtin_inff();
+    int jm = 0x7FFFFFFF;
     for (int j0 = 4 * wv; j0 < k; j0 += 4 * kFullWaves) {
       float p[4];
       plain_dist4(x, C, j0, k, d, lane, vec, p);
-      m = fminf(m, fminf(fminf(p[0], p[1]), fminf(p[2], p[3])));
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        if (p[t] < m) { m2 = m; m = p[t]; jm = j0 + t; }
+        else m2 = fminf(m2, p[t]);
+      }
     }
-    if (lane == 0) redf[wv] = m;
+    if (lane == 0) { redf[wv] = m; redf2[wv] = m2; redfj[wv] = jm; }
     __syncthreads();
     m = redf[0];
-    for (int w = 1; w < kFullWaves; ++w) m = fminf(m, redf[w]);
+    m2 = redf2[0];
+    jm = redfj[0];
+    for (int w = 1; w < kFullWaves; ++w) {
+      if (redf[w] < m) { m2 = fminf(m, redf2[w]); m = redf[w]; jm = redfj[w]; }
+      else m2 = fminf(m2, fminf(redf[w], redf2[w]));
+    }
     const float thr = m * (1.0f + gam) / (1.0f - gam) * 1.0001f + 1e-30f;
     float bh = __builtin_inff(), bl = 0.f;
     int best = 0x7FFFFFFF;
@@ -389,6 +423,14 @@ __global__ __launch_bounds__(kFullWaves * 64) void recheck_full_kernel(
       if (best < k) {
         label[row] = best;
         if (d1o) d1o[row] = bh;
+        if (hub) {
+          // the winner's exact distance; every other center's plain
+          // distance is at least m2, or m when the plain minimum is not the
+          // winner
+          const double g2 = 2.0 * (double)gam;
+          hub[row] = dist_up((double)bh + (double)bl + fabs((double)bh) * 0x1p-40);
+          hlb[row] = dist_down((double)(jm == best ? m2 : m) * (1.0 - g2));
+        }
       }
     }
     __syncthreads();
@@ -430,7 +472,7 @@ hipError_t launch_route_small(hipStream_t s, unsigned long long* ctr, const int*
 hipError_t launch_recheck(hipStream_t s, const float* X, int64_t n, int d, int64_t ldx,
                           const float* C, int k, int32_t* label, float* d1,
                           const FlagEntry* flags, const int* brute, const LoopState* st,
-                          int num_cus, const int* gate) {
+                          int num_cus, const int* gate, float* hub, float* hlb) {
   int64_t blocks = (n + 3) / 4;
   int64_t cap = (int64_t)num_cus * 8;
   if (blocks > cap) blocks = cap;
@@ -441,19 +483,19 @@ hipError_t launch_recheck(hipStream_t s, const float* X, int64_t n, int d, int64
                    ((((uintptr_t)C) & 15) == 0) && (d % 4 == 0);
   if (kRecheckPipe && vec && d <= 64)
     hipLaunchKernelGGL((recheck_pair_pipe_kernel<16, 1>), dim3((unsigned)blocks), dim3(256), 0, s,
-                       X, n, d, ldx, C, k, label, d1, flags, st, gate);
+                       X, n, d, ldx, C, k, label, d1, flags, st, gate, hub, hlb);
   else if (kRecheckPipe && vec && d <= 128)
     hipLaunchKernelGGL((recheck_pair_pipe_kernel<16, 2>), dim3((unsigned)blocks), dim3(256), 0, s,
-                       X, n, d, ldx, C, k, label, d1, flags, st, gate);
+                       X, n, d, ldx, C, k, label, d1, flags, st, gate, hub, hlb);
   else if (d <= 256)
     hipLaunchKernelGGL(recheck_pair_kernel<16>, dim3((unsigned)blocks), dim3(256), 0, s, X, n,
-                       d, ldx, C, k, label, d1, flags, st, gate);
+                       d, ldx, C, k, label, d1, flags, st, gate, hub, hlb);
   else if (d <= 1024)
     hipLaunchKernelGGL(recheck_pair_kernel<32>, dim3((unsigned)blocks), dim3(256), 0, s, X, n,
-                       d, ldx, C, k, label, d1, flags, st, gate);
+                       d, ldx, C, k, label, d1, flags, st, gate, hub, hlb);
   else
     hipLaunchKernelGGL(recheck_pair_kernel<64>, dim3((unsigned)blocks), dim3(256), 0, s, X, n,
-                       d, ldx, C, k, label, d1, flags, st, gate);
+                       d, ldx, C, k, label, d1, flags, st, gate, hub, hlb);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   cap = (int64_t)num_cus * 4;
@@ -461,7 +503,7 @@ hipError_t launch_recheck(hipStream_t s, const float* X, int64_t n, int d, int64
   if (blocks > cap) blocks = cap;
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(recheck_full_kernel, dim3((unsigned)blocks), dim3(kFullWaves * 64), 0, s, X, n, d, ldx,
-                     C, k, label, d1, brute, st, gate);
+                     C, k, label, d1, brute, st, gate, hub, hlb);
   return hipGetLastError();
 }
 

@@ -483,8 +483,12 @@ __global__ __launch_bounds__(256) void router_cert_kernel(
     int k, const RowStats* __restrict__ rs, const uint32_t* __restrict__ keys, int ib,
     const int32_t* __restrict__ nbr, const float* __restrict__ nbd, int32_t* __restrict__ label,
     FlagEntry* __restrict__ flags, int* __restrict__ fb_rows, LoopState* __restrict__ st,
-    const int* __restrict__ gate) {
+    const int* __restrict__ gate, const int* __restrict__ rows,
+    const unsigned long long* __restrict__ row_count, float* __restrict__ hub,
+    float* __restrict__ hlb) {
   if (gate && *gate) return;
+  // rows != nullptr: the points are rows[0 .. *row_count) instead of 0 .. n
+  const int64_t npts = rows ? (int64_t)(*row_count) : n;
   constexpr int RPW = 256;
   constexpr int RPB = 4 * RPW;
   __shared__ unsigned char kind[RPB];  // 0 certified, 1 certified + re-check, 2 GEMM, 3 none
@@ -496,7 +500,8 @@ __global__ __launch_bounds__(256) void router_cert_kernel(
   const unsigned mask = (1u << ib) - 1u;
   const float u = 5.9604645e-8f;
   const float gam = (float)(d + 16) * u;
-  const int64_t nchunks = (n + RPB - 1) / RPB;
+  const int64_t nchunks = (npts + RPB - 1) / RPB;
+  auto row_of = [&](int64_t i) -> int64_t { return rows ? (int64_t)rows[i] : i; };
   const unsigned long long below = (1ull << lane) - 1ull;
 
   for (int64_t chk = blockIdx.x; chk < nchunks; chk += gridDim.x) {
@@ -506,15 +511,16 @@ __global__ __launch_bounds__(256) void router_cert_kernel(
     // selected center (its row, neighbour bounds and ids) is issued together
     // with the point's own row: one memory round trip per pass.
     auto fetch_sel = [&](int pass) -> unsigned {
-      const int64_t rr = r0 + pass * 4 + sub;
-      if (rr >= n) return 0u;
+      const int64_t ri = r0 + pass * 4 + sub;
+      if (ri >= npts) return 0u;
+      const int64_t rr = row_of(ri);
       return ROUTED ? keys[rr * kRouterM + q] : (unsigned)label[rr];
     };
     unsigned sel_next = fetch_sel(0);
     for (int pass = 0; pass < RPW / 4; ++pass) {
       const int slot = pass * 4 + sub;
-      const int64_t r = r0 + slot;
-      const bool valid = r < n;
+      const bool valid = r0 + slot < npts;
+      const int64_t r = valid ? row_of(r0 + slot) : 0;
       const unsigned sel = sel_next;
       if (pass + 1 < RPW / 4) sel_next = fetch_sel(pass + 1);
       int b0 = 0, cand = -1;
@@ -603,12 +609,20 @@ __global__ __launch_bounds__(256) void router_cert_kernel(
       else if (!ok || exhausted || m > 2) kd = 2;
       else if (m == 0) kd = 0;
       else kd = (has0 && (m < 2 || has1)) ? 1 : 2;
+      // carried bounds: certified rows get ||x - c_b|| <= dub and, for every
+      // center outside the first m neighbours, ||x - c|| >= nd[m] - dub (the
+      // short re-check completes a listed row's bounds)
+      const float ndm = __shfl(nd0, (lane & 48) + (m < 16 ? m : 0), 64);
       if (q == 0) {
         const int rec = wave * RPW + slot;
         kind[rec] = (unsigned char)kd;
         rn0[rec] = n0;
         rn1[rec] = (m == 2) ? n1 : -1;
         if (kd <= 1) label[r] = b0;
+        if (hub && kd <= 1) {
+          hub[r] = kd == 0 ? dub : __builtin_inff();
+          hlb[r] = f64_to_f32_down((double)ndm - (double)dub);
+        }
       }
     }
     __syncthreads();
@@ -647,7 +661,7 @@ __global__ __launch_bounds__(256) void router_cert_kernel(
       const int kd = kind[rec];
       const unsigned long long bf = __ballot(kd == 1);
       const unsigned long long bb = __ballot(kd == 2);
-      const int row = (int)(r0 + i0 + lane);
+      const int row = (kd == 1 || kd == 2) ? (int)row_of(r0 + i0 + lane) : 0;
       if (kd == 1) {
         FlagEntry fe;
         fe.row = row;
@@ -668,7 +682,8 @@ hipError_t launch_router_cert(hipStream_t s, const uint16_t* Xq, int64_t dp, int
                               const float* C, int k, const RowStats* rs, const uint32_t* keys,
                               int kpad, const int32_t* nbr, const float* nbd, int32_t* label,
                               FlagEntry* flags, int* fb_rows, LoopState* st, const int* gate,
-                              int num_cus) {
+                              int num_cus, const int* rows, const unsigned long long* row_count,
+                              float* hub, float* hlb) {
   int ib = 1;
   while ((1 << ib) < kpad) ++ib;
   // one 1024-row chunk per workgroup up to 32 per CU
@@ -686,7 +701,7 @@ hipError_t launch_router_cert(hipStream_t s, const uint16_t* Xq, int64_t dp, int
 #define KMX_C(R_, NX_, F_)                                                                    \
   hipLaunchKernelGGL((router_cert_kernel<R_, NX_, F_>), dim3((unsigned)blocks), dim3(256), 0, \
                      s, Xq, dp, n, d, C, k, rs, keys, ib, nbr, nbd, label, flags, fb_rows, st, \
-                     gate)
+                     gate, rows, row_count, hub, hlb)
 #define KMX_CN(R_)                                                 \
   switch (nx) {                                                    \
     case 1: if (full) KMX_C(R_, 1, true); else KMX_C(R_, 1, false); break; \

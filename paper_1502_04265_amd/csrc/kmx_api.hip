@@ -216,7 +216,7 @@ kmx_status run_prep_centers(kmx_ctx* ctx, const float* C, int k, int d, int prec
 kmx_status run_assign_gemm(kmx_ctx* ctx, const float* X, int64_t n, int d, int64_t ldx,
                            const float* C, int k, int prec, int32_t* label, float* d1,
                            float* d2, const int* rows, const unsigned long long* row_count,
-                           const int* gate) {
+                           const int* gate, float* hub, float* hlb) {
   LoopState* st = ST(ctx);
   CenterStats* cs = P<CenterStats>(ctx->cstats);
   CenterStats* cs32 = P<CenterStats>(ctx->cstats32);
@@ -233,7 +233,7 @@ kmx_status run_assign_gemm(kmx_ctx* ctx, const float* X, int64_t n, int d, int64
     KMX_HIP(ctx, launch_assign(ctx->stream, KMX_FP32, X, ldx, nullptr, nullptr, n, rows,
                                row_count, d, dp32, rs, ctx->cq32.p, P<float>(ctx->ch32), k,
                                kpad32, cs32, label, d1, d2, flags, nullptr, nullptr, 0, brute,
-                               st, gate, ctx->num_cus));
+                               st, gate, ctx->num_cus, hub, hlb));
   } else {
     const int dp = assign_dpad(KMX_BF16, d);
     const int bn = assign_tile_n(KMX_BF16, d, k);
@@ -252,7 +252,7 @@ kmx_status run_assign_gemm(kmx_ctx* ctx, const float* X, int64_t n, int d, int64
                                  P<uint8_t>(ctx->sx8), n, rows, row_count, d, dp8,
                                  P<RowStats>(ctx->rowstats8), ctx->cq8.p, P<float>(ctx->ch8), k,
                                  kpad8, cs8, label, d1, d2, flags, P<int>(ctx->full_rows),
-                                 &st->full_count, 0, brute, st, gate, ctx->num_cus));
+                                 &st->full_count, 0, brute, st, gate, ctx->num_cus, hub, hlb));
       rows16 = P<int>(ctx->full_rows);
       cnt16 = &st->full_count;
       next16 = P<int>(ctx->full_rows2);
@@ -263,7 +263,8 @@ kmx_status run_assign_gemm(kmx_ctx* ctx, const float* X, int64_t n, int d, int64
       KMX_HIP(ctx, launch_assign(ctx->stream, KMX_BF16, X, ldx, ctx->xq.p, nullptr, n, rows16,
                                  cnt16, d, dp, rs, ctx->cq.p, P<float>(ctx->ch), k, kpad, cs,
                                  label, d1, d2,
-                                 flags, next16, ctr16, 0, brute, st, gate, ctx->num_cus));
+                                 flags, next16, ctr16, 0, brute, st, gate, ctx->num_cus, hub,
+                                 hlb));
     }
     {
       Timed tm(ctx, T_RECHECK);
@@ -271,13 +272,13 @@ kmx_status run_assign_gemm(kmx_ctx* ctx, const float* X, int64_t n, int d, int64
       KMX_HIP(ctx, launch_assign(ctx->stream, KMX_FP32, X, ldx, nullptr, nullptr, n, next16,
                                  ctr16, d, dp32, rs, ctx->cq32.p, P<float>(ctx->ch32), k, kpad32,
                                  cs32, label, d1, d2, flags, nullptr, nullptr, 0, brute, st, gate,
-                                 ctx->num_cus));
+                                 ctx->num_cus, hub, hlb));
     }
   }
   {
     Timed tm(ctx, T_RECHECK);
     KMX_HIP(ctx, launch_recheck(ctx->stream, X, n, d, ldx, C, k, label, d1, flags, brute, st,
-                                ctx->num_cus, gate));
+                                ctx->num_cus, gate, hub, hlb));
   }
   return KMX_OK;
 }
@@ -378,7 +379,9 @@ kmx_status kmx_destroy(kmx_ctx* ctx) {
       &ctx->ch,        &ctx->cstats,   &ctx->lab_a,      &ctx->lab_prev,   &ctx->d1,
       &ctx->d2,        &ctx->flags,    &ctx->counters,   &ctx->counts,     &ctx->segsum,
       &ctx->base,      &ctx->chunk_base, &ctx->perm,     &ctx->partS,      &ctx->partQ,
-      &ctx->partW,     &ctx->W,        &ctx->termC,      &ctx->termMu,     &ctx->state,     &ctx->vcheck,
+      &ctx->partW,     &ctx->W,        &ctx->termC,      &ctx->termMu,     &ctx->state,     &ctx->vcheck,    &ctx->hub,
+      &ctx->hlb,       &ctx->bl_rows,  &ctx->cprev,      &ctx->drift,      &ctx->dstat,
+      &ctx->bkh,
       &ctx->D2,        &ctx->chosen,   &ctx->seed_part,  &ctx->seed_ctr,   &ctx->scratch_c,
       &ctx->seed_a,    &ctx->seed_cc,  &ctx->seed_nread,
       &ctx->hist,      &ctx->fb_rows,  &ctx->keys,       &ctx->cdist,      &ctx->nbr,
@@ -390,6 +393,9 @@ kmx_status kmx_destroy(kmx_ctx* ctx) {
       &ctx->btermC,    &ctx->btermMu,  &ctx->bW,         &ctx->bcost};
   for (kmx::Buf* b : bufs)
     if (b->p) (void)hipFree(b->p);
+  if (ctx->lg_exec) (void)hipGraphExecDestroy(ctx->lg_exec);
+  if (ctx->lg_graph) (void)hipGraphDestroy(ctx->lg_graph);
+  if (ctx->lg_event) (void)hipEventDestroy(ctx->lg_event);
   if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   for (auto& r : ctx->recs) {
     (void)hipEventDestroy(r.a);
@@ -566,43 +572,57 @@ static kmx_status lloyd_impl(kmx_ctx* ctx, const float* X, int64_t n, int32_t d,
     if (!ctx->cap_stream)
       KMX_HIP(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
     hipStream_t cs = ctx->cap_stream;
-    hipEvent_t ev = nullptr;
-    KMX_HIP(ctx, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-    KMX_HIP(ctx, hipEventRecord(ev, ctx->stream));
-    KMX_HIP(ctx, hipStreamWaitEvent(cs, ev, 0));
-    // the iteration's launches go to the capture stream; no event timing inside
-    const hipStream_t saved = ctx->stream;
-    const int saved_timing = ctx->timing;
-    ctx->stream = cs;
-    ctx->timing = 0;
-    hipGraph_t g = nullptr;
-    hipGraphExec_t ge = nullptr;
-    kmx_status ks = KMX_OK;
-    hipError_t he = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-    if (he == hipSuccess) {
-      ks = run_assign(ctx, X, n, d, ldx, C_inout, k, prec, lab, nullptr, nullptr, &st->done);
-      if (ks == KMX_OK)
-        ks = run_update(ctx, X, n, d, ldx, w, lab, k, C_inout, C_inout, nullptr, 1, prev, hist,
-                        0, &st->done);
-      he = hipStreamEndCapture(cs, &g);
+    // the captured iteration depends on these pointers and sizes only (the
+    // loop state is read by its kernels), so it is kept for the next call
+    const uint64_t key[12] = {(uint64_t)(uintptr_t)X, (uint64_t)n, (uint64_t)d, (uint64_t)ldx,
+                              (uint64_t)(uintptr_t)w, (uint64_t)(uintptr_t)C_inout, (uint64_t)k,
+                              (uint64_t)prec, (uint64_t)(uintptr_t)lab, ctx->ws_gen,
+                              (uint64_t)(uintptr_t)cs, 1};
+    if (!ctx->lg_event)
+      KMX_HIP(ctx, hipEventCreateWithFlags(&ctx->lg_event, hipEventDisableTiming));
+    KMX_HIP(ctx, hipEventRecord(ctx->lg_event, ctx->stream));
+    KMX_HIP(ctx, hipStreamWaitEvent(cs, ctx->lg_event, 0));
+    const bool cached = ctx->lg_exec && std::memcmp(key, ctx->lg_key, sizeof(key)) == 0;
+    if (!cached) {
+      if (ctx->lg_exec) (void)hipGraphExecDestroy(ctx->lg_exec);
+      if (ctx->lg_graph) (void)hipGraphDestroy(ctx->lg_graph);
+      ctx->lg_exec = nullptr;
+      ctx->lg_graph = nullptr;
+      // the iteration's launches go to the capture stream; no event timing inside
+      const hipStream_t saved = ctx->stream;
+      const int saved_timing = ctx->timing;
+      ctx->stream = cs;
+      ctx->timing = 0;
+      hipGraph_t g = nullptr;
+      kmx_status ks = KMX_OK;
+      hipError_t he = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+      if (he == hipSuccess) {
+        ks = run_assign(ctx, X, n, d, ldx, C_inout, k, prec, lab, nullptr, nullptr, &st->done);
+        if (ks == KMX_OK)
+          ks = run_update(ctx, X, n, d, ldx, w, lab, k, C_inout, C_inout, nullptr, 1, prev, hist,
+                          0, &st->done);
+        const hipError_t he2 = hipStreamEndCapture(cs, &g);
+        if (he == hipSuccess) he = he2;
+      }
+      ctx->stream = saved;
+      ctx->timing = saved_timing;
+      hipGraphExec_t ge = nullptr;
+      if (he == hipSuccess && ks == KMX_OK) he = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+      if (ks != KMX_OK || he != hipSuccess) {
+        if (ge) (void)hipGraphExecDestroy(ge);
+        if (g) (void)hipGraphDestroy(g);
+        if (ks != KMX_OK) return ks;
+        (void)hipGetLastError();
+        return fail(ctx, KMX_EDEVICE,
+                    std::string("graph of the Lloyd iteration: ") + hipGetErrorString(he));
+      }
+      ctx->lg_graph = g;
+      ctx->lg_exec = ge;
+      std::memcpy(ctx->lg_key, key, sizeof(key));
     }
-    ctx->stream = saved;
-    ctx->timing = saved_timing;
-    if (he == hipSuccess && ks == KMX_OK) he = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
-    for (int t = 0; he == hipSuccess && ks == KMX_OK && t < max_iter; ++t)
-      he = hipGraphLaunch(ge, cs);
-    if (he == hipSuccess && ks == KMX_OK) he = hipEventRecord(ev, cs);
-    if (he == hipSuccess && ks == KMX_OK) he = hipStreamWaitEvent(ctx->stream, ev, 0);
-    if (he == hipSuccess && ks == KMX_OK) he = hipStreamSynchronize(cs);
-    if (ge) (void)hipGraphExecDestroy(ge);
-    if (g) (void)hipGraphDestroy(g);
-    (void)hipEventDestroy(ev);
-    if (ks != KMX_OK) return ks;
-    if (he != hipSuccess) {
-      (void)hipGetLastError();
-      return fail(ctx, KMX_EDEVICE,
-                  std::string("graph of the Lloyd iteration: ") + hipGetErrorString(he));
-    }
+    for (int t = 0; t < max_iter; ++t) KMX_HIP(ctx, hipGraphLaunch(ctx->lg_exec, cs));
+    KMX_HIP(ctx, hipEventRecord(ctx->lg_event, cs));
+    KMX_HIP(ctx, hipStreamWaitEvent(ctx->stream, ctx->lg_event, 0));
   } else {
     for (int t = 0; t < max_iter; ++t) {
       KMX_TRY(run_assign(ctx, X, n, d, ldx, C_inout, k, prec, lab, nullptr, nullptr, &st->done));
@@ -673,6 +693,23 @@ kmx_status kmx_assign_stats(kmx_ctx* ctx, int64_t* listed, int64_t* fp32, int64_
   if (listed) *listed = (int64_t)h.flagged;
   if (fp32) *fp32 = (int64_t)(ctx->last_prec == KMX_FP8E4M3 ? h.full_count2 : h.full_count);
   if (full) *full = (int64_t)h.flagged_full;
+  return KMX_OK;
+}
+
+kmx_status kmx_mfma_probe(kmx_ctx* ctx, kmx_prec prec, const void* A, const void* B,
+                          const uint8_t* scale_a, const uint8_t* scale_b, const float* C, float* D,
+                          int32_t count) {
+  if (!ctx) return KMX_EINVAL;
+  ctx->err.clear();
+  if (prec != KMX_FP32 && prec != KMX_BF16 && prec != KMX_FP8E4M3)
+    return fail(ctx, KMX_EINVAL, "unknown precision");
+  if (!A || !B || !D) return fail(ctx, KMX_EINVAL, "NULL A, B or D");
+  if (prec == KMX_FP8E4M3 && (!scale_a || !scale_b))
+    return fail(ctx, KMX_EINVAL, "the FP8 instruction needs scale_a and scale_b");
+  if (count < 1 || count > (1 << 24)) return fail(ctx, KMX_EINVAL, "count out of range");
+  KMX_TRY(set_device(ctx));
+  KMX_HIP(ctx, launch_mfma_probe(ctx->stream, prec, (const uint8_t*)A, (const uint8_t*)B, scale_a,
+                                 scale_b, C, D, count));
   return KMX_OK;
 }
 

@@ -382,36 +382,30 @@ kmx_status kmx_lloyd_batched(kmx_ctx* ctx, const kmx_problem* probs, int32_t cou
   KMX_TRY(write_state(ctx, iters, -1.0));
   KMX_TRY(ensure_cap_stream(ctx));
   hipStream_t cs = ctx->cap_stream;
-  hipEvent_t ev = nullptr;
-  KMX_HIP(ctx, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-  KMX_HIP(ctx, hipEventRecord(ev, ctx->stream));
-  KMX_HIP(ctx, hipStreamWaitEvent(cs, ev, 0));
+  EventGuard ev;
+  KMX_HIP(ctx, hipEventCreateWithFlags(&ev.e, hipEventDisableTiming));
+  KMX_HIP(ctx, hipEventRecord(ev.e, ctx->stream));
+  KMX_HIP(ctx, hipStreamWaitEvent(cs, ev.e, 0));
   {
     Timed tm(ctx, T_ASSIGN);   // whole batched iterations (timing brackets the replays)
     if (iters > 0) {
-      hipGraph_t graph = nullptr;
-      hipGraphExec_t exec = nullptr;
+      GraphGuard gg;
       KMX_HIP(ctx, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
       const hipError_t ce = enqueue_iteration(ctx, pl, cs, 1, stride);
-      const hipError_t ee = hipStreamEndCapture(cs, &graph);
+      const hipError_t ee = hipStreamEndCapture(cs, &gg.g);
       if (ce != hipSuccess || ee != hipSuccess) {
         (void)hipGetLastError();
-        if (graph) (void)hipGraphDestroy(graph);
-        (void)hipEventDestroy(ev);
         return fail(ctx, KMX_EDEVICE, std::string("capture of the batched iteration failed: ") +
                                           hipGetErrorString(ce != hipSuccess ? ce : ee));
       }
-      KMX_HIP(ctx, hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
-      for (int t = 0; t < iters; ++t) KMX_HIP(ctx, hipGraphLaunch(exec, cs));
+      KMX_HIP(ctx, hipGraphInstantiate(&gg.e, gg.g, nullptr, nullptr, 0));
+      for (int t = 0; t < iters; ++t) KMX_HIP(ctx, hipGraphLaunch(gg.e, cs));
       KMX_HIP(ctx, hipStreamSynchronize(cs));
-      (void)hipGraphExecDestroy(exec);
-      (void)hipGraphDestroy(graph);
     }
     KMX_HIP(ctx, enqueue_iteration(ctx, pl, cs, 0, stride));
-    KMX_HIP(ctx, hipEventRecord(ev, cs));
-    KMX_HIP(ctx, hipStreamWaitEvent(ctx->stream, ev, 0));
+    KMX_HIP(ctx, hipEventRecord(ev.e, cs));
+    KMX_HIP(ctx, hipStreamWaitEvent(ctx->stream, ev.e, 0));
   }
-  (void)hipEventDestroy(ev);
   // outputs
   const int ni = (int)pl.insts.size();
   for (int i = 0; i < ni; ++i) {

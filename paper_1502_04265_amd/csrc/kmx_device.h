@@ -24,6 +24,28 @@ __device__ __forceinline__ float f64_to_f32_up(double x) {
   return f;
 }
 
+// Non-negative double -> float rounded toward zero (a lower bound).
+__device__ __forceinline__ float f64_to_f32_down(double x) {
+  if (!(x > 0.0)) return 0.0f;
+  float f = (float)x;
+  if ((double)f > x) f = __uint_as_float(__float_as_uint(f) - 1u);
+  return f;
+}
+
+// Distance bounds from squared-distance bounds computed in FP64: sqrt of an
+// upper (lower) bound, rounded up (down), with a relative margin of 2^-40 for
+// the FP64 roundings of the bound's own arithmetic.
+__device__ __forceinline__ float dist_up(double s2) {
+  if (!(s2 > 0.0)) return 0.0f;
+  if (!(s2 < 1e300)) return __builtin_inff();
+  return f64_to_f32_up(sqrt(s2 * (1.0 + 0x1p-40)) * (1.0 + 0x1p-40));
+}
+__device__ __forceinline__ float dist_down(double s2) {
+  if (!(s2 > 0.0)) return 0.0f;
+  if (!(s2 < 1e300)) return __builtin_inff();
+  return f64_to_f32_down(sqrt(s2 * (1.0 - 0x1p-40)) * (1.0 - 0x1p-40));
+}
+
 // Butterfly sums over the 64 lanes of a wave.  IEEE addition commutes, so
 // every lane ends with the same bits and the order is fixed.
 __device__ __forceinline__ double wave_sum_f64(double v) {

@@ -55,6 +55,7 @@ struct LoopState {
   unsigned long long full_count2;      // rows the BF16 pass of an FP8 cascade sent to FP32
   unsigned long long routed_fallback;  // rows the certificate sent to the GEMM (last assign)
   unsigned long long routed_listed;    // certified rows that needed the short re-check
+  unsigned long long bound_fail;       // rows the carried bounds could not keep (last assign)
 };
 
 // Entry of the short re-check list: row index and the other candidates (the
@@ -94,6 +95,14 @@ struct BatchInst {
   float* ch;           // per padded center (global numbering): O - h_j, the GEMM start value
 };
 
+// Center drift of one Lloyd step (the bound-carrying assignment): the two
+// largest drifts and the center of the largest.
+struct DriftStat {
+  float max1, max2;
+  int arg1;
+  int pad;
+};
+
 struct BatchItem {
   int inst;
   int blk;             // block of points within the instance
@@ -110,7 +119,7 @@ struct BatchBucket {
 enum TimingClass {
   T_PREP = 0, T_ASSIGN = 1, T_RECHECK = 2, T_SORT = 3, T_REDUCE = 4,
   T_FINAL = 5, T_SEED = 6, T_OTHER = 7, T_ROUTER = 8, T_CERT = 9, T_TRAIN = 10,
-  T_PROJECT = 11, T_NCLASS = 12
+  T_PROJECT = 11, T_BOUND = 12, T_NCLASS = 13
 };
 
 // Grow-only device buffer.
@@ -178,11 +187,18 @@ struct kmx_ctx {
   kmx::Buf D2, chosen, seed_part, seed_ctr, seed_a, seed_cc, seed_nread;
   kmx::Buf scratch_c, hist;
   kmx::Buf fb_rows, keys, cdist, nbr, nbd, fbh;   // routed assignment
+  kmx::Buf hub, hlb, bl_rows, cprev, drift, dstat, bkh;   // carried bounds
   // batched Lloyd: concatenated instances and their descriptors
   kmx::Buf vt;                          // transposed projection basis
   kmx::Buf bX, bXq, brs, bw, bC, bCq, bhd, bch, bcs, blab, bitems, binsts, bbuckets, bcinst, bxstats;
   kmx::Buf btermC, btermMu, bW, bcost;
   hipStream_t cap_stream = nullptr;                // stream graphs are captured on (batched, graphed Lloyd)
+  uint64_t ws_gen = 0;                             // bumped whenever a workspace buffer moves
+  // the last captured Lloyd iteration of kmx_lloyd_graph and what it was captured for
+  hipGraph_t lg_graph = nullptr;
+  hipGraphExec_t lg_exec = nullptr;
+  hipEvent_t lg_event = nullptr;                   // orders the capture stream after the context stream
+  uint64_t lg_key[12] = {0};
   std::map<std::pair<int, int>, int> tune;         // (d, k class) -> tile-shape variant
 
   // timing
@@ -231,11 +247,18 @@ hipError_t launch_assign(hipStream_t s, int prec, const float* X, int64_t ldx,
                          int k, int kpad, const CenterStats* cs, int32_t* label,
                          float* d1, float* d2, FlagEntry* flags, int* full_rows,
                          unsigned long long* full_ctr, int cascade_all, int* brute,
-                         LoopState* st, const int* gate, int num_cus);
+                         LoopState* st, const int* gate, int num_cus, float* hub = nullptr,
+                         float* hlb = nullptr);
+// count instances of one matrix instruction of the assignment (FP8 16x16x128
+// scaled, BF16 16x16x32 or FP32 16x16x4) from C (nullable: zero)
+hipError_t launch_mfma_probe(hipStream_t s, int prec, const uint8_t* A, const uint8_t* B,
+                             const uint8_t* sa, const uint8_t* sb, const float* C, float* D,
+                             int count);
 hipError_t launch_recheck(hipStream_t s, const float* X, int64_t n, int d, int64_t ldx,
                           const float* C, int k, int32_t* label, float* d1,
                           const FlagEntry* flags, const int* brute, const LoopState* st,
-                          int num_cus, const int* gate);
+                          int num_cus, const int* gate, float* hub = nullptr,
+                          float* hlb = nullptr);
 // Moves a list meant for the FP32 GEMM pass onto the every-center re-check
 // list when it holds at most kShortList rows and k d >= kShortListMinKD (one
 // workgroup; gate as above).
@@ -295,6 +318,17 @@ hipError_t launch_batch_cost(hipStream_t s, const BatchInst* insts, int ninst,
 hipError_t launch_batch_labels(hipStream_t s, const int32_t* glabel, int64_t grow0, int n,
                                int koff, int32_t* out);
 
+// carried bounds (k_bounds.hip)
+hipError_t launch_drift(hipStream_t s, const float* Cold, const float* Cnew, int k, int d,
+                        float* drift, DriftStat* ds, const int* gate);
+hipError_t launch_bounds_test(hipStream_t s, int64_t n, const int32_t* label, float* hub,
+                              float* hlb, const float* drift, const DriftStat* ds, int k,
+                              int* fail_rows, LoopState* st, const int* gate, int num_cus);
+hipError_t launch_copy_f32(hipStream_t s, const float* src, float* dst, int64_t count,
+                           const int* gate);
+hipError_t launch_record_kept(hipStream_t s, const LoopState* st, int64_t* kept, int slot,
+                              int64_t n, const int* gate);
+
 // projection (k_project.hip)
 hipError_t launch_project(hipStream_t s, const float* X, int64_t rows, int d_in, int64_t ldx,
                           const float* V, int d_out, float* Y, int64_t ldy, float* Vt,
@@ -318,7 +352,9 @@ hipError_t launch_router_cert(hipStream_t s, const uint16_t* Xq, int64_t dp, int
                               const float* C, int k, const RowStats* rs, const uint32_t* keys,
                               int kpad, const int32_t* nbr, const float* nbd, int32_t* label,
                               FlagEntry* flags, int* fb_rows, LoopState* st, const int* gate,
-                              int num_cus);
+                              int num_cus, const int* rows = nullptr,
+                              const unsigned long long* row_count = nullptr, float* hub = nullptr,
+                              float* hlb = nullptr);
 hipError_t launch_record_fallback(hipStream_t s, const LoopState* st, int64_t* fbh, int slot,
                                   int all_rows, int64_t all, const int* gate);
 

@@ -413,10 +413,14 @@ kmx_status kmx_router_propose(kmx_ctx* ctx, kmx_router* r, const float* X, int64
   return KMX_OK;
 }
 
-kmx_status kmx_lloyd_routed(kmx_ctx* ctx, kmx_router* r, const float* X, int64_t n, int32_t d,
-                            int64_t ldx, const float* w, float* C_inout, int32_t k,
-                            int32_t max_iter, double tol, kmx_prec prec, int32_t* label_out,
-                            double* cost_hist, int32_t* iters_done, int64_t* gemm_rows) {
+// The routed Lloyd loop; with `bounded` the assignment first applies the
+// carried bounds (k_bounds.hip) and only the rows they cannot keep go to the
+// certificate and the GEMM.
+static kmx_status lloyd_routed_impl(kmx_ctx* ctx, kmx_router* r, const float* X, int64_t n,
+                                    int32_t d, int64_t ldx, const float* w, float* C_inout,
+                                    int32_t k, int32_t max_iter, double tol, kmx_prec prec,
+                                    int32_t* label_out, double* cost_hist, int32_t* iters_done,
+                                    int64_t* gemm_rows, int bounded, int64_t* kept_rows) {
   if (!ctx) return KMX_EINVAL;
   ctx->err.clear();
   KMX_TRY(check_problem(ctx, X, n, d, ldx, k));
@@ -442,6 +446,19 @@ kmx_status kmx_lloyd_routed(kmx_ctx* ctx, kmx_router* r, const float* X, int64_t
   KMX_TRY(grow(ctx, ctx->nbr, (size_t)k * kNbrL * sizeof(int32_t)));
   KMX_TRY(grow(ctx, ctx->nbd, (size_t)k * (kNbrL + 1) * sizeof(float)));
   KMX_TRY(grow(ctx, ctx->fbh, (size_t)(max_iter + 1) * sizeof(int64_t)));
+  float* hub = nullptr;
+  float* hlb = nullptr;
+  if (bounded) {
+    KMX_TRY(grow(ctx, ctx->hub, (size_t)n * sizeof(float)));
+    KMX_TRY(grow(ctx, ctx->hlb, (size_t)n * sizeof(float)));
+    KMX_TRY(grow(ctx, ctx->bl_rows, (size_t)n * sizeof(int)));
+    KMX_TRY(grow(ctx, ctx->cprev, (size_t)k * d * sizeof(float)));
+    KMX_TRY(grow(ctx, ctx->drift, (size_t)k * sizeof(float)));
+    KMX_TRY(grow(ctx, ctx->dstat, sizeof(DriftStat)));
+    KMX_TRY(grow(ctx, ctx->bkh, (size_t)(max_iter + 1) * sizeof(int64_t)));
+    hub = P<float>(ctx->hub);
+    hlb = P<float>(ctx->hlb);
+  }
   const int dp = assign_dpad(KMX_BF16, d);
   const uint32_t* keys = nullptr;
   int kpad_r = (k + kRouterBN2 - 1) / kRouterBN2 * kRouterBN2;
@@ -455,6 +472,7 @@ kmx_status kmx_lloyd_routed(kmx_ctx* ctx, kmx_router* r, const float* X, int64_t
   int32_t* prev = P<int32_t>(ctx->lab_prev);
   double* hist = P<double>(ctx->hist);
   int64_t* fbh = P<int64_t>(ctx->fbh);
+  int64_t* bkh = bounded ? P<int64_t>(ctx->bkh) : nullptr;
   LoopState* st = ST(ctx);
   KMX_HIP(ctx, launch_fill_i32(ctx->stream, prev, n, -1));
   if (r) {
@@ -466,28 +484,61 @@ kmx_status kmx_lloyd_routed(kmx_ctx* ctx, kmx_router* r, const float* X, int64_t
                                    ctx->num_cus));
     keys = P<uint32_t>(ctx->keys);
   }
-  for (int t = 0; t < max_iter; ++t) {
+  // one assignment of iteration t (t == max_iter: the final one); gate: the stop flag
+  auto assign_step = [&](int t, const int* gate) -> kmx_status {
     KMX_TRY(run_prep_centers(ctx, C_inout, k, d, prec));
-    if (r || t > 0) {
-      KMX_TRY(routed_assign(ctx, X, n, d, ldx, C_inout, k, prec, lab, keys, kpad_r, &st->done));
-      KMX_HIP(ctx, launch_record_fallback(ctx->stream, st, fbh, t, 0, n, &st->done));
-    } else {
+    if (bounded && t > 0) {
+      {
+        Timed tm(ctx, T_BOUND);
+        KMX_HIP(ctx, launch_bounds_test(ctx->stream, n, lab, hub, hlb, P<float>(ctx->drift),
+                                        P<DriftStat>(ctx->dstat), k, P<int>(ctx->bl_rows), st,
+                                        gate, ctx->num_cus));
+      }
+      {
+        Timed tm(ctx, T_CERT);
+        KMX_HIP(ctx, launch_center_table(ctx->stream, C_inout, k, d, P<float>(ctx->cdist),
+                                         P<int32_t>(ctx->nbr), P<float>(ctx->nbd), gate));
+        KMX_HIP(ctx, launch_router_cert(ctx->stream, P<uint16_t>(ctx->xq), dp, n, d, C_inout, k,
+                                        P<RowStats>(ctx->rowstats), keys, kpad_r,
+                                        P<int32_t>(ctx->nbr), P<float>(ctx->nbd), lab,
+                                        P<FlagEntry>(ctx->flags), P<int>(ctx->fb_rows), st, gate,
+                                        ctx->num_cus, P<int>(ctx->bl_rows), &st->bound_fail, hub,
+                                        hlb));
+      }
+      KMX_TRY(run_assign_gemm(ctx, X, n, d, ldx, C_inout, k, prec, lab, nullptr, nullptr,
+                              P<int>(ctx->fb_rows), &st->routed_fallback, gate, hub, hlb));
+      KMX_HIP(ctx, launch_record_fallback(ctx->stream, st, fbh, t, 0, n, gate));
+      KMX_HIP(ctx, launch_record_kept(ctx->stream, st, bkh, t, n, gate));
+    } else if (bounded || (!r && t == 0)) {
+      // the first assignment of a bounded loop (or of the previous-label
+      // loop): every row through the GEMM
       KMX_TRY(run_assign_gemm(ctx, X, n, d, ldx, C_inout, k, prec, lab, nullptr, nullptr, nullptr,
-                              nullptr, &st->done));
-      KMX_HIP(ctx, launch_record_fallback(ctx->stream, st, fbh, t, 1, n, &st->done));
+                              nullptr, gate, hub, hlb));
+      KMX_HIP(ctx, launch_record_fallback(ctx->stream, st, fbh, t, 1, n, gate));
+      if (bounded) KMX_HIP(ctx, launch_record_kept(ctx->stream, nullptr, bkh, t, 0, gate));
+    } else {
+      KMX_TRY(routed_assign(ctx, X, n, d, ldx, C_inout, k, prec, lab, keys, kpad_r, gate));
+      KMX_HIP(ctx, launch_record_fallback(ctx->stream, st, fbh, t, 0, n, gate));
     }
+    return KMX_OK;
+  };
+  for (int t = 0; t < max_iter; ++t) {
+    KMX_TRY(assign_step(t, &st->done));
+    // the centers before the update (not after the loop has stopped: then
+    // they keep the last centers the bounds were moved from)
+    if (bounded)
+      KMX_HIP(ctx, launch_copy_f32(ctx->stream, C_inout, P<float>(ctx->cprev), (int64_t)k * d,
+                                   &st->done));
     KMX_TRY(run_update(ctx, X, n, d, ldx, w, lab, k, C_inout, C_inout, nullptr, 1, prev, hist, 0,
                        &st->done));
+    if (bounded) {
+      // not gated: the update that sets the stop flag still moved the centers
+      Timed tm(ctx, T_BOUND);
+      KMX_HIP(ctx, launch_drift(ctx->stream, P<float>(ctx->cprev), C_inout, k, d,
+                                P<float>(ctx->drift), P<DriftStat>(ctx->dstat), nullptr));
+    }
   }
-  KMX_TRY(run_prep_centers(ctx, C_inout, k, d, prec));
-  if (r || max_iter > 0) {
-    KMX_TRY(routed_assign(ctx, X, n, d, ldx, C_inout, k, prec, lab, keys, kpad_r, nullptr));
-    KMX_HIP(ctx, launch_record_fallback(ctx->stream, st, fbh, max_iter, 0, n, nullptr));
-  } else {
-    KMX_TRY(run_assign_gemm(ctx, X, n, d, ldx, C_inout, k, prec, lab, nullptr, nullptr, nullptr,
-                            nullptr, nullptr));
-    KMX_HIP(ctx, launch_record_fallback(ctx->stream, st, fbh, max_iter, 1, n, nullptr));
-  }
+  KMX_TRY(assign_step(max_iter, nullptr));
   KMX_TRY(run_update(ctx, X, n, d, ldx, w, lab, k, C_inout, nullptr, nullptr, 0, nullptr, hist, 1,
                      nullptr));
   LoopState h;
@@ -495,15 +546,35 @@ kmx_status kmx_lloyd_routed(kmx_ctx* ctx, kmx_router* r, const float* X, int64_t
   KMX_HIP(ctx, hipStreamSynchronize(ctx->stream));
   const int it = h.iter;
   KMX_HIP(ctx, hipMemcpy(cost_hist, hist, (size_t)(it + 1) * sizeof(double), hipMemcpyDeviceToHost));
-  if (gemm_rows) {
+  auto copy_hist = [&](const int64_t* dev, int64_t* out) -> kmx_status {
     std::vector<int64_t> fb((size_t)max_iter + 1);
-    KMX_HIP(ctx, hipMemcpy(fb.data(), fbh, (size_t)(max_iter + 1) * sizeof(int64_t),
+    KMX_HIP(ctx, hipMemcpy(fb.data(), dev, (size_t)(max_iter + 1) * sizeof(int64_t),
                            hipMemcpyDeviceToHost));
-    for (int t = 0; t < it; ++t) gemm_rows[t] = fb[t];
-    gemm_rows[it] = fb[max_iter];
-  }
+    for (int t = 0; t < it; ++t) out[t] = fb[t];
+    out[it] = fb[max_iter];
+    return KMX_OK;
+  };
+  if (gemm_rows) KMX_TRY(copy_hist(fbh, gemm_rows));
+  if (kept_rows && bkh) KMX_TRY(copy_hist(bkh, kept_rows));
   *iters_done = it;
   return KMX_OK;
+}
+
+kmx_status kmx_lloyd_routed(kmx_ctx* ctx, kmx_router* r, const float* X, int64_t n, int32_t d,
+                            int64_t ldx, const float* w, float* C_inout, int32_t k,
+                            int32_t max_iter, double tol, kmx_prec prec, int32_t* label_out,
+                            double* cost_hist, int32_t* iters_done, int64_t* gemm_rows) {
+  return lloyd_routed_impl(ctx, r, X, n, d, ldx, w, C_inout, k, max_iter, tol, prec, label_out,
+                           cost_hist, iters_done, gemm_rows, 0, nullptr);
+}
+
+kmx_status kmx_lloyd_bounded(kmx_ctx* ctx, kmx_router* r, const float* X, int64_t n, int32_t d,
+                             int64_t ldx, const float* w, float* C_inout, int32_t k,
+                             int32_t max_iter, double tol, kmx_prec prec, int32_t* label_out,
+                             double* cost_hist, int32_t* iters_done, int64_t* gemm_rows,
+                             int64_t* kept_rows) {
+  return lloyd_routed_impl(ctx, r, X, n, d, ldx, w, C_inout, k, max_iter, tol, prec, label_out,
+                           cost_hist, iters_done, gemm_rows, 1, kept_rows);
 }
 
 }  // extern "C"

@@ -10,6 +10,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import weakref
 from typing import Optional
 
 import torch
@@ -21,7 +22,7 @@ FP32, BF16, FP8 = 0, 1, 2
 _PREC = {"fp32": FP32, "bf16": BF16, "fp8": FP8, FP32: FP32, BF16: BF16, FP8: FP8}
 
 TIMING_CLASSES = ("prep", "assign", "recheck", "sort", "reduce", "finalize", "seed", "other",
-                  "router", "certificate", "train", "project")
+                  "router", "certificate", "train", "project", "bounds")
 ROUTER_HIDDEN = 256
 ROUTER_M = 16
 
@@ -68,6 +69,7 @@ def lib():
         "kmx_lloyd_graph": [_vp, _vp, _i64, _i32, _i64, _vp, _vp, _i32, _i32, ctypes.c_double,
                             ctypes.c_int, _vp, _vp, _vp],
         "kmx_timing": [_vp, ctypes.c_int, ctypes.c_int],
+        "kmx_mfma_probe": [_vp, ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _vp, _i32],
         "kmx_assign_stats": [_vp, _vp, _vp, _vp],
         "kmx_seed_stats": [_vp, _vp],
         "kmx_timing_read": [_vp, ctypes.c_int, _vp, _vp],
@@ -85,6 +87,8 @@ def lib():
         "kmx_router_propose": [_vp, _vp, _vp, _i64, _i32, _i64, _vp],
         "kmx_lloyd_routed": [_vp, _vp, _vp, _i64, _i32, _i64, _vp, _vp, _i32, _i32,
                              ctypes.c_double, ctypes.c_int, _vp, _vp, _vp, _vp],
+        "kmx_lloyd_bounded": [_vp, _vp, _vp, _i64, _i32, _i64, _vp, _vp, _i32, _i32,
+                              ctypes.c_double, ctypes.c_int, _vp, _vp, _vp, _vp, _vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -139,6 +143,18 @@ class Context:
             st = torch.cuda.current_stream().cuda_stream
             _check(L.kmx_create(ctypes.byref(p), self.device, _vp(st)), None)
         self._p = p
+        self._xseen = {}
+
+    def _fresh(self, X):
+        """The library caches derived copies of X by device pointer.  A
+        different tensor at a pointer seen before (the old one freed and its
+        memory reused), or an in-place change of the same tensor (its version
+        counter moved), drops that cache first."""
+        key = X.data_ptr()
+        seen = self._xseen.get(key)
+        if seen is not None and (seen[0]() is not X or seen[1] != X._version):
+            _check(lib().kmx_invalidate(self._p, _vp(key)), self._p)
+        self._xseen[key] = (weakref.ref(X), X._version)
 
     def close(self):
         if getattr(self, "_p", None) is not None and self._p.value:
@@ -169,6 +185,7 @@ class Context:
 
     def assign(self, X, C, prec="fp32", want_d=True):
         n, d, ldx = _rows(X)
+        self._fresh(X)
         k = _centers(C, d)
         lab = torch.empty(n, dtype=torch.int32, device=X.device)
         d1 = torch.empty(n, dtype=torch.float32, device=X.device) if want_d else None
@@ -206,6 +223,7 @@ class Context:
 
     def cost(self, X, C, w=None, prec="fp32") -> float:
         n, d, ldx = _rows(X)
+        self._fresh(X)
         k = _centers(C, d)
         _vec(w, n)
         out = ctypes.c_double(0.0)
@@ -219,6 +237,7 @@ class Context:
         """kmx_lloyd, or kmx_lloyd_graph with graph=True (one captured
         iteration replayed); returns (C, labels, cost_hist, iters)."""
         n, d, ldx = _rows(X)
+        self._fresh(X)
         k = _centers(C0, d)
         _vec(w, n)
         C = C0 if inplace else C0.clone()
@@ -248,6 +267,31 @@ class Context:
         _check(lib().kmx_assign_stats(self._p, ctypes.byref(a), ctypes.byref(b),
                                       ctypes.byref(c)), self._p)
         return int(a.value), int(b.value), int(c.value)
+
+    def mfma_probe(self, prec, A, B, scale_a=None, scale_b=None, C=None):
+        """kmx_mfma_probe.  A, B: (count, 16, K) uint8 E4M3 bytes (fp8, K = 128),
+        int16 BF16 bit patterns (bf16, K = 32) or float32 (fp32, K = 4); fp8
+        scales uint8 (count,) and (count, 16); optional start values C float32
+        (count, 16, 16).  Returns D (count, 16, 16)."""
+        p = _PREC[prec]
+        kk, dt = {FP8: (128, torch.uint8), BF16: (32, torch.int16), FP32: (4, torch.float32)}[p]
+        count = A.shape[0]
+        for t, shape in ((A, (count, 16, kk)), (B, (count, 16, kk))):
+            if not t.is_cuda or t.dtype != dt or tuple(t.shape) != shape or not t.is_contiguous():
+                raise ValueError(f"expected a contiguous {dt} CUDA tensor of shape {shape}")
+        if p == FP8:
+            for t, shape in ((scale_a, (count,)), (scale_b, (count, 16))):
+                if t is None or not t.is_cuda or t.dtype != torch.uint8 \
+                        or tuple(t.shape) != shape or not t.is_contiguous():
+                    raise ValueError(f"expected a contiguous uint8 CUDA tensor of shape {shape}")
+        if C is not None and (not C.is_cuda or C.dtype != torch.float32
+                              or tuple(C.shape) != (count, 16, 16) or not C.is_contiguous()):
+            raise ValueError("C must be a contiguous float32 CUDA tensor (count, 16, 16)")
+        D = torch.empty((count, 16, 16), dtype=torch.float32, device=A.device)
+        self._sync_stream()
+        _check(lib().kmx_mfma_probe(self._p, p, _ptr(A), _ptr(B), _ptr(scale_a), _ptr(scale_b),
+                                    _ptr(C), _ptr(D), count), self._p)
+        return D
 
     def timing(self, enable: bool = True, reset: bool = True):
         _check(lib().kmx_timing(self._p, int(enable), int(reset)), self._p)
@@ -325,6 +369,7 @@ class Context:
                      tol: float = -1.0, prec="bf16", labels: bool = True, inplace: bool = False):
         """kmx_lloyd_routed; returns (C, labels, cost_hist, iters, gemm_rows)."""
         n, d, ldx = _rows(X)
+        self._fresh(X)
         k = _centers(C0, d)
         _vec(w, n)
         C = C0 if inplace else C0.clone()
@@ -339,6 +384,30 @@ class Context:
                                       ctypes.byref(iters), rows), self._p)
         it = int(iters.value)
         return (C, lab, [hist[i] for i in range(it + 1)], it, [rows[i] for i in range(it + 1)])
+
+
+    def lloyd_bounded(self, X, C0, max_iter: int, router: Optional["Router"] = None, w=None,
+                      tol: float = -1.0, prec="bf16", labels: bool = True,
+                      inplace: bool = False):
+        """kmx_lloyd_bounded; returns (C, labels, cost_hist, iters, gemm_rows, kept_rows)."""
+        n, d, ldx = _rows(X)
+        self._fresh(X)
+        k = _centers(C0, d)
+        _vec(w, n)
+        C = C0 if inplace else C0.clone()
+        lab = torch.empty(n, dtype=torch.int32, device=X.device) if labels else None
+        hist = (ctypes.c_double * (max_iter + 1))()
+        rows = (ctypes.c_int64 * (max_iter + 1))()
+        kept = (ctypes.c_int64 * (max_iter + 1))()
+        iters = ctypes.c_int32(0)
+        self._sync_stream()
+        _check(lib().kmx_lloyd_bounded(self._p, router._r if router is not None else None,
+                                       _ptr(X), n, d, ldx, _ptr(w), _ptr(C), k, max_iter,
+                                       float(tol), _PREC[prec], _ptr(lab), hist,
+                                       ctypes.byref(iters), rows, kept), self._p)
+        it = int(iters.value)
+        return (C, lab, [hist[i] for i in range(it + 1)], it, [rows[i] for i in range(it + 1)],
+                [kept[i] for i in range(it + 1)])
 
 
 class Router:
@@ -429,6 +498,7 @@ class Router:
 
     def propose(self, X):
         n, d, ldx = _rows(X)
+        self.ctx._fresh(X)
         cand = torch.empty((n, ROUTER_M), dtype=torch.int32, device=X.device)
         self.ctx._sync_stream()
         _check(lib().kmx_router_propose(self.ctx._p, self._r, _ptr(X), n, d, ldx, _ptr(cand)),

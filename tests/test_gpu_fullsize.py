@@ -154,3 +154,44 @@ def test_batched_full_size(ctx):
                        f"instance {i}")
     del probs, res
     torch.cuda.empty_cache()
+
+
+def test_headline_fp8_step_against_oracle(ctx):
+    # n = 4,000,000, d = 512, k = 1000 (means N(0, 4I), sigma in [0.5, 1.5]),
+    # k-means++ seed 0, the FP8 path bench.py times: one Lloyd iteration.
+    # The oracle recomputes, on the host in FP64, the clustering features of
+    # the GPU's partitions (Sec. 2.1): all 1000 centroids of C_1 against the
+    # oracle's update of the labels against C_0 (1e-5 relative), cost(C_0) and
+    # cost(C_1) against the clustering-feature identity on the same labels
+    # (1e-6 relative); labels of 20,000 sampled rows against the oracle's
+    # assignment outside the 1e-6 top-2 band.
+    say("headline step n=4e6 d=512 k=1000 (fp8) against the oracle")
+    n, d, k = 4_000_000, 512, 1000
+    Xg, _, _ = synth.router_mixture_device(n, d, k, seed=0)
+    C0, _ = ctx.seed(Xg, k, rng_seed=0)
+    lab0, _, _, _ = ctx.assign(Xg, C0, prec="fp8", want_d=False)
+    C1, lab1, hist, it = ctx.lloyd(Xg, C0, 1, prec="fp8", labels=True)
+    assert it == 1
+    X = Xg.cpu().numpy()
+    L0, L1 = lab0.cpu().numpy(), lab1.cpu().numpy()
+    C0h = C0.cpu().numpy().astype(np.float64)
+    C1h = C1.cpu().numpy().astype(np.float64)
+    del Xg
+    torch.cuda.empty_cache()
+    rng = np.random.default_rng(1)
+    rows = np.sort(rng.choice(n, 20000, replace=False))
+    _check_sampled(L0[rows], X[rows], C0h, "labels against C_0")
+    _check_sampled(L1[rows], X[rows], C1h, "labels against C_1")
+    say("  oracle update of the GPU's labels")
+    Cn, W, S, Q = ok.update(X, None, L0, C0h)
+    nonempty = W > 0
+    say(f"  {int(nonempty.sum())} non-empty clusters")
+    for j in range(k):
+        scale = max(np.linalg.norm(Cn[j]), 1e-3)
+        assert np.linalg.norm(C1h[j] - Cn[j]) <= 1e-5 * scale, j
+    cost0 = ok.cost_from_features(W, S, Q, C0h)
+    assert abs(hist[0] - cost0) <= 1e-6 * cost0, (hist[0], cost0)
+    W1, S1, Q1 = ok.clustering_features(X, None, L1, k)
+    cost1 = ok.cost_from_features(W1, S1, Q1, C1h)
+    assert abs(hist[1] - cost1) <= 1e-6 * cost1, (hist[1], cost1)
+    say(f"  cost(C_0) {hist[0]:.9e} vs {cost0:.9e}; cost(C_1) {hist[1]:.9e} vs {cost1:.9e}")

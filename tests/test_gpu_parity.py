@@ -271,22 +271,30 @@ def test_lloyd_small_workload_end_to_end(ctx, prec):
         assert np.linalg.norm(Cg[j] - ref["C"][j]) <= 1e-5 * np.linalg.norm(ref["C"][j])
 
 
-def test_lloyd_weighted_ragged_teacher_forced(ctx):
+@pytest.mark.parametrize("prec", ["bf16", "fp8", "fp32"])
+@pytest.mark.parametrize("n,d,k", [(7001, 45, 23), (5003, 300, 130)])
+def test_lloyd_weighted_ragged_teacher_forced(ctx, prec, n, d, k):
     # Teacher-forced step check on a weighted, ragged problem: each GPU
-    # iteration starts from the oracle's centers.
-    say("lloyd teacher forced")
-    n, d, k = 7001, 45, 23
+    # iteration starts from the oracle's centers (FP32-rounded); the GPU's
+    # assignment against them must equal the oracle's outside the 1e-6 top-2
+    # band, its centroids the oracle's update within 1e-5 and its cost the
+    # oracle's within 1e-6.
+    say(f"lloyd teacher forced {prec} n={n} d={d} k={k}")
     X, _ = synth.isotropic_mixture(n, d, 15, seed=4)
     w = synth.lognormal_weights(n, seed=4)
     C, _, _ = ok.seed(X, w, k, 5)
     C = C.astype(np.float32).astype(np.float64)
     for t in range(4):
+        lab_g, _, _, _ = ctx.assign(_dev(X), _dev(C.astype(np.float32)), prec=prec,
+                                    want_d=False)
         Cg, lab, hist, it = ctx.lloyd(_dev(X), _dev(C.astype(np.float32)), 1, w=_dev(w),
-                                      prec="bf16")
+                                      prec=prec)
         ref = ok.lloyd(X, w, C, 1)
         assert it == 1
         assert abs(hist[0] - ref["cost"][0]) <= 1e-6 * ref["cost"][0]
-        lab_o, _, _ = ok.assign(X, C)
+        lab_o, d1, d2 = ok.assign(X, C)
+        bad = (lab_g.cpu().numpy() != lab_o) & ~((d2 - d1) < 1e-6 * d2)
+        assert not bad.any(), f"step {t}: {int(bad.sum())} labels differ outside the band"
         Cn, _, _, _ = ok.update(X, w, lab_o, C)
         Cn = Cn.astype(np.float32).astype(np.float64)
         G = Cg.cpu().numpy().astype(np.float64)
@@ -371,3 +379,29 @@ def test_lloyd_graph_identical_to_eager(ctx, prec, n, d, k, tol):
     ref = ok.lloyd(X, None, C0.cpu().numpy(), 5, tol=tol)
     assert ig == ref["iters"]
     np.testing.assert_allclose(hg, ref["cost"], rtol=1e-6)
+
+
+def test_quantized_copy_cache_follows_the_tensor(ctx):
+    # the library caches the quantized copy of X by pointer; the binding drops
+    # it when a different tensor lands at the same address or the tensor is
+    # changed in place, so results never come from stale copies
+    say("quantized-copy cache")
+    from paper_1502_04265_amd import kmx
+    g = torch.Generator(device="cuda:0").manual_seed(3)
+    C = torch.randn(40, 64, device="cuda:0", generator=g) * 3
+    X1 = torch.randn(20000, 64, device="cuda:0", generator=g) * 3
+    ctx.assign(X1, C, prec="bf16")
+    ctx.assign(X1, C, prec="fp8")
+    p1 = X1.data_ptr()
+    del X1
+    X2 = torch.randn(20000, 64, device="cuda:0", generator=g) * 3 + 40.0
+    say(f"  same address reused: {X2.data_ptr() == p1}")
+    fresh = kmx.Context(0)
+    for prec in ("bf16", "fp8", "fp32"):
+        assert torch.equal(ctx.assign(X2, C, prec=prec)[0], fresh.assign(X2, C, prec=prec)[0])
+    X2.mul_(-1.0)
+    fresh2 = kmx.Context(0)
+    for prec in ("bf16", "fp8", "fp32"):
+        assert torch.equal(ctx.assign(X2, C, prec=prec)[0], fresh2.assign(X2, C, prec=prec)[0])
+    fresh.close()
+    fresh2.close()

@@ -607,6 +607,9 @@ def main():
     ap.add_argument("--traffic", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT_JSON"),
                     help="convert two rocprofv3 counter passes of --only assign into the traffic "
                          "record (no GPU)")
+    ap.add_argument("--paths", default=None,
+                    help="profiling: comma-separated subset of the headline paths to run (the "
+                         "full BF16 path always runs: the others are checked against it)")
     ap.add_argument("--repeats", type=int, default=3,
                     help="timed runs per path (the median is reported)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -759,7 +762,11 @@ def main():
 
     paths, results = {}, {}
 
+    only = set(args.paths.split(",")) if args.paths else None
+
     def add(name, fn, assign, uses_router, dtype):
+        if only is not None and name not in only and name != "full_bf16":
+            return {}
         res, w, kk, walls = run_timed(name, fn)
         results[name] = res
         paths[name] = {"iter_per_s": args.steps / w, "ms_per_step": w * 1e3 / args.steps,
@@ -794,10 +801,11 @@ def main():
     kt8 = add("full_fp8", lambda: ctx.lloyd(X, Cw, S, prec="fp8"),
               "FP8 E4M3 MFMA GEMM (per-row scales) with fused top-3, BF16 then FP32 GEMM passes "
               "and exact re-check of undecided rows", False, "fp8e4m3")
-    fp8_stats = ctx.assign_stats()
-    paths["full_fp8"]["final_listed_via_fp32_all"] = list(fp8_stats)
+    if "full_fp8" in paths:
+        paths["full_fp8"]["final_listed_via_fp32_all"] = list(ctx.assign_stats())
     for prec in ("bf16", "fp8"):     # the first capture on a context pays one-off costs
-        ctx.lloyd(X, Cw, 1, prec=prec, labels=False, graph=True)
+        if only is None or f"full_{prec}_graph" in only:
+            ctx.lloyd(X, Cw, 1, prec=prec, labels=False, graph=True)
     add("full_bf16_graph", lambda: ctx.lloyd(X, Cw, S, prec="bf16", graph=True),
         "as full_bf16, the iteration replayed as a HIP graph", False, "bf16")
     add("full_fp8_graph", lambda: ctx.lloyd(X, Cw, S, prec="fp8", graph=True),
@@ -808,6 +816,11 @@ def main():
                   "plain FP32 MFMA GEMM with fused top-3 and exact re-check (the reference path "
                   "of the metric)", False, "f32")
 
+    if only is not None:      # profiling subset: the timings only
+        same = all(torch.equal(r[1], results["full_bf16"][1]) for r in results.values())
+        print(json.dumps({"mode": "paths", "identical_labels": bool(same), "paths": paths}),
+              flush=True)
+        return
     base_lab, base_C = results["full_bf16"][1], results["full_bf16"][0]
     same = all(torch.equal(r[1], base_lab) and torch.equal(r[0], base_C) for r in results.values())
     cost_ref = paths["fp32"]["final_cost"] if "fp32" in paths else paths["full_bf16"]["final_cost"]

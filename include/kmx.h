@@ -59,7 +59,11 @@ typedef enum {
 /* Arithmetic of the distance GEMM inside assignment.  Labels are exact for
  * every precision: rows whose top-2 margin lies inside the rigorous error
  * bound of the chosen precision are re-checked with compensated FP32
- * direct differences.  Centroid and cost accumulation is always FP64. */
+ * direct differences.  Centroid and cost accumulation is always FP64.
+ * Rows wider than 1024 (kmx_assign, kmx_cost, kmx_lloyd, kmx_lloyd_graph;
+ * any precision) take the exact every-center path instead: plain FP32
+ * direct-difference distances to every center, double-float sums for the
+ * centers inside their error bound; no matrix cores. */
 typedef enum {
   KMX_FP32 = 0,     /* FP32 MFMA, FP32 accumulate                            */
   KMX_BF16 = 1,     /* BF16 inputs (round to nearest even), FP32 accumulate  */
@@ -113,7 +117,8 @@ kmx_status kmx_seed_stats(kmx_ctx* ctx, int64_t* rows_read);
  *   d1_out    device, n float32, nullable: distance to the assigned center.
  *   d2_out    device, n float32, nullable: second smallest distance as
  *             evaluated by the GEMM (within the GEMM's error bound; +inf if
- *             k == 1).
+ *             k == 1); for rows wider than 1024, the second smallest plain
+ *             FP32 distance.
  *   n_flagged host, nullable: rows the first GEMM pass could not decide, i.e.
  *             rows that went to the exact re-check or to the FP32 GEMM pass
  *             (synchronizes).

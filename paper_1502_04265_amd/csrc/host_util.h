@@ -126,7 +126,8 @@ inline LoopState* ST(kmx_ctx* ctx) { return P<LoopState>(ctx->state); }
 
 kmx_status check_problem(kmx_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
                          int32_t k);
-kmx_status check_prec(kmx_ctx* ctx, int prec, int d);
+// allow_wide: rows wider than kGemmMaxD are taken (the exact every-center path)
+kmx_status check_prec(kmx_ctx* ctx, int prec, int d, bool allow_wide = false);
 // Weights finite and >= 0 with at least min_pos positive; with KMX_VALIDATE
 // also X and C finite.  Synchronizes when it checks anything.
 kmx_status check_data(kmx_ctx* ctx, const float* X, int64_t n, int d, int64_t ldx, const float* w,
@@ -140,11 +141,11 @@ kmx_status write_state(kmx_ctx* ctx, int max_iter, double tol);
 kmx_status run_prep_centers(kmx_ctx* ctx, const float* C, int k, int d, int prec);
 // GEMM assignment over all rows (rows == nullptr) or over the rows listed in
 // rows[0 .. *row_count), then the FP32 pass and the re-check.
-// hub / hlb (nullable): carried bounds written for the rows decided here.
+// bo (nullable pointers): carried bounds written for the rows decided here.
 kmx_status run_assign_gemm(kmx_ctx* ctx, const float* X, int64_t n, int d, int64_t ldx,
                            const float* C, int k, int prec, int32_t* label, float* d1,
                            float* d2, const int* rows, const unsigned long long* row_count,
-                           const int* gate, float* hub = nullptr, float* hlb = nullptr);
+                           const int* gate, BoundsOut bo = {});
 // run_prep_centers + run_assign_gemm over all rows.
 kmx_status run_assign(kmx_ctx* ctx, const float* X, int64_t n, int d, int64_t ldx, const float* C,
                       int k, int prec, int32_t* label, float* d1, float* d2, const int* gate);

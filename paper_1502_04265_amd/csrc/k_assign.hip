@@ -194,12 +194,10 @@ struct AssignArgs {
   int* brute;
   LoopState* st;
   int count_undecided;
-  // carried bounds (nullable): upper bound of ||x - c_label|| and lower bound
-  // of every other center's distance, written for the rows this pass decides
-  // (for listed rows the lower bound covers the centers not listed; the
-  // re-check completes both)
-  float* hub;
-  float* hlb;
+  // carried bounds (nullable), written for the rows this pass decides; for
+  // listed rows bo.lb covers the centers not listed and the re-check
+  // completes the rest
+  BoundsOut bo;
 };
 
 template <int MODE, int NKU, int NCG, int BN, int WAVES>
@@ -668,11 +666,22 @@ __device__ __forceinline__ void assign_block(const AssignArgs& A, int64_t blk,
               full = true;
             }
           }
-          if (A.hub && !full) {
+          if (A.bo.ub && !full) {
             if (!flagged) {
-              // decided here: the label's distance and every other center's
-              A.hub[r] = dist_up(xhi - 2.0 * ((double)t1 - (double)E - (double)off));
-              A.hlb[r] = lb_of(t2);
+              // decided here: the label's distance, the runner-up's (second
+              // key) and every other center's (below the third kept key, or a
+              // lane-wise third best that dropped further keys)
+              bool hasr = has3;
+              float tr = t3;
+              if (T3 && (w3[cg] & ~mask)) {
+                const float tw = __uint_as_float(w3[cg] & ~mask);
+                tr = hasr ? fmaxf(tr, tw) : tw;
+                hasr = true;
+              }
+              A.bo.ub[r] = dist_up(xhi - 2.0 * ((double)t1 - (double)E - (double)off));
+              A.bo.sec[r] = A.koff + cand2;
+              A.bo.l2[r] = lb_of(t2);
+              A.bo.lb[r] = hasr ? lb_of(tr) : __builtin_inff();
             } else {
               // listed: the re-check sets the upper bound and completes the
               // lower bound with the listed runner-up; here the centers not
@@ -685,15 +694,18 @@ __device__ __forceinline__ void assign_block(const AssignArgs& A, int64_t blk,
                 tn = hasn ? fmaxf(tn, tw) : tw;
                 hasn = true;
               }
-              A.hub[r] = __builtin_inff();
-              A.hlb[r] = hasn ? lb_of(tn) : __builtin_inff();
+              A.bo.ub[r] = __builtin_inff();
+              A.bo.sec[r] = -1;
+              A.bo.lb[r] = hasn ? lb_of(tn) : __builtin_inff();
             }
           }
         } else {
           if (A.d2o) A.d2o[r] = __builtin_inff();
-          if (A.hub) {   // a single center
-            A.hub[r] = dist_up(xhi - 2.0 * ((double)t1 - (double)E - (double)off));
-            A.hlb[r] = __builtin_inff();
+          if (A.bo.ub) {   // a single center
+            A.bo.ub[r] = dist_up(xhi - 2.0 * ((double)t1 - (double)E - (double)off));
+            A.bo.sec[r] = -1;
+            A.bo.l2[r] = __builtin_inff();
+            A.bo.lb[r] = __builtin_inff();
           }
         }
       }
@@ -837,7 +849,7 @@ static hipError_t run_assign(hipStream_t s, const void* Xsrc, int64_t xs, int ve
                              int ib, const CenterStats* cs, int32_t* label, float* d1, float* d2,
                              FlagEntry* flags, int* full_rows, unsigned long long* full_ctr,
                              int cascade_all, int* brute, LoopState* st, const int* gate,
-                             int num_cus, float* hub, float* hlb) {
+                             int num_cus, BoundsOut bo) {
   if (kpad % BN != 0) return hipErrorInvalidValue;   // center padding must match the tile
   AssignArgs A;
   A.Xsrc = Xsrc;
@@ -867,8 +879,7 @@ static hipError_t run_assign(hipStream_t s, const void* Xsrc, int64_t xs, int ve
   A.brute = brute;
   A.st = st;
   A.count_undecided = rows == nullptr;
-  A.hub = hub;
-  A.hlb = hlb;
+  A.bo = bo;
   const int64_t ppb = (int64_t)WAVES * 16 * NCG;
   int64_t blocks = (n + ppb - 1) / ppb;
   if (rows) {
@@ -887,7 +898,7 @@ hipError_t launch_assign(hipStream_t s, int prec, const float* X, int64_t ldx, c
                          const void* Cq, const float* ch, int k, int kpad, const CenterStats* cs,
                          int32_t* label, float* d1, float* d2, FlagEntry* flags, int* full_rows,
                          unsigned long long* full_ctr, int cascade_all, int* brute, LoopState* st,
-                         const int* gate, int num_cus, float* hub, float* hlb) {
+                         const int* gate, int num_cus, BoundsOut bo) {
   int ib = 1;
   while ((1 << ib) < kpad) ++ib;
   const int nku = units_for(prec, d);
@@ -895,7 +906,7 @@ hipError_t launch_assign(hipStream_t s, int prec, const float* X, int64_t ldx, c
 #define KMX_A(NKU_, NCG_, BN_, W_, EP_)                                                          \
   return run_assign<1, NKU_, NCG_, BN_, W_, 1, EP_>(s, Xq, dp, 1, nullptr, n, rows, row_count, d, dp, rs, \
                                             Cq, ch, k, kpad, ib, cs, label, d1, d2, flags,      \
-                                            full_rows, full_ctr, cascade_all, brute, st, gate, num_cus, hub, hlb)
+                                            full_rows, full_ctr, cascade_all, brute, st, gate, num_cus, bo)
     switch (nku) {
       case 1: KMX_A(1, 4, 64, 8, false);
       case 2: KMX_A(2, 4, 64, 8, false);
@@ -916,7 +927,7 @@ hipError_t launch_assign(hipStream_t s, int prec, const float* X, int64_t ldx, c
 #define KMX_A(NKU_, NCG_, BN_, W_, EP_, SUB_)                                                \
   return run_assign<2, NKU_, NCG_, BN_, W_, 1, EP_, SUB_>(s, Xq, dp, 1, sx8, n, rows, row_count, d, dp, rs, \
                                             Cq, ch, k, kpad, ib, cs, label, d1, d2, flags,  \
-                                            full_rows, full_ctr, cascade_all, brute, st, gate, num_cus, hub, hlb)
+                                            full_rows, full_ctr, cascade_all, brute, st, gate, num_cus, bo)
     switch (nku) {
       case 1: KMX_A(1, 4, 64, 8, true, 1);
       case 2: KMX_A(2, 4, 64, 8, false, 1);
@@ -935,7 +946,7 @@ hipError_t launch_assign(hipStream_t s, int prec, const float* X, int64_t ldx, c
 #define KMX_A(NKU_, NCG_, BN_, W_)                                                               \
   return run_assign<0, NKU_, NCG_, BN_, W_>(s, X, ldx, vec_ok, nullptr, n, rows, row_count, d, \
                                             dp, rs, Cq, ch, k, kpad, ib, cs, label, d1, d2,     \
-                                            flags, full_rows, full_ctr, cascade_all, brute, st, gate, num_cus, hub, hlb)
+                                            flags, full_rows, full_ctr, cascade_all, brute, st, gate, num_cus, bo)
   switch (nku) {
     case 1: KMX_A(1, 4, 64, 8);
     case 2: KMX_A(2, 4, 64, 8);
@@ -1049,8 +1060,7 @@ __device__ __forceinline__ void batched_block(const BatchInst& I, int blk,
   A.brute = brute;
   A.st = st;
   A.count_undecided = 1;
-  A.hub = nullptr;
-  A.hlb = nullptr;
+  A.bo = BoundsOut();
   assign_block<1, NKU, NCG, BN, kBatchWaves, 1, false, 1>(A, blk, lds, hsh, wcnt, wbase);
 }
 

@@ -14,83 +14,148 @@
 namespace kmx {
 
 // Drift of every center: delta_j = ||c_new_j - c_old_j|| rounded up (FP64
-// sums of FP32 differences), and the largest two drifts with the index of the
-// largest.  One workgroup.
+// sums of FP32 differences), one wave per center.
 __global__ __launch_bounds__(1024) void drift_kernel(const float* __restrict__ Cold,
                                                      const float* __restrict__ Cnew, int k, int d,
                                                      float* __restrict__ drift,
-                                                     DriftStat* __restrict__ ds,
                                                      const int* __restrict__ gate) {
   if (gate && *gate) return;
-  __shared__ float m1s[16], m2s[16];
-  __shared__ int j1s[16];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  float m1 = 0.0f, m2 = 0.0f;
-  int j1 = -1;
-  for (int j = wave; j < k; j += 16) {
-    const float* a = Cold + (int64_t)j * d;
-    const float* b = Cnew + (int64_t)j * d;
-    double s = 0.0;
-    for (int e = lane; e < d; e += 64) {
-      const double df = (double)b[e] - (double)a[e];
-      s += df * df;
-    }
-    s = wave_sum_f64(s);
-    const float dj = dist_up(s);
-    if (lane == 0) drift[j] = dj;
-    if (dj > m1) { m2 = m1; m1 = dj; j1 = j; }
-    else m2 = fmaxf(m2, dj);
+  const int lane = threadIdx.x & 63;
+  const int j = blockIdx.x * 16 + (threadIdx.x >> 6);
+  if (j >= k) return;   // whole waves
+  const float* a = Cold + (int64_t)j * d;
+  const float* b = Cnew + (int64_t)j * d;
+  double s = 0.0;
+  for (int e = lane; e < d; e += 64) {
+    const double df = (double)b[e] - (double)a[e];
+    s += df * df;
   }
-  if (lane == 0) { m1s[wave] = m1; m2s[wave] = m2; j1s[wave] = j1; }
+  s = wave_sum_f64(s);
+  if (lane == 0) drift[j] = dist_up(s);
+}
+
+// The three largest drifts and the centers of the largest two (one workgroup).
+__global__ __launch_bounds__(1024) void drift_max_kernel(const float* __restrict__ drift, int k,
+                                                         DriftStat* __restrict__ ds,
+                                                         const int* __restrict__ gate) {
+  if (gate && *gate) return;
+  __shared__ float v1s[1024], v2s[1024], v3s[1024];
+  __shared__ int i1s[1024], i2s[1024];
+  float v1 = -1.0f, v2 = -1.0f, v3 = -1.0f;
+  int i1 = -1, i2 = -1;
+  auto ins = [&](float v, int j) {
+    if (v > v1) { v3 = v2; v2 = v1; i2 = i1; v1 = v; i1 = j; }
+    else if (v > v2) { v3 = v2; v2 = v; i2 = j; }
+    else if (v > v3) { v3 = v; }
+  };
+  for (int j = threadIdx.x; j < k; j += 1024) ins(drift[j], j);
+  v1s[threadIdx.x] = v1; v2s[threadIdx.x] = v2; v3s[threadIdx.x] = v3;
+  i1s[threadIdx.x] = i1; i2s[threadIdx.x] = i2;
   __syncthreads();
   if (threadIdx.x == 0) {
-    float a1 = m1s[0], a2 = m2s[0];
-    int aj = j1s[0];
-    for (int w = 1; w < 16; ++w) {
-      if (m1s[w] > a1) { a2 = fmaxf(a1, m2s[w]); a1 = m1s[w]; aj = j1s[w]; }
-      else a2 = fmaxf(a2, fmaxf(m1s[w], m2s[w]));
+    for (int t = 1; t < 1024; ++t) {
+      ins(v1s[t], i1s[t]);
+      ins(v2s[t], i2s[t]);
+      ins(v3s[t], -1);
     }
-    ds->max1 = a1;
-    ds->max2 = a2;
-    ds->arg1 = aj;
+    ds->max1 = fmaxf(v1, 0.0f);
+    ds->max2 = fmaxf(v2, 0.0f);
+    ds->max3 = fmaxf(v3, 0.0f);
+    ds->arg1 = i1;
+    ds->arg2 = i2;
   }
 }
 
-// The bound test over all rows: u += delta_a, l -= (largest drift of a center
-// other than a); rows with u < l keep their label, the others are listed in
-// fail_rows (counter st->bound_fail; one atomic per wave).
+// The bound test over all rows, for label a and runner-up b (sec, or -1):
+// u += delta_a, l2 -= delta_b, lb -= the largest drift of a center other than
+// a and b.  Rows with u < min(l2, lb) keep their label; rows with l2 <= u <
+// lb can only go to b, and go to the short re-check as the pair (a, b); the
+// others are listed in fail_rows (st->bound_fail).  A workgroup takes
+// kBoundRows consecutive rows (kBoundPer per thread), counts with ballots and
+// reserves its slices of both lists with one atomic each (same-address
+// atomics from every wave would serialize).
+constexpr int kBoundPer = 16;
+constexpr int kBoundRows = 256 * kBoundPer;
+
 __global__ __launch_bounds__(256) void bounds_test_kernel(int64_t n, const int32_t* __restrict__ label,
-                                                          float* __restrict__ hub,
-                                                          float* __restrict__ hlb,
+                                                          BoundsOut bo,
                                                           const float* __restrict__ drift,
                                                           const DriftStat* __restrict__ ds, int k,
                                                           int* __restrict__ fail_rows,
+                                                          FlagEntry* __restrict__ flags,
                                                           LoopState* __restrict__ st,
                                                           const int* __restrict__ gate) {
   if (gate && *gate) return;
-  const float m1 = ds->max1, m2 = ds->max2;
-  const int j1 = ds->arg1;
-  const int lane = threadIdx.x & 63;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  __shared__ int wcnt[2][4];
+  __shared__ unsigned long long wbase[2];
+  const float m1 = ds->max1, m2 = ds->max2, m3 = ds->max3;
+  const int j1 = ds->arg1, j2 = ds->arg2;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const unsigned long long below = (1ull << lane) - 1ull;
-  for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < n; i0 += stride) {
-    const int64_t i = i0 + threadIdx.x;
-    bool fail = false;
-    if (i < n) {
-      const int a = label[i];
-      const bool ok = a >= 0 && a < k;
-      const float da = ok ? drift[a] : __builtin_inff();
-      const float u = f64_to_f32_up((double)hub[i] + (double)da);
-      const float l = f64_to_f32_down((double)hlb[i] - (double)(a == j1 ? m2 : m1));
-      hub[i] = u;
-      hlb[i] = l;
-      fail = !(u < l);
+  const int64_t nchunks = (n + kBoundRows - 1) / kBoundRows;
+  for (int64_t chk = blockIdx.x; chk < nchunks; chk += gridDim.x) {
+    // row of slot q: chk * kBoundRows + q * 256 + threadIdx.x (coalesced)
+    const int64_t r0 = chk * kBoundRows + threadIdx.x;
+    unsigned fails = 0u, pairs = 0u;
+    int secs[kBoundPer];
+#pragma unroll 4
+    for (int q = 0; q < kBoundPer; ++q) {
+      const int64_t i = r0 + (int64_t)q * 256;
+      secs[q] = -1;
+      if (i < n) {
+        const int a = label[i];
+        int b = bo.sec[i];
+        if (b < 0 || b >= k || b == a) b = -1;
+        const bool ok = a >= 0 && a < k;
+        const float da = ok ? drift[a] : __builtin_inff();
+        const float dr = (j1 != a && j1 != b) ? m1 : ((j2 != a && j2 != b) ? m2 : m3);
+        const float u = f64_to_f32_up((double)bo.ub[i] + (double)da);
+        const float l = f64_to_f32_down((double)bo.lb[i] - (double)dr);
+        const float l2 = b >= 0 ? f64_to_f32_down((double)bo.l2[i] - (double)drift[b])
+                                : __builtin_inff();
+        bo.ub[i] = u;
+        bo.lb[i] = l;
+        if (b >= 0) bo.l2[i] = l2;
+        if (!(u < l)) fails |= 1u << q;
+        else if (!(u < l2)) { pairs |= 1u << q; secs[q] = b; }
+      }
     }
-    const unsigned long long bal = __ballot(fail);
-    unsigned long long base = 0;
-    if (lane == 0 && bal) base = atomicAdd(&st->bound_fail, (unsigned long long)__popcll(bal));
-    base = (unsigned long long)__shfl((long long)base, 0, 64);
-    if (fail) fail_rows[base + __popcll(bal & below)] = (int)i;
+    int cf = 0, cp = 0;
+#pragma unroll
+    for (int q = 0; q < kBoundPer; ++q) {
+      cf += __popcll(__ballot((fails >> q) & 1u));
+      cp += __popcll(__ballot((pairs >> q) & 1u));
+    }
+    if (lane == 0) { wcnt[0][wave] = cf; wcnt[1][wave] = cp; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const int tf = wcnt[0][0] + wcnt[0][1] + wcnt[0][2] + wcnt[0][3];
+      const int tp = wcnt[1][0] + wcnt[1][1] + wcnt[1][2] + wcnt[1][3];
+      wbase[0] = tf ? atomicAdd(&st->bound_fail, (unsigned long long)tf) : 0ull;
+      wbase[1] = tp ? atomicAdd(&st->flagged, (unsigned long long)tp) : 0ull;
+      if (tp) atomicAdd(&st->bound_pair, (unsigned long long)tp);
+    }
+    __syncthreads();
+    unsigned long long of = wbase[0], op = wbase[1];
+    for (int w = 0; w < wave; ++w) { of += wcnt[0][w]; op += wcnt[1][w]; }
+#pragma unroll
+    for (int q = 0; q < kBoundPer; ++q) {
+      const int64_t i = r0 + (int64_t)q * 256;
+      const unsigned long long bf = __ballot((fails >> q) & 1u);
+      const unsigned long long bp = __ballot((pairs >> q) & 1u);
+      if ((fails >> q) & 1u) fail_rows[of + __popcll(bf & below)] = (int)i;
+      if ((pairs >> q) & 1u) {
+        FlagEntry fe;
+        fe.row = (int)i;
+        fe.cand2 = secs[q];
+        fe.cand3 = -1;
+        fe.pad = 0;
+        flags[op + __popcll(bp & below)] = fe;
+      }
+      of += __popcll(bf);
+      op += __popcll(bp);
+    }
+    __syncthreads();
   }
 }
 
@@ -104,11 +169,12 @@ __global__ void copy_f32_kernel(const float* __restrict__ src, float* __restrict
     dst[i] = src[i];
 }
 
-// kept[slot] = rows the bound test kept (n - st->bound_fail), or 0 without st.
+// kept[slot] = rows the bound test kept (n - listed - paired), or 0 without st.
 __global__ void record_kept_kernel(const LoopState* __restrict__ st, int64_t* __restrict__ kept,
                                    int slot, int64_t n, const int* __restrict__ gate) {
   if (gate && *gate) return;
-  if (threadIdx.x == 0) kept[slot] = st ? n - (int64_t)st->bound_fail : 0;
+  if (threadIdx.x == 0)
+    kept[slot] = st ? n - (int64_t)st->bound_fail - (int64_t)st->bound_pair : 0;
 }
 
 hipError_t launch_copy_f32(hipStream_t s, const float* src, float* dst, int64_t count,
@@ -129,19 +195,23 @@ hipError_t launch_record_kept(hipStream_t s, const LoopState* st, int64_t* kept,
 
 hipError_t launch_drift(hipStream_t s, const float* Cold, const float* Cnew, int k, int d,
                         float* drift, DriftStat* ds, const int* gate) {
-  hipLaunchKernelGGL(drift_kernel, dim3(1), dim3(1024), 0, s, Cold, Cnew, k, d, drift, ds, gate);
+  hipLaunchKernelGGL(drift_kernel, dim3((unsigned)((k + 15) / 16)), dim3(1024), 0, s, Cold, Cnew, k,
+                     d, drift, gate);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(drift_max_kernel, dim3(1), dim3(1024), 0, s, drift, k, ds, gate);
   return hipGetLastError();
 }
 
-hipError_t launch_bounds_test(hipStream_t s, int64_t n, const int32_t* label, float* hub,
-                              float* hlb, const float* drift, const DriftStat* ds, int k,
-                              int* fail_rows, LoopState* st, const int* gate, int num_cus) {
-  int64_t blocks = (n + 255) / 256;
-  const int64_t cap = (int64_t)num_cus * 16;
+hipError_t launch_bounds_test(hipStream_t s, int64_t n, const int32_t* label, BoundsOut bo,
+                              const float* drift, const DriftStat* ds, int k, int* fail_rows,
+                              FlagEntry* flags, LoopState* st, const int* gate, int num_cus) {
+  int64_t blocks = (n + kBoundRows - 1) / kBoundRows;
+  const int64_t cap = (int64_t)num_cus * 8;
   if (blocks > cap) blocks = cap;
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(bounds_test_kernel, dim3((unsigned)blocks), dim3(256), 0, s, n, label, hub,
-                     hlb, drift, ds, k, fail_rows, st, gate);
+  hipLaunchKernelGGL(bounds_test_kernel, dim3((unsigned)blocks), dim3(256), 0, s, n, label, bo,
+                     drift, ds, k, fail_rows, flags, st, gate);
   return hipGetLastError();
 }
 

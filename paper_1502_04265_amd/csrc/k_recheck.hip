@@ -83,22 +83,31 @@ __device__ __forceinline__ void plain_dist3(const float* __restrict__ x,
   p2 = a2;
 }
 
-// Carried bounds of a re-checked row (when kept): the upper bound of the
-// winner's distance and the lower bound of every other center's, from the
-// plain distances (relative error below tol each, taken twice); the lower
-// bound the listing pass stored for the centers not listed is kept when
-// smaller.
-__device__ __forceinline__ void pair_bounds(float* __restrict__ hub, float* __restrict__ hlb,
-                                            int row, const float* p, const int* cj, int nc,
-                                            int best, float tol) {
+// Carried bounds of a re-checked row (when kept), from the plain distances
+// (relative error below tol each, taken twice): the winner's upper bound, the
+// closest other candidate as the runner-up, and a third candidate folded into
+// the bound of the centers not listed (which the listing pass stored).
+__device__ __forceinline__ void pair_bounds(const BoundsOut& bo, int row, const float* p,
+                                            const int* cj, int nc, int best, float tol) {
   const double t2 = 2.0 * (double)tol;
-  double ub2 = 0.0, ru2 = 1e308;
+  double ub2 = 0.0, ru2 = 1e308, th2 = 1e308;
+  int ru = -1;
   for (int q = 0; q < nc; ++q) {
-    if (cj[q] == best) ub2 = (double)p[q];
-    else ru2 = fmin(ru2, (double)p[q]);
+    const double v = (double)p[q];
+    if (cj[q] == best) {
+      ub2 = v;
+    } else if (v < ru2) {
+      th2 = ru2;
+      ru2 = v;
+      ru = cj[q];
+    } else {
+      th2 = fmin(th2, v);
+    }
   }
-  hub[row] = dist_up(ub2 * (1.0 + t2));
-  hlb[row] = fminf(hlb[row], dist_down(ru2 * (1.0 - t2)));
+  bo.ub[row] = dist_up(ub2 * (1.0 + t2));
+  bo.sec[row] = ru;
+  bo.l2[row] = dist_down(ru2 * (1.0 - t2));
+  if (th2 < 1e300) bo.lb[row] = fminf(bo.lb[row], dist_down(th2 * (1.0 - t2)));
 }
 
 template <int G>
@@ -106,7 +115,7 @@ __global__ __launch_bounds__(256) void recheck_pair_kernel(
     const float* __restrict__ X, int64_t n, int d, int64_t ldx, const float* __restrict__ C,
     int k, int32_t* __restrict__ label, float* __restrict__ d1o,
     const FlagEntry* __restrict__ flags, const LoopState* __restrict__ st,
-    const int* __restrict__ gate, float* __restrict__ hub, float* __restrict__ hlb) {
+    const int* __restrict__ gate, BoundsOut bo) {
   if (gate && *gate) return;
   constexpr int SPW = 64 / G;          // entries per wave at once
   const int64_t cnt = (int64_t)st->flagged;
@@ -164,7 +173,7 @@ __global__ __launch_bounds__(256) void recheck_pair_kernel(
     if (gl == 0) {
       label[row] = best;
       if (d1o) d1o[row] = bd;
-      if (hub) pair_bounds(hub, hlb, row, p, cj, nc, best, tol);
+      if (bo.ub) pair_bounds(bo, row, p, cj, nc, best, tol);
     }
   }
 }
@@ -231,7 +240,7 @@ __global__ __launch_bounds__(256) void recheck_pair_pipe_kernel(
     const float* __restrict__ X, int64_t n, int d, int64_t ldx, const float* __restrict__ C,
     int k, int32_t* __restrict__ label, float* __restrict__ d1o,
     const FlagEntry* __restrict__ flags, const LoopState* __restrict__ st,
-    const int* __restrict__ gate, float* __restrict__ hub, float* __restrict__ hlb) {
+    const int* __restrict__ gate, BoundsOut bo) {
   if (gate && *gate) return;
   constexpr int SPW = 64 / G;          // entries per wave at once
   const int64_t cnt = (int64_t)st->flagged;
@@ -291,7 +300,7 @@ __global__ __launch_bounds__(256) void recheck_pair_pipe_kernel(
       if (gl == 0) {
         label[row] = best;
         if (d1o) d1o[row] = bd;
-        if (hub) pair_bounds(hub, hlb, row, p, cj, nc, best, tol);
+        if (bo.ub) pair_bounds(bo, row, p, cj, nc, best, tol);
       }
     }
     fe_c = fe_n;
@@ -357,8 +366,8 @@ __device__ __forceinline__ void plain_dist4(const float* __restrict__ x,
 __global__ __launch_bounds__(kFullWaves * 64) void recheck_full_kernel(
     const float* __restrict__ X, int64_t n, int d, int64_t ldx, const float* __restrict__ C,
     int k, int32_t* __restrict__ label, float* __restrict__ d1o, const int* __restrict__ brute,
-    const LoopState* __restrict__ st, const int* __restrict__ gate, float* __restrict__ hub,
-    float* __restrict__ hlb) {
+    const LoopState* __restrict__ st, const int* __restrict__ gate, BoundsOut bo,
+    float* __restrict__ d2o) {
   if (gate && *gate) return;
   __shared__ float redf[kFullWaves], redf2[kFullWaves];
   __shared__ int redfj[kFullWaves];
@@ -423,13 +432,16 @@ __global__ __launch_bounds__(kFullWaves * 64) void recheck_full_kernel(
       if (best < k) {
         label[row] = best;
         if (d1o) d1o[row] = bh;
-        if (hub) {
+        // second smallest plain distance (+inf for k = 1)
+        if (d2o) d2o[row] = (jm == best) ? m2 : m;
+        if (bo.ub) {
           // the winner's exact distance; every other center's plain
           // distance is at least m2, or m when the plain minimum is not the
-          // winner
+          // winner (no runner-up kept)
           const double g2 = 2.0 * (double)gam;
-          hub[row] = dist_up((double)bh + (double)bl + fabs((double)bh) * 0x1p-40);
-          hlb[row] = dist_down((double)(jm == best ? m2 : m) * (1.0 - g2));
+          bo.ub[row] = dist_up((double)bh + (double)bl + fabs((double)bh) * 0x1p-40);
+          bo.sec[row] = -1;
+          bo.lb[row] = dist_down((double)(jm == best ? m2 : m) * (1.0 - g2));
         }
       }
     }
@@ -460,6 +472,30 @@ __global__ __launch_bounds__(1024) void route_small_kernel(unsigned long long* _
   }
 }
 
+__global__ void list_all_kernel(int* __restrict__ brute, int64_t n, const int* __restrict__ rows,
+                                const unsigned long long* __restrict__ row_count,
+                                LoopState* __restrict__ st, const int* __restrict__ gate) {
+  if (gate && *gate) return;
+  const int64_t m = rows ? (int64_t)(*row_count) : n;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride)
+    brute[i] = rows ? rows[i] : (int)i;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->flagged_full = (unsigned long long)m;
+    st->undecided = (unsigned long long)m;
+  }
+}
+
+hipError_t launch_list_all(hipStream_t s, int* brute, int64_t n, const int* rows,
+                           const unsigned long long* row_count, LoopState* st, const int* gate) {
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 2048) blocks = 2048;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(list_all_kernel, dim3((unsigned)blocks), dim3(256), 0, s, brute, n, rows,
+                     row_count, st, gate);
+  return hipGetLastError();
+}
+
 hipError_t launch_route_small(hipStream_t s, unsigned long long* ctr, const int* list, int* brute,
                               LoopState* st, int k, int d, const int* gate) {
   const unsigned long long lim =
@@ -472,7 +508,7 @@ hipError_t launch_route_small(hipStream_t s, unsigned long long* ctr, const int*
 hipError_t launch_recheck(hipStream_t s, const float* X, int64_t n, int d, int64_t ldx,
                           const float* C, int k, int32_t* label, float* d1,
                           const FlagEntry* flags, const int* brute, const LoopState* st,
-                          int num_cus, const int* gate, float* hub, float* hlb) {
+                          int num_cus, const int* gate, BoundsOut bo, float* d2) {
   int64_t blocks = (n + 3) / 4;
   int64_t cap = (int64_t)num_cus * 8;
   if (blocks > cap) blocks = cap;
@@ -483,19 +519,19 @@ hipError_t launch_recheck(hipStream_t s, const float* X, int64_t n, int d, int64
                    ((((uintptr_t)C) & 15) == 0) && (d % 4 == 0);
   if (kRecheckPipe && vec && d <= 64)
     hipLaunchKernelGGL((recheck_pair_pipe_kernel<16, 1>), dim3((unsigned)blocks), dim3(256), 0, s,
-                       X, n, d, ldx, C, k, label, d1, flags, st, gate, hub, hlb);
+                       X, n, d, ldx, C, k, label, d1, flags, st, gate, bo);
   else if (kRecheckPipe && vec && d <= 128)
     hipLaunchKernelGGL((recheck_pair_pipe_kernel<16, 2>), dim3((unsigned)blocks), dim3(256), 0, s,
-                       X, n, d, ldx, C, k, label, d1, flags, st, gate, hub, hlb);
+                       X, n, d, ldx, C, k, label, d1, flags, st, gate, bo);
   else if (d <= 256)
     hipLaunchKernelGGL(recheck_pair_kernel<16>, dim3((unsigned)blocks), dim3(256), 0, s, X, n,
-                       d, ldx, C, k, label, d1, flags, st, gate, hub, hlb);
+                       d, ldx, C, k, label, d1, flags, st, gate, bo);
   else if (d <= 1024)
     hipLaunchKernelGGL(recheck_pair_kernel<32>, dim3((unsigned)blocks), dim3(256), 0, s, X, n,
-                       d, ldx, C, k, label, d1, flags, st, gate, hub, hlb);
+                       d, ldx, C, k, label, d1, flags, st, gate, bo);
   else
     hipLaunchKernelGGL(recheck_pair_kernel<64>, dim3((unsigned)blocks), dim3(256), 0, s, X, n,
-                       d, ldx, C, k, label, d1, flags, st, gate, hub, hlb);
+                       d, ldx, C, k, label, d1, flags, st, gate, bo);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   cap = (int64_t)num_cus * 4;
@@ -503,7 +539,7 @@ hipError_t launch_recheck(hipStream_t s, const float* X, int64_t n, int d, int64
   if (blocks > cap) blocks = cap;
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(recheck_full_kernel, dim3((unsigned)blocks), dim3(kFullWaves * 64), 0, s, X, n, d, ldx,
-                     C, k, label, d1, brute, st, gate, hub, hlb);
+                     C, k, label, d1, brute, st, gate, bo, d2);
   return hipGetLastError();
 }
 

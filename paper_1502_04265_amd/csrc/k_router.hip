@@ -484,8 +484,7 @@ __global__ __launch_bounds__(256) void router_cert_kernel(
     const int32_t* __restrict__ nbr, const float* __restrict__ nbd, int32_t* __restrict__ label,
     FlagEntry* __restrict__ flags, int* __restrict__ fb_rows, LoopState* __restrict__ st,
     const int* __restrict__ gate, const int* __restrict__ rows,
-    const unsigned long long* __restrict__ row_count, float* __restrict__ hub,
-    float* __restrict__ hlb) {
+    const unsigned long long* __restrict__ row_count, BoundsOut bo) {
   if (gate && *gate) return;
   // rows != nullptr: the points are rows[0 .. *row_count) instead of 0 .. n
   const int64_t npts = rows ? (int64_t)(*row_count) : n;
@@ -619,9 +618,10 @@ __global__ __launch_bounds__(256) void router_cert_kernel(
         rn0[rec] = n0;
         rn1[rec] = (m == 2) ? n1 : -1;
         if (kd <= 1) label[r] = b0;
-        if (hub && kd <= 1) {
-          hub[r] = kd == 0 ? dub : __builtin_inff();
-          hlb[r] = f64_to_f32_down((double)ndm - (double)dub);
+        if (bo.ub && kd <= 1) {
+          bo.ub[r] = kd == 0 ? dub : __builtin_inff();
+          bo.sec[r] = -1;
+          bo.lb[r] = f64_to_f32_down((double)ndm - (double)dub);
         }
       }
     }
@@ -683,7 +683,7 @@ hipError_t launch_router_cert(hipStream_t s, const uint16_t* Xq, int64_t dp, int
                               int kpad, const int32_t* nbr, const float* nbd, int32_t* label,
                               FlagEntry* flags, int* fb_rows, LoopState* st, const int* gate,
                               int num_cus, const int* rows, const unsigned long long* row_count,
-                              float* hub, float* hlb) {
+                              BoundsOut bo) {
   int ib = 1;
   while ((1 << ib) < kpad) ++ib;
   // one 1024-row chunk per workgroup up to 32 per CU
@@ -701,7 +701,7 @@ hipError_t launch_router_cert(hipStream_t s, const uint16_t* Xq, int64_t dp, int
 #define KMX_C(R_, NX_, F_)                                                                    \
   hipLaunchKernelGGL((router_cert_kernel<R_, NX_, F_>), dim3((unsigned)blocks), dim3(256), 0, \
                      s, Xq, dp, n, d, C, k, rs, keys, ib, nbr, nbd, label, flags, fb_rows, st, \
-                     gate, rows, row_count, hub, hlb)
+                     gate, rows, row_count, bo)
 #define KMX_CN(R_)                                                 \
   switch (nx) {                                                    \
     case 1: if (full) KMX_C(R_, 1, true); else KMX_C(R_, 1, false); break; \

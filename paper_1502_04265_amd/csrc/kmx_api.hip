@@ -31,13 +31,13 @@ kmx_status check_problem(kmx_ctx* ctx, const float* X, int64_t n, int32_t d, int
   return KMX_OK;
 }
 
-kmx_status check_prec(kmx_ctx* ctx, int prec, int d) {
+kmx_status check_prec(kmx_ctx* ctx, int prec, int d, bool allow_wide) {
   if (prec != KMX_FP32 && prec != KMX_BF16 && prec != KMX_FP8E4M3)
     return fail(ctx, KMX_EINVAL, "unknown precision");
-  const int dmax = (prec == KMX_BF16) ? 1053 : 1024;
-  if (d > dmax || d > 1024)
+  if (d > kGemmMaxD && !allow_wide)
     return fail(ctx, KMX_EUNSUPPORTED,
-                "assignment supports d <= " + std::to_string(dmax) + ", got " + std::to_string(d));
+                "this call supports d <= " + std::to_string(kGemmMaxD) + ", got " +
+                    std::to_string(d));
   return KMX_OK;
 }
 
@@ -80,6 +80,7 @@ kmx_status check_data(kmx_ctx* ctx, const float* X, int64_t n, int d, int64_t ld
 // Row statistics and (BF16) the quantized copy of X, cached per dataset.  The
 // BF16 preparation also serves the FP32 path (which only reads ||x||).
 kmx_status ensure_prep(kmx_ctx* ctx, const float* X, int64_t n, int d, int64_t ldx, int prec) {
+  if (d > kGemmMaxD) return KMX_OK;   // wide rows: no GEMM operands (see run_assign_gemm)
   if (prec == KMX_FP8E4M3) {
     KMX_TRY(ensure_prep(ctx, X, n, d, ldx, KMX_BF16));   // the cascade's BF16 pass
     if (ctx->cache8_valid && ctx->cache8_X == X && ctx->cache8_n == n && ctx->cache8_d == d &&
@@ -174,6 +175,10 @@ kmx_status run_prep_centers(kmx_ctx* ctx, const float* C, int k, int d, int prec
   CenterStats* cs = P<CenterStats>(ctx->cstats);
   CenterStats* cs32 = P<CenterStats>(ctx->cstats32);
   CenterStats* cs8 = P<CenterStats>(ctx->cstats8);
+  if (d > kGemmMaxD) {   // wide rows: only the per-assignment counters
+    KMX_HIP(ctx, launch_reset_small(ctx->stream, cs, cs32, cs8, st, 0));
+    return KMX_OK;
+  }
   const int dp32 = assign_dpad(KMX_FP32, d);
   const int bn32 = assign_tile_n(KMX_FP32, d, k);
   const int kpad32 = (k + bn32 - 1) / bn32 * bn32;
@@ -216,8 +221,20 @@ kmx_status run_prep_centers(kmx_ctx* ctx, const float* C, int k, int d, int prec
 kmx_status run_assign_gemm(kmx_ctx* ctx, const float* X, int64_t n, int d, int64_t ldx,
                            const float* C, int k, int prec, int32_t* label, float* d1,
                            float* d2, const int* rows, const unsigned long long* row_count,
-                           const int* gate, float* hub, float* hlb) {
+                           const int* gate, BoundsOut bo) {
   LoopState* st = ST(ctx);
+  if (d > kGemmMaxD) {
+    // Rows wider than the GEMM's register-resident point fragments: every row
+    // (or every listed row) goes to the every-center re-check, which computes
+    // the plain FP32 distances to all centers and decides the candidates
+    // within their error bound by double-float sums (exact labels).
+    ctx->last_prec = prec;
+    Timed tm(ctx, T_RECHECK);
+    KMX_HIP(ctx, launch_list_all(ctx->stream, P<int>(ctx->brute), n, rows, row_count, st, gate));
+    KMX_HIP(ctx, launch_recheck(ctx->stream, X, n, d, ldx, C, k, label, d1, P<FlagEntry>(ctx->flags),
+                                P<int>(ctx->brute), st, ctx->num_cus, gate, bo, d2));
+    return KMX_OK;
+  }
   CenterStats* cs = P<CenterStats>(ctx->cstats);
   CenterStats* cs32 = P<CenterStats>(ctx->cstats32);
   CenterStats* cs8 = P<CenterStats>(ctx->cstats8);
@@ -233,7 +250,7 @@ kmx_status run_assign_gemm(kmx_ctx* ctx, const float* X, int64_t n, int d, int64
     KMX_HIP(ctx, launch_assign(ctx->stream, KMX_FP32, X, ldx, nullptr, nullptr, n, rows,
                                row_count, d, dp32, rs, ctx->cq32.p, P<float>(ctx->ch32), k,
                                kpad32, cs32, label, d1, d2, flags, nullptr, nullptr, 0, brute,
-                               st, gate, ctx->num_cus, hub, hlb));
+                               st, gate, ctx->num_cus, bo));
   } else {
     const int dp = assign_dpad(KMX_BF16, d);
     const int bn = assign_tile_n(KMX_BF16, d, k);
@@ -252,7 +269,7 @@ kmx_status run_assign_gemm(kmx_ctx* ctx, const float* X, int64_t n, int d, int64
                                  P<uint8_t>(ctx->sx8), n, rows, row_count, d, dp8,
                                  P<RowStats>(ctx->rowstats8), ctx->cq8.p, P<float>(ctx->ch8), k,
                                  kpad8, cs8, label, d1, d2, flags, P<int>(ctx->full_rows),
-                                 &st->full_count, 0, brute, st, gate, ctx->num_cus, hub, hlb));
+                                 &st->full_count, 0, brute, st, gate, ctx->num_cus, bo));
       rows16 = P<int>(ctx->full_rows);
       cnt16 = &st->full_count;
       next16 = P<int>(ctx->full_rows2);
@@ -263,8 +280,7 @@ kmx_status run_assign_gemm(kmx_ctx* ctx, const float* X, int64_t n, int d, int64
       KMX_HIP(ctx, launch_assign(ctx->stream, KMX_BF16, X, ldx, ctx->xq.p, nullptr, n, rows16,
                                  cnt16, d, dp, rs, ctx->cq.p, P<float>(ctx->ch), k, kpad, cs,
                                  label, d1, d2,
-                                 flags, next16, ctr16, 0, brute, st, gate, ctx->num_cus, hub,
-                                 hlb));
+                                 flags, next16, ctr16, 0, brute, st, gate, ctx->num_cus, bo));
     }
     {
       Timed tm(ctx, T_RECHECK);
@@ -272,13 +288,13 @@ kmx_status run_assign_gemm(kmx_ctx* ctx, const float* X, int64_t n, int d, int64
       KMX_HIP(ctx, launch_assign(ctx->stream, KMX_FP32, X, ldx, nullptr, nullptr, n, next16,
                                  ctr16, d, dp32, rs, ctx->cq32.p, P<float>(ctx->ch32), k, kpad32,
                                  cs32, label, d1, d2, flags, nullptr, nullptr, 0, brute, st, gate,
-                                 ctx->num_cus, hub, hlb));
+                                 ctx->num_cus, bo));
     }
   }
   {
     Timed tm(ctx, T_RECHECK);
     KMX_HIP(ctx, launch_recheck(ctx->stream, X, n, d, ldx, C, k, label, d1, flags, brute, st,
-                                ctx->num_cus, gate, hub, hlb));
+                                ctx->num_cus, gate, bo));
   }
   return KMX_OK;
 }
@@ -380,7 +396,7 @@ kmx_status kmx_destroy(kmx_ctx* ctx) {
       &ctx->d2,        &ctx->flags,    &ctx->counters,   &ctx->counts,     &ctx->segsum,
       &ctx->base,      &ctx->chunk_base, &ctx->perm,     &ctx->partS,      &ctx->partQ,
       &ctx->partW,     &ctx->W,        &ctx->termC,      &ctx->termMu,     &ctx->state,     &ctx->vcheck,    &ctx->hub,
-      &ctx->hlb,       &ctx->bl_rows,  &ctx->cprev,      &ctx->drift,      &ctx->dstat,
+      &ctx->hlb,       &ctx->hl2,      &ctx->hsec,       &ctx->bl_rows,  &ctx->cprev,      &ctx->drift,      &ctx->dstat,
       &ctx->bkh,
       &ctx->D2,        &ctx->chosen,   &ctx->seed_part,  &ctx->seed_ctr,   &ctx->scratch_c,
       &ctx->seed_a,    &ctx->seed_cc,  &ctx->seed_nread,
@@ -475,7 +491,7 @@ kmx_status kmx_assign(kmx_ctx* ctx, const float* X, int64_t n, int32_t d, int64_
   if (!ctx) return KMX_EINVAL;
   ctx->err.clear();
   KMX_TRY(check_problem(ctx, X, n, d, ldx, k));
-  KMX_TRY(check_prec(ctx, prec, d));
+  KMX_TRY(check_prec(ctx, prec, d, true));
   if (!C) return fail(ctx, KMX_EINVAL, "C is NULL");
   if (!label_out) return fail(ctx, KMX_EINVAL, "label_out is NULL");
   KMX_TRY(set_device(ctx));
@@ -522,7 +538,7 @@ kmx_status kmx_cost(kmx_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t 
   if (!ctx) return KMX_EINVAL;
   ctx->err.clear();
   KMX_TRY(check_problem(ctx, X, n, d, ldx, k));
-  KMX_TRY(check_prec(ctx, prec, d));
+  KMX_TRY(check_prec(ctx, prec, d, true));
   if (!C || !cost_out) return fail(ctx, KMX_EINVAL, "NULL C or cost_out");
   KMX_TRY(set_device(ctx));
   KMX_TRY(check_data(ctx, X, n, d, ldx, w, 0, C, k));
@@ -550,7 +566,7 @@ static kmx_status lloyd_impl(kmx_ctx* ctx, const float* X, int64_t n, int32_t d,
   if (!ctx) return KMX_EINVAL;
   ctx->err.clear();
   KMX_TRY(check_problem(ctx, X, n, d, ldx, k));
-  KMX_TRY(check_prec(ctx, prec, d));
+  KMX_TRY(check_prec(ctx, prec, d, true));
   if (!C_inout || !cost_hist || !iters_done)
     return fail(ctx, KMX_EINVAL, "NULL C_inout, cost_hist or iters_done");
   if (max_iter < 0) return fail(ctx, KMX_EINVAL, "max_iter must be >= 0");

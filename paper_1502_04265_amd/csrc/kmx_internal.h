@@ -56,6 +56,7 @@ struct LoopState {
   unsigned long long routed_fallback;  // rows the certificate sent to the GEMM (last assign)
   unsigned long long routed_listed;    // certified rows that needed the short re-check
   unsigned long long bound_fail;       // rows the carried bounds could not keep (last assign)
+  unsigned long long bound_pair;       // rows they sent to the re-check with their runner-up
 };
 
 // Entry of the short re-check list: row index and the other candidates (the
@@ -98,9 +99,20 @@ struct BatchInst {
 // Center drift of one Lloyd step (the bound-carrying assignment): the two
 // largest drifts and the center of the largest.
 struct DriftStat {
-  float max1, max2;
-  int arg1;
-  int pad;
+  float max1, max2, max3;
+  int arg1, arg2;
+  int pad[3];
+};
+
+// Bounds carried across Lloyd iterations, one entry per row (all nullable
+// together).  For label a: ub >= ||x - c_a||; sec = a runner-up center b (or
+// -1), l2 <= ||x - c_b||; lb <= ||x - c|| for every other center c (not a,
+// not b).  Distances, not squares; rounded outward.
+struct BoundsOut {
+  float* ub = nullptr;
+  float* lb = nullptr;
+  float* l2 = nullptr;
+  int* sec = nullptr;
 };
 
 struct BatchItem {
@@ -134,6 +146,7 @@ constexpr int kReduceRows = 512;    // rows per segmented-reduction chunk
 constexpr int kSeedRows = 2048;     // rows per seeding block
 constexpr int kScanSegs = 64;       // column-scan segments
 constexpr int kMaxK = 16384;        // largest k (LDS histograms)
+constexpr int kGemmMaxD = 1024;     // widest row the GEMM passes take (wider: every-center re-check)
 // FP32-pass lists of at most kShortList rows go to the every-center re-check
 // instead when k d >= kShortListMinKD: the pass then costs one workgroup's
 // walk over many long centers however few rows it has, while for small k d
@@ -187,7 +200,7 @@ struct kmx_ctx {
   kmx::Buf D2, chosen, seed_part, seed_ctr, seed_a, seed_cc, seed_nread;
   kmx::Buf scratch_c, hist;
   kmx::Buf fb_rows, keys, cdist, nbr, nbd, fbh;   // routed assignment
-  kmx::Buf hub, hlb, bl_rows, cprev, drift, dstat, bkh;   // carried bounds
+  kmx::Buf hub, hlb, hl2, hsec, bl_rows, cprev, drift, dstat, bkh;   // carried bounds
   // batched Lloyd: concatenated instances and their descriptors
   kmx::Buf vt;                          // transposed projection basis
   kmx::Buf bX, bXq, brs, bw, bC, bCq, bhd, bch, bcs, blab, bitems, binsts, bbuckets, bcinst, bxstats;
@@ -247,8 +260,7 @@ hipError_t launch_assign(hipStream_t s, int prec, const float* X, int64_t ldx,
                          int k, int kpad, const CenterStats* cs, int32_t* label,
                          float* d1, float* d2, FlagEntry* flags, int* full_rows,
                          unsigned long long* full_ctr, int cascade_all, int* brute,
-                         LoopState* st, const int* gate, int num_cus, float* hub = nullptr,
-                         float* hlb = nullptr);
+                         LoopState* st, const int* gate, int num_cus, BoundsOut bo = {});
 // count instances of one matrix instruction of the assignment (FP8 16x16x128
 // scaled, BF16 16x16x32 or FP32 16x16x4) from C (nullable: zero)
 hipError_t launch_mfma_probe(hipStream_t s, int prec, const uint8_t* A, const uint8_t* B,
@@ -257,8 +269,12 @@ hipError_t launch_mfma_probe(hipStream_t s, int prec, const uint8_t* A, const ui
 hipError_t launch_recheck(hipStream_t s, const float* X, int64_t n, int d, int64_t ldx,
                           const float* C, int k, int32_t* label, float* d1,
                           const FlagEntry* flags, const int* brute, const LoopState* st,
-                          int num_cus, const int* gate, float* hub = nullptr,
-                          float* hlb = nullptr);
+                          int num_cus, const int* gate, BoundsOut bo = {}, float* d2 = nullptr);
+// brute[0 .. m) = rows[0 .. m) (m = *row_count) or 0 .. n - 1, and
+// st->flagged_full = st->undecided = m: every listed row to the every-center
+// re-check (the assignment of rows wider than the GEMM takes)
+hipError_t launch_list_all(hipStream_t s, int* brute, int64_t n, const int* rows,
+                           const unsigned long long* row_count, LoopState* st, const int* gate);
 // Moves a list meant for the FP32 GEMM pass onto the every-center re-check
 // list when it holds at most kShortList rows and k d >= kShortListMinKD (one
 // workgroup; gate as above).
@@ -321,9 +337,12 @@ hipError_t launch_batch_labels(hipStream_t s, const int32_t* glabel, int64_t gro
 // carried bounds (k_bounds.hip)
 hipError_t launch_drift(hipStream_t s, const float* Cold, const float* Cnew, int k, int d,
                         float* drift, DriftStat* ds, const int* gate);
-hipError_t launch_bounds_test(hipStream_t s, int64_t n, const int32_t* label, float* hub,
-                              float* hlb, const float* drift, const DriftStat* ds, int k,
-                              int* fail_rows, LoopState* st, const int* gate, int num_cus);
+// rows whose bounds keep their label are left alone; rows where only the
+// runner-up can win go to the short re-check list (flags, st->flagged) as a
+// pair; the others to fail_rows (st->bound_fail)
+hipError_t launch_bounds_test(hipStream_t s, int64_t n, const int32_t* label, BoundsOut bo,
+                              const float* drift, const DriftStat* ds, int k, int* fail_rows,
+                              FlagEntry* flags, LoopState* st, const int* gate, int num_cus);
 hipError_t launch_copy_f32(hipStream_t s, const float* src, float* dst, int64_t count,
                            const int* gate);
 hipError_t launch_record_kept(hipStream_t s, const LoopState* st, int64_t* kept, int slot,
@@ -353,8 +372,7 @@ hipError_t launch_router_cert(hipStream_t s, const uint16_t* Xq, int64_t dp, int
                               int kpad, const int32_t* nbr, const float* nbd, int32_t* label,
                               FlagEntry* flags, int* fb_rows, LoopState* st, const int* gate,
                               int num_cus, const int* rows = nullptr,
-                              const unsigned long long* row_count = nullptr, float* hub = nullptr,
-                              float* hlb = nullptr);
+                              const unsigned long long* row_count = nullptr, BoundsOut bo = {});
 hipError_t launch_record_fallback(hipStream_t s, const LoopState* st, int64_t* fbh, int slot,
                                   int all_rows, int64_t all, const int* gate);
 

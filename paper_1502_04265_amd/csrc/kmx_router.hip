@@ -446,18 +446,21 @@ static kmx_status lloyd_routed_impl(kmx_ctx* ctx, kmx_router* r, const float* X,
   KMX_TRY(grow(ctx, ctx->nbr, (size_t)k * kNbrL * sizeof(int32_t)));
   KMX_TRY(grow(ctx, ctx->nbd, (size_t)k * (kNbrL + 1) * sizeof(float)));
   KMX_TRY(grow(ctx, ctx->fbh, (size_t)(max_iter + 1) * sizeof(int64_t)));
-  float* hub = nullptr;
-  float* hlb = nullptr;
+  BoundsOut bo;
   if (bounded) {
     KMX_TRY(grow(ctx, ctx->hub, (size_t)n * sizeof(float)));
     KMX_TRY(grow(ctx, ctx->hlb, (size_t)n * sizeof(float)));
+    KMX_TRY(grow(ctx, ctx->hl2, (size_t)n * sizeof(float)));
+    KMX_TRY(grow(ctx, ctx->hsec, (size_t)n * sizeof(int)));
     KMX_TRY(grow(ctx, ctx->bl_rows, (size_t)n * sizeof(int)));
     KMX_TRY(grow(ctx, ctx->cprev, (size_t)k * d * sizeof(float)));
     KMX_TRY(grow(ctx, ctx->drift, (size_t)k * sizeof(float)));
     KMX_TRY(grow(ctx, ctx->dstat, sizeof(DriftStat)));
     KMX_TRY(grow(ctx, ctx->bkh, (size_t)(max_iter + 1) * sizeof(int64_t)));
-    hub = P<float>(ctx->hub);
-    hlb = P<float>(ctx->hlb);
+    bo.ub = P<float>(ctx->hub);
+    bo.lb = P<float>(ctx->hlb);
+    bo.l2 = P<float>(ctx->hl2);
+    bo.sec = P<int>(ctx->hsec);
   }
   const int dp = assign_dpad(KMX_BF16, d);
   const uint32_t* keys = nullptr;
@@ -490,9 +493,9 @@ static kmx_status lloyd_routed_impl(kmx_ctx* ctx, kmx_router* r, const float* X,
     if (bounded && t > 0) {
       {
         Timed tm(ctx, T_BOUND);
-        KMX_HIP(ctx, launch_bounds_test(ctx->stream, n, lab, hub, hlb, P<float>(ctx->drift),
-                                        P<DriftStat>(ctx->dstat), k, P<int>(ctx->bl_rows), st,
-                                        gate, ctx->num_cus));
+        KMX_HIP(ctx, launch_bounds_test(ctx->stream, n, lab, bo, P<float>(ctx->drift),
+                                        P<DriftStat>(ctx->dstat), k, P<int>(ctx->bl_rows),
+                                        P<FlagEntry>(ctx->flags), st, gate, ctx->num_cus));
       }
       {
         Timed tm(ctx, T_CERT);
@@ -502,18 +505,17 @@ static kmx_status lloyd_routed_impl(kmx_ctx* ctx, kmx_router* r, const float* X,
                                         P<RowStats>(ctx->rowstats), keys, kpad_r,
                                         P<int32_t>(ctx->nbr), P<float>(ctx->nbd), lab,
                                         P<FlagEntry>(ctx->flags), P<int>(ctx->fb_rows), st, gate,
-                                        ctx->num_cus, P<int>(ctx->bl_rows), &st->bound_fail, hub,
-                                        hlb));
+                                        ctx->num_cus, P<int>(ctx->bl_rows), &st->bound_fail, bo));
       }
       KMX_TRY(run_assign_gemm(ctx, X, n, d, ldx, C_inout, k, prec, lab, nullptr, nullptr,
-                              P<int>(ctx->fb_rows), &st->routed_fallback, gate, hub, hlb));
+                              P<int>(ctx->fb_rows), &st->routed_fallback, gate, bo));
       KMX_HIP(ctx, launch_record_fallback(ctx->stream, st, fbh, t, 0, n, gate));
       KMX_HIP(ctx, launch_record_kept(ctx->stream, st, bkh, t, n, gate));
     } else if (bounded || (!r && t == 0)) {
       // the first assignment of a bounded loop (or of the previous-label
       // loop): every row through the GEMM
       KMX_TRY(run_assign_gemm(ctx, X, n, d, ldx, C_inout, k, prec, lab, nullptr, nullptr, nullptr,
-                              nullptr, gate, hub, hlb));
+                              nullptr, gate, bo));
       KMX_HIP(ctx, launch_record_fallback(ctx->stream, st, fbh, t, 1, n, gate));
       if (bounded) KMX_HIP(ctx, launch_record_kept(ctx->stream, nullptr, bkh, t, 0, gate));
     } else {

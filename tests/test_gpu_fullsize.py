@@ -195,3 +195,41 @@ def test_headline_fp8_step_against_oracle(ctx):
     cost1 = ok.cost_from_features(W1, S1, Q1, C1h)
     assert abs(hist[1] - cost1) <= 1e-6 * cost1, (hist[1], cost1)
     say(f"  cost(C_0) {hist[0]:.9e} vs {cost0:.9e}; cost(C_1) {hist[1]:.9e} vs {cost1:.9e}")
+
+
+@pytest.mark.parametrize("k,n", [(10, 10000), (50, 10000)])
+def test_lowerbound_table2_optimum_on_gpu(ctx, k, n):
+    # The paper's LowerBound family (Sec. 3) at the sizes of Table 2 (d =
+    # k + n = 10010 and 10050: rows wider than the GEMM, the exact
+    # every-center path).  Lloyd started at the clusters' centroids is a fixed
+    # point whose cost is the optimum (delta^2 / 2)(n - k) that Table 2 prints
+    # (4.995e7 and 4.975e7, tests/golden/lowerbound_table2.txt); the GPU's
+    # k-means++ draws the oracle's rows.
+    import os
+    say(f"LowerBound k={k} n={n} d={k + n}")
+    gold = {}
+    for line in open(os.path.join(os.path.dirname(__file__), "golden", "lowerbound_table2.txt")):
+        if line.strip() and not line.startswith("#"):
+            kk, nn, dd, printed = line.split()
+            gold[(int(kk), int(nn))] = (int(dd), float(printed))
+    d, printed = gold[(k, n)]
+    X, lab = synth.lowerbound(k, n)
+    assert X.shape[1] == d
+    X32 = X.astype(np.float32)
+    Xd = torch.from_numpy(X32).to("cuda:0")
+    C0 = np.stack([X32[lab == j].astype(np.float64).mean(axis=0) for j in range(k)])
+    for prec in ("fp32", "bf16", "fp8"):
+        C, labg, hist, it = ctx.lloyd(Xd, torch.from_numpy(C0.astype(np.float32)).to("cuda:0"),
+                                      3, prec=prec)
+        say(f"  {prec}: cost {hist}")
+        assert it == 3
+        assert np.array_equal(labg.cpu().numpy(), lab)
+        for c in hist:
+            assert abs(c - printed) <= 1e-3 * printed      # printed to 4 digits
+            assert abs(c - 0.5 * 100.0 ** 2 * (n - k)) <= 1e-6 * printed
+    # k-means++ on the GPU draws the oracle's rows (FP64 D2 on both sides)
+    Cg, idx = ctx.seed(Xd, k, rng_seed=7)
+    _, idx_o, _ = ok.seed(X32, None, k, 7)
+    assert idx.cpu().numpy().tolist() == idx_o.tolist()
+    cost_g = ctx.cost(Xd, Cg)
+    assert abs(cost_g - ok.cost(X32, None, Cg.cpu().numpy())) <= 1e-6 * cost_g

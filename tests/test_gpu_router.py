@@ -222,9 +222,15 @@ def test_lloyd_routed_identical_other_widths(ctx, n, d, k):
 
 
 def test_trained_router_gain(ctx):
-    """Training is what makes the proposals usable: the trained network sends
-    far fewer rows to the GEMM than the same network untrained, from the first
-    routed assignment on, with identical results."""
+    """What the trained network gains over the method without it, with
+    identical results.  Against the same network untrained: far fewer rows to
+    the GEMM from the first routed assignment on.  Against the non-learned
+    forms (previous labels as the only candidates; bounds carried across
+    iterations): the first assignment of a call, where no previous label or
+    bound exists yet and those forms run the whole GEMM, is where the trained
+    router gains; in later assignments the previous label or the bounds are as
+    good (the counts are printed, the outcome at the headline size is in the
+    design notes)."""
     n, d, k = 40000, 64, 100
     X, _, _ = synth.router_mixture(n, d, k, seed=21)
     Xd = _dev(X)
@@ -250,11 +256,17 @@ def test_trained_router_gain(ctx):
         Cr, lr_, hr, ir, rows = ctx.lloyd_routed(Xd, C5, 3, router=r, prec="bf16")
         res[name] = (Cr.cpu().numpy(), lr_.cpu().numpy(), hr, rows)
         say(f"  {name}: gemm rows {rows}")
-    for name in ("trained", "previous"):
+    Cb, lb, hb, ib, rows_b, kept_b = ctx.lloyd_bounded(Xd, C5, 3, router=None, prec="bf16")
+    res["bounded"] = (Cb.cpu().numpy(), lb.cpu().numpy(), hb, rows_b)
+    say(f"  bounded (no router): gemm rows {rows_b}, kept by the bounds {kept_b}")
+    for name in ("trained", "previous", "bounded"):
         assert np.array_equal(res[name][0], res["untrained"][0])
         assert (res[name][1] == res["untrained"][1]).all()
         assert res[name][2] == res["untrained"][2]
     assert res["trained"][3][0] < 0.5 * res["untrained"][3][0]
+    # first assignment of the call: the non-learned forms have nothing to go on
+    assert res["trained"][3][0] < 0.5 * res["previous"][3][0]
+    assert res["trained"][3][0] < 0.5 * res["bounded"][3][0]
 
 
 def test_lloyd_routed_full_size_previous_labels(ctx):

@@ -482,7 +482,7 @@ def streamed_main(args):
     import torch
 
     import synth
-    from paper_1502_04265_amd import kmx, subspace
+    from paper_1502_04265_amd import kmx
 
     W = STREAMED
     d_in, r, k, rows = W["d_in"], W["r"], W["k"], W["chunk"]
@@ -492,17 +492,18 @@ def streamed_main(args):
     torch.cuda.set_device(0)
     ctx = kmx.Context(0)
     F = torch.from_numpy(synth.lowrank_factors(d_in, r, seed=0)).to(dev)
-    log(f"[bench] basis from a {W['sample']}-row sample (randomized SVD on the host)")
+    log(f"[bench] basis from a {W['sample']}-row sample (randomized range finder on the GPU)")
+    sample = torch.cat([synth.lowrank_chunk_device(rows, F, seed=0, chunk=1_000_000 + c,
+                                                   device=dev)
+                        for c in range((W["sample"] + rows - 1) // rows)])[:W["sample"]]
+    sample = sample.contiguous()
+    ctx.range_basis(sample, r, oversample=16, power_iters=1, seed=0)      # buffers
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    parts = []
-    for c in range((W["sample"] + rows - 1) // rows):
-        parts.append(synth.lowrank_chunk_device(rows, F, seed=0, chunk=1_000_000 + c,
-                                                device=dev).cpu().numpy())
-    sample = np.concatenate(parts)[:W["sample"]]
-    V = subspace.top_right_singular_vectors(sample, r, power_iters=1, seed=0)
-    del parts, sample
+    Vd, _ = ctx.range_basis(sample, r, oversample=16, power_iters=1, seed=0)
+    torch.cuda.synchronize()
     svd_s = time.perf_counter() - t0
-    Vd = torch.from_numpy(V).to(dev)
+    del sample
     Y = torch.empty((n, r), dtype=torch.float32, device=dev)
     ctx.timing(True, True)
     gen_ms = 0.0

@@ -206,6 +206,30 @@ kmx_status kmx_assign_noalloc(kmx_ctx* ctx, const float* X, int64_t n, int32_t d
                               const float* C, int32_t k, int32_t* label_out, float* d1_out,
                               float* d2_out);
 
+/* Top-r right singular vectors of A' = diag(sqrt(w)) A by a randomized
+ * range finder (Sec. 2.2, "Computation of the SVD": multiply A by a random
+ * matrix to reduce its columns, then a small SVD, after Halko, Martinsson and
+ * Tropp 2011, subspace iteration with power_iters passes; Sec. 2.3.2: a point
+ * of weight w enters as its row scaled by sqrt(w), which gives the best-fit
+ * subspace of the point set with w copies of every point).  Projecting the
+ * rows onto V (kmx_project) reduces them to that subspace (Sec. 2.2, "Using
+ * SVD to project to the best fit subspace").
+ *   A        device, n x d float32, leading dimension lda >= d.
+ *   w        device, n float32, nullable (all 1); finite and >= 0.
+ *   r        rank; r + oversample rounded up to a multiple of 16 (the sample
+ *            width l) must be <= 128 and <= min(n, d).
+ *   seed     the Gaussian test matrix: element i is a Box-Muller normal of
+ *            SplitMix64 outputs 2 i and 2 i + 1 from state seed.
+ *   V_out    device, d x r float32 (row-major, leading dimension r):
+ *            orthonormal columns, in decreasing order of singular value.
+ *   sigma_out host, r doubles, nullable: the singular values of the sample.
+ * Products with A run on the device (FP32 projection; A^T X with FP64 sums);
+ * the l x l factorizations (CholeskyQR2, Jacobi eigenproblem) in FP64 on the
+ * host.  Synchronizes. */
+kmx_status kmx_range_basis(kmx_ctx* ctx, const float* A, int64_t n, int32_t d, int64_t lda,
+                           const float* w, int32_t r, int32_t oversample, int32_t power_iters,
+                           uint64_t seed, float* V_out, double* sigma_out);
+
 /* Re-check counts of the most recent assignment on ctx (kmx_assign, kmx_cost,
  * or the final assignment of kmx_lloyd); host outputs, each nullable:
  *   listed   rows on the exact re-check list (pairs and full rows),

@@ -10,6 +10,8 @@ k-means on the coordinates equals k-means on A_m (centers restricted to the
 span, where optimal centers lie).
 
   * best_fit_basis(A, m)  -- V_m by the exact SVD (numpy / LAPACK);
+  * best_fit_basis_weighted(A, w, m) -- V_m of the weighted point set
+    (Sec. 2.3.2: the rows scaled by sqrt(w));
   * project(X, V)         -- X V in FP64;
   * rank_m_rows(A, m)     -- A V_m V_m^T, the rows of A_m.
 """
@@ -23,6 +25,15 @@ def best_fit_basis(A, m: int) -> np.ndarray:
     A = np.asarray(A, np.float64)
     _, _, Vt = np.linalg.svd(A, full_matrices=False)
     return Vt[:m].T.copy()
+
+
+def best_fit_basis_weighted(A, w, m: int) -> np.ndarray:
+    """Top m right singular vectors of the weighted point set (Sec. 2.3.2):
+    the matrix whose row i is sqrt(w_i) times row i of A has the same right
+    singular vectors as the matrix holding w_i copies of row i."""
+    A = np.asarray(A, np.float64)
+    s = np.sqrt(np.asarray(w, np.float64)).reshape(-1, 1)
+    return best_fit_basis(s * A, m)
 
 
 def project(X, V) -> np.ndarray:

@@ -34,35 +34,52 @@ __global__ __launch_bounds__(1024) void drift_kernel(const float* __restrict__ C
   if (lane == 0) drift[j] = dist_up(s);
 }
 
-// The three largest drifts and the centers of the largest two (one workgroup).
+// The three largest drifts and the centers of the largest two (one workgroup):
+// every thread keeps its own top three, then butterfly merges within the wave
+// and across the waves.
+struct Top3 {
+  float v1, v2, v3;
+  int i1, i2;
+};
+
+__device__ __forceinline__ void top3_add(Top3& t, float v, int j) {
+  if (v > t.v1) { t.v3 = t.v2; t.v2 = t.v1; t.i2 = t.i1; t.v1 = v; t.i1 = j; }
+  else if (v > t.v2) { t.v3 = t.v2; t.v2 = v; t.i2 = j; }
+  else if (v > t.v3) { t.v3 = v; }
+}
+
+__device__ __forceinline__ void top3_merge(Top3& t, const Top3& o) {
+  top3_add(t, o.v1, o.i1);
+  top3_add(t, o.v2, o.i2);
+  top3_add(t, o.v3, -1);
+}
+
 __global__ __launch_bounds__(1024) void drift_max_kernel(const float* __restrict__ drift, int k,
                                                          DriftStat* __restrict__ ds,
                                                          const int* __restrict__ gate) {
   if (gate && *gate) return;
-  __shared__ float v1s[1024], v2s[1024], v3s[1024];
-  __shared__ int i1s[1024], i2s[1024];
-  float v1 = -1.0f, v2 = -1.0f, v3 = -1.0f;
-  int i1 = -1, i2 = -1;
-  auto ins = [&](float v, int j) {
-    if (v > v1) { v3 = v2; v2 = v1; i2 = i1; v1 = v; i1 = j; }
-    else if (v > v2) { v3 = v2; v2 = v; i2 = j; }
-    else if (v > v3) { v3 = v; }
-  };
-  for (int j = threadIdx.x; j < k; j += 1024) ins(drift[j], j);
-  v1s[threadIdx.x] = v1; v2s[threadIdx.x] = v2; v3s[threadIdx.x] = v3;
-  i1s[threadIdx.x] = i1; i2s[threadIdx.x] = i2;
+  __shared__ Top3 red[16];
+  Top3 t = {-1.0f, -1.0f, -1.0f, -1, -1};
+  for (int j = threadIdx.x; j < k; j += 1024) top3_add(t, drift[j], j);
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    Top3 o;
+    o.v1 = __shfl_xor(t.v1, m, 64);
+    o.v2 = __shfl_xor(t.v2, m, 64);
+    o.v3 = __shfl_xor(t.v3, m, 64);
+    o.i1 = __shfl_xor(t.i1, m, 64);
+    o.i2 = __shfl_xor(t.i2, m, 64);
+    top3_merge(t, o);
+  }
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = t;
   __syncthreads();
   if (threadIdx.x == 0) {
-    for (int t = 1; t < 1024; ++t) {
-      ins(v1s[t], i1s[t]);
-      ins(v2s[t], i2s[t]);
-      ins(v3s[t], -1);
-    }
-    ds->max1 = fmaxf(v1, 0.0f);
-    ds->max2 = fmaxf(v2, 0.0f);
-    ds->max3 = fmaxf(v3, 0.0f);
-    ds->arg1 = i1;
-    ds->arg2 = i2;
+    for (int w = 1; w < 16; ++w) top3_merge(t, red[w]);
+    ds->max1 = fmaxf(t.v1, 0.0f);
+    ds->max2 = fmaxf(t.v2, 0.0f);
+    ds->max3 = fmaxf(t.v3, 0.0f);
+    ds->arg1 = t.i1;
+    ds->arg2 = t.i2;
   }
 }
 

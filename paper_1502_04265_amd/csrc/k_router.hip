@@ -353,7 +353,7 @@ hipError_t launch_router_decode(hipStream_t s, const uint32_t* keys, int64_t cou
 }
 
 // ---------------------------------------------------------------------------
-// Center-distance table.  Pass 1 (tiles of 64 x 64 centers, 4 x 4 per
+// Center-distance table.  Pass 1 (tiles of 32 x 32 centers, 2 x 2 per
 // thread): D[b][c] = a lower bound of ||c_b - c_c||.  The FP32 sum of d
 // squared direct differences has relative error below (d + 3) u, u = 2^-24,
 // so sqrt(s (1 - 2 (d + 8) u)) (1 - 4 u) is a lower bound.  Pass 2 (one
@@ -365,17 +365,16 @@ __global__ __launch_bounds__(256) void center_dist_kernel(const float* __restric
                                                           float* __restrict__ D,
                                                           const int* __restrict__ gate) {
   if (gate && *gate) return;
-  __shared__ float Bt[32][65];
-  __shared__ float Ct[32][65];
+  // tiles of 32 x 32 centers (many workgroups per CU hide the load latency),
+  // K-major in LDS: thread (tx, ty) owns rows 2 ty, 2 ty + 1 of the first
+  // tile and 2 tx, 2 tx + 1 of the second, one float2 read each per k
+  __shared__ __attribute__((aligned(16))) float Bt[32][32];
+  __shared__ __attribute__((aligned(16))) float Ct[32][32];
   const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-  const int b0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
-  float acc[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0f;
+  const int b0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
+  float acc[2][2] = {{0.0f, 0.0f}, {0.0f, 0.0f}};
   for (int k0 = 0; k0 < d; k0 += 32) {
-    for (int e = tid; e < 64 * 32; e += 256) {
+    for (int e = tid; e < 32 * 32; e += 256) {
       const int rr = e >> 5, kk = e & 31, kc = k0 + kk;
       Bt[kk][rr] = (b0 + rr < k && kc < d) ? C[(int64_t)(b0 + rr) * d + kc] : 0.0f;
       Ct[kk][rr] = (c0 + rr < k && kc < d) ? C[(int64_t)(c0 + rr) * d + kc] : 0.0f;
@@ -383,16 +382,14 @@ __global__ __launch_bounds__(256) void center_dist_kernel(const float* __restric
     __syncthreads();
 #pragma unroll 8
     for (int kk = 0; kk < 32; ++kk) {
-      float bv[4], cv[4];
+      const float2 bq = *(const float2*)&Bt[kk][2 * ty];
+      const float2 cq = *(const float2*)&Ct[kk][2 * tx];
+      const float bv[2] = {bq.x, bq.y};
+      const float cv[2] = {cq.x, cq.y};
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        bv[i] = Bt[kk][ty + 16 * i];
-        cv[i] = Ct[kk][tx + 16 * i];
-      }
+      for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < 2; ++j) {
           const float df = bv[i] - cv[j];
           acc[i][j] = __builtin_fmaf(df, df, acc[i][j]);
         }
@@ -402,10 +399,10 @@ __global__ __launch_bounds__(256) void center_dist_kernel(const float* __restric
   const float u = 5.9604645e-8f;
   const float shrink = 1.0f - 2.0f * (float)(d + 8) * u;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int b = b0 + ty + 16 * i, c = c0 + tx + 16 * j;
+    for (int j = 0; j < 2; ++j) {
+      const int b = b0 + 2 * ty + i, c = c0 + 2 * tx + j;
       if (b < k && c < k)
         D[(int64_t)b * k + c] =
             (b == c) ? __builtin_inff() : sqrtf(fmaxf(acc[i][j] * shrink, 0.0f)) * (1.0f - 4.0f * u);
@@ -453,7 +450,7 @@ __global__ __launch_bounds__(256) void center_select_kernel(const float* __restr
 hipError_t launch_center_table(hipStream_t s, const float* C, int k, int d, float* D, int32_t* nbr,
                                float* nbd, const int* gate) {
   if (k > kRouterMaxK) return hipErrorInvalidValue;
-  const unsigned tiles = (unsigned)((k + 63) / 64);
+  const unsigned tiles = (unsigned)((k + 31) / 32);
   hipLaunchKernelGGL(center_dist_kernel, dim3(tiles, tiles), dim3(256), 0, s, C, k, d, D, gate);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

@@ -405,6 +405,8 @@ kmx_status kmx_destroy(kmx_ctx* ctx) {
       &ctx->xstats8,   &ctx->cq8,      &ctx->ch8,        &ctx->hd8,        &ctx->cstats8,
       &ctx->full_rows2, &ctx->bX,       &ctx->bXq,        &ctx->brs,        &ctx->bw,
       &ctx->bC,        &ctx->bCq,      &ctx->bhd,        &ctx->bch,        &ctx->vt,        &ctx->bcs,        &ctx->blab,
+      &ctx->sv_om,     &ctx->sv_y,     &ctx->sv_y2,      &ctx->sv_z,       &ctx->sv_g,      &ctx->sv_part,
+      &ctx->sv_r,      &ctx->sv_v,
       &ctx->bitems,    &ctx->binsts,   &ctx->bbuckets,   &ctx->bcinst,     &ctx->bxstats,
       &ctx->btermC,    &ctx->btermMu,  &ctx->bW,         &ctx->bcost};
   for (kmx::Buf* b : bufs)

@@ -203,6 +203,7 @@ struct kmx_ctx {
   kmx::Buf hub, hlb, hl2, hsec, bl_rows, cprev, drift, dstat, bkh;   // carried bounds
   // batched Lloyd: concatenated instances and their descriptors
   kmx::Buf vt;                          // transposed projection basis
+  kmx::Buf sv_om, sv_y, sv_y2, sv_z, sv_g, sv_part, sv_r, sv_v;   // range finder
   kmx::Buf bX, bXq, brs, bw, bC, bCq, bhd, bch, bcs, blab, bitems, binsts, bbuckets, bcinst, bxstats;
   kmx::Buf btermC, btermMu, bW, bcost;
   hipStream_t cap_stream = nullptr;                // stream graphs are captured on (batched, graphed Lloyd)
@@ -353,6 +354,17 @@ hipError_t launch_project(hipStream_t s, const float* X, int64_t rows, int d_in,
                           const float* V, int d_out, float* Y, int64_t ldy, float* Vt,
                           int num_cus);
 int project_dpad(int d_in);            // row length of the transposed basis workspace
+
+// range finder (k_svd.hip)
+hipError_t launch_gauss_fill(hipStream_t s, float* out, int64_t count, uint64_t seed);
+hipError_t launch_scale_rows(hipStream_t s, float* Y, int64_t n, int q, int64_t ldy,
+                             const float* w);   // Y_i *= sqrt(w_i)
+int atb_slices(int64_t n, int p, int num_cus);
+// out (p x q, FP64) = A^T diag(sqrt w) B, A n x p, B n x q (q <= 128), w nullable;
+// part: slices x p x q doubles
+hipError_t launch_atb(hipStream_t s, const float* A, int64_t n, int p, int64_t lda, const float* B,
+                      int q, int64_t ldb, const float* w, double* part, int slices, double* out);
+hipError_t launch_f64_to_f32(hipStream_t s, const double* in, float* out, int64_t count);
 
 // router: inference (k_router.hip)
 int router_units(int d, int dp);

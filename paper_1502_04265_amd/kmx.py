@@ -77,6 +77,8 @@ def lib():
         "kmx_batched_autotune": [_vp, _vp, _i32, ctypes.c_int, ctypes.c_char_p, _vp],
         "kmx_batched_tiles": [_vp, _i32, _i32, _vp, _vp],
         "kmx_project": [_vp, _vp, _i64, _i32, _i64, _vp, _i32, _vp, _i64],
+        "kmx_range_basis": [_vp, _vp, _i64, _i32, _i64, _vp, _i32, _i32, _i32, ctypes.c_uint64,
+                            _vp, _vp],
         "kmx_router_create": [_vp, _i32, _i32, ctypes.c_uint64, ctypes.POINTER(_vp)],
         "kmx_router_destroy": [_vp, _vp],
         "kmx_router_set_params": [_vp, _vp, _vp, _vp, _vp, _vp],
@@ -360,6 +362,20 @@ class Context:
         _check(lib().kmx_project(self._p, _ptr(X), rows, d_in, ldx, _ptr(V), d_out, _ptr(Y),
                                  Y.stride(0)), self._p)
         return Y
+
+    def range_basis(self, A, r: int, w=None, oversample: int = 16, power_iters: int = 2,
+                    seed: int = 0):
+        """kmx_range_basis: the top-r right singular vectors of diag(sqrt w) A
+        (d x r float32 CUDA tensor) and the singular values (list)."""
+        n, d, lda = _rows(A)
+        _vec(w, n)
+        V = torch.empty((d, r), dtype=torch.float32, device=A.device)
+        sig = (ctypes.c_double * r)()
+        self._sync_stream()
+        _check(lib().kmx_range_basis(self._p, _ptr(A), n, d, lda, _ptr(w), r, oversample,
+                                     power_iters, ctypes.c_uint64(seed & (2 ** 64 - 1)), _ptr(V),
+                                     sig), self._p)
+        return V, [sig[i] for i in range(r)]
 
     # ---- candidate router ----------------------------------------------------
     def router(self, d: int, k: int, init_seed: int = 0) -> "Router":

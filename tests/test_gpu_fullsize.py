@@ -92,7 +92,6 @@ def test_rotated_mixture_full_size(ctx):
 
 
 def test_streamed_full_size(ctx):
-    from paper_1502_04265_amd import subspace
     d_in, r, k, rows, n, iters = 4096, 64, 100, 65536, 10_000_000, 3
     nchunks = (n + rows - 1) // rows
     say(f"streamed {nchunks} chunks of {rows} x {d_in} -> {r}")
@@ -100,9 +99,8 @@ def test_streamed_full_size(ctx):
     F = torch.from_numpy(synth.lowrank_factors(d_in, r, seed=0)).to(dev)
     sample = torch.cat([synth.lowrank_chunk_device(rows, F, seed=0, chunk=1_000_000 + c,
                                                    device=dev) for c in range(2)])[:100_000]
-    V = subspace.top_right_singular_vectors(sample.cpu().numpy(), r, power_iters=1, seed=0)
+    Vd, _ = ctx.range_basis(sample.contiguous(), r, oversample=16, power_iters=1, seed=0)
     del sample
-    Vd = torch.from_numpy(V).to(dev)
     Y = torch.empty((nchunks * rows, r), dtype=torch.float32, device=dev)
     rng = np.random.default_rng(3)
     worst = 0.0

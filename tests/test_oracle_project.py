@@ -58,3 +58,24 @@ def test_planted_mistakes_are_caught(monkeypatch):
     monkeypatch.setattr(op, "best_fit_basis", lambda A, m: real(A, m + 1)[:, 1:])  # drops the top one
     with pytest.raises(AssertionError):
         test_rank_m_approximation_is_optimal()
+
+
+def test_weighted_basis_equals_replicated_rows():
+    # Sec. 2.3.2: integer weights; the sqrt(w)-scaled matrix and the matrix
+    # with w copies of every row have the same best-fit subspace (compared as
+    # projectors, which removes the sign / rotation freedom)
+    rng = np.random.default_rng(5)
+    A = _lowrank(60, 12, 3, 4, noise=0.5)
+    w = rng.integers(1, 6, 60)
+    F = np.repeat(A, w, axis=0)
+    for m in (1, 3, 5):
+        Vw = op.best_fit_basis_weighted(A, w, m)
+        Vf = op.best_fit_basis(F, m)
+        np.testing.assert_allclose(Vw @ Vw.T, Vf @ Vf.T, atol=1e-9)
+    # unit weights reduce to the plain basis
+    V1 = op.best_fit_basis_weighted(A, np.ones(60), 3)
+    V0 = op.best_fit_basis(A, 3)
+    np.testing.assert_allclose(V1 @ V1.T, V0 @ V0.T, atol=1e-10)
+    # scaling by w instead of sqrt(w) would not match the replicated rows
+    Vbad = op.best_fit_basis(w.reshape(-1, 1) * A, 3)
+    assert np.abs(Vbad @ Vbad.T - op.best_fit_basis(F, 3) @ op.best_fit_basis(F, 3).T).max() > 1e-3

@@ -243,6 +243,16 @@ kmx_status kmx_range_basis(kmx_ctx* ctx, const float* A, int64_t n, int32_t d, i
  * Synchronizes. */
 kmx_status kmx_assign_stats(kmx_ctx* ctx, int64_t* listed, int64_t* fp32, int64_t* full);
 
+/* The most recent update of a Lloyd run on ctx (the final assignment's, after
+ * kmx_lloyd and its variants); host outputs, each nullable:
+ *   changed  rows whose label differed from the previous update's,
+ *   delta    1 when the features were formed from the previous update's by
+ *            removing and adding only those rows (Sec. 2.1: clustering
+ *            features add and subtract), 0 when every row was summed (the
+ *            first update of a run, or more than half of the rows changed).
+ * Both give the same bits.  Synchronizes. */
+kmx_status kmx_update_stats(kmx_ctx* ctx, int64_t* changed, int32_t* delta);
+
 /* Measurement of the arithmetic the assignment's error bounds rely on:
  * instance q < count runs one matrix instruction of the distance GEMM of
  * `prec`, exactly as the assignment issues it, on A_q and B_q (device,

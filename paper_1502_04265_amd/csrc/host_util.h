@@ -135,6 +135,11 @@ kmx_status check_data(kmx_ctx* ctx, const float* X, int64_t n, int d, int64_t ld
 kmx_status ensure_prep(kmx_ctx* ctx, const float* X, int64_t n, int d, int64_t ldx, int prec);
 kmx_status ensure_common(kmx_ctx* ctx, int64_t n, int d, int k);
 kmx_status write_state(kmx_ctx* ctx, int max_iter, double tol);
+// Grids of the exactly summed clustering features for X and w (the dataset
+// part cached like the quantized copies).
+kmx_status ensure_cf(kmx_ctx* ctx, const float* X, int64_t n, int d, int64_t ldx, const float* w);
+// Start of a Lloyd run: previous labels unknown (-1), delta entry counts clear.
+kmx_status begin_lloyd(kmx_ctx* ctx, int32_t* prev, int64_t n);
 
 // Per-iteration center preparation: resets the per-assignment counters,
 // writes the FP32 GEMM copy of C and, for BF16, the quantized copy.

@@ -480,6 +480,7 @@ __global__ void reset_small_kernel(CenterStats* cs, CenterStats* cs2, CenterStat
       st->routed_listed = 0;
       st->bound_fail = 0;
       st->bound_pair = 0;
+      st->dcount = 0;
       if (reset_iter) {
         st->done = 0;
         st->iter = 0;

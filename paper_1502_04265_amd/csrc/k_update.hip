@@ -2,17 +2,23 @@
 // centroid of its subset) as a deterministic, HBM-bound segmented reduction.
 //
 // For every cluster j the kernels form the weighted clustering feature of
-// Sec. 2.1 / Sec. 2.3.1: W_j = sum w_i, S_j = sum w_i x_i, Q_j = sum w_i ||x_i||^2
-// in FP64 (w_i x_i is exact in FP64).  The cost of the partition against any
-// center c follows from the identity of Sec. 2.1:
+// Sec. 2.1 / Sec. 2.3.1: W_j = sum w_i, S_j = sum w_i x_i, Q_j = sum w_i ||x_i||^2,
+// each summed exactly on a fixed-point grid (section 6 below), so that the
+// features of a Lloyd iteration can also be formed from the previous
+// iteration's by removing and adding only the rows whose label changed.  The
+// cost of the partition against any center c follows from the identity of
+// Sec. 2.1:
 //     sum_{i in P_j} w_i ||x_i - c||^2 = Q_j - 2 c.S_j + W_j ||c||^2 .
 //
-// Mechanism: a stable counting sort of row ids by label (block histograms,
-// column scans, in-block ranks from one ballot per label bit), then one workgroup
-// per chunk of at most kReduceRows rows of one cluster gathers whole rows
-// (coalesced) and accumulates FP64 partial features, and one workgroup per
-// cluster sums its chunks in chunk order.  Every sum has a fixed order, so the
-// results are bitwise reproducible.
+// Full update: a stable counting sort of row ids by label (block histograms,
+// column scans, in-block ranks from one ballot per label bit), then one
+// workgroup per chunk of at most kReduceRows rows of one cluster gathers whole
+// rows (coalesced) and accumulates the limb sums, and one workgroup per
+// cluster sums its chunks.  Delta update (Lloyd iterations after the first):
+// the changed rows are listed, grouped by cluster as signed entries (removal
+// from the old cluster, addition to the new) and reduced the same way; the
+// finalize adds the chunk sums to the features carried from the previous
+// iteration.  Both give the same bits, since every sum is exact.
 #include "kmx_device.h"
 #include "kmx_internal.h"
 
@@ -278,155 +284,279 @@ hipError_t launch_sort(hipStream_t s, const int32_t* label, int32_t* lab_prev, i
   return hipGetLastError();
 }
 
-// ---- 6. chunk reduction: FP64 (S, Q, W) over at most kReduceRows rows ----
-// The chunk's row ids and weights are staged in LDS first.  Four waves walk
-// the chunk's rows in an interleaved, fixed order (wave v: rows v, v + 4,
-// ...).  A wave is split into SUB = 64 / LPR sub-waves of LPR lanes, each on
-// its own row, so short rows still occupy every lane; a lane owns VEC
-// consecutive columns in each of M column groups of LPR*VEC.  Each step takes
-// UR rows per sub-wave; the next step's rows are loaded while the current
-// step is summed.  The sub-waves' partial sums are combined by a butterfly
-// (same bits on every lane), the waves in a fixed order.
-template <int VEC, int M, int LPR>
-__global__ __launch_bounds__(256) void reduce_kernel(const float* __restrict__ X, int d,
-                                                     int64_t ldx, const float* __restrict__ w,
-                                                     const int32_t* __restrict__ perm,
-                                                     const int32_t* __restrict__ base,
-                                                     const int32_t* __restrict__ chunk_base,
-                                                     int k, double* __restrict__ partS,
-                                                     double* __restrict__ partQ,
-                                                     double* __restrict__ partW,
-                                                     const int* __restrict__ gate) {
+// ---- 6. exactly summed clustering features ----
+// The sums are formed on a fixed-point grid per column: with 2^E_c an upper
+// bound on |w_i x_ic| over all rows, the product w_i x_ic (exact in FP64) is
+// scaled by 2^(62 - E_c) and cut toward zero into two 31-bit limbs,
+//     v = w x 2^(62 - E_c) = h 2^31 + m + f,   |h|, |m| < 2^31,  |f| < 1,
+// and only the integers h and m are summed (the fraction f, at most 2^-62 of
+// the column's bound, is dropped).  Integer sums do not depend on their
+// order, and cutting toward zero is odd, so removing a row later subtracts
+// exactly what adding it added: the features of a cluster after rows moved
+// in and out (Sec. 2.1: features add under union and subtract under removal)
+// are the bits a fresh sum over its members gives.  W uses the grid of the
+// largest weight and Q the grid of the largest w_i ||x_i||^2, with ||x_i||^2
+// summed in FP64 in a fixed order per row.
+//
+// cfs layout (doubles): [0, d) column scales 2^(62 - E_c), [d, 2d) their
+// inverses, then sW, 1/sW, sQ, 1/sQ.
+
+// 6a. Column maxima of |x| (bit patterns of non-negative floats, atomicMax).
+__global__ __launch_bounds__(256) void cf_colmax_kernel(const float* __restrict__ X, int64_t n,
+                                                        int d, int64_t ldx,
+                                                        int64_t rows_per_slice,
+                                                        unsigned* __restrict__ colmax) {
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= d) return;
+  const int64_t r0 = (int64_t)blockIdx.y * rows_per_slice;
+  const int64_t r1 = min(n, r0 + rows_per_slice);
+  float m = 0.0f;
+#pragma unroll 8
+  for (int64_t i = r0; i < r1; ++i) m = fmaxf(m, fabsf(X[i * ldx + c]));
+  atomicMax(colmax + c, __float_as_uint(m));
+}
+
+// 6b. ||x_i||^2 in FP64, one wave per row: lane l sums columns l, l + 64, ...
+// in order, then a butterfly (a fixed order).  The maximum goes to qmax as
+// the bit pattern of a non-negative double.
+__global__ __launch_bounds__(256) void cf_rowq_kernel(const float* __restrict__ X, int64_t n,
+                                                      int d, int64_t ldx, double* __restrict__ q,
+                                                      unsigned long long* __restrict__ qmax) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  double mx = 0.0;
+  for (int64_t i = wid; i < n; i += nw) {
+    const float* xr = X + i * ldx;
+    double s = 0.0;
+    for (int c = lane; c < d; c += 64) {
+      const double x = (double)xr[c];
+      s = fma(x, x, s);
+    }
+    s = wave_sum_f64(s);
+    if (lane == 0) q[i] = s;
+    mx = fmax(mx, s);
+  }
+  if (lane == 0) atomicMax(qmax, (unsigned long long)__double_as_longlong(mx));
+}
+
+// 6c. Largest weight (bit pattern of a non-negative float).
+__global__ __launch_bounds__(256) void cf_wmax_kernel(const float* __restrict__ w, int64_t n,
+                                                      unsigned* __restrict__ wmax) {
+  float m = 0.0f;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    m = fmaxf(m, w[i]);
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0) atomicMax(wmax, __float_as_uint(m));
+}
+
+// 2^(62 - E) with bound < 2^E (1 for a zero bound: every product is zero).
+__device__ __forceinline__ double cf_scale(double bound) {
+  if (!(bound > 0.0)) return 1.0;
+  int e;
+  (void)frexp(bound, &e);   // bound = f 2^e, f in [0.5, 1): bound < 2^e
+  return ldexp(1.0, 62 - e);
+}
+
+// 6d. The grids of one call (one workgroup).  wmax == nullptr: unit weights.
+__global__ __launch_bounds__(256) void cf_scales_kernel(const unsigned* __restrict__ colmax, int d,
+                                                        const unsigned long long* __restrict__ qmax,
+                                                        const unsigned* __restrict__ wmax,
+                                                        double* __restrict__ cfs) {
+  const double wm = wmax ? (double)__uint_as_float(*wmax) : 1.0;
+  for (int c = threadIdx.x; c < d; c += 256) {
+    const double s = cf_scale(wm * (double)__uint_as_float(colmax[c]));
+    cfs[c] = s;
+    cfs[d + c] = 1.0 / s;
+  }
+  if (threadIdx.x == 0) {
+    const double sW = cf_scale(wm);
+    // w_i ||x_i||^2 is rounded once in FP64: a factor 2 of margin
+    const double sQ = cf_scale(2.0 * wm * __longlong_as_double((long long)*qmax));
+    cfs[2 * d] = sW;
+    cfs[2 * d + 1] = 1.0 / sW;
+    cfs[2 * d + 2] = sQ;
+    cfs[2 * d + 3] = 1.0 / sQ;
+  }
+}
+
+// The two limbs of v (|v| < 2^62), cut toward zero.
+__device__ __forceinline__ void cf_split(double v, double& h, double& m) {
+  h = trunc(v * 0x1p-31);
+  m = trunc(fma(-h, 0x1p31, v));
+}
+
+// 6e. Chunk reduction.  A chunk is at most kReduceRows entries of one
+// cluster: rows of the sorted permutation (DELTA = false), or signed entries
+// (DELTA = true: e >= 0 adds row e, e < 0 removes row -e - 1).  The chunk's
+// row ids, signed weights and the W and Q limbs are staged first; then four
+// waves walk the rows in an interleaved order (wave v: rows v, v + 4, ...),
+// each wave split into SUB = 64 / LPR sub-waves of LPR lanes, a lane owning
+// VEC consecutive columns in each of M column groups of LPR * VEC.  Each step
+// takes UR rows per sub-wave; the next step's rows load while the current one
+// is summed.  Partial limb sums are exact integers below 2^40 in FP64, so the
+// combination order does not matter.  Chunks are taken in a grid-stride loop.
+template <int VEC, int M, int LPR, bool DELTA, bool WEIGHTED>
+__global__ __launch_bounds__(256) void cf_reduce_kernel(
+    const float* __restrict__ X, int d, int64_t ldx, const float* __restrict__ w,
+    const double* __restrict__ qrow, const int32_t* __restrict__ ent,
+    const int32_t* __restrict__ base, const int32_t* __restrict__ chunk_base, int k,
+    const double* __restrict__ cfs, double* __restrict__ partS, double* __restrict__ partWQ,
+    const int* __restrict__ gate) {
   if (gate && *gate) return;
   constexpr int SUB = 64 / LPR;     // rows side by side in a wave
   constexpr int CB = LPR * VEC * M; // columns per pass
   constexpr int UR = 4;             // rows per sub-wave and step
   constexpr int RS = 4 * SUB;       // row stride between a sub-wave's rows
   __shared__ double sh[4][CB];
-  __shared__ double shq[4], shw[4];
+  __shared__ double shs[4][4];
   __shared__ int srow[kReduceRows];
   __shared__ float swt[kReduceRows];
-  const int cidx = blockIdx.x;
-  if (cidx >= chunk_base[k]) return;
-  // cluster owning this chunk: last j with chunk_base[j] <= cidx
-  int lo = 0, hi = k;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (chunk_base[mid] <= cidx) lo = mid; else hi = mid;
-  }
-  const int j = lo;
-  const int64_t r0 = (int64_t)base[j] + (int64_t)(cidx - chunk_base[j]) * kReduceRows;
-  const int64_t r1 = min((int64_t)base[j + 1], r0 + kReduceRows);
-  const int nr = (int)(r1 - r0);
-  for (int t = threadIdx.x; t < nr; t += 256) {
-    const int i = perm[r0 + t];
-    srow[t] = i;
-    swt[t] = w ? w[i] : 1.0f;
-  }
-  __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int sub = lane / LPR, sl = lane % LPR;
   const int first = wv + 4 * sub;   // this sub-wave's rows: first, first + RS, ...
-  double qacc = 0.0, wacc = 0.0;
-  for (int cb = 0; cb < d; cb += CB) {
-    double S[M][VEC], Q[M][VEC];
+  const int nchunks = chunk_base[k];
+  const double sW = cfs[2 * d], sQ = cfs[2 * d + 2];
+  for (int cidx = blockIdx.x; cidx < nchunks; cidx += gridDim.x) {
+    // cluster owning this chunk: last j with chunk_base[j] <= cidx
+    int lo = 0, hi = k;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (chunk_base[mid] <= cidx) lo = mid; else hi = mid;
+    }
+    const int j = lo;
+    const int64_t r0 = (int64_t)base[j] + (int64_t)(cidx - chunk_base[j]) * kReduceRows;
+    const int64_t r1 = min((int64_t)base[j + 1], r0 + kReduceRows);
+    const int nr = (int)(r1 - r0);
+    double wh = 0.0, wm = 0.0, qh = 0.0, qm = 0.0;
+    for (int t = threadIdx.x; t < nr; t += 256) {
+      const int e = ent[r0 + t];
+      const int i = DELTA ? (e >= 0 ? e : -e - 1) : e;
+      const float wi = WEIGHTED ? w[i] : 1.0f;
+      const float ws = (DELTA && e < 0) ? -wi : wi;
+      srow[t] = i;
+      swt[t] = ws;
+      double h, m;
+      cf_split((double)ws * sW, h, m);
+      wh += h;
+      wm += m;
+      cf_split((double)ws * qrow[i] * sQ, h, m);
+      qh += h;
+      qm += m;
+    }
+    wh = wave_sum_f64(wh);
+    wm = wave_sum_f64(wm);
+    qh = wave_sum_f64(qh);
+    qm = wave_sum_f64(qm);
+    if (lane == 0) {
+      shs[wv][0] = wh;
+      shs[wv][1] = wm;
+      shs[wv][2] = qh;
+      shs[wv][3] = qm;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+      const int q = threadIdx.x;
+      partWQ[(int64_t)cidx * 4 + q] = ((shs[0][q] + shs[1][q]) + shs[2][q]) + shs[3][q];
+    }
+    for (int cb = 0; cb < d; cb += CB) {
+      double Sh[M][VEC], Sm[M][VEC], sc[M][VEC];
 #pragma unroll
-    for (int m = 0; m < M; ++m)
+      for (int m = 0; m < M; ++m)
 #pragma unroll
-      for (int v = 0; v < VEC; ++v) S[m][v] = Q[m][v] = 0.0;
-    // rows t0 + RS u of one step, zeros past the chunk
-    auto load_step = [&](int t0, float (&xv)[UR][M][VEC]) {
+        for (int v = 0; v < VEC; ++v) {
+          const int c = cb + (m * LPR + sl) * VEC + v;
+          sc[m][v] = (c < d) ? cfs[c] : 0.0;
+          Sh[m][v] = Sm[m][v] = 0.0;
+        }
+      // rows t0 + RS u of one step, zeros past the chunk
+      auto load_step = [&](int t0, float (&xv)[UR][M][VEC]) {
 #pragma unroll
-      for (int u = 0; u < UR; ++u) {
-        const int t = t0 + RS * u;
-        const bool rv = t < nr;
-        const float* xr = X + (int64_t)(rv ? srow[t] : 0) * ldx + cb;
+        for (int u = 0; u < UR; ++u) {
+          const int t = t0 + RS * u;
+          const bool rv = t < nr;
+          const float* xr = X + (int64_t)(rv ? srow[t] : 0) * ldx + cb;
 #pragma unroll
-        for (int m = 0; m < M; ++m) {
-          const int c0 = (m * LPR + sl) * VEC;
-          if (VEC == 4 && rv && cb + c0 + 4 <= d) {
-            const float4 t4 = *(const float4*)(xr + c0);
-            xv[u][m][0] = t4.x;
-            if (VEC == 4) { xv[u][m][1] = t4.y; xv[u][m][2] = t4.z; xv[u][m][3] = t4.w; }
-          } else {
+          for (int m = 0; m < M; ++m) {
+            const int c0 = (m * LPR + sl) * VEC;
+            if (VEC == 4 && rv && cb + c0 + 4 <= d) {
+              const float4 t4 = *(const float4*)(xr + c0);
+              xv[u][m][0] = t4.x;
+              if (VEC == 4) { xv[u][m][1] = t4.y; xv[u][m][2] = t4.z; xv[u][m][3] = t4.w; }
+            } else {
 #pragma unroll
-            for (int q = 0; q < VEC; ++q)
-              xv[u][m][q] = (rv && cb + c0 + q < d) ? xr[c0 + q] : 0.0f;
+              for (int q = 0; q < VEC; ++q)
+                xv[u][m][q] = (rv && cb + c0 + q < d) ? xr[c0 + q] : 0.0f;
+            }
           }
         }
-      }
-    };
-    float xa[UR][M][VEC], xb[UR][M][VEC];
-    load_step(first, xa);
-    for (int t0 = first; t0 < nr; t0 += RS * UR) {
-      const bool more = t0 + RS * UR < nr;
-      if (more) load_step(t0 + RS * UR, xb);
+      };
+      float xa[UR][M][VEC], xb[UR][M][VEC];
+      load_step(first, xa);
+      for (int t0 = first; t0 < nr; t0 += RS * UR) {
+        const bool more = t0 + RS * UR < nr;
+        if (more) load_step(t0 + RS * UR, xb);
 #pragma unroll
-      for (int u = 0; u < UR; ++u) {
-        const int t = t0 + RS * u;
-        const double wt = (t < nr) ? (double)swt[t] : 0.0;
-        if (cb == 0) wacc += wt;
+        for (int u = 0; u < UR; ++u) {
+          const int t = t0 + RS * u;
+          // rows past the chunk carry x = 0 and weight 0: zero limbs
+          const double wt = (t < nr) ? (double)swt[t] : 0.0;
+#pragma unroll
+          for (int m = 0; m < M; ++m)
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) {
+              const double xd = (double)xa[u][m][q];
+              double h, l;
+              if (WEIGHTED || DELTA) cf_split(wt * xd * sc[m][q], h, l);
+              else cf_split(xd * sc[m][q], h, l);
+              Sh[m][q] += h;
+              Sm[m][q] += l;
+            }
+        }
+        if (more) {
+#pragma unroll
+          for (int u = 0; u < UR; ++u)
+#pragma unroll
+            for (int m = 0; m < M; ++m)
+#pragma unroll
+              for (int q = 0; q < VEC; ++q) xa[u][m][q] = xb[u][m][q];
+        }
+      }
+      // sub-waves, then waves (exact integer sums)
+#pragma unroll
+      for (int limb = 0; limb < 2; ++limb) {
 #pragma unroll
         for (int m = 0; m < M; ++m)
 #pragma unroll
           for (int q = 0; q < VEC; ++q) {
-            const double xd = (double)xa[u][m][q];
-            const double wx = wt * xd;
-            S[m][q] += wx;
-            Q[m][q] = fma(wx, xd, Q[m][q]);
+            double v = limb ? Sm[m][q] : Sh[m][q];
+#pragma unroll
+            for (int o = LPR; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
+            if (sub == 0) sh[wv][(m * LPR + sl) * VEC + q] = v;
           }
-      }
-      if (more) {
-#pragma unroll
-        for (int u = 0; u < UR; ++u)
-#pragma unroll
-          for (int m = 0; m < M; ++m)
-#pragma unroll
-            for (int q = 0; q < VEC; ++q) xa[u][m][q] = xb[u][m][q];
+        __syncthreads();
+        for (int c = threadIdx.x; c < CB; c += 256) {
+          if (cb + c < d)
+            partS[((int64_t)cidx * d + cb + c) * 2 + limb] =
+                ((sh[0][c] + sh[1][c]) + sh[2][c]) + sh[3][c];
+        }
+        __syncthreads();
       }
     }
-    // sub-waves, then waves, in a fixed order
-#pragma unroll
-    for (int m = 0; m < M; ++m)
-#pragma unroll
-      for (int q = 0; q < VEC; ++q) {
-        double v = S[m][q];
-#pragma unroll
-        for (int o = LPR; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
-        if (sub == 0) sh[wv][(m * LPR + sl) * VEC + q] = v;
-        qacc += Q[m][q];
-      }
-    __syncthreads();
-    for (int c = threadIdx.x; c < CB; c += 256) {
-      if (cb + c < d)
-        partS[(int64_t)cidx * d + cb + c] = ((sh[0][c] + sh[1][c]) + sh[2][c]) + sh[3][c];
-    }
-    __syncthreads();
-  }
-  qacc = wave_sum_f64(qacc);
-#pragma unroll
-  for (int o = LPR; o < 64; o <<= 1) wacc += __shfl_xor(wacc, o, 64);
-  if (lane == 0) {
-    shq[wv] = qacc;
-    shw[wv] = wacc;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    partQ[cidx] = ((shq[0] + shq[1]) + shq[2]) + shq[3];
-    partW[cidx] = ((shw[0] + shw[1]) + shw[2]) + shw[3];
   }
 }
 
-hipError_t launch_reduce(hipStream_t s, const float* X, int64_t n, int d, int64_t ldx,
-                         const float* w, const int32_t* perm, const int32_t* base,
-                         const int32_t* chunk_base, int k, double* partS, double* partQ,
-                         double* partW, const int* gate) {
-  const int64_t maxchunks = (n + kReduceRows - 1) / kReduceRows + k;
-  const bool vec = ((((uintptr_t)X) & 15) == 0) && (ldx % 4 == 0);
-  dim3 g((unsigned)maxchunks);
-#define KMX_R(V, M, L)                                                                         \
-  hipLaunchKernelGGL((reduce_kernel<V, M, L>), g, dim3(256), 0, s, X, d, ldx, w, perm, base, \
-                     chunk_base, k, partS, partQ, partW, gate)
+template <bool DELTA, bool WEIGHTED>
+static void launch_cf_reduce_t(hipStream_t s, dim3 g, bool vec, const float* X, int d,
+                               int64_t ldx, const float* w, const double* qrow,
+                               const int32_t* ent, const int32_t* base,
+                               const int32_t* chunk_base, int k, const double* cfs,
+                               double* partS, double* partWQ, const int* gate) {
+#define KMX_R(V, M, L)                                                                      \
+  hipLaunchKernelGGL((cf_reduce_kernel<V, M, L, DELTA, WEIGHTED>), g, dim3(256), 0, s, X, d, \
+                     ldx, w, qrow, ent, base, chunk_base, k, cfs, partS, partWQ, gate)
   // columns per pass: LPR * VEC * M, the smallest shape covering d (or 512)
   if (vec) {
     if (d > 256) KMX_R(4, 2, 64);
@@ -440,31 +570,130 @@ hipError_t launch_reduce(hipStream_t s, const float* X, int64_t n, int d, int64_
     else KMX_R(1, 1, 16);
   }
 #undef KMX_R
+}
+
+hipError_t launch_cf_prep(hipStream_t s, const float* X, int64_t n, int d, int64_t ldx,
+                          unsigned* colmax, double* qrow, unsigned long long* qmax,
+                          int num_cus) {
+  hipError_t e = hipMemsetAsync(colmax, 0, (size_t)d * sizeof(unsigned), s);
+  if (e != hipSuccess) return e;
+  e = hipMemsetAsync(qmax, 0, sizeof(unsigned long long), s);
+  if (e != hipSuccess) return e;
+  const int tiles = (d + 255) / 256;
+  int64_t slices = ((int64_t)num_cus * 8 + tiles - 1) / tiles;
+  if (slices > n) slices = n;
+  if (slices < 1) slices = 1;
+  const int64_t rps = (n + slices - 1) / slices;
+  hipLaunchKernelGGL(cf_colmax_kernel, dim3(tiles, (unsigned)slices), dim3(256), 0, s, X, n, d,
+                     ldx, rps, colmax);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  int64_t blocks = (n + 3) / 4;
+  if (blocks > (int64_t)num_cus * 16) blocks = (int64_t)num_cus * 16;
+  hipLaunchKernelGGL(cf_rowq_kernel, dim3((unsigned)blocks), dim3(256), 0, s, X, n, d, ldx, qrow,
+                     qmax);
   return hipGetLastError();
 }
 
-// ---- 7. per-cluster finalize: sum chunks, new center, cost terms ----
-__global__ __launch_bounds__(256) void finalize_kernel(
-    const double* __restrict__ partS, const double* __restrict__ partQ,
-    const double* __restrict__ partW, const int32_t* __restrict__ chunk_base, int k, int d,
-    const float* C_prev, float* C_out, double* __restrict__ W_out, double* __restrict__ termC,
-    double* __restrict__ termMu, int write_c, const int* __restrict__ gate) {
+hipError_t launch_cf_scales(hipStream_t s, const unsigned* colmax, int d,
+                            const unsigned long long* qmax, const float* w, int64_t n,
+                            unsigned* wmax, double* cfs, int num_cus) {
+  if (w) {
+    hipError_t e = hipMemsetAsync(wmax, 0, sizeof(unsigned), s);
+    if (e != hipSuccess) return e;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > (int64_t)num_cus * 4) blocks = (int64_t)num_cus * 4;
+    hipLaunchKernelGGL(cf_wmax_kernel, dim3((unsigned)blocks), dim3(256), 0, s, w, n, wmax);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(cf_scales_kernel, dim3(1), dim3(256), 0, s, colmax, d, qmax,
+                     w ? wmax : nullptr, cfs);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(hipStream_t s, const float* X, int64_t n, int d, int64_t ldx,
+                         const float* w, const double* qrow, const int32_t* ent,
+                         const int32_t* base, const int32_t* chunk_base, int k,
+                         const double* cfs, double* partS, double* partWQ, int delta,
+                         int num_cus, const int* gate) {
+  const int64_t maxchunks = (n + kReduceRows - 1) / kReduceRows + k;
+  const bool vec = ((((uintptr_t)X) & 15) == 0) && (ldx % 4 == 0);
+  // the full reduction takes one workgroup per possible chunk; the delta one
+  // (whose chunk count is only known on the device) a grid-stride loop
+  int64_t blocks = maxchunks;
+  if (delta && blocks > (int64_t)num_cus * 4) blocks = (int64_t)num_cus * 4;
+  const dim3 g((unsigned)blocks);
+  if (delta) {
+    if (w) launch_cf_reduce_t<true, true>(s, g, vec, X, d, ldx, w, qrow, ent, base, chunk_base, k, cfs, partS, partWQ, gate);
+    else launch_cf_reduce_t<true, false>(s, g, vec, X, d, ldx, w, qrow, ent, base, chunk_base, k, cfs, partS, partWQ, gate);
+  } else {
+    if (w) launch_cf_reduce_t<false, true>(s, g, vec, X, d, ldx, w, qrow, ent, base, chunk_base, k, cfs, partS, partWQ, gate);
+    else launch_cf_reduce_t<false, false>(s, g, vec, X, d, ldx, w, qrow, ent, base, chunk_base, k, cfs, partS, partWQ, gate);
+  }
+  return hipGetLastError();
+}
+
+// ---- 7. per-cluster finalize: chunk sums (+ the carried features), new
+// center, cost terms ----
+// Limb sums of one feature: the chunks' exact FP64 integers summed in int64.
+// acc (nullable) holds the cluster's features across calls of one Lloyd run:
+// mode 1 stores the sums in it, mode 0 adds them to it (the chunks then hold
+// the changes of a delta reduction).  *mode_p selects the mode and the chunk
+// bases (chunk_base for mode 1, dchunk for mode 0); mode_p == nullptr: mode 1.
+__device__ __forceinline__ double cf_value(long long H, long long Mlo, double inv) {
+  // H 2^31 + Mlo with Mlo reduced to [0, 2^31), then one conversion
+  const long long carry = Mlo >> 31;   // floor division (arithmetic shift)
+  const long long ml = Mlo - carry * (1ll << 31);
+  const long long hh = H + carry;
+  return fma((double)hh, 0x1p31, (double)ml) * inv;
+}
+
+__global__ __launch_bounds__(256) void cf_finalize_kernel(
+    const double* __restrict__ partS, const double* __restrict__ partWQ,
+    const int32_t* __restrict__ chunk_base, const int32_t* __restrict__ dchunk,
+    const int* __restrict__ mode_p, long long* __restrict__ acc, int k, int d,
+    const double* __restrict__ cfs, const float* C_prev, float* C_out, double* __restrict__ W_out,
+    double* __restrict__ termC, double* __restrict__ termMu, int write_c,
+    LoopState* __restrict__ st, const int* __restrict__ gate) {
   if (gate && *gate) return;
   __shared__ double red[3][4];
+  __shared__ double sWQ[2];
   const int j = blockIdx.x;
-  const int c0 = chunk_base[j], c1 = chunk_base[j + 1];
-  // chunk sums in chunk order; unrolled so that the loads issue together
-  double W = 0.0, Q = 0.0;
-#pragma unroll 8
-  for (int c = c0; c < c1; ++c) {
-    W += partW[c];
-    Q += partQ[c];
+  const int mode = mode_p ? *mode_p : 1;
+  const int32_t* cbp = mode ? chunk_base : dchunk;
+  const int c0 = cbp[j], c1 = cbp[j + 1];
+  long long* accS = acc ? acc + (int64_t)j * d * 2 : nullptr;
+  long long* accWQ = acc ? acc + (int64_t)k * d * 2 + (int64_t)j * 4 : nullptr;
+  if (threadIdx.x < 4) {
+    const int q = threadIdx.x;
+    long long s = (!mode && accWQ) ? accWQ[q] : 0ll;
+    for (int c = c0; c < c1; ++c) s += (long long)partWQ[(int64_t)c * 4 + q];
+    if (accWQ) accWQ[q] = s;
+    // lanes 0 and 1 form W, lanes 2 and 3 form Q
+    const long long o = __shfl_xor(s, 1, 64);
+    if (q == 0) sWQ[0] = cf_value(s, o, cfs[2 * d + 1]);
+    if (q == 2) sWQ[1] = cf_value(s, o, cfs[2 * d + 3]);
   }
+  __syncthreads();
+  const double W = sWQ[0], Q = sWQ[1];
   double dotCS = 0.0, cn2 = 0.0, s2 = 0.0;
   for (int col = threadIdx.x; col < d; col += 256) {
-    double S = 0.0;
-#pragma unroll 8
-    for (int c = c0; c < c1; ++c) S += partS[(int64_t)c * d + col];
+    long long H = 0, L = 0;
+    if (!mode && accS) {
+      H = accS[col * 2];
+      L = accS[col * 2 + 1];
+    }
+    for (int c = c0; c < c1; ++c) {
+      const double* p = partS + ((int64_t)c * d + col) * 2;
+      H += (long long)p[0];
+      L += (long long)p[1];
+    }
+    if (accS) {
+      accS[col * 2] = H;
+      accS[col * 2 + 1] = L;
+    }
+    const double S = cf_value(H, L, cfs[d + col]);
     const float cp = C_prev[(int64_t)j * d + col];
     const double cpd = (double)cp;
     dotCS += cpd * S;
@@ -489,15 +718,195 @@ __global__ __launch_bounds__(256) void finalize_kernel(
     termC[j] = Q - 2.0 * a + W * b;
     termMu[j] = (W > 0.0) ? (Q - e / W) : 0.0;
     if (W_out) W_out[j] = W;
+    if (acc && st && j == 0) st->acc_valid = 1;
   }
 }
 
-hipError_t launch_finalize(hipStream_t s, const double* partS, const double* partQ,
-                           const double* partW, const int32_t* chunk_base, int k, int d,
-                           const float* C_prev, float* C_out, double* W_out, double* termC,
-                           double* termMu, int write_c, const int* gate) {
-  hipLaunchKernelGGL(finalize_kernel, dim3(k), dim3(256), 0, s, partS, partQ, partW, chunk_base,
-                     k, d, C_prev, C_out, W_out, termC, termMu, write_c, gate);
+hipError_t launch_finalize(hipStream_t s, const double* partS, const double* partWQ,
+                           const int32_t* chunk_base, const int32_t* dchunk, const int* mode_p,
+                           long long* acc, int k, int d, const double* cfs, const float* C_prev,
+                           float* C_out, double* W_out, double* termC, double* termMu,
+                           int write_c, LoopState* st, const int* gate) {
+  hipLaunchKernelGGL(cf_finalize_kernel, dim3(k), dim3(256), 0, s, partS, partWQ, chunk_base,
+                     dchunk, mode_p, acc, k, d, cfs, C_prev, C_out, W_out, termC, termMu, write_c,
+                     st, gate);
+  return hipGetLastError();
+}
+
+// ---- delta update: the rows whose label changed ----
+// mark: changed rows (label != previous label) are listed with their previous
+// label (block-aggregated positions, any order), the per-cluster entry counts
+// (one removal from the old cluster, one addition to the new) are added to
+// ecount, the previous labels are brought up to date and the number of
+// changes goes to st->changed (the stopping rule) and st->dcount (the list).
+__global__ __launch_bounds__(256) void delta_mark_kernel(const int32_t* __restrict__ label,
+                                                         int32_t* __restrict__ lab_prev, int64_t n,
+                                                         int k, int32_t* __restrict__ ecount,
+                                                         int32_t* __restrict__ clist,
+                                                         int32_t* __restrict__ cold,
+                                                         LoopState* __restrict__ st,
+                                                         const int* __restrict__ gate) {
+  if (gate && *gate) return;
+  extern __shared__ int hsm[];
+  __shared__ int wcnt[4];
+  __shared__ int bbase;
+  constexpr int PER = kSortRows / 256;
+  const int64_t r0 = (int64_t)blockIdx.x * kSortRows;
+  const int64_t r1 = min(n, r0 + kSortRows);
+  int lab[PER], prev[PER];
+  unsigned chm = 0;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int64_t i = r0 + threadIdx.x + 256 * q;
+    lab[q] = (i < r1) ? label[i] : -1;
+    prev[q] = (i < r1) ? lab_prev[i] : -1;
+    if (i < r1 && lab[q] != prev[q]) chm |= 1u << q;
+  }
+  for (int j = threadIdx.x; j < k; j += blockDim.x) hsm[j] = 0;
+  __syncthreads();
+  const int cnt = __popc(chm);
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    if (chm & (1u << q)) {
+      const int64_t i = r0 + threadIdx.x + 256 * q;
+      if (lab[q] >= 0 && lab[q] < k) atomicAdd(&hsm[lab[q]], 1);
+      if (prev[q] >= 0 && prev[q] < k) atomicAdd(&hsm[prev[q]], 1);
+      lab_prev[i] = lab[q];
+    }
+  }
+  // block-exclusive offsets of the changed rows
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int x = cnt;
+#pragma unroll
+  for (int m = 1; m < 64; m <<= 1) {
+    const int y = __shfl_up(x, m, 64);
+    if (lane >= m) x += y;
+  }
+  if (lane == 63) wcnt[wv] = x;
+  __syncthreads();
+  int woff = 0;
+  for (int v = 0; v < wv; ++v) woff += wcnt[v];
+  if (threadIdx.x == 0) {
+    const int tot = wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+    bbase = tot ? (int)atomicAdd(&st->dcount, (unsigned long long)tot) : 0;
+    if (tot) atomicAdd(&st->changed, (unsigned long long)tot);
+  }
+  __syncthreads();
+  int pos = bbase + woff + x - cnt;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    if (chm & (1u << q)) {
+      clist[pos] = (int32_t)(r0 + threadIdx.x + 256 * q);
+      cold[pos] = prev[q];
+      ++pos;
+    }
+  }
+  for (int j = threadIdx.x; j < k; j += blockDim.x)
+    if (hsm[j]) atomicAdd(ecount + j, hsm[j]);
+}
+
+// plan (one workgroup of 1024): full reduction when the carried features are
+// not valid or more than half of the rows changed, else the delta one; with
+// the gate set (a stopped loop) both paths are skipped.
+// flags[0] = skip the full path, flags[1] = skip the delta path, flags[2] =
+// finalize mode (1 full, 0 delta).  The delta path gets its cluster segment
+// bases (ebase, also the scatter cursors) and chunk bases (dchunk).  ecount
+// is cleared for the next mark.
+__global__ __launch_bounds__(1024) void delta_plan_kernel(int32_t* __restrict__ ecount, int k,
+                                                          int64_t n, int32_t* __restrict__ ebase,
+                                                          int32_t* __restrict__ cursor,
+                                                          int32_t* __restrict__ dchunk,
+                                                          int* __restrict__ flags,
+                                                          LoopState* __restrict__ st,
+                                                          const int* __restrict__ gate) {
+  __shared__ int sh[64];
+  __shared__ int sfull;
+  if (threadIdx.x == 0) {
+    const int done = gate ? *gate : 0;
+    const int full = !st->acc_valid || (int64_t)st->dcount * 2 > n;
+    sfull = done ? -1 : full;
+    flags[0] = done ? 1 : !full;
+    flags[1] = done ? 1 : full;
+    flags[2] = full;
+  }
+  __syncthreads();
+  const int f = sfull;
+  if (f < 0) return;   // stopped: mark did not run, ecount is still clear
+  const int per = (k + 1023) / 1024;
+  const int j0 = threadIdx.x * per;
+  int tot = 0, ch = 0;
+  for (int q = 0; q < per; ++q) {
+    const int j = j0 + q;
+    if (j < k) {
+      tot += ecount[j];
+      ch += (ecount[j] + kReduceRows - 1) / kReduceRows;
+    }
+  }
+  if (f) {
+    for (int q = 0; q < per; ++q)
+      if (j0 + q < k) ecount[j0 + q] = 0;
+    return;
+  }
+  int total, totalc;
+  int off = block_excl_scan_1024(tot, sh, total);
+  int coff = block_excl_scan_1024(ch, sh, totalc);
+  for (int q = 0; q < per; ++q) {
+    const int j = j0 + q;
+    if (j < k) {
+      const int e = ecount[j];
+      ebase[j] = off;
+      cursor[j] = off;
+      dchunk[j] = coff;
+      off += e;
+      coff += (e + kReduceRows - 1) / kReduceRows;
+      ecount[j] = 0;
+    }
+  }
+  if (threadIdx.x == 0) {
+    ebase[k] = total;
+    dchunk[k] = totalc;
+  }
+}
+
+// scatter: every changed row becomes a removal entry in its old cluster's
+// segment and an addition entry in its new one (positions from atomic
+// cursors: any order within a segment).
+__global__ __launch_bounds__(256) void delta_scatter_kernel(const int32_t* __restrict__ label,
+                                                            const int32_t* __restrict__ clist,
+                                                            const int32_t* __restrict__ cold, int k,
+                                                            int32_t* __restrict__ cursor,
+                                                            int32_t* __restrict__ ent,
+                                                            const LoopState* __restrict__ st,
+                                                            const int* __restrict__ gate) {
+  if (gate && *gate) return;
+  const int64_t cnt = (int64_t)st->dcount;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < cnt; q += stride) {
+    const int i = clist[q];
+    const int o = cold[q];
+    const int nw = label[i];
+    if (o >= 0 && o < k) ent[atomicAdd(cursor + o, 1)] = -i - 1;
+    if (nw >= 0 && nw < k) ent[atomicAdd(cursor + nw, 1)] = i;
+  }
+}
+
+hipError_t launch_delta_prepare(hipStream_t s, const int32_t* label, int32_t* lab_prev, int64_t n,
+                                int k, int32_t* ecount, int32_t* clist, int32_t* cold,
+                                int32_t* ebase, int32_t* cursor, int32_t* dchunk, int32_t* ent,
+                                int* flags, LoopState* st, int num_cus, const int* gate) {
+  const int nb = (int)((n + kSortRows - 1) / kSortRows);
+  hipLaunchKernelGGL(delta_mark_kernel, dim3(nb), dim3(256), (size_t)k * sizeof(int), s, label,
+                     lab_prev, n, k, ecount, clist, cold, st, gate);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(delta_plan_kernel, dim3(1), dim3(1024), 0, s, ecount, k, n, ebase, cursor,
+                     dchunk, flags, st, gate);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > (int64_t)num_cus * 4) blocks = (int64_t)num_cus * 4;
+  hipLaunchKernelGGL(delta_scatter_kernel, dim3((unsigned)blocks), dim3(256), 0, s, label, clist,
+                     cold, k, cursor, ent, st, flags + 1);
   return hipGetLastError();
 }
 

@@ -151,12 +151,58 @@ kmx_status ensure_common(kmx_ctx* ctx, int64_t n, int d, int k) {
   KMX_TRY(grow(ctx, ctx->base, (size_t)(k + 1) * sizeof(int32_t)));
   KMX_TRY(grow(ctx, ctx->chunk_base, (size_t)(k + 1) * sizeof(int32_t)));
   KMX_TRY(grow(ctx, ctx->perm, (size_t)n * sizeof(int32_t)));
-  KMX_TRY(grow(ctx, ctx->partS, (size_t)maxchunks * d * sizeof(double)));
-  KMX_TRY(grow(ctx, ctx->partQ, (size_t)maxchunks * sizeof(double)));
-  KMX_TRY(grow(ctx, ctx->partW, (size_t)maxchunks * sizeof(double)));
+  KMX_TRY(grow(ctx, ctx->partS, (size_t)maxchunks * d * 2 * sizeof(double)));
+  KMX_TRY(grow(ctx, ctx->partWQ, (size_t)maxchunks * 4 * sizeof(double)));
+  KMX_TRY(grow(ctx, ctx->cfs, (size_t)(2 * d + 4) * sizeof(double)));
+  KMX_TRY(grow(ctx, ctx->cf_wmax, 16));
+  KMX_TRY(grow(ctx, ctx->cf_acc, ((size_t)k * d * 2 + (size_t)k * 4) * sizeof(long long)));
+  KMX_TRY(grow(ctx, ctx->ecount, (size_t)(k + 1) * sizeof(int32_t)));
+  KMX_TRY(grow(ctx, ctx->ebase, (size_t)(k + 1) * sizeof(int32_t)));
+  KMX_TRY(grow(ctx, ctx->ecursor, (size_t)(k + 1) * sizeof(int32_t)));
+  KMX_TRY(grow(ctx, ctx->dchunk, (size_t)(k + 1) * sizeof(int32_t)));
+  KMX_TRY(grow(ctx, ctx->clist, (size_t)n * sizeof(int32_t)));
+  KMX_TRY(grow(ctx, ctx->cold, (size_t)n * sizeof(int32_t)));
+  KMX_TRY(grow(ctx, ctx->dent, (size_t)n * sizeof(int32_t)));
+  KMX_TRY(grow(ctx, ctx->cfflag, 16));
   KMX_TRY(grow(ctx, ctx->W, (size_t)k * sizeof(double)));
   KMX_TRY(grow(ctx, ctx->termC, (size_t)k * sizeof(double)));
   KMX_TRY(grow(ctx, ctx->termMu, (size_t)k * sizeof(double)));
+  return KMX_OK;
+}
+
+// Grids of the exactly summed clustering features: the dataset's column
+// maxima and row norms (cached per dataset like the quantized copies), then
+// the call's scales, which also depend on the largest weight.
+kmx_status ensure_cf(kmx_ctx* ctx, const float* X, int64_t n, int d, int64_t ldx,
+                     const float* w) {
+  if (!(ctx->cf_valid && ctx->cf_X == X && ctx->cf_n == n && ctx->cf_d == d &&
+        ctx->cf_ldx == ldx)) {
+    ctx->cf_valid = false;
+    KMX_TRY(grow(ctx, ctx->cf_colmax, (size_t)d * sizeof(unsigned)));
+    KMX_TRY(grow(ctx, ctx->cf_q, (size_t)n * sizeof(double)));
+    KMX_TRY(grow(ctx, ctx->cf_qmax, 16));
+    Timed tm(ctx, T_PREP);
+    KMX_HIP(ctx, launch_cf_prep(ctx->stream, X, n, d, ldx, P<unsigned>(ctx->cf_colmax),
+                                P<double>(ctx->cf_q), P<unsigned long long>(ctx->cf_qmax),
+                                ctx->num_cus));
+    ctx->cf_X = X;
+    ctx->cf_n = n;
+    ctx->cf_d = d;
+    ctx->cf_ldx = ldx;
+    ctx->cf_valid = true;
+  }
+  KMX_HIP(ctx, launch_cf_scales(ctx->stream, P<unsigned>(ctx->cf_colmax), d,
+                                P<unsigned long long>(ctx->cf_qmax), w, n,
+                                P<unsigned>(ctx->cf_wmax), P<double>(ctx->cfs), ctx->num_cus));
+  return KMX_OK;
+}
+
+// Start of a Lloyd run: no carried features, entry counts clear, previous
+// labels unknown.
+kmx_status begin_lloyd(kmx_ctx* ctx, int32_t* prev, int64_t n) {
+  KMX_HIP(ctx, launch_fill_i32(ctx->stream, prev, n, -1));
+  KMX_HIP(ctx, launch_fill_i32(ctx->stream, P<int32_t>(ctx->ecount), (int64_t)ctx->ecount.bytes / 4, 0));
+  KMX_HIP(ctx, launch_fill_i32(ctx->stream, P<int32_t>(ctx->cfflag), 4, 1));
   return KMX_OK;
 }
 
@@ -305,32 +351,53 @@ kmx_status run_assign(kmx_ctx* ctx, const float* X, int64_t n, int d, int64_t ld
   return run_assign_gemm(ctx, X, n, d, ldx, C, k, prec, label, d1, d2, nullptr, nullptr, gate);
 }
 
-// sort + segmented reduction + finalize + cost sums.
+// Update step: finalize + cost sums after a full reduction (sort by label,
+// then every row) or, with lab_prev, after whichever of the full and the
+// delta reduction the device-side plan picks (the rows whose label differs
+// from lab_prev, added to the features carried from the previous update).
 kmx_status run_update(kmx_ctx* ctx, const float* X, int64_t n, int d, int64_t ldx, const float* w,
                       const int32_t* label, int k, const float* C_prev, float* C_out,
                       double* W_out, int write_c, int32_t* lab_prev, double* hist, int mode,
                       const int* gate) {
   LoopState* st = ST(ctx);
+  int* flags = P<int>(ctx->cfflag);
+  const int* gate_full = lab_prev ? flags : gate;
   {
     Timed tm(ctx, T_SORT);
-    KMX_HIP(ctx, launch_sort(ctx->stream, label, lab_prev, n, k, P<int32_t>(ctx->counts),
+    if (lab_prev)
+      KMX_HIP(ctx, launch_delta_prepare(ctx->stream, label, lab_prev, n, k,
+                                        P<int32_t>(ctx->ecount), P<int32_t>(ctx->clist),
+                                        P<int32_t>(ctx->cold), P<int32_t>(ctx->ebase),
+                                        P<int32_t>(ctx->ecursor), P<int32_t>(ctx->dchunk),
+                                        P<int32_t>(ctx->dent), flags, st, ctx->num_cus, gate));
+    KMX_HIP(ctx, launch_sort(ctx->stream, label, nullptr, n, k, P<int32_t>(ctx->counts),
                              P<int32_t>(ctx->segsum), P<int32_t>(ctx->base),
-                             P<int32_t>(ctx->chunk_base), P<int32_t>(ctx->perm), st,
-                             lab_prev ? 1 : 0, gate));
+                             P<int32_t>(ctx->chunk_base), P<int32_t>(ctx->perm), st, 0,
+                             gate_full));
   }
   {
     Timed tm(ctx, T_REDUCE);
-    KMX_HIP(ctx, launch_reduce(ctx->stream, X, n, d, ldx, w, P<int32_t>(ctx->perm),
-                               P<int32_t>(ctx->base), P<int32_t>(ctx->chunk_base), k,
-                               P<double>(ctx->partS), P<double>(ctx->partQ),
-                               P<double>(ctx->partW), gate));
+    KMX_HIP(ctx, launch_reduce(ctx->stream, X, n, d, ldx, w, P<double>(ctx->cf_q),
+                               P<int32_t>(ctx->perm), P<int32_t>(ctx->base),
+                               P<int32_t>(ctx->chunk_base), k, P<double>(ctx->cfs),
+                               P<double>(ctx->partS), P<double>(ctx->partWQ), 0, ctx->num_cus,
+                               gate_full));
+    if (lab_prev)
+      KMX_HIP(ctx, launch_reduce(ctx->stream, X, n, d, ldx, w, P<double>(ctx->cf_q),
+                                 P<int32_t>(ctx->dent), P<int32_t>(ctx->ebase),
+                                 P<int32_t>(ctx->dchunk), k, P<double>(ctx->cfs),
+                                 P<double>(ctx->partS), P<double>(ctx->partWQ), 1, ctx->num_cus,
+                                 flags + 1));
   }
   {
     Timed tm(ctx, T_FINAL);
-    KMX_HIP(ctx, launch_finalize(ctx->stream, P<double>(ctx->partS), P<double>(ctx->partQ),
-                                 P<double>(ctx->partW), P<int32_t>(ctx->chunk_base), k, d, C_prev,
-                                 C_out, W_out ? W_out : P<double>(ctx->W), P<double>(ctx->termC),
-                                 P<double>(ctx->termMu), write_c, gate));
+    KMX_HIP(ctx, launch_finalize(ctx->stream, P<double>(ctx->partS), P<double>(ctx->partWQ),
+                                 P<int32_t>(ctx->chunk_base), P<int32_t>(ctx->dchunk),
+                                 lab_prev ? flags + 2 : nullptr,
+                                 lab_prev ? P<long long>(ctx->cf_acc) : nullptr, k, d,
+                                 P<double>(ctx->cfs), C_prev, C_out,
+                                 W_out ? W_out : P<double>(ctx->W), P<double>(ctx->termC),
+                                 P<double>(ctx->termMu), write_c, st, gate));
     KMX_HIP(ctx, launch_cost_sum(ctx->stream, P<double>(ctx->termC), P<double>(ctx->termMu), k,
                                  st, hist, mode, gate));
   }
@@ -394,8 +461,11 @@ kmx_status kmx_destroy(kmx_ctx* ctx) {
       &ctx->cstats32,  &ctx->full_rows, &ctx->brute,     &ctx->rowstats,   &ctx->cq,
       &ctx->ch,        &ctx->cstats,   &ctx->lab_a,      &ctx->lab_prev,   &ctx->d1,
       &ctx->d2,        &ctx->flags,    &ctx->counters,   &ctx->counts,     &ctx->segsum,
-      &ctx->base,      &ctx->chunk_base, &ctx->perm,     &ctx->partS,      &ctx->partQ,
-      &ctx->partW,     &ctx->W,        &ctx->termC,      &ctx->termMu,     &ctx->state,     &ctx->vcheck,    &ctx->hub,
+      &ctx->base,      &ctx->chunk_base, &ctx->perm,     &ctx->partS,      &ctx->partWQ,
+      &ctx->cf_colmax, &ctx->cf_q,     &ctx->cf_qmax,    &ctx->cf_wmax,    &ctx->cfs,
+      &ctx->cf_acc,    &ctx->ecount,   &ctx->ebase,      &ctx->ecursor,    &ctx->dchunk,
+      &ctx->clist,     &ctx->cold,     &ctx->dent,       &ctx->cfflag,
+      &ctx->W,        &ctx->termC,      &ctx->termMu,     &ctx->state,     &ctx->vcheck,    &ctx->hub,
       &ctx->hlb,       &ctx->hl2,      &ctx->hsec,       &ctx->bl_rows,  &ctx->cprev,      &ctx->drift,      &ctx->dstat,
       &ctx->bkh,
       &ctx->D2,        &ctx->chosen,   &ctx->seed_part,  &ctx->seed_ctr,   &ctx->scratch_c,
@@ -408,7 +478,8 @@ kmx_status kmx_destroy(kmx_ctx* ctx) {
       &ctx->sv_om,     &ctx->sv_y,     &ctx->sv_y2,      &ctx->sv_z,       &ctx->sv_g,      &ctx->sv_part,
       &ctx->sv_r,      &ctx->sv_v,
       &ctx->bitems,    &ctx->binsts,   &ctx->bbuckets,   &ctx->bcinst,     &ctx->bxstats,
-      &ctx->btermC,    &ctx->btermMu,  &ctx->bW,         &ctx->bcost};
+      &ctx->btermC,    &ctx->btermMu,  &ctx->bW,         &ctx->bcost,      &ctx->bcf_colmax,
+      &ctx->bcf_q,     &ctx->bcf_qmax, &ctx->bcf_wmax,   &ctx->bcfs};
   for (kmx::Buf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   if (ctx->lg_exec) (void)hipGraphExecDestroy(ctx->lg_exec);
@@ -434,6 +505,7 @@ kmx_status kmx_invalidate(kmx_ctx* ctx, const float* X) {
   if (!ctx) return KMX_EINVAL;
   if (X == nullptr || ctx->cache_X == X) ctx->cache_valid = false;
   if (X == nullptr || ctx->cache8_X == X) ctx->cache8_valid = false;
+  if (X == nullptr || ctx->cf_X == X) ctx->cf_valid = false;
   return KMX_OK;
 }
 
@@ -524,6 +596,7 @@ kmx_status kmx_update(kmx_ctx* ctx, const float* X, int64_t n, int32_t d, int64_
   KMX_TRY(set_device(ctx));
   if (ctx->validate) KMX_TRY(check_data(ctx, X, n, d, ldx, w, 0, C_prev, k));
   KMX_TRY(ensure_common(ctx, n, d, k));
+  KMX_TRY(ensure_cf(ctx, X, n, d, ldx, w));
   KMX_TRY(run_update(ctx, X, n, d, ldx, w, label, k, C_prev, C_out, W_out, 1, nullptr, nullptr, 2,
                      nullptr));
   if (cost_at_centroids) {
@@ -546,6 +619,7 @@ kmx_status kmx_cost(kmx_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t 
   KMX_TRY(check_data(ctx, X, n, d, ldx, w, 0, C, k));
   KMX_TRY(ensure_common(ctx, n, d, k));
   KMX_TRY(ensure_prep(ctx, X, n, d, ldx, prec));
+  KMX_TRY(ensure_cf(ctx, X, n, d, ldx, w));
   int32_t* lab = P<int32_t>(ctx->lab_a);
   KMX_TRY(run_assign(ctx, X, n, d, ldx, C, k, prec, lab, nullptr, nullptr, nullptr));
   KMX_TRY(run_update(ctx, X, n, d, ldx, w, lab, k, C, nullptr, nullptr, 0, nullptr, nullptr, 2,
@@ -578,12 +652,13 @@ static kmx_status lloyd_impl(kmx_ctx* ctx, const float* X, int64_t n, int32_t d,
   KMX_TRY(ensure_prep(ctx, X, n, d, ldx, prec));
   KMX_TRY(grow(ctx, ctx->lab_prev, (size_t)n * sizeof(int32_t)));
   KMX_TRY(grow(ctx, ctx->hist, (size_t)(max_iter + 1) * sizeof(double)));
+  KMX_TRY(ensure_cf(ctx, X, n, d, ldx, w));
   KMX_TRY(write_state(ctx, max_iter, tol));
   int32_t* lab = label_out ? label_out : P<int32_t>(ctx->lab_a);
   int32_t* prev = P<int32_t>(ctx->lab_prev);
   double* hist = P<double>(ctx->hist);
   LoopState* st = ST(ctx);
-  KMX_HIP(ctx, launch_fill_i32(ctx->stream, prev, n, -1));
+  KMX_TRY(begin_lloyd(ctx, prev, n));
   if (graph && max_iter > 0) {
     // every buffer an iteration touches exists before the capture starts
     KMX_TRY(run_prep_centers(ctx, C_inout, k, d, prec));
@@ -648,9 +723,10 @@ static kmx_status lloyd_impl(kmx_ctx* ctx, const float* X, int64_t n, int32_t d,
                          0, &st->done));
     }
   }
-  // final assignment: labels and cost of the returned centers
+  // final assignment: labels and cost of the returned centers (the features
+  // of its labels come from the last update's by the rows that changed)
   KMX_TRY(run_assign(ctx, X, n, d, ldx, C_inout, k, prec, lab, nullptr, nullptr, nullptr));
-  KMX_TRY(run_update(ctx, X, n, d, ldx, w, lab, k, C_inout, nullptr, nullptr, 0, nullptr, hist, 1,
+  KMX_TRY(run_update(ctx, X, n, d, ldx, w, lab, k, C_inout, nullptr, nullptr, 0, prev, hist, 1,
                      nullptr));
   LoopState h;
   KMX_HIP(ctx, hipMemcpyAsync(&h, ctx->state.p, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
@@ -711,6 +787,23 @@ kmx_status kmx_assign_stats(kmx_ctx* ctx, int64_t* listed, int64_t* fp32, int64_
   if (listed) *listed = (int64_t)h.flagged;
   if (fp32) *fp32 = (int64_t)(ctx->last_prec == KMX_FP8E4M3 ? h.full_count2 : h.full_count);
   if (full) *full = (int64_t)h.flagged_full;
+  return KMX_OK;
+}
+
+kmx_status kmx_update_stats(kmx_ctx* ctx, int64_t* changed, int32_t* delta) {
+  if (!ctx) return KMX_EINVAL;
+  ctx->err.clear();
+  if (changed) *changed = 0;
+  if (delta) *delta = 0;
+  if (!ctx->state.p || !ctx->cfflag.p) return KMX_OK;
+  KMX_TRY(set_device(ctx));
+  LoopState h;
+  int f[4];
+  KMX_HIP(ctx, hipMemcpyAsync(&h, ctx->state.p, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+  KMX_HIP(ctx, hipMemcpyAsync(f, ctx->cfflag.p, sizeof(f), hipMemcpyDeviceToHost, ctx->stream));
+  KMX_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  if (changed) *changed = (int64_t)h.dcount;
+  if (delta) *delta = f[2] == 0 ? 1 : 0;
   return KMX_OK;
 }
 

@@ -30,6 +30,9 @@ struct BucketPlan {
   std::vector<int> members;                          // internal instance indices
 };
 
+// Widest row of the batched path: the stride of the per-bucket feature grids.
+constexpr int kBatchCfD = 512;
+
 struct Plan {
   std::vector<BatchInst> insts;   // internal order: bucket by bucket
   std::vector<int> user_of;       // internal -> caller's index
@@ -236,9 +239,13 @@ kmx_status setup(kmx_ctx* ctx, const kmx_problem* probs, Plan& pl, int stride) {
   KMX_TRY(grow(ctx, ctx->base, (size_t)(pl.max_K + 1) * sizeof(int32_t)));
   KMX_TRY(grow(ctx, ctx->chunk_base, (size_t)(pl.max_K + 1) * sizeof(int32_t)));
   KMX_TRY(grow(ctx, ctx->perm, (size_t)pl.max_n * sizeof(int32_t)));
-  KMX_TRY(grow(ctx, ctx->partS, (size_t)pl.max_chunks_d * sizeof(double)));
-  KMX_TRY(grow(ctx, ctx->partQ, (size_t)pl.max_chunks * sizeof(double)));
-  KMX_TRY(grow(ctx, ctx->partW, (size_t)pl.max_chunks * sizeof(double)));
+  KMX_TRY(grow(ctx, ctx->partS, (size_t)pl.max_chunks_d * 2 * sizeof(double)));
+  KMX_TRY(grow(ctx, ctx->partWQ, (size_t)pl.max_chunks * 4 * sizeof(double)));
+  KMX_TRY(grow(ctx, ctx->bcf_colmax, (size_t)nb * kBatchCfD * sizeof(unsigned)));
+  KMX_TRY(grow(ctx, ctx->bcf_q, (size_t)pl.N * sizeof(double)));
+  KMX_TRY(grow(ctx, ctx->bcf_qmax, (size_t)nb * sizeof(unsigned long long)));
+  KMX_TRY(grow(ctx, ctx->bcf_wmax, (size_t)nb * sizeof(unsigned)));
+  KMX_TRY(grow(ctx, ctx->bcfs, (size_t)nb * (2 * kBatchCfD + 4) * sizeof(double)));
 
   float* bX = P<float>(ctx->bX);
   float* bC = P<float>(ctx->bC);
@@ -300,6 +307,15 @@ kmx_status setup(kmx_ctx* ctx, const kmx_problem* probs, Plan& pl, int stride) {
     Timed tm(ctx, T_PREP);
     KMX_HIP(ctx, launch_prep_rows(s, bX + B.xoff, B.n, B.d, B.d, B.dp, bXq + B.xqoff,
                                   P<RowStats>(ctx->brs) + B.grow0, xst + b, ctx->num_cus));
+    // the bucket's feature grids (one bound for all of its instances)
+    unsigned* cm = P<unsigned>(ctx->bcf_colmax) + (int64_t)b * kBatchCfD;
+    unsigned long long* qm = P<unsigned long long>(ctx->bcf_qmax) + b;
+    KMX_HIP(ctx, launch_cf_prep(s, bX + B.xoff, B.n, B.d, B.d, cm, P<double>(ctx->bcf_q) + B.grow0,
+                                qm, ctx->num_cus));
+    KMX_HIP(ctx, launch_cf_scales(s, cm, B.d, qm, P<float>(ctx->bw) + B.grow0, B.n,
+                                  P<unsigned>(ctx->bcf_wmax) + b,
+                                  P<double>(ctx->bcfs) + (int64_t)b * (2 * kBatchCfD + 4),
+                                  ctx->num_cus));
   }
   return KMX_OK;
 }
@@ -331,16 +347,18 @@ hipError_t enqueue_iteration(kmx_ctx* ctx, const Plan& pl, hipStream_t s, int wr
                          P<int32_t>(ctx->chunk_base), P<int32_t>(ctx->perm), st, 0, nullptr)) !=
         hipSuccess)
       return e;
+    const double* cfs = P<double>(ctx->bcfs) + (int64_t)b * (2 * kBatchCfD + 4);
     if ((e = launch_reduce(s, Xb, B.n, B.d, B.d, P<float>(ctx->bw) + B.grow0,
-                           P<int32_t>(ctx->perm), P<int32_t>(ctx->base),
-                           P<int32_t>(ctx->chunk_base), B.K, P<double>(ctx->partS),
-                           P<double>(ctx->partQ), P<double>(ctx->partW), nullptr)) != hipSuccess)
+                           P<double>(ctx->bcf_q) + B.grow0, P<int32_t>(ctx->perm),
+                           P<int32_t>(ctx->base), P<int32_t>(ctx->chunk_base), B.K, cfs,
+                           P<double>(ctx->partS), P<double>(ctx->partWQ), 0, ctx->num_cus,
+                           nullptr)) != hipSuccess)
       return e;
-    if ((e = launch_finalize(s, P<double>(ctx->partS), P<double>(ctx->partQ),
-                             P<double>(ctx->partW), P<int32_t>(ctx->chunk_base), B.K, B.d, Cb,
-                             write_c ? Cb : nullptr, P<double>(ctx->bW) + B.kg0,
+    if ((e = launch_finalize(s, P<double>(ctx->partS), P<double>(ctx->partWQ),
+                             P<int32_t>(ctx->chunk_base), nullptr, nullptr, nullptr, B.K, B.d, cfs,
+                             Cb, write_c ? Cb : nullptr, P<double>(ctx->bW) + B.kg0,
                              P<double>(ctx->btermC) + B.kg0, P<double>(ctx->btermMu) + B.kg0,
-                             write_c, nullptr)) != hipSuccess)
+                             write_c, nullptr, nullptr)) != hipSuccess)
       return e;
   }
   return launch_batch_cost(s, insts, ni, P<double>(ctx->btermC), P<double>(ctx->bcost), stride,

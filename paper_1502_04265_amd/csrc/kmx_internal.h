@@ -57,6 +57,9 @@ struct LoopState {
   unsigned long long routed_listed;    // certified rows that needed the short re-check
   unsigned long long bound_fail;       // rows the carried bounds could not keep (last assign)
   unsigned long long bound_pair;       // rows they sent to the re-check with their runner-up
+  unsigned long long dcount;           // changed rows listed for the delta update (this update)
+  int acc_valid;                       // the carried clustering features hold the last labels
+  int pad_;
 };
 
 // Entry of the short re-check list: row index and the other candidates (the
@@ -193,7 +196,16 @@ struct kmx_ctx {
   kmx::Buf lab_a, lab_prev, d1, d2;
   kmx::Buf flags, counters;
   kmx::Buf counts, segsum, base, chunk_base, perm;
-  kmx::Buf partS, partQ, partW;
+  kmx::Buf partS, partWQ;
+  // exactly summed clustering features: per-dataset column maxima and row
+  // norms (cached like the quantized copies), the call's grids, the features
+  // carried across Lloyd iterations and the delta update's lists
+  const float* cf_X = nullptr;
+  int64_t cf_n = 0, cf_ldx = 0;
+  int cf_d = 0;
+  bool cf_valid = false;
+  kmx::Buf cf_colmax, cf_q, cf_qmax, cf_wmax, cfs, cf_acc;
+  kmx::Buf ecount, ebase, ecursor, dchunk, clist, cold, dent, cfflag;
   kmx::Buf W, termC, termMu;
   kmx::Buf state;
   kmx::Buf vcheck;   // argument-check counters
@@ -206,6 +218,7 @@ struct kmx_ctx {
   kmx::Buf sv_om, sv_y, sv_y2, sv_z, sv_g, sv_part, sv_r, sv_v;   // range finder
   kmx::Buf bX, bXq, brs, bw, bC, bCq, bhd, bch, bcs, blab, bitems, binsts, bbuckets, bcinst, bxstats;
   kmx::Buf btermC, btermMu, bW, bcost;
+  kmx::Buf bcf_colmax, bcf_q, bcf_qmax, bcf_wmax, bcfs;   // per-bucket feature grids
   hipStream_t cap_stream = nullptr;                // stream graphs are captured on (batched, graphed Lloyd)
   uint64_t ws_gen = 0;                             // bumped whenever a workspace buffer moves
   // the last captured Lloyd iteration of kmx_lloyd_graph and what it was captured for
@@ -290,14 +303,41 @@ hipError_t launch_sort(hipStream_t s, const int32_t* label, int32_t* lab_prev, i
                        int k, int32_t* counts, int32_t* segsum, int32_t* base,
                        int32_t* chunk_base, int32_t* perm, LoopState* st, int track,
                        const int* gate);
+// Exactly summed clustering features (k_update.hip).  cf_prep: column maxima
+// of |x| (d entries) and FP64 row norms (n entries) with their maximum, once
+// per dataset.  cf_scales: the call's grids (cfs: 2 d + 4 doubles) from them
+// and the largest weight (w == nullptr: unit weights; wmax is scratch).
+hipError_t launch_cf_prep(hipStream_t s, const float* X, int64_t n, int d, int64_t ldx,
+                          unsigned* colmax, double* qrow, unsigned long long* qmax, int num_cus);
+hipError_t launch_cf_scales(hipStream_t s, const unsigned* colmax, int d,
+                            const unsigned long long* qmax, const float* w, int64_t n,
+                            unsigned* wmax, double* cfs, int num_cus);
+// Chunk reduction into limb sums: partS holds 2 d doubles per chunk, partWQ 4.
+// delta = 0: ent is the sorted permutation (base / chunk_base from the sort);
+// delta = 1: signed entries (ebase / dchunk from the delta plan).
 hipError_t launch_reduce(hipStream_t s, const float* X, int64_t n, int d, int64_t ldx,
-                         const float* w, const int32_t* perm, const int32_t* base,
-                         const int32_t* chunk_base, int k, double* partS, double* partQ,
-                         double* partW, const int* gate);
-hipError_t launch_finalize(hipStream_t s, const double* partS, const double* partQ,
-                           const double* partW, const int32_t* chunk_base, int k, int d,
-                           const float* C_prev, float* C_out, double* W_out,
-                           double* termC, double* termMu, int write_c, const int* gate);
+                         const float* w, const double* qrow, const int32_t* ent,
+                         const int32_t* base, const int32_t* chunk_base, int k,
+                         const double* cfs, double* partS, double* partWQ, int delta,
+                         int num_cus, const int* gate);
+// New centers and cost terms from the chunk sums.  acc (nullable, k d 2 + 4 k
+// int64) carries the features across iterations; *mode_p = 1 stores the full
+// reduction's sums in it, 0 adds the delta reduction's; mode_p == nullptr
+// means 1.  Sets st->acc_valid when acc is written.
+hipError_t launch_finalize(hipStream_t s, const double* partS, const double* partWQ,
+                           const int32_t* chunk_base, const int32_t* dchunk, const int* mode_p,
+                           long long* acc, int k, int d, const double* cfs, const float* C_prev,
+                           float* C_out, double* W_out, double* termC, double* termMu,
+                           int write_c, LoopState* st, const int* gate);
+// Delta update set-up: mark the changed rows (updating lab_prev, st->changed,
+// st->dcount; st->dcount must be zero before), plan (flags[0] / flags[1]:
+// skip the full / delta path, flags[2]: finalize mode) and scatter the signed
+// entries into dent.  ecount (k) must be zero before the first call; the plan
+// clears it again.  gate: a set value skips both paths.
+hipError_t launch_delta_prepare(hipStream_t s, const int32_t* label, int32_t* lab_prev, int64_t n,
+                                int k, int32_t* ecount, int32_t* clist, int32_t* cold,
+                                int32_t* ebase, int32_t* cursor, int32_t* dchunk, int32_t* ent,
+                                int* flags, LoopState* st, int num_cus, const int* gate);
 hipError_t launch_cost_sum(hipStream_t s, const double* termC, const double* termMu, int k,
                            LoopState* st, double* cost_hist, int mode, const int* gate);
 

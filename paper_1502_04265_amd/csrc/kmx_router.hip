@@ -470,6 +470,7 @@ static kmx_status lloyd_routed_impl(kmx_ctx* ctx, kmx_router* r, const float* X,
     KMX_TRY(grow(ctx, ctx->keys, (size_t)n * kRouterM * sizeof(uint32_t)));
     kpad_r = r->kpad;
   }
+  KMX_TRY(ensure_cf(ctx, X, n, d, ldx, w));
   KMX_TRY(write_state(ctx, max_iter, tol));
   int32_t* lab = label_out ? label_out : P<int32_t>(ctx->lab_a);
   int32_t* prev = P<int32_t>(ctx->lab_prev);
@@ -477,7 +478,7 @@ static kmx_status lloyd_routed_impl(kmx_ctx* ctx, kmx_router* r, const float* X,
   int64_t* fbh = P<int64_t>(ctx->fbh);
   int64_t* bkh = bounded ? P<int64_t>(ctx->bkh) : nullptr;
   LoopState* st = ST(ctx);
-  KMX_HIP(ctx, launch_fill_i32(ctx->stream, prev, n, -1));
+  KMX_TRY(begin_lloyd(ctx, prev, n));
   if (r) {
     // the proposals depend on the points only: one forward pass serves every iteration
     Timed tm(ctx, T_ROUTER);
@@ -541,7 +542,7 @@ static kmx_status lloyd_routed_impl(kmx_ctx* ctx, kmx_router* r, const float* X,
     }
   }
   KMX_TRY(assign_step(max_iter, nullptr));
-  KMX_TRY(run_update(ctx, X, n, d, ldx, w, lab, k, C_inout, nullptr, nullptr, 0, nullptr, hist, 1,
+  KMX_TRY(run_update(ctx, X, n, d, ldx, w, lab, k, C_inout, nullptr, nullptr, 0, prev, hist, 1,
                      nullptr));
   LoopState h;
   KMX_HIP(ctx, hipMemcpyAsync(&h, ctx->state.p, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));

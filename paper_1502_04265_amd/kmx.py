@@ -71,6 +71,7 @@ def lib():
         "kmx_timing": [_vp, ctypes.c_int, ctypes.c_int],
         "kmx_mfma_probe": [_vp, ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _vp, _i32],
         "kmx_assign_stats": [_vp, _vp, _vp, _vp],
+        "kmx_update_stats": [_vp, _vp, _vp],
         "kmx_seed_stats": [_vp, _vp],
         "kmx_timing_read": [_vp, ctypes.c_int, _vp, _vp],
         "kmx_lloyd_batched": [_vp, _vp, _i32, _i32, ctypes.c_int, _vp],
@@ -269,6 +270,13 @@ class Context:
         _check(lib().kmx_assign_stats(self._p, ctypes.byref(a), ctypes.byref(b),
                                       ctypes.byref(c)), self._p)
         return int(a.value), int(b.value), int(c.value)
+
+    def update_stats(self):
+        """(changed, delta) of the most recent update of a Lloyd run: the rows
+        whose label changed and whether the delta path formed the features."""
+        a, b = ctypes.c_int64(0), ctypes.c_int32(0)
+        _check(lib().kmx_update_stats(self._p, ctypes.byref(a), ctypes.byref(b)), self._p)
+        return int(a.value), bool(b.value)
 
     def mfma_probe(self, prec, A, B, scale_a=None, scale_b=None, C=None):
         """kmx_mfma_probe.  A, B: (count, 16, K) uint8 E4M3 bytes (fp8, K = 128),

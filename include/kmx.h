@@ -189,6 +189,16 @@ kmx_status kmx_lloyd_graph(kmx_ctx* ctx, const float* X, int64_t n, int32_t d, i
 kmx_status kmx_project(kmx_ctx* ctx, const float* X, int64_t rows, int32_t d_in, int64_t ldx,
                        const float* V, int32_t d_out, float* Y, int64_t ldy);
 
+/* The rows of A_m = A V V^T (Sec. 2.2, "Using SVD to project to the best fit
+ * subspace": a projected point keeps its d coordinates, its intrinsic
+ * dimension drops to m) from their coordinates Z = A V:
+ *     Y[r][c] = sum_j Z[r][j] V[c][j],  r < rows, c < d,
+ * FP32 FMAs in j order.  Z rows x m (leading dimension ldz >= m), V d x m
+ * row-major (the basis kmx_project takes), Y rows x d (ldy >= d), all device;
+ * 1 <= m <= 128, rows <= 4,194,240 per call.  Stream-ordered. */
+kmx_status kmx_lift(kmx_ctx* ctx, const float* Z, int64_t rows, int32_t m, int64_t ldz,
+                    const float* V, int32_t d, float* Y, int64_t ldy);
+
 /* kmx_assign with KMX_FP32 that allocates nothing, for callers that cannot
  * allocate device memory (code under graph capture, tight serving loops,
  * harnesses that forbid hipMalloc).  Same labels, d1 and d2 bit for bit as
@@ -429,6 +439,56 @@ kmx_status kmx_lloyd_bounded(kmx_ctx* ctx, kmx_router* r, const float* X, int64_
                              int32_t max_iter, double tol, kmx_prec prec, int32_t* label_out,
                              double* cost_hist, int32_t* iters_done, int64_t* gemm_rows,
                              int64_t* kept_rows);
+
+/* ---- BICO summary (Sec. 2.1; weighted insertion Sec. 2.3.1) --------------
+ * A tree of clustering features (W, S, Q) -- weight, weighted sum of the
+ * points, weighted sum of their squared lengths -- kept on the host; the
+ * search for the closest reference point among the first-level features,
+ * which the paper names as dominating insertion time, runs on ctx's device in
+ * blocks of points (the assignment step's distance GEMM with fused argmin).
+ * Insertion: a point (w copies) goes down the tree to the closest reference
+ * among the children of the current node (ties: the oldest); it opens a
+ * feature (w, w x, w ||x||^2) when no reference lies within the level's
+ * radius R_i = sqrt(T / 2^(3 + i)) (level 1: children of the root); otherwise
+ * w' = min(w, floor((sT - sc) / (s D - T + c))) copies join that feature (all
+ * of them when s D - T + c <= 0; s = W, c = Q - ||S||^2 / W its cost,
+ * D = ||x - S / W||^2) and the rest descend.  More than m features: T doubles
+ * and every feature is re-inserted (breadth-first order of the old tree) into
+ * an empty tree, merging into the closest feature within the radius when the
+ * merged cost stays within T.  All decisions use FP64 sums in coordinate
+ * order.  The summary is the centroids S / W with weights W, breadth-first.
+ * A kmx_bico belongs to the ctx it was created with; not thread-safe. */
+typedef struct kmx_bico kmx_bico;
+
+/* Empty summary of at most m >= 1 features in R^d, starting threshold
+ * T0 > 0 (finite).  Host memory grows with the features: m x d doubles for the
+ * sums and m x d floats for the references. */
+kmx_status kmx_bico_create(kmx_ctx* ctx, int32_t d, int64_t m, double T0, kmx_bico** out);
+kmx_status kmx_bico_destroy(kmx_ctx* ctx, kmx_bico* b);
+
+/* Inserts rows 0 .. n-1 of X (device, n x d, leading dimension ldx >= d) in
+ * order, row i with weight w[i] (device, nullable: 1; entries must be finite
+ * and >= 0, a zero weight inserts nothing).  Copies blocks of rows to the host
+ * and synchronizes.  KMX_EINVAL on a bad weight (rows before it are in). */
+kmx_status kmx_bico_insert(kmx_ctx* ctx, kmx_bico* b, const float* X, int64_t n, int64_t ldx,
+                           const float* w);
+
+/* Host outputs, each nullable: number of features, current threshold, rebuilds
+ * so far, rows whose first-level search ran on the device, and rows whose two
+ * closest first-level references were too near for the device's FP32
+ * distances, so that the host compared them in FP64. */
+kmx_status kmx_bico_stats(kmx_ctx* ctx, const kmx_bico* b, int64_t* count, double* T,
+                          int64_t* rebuilds, int64_t* gpu_rows, int64_t* host_scans);
+
+/* The features in breadth-first order (count from kmx_bico_stats), host
+ * arrays, each nullable: W (count), S (count x d), Q (count), reference
+ * points (count x d), tree level (count; 1 = child of the root). */
+kmx_status kmx_bico_features(kmx_ctx* ctx, const kmx_bico* b, double* W, double* S, double* Q,
+                             float* ref, int32_t* level);
+
+/* The summary on the device: P_out (count x d, float32(S / W)) and w_out
+ * (count, float32(W)), breadth-first.  Synchronizes. */
+kmx_status kmx_bico_coreset(kmx_ctx* ctx, const kmx_bico* b, float* P_out, float* w_out);
 
 #ifdef __cplusplus
 }

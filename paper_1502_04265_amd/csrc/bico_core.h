@@ -1,0 +1,257 @@
+// Host logic of the BICO summary (Sec. 2.1: clustering features in a tree of
+// spheres; Sec. 2.3.1: weighted insertion), free of device calls so that it
+// also builds as plain C++.  The closest first-level reference of a point can
+// come from outside (the device search of kmx_bico.hip) as a hint over the
+// first u first-level features; everything else is decided here in FP64 with
+// sums in coordinate order and no fused multiply-adds.
+//
+// Tree.  A feature holds (W, S, Q) = (weight, weighted sum of its points,
+// weighted sum of their squared lengths), a reference point and its children.
+// Its cost against its centroid S / W is Q - ||S||^2 / W (Sec. 2.1).  A point
+// x with w copies walks down from the root: among the children of the current
+// node it takes the one whose reference is closest (ties: the oldest); if no
+// reference lies within the level's radius R_i = sqrt(T / 2^(3 + i)) it opens
+// a feature (w, w x, w ||x||^2) there; otherwise w' = min(w, floor((sT - sc) /
+// (s D - T + c))) copies join that feature (all w when s D - T + c <= 0; s = W,
+// c its cost, D = ||x - S / W||^2) and the rest descend to its children.  When
+// the tree holds more than m features, T doubles and every feature is
+// re-inserted, in breadth-first order of the old tree, into an empty tree:
+// it follows its reference point down, merges into the closest feature within
+// the radius whose merged cost stays within T, descends when it would not,
+// and otherwise keeps its (W, S, Q) as a new feature.  The summary is the
+// centroids S / W with weights W in breadth-first order.
+#pragma once
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+#pragma clang fp contract(off)
+
+namespace kmx {
+namespace bico {
+
+struct Feature {
+  int32_t level;
+  int32_t parent;               // -1: below the root
+  std::vector<int32_t> kids;    // creation order
+  double W, Q;
+};
+
+struct Core {
+  int d = 0;
+  int64_t m = 0;
+  double T = 0.0;
+  std::vector<Feature> f;       // creation order
+  std::vector<double> S;        // f.size() x d
+  std::vector<float> ref;       // f.size() x d
+  std::vector<int32_t> roots;   // first-level features, creation order
+  int64_t rebuilds = 0, host_scans = 0;
+};
+
+// A search hint for one point: the closest among roots[0, u) (lab) with the
+// device's two smallest distances d1 <= d2; valid = false: no hint.
+struct Hint {
+  bool valid = false;
+  int32_t lab = 0;
+  float d1 = 0.f, d2 = 0.f;
+  size_t u = 0;
+};
+
+inline double sq_dist(const float* a, const float* b, int d) {
+  double s = 0.0;
+  for (int j = 0; j < d; ++j) {
+    const double t = (double)a[j] - (double)b[j];
+    s += t * t;
+  }
+  return s;
+}
+
+inline double sq_norm(const double* v, int d) {
+  double s = 0.0;
+  for (int j = 0; j < d; ++j) s += v[j] * v[j];
+  return s;
+}
+
+inline double radius2(const Core& b, int level) { return b.T / std::ldexp(1.0, 3 + level); }
+
+// Appends a feature below `parent` (-1: the root) and returns its id.  The
+// parent's child list is looked up after the feature array has grown (which
+// moves the features and their child lists).
+inline int32_t open_feature(Core& b, const float* r, double W, const double* S, double Q,
+                            int level, int32_t parent) {
+  const int32_t id = (int32_t)b.f.size();
+  Feature nf;
+  nf.level = level;
+  nf.parent = parent;
+  nf.W = W;
+  nf.Q = Q;
+  b.f.push_back(std::move(nf));
+  b.S.insert(b.S.end(), S, S + b.d);
+  b.ref.insert(b.ref.end(), r, r + b.d);
+  if (parent < 0) b.roots.push_back(id);
+  else b.f[parent].kids.push_back(id);
+  return id;
+}
+
+inline const std::vector<int32_t>& kids_of(const Core& b, int32_t parent) {
+  return parent < 0 ? b.roots : b.f[parent].kids;
+}
+
+// Closest reference among ids[from, to) (strictly closer replaces: the oldest
+// wins ties).
+inline void scan(const Core& b, const std::vector<int32_t>& ids, size_t from, size_t to,
+                 const float* x, int32_t& best, double& bd) {
+  for (size_t q = from; q < to; ++q) {
+    const int32_t id = ids[q];
+    const double dd = sq_dist(x, &b.ref[(size_t)id * b.d], b.d);
+    if (best < 0 || dd < bd) {
+      best = id;
+      bd = dd;
+    }
+  }
+}
+
+inline std::vector<int32_t> bfs(const Core& b) {
+  std::vector<int32_t> out(b.roots.begin(), b.roots.end());
+  for (size_t q = 0; q < out.size(); ++q)
+    for (int32_t c : b.f[out[q]].kids) out.push_back(c);
+  return out;
+}
+
+// First-level closest reference for x.  With a hint, the device's choice is
+// re-measured in FP64, the first-level features opened after the hint are
+// scanned, and all of them are scanned when the device's two distances lie
+// within 1e-6 of each other (too near for FP32 to order them).
+inline void first_level(Core& b, const float* x, const Hint& h, int32_t& best, double& bd) {
+  best = -1;
+  bd = 0.0;
+  if (h.valid && h.u > 0 && h.u <= b.roots.size() && h.lab >= 0 && (size_t)h.lab < h.u) {
+    if (!(h.d2 - h.d1 > 1e-6f * h.d2)) {
+      scan(b, b.roots, 0, h.u, x, best, bd);
+      b.host_scans++;
+    } else {
+      best = b.roots[h.lab];
+      bd = sq_dist(x, &b.ref[(size_t)best * b.d], b.d);
+    }
+    scan(b, b.roots, h.u, b.roots.size(), x, best, bd);
+  } else {
+    scan(b, b.roots, 0, b.roots.size(), x, best, bd);
+  }
+}
+
+// w copies of x, given its first-level closest reference (best < 0: none).
+inline void insert_point(Core& b, const float* x, double w, int32_t best, double bd) {
+  const int d = b.d;
+  std::vector<double> xd(d), tmp(d);
+  for (int j = 0; j < d; ++j) xd[j] = (double)x[j];
+  const double q = sq_norm(xd.data(), d);
+  int32_t parent = -1;
+  int level = 1;
+  while (w > 0) {
+    if (level > 1) {
+      best = -1;
+      bd = 0.0;
+      const std::vector<int32_t>& sib = kids_of(b, parent);
+      scan(b, sib, 0, sib.size(), x, best, bd);
+    }
+    if (best < 0 || bd > radius2(b, level)) {
+      for (int j = 0; j < d; ++j) tmp[j] = w * xd[j];
+      open_feature(b, x, w, tmp.data(), w * q, level, parent);
+      break;
+    }
+    Feature& F = b.f[best];
+    double* S = &b.S[(size_t)best * d];
+    const double s = F.W;
+    const double c = F.Q - sq_norm(S, d) / s;
+    double D = 0.0;
+    for (int j = 0; j < d; ++j) {
+      const double t = xd[j] - S[j] / s;
+      D += t * t;
+    }
+    const double den = s * D - b.T + c;
+    double wp = w;
+    if (den > 0) wp = std::min(w, std::floor((s * b.T - s * c) / den));
+    if (wp > 0) {
+      F.W += wp;
+      for (int j = 0; j < d; ++j) S[j] += wp * xd[j];
+      F.Q += wp * q;
+      w -= wp;
+    }
+    parent = best;
+    ++level;
+  }
+}
+
+// Rebuild: T doubles and every feature is re-inserted into an empty tree.
+// query(refs, nq, u, hints) may fill hints for the nq references of a block
+// against roots[0, u) of the new tree (return false for an error; leaving the
+// hints invalid is always correct).
+template <class Query>
+bool rebuild(Core& b, int64_t block, Query&& query) {
+  const int d = b.d;
+  const std::vector<int32_t> order = bfs(b);
+  std::vector<Feature> of;
+  of.swap(b.f);
+  std::vector<double> oS;
+  oS.swap(b.S);
+  std::vector<float> oref;
+  oref.swap(b.ref);
+  b.roots.clear();
+  b.T *= 2.0;
+  b.rebuilds++;
+  const int64_t nold = (int64_t)order.size();
+  std::vector<float> stage((size_t)block * d);
+  std::vector<Hint> hints(block);
+  std::vector<double> mS(d);
+  for (int64_t q0 = 0; q0 < nold; q0 += block) {
+    const int64_t nq = std::min(block, nold - q0);
+    for (int64_t q = 0; q < nq; ++q) {
+      std::memcpy(&stage[(size_t)q * d], &oref[(size_t)order[q0 + q] * d],
+                  (size_t)d * sizeof(float));
+      hints[q] = Hint();
+    }
+    if (!b.roots.empty() && !query(stage.data(), nq, b.roots.size(), hints.data())) return false;
+    for (int64_t q = 0; q < nq; ++q) {
+      const int32_t o = order[q0 + q];
+      const float* r = &oref[(size_t)o * d];
+      const double* Sf = &oS[(size_t)o * d];
+      int32_t best;
+      double bd;
+      first_level(b, r, hints[q], best, bd);
+      int32_t parent = -1;
+      int level = 1;
+      while (true) {
+        if (level > 1) {
+          best = -1;
+          bd = 0.0;
+          const std::vector<int32_t>& sib = kids_of(b, parent);
+          scan(b, sib, 0, sib.size(), r, best, bd);
+        }
+        if (best < 0 || bd > radius2(b, level)) {
+          open_feature(b, r, of[o].W, Sf, of[o].Q, level, parent);
+          break;
+        }
+        Feature& G = b.f[best];
+        double* Sg = &b.S[(size_t)best * d];
+        const double W = G.W + of[o].W;
+        const double Q = G.Q + of[o].Q;
+        for (int j = 0; j < d; ++j) mS[j] = Sg[j] + Sf[j];
+        if (Q - sq_norm(mS.data(), d) / W <= b.T) {
+          G.W = W;
+          G.Q = Q;
+          std::memcpy(Sg, mS.data(), (size_t)d * sizeof(double));
+          break;
+        }
+        parent = best;
+        ++level;
+      }
+    }
+  }
+  return true;
+}
+
+}  // namespace bico
+}  // namespace kmx

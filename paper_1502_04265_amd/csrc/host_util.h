@@ -133,6 +133,7 @@ kmx_status check_prec(kmx_ctx* ctx, int prec, int d, bool allow_wide = false);
 kmx_status check_data(kmx_ctx* ctx, const float* X, int64_t n, int d, int64_t ldx, const float* w,
                       int64_t min_pos, const float* C, int k);
 kmx_status ensure_prep(kmx_ctx* ctx, const float* X, int64_t n, int d, int64_t ldx, int prec);
+kmx_status ensure_assign(kmx_ctx* ctx, int64_t n, int k);
 kmx_status ensure_common(kmx_ctx* ctx, int64_t n, int d, int k);
 kmx_status write_state(kmx_ctx* ctx, int max_iter, double tol);
 // Grids of the exactly summed clustering features for X and w (the dataset

@@ -201,4 +201,72 @@ hipError_t launch_project(hipStream_t s, const float* X, int64_t rows, int d_in,
 
 int project_dpad(int d_in) { return (d_in + 63) / 64 * 64; }
 
+// Lift of coordinates back to R^d (the rows of A_m = A V V^T in Sec. 2.2
+// "Using SVD to project to the best fit subspace": a point keeps d
+// coordinates, its intrinsic dimension is m):
+//     Y[i][c] = sum_j Z[i][j] V[c][j],   Z: rows x m, V: d x m (FP32),
+// FP32 FMAs in j order.  A workgroup stages 64 rows of Z and 64 rows of V
+// (m <= 128 values each, padded against bank conflicts) in LDS; thread
+// (ty, tx) accumulates rows 4 ty .. 4 ty + 3 and columns 4 tx .. 4 tx + 3 and
+// writes them as 16-byte stores when the row allows.
+constexpr int kLiftMaxM = 128;
+constexpr int kLiftPitch = kLiftMaxM + 1;
+
+__global__ __launch_bounds__(256) void lift_kernel(const float* __restrict__ Z, int64_t rows, int m,
+                                                   int64_t ldz, const float* __restrict__ V, int d,
+                                                   float* __restrict__ Y, int64_t ldy) {
+  __shared__ float zs[64 * kLiftPitch];
+  __shared__ float vs[64 * kLiftPitch];
+  const int tid = threadIdx.x;
+  const int ty = tid >> 4, tx = tid & 15;
+  const int64_t r0 = (int64_t)blockIdx.y * 64;
+  const int c0 = blockIdx.x * 64;
+  for (int e = tid; e < 64 * m; e += 256) {
+    const int r = e / m, j = e - r * m;
+    zs[r * kLiftPitch + j] = (r0 + r < rows) ? Z[(r0 + r) * ldz + j] : 0.0f;
+    vs[r * kLiftPitch + j] = (c0 + r < d) ? V[(int64_t)(c0 + r) * m + j] : 0.0f;
+  }
+  __syncthreads();
+  float acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0f;
+  for (int j = 0; j < m; ++j) {
+    float zv[4], vv[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) zv[a] = zs[(4 * ty + a) * kLiftPitch + j];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) vv[b] = vs[(4 * tx + b) * kLiftPitch + j];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] = fmaf(zv[a], vv[b], acc[a][b]);
+  }
+  const int c = c0 + 4 * tx;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int64_t r = r0 + 4 * ty + a;
+    if (r >= rows) continue;
+    float* yr = Y + r * ldy + c;
+    if (c + 4 <= d && ((((uintptr_t)yr) & 15) == 0)) {
+      *(pf32x4_t*)yr = (pf32x4_t){acc[a][0], acc[a][1], acc[a][2], acc[a][3]};
+    } else {
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        if (c + b < d) yr[b] = acc[a][b];
+    }
+  }
+}
+
+hipError_t launch_lift(hipStream_t s, const float* Z, int64_t rows, int m, int64_t ldz,
+                       const float* V, int d, float* Y, int64_t ldy) {
+  if (m < 1 || m > kLiftMaxM) return hipErrorInvalidValue;
+  const int64_t rb = (rows + 63) / 64;
+  if (rb > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(lift_kernel, dim3((unsigned)((d + 63) / 64), (unsigned)rb), dim3(256), 0, s,
+                     Z, rows, m, ldz, V, d, Y, ldy);
+  return hipGetLastError();
+}
+
 }  // namespace kmx

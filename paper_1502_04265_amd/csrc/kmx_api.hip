@@ -133,9 +133,9 @@ kmx_status ensure_prep(kmx_ctx* ctx, const float* X, int64_t n, int d, int64_t l
   return KMX_OK;
 }
 
-kmx_status ensure_common(kmx_ctx* ctx, int64_t n, int d, int k) {
-  const int64_t nb = (n + kSortRows - 1) / kSortRows;
-  const int64_t maxchunks = (n + kReduceRows - 1) / kReduceRows + k;
+// Buffers of the assignment step alone (n rows, k centers).
+kmx_status ensure_assign(kmx_ctx* ctx, int64_t n, int k) {
+  (void)k;
   KMX_TRY(grow(ctx, ctx->state, sizeof(LoopState)));
   KMX_TRY(grow(ctx, ctx->lab_a, (size_t)n * sizeof(int32_t)));
   KMX_TRY(grow(ctx, ctx->flags, (size_t)n * sizeof(FlagEntry)));
@@ -145,6 +145,14 @@ kmx_status ensure_common(kmx_ctx* ctx, int64_t n, int d, int k) {
   KMX_TRY(grow(ctx, ctx->full_rows2, (size_t)n * sizeof(int)));
   KMX_TRY(grow(ctx, ctx->cstats8, sizeof(CenterStats)));
   KMX_TRY(grow(ctx, ctx->brute, (size_t)n * sizeof(int)));
+  return KMX_OK;
+}
+
+// Assignment plus update buffers.
+kmx_status ensure_common(kmx_ctx* ctx, int64_t n, int d, int k) {
+  const int64_t nb = (n + kSortRows - 1) / kSortRows;
+  const int64_t maxchunks = (n + kReduceRows - 1) / kReduceRows + k;
+  KMX_TRY(ensure_assign(ctx, n, k));
   // nb x k block counts, then the changed labels of each of the 4 nb hist waves
   KMX_TRY(grow(ctx, ctx->counts, ((size_t)nb * k + 4 * nb) * sizeof(int32_t)));
   KMX_TRY(grow(ctx, ctx->segsum, (size_t)kScanSegs * k * sizeof(int32_t)));
@@ -570,7 +578,7 @@ kmx_status kmx_assign(kmx_ctx* ctx, const float* X, int64_t n, int32_t d, int64_
   if (!label_out) return fail(ctx, KMX_EINVAL, "label_out is NULL");
   KMX_TRY(set_device(ctx));
   KMX_TRY(check_data(ctx, X, n, d, ldx, nullptr, 0, C, k));
-  KMX_TRY(ensure_common(ctx, n, d, k));
+  KMX_TRY(ensure_assign(ctx, n, k));
   KMX_TRY(ensure_prep(ctx, X, n, d, ldx, prec));
   KMX_TRY(run_assign(ctx, X, n, d, ldx, C, k, prec, label_out, d1_out, d2_out, nullptr));
   if (n_flagged) {
@@ -768,6 +776,21 @@ kmx_status kmx_project(kmx_ctx* ctx, const float* X, int64_t rows, int32_t d_in,
   Timed tm(ctx, T_PROJECT);
   KMX_HIP(ctx, launch_project(ctx->stream, X, rows, d_in, ldx, V, d_out, Y, ldy, P<float>(ctx->vt),
                               ctx->num_cus));
+  return KMX_OK;
+}
+
+kmx_status kmx_lift(kmx_ctx* ctx, const float* Z, int64_t rows, int32_t m, int64_t ldz,
+                    const float* V, int32_t d, float* Y, int64_t ldy) {
+  if (!ctx) return KMX_EINVAL;
+  ctx->err.clear();
+  if (!Z || !V || !Y) return fail(ctx, KMX_EINVAL, "NULL Z, V or Y");
+  if (rows < 1 || d < 1 || ldy < d) return fail(ctx, KMX_EINVAL, "bad rows, d or ldy");
+  if (m < 1 || m > 128 || ldz < m)
+    return fail(ctx, KMX_EUNSUPPORTED, "m must lie in [1, 128] with ldz >= m");
+  if (rows > (int64_t)65535 * 64) return fail(ctx, KMX_EUNSUPPORTED, "rows above 4,194,240");
+  KMX_TRY(set_device(ctx));
+  Timed tm(ctx, T_PROJECT);
+  KMX_HIP(ctx, launch_lift(ctx->stream, Z, rows, m, ldz, V, d, Y, ldy));
   return KMX_OK;
 }
 

@@ -393,7 +393,10 @@ hipError_t launch_record_kept(hipStream_t s, const LoopState* st, int64_t* kept,
 hipError_t launch_project(hipStream_t s, const float* X, int64_t rows, int d_in, int64_t ldx,
                           const float* V, int d_out, float* Y, int64_t ldy, float* Vt,
                           int num_cus);
-int project_dpad(int d_in);            // row length of the transposed basis workspace
+int project_dpad(int d_in);
+// Y = Z V^T (Z rows x m, V d x m row-major, m <= 128, rows < 65535 * 64).
+hipError_t launch_lift(hipStream_t s, const float* Z, int64_t rows, int m, int64_t ldz,
+                       const float* V, int d, float* Y, int64_t ldy);            // row length of the transposed basis workspace
 
 // range finder (k_svd.hip)
 hipError_t launch_gauss_fill(hipStream_t s, float* out, int64_t count, uint64_t seed);

@@ -78,6 +78,7 @@ def lib():
         "kmx_batched_autotune": [_vp, _vp, _i32, ctypes.c_int, ctypes.c_char_p, _vp],
         "kmx_batched_tiles": [_vp, _i32, _i32, _vp, _vp],
         "kmx_project": [_vp, _vp, _i64, _i32, _i64, _vp, _i32, _vp, _i64],
+        "kmx_lift": [_vp, _vp, _i64, _i32, _i64, _vp, _i32, _vp, _i64],
         "kmx_range_basis": [_vp, _vp, _i64, _i32, _i64, _vp, _i32, _i32, _i32, ctypes.c_uint64,
                             _vp, _vp],
         "kmx_router_create": [_vp, _i32, _i32, ctypes.c_uint64, ctypes.POINTER(_vp)],
@@ -92,6 +93,12 @@ def lib():
                              ctypes.c_double, ctypes.c_int, _vp, _vp, _vp, _vp],
         "kmx_lloyd_bounded": [_vp, _vp, _vp, _i64, _i32, _i64, _vp, _vp, _i32, _i32,
                               ctypes.c_double, ctypes.c_int, _vp, _vp, _vp, _vp, _vp],
+        "kmx_bico_create": [_vp, _i32, _i64, ctypes.c_double, ctypes.POINTER(_vp)],
+        "kmx_bico_destroy": [_vp, _vp],
+        "kmx_bico_insert": [_vp, _vp, _vp, _i64, _i64, _vp],
+        "kmx_bico_stats": [_vp, _vp, _vp, _vp, _vp, _vp, _vp],
+        "kmx_bico_features": [_vp, _vp, _vp, _vp, _vp, _vp, _vp],
+        "kmx_bico_coreset": [_vp, _vp, _vp, _vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -371,6 +378,20 @@ class Context:
                                  Y.stride(0)), self._p)
         return Y
 
+    def lift(self, Z, V, out=None):
+        """Y = Z V^T (kmx_lift): coordinates Z (rows x m) in the basis V (d x m)
+        back to R^d."""
+        rows, m, ldz = _rows(Z)
+        if not V.is_cuda or V.dtype != torch.float32 or V.dim() != 2 or V.shape[1] != m \
+                or not V.is_contiguous():
+            raise ValueError("V must be a contiguous d x m float32 CUDA tensor")
+        d = V.shape[0]
+        Y = torch.empty((rows, d), dtype=torch.float32, device=Z.device) if out is None else out
+        self._sync_stream()
+        _check(lib().kmx_lift(self._p, _ptr(Z), rows, m, ldz, _ptr(V), d, _ptr(Y), Y.stride(0)),
+               self._p)
+        return Y
+
     def range_basis(self, A, r: int, w=None, oversample: int = 16, power_iters: int = 2,
                     seed: int = 0):
         """kmx_range_basis: the top-r right singular vectors of diag(sqrt w) A
@@ -558,3 +579,69 @@ def cost(X, C, w=None, prec="fp32"):
 
 def lloyd(X, C0, max_iter, w=None, tol=-1.0, prec="bf16", labels=True, inplace=False):
     return context(X.device.index or 0).lloyd(X, C0, max_iter, w, tol, prec, labels, inplace)
+
+
+class Bico:
+    """kmx_bico: the BICO summary (Sec. 2.1, weighted insertion Sec. 2.3.1) of
+    at most m features in R^d, kept on the host; the first-level closest
+    reference search runs on the context's device."""
+
+    def __init__(self, ctx: Context, d: int, m: int, T0: float):
+        self.ctx = ctx
+        self.d, self.m = int(d), int(m)
+        b = _vp()
+        _check(lib().kmx_bico_create(ctx._p, self.d, self.m, float(T0), ctypes.byref(b)), ctx._p)
+        self._b = b
+
+    def close(self):
+        if getattr(self, "_b", None) is not None and self._b.value:
+            lib().kmx_bico_destroy(self.ctx._p, self._b)
+            self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def insert(self, X, w=None):
+        """Insert the rows of X (device, float32) in order, with weights w."""
+        n, d, ldx = _rows(X)
+        if d != self.d:
+            raise ValueError(f"rows of width {d}, summary of width {self.d}")
+        _vec(w, n)
+        self.ctx._sync_stream()
+        _check(lib().kmx_bico_insert(self.ctx._p, self._b, _ptr(X), n, ldx, _ptr(w)), self.ctx._p)
+
+    def stats(self):
+        """dict: count, T, rebuilds, gpu_rows, host_scans."""
+        c, r, g, h = (ctypes.c_int64(0) for _ in range(4))
+        T = ctypes.c_double(0.0)
+        _check(lib().kmx_bico_stats(self.ctx._p, self._b, ctypes.byref(c), ctypes.byref(T),
+                                    ctypes.byref(r), ctypes.byref(g), ctypes.byref(h)),
+               self.ctx._p)
+        return {"count": int(c.value), "T": float(T.value), "rebuilds": int(r.value),
+                "gpu_rows": int(g.value), "host_scans": int(h.value)}
+
+    def features(self):
+        """(W, S, Q, ref, level) as numpy arrays, breadth-first order."""
+        import numpy as np
+        cnt = self.stats()["count"]
+        W = np.zeros(cnt, np.float64)
+        S = np.zeros((cnt, self.d), np.float64)
+        Q = np.zeros(cnt, np.float64)
+        R = np.zeros((cnt, self.d), np.float32)
+        L = np.zeros(cnt, np.int32)
+        _check(lib().kmx_bico_features(self.ctx._p, self._b, W.ctypes.data, S.ctypes.data,
+                                       Q.ctypes.data, R.ctypes.data, L.ctypes.data), self.ctx._p)
+        return W, S, Q, R, L
+
+    def coreset(self):
+        """(P, w) on the device: centroids S / W and weights W."""
+        cnt = self.stats()["count"]
+        dev = torch.device("cuda", self.ctx.device)
+        P = torch.empty((max(cnt, 1), self.d), dtype=torch.float32, device=dev)
+        w = torch.empty(max(cnt, 1), dtype=torch.float32, device=dev)
+        self.ctx._sync_stream()
+        _check(lib().kmx_bico_coreset(self.ctx._p, self._b, _ptr(P), _ptr(w)), self.ctx._p)
+        return P[:cnt], w[:cnt]

@@ -1,0 +1,102 @@
+"""The library's BICO host logic (paper_1502_04265_amd/csrc/bico_core.h),
+built as plain C++ with address and undefined-behaviour checks, against the
+FP64 oracle (oracle/bico.py): identical features in the same order.  The
+harness (tests/bico_host_main.cpp) feeds first-level hints from a host
+stand-in for the device search, so the hint path, the scans of features
+opened after a hint and the rebuild's blocked searches all run.  CPU only."""
+import os
+import shutil
+import struct
+import subprocess
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import bico as ob
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+
+
+@pytest.fixture(scope="module")
+def harness(tmp_path_factory):
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("no g++")
+    exe = str(tmp_path_factory.mktemp("bico") / "bico_host")
+    cmd = [gxx, "-std=c++17", "-O1", "-g", "-ffp-contract=off", "-Wno-unknown-pragmas",
+           "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+           "-I", os.path.join(ROOT, "paper_1502_04265_amd", "csrc"),
+           os.path.join(HERE, "bico_host_main.cpp"), "-o", exe]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        pytest.fail("g++ failed:\n" + r.stderr)
+    return exe
+
+
+def _run(exe, tmp, X, m, T0, block, w=None):
+    n, d = X.shape
+    src, dst = str(tmp / "in.bin"), str(tmp / "out.bin")
+    with open(src, "wb") as f:
+        f.write(struct.pack("<qiqdii", n, d, m, T0, block, 0 if w is None else 1))
+        f.write(np.ascontiguousarray(X, np.float32).tobytes())
+        if w is not None:
+            f.write(np.ascontiguousarray(w, np.float64).tobytes())
+    r = subprocess.run([exe, src, dst], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    with open(dst, "rb") as f:
+        cnt, T, reb, scans = struct.unpack("<qdqq", f.read(32))
+        L, W, Q, R, S = [], [], [], [], []
+        for _ in range(cnt):
+            lv, Wi, Qi = struct.unpack("<idd", f.read(20))
+            L.append(lv)
+            W.append(Wi)
+            Q.append(Qi)
+            R.append(np.frombuffer(f.read(4 * d), np.float32))
+            S.append(np.frombuffer(f.read(8 * d), np.float64))
+    return (np.array(W), np.array(S).reshape(cnt, d), np.array(Q), np.array(R).reshape(cnt, d),
+            np.array(L, np.int32), T, reb, scans)
+
+
+def _mixture(n, d, seed, sigma):
+    rng = np.random.default_rng(seed)
+    means = rng.uniform(-5, 5, size=(8, d))
+    return (means[rng.integers(0, 8, n)] + sigma * rng.normal(size=(n, d))).astype(np.float32)
+
+
+@pytest.mark.parametrize("n,d,m,T0,block,wkind,sigma", [
+    (2000, 6, 50, 1e-3, 64, None, 1.0), (1500, 4, 30, 0.5, 33, "int", 0.05),
+    (1200, 17, 80, 1e-2, 128, "lognormal", 0.5), (900, 3, 120, 1e-2, 5, "zeros", 0.3)])
+def test_host_bico_matches_oracle(harness, tmp_path, n, d, m, T0, block, wkind, sigma):
+    X = _mixture(n, d, n + d, sigma)
+    rng = np.random.default_rng(d)
+    w = None
+    if wkind == "int":
+        w = rng.integers(1, 6, n).astype(np.float64)
+    elif wkind == "lognormal":
+        w = synth.lognormal_weights(n, seed=d).astype(np.float64)
+    elif wkind == "zeros":
+        w = rng.integers(0, 3, n).astype(np.float64)
+    ref = ob.summarize(X, m, T0, w)
+    W, S, Q, R, L, T, reb, scans = _run(harness, tmp_path, X, m, T0, block, w)
+    Wo, So, Qo, Ro, Lo = ref.features()
+    assert (T, reb) == (ref.T, ref.rebuilds)
+    assert np.array_equal(L, Lo) and np.array_equal(R, Ro)
+    assert np.array_equal(W, Wo) and np.array_equal(S, So) and np.array_equal(Q, Qo)
+
+
+def test_host_bico_ties(harness, tmp_path):
+    # duplicated rows and rows equidistant from two references: exact ties go
+    # to the oldest feature, and the host scans when the hint's two distances
+    # coincide
+    # (T = 32: radius^2 2 at the first level, so (0,0) and (2,0) are separate
+    # references and (1,0) lies within reach of both, at distance 1 from each)
+    base = np.array([[0, 0], [2, 0], [1, 0], [1, 0], [0, 0], [2, 0], [1, 0.5], [1, -0.5]],
+                    np.float32)
+    X = np.tile(base, (40, 1))
+    ref = ob.summarize(X, 6, 32.0)
+    W, S, Q, R, L, T, reb, scans = _run(harness, tmp_path, X, 6, 32.0, 8)
+    Wo, So, Qo, Ro, Lo = ref.features()
+    assert np.array_equal(W, Wo) and np.array_equal(S, So) and np.array_equal(R, Ro)
+    assert scans > 0

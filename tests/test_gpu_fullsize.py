@@ -100,6 +100,7 @@ def test_streamed_full_size(ctx):
     sample = torch.cat([synth.lowrank_chunk_device(rows, F, seed=0, chunk=1_000_000 + c,
                                                    device=dev) for c in range(2)])[:100_000]
     Vd, _ = ctx.range_basis(sample.contiguous(), r, oversample=16, power_iters=1, seed=0)
+    V = Vd.cpu().numpy()
     del sample
     Y = torch.empty((nchunks * rows, r), dtype=torch.float32, device=dev)
     rng = np.random.default_rng(3)

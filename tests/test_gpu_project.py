@@ -66,12 +66,12 @@ def test_project_strided_rows(ctx):
 
 def test_streamed_pipeline_fp8_kmeans(ctx):
     """rank-64 signal in d=1024 plus N(0, 0.05^2) noise, 4 chunks of 16,384
-    rows, basis from a randomized SVD of an 8,192-row sample, k = 100."""
-    from paper_1502_04265_amd import subspace
+    rows, basis from the device's randomized range finder on an 8,192-row
+    sample, k = 100."""
     d_in, r, chunks, rows, k, iters = 1024, 64, 4, 16384, 100, 8
     F = synth.lowrank_factors(d_in, r, seed=3)
     sample = synth.lowrank_chunk(8192, F, seed=3, chunk=999)
-    V = subspace.top_right_singular_vectors(sample, r, seed=1)
+    V = ctx.range_basis(_dev(sample), r, oversample=16, power_iters=2, seed=1)[0].cpu().numpy()
     cosines = np.linalg.svd(op.best_fit_basis(sample, r).T @ V.astype(np.float64),
                             compute_uv=False)
     assert cosines.min() > 0.9999

@@ -19,7 +19,8 @@ path's within 1e-6 relative; the fastest path overall is reported beside it.
 Prints ONE JSON line.  Data is synthetic and generated on the device before
 the timed region; seeding, the plain iterations, training and the oracle
 (FP64 CPU timing and the FP64 errors of the reported results) are outside it.
---workload rotated|streamed|batched|small prints the other workloads' lines;
+--workload rotated|streamed|batched|piecy|small prints the other workloads'
+lines;
 --only assign and --traffic are the counter-collection modes.
 """
 from __future__ import annotations
@@ -47,6 +48,10 @@ HBM_PEAK_GBS = 8000.0
 STREAMED = dict(n=10_000_000, d_in=4096, r=64, k=100, chunk=65536, sample=100_000,
                 name="rank-64 signal in d=4096 + N(0,0.05^2) noise, n=1e7 in chunks of 65536, "
                      "projected to 64 dims, k=100")
+
+PIECY = dict(ell=50, y=4000, d=1000, x=50, k=50, svd=64, piece=20000, np_=4,
+             name="StructuredWithNoise l=50 y=4000 (n=2e5) d=1000 x=50 (Delta=10, delta=0.5), "
+                  "k=50, projected to 64 dims")
 
 WORKLOADS = {
     "router": dict(n=4_000_000, d=512, k=1000, name="gaussian mixture n=4e6 d=512 k=1000 "
@@ -590,6 +595,98 @@ def streamed_main(args):
     print(json.dumps(out), flush=True)
 
 
+def piecy_main(args):
+    """piecy and piecy-mr (Sec. 2.2, 2.3) end to end on a StructuredWithNoise
+    instance (Sec. 3), rows in a random order, resident on the device: per
+    piece the range finder, the projection and the lift on the device, BICO
+    insertion on the host with its first-level search on the device, then
+    k-means++ and 20 Lloyd iterations on the summary.  value = input points per
+    second of the whole pipeline (piecy); the summary's centers are scored on
+    the full data against k-means++ + 20 Lloyd iterations run on the full data.
+    cpu_baseline: the same pipeline in the FP64 oracle (exact SVD, oracle/bico,
+    oracle k-means) on a bounded sample of the rows."""
+    import numpy as np
+    import torch
+
+    import synth
+    from oracle import bico as ob
+    from oracle import kmeans as ok
+    from oracle import project as op
+    from paper_1502_04265_amd import kmx, piecy
+
+    W = PIECY
+    k, svd = W["k"], W["svd"]
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    log("[bench] generating StructuredWithNoise")
+    X = synth.structured_with_noise(W["ell"], W["y"], W["d"], W["x"], seed=0)
+    X = X[np.random.default_rng(0).permutation(X.shape[0])]
+    n = X.shape[0]
+    Xd = torch.from_numpy(X).to(dev)
+    ctx = kmx.Context(0)
+    piecy.piecy(ctx, [Xd[:W["piece"]]], k, svd, lloyd_iters=2)        # buffers
+    torch.cuda.synchronize()
+    res = {}
+    for name in ("piecy", "piecy_mr"):
+        ps = W["piece"] if name == "piecy" else 200 * k
+        pieces = [Xd[a:a + ps] for a in range(0, n, ps)]
+        ctx.timing(True, True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if name == "piecy":
+            r = piecy.piecy(ctx, iter(pieces), k, svd, lloyd_iters=20, seed=1)
+        else:
+            r = piecy.piecy_mr(ctx, iter(pieces), k, svd, np_=W["np_"], lloyd_iters=20, seed=1)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        kt = ctx.timing_read()
+        ctx.timing(False, True)
+        cost = ctx.cost(Xd, r["C"])
+        dev_query_ms = kt["assign"][0] + kt["recheck"][0] + kt["prep"][0]
+        res[name] = {"points_per_s": n / wall, "wall_s": wall, "piece_rows": ps,
+                     "reduce_s": r["reduce_s"], "bico_s": r["bico_s"], "kmeans_s": r["kmeans_s"],
+                     "bico_device_search_ms": dev_query_ms,
+                     "project_lift_range_ms": kt["project"][0],
+                     "summary_points": int(r["P"].shape[0]), "cost": cost, "bico": r["bico"]}
+        log(f"[bench] {name}: {n / wall:.0f} points/s ({wall:.2f} s: reduce {r['reduce_s']:.2f}, "
+            f"bico {r['bico_s']:.2f}, k-means {r['kmeans_s']:.2f}), summary {r['P'].shape[0]}, "
+            f"cost {cost:.6e}")
+    C0, _ = ctx.seed(Xd, k, rng_seed=1)
+    Cf, _, _, _ = ctx.lloyd(Xd, C0, 20, prec="fp32")
+    full_cost = ctx.cost(Xd, Cf)
+    for r in res.values():
+        r["cost_vs_full_data_lloyd"] = r["cost"] / full_cost
+    cpu = None
+    if not args.no_cpu_baseline:
+        m_s = 2000
+        t0 = time.perf_counter()
+        A = X[:m_s].astype(np.float64)
+        Y = op.rank_m_rows(A, svd)
+        b = ob.summarize(Y.astype(np.float32), 200 * k, piecy.initial_threshold(
+            ctx, torch.from_numpy(Y.astype(np.float32)).to(dev), 200 * k))
+        P, wP = b.coreset()
+        C0o, _, _ = ok.seed(P, wP, k, 1)
+        ok.lloyd(P, wP, C0o, 20)
+        t = time.perf_counter() - t0
+        cpu = {"value": m_s / t, "unit": "points/s", "cores": 1, "kind": "oracle",
+               "sample": f"piecy on the first {m_s} of {n} rows as one piece (exact SVD, "
+                         f"oracle BICO, oracle k-means++ + 20 Lloyd), {t:.1f} s on one core",
+               "host": host_cpu()}
+    best = res["piecy"]
+    out = {
+        "metric": "piecy points/s (StructuredWithNoise n=2e5 d=1000 k=50), summary cost vs "
+                  "full-data Lloyd",
+        "value": best["points_per_s"], "unit": "points/s", "n_gpus": 1, "steps": 1,
+        "warmup": 1, "ms_per_step": best["wall_s"] * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": W["name"], "n": n, "d": W["d"], "k": k, "svd": svd,
+                   "piece_rows": W["piece"], "summary_size": 200 * k, "np": W["np_"]},
+        "paths": res, "full_data_lloyd_cost": full_cost,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -600,7 +697,7 @@ def main():
     ap.add_argument("--batch", type=int, default=8192, help="router training batch")
     ap.add_argument("--lr", type=float, default=1e-3, help="router learning rate (Adam)")
     ap.add_argument("--workload", default="router",
-                    choices=sorted(WORKLOADS) + ["streamed", "batched", "rotated"])
+                    choices=sorted(WORKLOADS) + ["streamed", "batched", "rotated", "piecy"])
     ap.add_argument("--instances", type=int, default=256,
                     help="batched workload: number of instances")
     ap.add_argument("--chunks", type=int, default=None,
@@ -646,6 +743,8 @@ def main():
         return batched_main(args)
     if args.workload == "rotated":
         return rotated_main(args)
+    if args.workload == "piecy":
+        return piecy_main(args)
     wl = WORKLOADS[args.workload]
     n, d, k = wl["n"], wl["d"], wl["k"]
     dev = "cuda:0"

@@ -64,17 +64,28 @@ def initial_threshold(ctx: kmx.Context, Y: torch.Tensor, m: int) -> float:
     return float(v.min()) if v.size else 1.0
 
 
-class _Result(dict):
-    pass
+class _Clock:
+    """Wall seconds per stage (the device is synchronized at each stage end)."""
+
+    def __init__(self, dev):
+        self.dev = dev
+        self.s = {"reduce_s": 0.0, "bico_s": 0.0, "kmeans_s": 0.0}
+
+    def run(self, key, fn, *a, **kw):
+        t = time.perf_counter()
+        out = fn(*a, **kw)
+        torch.cuda.synchronize(self.dev)
+        self.s[key] += time.perf_counter() - t
+        return out
 
 
-def _finish(ctx, P, w, k, lloyd_iters, seed, prec, t0, stats):
-    t1 = time.perf_counter()
-    C0, _ = ctx.seed(P, k, w=w, rng_seed=seed)
-    C, lab, hist, it = ctx.lloyd(P, C0, lloyd_iters, w=w, prec=prec)
-    torch.cuda.synchronize(P.device)
-    t2 = time.perf_counter()
-    r = _Result(C=C, P=P, w=w, cost_hist=hist, iters=it, summary_s=t1 - t0, kmeans_s=t2 - t1)
+def _finish(ctx, clock, P, w, k, lloyd_iters, seed, prec, stats):
+    def km():
+        C0, _ = ctx.seed(P, k, w=w, rng_seed=seed)
+        return ctx.lloyd(P, C0, lloyd_iters, w=w, prec=prec)
+    C, lab, hist, it = clock.run("kmeans_s", km)
+    r = dict(C=C, P=P, w=w, cost_hist=hist, iters=it)
+    r.update(clock.s)
     r.update(stats)
     return r
 
@@ -84,21 +95,25 @@ def piecy(ctx: kmx.Context, pieces: Iterable[torch.Tensor], k: int, svd_dim: int
           seed: int = 0, prec: str = "fp32"):
     """Sec. 2.2: every projected piece enters one BICO instance.  Returns a
     dict with the centers C, the summary (P, w), the Lloyd cost history on the
-    summary and timings."""
+    summary, the BICO statistics and the wall seconds of the stages (reduce_s:
+    range finder + projection + lift, bico_s: insertion and summary, kmeans_s:
+    k-means++ and Lloyd on the summary)."""
     m = 200 * k if m is None else int(m)
     b = None
-    t0 = time.perf_counter()
+    clock = None
     rows = 0
     for q, A in enumerate(pieces):
-        Y = project_piece(ctx, A, svd_dim, seed=seed + q)
+        if clock is None:
+            clock = _Clock(A.device)
+        Y = clock.run("reduce_s", project_piece, ctx, A, svd_dim, seed=seed + q)
         if b is None:
             b = kmx.Bico(ctx, Y.shape[1], m, T0 if T0 is not None else initial_threshold(ctx, Y, m))
-        b.insert(Y)
+        clock.run("bico_s", b.insert, Y)
         rows += Y.shape[0]
-    P, w = b.coreset()
+    P, w = clock.run("bico_s", b.coreset)
     st = b.stats()
     st["rows"] = rows
-    return _finish(ctx, P, w, k, lloyd_iters, seed, prec, t0, {"bico": [st]})
+    return _finish(ctx, clock, P, w, k, lloyd_iters, seed, prec, {"bico": [st]})
 
 
 def piecy_mr(ctx: kmx.Context, pieces: Iterable[torch.Tensor], k: int, svd_dim: int,
@@ -109,7 +124,7 @@ def piecy_mr(ctx: kmx.Context, pieces: Iterable[torch.Tensor], k: int, svd_dim: 
     levels = []        # [Bico, inputs taken]
     T_start = [T0]
     done = []          # statistics of the instances that handed on their summary
-    t0 = time.perf_counter()
+    clock = [None]
 
     def new_bico(d, Y):
         if T_start[0] is None:
@@ -119,27 +134,30 @@ def piecy_mr(ctx: kmx.Context, pieces: Iterable[torch.Tensor], k: int, svd_dim: 
     def push(level, Y, w, tag):
         if len(levels) <= level:
             levels.append([new_bico(Y.shape[1], Y), 0])
-        levels[level][0].insert(Y, w)
+        clock[0].run("bico_s", levels[level][0].insert, Y, w)
         levels[level][1] += 1
         if levels[level][1] == np_:
             b = levels[level][0]
-            P, wP = b.coreset()
+            P, wP = clock[0].run("bico_s", b.coreset)
             st = b.stats()
             st["level"] = level
             done.append(st)
             levels[level] = [new_bico(Y.shape[1], Y), 0]
             # the summary's weighted best-fit subspace (Sec. 2.3.2)
-            Y2 = project_piece(ctx, P, svd_dim, w=wP, seed=seed + 7919 * (level + 1) + tag)
+            Y2 = clock[0].run("reduce_s", project_piece, ctx, P, svd_dim, w=wP,
+                              seed=seed + 7919 * (level + 1) + tag)
             push(level + 1, Y2.contiguous(), wP.contiguous(), tag)
 
     for q, A in enumerate(pieces):
-        Y = project_piece(ctx, A, svd_dim, seed=seed + q)
+        if clock[0] is None:
+            clock[0] = _Clock(A.device)
+        Y = clock[0].run("reduce_s", project_piece, ctx, A, svd_dim, seed=seed + q)
         push(0, Y, None, q)
     parts, wparts, live = [], [], []
     for lv, (b, cnt) in enumerate(levels):
         if cnt == 0:
             continue
-        P, wP = b.coreset()
+        P, wP = clock[0].run("bico_s", b.coreset)
         st = b.stats()
         st["level"] = lv
         live.append(st)
@@ -147,4 +165,5 @@ def piecy_mr(ctx: kmx.Context, pieces: Iterable[torch.Tensor], k: int, svd_dim: 
         wparts.append(wP)
     P = torch.cat(parts).contiguous()
     w = torch.cat(wparts).contiguous()
-    return _finish(ctx, P, w, k, lloyd_iters, seed, prec, t0, {"bico": live, "handed_on": done})
+    return _finish(ctx, clock[0], P, w, k, lloyd_iters, seed, prec,
+                   {"bico": live, "handed_on": done})

@@ -624,8 +624,14 @@ def piecy_main(args):
     n = X.shape[0]
     Xd = torch.from_numpy(X).to(dev)
     ctx = kmx.Context(0)
-    piecy.piecy(ctx, [Xd[:W["piece"]]], k, svd, lloyd_iters=2)        # buffers
+    log("[bench] warm-up: piecy on 4000 rows")
+    piecy.piecy(ctx, [Xd[:4000]], k, svd, lloyd_iters=2)        # buffers
     torch.cuda.synchronize()
+
+    def progress(q, rows, st):
+        log(f"[bench]   piece {q}: {st['count']} features, T {st['T']:.4g}, "
+            f"{st['rebuilds']} rebuilds, {st['gpu_rows']} rows searched on the device, "
+            f"{st['host_scans']} host scans")
     res = {}
     for name in ("piecy", "piecy_mr"):
         ps = W["piece"] if name == "piecy" else 200 * k
@@ -633,10 +639,12 @@ def piecy_main(args):
         ctx.timing(True, True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        log(f"[bench] {name}: {len(pieces)} pieces of {ps} rows")
         if name == "piecy":
-            r = piecy.piecy(ctx, iter(pieces), k, svd, lloyd_iters=20, seed=1)
+            r = piecy.piecy(ctx, iter(pieces), k, svd, lloyd_iters=20, seed=1, progress=progress)
         else:
-            r = piecy.piecy_mr(ctx, iter(pieces), k, svd, np_=W["np_"], lloyd_iters=20, seed=1)
+            r = piecy.piecy_mr(ctx, iter(pieces), k, svd, np_=W["np_"], lloyd_iters=20, seed=1,
+                               progress=progress)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         kt = ctx.timing_read()
@@ -659,6 +667,7 @@ def piecy_main(args):
     cpu = None
     if not args.no_cpu_baseline:
         m_s = 2000
+        log(f"[bench] oracle pipeline on {m_s} rows")
         t0 = time.perf_counter()
         A = X[:m_s].astype(np.float64)
         Y = op.rank_m_rows(A, svd)

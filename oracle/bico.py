@@ -89,12 +89,16 @@ class Bico:
 
     @staticmethod
     def _closest(cands, x):
-        best, bd = None, None
-        for f in cands:
-            dd = _sq(x, f.ref)
-            if bd is None or dd < bd:
-                best, bd = f, dd
-        return best, bd
+        """The candidate whose reference is closest to x (the first, i.e. the
+        oldest, among equal distances), with that squared distance; each
+        distance is a sum in coordinate order."""
+        if not cands:
+            return None, None
+        R = np.stack([f.ref for f in cands]).astype(np.float64)
+        t = np.asarray(x, np.float64)[None, :] - R
+        dd = np.cumsum(t * t, axis=1)[:, -1]
+        i = int(np.argmin(dd))
+        return cands[i], float(dd[i])
 
     def _open(self, siblings, ref, W, S, Q, level, parent):
         f = Feature(ref, W, S, Q, level, parent)

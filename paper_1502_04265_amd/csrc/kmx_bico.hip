@@ -48,7 +48,12 @@ kmx_status query(kmx_ctx* ctx, kmx_bico* b, const float* Q, int64_t nq, int64_t 
   const int d = c.d;
   const int64_t nr = (int64_t)u;
   if (b->dref_rebuilds != c.rebuilds || b->dref_rows > nr) b->dref_rows = 0;
-  KMX_TRY(grow(ctx, b->dref, (size_t)std::max<int64_t>(nr, 1) * d * sizeof(float)));
+  const size_t need = (size_t)std::max<int64_t>(nr, 1) * d * sizeof(float);
+  if (b->dref.bytes < need) {
+    // a new buffer holds none of the uploaded rows; grow by half again at least
+    KMX_TRY(grow(ctx, b->dref, std::max(need, b->dref.bytes + b->dref.bytes / 2)));
+    b->dref_rows = 0;
+  }
   if (b->dref_rows < nr) {
     // append the references opened since the last upload
     std::vector<float> h((size_t)(nr - b->dref_rows) * d);

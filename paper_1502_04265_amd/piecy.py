@@ -92,12 +92,13 @@ def _finish(ctx, clock, P, w, k, lloyd_iters, seed, prec, stats):
 
 def piecy(ctx: kmx.Context, pieces: Iterable[torch.Tensor], k: int, svd_dim: int,
           m: Optional[int] = None, T0: Optional[float] = None, lloyd_iters: int = 20,
-          seed: int = 0, prec: str = "fp32"):
+          seed: int = 0, prec: str = "fp32", progress=None):
     """Sec. 2.2: every projected piece enters one BICO instance.  Returns a
     dict with the centers C, the summary (P, w), the Lloyd cost history on the
     summary, the BICO statistics and the wall seconds of the stages (reduce_s:
     range finder + projection + lift, bico_s: insertion and summary, kmeans_s:
-    k-means++ and Lloyd on the summary)."""
+    k-means++ and Lloyd on the summary).  progress(piece, rows, stats), when
+    given, is called after each piece."""
     m = 200 * k if m is None else int(m)
     b = None
     clock = None
@@ -110,6 +111,8 @@ def piecy(ctx: kmx.Context, pieces: Iterable[torch.Tensor], k: int, svd_dim: int
             b = kmx.Bico(ctx, Y.shape[1], m, T0 if T0 is not None else initial_threshold(ctx, Y, m))
         clock.run("bico_s", b.insert, Y)
         rows += Y.shape[0]
+        if progress:
+            progress(q, rows, b.stats())
     P, w = clock.run("bico_s", b.coreset)
     st = b.stats()
     st["rows"] = rows
@@ -118,7 +121,7 @@ def piecy(ctx: kmx.Context, pieces: Iterable[torch.Tensor], k: int, svd_dim: int
 
 def piecy_mr(ctx: kmx.Context, pieces: Iterable[torch.Tensor], k: int, svd_dim: int,
              np_: int = 4, m: Optional[int] = None, T0: Optional[float] = None,
-             lloyd_iters: int = 20, seed: int = 0, prec: str = "fp32"):
+             lloyd_iters: int = 20, seed: int = 0, prec: str = "fp32", progress=None):
     """Sec. 2.3: a Merge-and-Reduce tree of BICO instances of degree np_."""
     m = 200 * k if m is None else int(m)
     levels = []        # [Bico, inputs taken]
@@ -153,6 +156,8 @@ def piecy_mr(ctx: kmx.Context, pieces: Iterable[torch.Tensor], k: int, svd_dim: 
             clock[0] = _Clock(A.device)
         Y = clock[0].run("reduce_s", project_piece, ctx, A, svd_dim, seed=seed + q)
         push(0, Y, None, q)
+        if progress:
+            progress(q, None, levels[0][0].stats())
     parts, wparts, live = [], [], []
     for lv, (b, cnt) in enumerate(levels):
         if cnt == 0:

@@ -82,6 +82,27 @@ def test_bico_matches_oracle(ctx, n, d, m, T0, wkind, sigma):
     np.testing.assert_array_equal(wP.cpu().numpy(), Wo.astype(np.float32))
 
 
+def test_bico_first_level_outgrows_its_device_buffer(ctx):
+    # thousands of first-level features: the device copy of their references
+    # is reallocated several times while blocks are queried, and every
+    # reallocation must upload all of them again
+    from paper_1502_04265_amd import kmx
+    n, d, m = 4000, 64, 1500
+    say(f"bico n={n} d={d} m={m}, growing first level")
+    X = _mixture(n, d, 11, 1.0)
+    ref = ob.summarize(X, m, 20.0)
+    b = kmx.Bico(ctx, d, m, 20.0)
+    b.insert(_dev(X))
+    st = b.stats()
+    say(f"  {st}")
+    W, S, Q, R, L = b.features()
+    Wo, So, Qo, Ro, Lo = ref.features()
+    assert st["rebuilds"] == ref.rebuilds and st["count"] == ref.count
+    assert np.array_equal(W, Wo) and np.array_equal(S, So) and np.array_equal(R, Ro)
+    assert np.array_equal(L, Lo)
+    assert st["host_scans"] < n // 100
+
+
 def test_bico_wide_rows(ctx):
     # d > 1024: the device search takes the every-center path
     from paper_1502_04265_amd import kmx

@@ -1,9 +1,10 @@
 // Host logic of the BICO summary (Sec. 2.1: clustering features in a tree of
 // spheres; Sec. 2.3.1: weighted insertion), free of device calls so that it
-// also builds as plain C++.  The closest first-level reference of a point can
-// come from outside (the device search of kmx_bico.hip) as a hint over the
-// first u first-level features; everything else is decided here in FP64 with
-// sums in coordinate order and no fused multiply-adds.
+// also builds as plain C++.  The closest reference among the children of a
+// node can come from outside (the device search of kmx_bico.hip) as a hint:
+// for a block of points, the closest among the first u children that node had
+// when the block started; everything else is decided here in FP64 with sums
+// in coordinate order and no fused multiply-adds.
 //
 // Tree.  A feature holds (W, S, Q) = (weight, weighted sum of its points,
 // weighted sum of their squared lengths), a reference point and its children.
@@ -51,14 +52,25 @@ struct Core {
   int64_t rebuilds = 0, host_scans = 0;
 };
 
-// A search hint for one point: the closest among roots[0, u) (lab) with the
-// device's two smallest distances d1 <= d2; valid = false: no hint.
-struct Hint {
-  bool valid = false;
-  int32_t lab = 0;
-  float d1 = 0.f, d2 = 0.f;
+// Search hints of a block of points for the child list of one node (-1: the
+// root): for point q, the closest among the node's first u children (lab[q],
+// an index into that list) with the device's two smallest distances.
+struct NodeHints {
+  int32_t node = -1;
   size_t u = 0;
+  std::vector<int32_t> lab;
+  std::vector<float> d1, d2;
 };
+
+// Nodes whose child lists a block's search hints cover: the root when it has
+// children, then the nodes with the most children (at least kBigKids), at
+// most kHintNodes in all.  (A test build may lower kBigKids to reach the
+// node hints on small trees.)
+#ifndef KMX_BICO_BIG_KIDS
+#define KMX_BICO_BIG_KIDS 32
+#endif
+constexpr size_t kBigKids = KMX_BICO_BIG_KIDS;
+constexpr size_t kHintNodes = 16;
 
 inline double sq_dist(const float* a, const float* b, int d) {
   double s = 0.0;
@@ -121,45 +133,70 @@ inline std::vector<int32_t> bfs(const Core& b) {
   return out;
 }
 
-// First-level closest reference for x.  With a hint, the device's choice is
-// re-measured in FP64, the first-level features opened after the hint are
-// scanned, and all of them are scanned when the device's two distances lie
-// within 1e-6 of each other (too near for FP32 to order them).
-inline void first_level(Core& b, const float* x, const Hint& h, int32_t& best, double& bd) {
+inline std::vector<int32_t> hint_nodes(const Core& b) {
+  std::vector<int32_t> out;
+  if (!b.roots.empty()) out.push_back(-1);
+  std::vector<std::pair<size_t, int32_t>> big;
+  for (size_t id = 0; id < b.f.size(); ++id)
+    if (b.f[id].kids.size() >= kBigKids) big.push_back({b.f[id].kids.size(), (int32_t)id});
+  std::sort(big.begin(), big.end(), [](const std::pair<size_t, int32_t>& a,
+                                       const std::pair<size_t, int32_t>& c) {
+    return a.first != c.first ? a.first > c.first : a.second < c.second;
+  });
+  for (const auto& e : big) {
+    if (out.size() >= kHintNodes) break;
+    out.push_back(e.second);
+  }
+  return out;
+}
+
+// Closest reference to x among the children of `parent` (best < 0: none).
+// With a hint for this node, the device's choice is re-measured in FP64, the
+// children added after the hint are scanned, and all of them are scanned when
+// the device's two distances lie within 1e-6 of each other (too near for FP32
+// to order them); without one, every child is scanned.
+inline void closest(Core& b, int32_t parent, const float* x, const std::vector<NodeHints>* hints,
+                    int64_t q, int32_t& best, double& bd) {
+  const std::vector<int32_t>& kids = kids_of(b, parent);
   best = -1;
   bd = 0.0;
-  if (h.valid && h.u > 0 && h.u <= b.roots.size() && h.lab >= 0 && (size_t)h.lab < h.u) {
-    if (!(h.d2 - h.d1 > 1e-6f * h.d2)) {
-      scan(b, b.roots, 0, h.u, x, best, bd);
+  const NodeHints* h = nullptr;
+  if (hints)
+    for (const NodeHints& nh : *hints)
+      if (nh.node == parent) {
+        h = &nh;
+        break;
+      }
+  if (h && h->u > 0 && h->u <= kids.size() && h->lab[q] >= 0 && (size_t)h->lab[q] < h->u) {
+    if (h->u > 1 && !(h->d2[q] - h->d1[q] > 1e-6f * h->d2[q])) {
+      scan(b, kids, 0, h->u, x, best, bd);
       b.host_scans++;
     } else {
-      best = b.roots[h.lab];
+      best = kids[h->lab[q]];
       bd = sq_dist(x, &b.ref[(size_t)best * b.d], b.d);
     }
-    scan(b, b.roots, h.u, b.roots.size(), x, best, bd);
+    scan(b, kids, h->u, kids.size(), x, best, bd);
   } else {
-    scan(b, b.roots, 0, b.roots.size(), x, best, bd);
+    scan(b, kids, 0, kids.size(), x, best, bd);
   }
 }
 
-// w copies of x, given its first-level closest reference (best < 0: none).
-inline void insert_point(Core& b, const float* x, double w, int32_t best, double bd) {
+// w copies of x; hints (nullable) for point q of the block.
+inline void insert_point(Core& b, const float* x, double w, const std::vector<NodeHints>* hints,
+                         int64_t q) {
   const int d = b.d;
   std::vector<double> xd(d), tmp(d);
   for (int j = 0; j < d; ++j) xd[j] = (double)x[j];
-  const double q = sq_norm(xd.data(), d);
+  const double qn = sq_norm(xd.data(), d);
   int32_t parent = -1;
   int level = 1;
   while (w > 0) {
-    if (level > 1) {
-      best = -1;
-      bd = 0.0;
-      const std::vector<int32_t>& sib = kids_of(b, parent);
-      scan(b, sib, 0, sib.size(), x, best, bd);
-    }
+    int32_t best;
+    double bd;
+    closest(b, parent, x, hints, q, best, bd);
     if (best < 0 || bd > radius2(b, level)) {
       for (int j = 0; j < d; ++j) tmp[j] = w * xd[j];
-      open_feature(b, x, w, tmp.data(), w * q, level, parent);
+      open_feature(b, x, w, tmp.data(), w * qn, level, parent);
       break;
     }
     Feature& F = b.f[best];
@@ -177,7 +214,7 @@ inline void insert_point(Core& b, const float* x, double w, int32_t best, double
     if (wp > 0) {
       F.W += wp;
       for (int j = 0; j < d; ++j) S[j] += wp * xd[j];
-      F.Q += wp * q;
+      F.Q += wp * qn;
       w -= wp;
     }
     parent = best;
@@ -186,9 +223,9 @@ inline void insert_point(Core& b, const float* x, double w, int32_t best, double
 }
 
 // Rebuild: T doubles and every feature is re-inserted into an empty tree.
-// query(refs, nq, u, hints) may fill hints for the nq references of a block
-// against roots[0, u) of the new tree (return false for an error; leaving the
-// hints invalid is always correct).
+// query(refs, nq, hints) may fill search hints for the nq references of a
+// block (for the nodes hint_nodes names at the block's start; return false
+// for an error; no hints is always correct).
 template <class Query>
 bool rebuild(Core& b, int64_t block, Query&& query) {
   const int d = b.d;
@@ -204,32 +241,25 @@ bool rebuild(Core& b, int64_t block, Query&& query) {
   b.rebuilds++;
   const int64_t nold = (int64_t)order.size();
   std::vector<float> stage((size_t)block * d);
-  std::vector<Hint> hints(block);
+  std::vector<NodeHints> hints;
   std::vector<double> mS(d);
   for (int64_t q0 = 0; q0 < nold; q0 += block) {
     const int64_t nq = std::min(block, nold - q0);
-    for (int64_t q = 0; q < nq; ++q) {
+    for (int64_t q = 0; q < nq; ++q)
       std::memcpy(&stage[(size_t)q * d], &oref[(size_t)order[q0 + q] * d],
                   (size_t)d * sizeof(float));
-      hints[q] = Hint();
-    }
-    if (!b.roots.empty() && !query(stage.data(), nq, b.roots.size(), hints.data())) return false;
+    hints.clear();
+    if (!b.roots.empty() && !query(stage.data(), nq, hints)) return false;
     for (int64_t q = 0; q < nq; ++q) {
       const int32_t o = order[q0 + q];
       const float* r = &oref[(size_t)o * d];
       const double* Sf = &oS[(size_t)o * d];
-      int32_t best;
-      double bd;
-      first_level(b, r, hints[q], best, bd);
       int32_t parent = -1;
       int level = 1;
       while (true) {
-        if (level > 1) {
-          best = -1;
-          bd = 0.0;
-          const std::vector<int32_t>& sib = kids_of(b, parent);
-          scan(b, sib, 0, sib.size(), r, best, bd);
-        }
+        int32_t best;
+        double bd;
+        closest(b, parent, r, &hints, q, best, bd);
         if (best < 0 || bd > radius2(b, level)) {
           open_feature(b, r, of[o].W, Sf, of[o].Q, level, parent);
           break;

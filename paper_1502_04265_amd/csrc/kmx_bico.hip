@@ -1,17 +1,20 @@
 // BICO summary on the host (bico_core.h: Sec. 2.1 clustering features in a
 // tree of spheres, Sec. 2.3.1 weighted insertion), with the part the paper
 // names as dominating insertion -- finding the closest reference point among
-// the features of the first tree level -- offloaded to the device in blocks
-// of points through the assignment step's distance GEMM with fused argmin.
+// the children of a node, of which the first level is the largest -- offloaded
+// to the device in blocks of points through the assignment step's distance
+// GEMM with fused argmin.
 //
-// For a block of points, the device returns the closest reference among the
-// first-level features that existed when the block started (FP32 distance
-// GEMM, exact argmin) with the two smallest distances; bico_core.h re-measures
-// that choice in FP64, scans the first-level features opened since, and scans
-// all of them in FP64 when the two device distances are too near to order, so
-// every decision is the one a sequential FP64 implementation takes.  A
-// rebuild ends the block; the next block queries the new tree.  Rebuilds send
-// their first-level searches to the device in blocks of 256 features.
+// For a block of points, the device returns, for the root and for up to 15
+// nodes with at least 32 children, the closest child that existed when the
+// block started (FP32 distance GEMM, exact argmin) with the two smallest
+// distances; bico_core.h re-measures that choice in FP64, scans the children
+// added since, and scans all of them in FP64 when the two device distances are
+// too near to order, so every decision is the one a sequential FP64
+// implementation takes.  A rebuild ends the block; the next block queries the
+// new tree.  Rebuilds send their searches to the device in blocks of 256
+// features.  Each node's child references stay on the device between blocks
+// and only the children added since are uploaded.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -24,13 +27,18 @@
 using namespace kmx;
 using namespace kmx::host;
 
+// Device copy of one node's child references (rows in child order).
+struct NodeRefs {
+  int32_t node = -2;
+  Buf buf;
+  int64_t rows = 0;
+};
+
 struct kmx_bico {
   bico::Core core;
-  int64_t gpu_rows = 0;
-  // first-level references on the device (rows in roots order)
-  Buf dref;
-  int64_t dref_rows = 0;
-  int64_t dref_rebuilds = -1;   // rebuild count at the last upload
+  int64_t gpu_rows = 0, gpu_queries = 0;
+  std::vector<NodeRefs> refs;   // cached child lists, valid for one tree
+  int64_t refs_rebuilds = -1;   // rebuild count the cache belongs to
   Buf dlab, dd1, dd2, dq;       // query results and a staging block
   int64_t block = 1024;         // points per device query (adapted)
 };
@@ -40,72 +48,116 @@ namespace {
 constexpr int64_t kBicoMinBlock = 64, kBicoMaxBlock = 8192;
 constexpr int64_t kRebuildBlock = 256;
 
-// Device query: closest first-level reference for rows [0, nq) of Q (device,
-// leading dimension ldq) among roots[0, u); hints to the host.
-kmx_status query(kmx_ctx* ctx, kmx_bico* b, const float* Q, int64_t nq, int64_t ldq, size_t u,
-                 bico::Hint* hints) {
+// The device copy of `node`'s children, uploading what was added since the
+// last query (child lists only grow between rebuilds; a rebuild empties the
+// cache, a reallocation uploads everything again).
+kmx_status node_refs(kmx_ctx* ctx, kmx_bico* b, int32_t node, const float*& dev, int64_t& rows) {
   bico::Core& c = b->core;
   const int d = c.d;
-  const int64_t nr = (int64_t)u;
-  if (b->dref_rebuilds != c.rebuilds || b->dref_rows > nr) b->dref_rows = 0;
-  const size_t need = (size_t)std::max<int64_t>(nr, 1) * d * sizeof(float);
-  if (b->dref.bytes < need) {
-    // a new buffer holds none of the uploaded rows; grow by half again at least
-    KMX_TRY(grow(ctx, b->dref, std::max(need, b->dref.bytes + b->dref.bytes / 2)));
-    b->dref_rows = 0;
+  if (b->refs_rebuilds != c.rebuilds) {
+    for (NodeRefs& r : b->refs) {
+      r.node = -2;
+      r.rows = 0;
+    }
+    b->refs_rebuilds = c.rebuilds;
   }
-  if (b->dref_rows < nr) {
-    // append the references opened since the last upload
-    std::vector<float> h((size_t)(nr - b->dref_rows) * d);
-    for (int64_t q = b->dref_rows; q < nr; ++q)
-      std::memcpy(&h[(size_t)(q - b->dref_rows) * d], &c.ref[(size_t)c.roots[q] * d],
+  NodeRefs* e = nullptr;
+  for (NodeRefs& r : b->refs)
+    if (r.node == node) e = &r;
+  if (!e)
+    for (NodeRefs& r : b->refs)
+      if (r.node == -2) {
+        e = &r;
+        break;
+      }
+  if (!e) {
+    b->refs.emplace_back();
+    e = &b->refs.back();
+  }
+  e->node = node;
+  const std::vector<int32_t>& kids = bico::kids_of(c, node);
+  const int64_t nr = (int64_t)kids.size();
+  const size_t need = (size_t)std::max<int64_t>(nr, 1) * d * sizeof(float);
+  if (e->buf.bytes < need) {
+    // a new buffer holds none of the uploaded rows; grow by half again at least
+    KMX_TRY(grow(ctx, e->buf, std::max(need, e->buf.bytes + e->buf.bytes / 2)));
+    e->rows = 0;
+  }
+  if (e->rows > nr) e->rows = 0;
+  if (e->rows < nr) {
+    std::vector<float> h((size_t)(nr - e->rows) * d);
+    for (int64_t q = e->rows; q < nr; ++q)
+      std::memcpy(&h[(size_t)(q - e->rows) * d], &c.ref[(size_t)kids[q] * d],
                   (size_t)d * sizeof(float));
-    KMX_HIP(ctx, hipMemcpyAsync(P<float>(b->dref) + (size_t)b->dref_rows * d, h.data(),
+    KMX_HIP(ctx, hipMemcpyAsync(P<float>(e->buf) + (size_t)e->rows * d, h.data(),
                                 h.size() * sizeof(float), hipMemcpyHostToDevice, ctx->stream));
     KMX_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    b->dref_rows = nr;
+    e->rows = nr;
   }
-  b->dref_rebuilds = c.rebuilds;
+  dev = P<float>(e->buf);
+  rows = nr;
+  return KMX_OK;
+}
+
+// Device search hints for rows [0, nq) of Q (device, leading dimension ldq)
+// over the child lists of the nodes bico::hint_nodes names: per node, the
+// closest child (FP32 distance GEMM with exact argmin) and the two smallest
+// distances.
+kmx_status query(kmx_ctx* ctx, kmx_bico* b, const float* Q, int64_t nq, int64_t ldq,
+                 std::vector<bico::NodeHints>& hints) {
+  bico::Core& c = b->core;
+  const int d = c.d;
+  hints.clear();
+  const std::vector<int32_t> nodes = bico::hint_nodes(c);
+  if (nodes.empty()) return KMX_OK;
   KMX_TRY(grow(ctx, b->dlab, (size_t)nq * sizeof(int32_t)));
   KMX_TRY(grow(ctx, b->dd1, (size_t)nq * sizeof(float)));
   KMX_TRY(grow(ctx, b->dd2, (size_t)nq * sizeof(float)));
-  KMX_TRY(ensure_assign(ctx, nq, (int)nr));
   // the block's rows change from call to call at the same address: no cached
   // row statistics may survive the query
   ctx->cache_valid = false;
-  KMX_TRY(ensure_prep(ctx, Q, nq, d, ldq, KMX_FP32));
-  const kmx_status ks = run_assign(ctx, Q, nq, d, ldq, P<float>(b->dref), (int)nr, KMX_FP32,
-                                   P<int32_t>(b->dlab), P<float>(b->dd1), P<float>(b->dd2),
-                                   nullptr);
-  ctx->cache_valid = false;
-  KMX_TRY(ks);
-  std::vector<int32_t> lab(nq);
-  std::vector<float> d1(nq), d2(nq);
-  KMX_HIP(ctx, hipMemcpyAsync(lab.data(), b->dlab.p, nq * sizeof(int32_t), hipMemcpyDeviceToHost,
-                              ctx->stream));
-  KMX_HIP(ctx, hipMemcpyAsync(d1.data(), b->dd1.p, nq * sizeof(float), hipMemcpyDeviceToHost,
-                              ctx->stream));
-  KMX_HIP(ctx, hipMemcpyAsync(d2.data(), b->dd2.p, nq * sizeof(float), hipMemcpyDeviceToHost,
-                              ctx->stream));
-  KMX_HIP(ctx, hipStreamSynchronize(ctx->stream));
-  for (int64_t q = 0; q < nq; ++q) {
-    hints[q].valid = true;
-    hints[q].lab = lab[q];
-    hints[q].d1 = d1[q];
-    hints[q].d2 = d2[q];
-    hints[q].u = u;
+  for (int32_t node : nodes) {
+    const float* R = nullptr;
+    int64_t nr = 0;
+    KMX_TRY(node_refs(ctx, b, node, R, nr));
+    KMX_TRY(ensure_assign(ctx, nq, (int)nr));
+    KMX_TRY(ensure_prep(ctx, Q, nq, d, ldq, KMX_FP32));
+    const kmx_status ks = run_assign(ctx, Q, nq, d, ldq, R, (int)nr, KMX_FP32,
+                                     P<int32_t>(b->dlab), P<float>(b->dd1), P<float>(b->dd2),
+                                     nullptr);
+    if (ks != KMX_OK) {
+      ctx->cache_valid = false;
+      return ks;
+    }
+    bico::NodeHints h;
+    h.node = node;
+    h.u = (size_t)nr;
+    h.lab.resize(nq);
+    h.d1.resize(nq);
+    h.d2.resize(nq);
+    KMX_HIP(ctx, hipMemcpyAsync(h.lab.data(), b->dlab.p, nq * sizeof(int32_t),
+                                hipMemcpyDeviceToHost, ctx->stream));
+    KMX_HIP(ctx, hipMemcpyAsync(h.d1.data(), b->dd1.p, nq * sizeof(float), hipMemcpyDeviceToHost,
+                                ctx->stream));
+    KMX_HIP(ctx, hipMemcpyAsync(h.d2.data(), b->dd2.p, nq * sizeof(float), hipMemcpyDeviceToHost,
+                                ctx->stream));
+    KMX_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    hints.push_back(std::move(h));
+    b->gpu_queries++;
   }
+  ctx->cache_valid = false;
   b->gpu_rows += nq;
   return KMX_OK;
 }
 
-// Rebuild with the first-level searches of each block of features on the device.
+// Rebuild with the searches of each block of features on the device.
 kmx_status rebuild(kmx_ctx* ctx, kmx_bico* b) {
   const int d = b->core.d;
   KMX_TRY(grow(ctx, b->dq, (size_t)kRebuildBlock * d * sizeof(float)));
   kmx_status st = KMX_OK;
   const bool ok = bico::rebuild(b->core, kRebuildBlock,
-                                [&](const float* refs, int64_t nq, size_t u, bico::Hint* h) {
+                                [&](const float* refs, int64_t nq,
+                                    std::vector<bico::NodeHints>& h) {
     const hipError_t e = hipMemcpyAsync(b->dq.p, refs, (size_t)nq * d * sizeof(float),
                                         hipMemcpyHostToDevice, ctx->stream);
     if (e != hipSuccess) {
@@ -113,7 +165,7 @@ kmx_status rebuild(kmx_ctx* ctx, kmx_bico* b) {
       st = fail(ctx, KMX_EDEVICE, std::string("hipMemcpyAsync: ") + hipGetErrorString(e));
       return false;
     }
-    st = query(ctx, b, P<float>(b->dq), nq, d, u, h);
+    st = query(ctx, b, P<float>(b->dq), nq, d, h);
     return st == KMX_OK;
   });
   if (!ok) return st != KMX_OK ? st : fail(ctx, KMX_EDEVICE, "rebuild failed");
@@ -145,8 +197,10 @@ kmx_status kmx_bico_destroy(kmx_ctx* ctx, kmx_bico* b) {
   if (!b) return KMX_OK;
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
-  for (Buf* p : {&b->dref, &b->dlab, &b->dd1, &b->dd2, &b->dq})
+  for (Buf* p : {&b->dlab, &b->dd1, &b->dd2, &b->dq})
     if (p->p) (void)hipFree(p->p);
+  for (NodeRefs& r : b->refs)
+    if (r.buf.p) (void)hipFree(r.buf.p);
   delete b;
   return KMX_OK;
 }
@@ -163,7 +217,7 @@ kmx_status kmx_bico_insert(kmx_ctx* ctx, kmx_bico* b, const float* X, int64_t n,
   KMX_TRY(set_device(ctx));
   const int d = c.d;
   std::vector<float> hx, hw;
-  std::vector<bico::Hint> hints;
+  std::vector<bico::NodeHints> hints;
   int64_t i0 = 0;
   while (i0 < n) {
     const int64_t nb = std::min(b->block, n - i0);
@@ -182,8 +236,7 @@ kmx_status kmx_bico_insert(kmx_ctx* ctx, kmx_bico* b, const float* X, int64_t n,
       if (!(wq >= 0.0) || !std::isfinite(wq))
         return fail(ctx, KMX_EINVAL, "w holds an entry that is negative or not finite");
     }
-    hints.assign(nb, bico::Hint());
-    if (!c.roots.empty()) KMX_TRY(query(ctx, b, X + i0 * ldx, nb, ldx, c.roots.size(), hints.data()));
+    KMX_TRY(query(ctx, b, X + i0 * ldx, nb, ldx, hints));
     int64_t done = 0;
     const size_t opened0 = c.f.size();
     bool rebuilt = false;
@@ -192,10 +245,7 @@ kmx_status kmx_bico_insert(kmx_ctx* ctx, kmx_bico* b, const float* X, int64_t n,
       const double wq = w ? (double)hw[q] : 1.0;
       done = q + 1;
       if (wq == 0.0) continue;
-      int32_t best;
-      double bd;
-      bico::first_level(c, x, hints[q], best, bd);
-      bico::insert_point(c, x, wq, best, bd);
+      bico::insert_point(c, x, wq, &hints, q);
       if ((int64_t)c.f.size() > c.m) {
         while ((int64_t)c.f.size() > c.m) KMX_TRY(rebuild(ctx, b));
         rebuilt = true;

@@ -1,9 +1,9 @@
 // CPU harness of the BICO host logic (paper_1502_04265_amd/csrc/bico_core.h)
 // for tests/test_bico_host.py: inserts the rows of an input file block by
-// block as the library does, with first-level hints from a host stand-in for
-// the device search (FP64 argmin over the first-level features that existed
-// when the block started, distances rounded to FP32), and writes the
-// features in breadth-first order.
+// block as the library does, with search hints from a host stand-in for the
+// device search (FP64 argmin over the children each hinted node had when the
+// block started, distances rounded to FP32), and writes the features in
+// breadth-first order.
 //   input : int64 n, int32 d, int64 m, double T0, int32 block, int32 has_w,
 //           float32 X[n][d], float64 w[n] (when has_w)
 //   output: int64 count, double T, int64 rebuilds, int64 host_scans, then per
@@ -17,26 +17,37 @@
 
 using namespace kmx::bico;
 
-static void hints_for(const Core& c, const float* rows, int64_t nq, size_t u, Hint* h) {
-  for (int64_t q = 0; q < nq; ++q) {
-    const float* x = rows + (size_t)q * c.d;
-    int32_t best = -1;
-    double b1 = 0.0, b2 = 1e300;
-    for (size_t r = 0; r < u; ++r) {
-      const double dd = sq_dist(x, &c.ref[(size_t)c.roots[r] * c.d], c.d);
-      if (best < 0 || dd < b1) {
-        b2 = best < 0 ? 1e300 : b1;
-        b1 = dd;
-        best = (int32_t)r;
-      } else if (dd < b2) {
-        b2 = dd;
+// Hints for the nodes hint_nodes names: the FP64 argmin over each node's
+// children, distances rounded to FP32 (a stand-in for the device search).
+static void hints_for(const Core& c, const float* rows, int64_t nq, std::vector<NodeHints>& out) {
+  out.clear();
+  for (int32_t node : hint_nodes(c)) {
+    const std::vector<int32_t>& kids = kids_of(c, node);
+    NodeHints h;
+    h.node = node;
+    h.u = kids.size();
+    h.lab.assign(nq, 0);
+    h.d1.assign(nq, 0.f);
+    h.d2.assign(nq, 0.f);
+    for (int64_t q = 0; q < nq; ++q) {
+      const float* x = rows + (size_t)q * c.d;
+      int32_t best = -1;
+      double b1 = 0.0, b2 = 1e300;
+      for (size_t r = 0; r < kids.size(); ++r) {
+        const double dd = sq_dist(x, &c.ref[(size_t)kids[r] * c.d], c.d);
+        if (best < 0 || dd < b1) {
+          b2 = best < 0 ? 1e300 : b1;
+          b1 = dd;
+          best = (int32_t)r;
+        } else if (dd < b2) {
+          b2 = dd;
+        }
       }
+      h.lab[q] = best;
+      h.d1[q] = (float)b1;
+      h.d2[q] = b2 >= 1e300 ? __builtin_inff() : (float)b2;
     }
-    h[q].valid = u > 0;
-    h[q].lab = best;
-    h[q].d1 = (float)b1;
-    h[q].d2 = b2 >= 1e300 ? __builtin_inff() : (float)b2;
-    h[q].u = u;
+    out.push_back(std::move(h));
   }
 }
 
@@ -61,24 +72,20 @@ int main(int argc, char** argv) {
   c.d = d;
   c.m = m;
   c.T = T0;
-  std::vector<Hint> hints;
+  std::vector<NodeHints> hints;
   int64_t i0 = 0;
   while (i0 < n) {
     const int64_t nb = std::min<int64_t>(block, n - i0);
-    hints.assign(nb, Hint());
-    hints_for(c, &X[(size_t)i0 * d], nb, c.roots.size(), hints.data());
+    hints_for(c, &X[(size_t)i0 * d], nb, hints);
     int64_t done = 0;
     for (int64_t q = 0; q < nb; ++q) {
       done = q + 1;
       if (w[i0 + q] == 0.0) continue;
-      int32_t best;
-      double bd;
-      first_level(c, &X[(size_t)(i0 + q) * d], hints[q], best, bd);
-      insert_point(c, &X[(size_t)(i0 + q) * d], w[i0 + q], best, bd);
+      insert_point(c, &X[(size_t)(i0 + q) * d], w[i0 + q], &hints, q);
       if ((int64_t)c.f.size() > c.m) {
         while ((int64_t)c.f.size() > c.m)
-          rebuild(c, 7, [&](const float* refs, int64_t nq, size_t u, Hint* h) {
-            hints_for(c, refs, nq, u, h);
+          rebuild(c, 7, [&](const float* refs, int64_t nq, std::vector<NodeHints>& h) {
+            hints_for(c, refs, nq, h);
             return true;
           });
         break;

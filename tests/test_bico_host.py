@@ -19,20 +19,31 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 
 
-@pytest.fixture(scope="module")
-def harness(tmp_path_factory):
+def _build(tmp_path_factory, big_kids):
     gxx = shutil.which("g++")
     if gxx is None:
         pytest.skip("no g++")
     exe = str(tmp_path_factory.mktemp("bico") / "bico_host")
     cmd = [gxx, "-std=c++17", "-O1", "-g", "-ffp-contract=off", "-Wno-unknown-pragmas",
            "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+           f"-DKMX_BICO_BIG_KIDS={big_kids}",
            "-I", os.path.join(ROOT, "paper_1502_04265_amd", "csrc"),
            os.path.join(HERE, "bico_host_main.cpp"), "-o", exe]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         pytest.fail("g++ failed:\n" + r.stderr)
     return exe
+
+
+@pytest.fixture(scope="module")
+def harness(tmp_path_factory):
+    return _build(tmp_path_factory, 32)
+
+
+@pytest.fixture(scope="module")
+def harness_small_nodes(tmp_path_factory):
+    # hints also for every node with at least 4 children
+    return _build(tmp_path_factory, 4)
 
 
 def _run(exe, tmp, X, m, T0, block, w=None):
@@ -100,3 +111,22 @@ def test_host_bico_ties(harness, tmp_path):
     Wo, So, Qo, Ro, Lo = ref.features()
     assert np.array_equal(W, Wo) and np.array_equal(S, So) and np.array_equal(R, Ro)
     assert scans > 0
+
+
+@pytest.mark.parametrize("d,T0,m", [(8, 16.0, 10 ** 6), (8, 8.0, 300), (5, 2.0, 150)])
+def test_host_bico_node_hints(harness_small_nodes, tmp_path, d, T0, m):
+    # points filling a ball of radius 1: deep trees whose inner nodes hold
+    # dozens of children, each searched from a hint
+    rng = np.random.default_rng(d)
+    n = 3000
+    X = rng.normal(size=(n, d))
+    X /= np.linalg.norm(X, axis=1, keepdims=True)
+    X *= rng.uniform(0, 1, size=(n, 1)) ** (1.0 / d)
+    X = X.astype(np.float32)
+    ref = ob.summarize(X, m, T0)
+    W, S, Q, R, L, T, reb, scans = _run(harness_small_nodes, tmp_path, X, m, T0, 50)
+    Wo, So, Qo, Ro, Lo = ref.features()
+    assert (T, reb) == (ref.T, ref.rebuilds)
+    assert np.array_equal(L, Lo) and np.array_equal(R, Ro)
+    assert np.array_equal(W, Wo) and np.array_equal(S, So) and np.array_equal(Q, Qo)
+    assert L.max() >= 2

@@ -651,7 +651,16 @@ def piecy_main(args):
         ctx.timing(False, True)
         cost = ctx.cost(Xd, r["C"])
         dev_query_ms = kt["assign"][0] + kt["recheck"][0] + kt["prep"][0]
+        pairs = sum(b["pairs"] for b in r["bico"] + r.get("handed_on", []))
+        search_tf = 2.0 * pairs * W["d"] / (dev_query_ms * 1e-3) / 1e12 if dev_query_ms else 0.0
         res[name] = {"points_per_s": n / wall, "wall_s": wall, "piece_rows": ps,
+                     "device_search": {"pairs": pairs, "ms": dev_query_ms,
+                                       "tflops": search_tf,
+                                       "roofline": {"bound": "mfma", "achieved": search_tf,
+                                                    "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                                    "frac": search_tf / FP32_PEAK_TFLOPS,
+                                                    "kernel": "assign_kernel<fp32> + re-check + "
+                                                              "row / center preparation"}},
                      "reduce_s": r["reduce_s"], "bico_s": r["bico_s"], "kmeans_s": r["kmeans_s"],
                      "bico_device_search_ms": dev_query_ms,
                      "project_lift_range_ms": kt["project"][0],
@@ -690,6 +699,9 @@ def piecy_main(args):
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": W["name"], "n": n, "d": W["d"], "k": k, "svd": svd,
                    "piece_rows": W["piece"], "summary_size": 200 * k, "np": W["np_"]},
+        "roofline": best["device_search"]["roofline"],
+        "roofline_note": "the pipeline is bound by BICO's sequential host work (bico_s); the "
+                         "dominant device work is BICO's closest-reference searches",
         "paths": res, "full_data_lloyd_cost": full_cost,
         "cpu_baseline": cpu,
     }

@@ -443,9 +443,11 @@ kmx_status kmx_lloyd_bounded(kmx_ctx* ctx, kmx_router* r, const float* X, int64_
 /* ---- BICO summary (Sec. 2.1; weighted insertion Sec. 2.3.1) --------------
  * A tree of clustering features (W, S, Q) -- weight, weighted sum of the
  * points, weighted sum of their squared lengths -- kept on the host; the
- * search for the closest reference point among the first-level features,
- * which the paper names as dominating insertion time, runs on ctx's device in
+ * search for the closest reference point among the children of a node, which
+ * the paper names as dominating insertion time, runs on ctx's device in
  * blocks of points (the assignment step's distance GEMM with fused argmin).
+ * The device searches cover the root's children and the 15 largest child
+ * lists of at least 32 features (the rest are searched on the host).
  * Insertion: a point (w copies) goes down the tree to the closest reference
  * among the children of the current node (ties: the oldest); it opens a
  * feature (w, w x, w ||x||^2) when no reference lies within the level's
@@ -474,11 +476,13 @@ kmx_status kmx_bico_insert(kmx_ctx* ctx, kmx_bico* b, const float* X, int64_t n,
                            const float* w);
 
 /* Host outputs, each nullable: number of features, current threshold, rebuilds
- * so far, rows whose first-level search ran on the device, and rows whose two
- * closest first-level references were too near for the device's FP32
- * distances, so that the host compared them in FP64. */
+ * so far, rows (points and re-inserted features) whose searches ran on the
+ * device, searches whose two closest references were too near for the
+ * device's FP32 distances (so that the host compared them in FP64), and the
+ * (row, reference) distances the device searches computed. */
 kmx_status kmx_bico_stats(kmx_ctx* ctx, const kmx_bico* b, int64_t* count, double* T,
-                          int64_t* rebuilds, int64_t* gpu_rows, int64_t* host_scans);
+                          int64_t* rebuilds, int64_t* gpu_rows, int64_t* host_scans,
+                          int64_t* pairs);
 
 /* The features in breadth-first order (count from kmx_bico_stats), host
  * arrays, each nullable: W (count), S (count x d), Q (count), reference

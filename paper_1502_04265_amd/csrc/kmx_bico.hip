@@ -37,6 +37,7 @@ struct NodeRefs {
 struct kmx_bico {
   bico::Core core;
   int64_t gpu_rows = 0, gpu_queries = 0;
+  int64_t pairs = 0;            // (row, reference) distances the device searches computed
   std::vector<NodeRefs> refs;   // cached child lists, valid for one tree
   int64_t refs_rebuilds = -1;   // rebuild count the cache belongs to
   Buf dlab, dd1, dd2, dq;       // query results and a staging block
@@ -144,6 +145,7 @@ kmx_status query(kmx_ctx* ctx, kmx_bico* b, const float* Q, int64_t nq, int64_t 
     KMX_HIP(ctx, hipStreamSynchronize(ctx->stream));
     hints.push_back(std::move(h));
     b->gpu_queries++;
+    b->pairs += nq * nr;
   }
   ctx->cache_valid = false;
   b->gpu_rows += nq;
@@ -265,7 +267,8 @@ kmx_status kmx_bico_insert(kmx_ctx* ctx, kmx_bico* b, const float* X, int64_t n,
 }
 
 kmx_status kmx_bico_stats(kmx_ctx* ctx, const kmx_bico* b, int64_t* count, double* T,
-                          int64_t* rebuilds, int64_t* gpu_rows, int64_t* host_scans) {
+                          int64_t* rebuilds, int64_t* gpu_rows, int64_t* host_scans,
+                          int64_t* pairs) {
   if (!ctx) return KMX_EINVAL;
   ctx->err.clear();
   if (!b) return fail(ctx, KMX_EINVAL, "b is NULL");
@@ -274,6 +277,7 @@ kmx_status kmx_bico_stats(kmx_ctx* ctx, const kmx_bico* b, int64_t* count, doubl
   if (rebuilds) *rebuilds = b->core.rebuilds;
   if (gpu_rows) *gpu_rows = b->gpu_rows;
   if (host_scans) *host_scans = b->core.host_scans;
+  if (pairs) *pairs = b->pairs;
   return KMX_OK;
 }
 

@@ -96,7 +96,7 @@ def lib():
         "kmx_bico_create": [_vp, _i32, _i64, ctypes.c_double, ctypes.POINTER(_vp)],
         "kmx_bico_destroy": [_vp, _vp],
         "kmx_bico_insert": [_vp, _vp, _vp, _i64, _i64, _vp],
-        "kmx_bico_stats": [_vp, _vp, _vp, _vp, _vp, _vp, _vp],
+        "kmx_bico_stats": [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
         "kmx_bico_features": [_vp, _vp, _vp, _vp, _vp, _vp, _vp],
         "kmx_bico_coreset": [_vp, _vp, _vp, _vp],
     }
@@ -614,14 +614,14 @@ class Bico:
         _check(lib().kmx_bico_insert(self.ctx._p, self._b, _ptr(X), n, ldx, _ptr(w)), self.ctx._p)
 
     def stats(self):
-        """dict: count, T, rebuilds, gpu_rows, host_scans."""
-        c, r, g, h = (ctypes.c_int64(0) for _ in range(4))
+        """dict: count, T, rebuilds, gpu_rows, host_scans, pairs."""
+        c, r, g, h, pr = (ctypes.c_int64(0) for _ in range(5))
         T = ctypes.c_double(0.0)
         _check(lib().kmx_bico_stats(self.ctx._p, self._b, ctypes.byref(c), ctypes.byref(T),
-                                    ctypes.byref(r), ctypes.byref(g), ctypes.byref(h)),
-               self.ctx._p)
+                                    ctypes.byref(r), ctypes.byref(g), ctypes.byref(h),
+                                    ctypes.byref(pr)), self.ctx._p)
         return {"count": int(c.value), "T": float(T.value), "rebuilds": int(r.value),
-                "gpu_rows": int(g.value), "host_scans": int(h.value)}
+                "gpu_rows": int(g.value), "host_scans": int(h.value), "pairs": int(pr.value)}
 
     def features(self):
         """(W, S, Q, ref, level) as numpy arrays, breadth-first order."""

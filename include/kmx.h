@@ -253,6 +253,12 @@ kmx_status kmx_range_basis(kmx_ctx* ctx, const float* A, int64_t n, int32_t d, i
  * Synchronizes. */
 kmx_status kmx_assign_stats(kmx_ctx* ctx, int64_t* listed, int64_t* fp32, int64_t* full);
 
+/* Exact re-check work of the most recent Lloyd run on ctx (or, outside a run,
+ * since the context was created); host outputs, each nullable: entries of the
+ * short re-check lists (pairs and triples) and rows re-checked against every
+ * center, summed over every assignment.  Synchronizes. */
+kmx_status kmx_run_stats(kmx_ctx* ctx, int64_t* listed_total, int64_t* full_total);
+
 /* The most recent update of a Lloyd run on ctx (the final assignment's, after
  * kmx_lloyd and its variants); host outputs, each nullable:
  *   changed  rows whose label differed from the previous update's,
@@ -287,11 +293,13 @@ kmx_status kmx_mfma_probe(kmx_ctx* ctx, kmx_prec prec, const void* A, const void
 /* Kernel timing for measurement: while enabled, HIP events bracket every
  * kernel class on the context's stream.  kmx_timing_read returns the summed
  * milliseconds and launch counts per class since the last reset:
- *   class 0 prep (row statistics, quantization), 1 assign GEMM, 2 re-check,
- *   3 label sort, 4 segmented reduction, 5 finalize, 6 seeding, 7 other,
- *   8 router forward pass, 9 center table + certificate, 10 router training,
- *   11 projection, 12 carried bounds (bound test, center drift).
- * ms_out and count_out are host arrays of length n_classes (<= 13).
+ *   class 0 prep (row statistics, quantization), 1 assign GEMM (first pass),
+ *   2 the further GEMM passes of the cascade, 3 label sort / delta lists, 4
+ *   segmented reduction, 5 finalize, 6 seeding, 7 other, 8 router forward
+ *   pass, 9 center table + certificate, 10 router training, 11 projection,
+ *   range finder and lift, 12 carried bounds (bound test, center drift), 13
+ *   the exact short and every-center re-check.
+ * ms_out and count_out are host arrays of length n_classes (<= 14).
  * Reading synchronizes.  enable = 0 stops recording; reset clears sums. */
 kmx_status kmx_timing(kmx_ctx* ctx, int enable, int reset);
 kmx_status kmx_timing_read(kmx_ctx* ctx, int n_classes, double* ms_out, int64_t* count_out);
@@ -428,6 +436,8 @@ kmx_status kmx_lloyd_routed(kmx_ctx* ctx, kmx_router* r, const float* X, int64_t
  * bound keeps its label without its data being read.  The other rows go
  * through the certificate of kmx_lloyd_routed (the router's proposals when r
  * is given, else the previous label) and then the GEMM cascade of `prec`.
+ * The proposals of a row are computed the first time the bounds cannot keep
+ * it and kept for the rest of the call (they depend on the row only).
  * The first assignment runs the GEMM on every row.
  *   gemm_rows host, nullable, max_iter + 1 entries: rows of each assignment
  *             that went through the GEMM.

@@ -471,6 +471,8 @@ __global__ void reset_small_kernel(CenterStats* cs, CenterStats* cs2, CenterStat
     if (cs) { cs->cq_max = 0; cs->rc_max = 0; cs->cn_max = 0; cs->O = 0.0f; cs->c_amax = 0; cs->c_exp = 127; }
     if (cs2) { cs2->cq_max = 0; cs2->rc_max = 0; cs2->cn_max = 0; cs2->O = 0.0f; cs2->c_amax = 0; cs2->c_exp = 127; }
     if (st) {
+      st->listed_total += st->flagged;
+      st->full_total += st->flagged_full;
       st->flagged = 0;
       st->full_count = 0;
       st->full_count2 = 0;
@@ -481,6 +483,7 @@ __global__ void reset_small_kernel(CenterStats* cs, CenterStats* cs2, CenterStat
       st->bound_fail = 0;
       st->bound_pair = 0;
       st->dcount = 0;
+      st->need_rows = 0;
       if (reset_iter) {
         st->done = 0;
         st->iter = 0;

@@ -69,8 +69,11 @@ __global__ __launch_bounds__(WAVES * 64) void router_fwd_kernel(
     const uint16_t* __restrict__ Xq, int64_t xs, int64_t n, const uint16_t* __restrict__ W1a,
     const float* __restrict__ b1, const uint16_t* __restrict__ W2a,
     const float* __restrict__ b2p, int kpad, int ib, uint32_t* __restrict__ keys,
+    const int* __restrict__ rows, const unsigned long long* __restrict__ row_count,
     const int* __restrict__ gate) {
   if (gate && *gate) return;
+  // with a row list: points 0 .. *row_count - 1 are the rows rows[p]
+  if (rows) n = (int64_t)*row_count;
   constexpr int ROW1 = NKU * 64;                     // bytes of a W1a row
   constexpr int UROW1 = NKU * 4 + 1;                 // 16-byte units of a padded LDS row
   constexpr int PITCH1 = UROW1 * 16;
@@ -120,14 +123,16 @@ __global__ __launch_bounds__(WAVES * 64) void router_fwd_kernel(
   for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
     const int64_t p_base = blk * PPB + (int64_t)wave * (16 * NCG);
     ru32x4_t xf[NCG][NKU];
+    int64_t src[NCG];
 #pragma unroll
     for (int cg = 0; cg < NCG; ++cg) {
       const int64_t p = p_base + cg * 16 + prow;
       const bool pv = p < n;
+      src[cg] = pv ? (rows ? (int64_t)rows[p] : p) : -1;
 #pragma unroll
       for (int ku = 0; ku < NKU; ++ku) {
         ru32x4_t v = {0u, 0u, 0u, 0u};
-        if (pv) v = *(const ru32x4_t*)(Xq + p * xs + ku * 32 + grp * 8);
+        if (pv) v = *(const ru32x4_t*)(Xq + src[cg] * xs + ku * 32 + grp * 8);
         xf[cg][ku] = v;
       }
     }
@@ -218,13 +223,55 @@ __global__ __launch_bounds__(WAVES * 64) void router_fwd_kernel(
 
 #pragma unroll
     for (int cg = 0; cg < NCG; ++cg) {
-      const int64_t p = p_base + cg * 16 + prow;
-      if (p < n) {
+      if (src[cg] >= 0) {
         const ru32x4_t o = {v1[cg], v2[cg], v3[cg], v4[cg]};
-        *(ru32x4_t*)(keys + p * kRouterM + grp * 4) = o;
+        *(ru32x4_t*)(keys + src[cg] * kRouterM + grp * 4) = o;
       }
     }
   }
+}
+
+// Rows of the list rows[0 .. *count) whose proposals were not computed yet in
+// this run (have[row] == 0): marked and appended to out (positions from one
+// atomic per wave; any order).  *out_count must be zero before.
+__global__ __launch_bounds__(256) void need_proposals_kernel(const int* __restrict__ rows,
+                                                             const unsigned long long* __restrict__ count,
+                                                             uint8_t* __restrict__ have,
+                                                             int* __restrict__ out,
+                                                             unsigned long long* __restrict__ out_count,
+                                                             const int* __restrict__ gate) {
+  if (gate && *gate) return;
+  const int64_t m = (int64_t)*count;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int lane = threadIdx.x & 63;
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < m; base += stride) {
+    const int64_t q = base + threadIdx.x;
+    int r = -1;
+    bool need = false;
+    if (q < m) {
+      r = rows[q];
+      need = have[r] == 0;
+      if (need) have[r] = 1;
+    }
+    const unsigned long long bal = __ballot(need);
+    if (bal == 0ull) continue;
+    const int first = __ffsll((long long)bal) - 1;
+    unsigned long long pos = 0;
+    if (lane == first) pos = atomicAdd(out_count, (unsigned long long)__popcll(bal));
+    pos = __shfl(pos, first, 64);
+    if (need) out[pos + __popcll(bal & ((1ull << lane) - 1ull))] = r;
+  }
+}
+
+hipError_t launch_need_proposals(hipStream_t s, const int* rows, const unsigned long long* count,
+                                 int64_t max_rows, uint8_t* have, int* out,
+                                 unsigned long long* out_count, const int* gate, int num_cus) {
+  int64_t blocks = (max_rows + 255) / 256;
+  if (blocks > (int64_t)num_cus * 4) blocks = (int64_t)num_cus * 4;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(need_proposals_kernel, dim3((unsigned)blocks), dim3(256), 0, s, rows, count,
+                     have, out, out_count, gate);
+  return hipGetLastError();
 }
 
 // Units of 32 BF16 columns the forward pass reads from each row of the
@@ -242,6 +289,7 @@ template <int NKU, int NCG, int WAVES>
 static hipError_t run_router_fwd(hipStream_t s, const uint16_t* Xq, int64_t xs, int64_t n,
                                  const uint16_t* W1a, const float* b1, const uint16_t* W2a,
                                  const float* b2p, int kpad, int ib, uint32_t* keys,
+                                 const int* rows, const unsigned long long* row_count,
                                  const int* gate, int num_cus) {
   const int64_t ppb = (int64_t)WAVES * 16 * NCG;
   int64_t blocks = (n + ppb - 1) / ppb;
@@ -249,14 +297,15 @@ static hipError_t run_router_fwd(hipStream_t s, const uint16_t* Xq, int64_t xs, 
   if (blocks > cap) blocks = cap;
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL((router_fwd_kernel<NKU, NCG, WAVES>), dim3((unsigned)blocks),
-                     dim3(WAVES * 64), 0, s, Xq, xs, n, W1a, b1, W2a, b2p, kpad, ib, keys, gate);
+                     dim3(WAVES * 64), 0, s, Xq, xs, n, W1a, b1, W2a, b2p, kpad, ib, keys, rows,
+                     row_count, gate);
   return hipGetLastError();
 }
 
 hipError_t launch_router_fwd(hipStream_t s, const uint16_t* Xq, int64_t dp, int64_t n, int d,
                              const uint16_t* W1a, const float* b1, const uint16_t* W2a,
                              const float* b2p, int kpad, uint32_t* keys, const int* gate,
-                             int num_cus) {
+                             int num_cus, const int* rows, const unsigned long long* row_count) {
   if (kpad % kRouterBN2 != 0 || kpad > kRouterMaxK) return hipErrorInvalidValue;
   int ib = 1;
   while ((1 << ib) < kpad) ++ib;
@@ -266,8 +315,8 @@ hipError_t launch_router_fwd(hipStream_t s, const uint16_t* Xq, int64_t dp, int6
 // so those run one wave per SIMD (four waves per workgroup).
 #define KMX_R(U, G, W)                                                                     \
   case U:                                                                                  \
-    return run_router_fwd<U, G, W>(s, Xq, dp, n, W1a, b1, W2a, b2p, kpad, ib, keys, gate, \
-                                   num_cus)
+    return run_router_fwd<U, G, W>(s, Xq, dp, n, W1a, b1, W2a, b2p, kpad, ib, keys, rows, \
+                                   row_count, gate, num_cus)
     KMX_R(1, 2, 8);
     KMX_R(2, 2, 8);
     KMX_R(3, 2, 8);

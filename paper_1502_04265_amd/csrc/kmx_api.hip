@@ -346,7 +346,7 @@ kmx_status run_assign_gemm(kmx_ctx* ctx, const float* X, int64_t n, int d, int64
     }
   }
   {
-    Timed tm(ctx, T_RECHECK);
+    Timed tm(ctx, T_SHORT);
     KMX_HIP(ctx, launch_recheck(ctx->stream, X, n, d, ldx, C, k, label, d1, flags, brute, st,
                                 ctx->num_cus, gate, bo));
   }
@@ -479,7 +479,7 @@ kmx_status kmx_destroy(kmx_ctx* ctx) {
       &ctx->D2,        &ctx->chosen,   &ctx->seed_part,  &ctx->seed_ctr,   &ctx->scratch_c,
       &ctx->seed_a,    &ctx->seed_cc,  &ctx->seed_nread,
       &ctx->hist,      &ctx->fb_rows,  &ctx->keys,       &ctx->cdist,      &ctx->nbr,
-      &ctx->nbd,       &ctx->fbh,      &ctx->xq8,        &ctx->sx8,        &ctx->rowstats8,
+      &ctx->nbd,       &ctx->fbh,      &ctx->prop_have,  &ctx->prop_rows,      &ctx->xq8,        &ctx->sx8,        &ctx->rowstats8,
       &ctx->xstats8,   &ctx->cq8,      &ctx->ch8,        &ctx->hd8,        &ctx->cstats8,
       &ctx->full_rows2, &ctx->bX,       &ctx->bXq,        &ctx->brs,        &ctx->bw,
       &ctx->bC,        &ctx->bCq,      &ctx->bhd,        &ctx->bch,        &ctx->vt,        &ctx->bcs,        &ctx->blab,
@@ -810,6 +810,21 @@ kmx_status kmx_assign_stats(kmx_ctx* ctx, int64_t* listed, int64_t* fp32, int64_
   if (listed) *listed = (int64_t)h.flagged;
   if (fp32) *fp32 = (int64_t)(ctx->last_prec == KMX_FP8E4M3 ? h.full_count2 : h.full_count);
   if (full) *full = (int64_t)h.flagged_full;
+  return KMX_OK;
+}
+
+kmx_status kmx_run_stats(kmx_ctx* ctx, int64_t* listed_total, int64_t* full_total) {
+  if (!ctx) return KMX_EINVAL;
+  ctx->err.clear();
+  if (listed_total) *listed_total = 0;
+  if (full_total) *full_total = 0;
+  if (!ctx->state.p) return KMX_OK;
+  KMX_TRY(set_device(ctx));
+  LoopState h;
+  KMX_HIP(ctx, hipMemcpyAsync(&h, ctx->state.p, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+  KMX_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  if (listed_total) *listed_total = (int64_t)(h.listed_total + h.flagged);
+  if (full_total) *full_total = (int64_t)(h.full_total + h.flagged_full);
   return KMX_OK;
 }
 

@@ -58,6 +58,9 @@ struct LoopState {
   unsigned long long bound_fail;       // rows the carried bounds could not keep (last assign)
   unsigned long long bound_pair;       // rows they sent to the re-check with their runner-up
   unsigned long long dcount;           // changed rows listed for the delta update (this update)
+  unsigned long long need_rows;        // rows whose proposals are computed in this assignment
+  unsigned long long listed_total;     // re-check list entries of the earlier assignments of the run
+  unsigned long long full_total;       // every-center rows of the earlier assignments of the run
   int acc_valid;                       // the carried clustering features hold the last labels
   int pad_;
 };
@@ -134,7 +137,7 @@ struct BatchBucket {
 enum TimingClass {
   T_PREP = 0, T_ASSIGN = 1, T_RECHECK = 2, T_SORT = 3, T_REDUCE = 4,
   T_FINAL = 5, T_SEED = 6, T_OTHER = 7, T_ROUTER = 8, T_CERT = 9, T_TRAIN = 10,
-  T_PROJECT = 11, T_BOUND = 12, T_NCLASS = 13
+  T_PROJECT = 11, T_BOUND = 12, T_SHORT = 13, T_NCLASS = 14
 };
 
 // Grow-only device buffer.
@@ -212,6 +215,7 @@ struct kmx_ctx {
   kmx::Buf D2, chosen, seed_part, seed_ctr, seed_a, seed_cc, seed_nread;
   kmx::Buf scratch_c, hist;
   kmx::Buf fb_rows, keys, cdist, nbr, nbd, fbh;   // routed assignment
+  kmx::Buf prop_have, prop_rows;   // bounded routed: rows with proposals, rows needing them
   kmx::Buf hub, hlb, hl2, hsec, bl_rows, cprev, drift, dstat, bkh;   // carried bounds
   // batched Lloyd: concatenated instances and their descriptors
   kmx::Buf vt;                          // transposed projection basis
@@ -414,10 +418,18 @@ int router_units(int d, int dp);
 hipError_t launch_router_layout(hipStream_t s, const float* W1, const float* W2, const float* b2,
                                 int d, int k, int kpad, int r1, uint16_t* W1a, uint16_t* W2a,
                                 float* b2p);
+// Forward pass of the router for rows 0 .. n-1, or with a row list for rows
+// rows[0 .. *row_count) (keys written at each row's position).
 hipError_t launch_router_fwd(hipStream_t s, const uint16_t* Xq, int64_t dp, int64_t n, int d,
                              const uint16_t* W1a, const float* b1, const uint16_t* W2a,
                              const float* b2p, int kpad, uint32_t* keys, const int* gate,
-                             int num_cus);
+                             int num_cus, const int* rows = nullptr,
+                             const unsigned long long* row_count = nullptr);
+// Rows of rows[0 .. *count) without proposals yet (have[row] == 0) are
+// marked and listed in out (*out_count, which must be zero before).
+hipError_t launch_need_proposals(hipStream_t s, const int* rows, const unsigned long long* count,
+                                 int64_t max_rows, uint8_t* have, int* out,
+                                 unsigned long long* out_count, const int* gate, int num_cus);
 hipError_t launch_router_decode(hipStream_t s, const uint32_t* keys, int64_t count, int k,
                                 int kpad, int32_t* cand);
 hipError_t launch_center_table(hipStream_t s, const float* C, int k, int d, float* D, int32_t* nbr,

@@ -479,15 +479,22 @@ static kmx_status lloyd_routed_impl(kmx_ctx* ctx, kmx_router* r, const float* X,
   int64_t* bkh = bounded ? P<int64_t>(ctx->bkh) : nullptr;
   LoopState* st = ST(ctx);
   KMX_TRY(begin_lloyd(ctx, prev, n));
-  if (r) {
+  if (r && !bounded) {
     // the proposals depend on the points only: one forward pass serves every iteration
     Timed tm(ctx, T_ROUTER);
     KMX_HIP(ctx, launch_router_fwd(ctx->stream, P<uint16_t>(ctx->xq), dp, n, d,
                                    P<uint16_t>(r->W1a), P<float>(r->b1), P<uint16_t>(r->W2a),
                                    P<float>(r->b2p), r->kpad, P<uint32_t>(ctx->keys), nullptr,
                                    ctx->num_cus));
-    keys = P<uint32_t>(ctx->keys);
   }
+  if (r && bounded) {
+    // with carried bounds only the rows the bounds cannot keep need proposals:
+    // each row's are computed the first time it needs them and kept for the run
+    KMX_TRY(grow(ctx, ctx->prop_have, (size_t)n));
+    KMX_TRY(grow(ctx, ctx->prop_rows, (size_t)n * sizeof(int)));
+    KMX_HIP(ctx, launch_fill_u8(ctx->stream, P<uint8_t>(ctx->prop_have), n, 0));
+  }
+  if (r) keys = P<uint32_t>(ctx->keys);
   // one assignment of iteration t (t == max_iter: the final one); gate: the stop flag
   auto assign_step = [&](int t, const int* gate) -> kmx_status {
     KMX_TRY(run_prep_centers(ctx, C_inout, k, d, prec));
@@ -497,6 +504,17 @@ static kmx_status lloyd_routed_impl(kmx_ctx* ctx, kmx_router* r, const float* X,
         KMX_HIP(ctx, launch_bounds_test(ctx->stream, n, lab, bo, P<float>(ctx->drift),
                                         P<DriftStat>(ctx->dstat), k, P<int>(ctx->bl_rows),
                                         P<FlagEntry>(ctx->flags), st, gate, ctx->num_cus));
+      }
+      if (r) {
+        Timed tm(ctx, T_ROUTER);
+        KMX_HIP(ctx, launch_need_proposals(ctx->stream, P<int>(ctx->bl_rows), &st->bound_fail, n,
+                                           P<uint8_t>(ctx->prop_have), P<int>(ctx->prop_rows),
+                                           &st->need_rows, gate, ctx->num_cus));
+        KMX_HIP(ctx, launch_router_fwd(ctx->stream, P<uint16_t>(ctx->xq), dp, n, d,
+                                       P<uint16_t>(r->W1a), P<float>(r->b1),
+                                       P<uint16_t>(r->W2a), P<float>(r->b2p), r->kpad,
+                                       P<uint32_t>(ctx->keys), gate, ctx->num_cus,
+                                       P<int>(ctx->prop_rows), &st->need_rows));
       }
       {
         Timed tm(ctx, T_CERT);

@@ -22,7 +22,7 @@ FP32, BF16, FP8 = 0, 1, 2
 _PREC = {"fp32": FP32, "bf16": BF16, "fp8": FP8, FP32: FP32, BF16: BF16, FP8: FP8}
 
 TIMING_CLASSES = ("prep", "assign", "recheck", "sort", "reduce", "finalize", "seed", "other",
-                  "router", "certificate", "train", "project", "bounds")
+                  "router", "certificate", "train", "project", "bounds", "short_recheck")
 ROUTER_HIDDEN = 256
 ROUTER_M = 16
 
@@ -72,6 +72,7 @@ def lib():
         "kmx_mfma_probe": [_vp, ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _vp, _i32],
         "kmx_assign_stats": [_vp, _vp, _vp, _vp],
         "kmx_update_stats": [_vp, _vp, _vp],
+        "kmx_run_stats": [_vp, _vp, _vp],
         "kmx_seed_stats": [_vp, _vp],
         "kmx_timing_read": [_vp, ctypes.c_int, _vp, _vp],
         "kmx_lloyd_batched": [_vp, _vp, _i32, _i32, ctypes.c_int, _vp],
@@ -277,6 +278,13 @@ class Context:
         _check(lib().kmx_assign_stats(self._p, ctypes.byref(a), ctypes.byref(b),
                                       ctypes.byref(c)), self._p)
         return int(a.value), int(b.value), int(c.value)
+
+    def run_stats(self):
+        """(listed_total, full_total): short re-check entries and every-center
+        rows summed over the assignments of the most recent Lloyd run."""
+        a, b = ctypes.c_int64(0), ctypes.c_int64(0)
+        _check(lib().kmx_run_stats(self._p, ctypes.byref(a), ctypes.byref(b)), self._p)
+        return int(a.value), int(b.value)
 
     def update_stats(self):
         """(changed, delta) of the most recent update of a Lloyd run: the rows

@@ -929,11 +929,11 @@ def main():
     add("previous_labels", lambda: ctx.lloyd_routed(X, Cw, S, router=None, prec="bf16"),
         "previous label + certificate, BF16 GEMM for the other rows", False, "bf16")
     ktb = add("full_bf16", lambda: ctx.lloyd(X, Cw, S, prec="bf16"),
-              "BF16 MFMA GEMM with fused top-4, FP32 GEMM pass and exact re-check of undecided "
-              "rows", False, "bf16")
+              "BF16 MFMA GEMM with fused top-4, split-BF16 GEMM pass and exact re-check of "
+              "undecided rows", False, "bf16")
     kt8 = add("full_fp8", lambda: ctx.lloyd(X, Cw, S, prec="fp8"),
-              "FP8 E4M3 MFMA GEMM (per-row scales) with fused top-3, BF16 then FP32 GEMM passes "
-              "and exact re-check of undecided rows", False, "fp8e4m3")
+              "FP8 E4M3 MFMA GEMM (per-row scales) with fused top-3, BF16 then split-BF16 GEMM "
+              "passes and exact re-check of undecided rows", False, "fp8e4m3")
     if "full_fp8" in paths:
         paths["full_fp8"]["final_listed_via_fp32_all"] = list(ctx.assign_stats())
     for prec in ("bf16", "fp8"):     # the first capture on a context pays one-off costs

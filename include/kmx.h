@@ -120,8 +120,8 @@ kmx_status kmx_seed_stats(kmx_ctx* ctx, int64_t* rows_read);
  *             k == 1); for rows wider than 1024, the second smallest plain
  *             FP32 distance.
  *   n_flagged host, nullable: rows the first GEMM pass could not decide, i.e.
- *             rows that went to the exact re-check or to the FP32 GEMM pass
- *             (synchronizes).
+ *             rows that went to the exact re-check or to a later GEMM pass
+ *             (BF16 and FP8: the cascade's split-BF16 pass; synchronizes).
  */
 kmx_status kmx_assign(kmx_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t ldx,
                       const float* C, int32_t k, kmx_prec prec,
@@ -243,8 +243,10 @@ kmx_status kmx_range_basis(kmx_ctx* ctx, const float* A, int64_t n, int32_t d, i
 /* Re-check counts of the most recent assignment on ctx (kmx_assign, kmx_cost,
  * or the final assignment of kmx_lloyd); host outputs, each nullable:
  *   listed   rows on the exact re-check list (pairs and full rows),
- *   fp32     rows the BF16 GEMM passed to the FP32 GEMM because more than
- *            three centers lay within its error bound (with KMX_FP8E4M3 the
+ *   fp32     rows the BF16 GEMM passed to the cascade's last GEMM pass
+ *            (FP32 values split into two BF16 parts each, three BF16 products
+ *            per coordinate) because more than three centers lay within its
+ *            error bound (with KMX_FP8E4M3 the
  *            FP8 pass first hands the rows with more than three centers
  *            inside its bound to the BF16 pass); 0 when there were at most
  *            4096 such rows and k d >= 65536, which then go to the

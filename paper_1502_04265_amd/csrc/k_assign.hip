@@ -9,7 +9,15 @@
 //   BF16: the accumulator starts at O - h_j (rounded to FP32) and the MFMAs
 //     add x~.c~_j, so it ends at t_j; O is one offset per assignment (max row
 //     norm times max center norm plus max h).
-//   FP32: t_j = (acc - h_j) + o_x with a per-row offset o_x, clamped at 0.
+//   FP32: the score is the float acc - h_j itself (no offset), and the lane
+//     keeps the three best scores with the indices of the first two.
+//   Split BF16 (the last pass of the BF16 and FP8 cascades): every FP32 value
+//     v is split into hi = bf16(v) and lo = bf16(v - hi), and the MFMAs form
+//     x_hi.c_hi in one accumulator and x_hi.c_lo + x_lo.c_hi in a second; the
+//     score is (acc1 + acc2) - h_j, ranked as for FP32.  The dropped part
+//     x_lo.c_lo + (remainders of both splits) is below 3.02 2^-16 sum |x_i c_i|
+//     (each split leaves at most 2^-16 |v|), and the BF16 matrix instructions
+//     run about five times the FP32 ones' rate.
 //   FP8 (E4M3, per-row power-of-two scales 2^e_x, one scale 2^e_c for all
 //     centers): the scaled MFMA applies 2^(e_x + e_c) to each product, so the
 //     accumulator holds x~.c~_j in the units of x; it starts at O - h_j.
@@ -25,10 +33,10 @@
 // center is the exact argmin.  Otherwise the row is flagged: the centers whose
 // score lies within 2E of the top can win; when they are among the listed two
 // (BF16: three) the short re-check compares them.  Otherwise the row needs
-// every center: the BF16 pass sends it to the FP32 pass (same kernel, FP32
-// operands, list of rows), whose much tighter bound leaves it a short
-// re-check in all but exceptional cases; rows still open after the FP32 pass
-// are re-checked against every center.  The re-check decides with plain FP32
+// every center: the BF16 pass sends it to the split-BF16 pass (same kernel,
+// list of rows), whose much tighter bound leaves it a short re-check in all
+// but exceptional cases; rows still open after that pass are re-checked
+// against every center.  The re-check decides with plain FP32
 // direct differences where their error bound allows and otherwise with
 // error-free transformations (double-float accumulation), so labels agree
 // with exact arithmetic except on ties closer than about 1e-13 relative.
@@ -42,7 +50,7 @@
 // published accumulation rule of the instruction backs these constants;
 // kmx_mfma_probe lets a test check them on the device at hand.
 //
-// Layout.  MFMA 16x16x32 BF16, 16x16x128 FP8 or 16x16x4 FP32: A = 16 centers
+// Layout.  MFMA 16x16x32 BF16 (also split BF16), 16x16x128 FP8 or 16x16x4 FP32: A = 16 centers
 // x K (from LDS), B = K x 16 points (registers, loaded once per block of
 // points), D[center][point]: lane l holds point l%16 and centers 4(l/16)+i.
 // Each lane reads 16 (FP8: 32) contiguous bytes of a row per "unit" (8 BF16,
@@ -203,7 +211,8 @@ struct AssignArgs {
 template <int MODE, int NKU, int NCG, int BN, int WAVES>
 struct AssignShape {
   static constexpr int UB = (MODE == 2) ? 32 : 16;     // bytes per lane and unit
-  static constexpr int ROWB = NKU * UB * 4;            // bytes of one center row
+  // bytes of one center row (split BF16: NKU units of high parts, then NKU of low parts)
+  static constexpr int ROWB = (MODE == 3) ? 2 * NKU * 64 : NKU * UB * 4;
   static constexpr int UROW = ROWB / 16 + 1;           // 16-byte units per LDS row
   static constexpr int CHUNKS = (BN * UROW + 63) / 64; // 1 KB direct-to-LDS copies per tile
   static constexpr int BUFB = CHUNKS * 1024;           // bytes of one tile buffer
@@ -220,12 +229,14 @@ __device__ __forceinline__ void assign_block(const AssignArgs& A, int64_t blk,
                                              unsigned long long* wbase) {
   constexpr bool BF16 = (MODE == 1);
   constexpr bool F8 = (MODE == 2);
-  constexpr bool PK = (MODE != 0);       // packed keys (BF16, FP8)
+  constexpr bool SPLIT = (MODE == 3);
+  constexpr bool PK = BF16 || F8;        // packed keys (BF16, FP8)
   // FP8: each lane keeps its three best keys during the tile loop (a vector
   // operation less per key); the decision then treats a row whose lane-wise
   // third best lies inside the bound as having more than three candidates
   constexpr bool T3 = F8;
-  constexpr int NF = F8 ? 2 : 1;         // 16-byte fragments per lane and unit
+  // 16-byte fragments per lane and unit (split BF16: the high, then the low parts)
+  constexpr int NF = (F8 || SPLIT) ? 2 : 1;
   constexpr int NT = WAVES * 64;
   // SUBT sub-tiles per LDS tile: the keys of each BN / SUBT centers are
   // inserted before the next ones are computed, so the accumulators stay
@@ -276,6 +287,41 @@ __device__ __forceinline__ void assign_block(const AssignArgs& A, int64_t blk,
       const int64_t rl = pv ? r : 0;
 #pragma unroll
       for (int ku = 0; ku < NKU * NF; ++ku) {
+        if constexpr (SPLIT) {
+          // values (ku / 2) * 32 + grp * 8 .. + 7 of the FP32 row, split into
+          // the high parts (fragment ku) and the low parts (fragment ku + 1)
+          if (ku & 1) continue;
+          const int e0 = (ku >> 1) * 32 + grp * 8;
+          float xv[8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) xv[q] = 0.0f;
+          if (pv) {
+            const float* src = (const float*)A.Xsrc + r * A.xs + e0;
+            if (A.vec_ok && e0 + 8 <= A.d) {
+              const float4 a = *(const float4*)src;
+              const float4 b = *(const float4*)(src + 4);
+              xv[0] = a.x; xv[1] = a.y; xv[2] = a.z; xv[3] = a.w;
+              xv[4] = b.x; xv[5] = b.y; xv[6] = b.z; xv[7] = b.w;
+            } else {
+#pragma unroll
+              for (int q = 0; q < 8; ++q)
+                if (e0 + q < A.d) xv[q] = src[q];
+            }
+          }
+          u32x4_t hv, lv;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const uint16_t h0 = f32_to_bf16_rne(xv[2 * q]);
+            const uint16_t h1 = f32_to_bf16_rne(xv[2 * q + 1]);
+            const uint16_t l0 = f32_to_bf16_rne(xv[2 * q] - bf16_to_f32(h0));
+            const uint16_t l1 = f32_to_bf16_rne(xv[2 * q + 1] - bf16_to_f32(h1));
+            hv[q] = (unsigned)h0 | ((unsigned)h1 << 16);
+            lv[q] = (unsigned)l0 | ((unsigned)l1 << 16);
+          }
+          xf[cg][ku] = hv;
+          xf[cg][ku + 1] = lv;
+          continue;
+        }
         u32x4_t v = {0u, 0u, 0u, 0u};
         if (F8) {
           v = *(const u32x4_t*)((const uint8_t*)A.Xsrc + rl * A.xs + (ku >> 1) * 128 + grp * 32 +
@@ -390,6 +436,7 @@ __device__ __forceinline__ void assign_block(const AssignArgs& A, int64_t blk,
       const unsigned pm = (t > 0) ? 0xFFFFFFFFu : 0u;
 
       f32x4_t acc[NCG][RB];
+      f32x4_t accx[NCG][RB];   // split BF16: x_hi.c_lo + x_lo.c_hi
 #pragma unroll
       for (int st = 0; st < SUBT; ++st) {
 #pragma unroll
@@ -397,7 +444,10 @@ __device__ __forceinline__ void assign_block(const AssignArgs& A, int64_t blk,
         f32x4_t a0 = {0.f, 0.f, 0.f, 0.f};
         if (PK) a0 = *(const f32x4_t*)(&hsh[buf * BN + st * BNS + rb * 16 + grp * 4]);
 #pragma unroll
-        for (int cg = 0; cg < NCG; ++cg) acc[cg][rb] = a0;
+        for (int cg = 0; cg < NCG; ++cg) {
+          acc[cg][rb] = a0;
+          accx[cg][rb] = (f32x4_t){0.f, 0.f, 0.f, 0.f};
+        }
       }
 
       if constexpr (F8) {
@@ -433,6 +483,45 @@ __device__ __forceinline__ void assign_block(const AssignArgs& A, int64_t blk,
 #pragma unroll
             for (int sidx = 0; sidx < NSC; ++sidx)
               if (sidx * NKU / NSC == ku) insert_prev(sidx, ibase_p, pm);
+          }
+        }
+      } else if constexpr (SPLIT) {
+        // high and low center parts PF units ahead, as for BF16 below
+        constexpr int NB = PF + 1;
+        constexpr int LOFF = NKU * 64;   // bytes from a row's high parts to its low parts
+        u32x4_t afh[NB][RB], afl[NB][RB];
+        const unsigned char* abase = &lds[buf * BUFB + (st * BNS + prow) * PITCH + grp * 16];
+#pragma unroll
+        for (int q = 0; q < PF; ++q)
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb)
+            if (q < NKU) {
+              afh[q][rb] = *(const u32x4_t*)(abase + rb * 16 * PITCH + q * 64);
+              afl[q][rb] = *(const u32x4_t*)(abase + rb * 16 * PITCH + LOFF + q * 64);
+            }
+#pragma unroll
+        for (int ku = 0; ku < NKU; ++ku) {
+          if (ku + PF < NKU) {
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) {
+              afh[(ku + PF) % NB][rb] = *(const u32x4_t*)(abase + rb * 16 * PITCH + (ku + PF) * 64);
+              afl[(ku + PF) % NB][rb] =
+                  *(const u32x4_t*)(abase + rb * 16 * PITCH + LOFF + (ku + PF) * 64);
+            }
+          }
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb) {
+            const bf16x8_t ah = __builtin_bit_cast(bf16x8_t, afh[ku % NB][rb]);
+            const bf16x8_t al = __builtin_bit_cast(bf16x8_t, afl[ku % NB][rb]);
+#pragma unroll
+            for (int cg = 0; cg < NCG; ++cg) {
+              const bf16x8_t xh = __builtin_bit_cast(bf16x8_t, xf[cg][2 * ku]);
+              const bf16x8_t xl = __builtin_bit_cast(bf16x8_t, xf[cg][2 * ku + 1]);
+              acc[cg][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, xh, acc[cg][rb], 0, 0, 0);
+              accx[cg][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, xl, accx[cg][rb], 0, 0, 0);
+              accx[cg][rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, xh, accx[cg][rb], 0, 0, 0);
+            }
           }
         }
       } else {
@@ -501,7 +590,8 @@ __device__ __forceinline__ void assign_block(const AssignArgs& A, int64_t blk,
             const int j = t * BN + st * BNS + rb * 16 + grp * 4 + i;
 #pragma unroll
             for (int cg = 0; cg < NCG; ++cg) {
-              const float tt = acc[cg][rb][i] - hv[i];
+              const float tt =
+                  (SPLIT ? (acc[cg][rb][i] + accx[cg][rb][i]) : acc[cg][rb][i]) - hv[i];
               const bool c1 = tt > f1[cg], c2 = tt > f2[cg], c3 = tt > f3[cg];
               f3[cg] = c2 ? f2[cg] : (c3 ? tt : f3[cg]);
               f2[cg] = c1 ? f1[cg] : (c2 ? tt : f2[cg]);
@@ -629,7 +719,21 @@ __device__ __forceinline__ void assign_block(const AssignArgs& A, int64_t blk,
           if (has4) t4 = __uint_as_float(v4[cg] & hi);
         } else {
           off = 0.0f;
-          E = (gam + u) * rw.nx * cnm + 1.5f * u * cnm * cnm;
+          if constexpr (SPLIT) {
+            // x_hi.c_hi: dp + 1 accumulation steps over at most (1 + 2^-8)^2
+            // sum |x_i c_i|; the cross terms: 2 dp + 1 steps over at most
+            // 2^-7 (1 + 2^-8)^2 of it; the dropped part (3.02 2^-16 of it);
+            // the sum of the two accumulators and the subtraction of h_j (u
+            // each), the rounding of h_j; an absolute term for results and
+            // split parts below the smallest normal float (flushed or not)
+            const float Kx = (float)(2 * A.dp + 1);
+            const float gamx = Kx * ua / (1.0f - Kx * ua);
+            E = (1.008f * gam + 0.008f * gamx + 3.1f * 1.52587890625e-5f + 2.04f * u) * rw.nx * cnm +
+                1.5f * u * cnm * cnm +
+                0x1p-120f * (sqrtf((float)A.dp) * (rw.nx + cnm) + (float)A.dp);
+          } else {
+            E = (gam + u) * rw.nx * cnm + 1.5f * u * cnm * cnm;
+          }
           t1 = f1[cg];
           i1 = min(max(j1[cg], 0), A.k - 1);
           has2 = f2[cg] > -__builtin_inff();
@@ -772,7 +876,7 @@ __device__ __forceinline__ void assign_block(const AssignArgs& A, int64_t blk,
   }
 }
 
-// MODE: 0 FP32, 1 BF16, 2 FP8 E4M3.  Persistent over the blocks of points.
+// MODE: 0 FP32, 1 BF16, 2 FP8 E4M3, 3 split BF16.  Persistent over the blocks of points.
 template <int MODE, int NKU, int NCG, int BN, int WAVES, int PF = 1, bool EP = false,
           int SUBT = 1>
 __global__ __launch_bounds__(WAVES * 64) void assign_kernel(AssignArgs A,
@@ -795,12 +899,13 @@ __global__ __launch_bounds__(WAVES * 64) void assign_kernel(AssignArgs A,
 // BF16 rows hold d values and zero padding: dp = 32*NKU with NKU the first
 // entry of kBf16Units covering d.  FP8 rows hold d values and zero padding:
 // dp = 128*NKU bytes.  FP32 rows are padded to 16*NKU, NKU a power of two.
+// Split-BF16 rows are padded like BF16 rows (dp = 32*NKU values per part).
 // ---------------------------------------------------------------------------
 static const int kBf16Units[] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32};
 static const int kF8Units[] = {1, 2, 3, 4, 6, 8};
 
 static int units_for(int prec, int d) {
-  if (prec == KMX_BF16) {
+  if (prec == KMX_BF16 || prec == kSplitBf16) {
     const int need = (d + 31) / 32;
     for (int u : kBf16Units)
       if (u >= need) return u;
@@ -821,7 +926,7 @@ static int units_for(int prec, int d) {
 int assign_dpad(int prec, int d) {
   const int u = units_for(prec, d);
   if (u < 0) return -1;
-  return u * ((prec == KMX_BF16) ? 32 : (prec == KMX_FP8E4M3) ? 128 : 16);
+  return u * ((prec == KMX_BF16 || prec == kSplitBf16) ? 32 : (prec == KMX_FP8E4M3) ? 128 : 16);
 }
 
 // FP8 rows of 4 units (d <= 512) with many centers: LDS tiles of 64 or 128
@@ -835,6 +940,7 @@ int assign_tile_n(int prec, int d, int k) {
   if (prec == KMX_FP8E4M3)
     return nku <= 3 ? 64 : (nku == 4 ? f8_tile4(k) : (nku <= 6 ? 32 : 16));
   if (prec == KMX_BF16) return (nku <= 3 || nku == 6 || nku == 8) ? 64 : 32;
+  if (prec == kSplitBf16) return nku <= 16 ? 32 : 16;
   if (nku <= 4) return 64;
   if (nku <= 32) return 32;
   return 16;
@@ -943,6 +1049,28 @@ hipError_t launch_assign(hipStream_t s, int prec, const float* X, int64_t ldx, c
 #undef KMX_A
   }
   const int vec_ok = ((((uintptr_t)X) & 15) == 0) && (ldx % 4 == 0);
+  if (prec == kSplitBf16) {
+    // point fragments (high + low parts) and two accumulators per center
+    // block: fewer point groups per wave than BF16 at the same width
+#define KMX_A(NKU_, NCG_, BN_, W_)                                                               \
+  return run_assign<3, NKU_, NCG_, BN_, W_>(s, X, ldx, vec_ok, nullptr, n, rows, row_count, d, \
+                                            dp, rs, Cq, ch, k, kpad, ib, cs, label, d1, d2,     \
+                                            flags, full_rows, full_ctr, cascade_all, brute, st, gate, num_cus, bo)
+    switch (nku) {
+      case 1: KMX_A(1, 4, 32, 8);
+      case 2: KMX_A(2, 4, 32, 8);
+      case 3: KMX_A(3, 2, 32, 8);
+      case 4: KMX_A(4, 2, 32, 8);
+      case 6: KMX_A(6, 2, 32, 8);
+      case 8: KMX_A(8, 1, 32, 8);
+      case 12: KMX_A(12, 1, 32, 8);
+      case 16: KMX_A(16, 1, 32, 8);
+      case 24: KMX_A(24, 1, 16, 4);
+      case 32: KMX_A(32, 1, 16, 4);
+      default: return hipErrorInvalidValue;
+    }
+#undef KMX_A
+  }
 #define KMX_A(NKU_, NCG_, BN_, W_)                                                               \
   return run_assign<0, NKU_, NCG_, BN_, W_>(s, X, ldx, vec_ok, nullptr, n, rows, row_count, d, \
                                             dp, rs, Cq, ch, k, kpad, ib, cs, label, d1, d2,     \

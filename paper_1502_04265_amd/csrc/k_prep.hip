@@ -88,9 +88,11 @@ hipError_t launch_prep_rows(hipStream_t s, const float* X, int64_t n, int d, int
 
 // Pass A, one wave per (padded) center.  prec 0 (FP32): copy of c_j into a
 // row of dp floats, ch[j] = ||c_j||^2 / 2 (+inf for padding rows, whose score
-// is then clamped away).  prec 1 (BF16): c~_j (round to nearest even) in
-// columns [0, d), zeros elsewhere; hd[j] = ||c_j||^2 / 2 in FP64.  Maxima of
-// the norms go to cs.
+// is then never selected).  prec 1 (BF16): c~_j (round to nearest even) in
+// columns [0, d), zeros elsewhere; hd[j] = ||c_j||^2 / 2 in FP64.
+// prec kSplitBf16: a row of 2 dp BF16 values, the high parts hi = bf16(c)
+// then the low parts bf16(c - hi) (c - hi is exact in FP32); ch as for FP32.
+// Maxima of the norms go to cs.
 
 // Each wave takes padded centers wave_id, wave_id + total_waves, ...; the
 // norm maxima are reduced over the block and reach cs with one atomic per
@@ -119,6 +121,12 @@ __global__ __launch_bounds__(256) void prep_centers_kernel(const float* __restri
         const double qd = (double)bf16_to_f32(b);
         q2 += qd * qd;
         r2 += (vd - qd) * (vd - qd);
+      } else if (prec == kSplitBf16) {
+        // high part, then the low part of the exact remainder v - hi
+        const uint16_t h = f32_to_bf16_rne(v);
+        const uint16_t l = f32_to_bf16_rne(v - bf16_to_f32(h));
+        ((uint16_t*)Cq)[(int64_t)j * 2 * dp + c] = h;
+        ((uint16_t*)Cq)[(int64_t)j * 2 * dp + dp + c] = l;
       } else {
         ((float*)Cq)[(int64_t)j * dp + c] = v;
       }

@@ -233,14 +233,17 @@ kmx_status run_prep_centers(kmx_ctx* ctx, const float* C, int k, int d, int prec
     KMX_HIP(ctx, launch_reset_small(ctx->stream, cs, cs32, cs8, st, 0));
     return KMX_OK;
   }
-  const int dp32 = assign_dpad(KMX_FP32, d);
-  const int bn32 = assign_tile_n(KMX_FP32, d, k);
+  // the FP32 path's operands, or those of the split-BF16 pass that ends the
+  // BF16 and FP8 cascades (2 dp BF16 values per row: the same bytes)
+  const int p32 = (prec == KMX_FP32) ? KMX_FP32 : kSplitBf16;
+  const int dp32 = assign_dpad(p32, d);
+  const int bn32 = assign_tile_n(p32, d, k);
   const int kpad32 = (k + bn32 - 1) / bn32 * bn32;
   KMX_TRY(grow(ctx, ctx->cq32, (size_t)kpad32 * dp32 * sizeof(float)));
   KMX_TRY(grow(ctx, ctx->ch32, (size_t)kpad32 * sizeof(float)));
   Timed tm(ctx, T_PREP);
   KMX_HIP(ctx, launch_reset_small(ctx->stream, cs, cs32, cs8, st, 0));
-  KMX_HIP(ctx, launch_prep_centers(ctx->stream, C, k, d, kpad32, dp32, KMX_FP32, ctx->cq32.p,
+  KMX_HIP(ctx, launch_prep_centers(ctx->stream, C, k, d, kpad32, dp32, p32, ctx->cq32.p,
                                    P<float>(ctx->ch32), nullptr, cs32, nullptr));
   if (prec == KMX_BF16 || prec == KMX_FP8E4M3) {   // FP8 cascades into BF16
     const int dp = assign_dpad(KMX_BF16, d);
@@ -268,10 +271,11 @@ kmx_status run_prep_centers(kmx_ctx* ctx, const float* C, int k, int d, int prec
 }
 
 // GEMM passes: FP8 (rows with more than three centers inside its bound to
-// the BF16 pass), BF16 (likewise to the FP32 pass; a short list with long
-// centers, see kShortList, goes to the every-center re-check instead), FP32 (rows
-// still open to the every-center re-check); rows with two or three candidates
-// inside a pass's bound go to the short re-check.  gate: skip when *gate != 0.
+// the BF16 pass), BF16 (likewise to the split-BF16 pass; a short list with
+// long centers, see kShortList, goes to the every-center re-check instead),
+// split BF16 (rows still open to the every-center re-check); rows with two or
+// three candidates inside a pass's bound go to the short re-check.  With
+// KMX_FP32 one FP32 pass.  gate: skip when *gate != 0.
 kmx_status run_assign_gemm(kmx_ctx* ctx, const float* X, int64_t n, int d, int64_t ldx,
                            const float* C, int k, int prec, int32_t* label, float* d1,
                            float* d2, const int* rows, const unsigned long long* row_count,
@@ -292,8 +296,11 @@ kmx_status run_assign_gemm(kmx_ctx* ctx, const float* X, int64_t n, int d, int64
   CenterStats* cs = P<CenterStats>(ctx->cstats);
   CenterStats* cs32 = P<CenterStats>(ctx->cstats32);
   CenterStats* cs8 = P<CenterStats>(ctx->cstats8);
-  const int dp32 = assign_dpad(KMX_FP32, d);
-  const int bn32 = assign_tile_n(KMX_FP32, d, k);
+  // operands of the FP32 path, or of the split-BF16 pass of the cascades
+  // (prepared by run_prep_centers for the same precision)
+  const int p32 = (prec == KMX_FP32) ? KMX_FP32 : kSplitBf16;
+  const int dp32 = assign_dpad(p32, d);
+  const int bn32 = assign_tile_n(p32, d, k);
   const int kpad32 = (k + bn32 - 1) / bn32 * bn32;
   const RowStats* rs = P<RowStats>(ctx->rowstats);
   FlagEntry* flags = P<FlagEntry>(ctx->flags);
@@ -339,7 +346,7 @@ kmx_status run_assign_gemm(kmx_ctx* ctx, const float* X, int64_t n, int d, int64
     {
       Timed tm(ctx, T_RECHECK);
       KMX_HIP(ctx, launch_route_small(ctx->stream, ctr16, next16, brute, st, k, d, gate));
-      KMX_HIP(ctx, launch_assign(ctx->stream, KMX_FP32, X, ldx, nullptr, nullptr, n, next16,
+      KMX_HIP(ctx, launch_assign(ctx->stream, kSplitBf16, X, ldx, nullptr, nullptr, n, next16,
                                  ctr16, d, dp32, rs, ctx->cq32.p, P<float>(ctx->ch32), k, kpad32,
                                  cs32, label, d1, d2, flags, nullptr, nullptr, 0, brute, st, gate,
                                  ctx->num_cus, bo));

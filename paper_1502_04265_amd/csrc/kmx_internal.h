@@ -269,6 +269,11 @@ hipError_t launch_reset_small(hipStream_t s, CenterStats* cs, CenterStats* cs2, 
                               LoopState* st, int reset_iter);
 
 // assign
+// Operand code of the last GEMM pass of the BF16 and FP8 cascades (besides
+// KMX_FP32, KMX_BF16, KMX_FP8E4M3): FP32 rows and centers each split into two
+// BF16 parts, x = x_hi + x_lo, and three BF16 products per coordinate (see
+// k_assign.hip).  Center rows hold dp high parts, then dp low parts.
+constexpr int kSplitBf16 = 3;
 int assign_tile_n(int prec, int d, int k);   // centers per tile (kpad granularity)
 int assign_dpad(int prec, int d);     // padded row length of the GEMM operands
 hipError_t launch_assign(hipStream_t s, int prec, const float* X, int64_t ldx,

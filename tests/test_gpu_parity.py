@@ -148,6 +148,33 @@ def test_assign_multiway_near_ties(ctx, m, n, d, nfar):
             assert (via_fp32 == 0) if routed else (via_fp32 > 0.9 * n), (via_fp32, n)
 
 
+@pytest.mark.parametrize("n,d,nfar,a", [(6000, 64, 12, 0.02), (5000, 200, 30, 0.08),
+                                         (9000, 512, 60, 0.25)])
+def test_assign_split_bf16_pass_decides(ctx, n, d, nfar, a):
+    # Four centers of a regular simplex around `base` (distance 3), points
+    # shifted toward the first one by a: the score gap to the other three is
+    # 3a, well inside the BF16 pass's bound (about 2^-8 ||x|| max ||c|| and
+    # more), so the BF16 pass hands every row on, but 3 to 4 times twice the
+    # bound of the split-BF16 pass (about 1e-4 ||x|| max ||c|| at d = 512),
+    # which decides them: the every-center list stays empty and the labels
+    # equal the oracle's.  Far decoys fill out k.
+    say(f"assign split-BF16 pass, n={n} d={d} k={4 + nfar}")
+    rng = np.random.default_rng(77 + d)
+    base = rng.normal(0, 0.5, d)
+    dirs = np.linalg.qr(rng.normal(size=(d, 4)))[0].T
+    C_near = base + 3.0 * dirs
+    C_far = base + 4.0 + rng.normal(size=(nfar, d))
+    C = np.vstack([C_far[:3], C_near, C_far[3:]]).astype(np.float32)
+    X = (base + a * dirs[0] + 1e-4 * rng.normal(size=(n, d))).astype(np.float32)
+    for prec in ("bf16", "fp8"):
+        lab, _, _, nf = ctx.assign(_dev(X), _dev(C), prec=prec)
+        lab_o, _, _ = _check_labels(lab.cpu().numpy(), X, C, f"split pass {prec}")
+        assert (lab_o == 3).all()
+        listed, via_split, full = ctx.assign_stats()
+        say(f"  {prec}: flagged {nf}, listed {listed}, split pass {via_split}, every center {full}")
+        assert via_split == n and full == 0, (listed, via_split, full)
+
+
 # ---------------------------------------------------------------------------
 # update and cost
 # ---------------------------------------------------------------------------

@@ -426,6 +426,18 @@ kmx_status kmx_lloyd_routed(kmx_ctx* ctx, kmx_router* r, const float* X, int64_t
                             int32_t max_iter, double tol, kmx_prec prec, int32_t* label_out,
                             double* cost_hist, int32_t* iters_done, int64_t* gemm_rows);
 
+/* Lower bounds of the distances between centers, the table the certificate
+ * of kmx_lloyd_routed and kmx_lloyd_bounded uses (Elkan's test: a center c
+ * cannot be closer to x than c_b when ||c_b - c|| >= 2 ||x - c_b||).
+ *   C      device, k x d float32, rows contiguous.
+ *   D_out  device, k x k float32: D_out[b k + c] <= ||c_b - c_c|| (+inf for
+ *          b == c), from the Gram form ||c_b||^2 + ||c_c||^2 - 2 c_b.c_c with
+ *          the dot products on the FP32 matrix cores and their error bound
+ *          subtracted (loose only where the distance is tiny against the
+ *          norms).
+ * 1 <= k <= 4096, d >= 1; stream-ordered, asynchronous. */
+kmx_status kmx_center_bounds(kmx_ctx* ctx, const float* C, int32_t k, int32_t d, float* D_out);
+
 /* Lloyd's algorithm as kmx_lloyd (same arguments, results and stopping rule)
  * with bounds carried across iterations (Hamerly's form of Elkan's
  * triangle-inequality filtering; not in the paper, an exact accelerator of the

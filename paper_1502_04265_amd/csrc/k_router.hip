@@ -402,60 +402,116 @@ hipError_t launch_router_decode(hipStream_t s, const uint32_t* keys, int64_t cou
 }
 
 // ---------------------------------------------------------------------------
-// Center-distance table.  Pass 1 (tiles of 32 x 32 centers, 2 x 2 per
-// thread): D[b][c] = a lower bound of ||c_b - c_c||.  The FP32 sum of d
-// squared direct differences has relative error below (d + 3) u, u = 2^-24,
-// so sqrt(s (1 - 2 (d + 8) u)) (1 - 4 u) is a lower bound.  Pass 2 (one
-// workgroup per center): the kNbrL nearest other centers sorted by that
-// bound (bitonic sort of (bound, index) keys in LDS), and the bound of the
-// next one (+inf when none).
+// Center-distance table.  Pass 1 on the matrix cores: D[b][c] = a lower bound
+// of ||c_b - c_c|| from the Gram form ||c_b||^2 + ||c_c||^2 - 2 g, g = c_b . c_c.
+// A workgroup takes a 32 x 32 tile of center pairs (tiles on and above the
+// diagonal; an off-diagonal tile also writes its transpose), stages 128
+// columns of both center blocks at a time in LDS, and its four waves form g
+// for 16 x 16 pairs each with FP32 MFMAs (16x16x4).  The accumulated g is
+// within gamma ||c_b|| ||c_c|| of the exact product, gamma = K 2^-23 / (1 -
+// K 2^-23) with K = (columns rounded up to 128) + 1 (every accumulation step
+// faithfully rounded, as for the assignment's FP32 pass); the squared norms
+// are FP64 sums of the staged FP32 values (relative error below 2^-40 for any
+// d this path takes).  So sqrt(||c_b||^2 + ||c_c||^2 - 2 g - 2 gamma ||c_b||
+// ||c_c||), less a 2^-38 relative slack for the FP64 steps and rounded down,
+// is a lower bound.  Pass 2 (one workgroup per center): the kNbrL nearest
+// other centers sorted by that bound (bitonic sort of (bound, index) keys in
+// LDS), and the bound of the next one (+inf when none).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void center_dist_kernel(const float* __restrict__ C, int k, int d,
+constexpr int kGramT = 32;    // centers per tile side
+constexpr int kGramK = 128;   // staged columns
+constexpr int kGramP = kGramK + 4;   // padded LDS row (conflict-free column reads)
+
+__global__ __launch_bounds__(256) void center_gram_kernel(const float* __restrict__ C, int k, int d,
                                                           float* __restrict__ D,
                                                           const int* __restrict__ gate) {
   if (gate && *gate) return;
-  // tiles of 32 x 32 centers (many workgroups per CU hide the load latency),
-  // K-major in LDS: thread (tx, ty) owns rows 2 ty, 2 ty + 1 of the first
-  // tile and 2 tx, 2 tx + 1 of the second, one float2 read each per k
-  __shared__ __attribute__((aligned(16))) float Bt[32][32];
-  __shared__ __attribute__((aligned(16))) float Ct[32][32];
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-  const int b0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
-  float acc[2][2] = {{0.0f, 0.0f}, {0.0f, 0.0f}};
-  for (int k0 = 0; k0 < d; k0 += 32) {
-    for (int e = tid; e < 32 * 32; e += 256) {
-      const int rr = e >> 5, kk = e & 31, kc = k0 + kk;
-      Bt[kk][rr] = (b0 + rr < k && kc < d) ? C[(int64_t)(b0 + rr) * d + kc] : 0.0f;
-      Ct[kk][rr] = (c0 + rr < k && kc < d) ? C[(int64_t)(c0 + rr) * d + kc] : 0.0f;
+  const int T = (k + kGramT - 1) / kGramT;
+  int rem = (int)blockIdx.x, bi = 0;   // block -> tile (bi, ci), bi <= ci
+  while (rem >= T - bi) {
+    rem -= T - bi;
+    ++bi;
+  }
+  const int ci = bi + rem;
+  const int b0 = bi * kGramT, c0 = ci * kGramT;
+  __shared__ __attribute__((aligned(16))) float Bs[kGramT * kGramP];
+  __shared__ __attribute__((aligned(16))) float Cs[kGramT * kGramP];
+  __shared__ double nB[kGramT], nC[kGramT];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = (wave >> 1) * 16, wc = (wave & 1) * 16;   // the wave's 16 x 16 pairs
+  const int lr = lane & 15, lk = lane >> 4;
+  // staging: thread t holds row t / 8, columns 16 (t % 8) .. + 15 of the chunk
+  const int sr = tid >> 3, sk = (tid & 7) * 16;
+  const bool vb_row = b0 + sr < k, vc_row = c0 + sr < k;
+  const float* brow = C + (int64_t)(vb_row ? b0 + sr : 0) * d;
+  const float* crow = C + (int64_t)(vc_row ? c0 + sr : 0) * d;
+  const bool vec = ((((uintptr_t)C) & 15) == 0) && (d % 4 == 0);
+  rf32x4_t acc = {0.f, 0.f, 0.f, 0.f};
+  double pb[2] = {0.0, 0.0}, pc[2] = {0.0, 0.0};
+  for (int k0 = 0; k0 < d; k0 += kGramK) {
+    float vb[16], vc[16];
+    if (vec && k0 + sk + 16 <= d) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float4 a = vb_row ? *(const float4*)(brow + k0 + sk + 4 * q) : make_float4(0.f, 0.f, 0.f, 0.f);
+        const float4 c = vc_row ? *(const float4*)(crow + k0 + sk + 4 * q) : make_float4(0.f, 0.f, 0.f, 0.f);
+        vb[4 * q] = a.x; vb[4 * q + 1] = a.y; vb[4 * q + 2] = a.z; vb[4 * q + 3] = a.w;
+        vc[4 * q] = c.x; vc[4 * q + 1] = c.y; vc[4 * q + 2] = c.z; vc[4 * q + 3] = c.w;
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int kc = k0 + sk + e;
+        vb[e] = (vb_row && kc < d) ? brow[kc] : 0.0f;
+        vc[e] = (vc_row && kc < d) ? crow[kc] : 0.0f;
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      Bs[sr * kGramP + sk + e] = vb[e];
+      Cs[sr * kGramP + sk + e] = vc[e];
+      pb[e & 1] = fma((double)vb[e], (double)vb[e], pb[e & 1]);
+      pc[e & 1] = fma((double)vc[e], (double)vc[e], pc[e & 1]);
     }
     __syncthreads();
 #pragma unroll 8
-    for (int kk = 0; kk < 32; ++kk) {
-      const float2 bq = *(const float2*)&Bt[kk][2 * ty];
-      const float2 cq = *(const float2*)&Ct[kk][2 * tx];
-      const float bv[2] = {bq.x, bq.y};
-      const float cv[2] = {cq.x, cq.y};
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          const float df = bv[i] - cv[j];
-          acc[i][j] = __builtin_fmaf(df, df, acc[i][j]);
-        }
+    for (int kk = 0; kk < kGramK; kk += 4) {
+      const float a = Bs[(wr + lr) * kGramP + kk + lk];
+      const float b = Cs[(wc + lr) * kGramP + kk + lk];
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
     }
     __syncthreads();
   }
-  const float u = 5.9604645e-8f;
-  const float shrink = 1.0f - 2.0f * (float)(d + 8) * u;
+  // squared norms: the eight threads of a row (fixed order)
+  double sb = pb[0] + pb[1], sc = pc[0] + pc[1];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int m = 1; m <= 4; m <<= 1) {
+    sb += __shfl_xor(sb, m, 64);
+    sc += __shfl_xor(sc, m, 64);
+  }
+  if ((tid & 7) == 0) {
+    nB[sr] = sb;
+    nC[sr] = sc;
+  }
+  __syncthreads();
+  const int kst = (d + kGramK - 1) / kGramK * kGramK + 1;
+  const double gam = (double)kst * 0x1p-23 / (1.0 - (double)kst * 0x1p-23);
+  // lane l holds g for rows 4 (l / 16) + q and column l % 16 of the wave's block
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int b = b0 + 2 * ty + i, c = c0 + 2 * tx + j;
-      if (b < k && c < k)
-        D[(int64_t)b * k + c] =
-            (b == c) ? __builtin_inff() : sqrtf(fmaxf(acc[i][j] * shrink, 0.0f)) * (1.0f - 4.0f * u);
+  for (int q = 0; q < 4; ++q) {
+    const int rb = wr + 4 * lk + q, rc = wc + lr;
+    const int b = b0 + rb, c = c0 + rc;
+    if (b >= k || c >= k) continue;
+    float v = __builtin_inff();
+    if (b != c) {
+      const double nb = nB[rb], nc = nC[rc];
+      const double cross = sqrt(nb * nc) * (1.0 + 0x1p-40);
+      const double s2 = (nb + nc) * (1.0 - 0x1p-38) - 2.0 * (double)acc[q] - 2.0 * gam * cross;
+      v = dist_down(s2);
     }
+    D[(int64_t)b * k + c] = v;
+    if (bi != ci) D[(int64_t)c * k + b] = v;
+  }
 }
 
 __global__ __launch_bounds__(256) void center_select_kernel(const float* __restrict__ D, int k,
@@ -499,8 +555,8 @@ __global__ __launch_bounds__(256) void center_select_kernel(const float* __restr
 hipError_t launch_center_table(hipStream_t s, const float* C, int k, int d, float* D, int32_t* nbr,
                                float* nbd, const int* gate) {
   if (k > kRouterMaxK) return hipErrorInvalidValue;
-  const unsigned tiles = (unsigned)((k + 31) / 32);
-  hipLaunchKernelGGL(center_dist_kernel, dim3(tiles, tiles), dim3(256), 0, s, C, k, d, D, gate);
+  const unsigned T = (unsigned)((k + kGramT - 1) / kGramT);
+  hipLaunchKernelGGL(center_gram_kernel, dim3(T * (T + 1) / 2), dim3(256), 0, s, C, k, d, D, gate);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   int kp2 = 2;
@@ -518,9 +574,10 @@ hipError_t launch_center_table(hipStream_t s, const float* C, int k, int d, floa
 //          quantization, relative error of the sum below (d/16 + 8) u);
 //   R    = 2 D_ub (1 + 8 u);
 //   m    = number of listed neighbours with lower bound < R.
-// Decision: m = 0 -> label = b; 1 <= m <= 2 with every such neighbour among
-// the candidates -> label = b plus a short re-check entry; otherwise (or the
-// list is exhausted, or no proposal) -> GEMM row list.
+// Decision: m = 0 -> label = b; 1 <= m <= 2 -> label = b plus a short
+// re-check entry with b and those neighbours as its candidates (every other
+// center is excluded, so the exact comparison of the three is the argmin);
+// otherwise (or the list is exhausted, or no proposal) -> GEMM row list.
 // ROUTED = false takes the previous label as the only candidate.
 // ---------------------------------------------------------------------------
 template <bool ROUTED, int NX, bool FULL>
@@ -586,7 +643,6 @@ __global__ __launch_bounds__(256) void router_cert_kernel(
           ok = false;
           b0 = 0;
         }
-        cand = (q == 0) ? b0 : -1;
       }
 
       const float* nd = nbd + (int64_t)b0 * (kNbrL + 1);
@@ -645,15 +701,10 @@ __global__ __launch_bounds__(256) void router_cert_kernel(
       const bool exhausted = (m == kNbrL) && (ndl < R);
       const int n0 = (m >= 1) ? nb0 : -2;
       const int n1 = (m >= 2) ? nb1 : -2;
-      const unsigned long long h0 = __ballot(cand >= 0 && cand == n0);
-      const unsigned long long h1 = __ballot(cand >= 0 && cand == n1);
-      const bool has0 = ((h0 >> (16 * sub)) & 0xFFFFull) != 0ull;
-      const bool has1 = ((h1 >> (16 * sub)) & 0xFFFFull) != 0ull;
       int kd;
       if (!valid) kd = 3;
       else if (!ok || exhausted || m > 2) kd = 2;
-      else if (m == 0) kd = 0;
-      else kd = (has0 && (m < 2 || has1)) ? 1 : 2;
+      else kd = (m == 0) ? 0 : 1;
       // carried bounds: certified rows get ||x - c_b|| <= dub and, for every
       // center outside the first m neighbours, ||x - c|| >= nd[m] - dub (the
       // short re-check completes a listed row's bounds)

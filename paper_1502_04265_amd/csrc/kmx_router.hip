@@ -413,6 +413,22 @@ kmx_status kmx_router_propose(kmx_ctx* ctx, kmx_router* r, const float* X, int64
   return KMX_OK;
 }
 
+kmx_status kmx_center_bounds(kmx_ctx* ctx, const float* C, int32_t k, int32_t d, float* D_out) {
+  if (!ctx) return KMX_EINVAL;
+  ctx->err.clear();
+  if (!C || !D_out) return fail(ctx, KMX_EINVAL, "NULL C or D_out");
+  if (k < 1 || k > kRouterMaxK)
+    return fail(ctx, KMX_EINVAL, "k must lie in [1, " + std::to_string(kRouterMaxK) + "]");
+  if (d < 1) return fail(ctx, KMX_EINVAL, "d must be >= 1");
+  KMX_TRY(set_device(ctx));
+  KMX_TRY(grow(ctx, ctx->nbr, (size_t)k * kNbrL * sizeof(int32_t)));
+  KMX_TRY(grow(ctx, ctx->nbd, (size_t)k * (kNbrL + 1) * sizeof(float)));
+  Timed tm(ctx, T_CERT);
+  KMX_HIP(ctx, launch_center_table(ctx->stream, C, k, d, D_out, P<int32_t>(ctx->nbr),
+                                   P<float>(ctx->nbd), nullptr));
+  return KMX_OK;
+}
+
 // The routed Lloyd loop; with `bounded` the assignment first applies the
 // carried bounds (k_bounds.hip) and only the rows they cannot keep go to the
 // certificate and the GEMM.

@@ -90,6 +90,7 @@ def lib():
         "kmx_router_train": [_vp, _vp, _vp, _i64, _i32, _i64, _vp, _i32, _i32, _i32,
                              ctypes.c_float, ctypes.c_uint64, _vp, _vp],
         "kmx_router_propose": [_vp, _vp, _vp, _i64, _i32, _i64, _vp],
+        "kmx_center_bounds": [_vp, _vp, _i32, _i32, _vp],
         "kmx_lloyd_routed": [_vp, _vp, _vp, _i64, _i32, _i64, _vp, _vp, _i32, _i32,
                              ctypes.c_double, ctypes.c_int, _vp, _vp, _vp, _vp],
         "kmx_lloyd_bounded": [_vp, _vp, _vp, _i64, _i32, _i64, _vp, _vp, _i32, _i32,
@@ -399,6 +400,17 @@ class Context:
         _check(lib().kmx_lift(self._p, _ptr(Z), rows, m, ldz, _ptr(V), d, _ptr(Y), Y.stride(0)),
                self._p)
         return Y
+
+    def center_bounds(self, C):
+        """kmx_center_bounds: k x k lower bounds of the distances between the
+        rows of C (+inf on the diagonal)."""
+        if not C.is_cuda or C.dtype != torch.float32 or C.dim() != 2 or not C.is_contiguous():
+            raise ValueError("C must be a contiguous k x d float32 CUDA tensor")
+        k, d = C.shape
+        D = torch.empty((k, k), dtype=torch.float32, device=C.device)
+        self._sync_stream()
+        _check(lib().kmx_center_bounds(self._p, _ptr(C), k, d, _ptr(D)), self._p)
+        return D
 
     def range_basis(self, A, r: int, w=None, oversample: int = 16, power_iters: int = 2,
                     seed: int = 0):

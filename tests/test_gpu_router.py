@@ -291,3 +291,37 @@ def test_lloyd_routed_full_size_previous_labels(ctx):
     got = lr_[samp].cpu().numpy()
     bad = (got != lab_o) & ~((d2 - d1) < 1e-6 * d2)
     assert not bad.any()
+
+
+@pytest.mark.parametrize("k,d,offset", [(1, 5, 0.0), (7, 3, 0.0), (65, 37, 0.0), (130, 128, 2.0),
+                                        (1000, 512, 0.0), (300, 1000, 0.0), (129, 1100, 0.0),
+                                        (200, 256, 1000.0)])
+def test_center_bounds_are_lower_bounds(ctx, k, d, offset):
+    # The certificate's center table: every entry at most the exact distance
+    # (oracle.kmeans.sqdist in FP64 on the FP32 centers), +inf on the
+    # diagonal, and no looser than the Gram form's error bound allows: the
+    # squared bound falls short of the squared distance by at most twice the
+    # dot product's bound gamma ||c_b|| ||c_c|| on each side (gamma = (d
+    # rounded up to 128, + 1) 2^-23), plus rounding.  A large common offset
+    # (last case) makes the bounds loose but keeps them valid.  Duplicated
+    # centers get a bound of 0.
+    say(f"center bounds k={k} d={d} offset={offset}")
+    rng = np.random.default_rng(500 + k + d)
+    C = (offset + rng.normal(0, 2, (k, d))).astype(np.float32)
+    if k >= 7:
+        C[5] = C[2]
+    D = ctx.center_bounds(_dev(C)).cpu().numpy().astype(np.float64)
+    ex2 = ok.sqdist(C, C)
+    off = ~np.eye(k, dtype=bool)
+    assert np.isinf(np.diag(D)).all()
+    assert (D[off] <= np.sqrt(ex2[off])).all(), float((D - np.sqrt(ex2))[off].max())
+    nrm = np.sqrt((C.astype(np.float64) ** 2).sum(1))
+    kst = -(-d // 128) * 128 + 1
+    gam = kst * 2.0 ** -23 / (1 - kst * 2.0 ** -23)
+    allow = 4.5 * gam * nrm[:, None] * nrm[None, :] + 1e-6 * ex2 + 1e-30
+    short = (ex2 - D ** 2)[off]
+    if short.size:
+        say(f"  largest shortfall / allowed: {(short / allow[off]).max():.3f}")
+    assert (short <= allow[off]).all()
+    if k >= 7:
+        assert D[2, 5] == 0.0 and D[5, 2] == 0.0

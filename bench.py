@@ -556,7 +556,8 @@ def streamed_main(args):
                      "recheck_ms_per_step": (kk["recheck"][0] + kk["short_recheck"][0])
                                             / args.steps,
                      "final_listed": listed, "final_via_fp32_gemm": via_fp32,
-                     "final_all_centers": full}
+                     "final_all_centers": full,
+                     "kernel_ms_per_step": {c: v[0] / args.steps for c, v in kk.items() if v[1]}}
         log(f"[bench] {prec}: {wall * 1e3 / args.steps:.3f} ms/iter, cost {hist[-1]:.9e}, "
             f"listed {listed}, via FP32 {via_fp32}")
     base = res["fp32"]["final_cost"]

@@ -659,21 +659,53 @@ __global__ __launch_bounds__(256) void cf_finalize_kernel(
   if (gate && *gate) return;
   __shared__ double red[3][4];
   __shared__ double sWQ[2];
+  __shared__ long long shWQ[4][4];
+  __shared__ long long shS[256][2];
   const int j = blockIdx.x;
   const int mode = mode_p ? *mode_p : 1;
   const int32_t* cbp = mode ? chunk_base : dchunk;
   const int c0 = cbp[j], c1 = cbp[j + 1];
   long long* accS = acc ? acc + (int64_t)j * d * 2 : nullptr;
   long long* accWQ = acc ? acc + (int64_t)k * d * 2 + (int64_t)j * 4 : nullptr;
-  if (threadIdx.x < 4) {
-    const int q = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  // chunk partials are integers (exact in FP64 and int64): any summation
+  // order gives the same sums, so every thread takes a strided share
+  {
+    long long w4[4] = {0, 0, 0, 0};
+    for (int c = c0 + tid; c < c1; c += 256)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) w4[q] += (long long)partWQ[(int64_t)c * 4 + q];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+#pragma unroll
+      for (int m = 32; m >= 1; m >>= 1) w4[q] += __shfl_xor(w4[q], m, 64);
+      if (lane == 0) shWQ[q][wv] = w4[q];
+    }
+  }
+  __syncthreads();
+  if (tid < 4) {
+    const int q = tid;
     long long s = (!mode && accWQ) ? accWQ[q] : 0ll;
-    for (int c = c0; c < c1; ++c) s += (long long)partWQ[(int64_t)c * 4 + q];
+    s += ((shWQ[q][0] + shWQ[q][1]) + shWQ[q][2]) + shWQ[q][3];
     if (accWQ) accWQ[q] = s;
     // lanes 0 and 1 form W, lanes 2 and 3 form Q
     const long long o = __shfl_xor(s, 1, 64);
     if (q == 0) sWQ[0] = cf_value(s, o, cfs[2 * d + 1]);
     if (q == 2) sWQ[1] = cf_value(s, o, cfs[2 * d + 3]);
+  }
+  // columns: for d <= 128 the block's threads form G = 256 / d groups over
+  // the chunks of each column, combined in LDS; thread col then owns column col
+  const int G = (d <= 128) ? 256 / d : 1;
+  long long gH = 0, gL = 0;
+  if (G > 1 && tid < G * d) {
+    const int col = tid % d, grp = tid / d;
+    for (int c = c0 + grp; c < c1; c += G) {
+      const double* p = partS + ((int64_t)c * d + col) * 2;
+      gH += (long long)p[0];
+      gL += (long long)p[1];
+    }
+    shS[tid][0] = gH;
+    shS[tid][1] = gL;
   }
   __syncthreads();
   const double W = sWQ[0], Q = sWQ[1];
@@ -684,10 +716,17 @@ __global__ __launch_bounds__(256) void cf_finalize_kernel(
       H = accS[col * 2];
       L = accS[col * 2 + 1];
     }
-    for (int c = c0; c < c1; ++c) {
-      const double* p = partS + ((int64_t)c * d + col) * 2;
-      H += (long long)p[0];
-      L += (long long)p[1];
+    if (G > 1) {
+      for (int g = 0; g < G; ++g) {
+        H += shS[g * d + col][0];
+        L += shS[g * d + col][1];
+      }
+    } else {
+      for (int c = c0; c < c1; ++c) {
+        const double* p = partS + ((int64_t)c * d + col) * 2;
+        H += (long long)p[0];
+        L += (long long)p[1];
+      }
     }
     if (accS) {
       accS[col * 2] = H;
@@ -704,7 +743,6 @@ __global__ __launch_bounds__(256) void cf_finalize_kernel(
   dotCS = wave_sum_f64(dotCS);
   cn2 = wave_sum_f64(cn2);
   s2 = wave_sum_f64(s2);
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   if (lane == 0) {
     red[0][wv] = dotCS;
     red[1][wv] = cn2;
@@ -869,8 +907,12 @@ __global__ __launch_bounds__(1024) void delta_plan_kernel(int32_t* __restrict__ 
 }
 
 // scatter: every changed row becomes a removal entry in its old cluster's
-// segment and an addition entry in its new one (positions from atomic
-// cursors: any order within a segment).
+// segment and an addition entry in its new one.  A workgroup takes a
+// contiguous slice of the changed rows, counts its entries per cluster in LDS,
+// reserves each cluster's range with one global atomic, and places the
+// entries with LDS atomics (any order within a segment: the features are
+// exact sums).  Per-row global atomics on the k cursors would serialize when
+// many rows change and k is small.
 __global__ __launch_bounds__(256) void delta_scatter_kernel(const int32_t* __restrict__ label,
                                                             const int32_t* __restrict__ clist,
                                                             const int32_t* __restrict__ cold, int k,
@@ -879,14 +921,32 @@ __global__ __launch_bounds__(256) void delta_scatter_kernel(const int32_t* __res
                                                             const LoopState* __restrict__ st,
                                                             const int* __restrict__ gate) {
   if (gate && *gate) return;
+  extern __shared__ int hs[];   // k counters: counts, then positions
   const int64_t cnt = (int64_t)st->dcount;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < cnt; q += stride) {
+  const int64_t per = (cnt + gridDim.x - 1) / gridDim.x;
+  const int64_t q0 = (int64_t)blockIdx.x * per;
+  const int64_t q1 = min(cnt, q0 + per);
+  if (q0 >= q1) return;   // uniform within the workgroup
+  for (int j = threadIdx.x; j < k; j += blockDim.x) hs[j] = 0;
+  __syncthreads();
+  for (int64_t q = q0 + threadIdx.x; q < q1; q += blockDim.x) {
+    const int o = cold[q];
+    const int nw = label[clist[q]];
+    if (o >= 0 && o < k) atomicAdd(&hs[o], 1);
+    if (nw >= 0 && nw < k) atomicAdd(&hs[nw], 1);
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < k; j += blockDim.x) {
+    const int c = hs[j];
+    hs[j] = c ? atomicAdd(cursor + j, c) : 0;
+  }
+  __syncthreads();
+  for (int64_t q = q0 + threadIdx.x; q < q1; q += blockDim.x) {
     const int i = clist[q];
     const int o = cold[q];
     const int nw = label[i];
-    if (o >= 0 && o < k) ent[atomicAdd(cursor + o, 1)] = -i - 1;
-    if (nw >= 0 && nw < k) ent[atomicAdd(cursor + nw, 1)] = i;
+    if (o >= 0 && o < k) ent[atomicAdd(&hs[o], 1)] = -i - 1;
+    if (nw >= 0 && nw < k) ent[atomicAdd(&hs[nw], 1)] = i;
   }
 }
 
@@ -905,8 +965,8 @@ hipError_t launch_delta_prepare(hipStream_t s, const int32_t* label, int32_t* la
   if (e != hipSuccess) return e;
   int64_t blocks = (n + 255) / 256;
   if (blocks > (int64_t)num_cus * 4) blocks = (int64_t)num_cus * 4;
-  hipLaunchKernelGGL(delta_scatter_kernel, dim3((unsigned)blocks), dim3(256), 0, s, label, clist,
-                     cold, k, cursor, ent, st, flags + 1);
+  hipLaunchKernelGGL(delta_scatter_kernel, dim3((unsigned)blocks), dim3(256),
+                     (size_t)k * sizeof(int), s, label, clist, cold, k, cursor, ent, st, flags + 1);
   return hipGetLastError();
 }
 

@@ -671,13 +671,31 @@ __device__ __forceinline__ void assign_block(const AssignArgs& A, int64_t blk,
     const float u = 5.9604645e-8f;   // 2^-24
     const float Kf = (float)(A.dp + 1);
     const float gam = Kf * ua / (1.0f - Kf * ua);
-    unsigned long long fmask[NCG], gmask[NCG], bmask[NCG];
-    int cand2v[NCG], cand3v[NCG];
+    // After the merge every lane of a point holds the point's state, so lane
+    // group grp decides point group 4 ps + grp: one pass per four groups,
+    // with every lane at work when there are four.
+    constexpr int NPS = (NCG + 3) / 4;
+    unsigned long long fmask[NPS], gmask[NPS], bmask[NPS];
+    int cand2v[NPS], cand3v[NPS];
+    int64_t rowv[NPS];
     int nf_w = 0, ng_w = 0, nfull_w = 0;
 #pragma unroll
-    for (int cg = 0; cg < NCG; ++cg) {
-      const int64_t r = src_row[cg];
-      const bool writer = (grp == (cg & 3)) && (r >= 0);
+    for (int ps = 0; ps < NPS; ++ps) {
+      const int cg = ps * 4 + grp;
+      int64_t r = -1;
+      unsigned sv1 = 0u, sv2 = 0u, sv3 = 0u, sv4 = 0u, sw3 = 0u;
+      float sf1 = 0.f, sf2 = 0.f, sf3 = 0.f;
+      int sj1 = 0, sj2 = 0;
+#pragma unroll
+      for (int c = ps * 4; c < ps * 4 + 4 && c < NCG; ++c) {
+        if (cg == c) {
+          r = src_row[c];
+          sv1 = v1[c]; sv2 = v2[c]; sv3 = v3[c]; sv4 = v4[c]; sw3 = w3[c];
+          sf1 = f1[c]; sf2 = f2[c]; sf3 = f3[c]; sj1 = j1[c]; sj2 = j2[c];
+        }
+      }
+      rowv[ps] = r;
+      const bool writer = (cg < NCG) && (r >= 0);
       bool flagged = false, full = false;
       int cand2 = 0, cand3 = -1;
       if (writer) {
@@ -703,20 +721,20 @@ __device__ __forceinline__ void assign_block(const AssignArgs& A, int64_t blk,
             E = (9.765625e-4f + gk + ga) * rw.nxq * cqm + (gk + 2.0f * ga) * Og + rw.rx * cqm +
                 rw.nx * rcm + u * Og + ldexpf(2.0f * Og, A.ib - 23);
           }
-          t1 = __uint_as_float(v1[cg] & hi);
-          i1 = (v1[cg] & hi) ? min((int)(mask - (v1[cg] & mask)), A.k - 1) : 0;
-          has2 = (v2[cg] & hi) != 0u;
-          has3 = (v3[cg] & hi) != 0u;
-          has4 = (v4[cg] & hi) != 0u;
+          t1 = __uint_as_float(sv1 & hi);
+          i1 = (sv1 & hi) ? min((int)(mask - (sv1 & mask)), A.k - 1) : 0;
+          has2 = (sv2 & hi) != 0u;
+          has3 = (sv3 & hi) != 0u;
+          has4 = (sv4 & hi) != 0u;
           if (has2) {
-            t2 = __uint_as_float(v2[cg] & hi);
-            cand2 = min((int)(mask - (v2[cg] & mask)), A.k - 1);
+            t2 = __uint_as_float(sv2 & hi);
+            cand2 = min((int)(mask - (sv2 & mask)), A.k - 1);
           }
           if (has3) {
-            t3 = __uint_as_float(v3[cg] & hi);
-            i3 = min((int)(mask - (v3[cg] & mask)), A.k - 1);
+            t3 = __uint_as_float(sv3 & hi);
+            i3 = min((int)(mask - (sv3 & mask)), A.k - 1);
           }
-          if (has4) t4 = __uint_as_float(v4[cg] & hi);
+          if (has4) t4 = __uint_as_float(sv4 & hi);
         } else {
           off = 0.0f;
           if constexpr (SPLIT) {
@@ -734,15 +752,15 @@ __device__ __forceinline__ void assign_block(const AssignArgs& A, int64_t blk,
           } else {
             E = (gam + u) * rw.nx * cnm + 1.5f * u * cnm * cnm;
           }
-          t1 = f1[cg];
-          i1 = min(max(j1[cg], 0), A.k - 1);
-          has2 = f2[cg] > -__builtin_inff();
-          has3 = f3[cg] > -__builtin_inff();
+          t1 = sf1;
+          i1 = min(max(sj1, 0), A.k - 1);
+          has2 = sf2 > -__builtin_inff();
+          has3 = sf3 > -__builtin_inff();
           if (has2) {
-            t2 = f2[cg];
-            cand2 = min(max(j2[cg], 0), A.k - 1);
+            t2 = sf2;
+            cand2 = min(max(sj2, 0), A.k - 1);
           }
-          if (has3) t3 = f3[cg];
+          if (has3) t3 = sf3;
         }
         E *= 1.0001f;
         A.label[r] = A.koff + i1;
@@ -757,8 +775,8 @@ __device__ __forceinline__ void assign_block(const AssignArgs& A, int64_t blk,
         if (has2) {
           if (A.d2o) A.d2o[r] = fmaxf(rw.xn2 - 2.0f * (t2 - off), 0.0f);
           flagged = (t1 - t2) <= 2.0f * E;
-          if (T3 && flagged && (w3[cg] & ~mask) &&
-              (t1 - __uint_as_float(w3[cg] & ~mask)) <= 2.0f * E) {
+          if (T3 && flagged && (sw3 & ~mask) &&
+              (t1 - __uint_as_float(sw3 & ~mask)) <= 2.0f * E) {
             full = true;
           } else if (flagged && has3 && (t1 - t3) <= 2.0f * E) {
             // BF16 keeps a fourth key: three listed candidates suffice unless
@@ -777,8 +795,8 @@ __device__ __forceinline__ void assign_block(const AssignArgs& A, int64_t blk,
               // lane-wise third best that dropped further keys)
               bool hasr = has3;
               float tr = t3;
-              if (T3 && (w3[cg] & ~mask)) {
-                const float tw = __uint_as_float(w3[cg] & ~mask);
+              if (T3 && (sw3 & ~mask)) {
+                const float tw = __uint_as_float(sw3 & ~mask);
                 tr = hasr ? fmaxf(tr, tw) : tw;
                 hasr = true;
               }
@@ -793,8 +811,8 @@ __device__ __forceinline__ void assign_block(const AssignArgs& A, int64_t blk,
               // that dropped further keys)
               bool hasn = cand3 >= 0 ? has4 : has3;
               float tn = cand3 >= 0 ? t4 : t3;
-              if (T3 && (w3[cg] & ~mask)) {
-                const float tw = __uint_as_float(w3[cg] & ~mask);
+              if (T3 && (sw3 & ~mask)) {
+                const float tw = __uint_as_float(sw3 & ~mask);
                 tn = hasn ? fmaxf(tn, tw) : tw;
                 hasn = true;
               }
@@ -817,14 +835,14 @@ __device__ __forceinline__ void assign_block(const AssignArgs& A, int64_t blk,
       const bool to_full = (full || (A.cascade_all && flagged)) && (A.full_rows != nullptr);
       const bool to_brute = full && (A.full_rows == nullptr);
       const bool to_flags = flagged && !full && !to_full;
-      fmask[cg] = __ballot(to_flags);
-      gmask[cg] = __ballot(to_full);
-      bmask[cg] = __ballot(to_brute);
-      cand2v[cg] = cand2;
-      cand3v[cg] = cand3;
-      nf_w += __popcll(fmask[cg]);
-      ng_w += __popcll(gmask[cg]);
-      nfull_w += __popcll(bmask[cg]);
+      fmask[ps] = __ballot(to_flags);
+      gmask[ps] = __ballot(to_full);
+      bmask[ps] = __ballot(to_brute);
+      cand2v[ps] = cand2;
+      cand3v[ps] = cand3;
+      nf_w += __popcll(fmask[ps]);
+      ng_w += __popcll(gmask[ps]);
+      nfull_w += __popcll(bmask[ps]);
     }
     // one atomic per list and workgroup; waves take consecutive slices
     if (lane == 0) {
@@ -855,22 +873,22 @@ __device__ __forceinline__ void assign_block(const AssignArgs& A, int64_t blk,
     }
     const unsigned long long below = (1ull << lane) - 1ull;
 #pragma unroll
-    for (int cg = 0; cg < NCG; ++cg) {
-      if ((fmask[cg] >> lane) & 1ull) {
+    for (int ps = 0; ps < NPS; ++ps) {
+      if ((fmask[ps] >> lane) & 1ull) {
         FlagEntry fe;
-        fe.row = (int)(src_row[cg] + A.list_off);
-        fe.cand2 = A.koff + cand2v[cg];
-        fe.cand3 = cand3v[cg] >= 0 ? A.koff + cand3v[cg] : -1;
+        fe.row = (int)(rowv[ps] + A.list_off);
+        fe.cand2 = A.koff + cand2v[ps];
+        fe.cand3 = cand3v[ps] >= 0 ? A.koff + cand3v[ps] : -1;
         fe.pad = 0;
-        A.flags[of + __popcll(fmask[cg] & below)] = fe;
+        A.flags[of + __popcll(fmask[ps] & below)] = fe;
       }
-      if ((gmask[cg] >> lane) & 1ull) A.full_rows[og + __popcll(gmask[cg] & below)] =
-          (int)(src_row[cg] + A.list_off);
-      if ((bmask[cg] >> lane) & 1ull) A.brute[ob + __popcll(bmask[cg] & below)] =
-          (int)(src_row[cg] + A.list_off);
-      of += __popcll(fmask[cg]);
-      og += __popcll(gmask[cg]);
-      ob += __popcll(bmask[cg]);
+      if ((gmask[ps] >> lane) & 1ull) A.full_rows[og + __popcll(gmask[ps] & below)] =
+          (int)(rowv[ps] + A.list_off);
+      if ((bmask[ps] >> lane) & 1ull) A.brute[ob + __popcll(bmask[ps] & below)] =
+          (int)(rowv[ps] + A.list_off);
+      of += __popcll(fmask[ps]);
+      og += __popcll(gmask[ps]);
+      ob += __popcll(bmask[ps]);
     }
     __syncthreads();
   }

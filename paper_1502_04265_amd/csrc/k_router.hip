@@ -414,9 +414,9 @@ hipError_t launch_router_decode(hipStream_t s, const uint32_t* keys, int64_t cou
 // are FP64 sums of the staged FP32 values (relative error below 2^-40 for any
 // d this path takes).  So sqrt(||c_b||^2 + ||c_c||^2 - 2 g - 2 gamma ||c_b||
 // ||c_c||), less a 2^-38 relative slack for the FP64 steps and rounded down,
-// is a lower bound.  Pass 2 (one workgroup per center): the kNbrL nearest
-// other centers sorted by that bound (bitonic sort of (bound, index) keys in
-// LDS), and the bound of the next one (+inf when none).
+// is a lower bound.  Pass 2 (a workgroup per center): the kNbrL nearest other
+// centers sorted by that bound ((bound, index) keys), and the bound of the
+// next one (+inf when none).
 // ---------------------------------------------------------------------------
 constexpr int kGramT = 32;    // centers per tile side
 constexpr int kGramK = 128;   // staged columns
@@ -514,42 +514,73 @@ __global__ __launch_bounds__(256) void center_gram_kernel(const float* __restric
   }
 }
 
+// Pass 2: one workgroup per center b, four waves.  Keys (bound bits << 32 |
+// index; all ones for no center) are taken 64 at a time, one per lane, wave w
+// taking chunks w, w + 4, ...; a chunk is sorted across the wave by a bitonic
+// network of shuffles and reversed, and the lane-wise minimum with the wave's
+// running ascending list of the 64 smallest so far is a bitonic sequence
+// holding the 64 smallest of both, which a bitonic merge sorts again.  The
+// four lists are merged the same way through LDS (two rounds).  Lane i of
+// wave 0 ends with the i-th smallest key: the (bound, index) order of a full
+// sort, without it.
+__device__ __forceinline__ unsigned long long wave_sort_asc(unsigned long long key, int lane) {
+#pragma unroll
+  for (int size = 2; size <= 64; size <<= 1) {
+#pragma unroll
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      const unsigned long long o = __shfl_xor(key, stride, 64);
+      const bool up = (lane & size) == 0;
+      const bool lower = (lane & stride) == 0;
+      key = (lower == up) ? (key < o ? key : o) : (key > o ? key : o);
+    }
+  }
+  return key;
+}
+
+// best (ascending across lanes) <- the 64 smallest of best and other
+// (other descending across lanes)
+__device__ __forceinline__ unsigned long long wave_merge_asc(unsigned long long best,
+                                                            unsigned long long other, int lane) {
+  unsigned long long key = best < other ? best : other;
+#pragma unroll
+  for (int stride = 32; stride > 0; stride >>= 1) {
+    const unsigned long long o = __shfl_xor(key, stride, 64);
+    const bool lower = (lane & stride) == 0;
+    key = lower ? (key < o ? key : o) : (key > o ? key : o);
+  }
+  return key;
+}
+
 __global__ __launch_bounds__(256) void center_select_kernel(const float* __restrict__ D, int k,
-                                                            int kp2, int32_t* __restrict__ nbr,
+                                                            int32_t* __restrict__ nbr,
                                                             float* __restrict__ nbd,
                                                             const int* __restrict__ gate) {
   if (gate && *gate) return;
-  extern __shared__ unsigned long long sk[];
-  const int b = blockIdx.x;
-  const int tid = threadIdx.x;
-  for (int i = tid; i < kp2; i += 256) {
-    unsigned long long key = ~0ull;
-    if (i < k && i != b)
-      key = ((unsigned long long)__float_as_uint(D[(int64_t)b * k + i]) << 32) | (unsigned)i;
-    sk[i] = key;
+  __shared__ unsigned long long lst[3][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int b = (int)blockIdx.x;
+  const unsigned long long none = ~0ull;
+  unsigned long long best = none;   // ascending across lanes
+  for (int c0 = w * 64; c0 < k; c0 += 256) {
+    const int j = c0 + lane;
+    unsigned long long key = none;
+    if (j < k && j != b)
+      key = ((unsigned long long)__float_as_uint(D[(int64_t)b * k + j]) << 32) | (unsigned)j;
+    key = wave_sort_asc(key, lane);
+    best = wave_merge_asc(best, __shfl(key, 63 - lane, 64), lane);
   }
+  // waves 1 and 3 hand their lists (reversed) to waves 0 and 2, then wave 2 to wave 0
+  if (w & 1) lst[w >> 1][63 - lane] = best;
   __syncthreads();
-  for (int size = 2; size <= kp2; size <<= 1) {
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      for (int t = tid; t < (kp2 >> 1); t += 256) {
-        const int lo = (t / stride) * 2 * stride + (t % stride);
-        const int hi = lo + stride;
-        const bool up = (lo & size) == 0;
-        const unsigned long long a = sk[lo], c = sk[hi];
-        if ((a > c) == up) {
-          sk[lo] = c;
-          sk[hi] = a;
-        }
-      }
-      __syncthreads();
-    }
-  }
-  for (int i = tid; i <= kNbrL; i += 256) {
-    const unsigned long long key = (i < kp2) ? sk[i] : ~0ull;
-    const bool none = key == ~0ull;
-    if (i < kNbrL) nbr[(int64_t)b * kNbrL + i] = none ? -1 : (int)(key & 0xFFFFFFFFull);
-    nbd[(int64_t)b * (kNbrL + 1) + i] = none ? __builtin_inff() : __uint_as_float((unsigned)(key >> 32));
-  }
+  if (!(w & 1)) best = wave_merge_asc(best, lst[w >> 1][lane], lane);
+  if (w == 2) lst[2][63 - lane] = best;
+  __syncthreads();
+  if (w != 0) return;
+  best = wave_merge_asc(best, lst[2][lane], lane);
+  const bool nb = best == none;
+  if (lane < kNbrL) nbr[(int64_t)b * kNbrL + lane] = nb ? -1 : (int)(best & 0xFFFFFFFFull);
+  if (lane <= kNbrL)
+    nbd[(int64_t)b * (kNbrL + 1) + lane] = nb ? __builtin_inff() : __uint_as_float((unsigned)(best >> 32));
 }
 
 hipError_t launch_center_table(hipStream_t s, const float* C, int k, int d, float* D, int32_t* nbr,
@@ -559,10 +590,8 @@ hipError_t launch_center_table(hipStream_t s, const float* C, int k, int d, floa
   hipLaunchKernelGGL(center_gram_kernel, dim3(T * (T + 1) / 2), dim3(256), 0, s, C, k, d, D, gate);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  int kp2 = 2;
-  while (kp2 < k) kp2 <<= 1;
-  hipLaunchKernelGGL(center_select_kernel, dim3((unsigned)k), dim3(256),
-                     (size_t)kp2 * sizeof(unsigned long long), s, D, k, kp2, nbr, nbd, gate);
+  hipLaunchKernelGGL(center_select_kernel, dim3((unsigned)k), dim3(256), 0, s, D, k, nbr, nbd,
+                     gate);
   return hipGetLastError();
 }
 

@@ -772,6 +772,11 @@ hipError_t launch_finalize(hipStream_t s, const double* partS, const double* par
 }
 
 // ---- delta update: the rows whose label changed ----
+// A mark workgroup takes kMarkRows rows (32 per thread, one bit each in the
+// change mask): its two same-address atomics (list position, change count)
+// serialize across workgroups, so fewer, larger workgroups are faster
+// (8192 rows: 43 -> 26 us at n = 4M).
+constexpr int kMarkRows = 8192;
 // mark: changed rows (label != previous label) are listed with their previous
 // label (block-aggregated positions, any order), the per-cluster entry counts
 // (one removal from the old cluster, one addition to the new) are added to
@@ -788,9 +793,9 @@ __global__ __launch_bounds__(256) void delta_mark_kernel(const int32_t* __restri
   extern __shared__ int hsm[];
   __shared__ int wcnt[4];
   __shared__ int bbase;
-  constexpr int PER = kSortRows / 256;
-  const int64_t r0 = (int64_t)blockIdx.x * kSortRows;
-  const int64_t r1 = min(n, r0 + kSortRows);
+  constexpr int PER = kMarkRows / 256;
+  const int64_t r0 = (int64_t)blockIdx.x * kMarkRows;
+  const int64_t r1 = min(n, r0 + kMarkRows);
   int lab[PER], prev[PER];
   unsigned chm = 0;
 #pragma unroll
@@ -954,7 +959,7 @@ hipError_t launch_delta_prepare(hipStream_t s, const int32_t* label, int32_t* la
                                 int k, int32_t* ecount, int32_t* clist, int32_t* cold,
                                 int32_t* ebase, int32_t* cursor, int32_t* dchunk, int32_t* ent,
                                 int* flags, LoopState* st, int num_cus, const int* gate) {
-  const int nb = (int)((n + kSortRows - 1) / kSortRows);
+  const int nb = (int)((n + kMarkRows - 1) / kMarkRows);
   hipLaunchKernelGGL(delta_mark_kernel, dim3(nb), dim3(256), (size_t)k * sizeof(int), s, label,
                      lab_prev, n, k, ecount, clist, cold, st, gate);
   hipError_t e = hipGetLastError();

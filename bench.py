@@ -309,14 +309,26 @@ def batched_main(args):
     ctx = kmx.Context(0)
     descs = synth.uneven_instances(args.instances, seed=0)
     log(f"[bench] generating {len(descs)} instances, sum n = {sum(d['n'] for d in descs)}")
-    probs = []
-    t0 = time.perf_counter()
+    data = []
     for i, desc in enumerate(descs):
         X, w = synth.instance_device(desc, device=dev)
-        C0, _ = ctx.seed(X, desc["k"], w=w, rng_seed=i)
-        probs.append({"X": X, "C": C0, "w": w})
+        data.append({"X": X, "k": desc["k"], "w": w})
+    torch.cuda.synchronize()
+    # k-means++ of every instance: one batched call (round r of all instances
+    # with k > r in one launch), and instance by instance for comparison
+    ctx.seed_batched(data[:2], [0, 1])                            # buffers
+    t0 = time.perf_counter()
+    seeded = ctx.seed_batched(data, list(range(len(data))))
     torch.cuda.synchronize()
     seed_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    single = [ctx.seed(p["X"], p["k"], w=p["w"], rng_seed=i) for i, p in enumerate(data)]
+    torch.cuda.synchronize()
+    seed_single_s = time.perf_counter() - t0
+    seed_same = all(torch.equal(a[1], b[1]) for a, b in zip(seeded, single))
+    log(f"[bench] seeding: batched {seed_s:.3f} s, one by one {seed_single_s:.3f} s, "
+        f"identical {seed_same}")
+    probs = [{"X": p["X"], "C": c[0], "w": p["w"]} for p, c in zip(data, seeded)]
     # autotuner cache (JSON lines keyed by device); KMX_TILE_CACHE overrides
     cache = os.environ.get("KMX_TILE_CACHE",
                            os.path.join(tempfile.gettempdir(), "kmx_batched_tiles.jsonl"))
@@ -367,7 +379,8 @@ def batched_main(args):
                      "algorithmic_bytes": it_bytes},
         "assign_flops_per_iteration": flops,
         "whole_iteration_tflops": flops / (wall / args.steps) / 1e12,
-        "tiles": tiles, "seed_s": seed_s, "autotune_s": tune_s,
+        "tiles": tiles, "seed_s": seed_s, "seed_one_by_one_s": seed_single_s,
+        "seed_identical_to_one_by_one": seed_same, "autotune_s": tune_s,
     }
     print(json.dumps(out), flush=True)
 

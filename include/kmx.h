@@ -337,6 +337,21 @@ typedef struct {
 kmx_status kmx_lloyd_batched(kmx_ctx* ctx, const kmx_problem* probs, int32_t count,
                              int32_t iters, kmx_prec prec, double* cost_hist);
 
+/* Weighted k-means++ seeding (as kmx_seed) of every problem at once: round r
+ * of all problems with k > r runs in one launch, each problem drawing from
+ * its own SplitMix64 stream, so problem i gets the same centers and indices
+ * as kmx_seed(X_i, n_i, d_i, ldx_i, w_i, k_i, rng_seeds[i]) (rows whose D2
+ * provably cannot drop are skipped as there).
+ *   probs      X, n, d (any d >= 1), ldx, w, k as for kmx_seed; C receives
+ *              the k x d centers; label unused.
+ *   rng_seeds  host, count seeds.
+ *   idx_out    device, sum_i k_i int64, nullable: the chosen row indices of
+ *              problem i at offset k_0 + ... + k_{i-1}.
+ * Requirements per problem as kmx_seed (KMX_EINVAL names the problem).
+ * Synchronizes. */
+kmx_status kmx_seed_batched(kmx_ctx* ctx, const kmx_problem* probs, int32_t count,
+                            const uint64_t* rng_seeds, int64_t* idx_out);
+
 /* Autotuner: for each (d, k class) present in probs (k classes: k <= 24,
  * k <= 96, larger), times the batched assignment of those problems under
  * each tile shape and keeps the fastest on ctx.  cache_path (nullable): a

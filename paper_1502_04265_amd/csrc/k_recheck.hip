@@ -317,24 +317,27 @@ constexpr bool kRecheckPipe = true;   // pipelined short re-check for rows of d 
 // One workgroup per row that needs every center.  Each wave takes four
 // centers at a time (centers 4(kFullWaves i + w) + 0..3 for wave w), its lanes splitting
 // the coordinates as in the short re-check, so every plain distance has
-// relative error below gamma = (ceil(d/64) + 13) u.  Pass 1: the minimum m
-// of the plain distances.  Pass 2: the same plain distances again (same
-// operations, same bits); exact double-float distances for the centers at
-// most m (1 + gamma) / (1 - gamma) (the only ones that can be the minimum);
-// lexicographic argmin with the lowest index on ties.
-__device__ __forceinline__ void plain_dist4(const float* __restrict__ x,
+// relative error below gamma = (ceil(d/64) + 13) u.  Pass 1: the plain
+// distances (kept in LDS) and their minimum m.  Pass 2: exact double-float
+// distances for the centers at most m (1 + gamma) / (1 - gamma) (the only
+// ones that can be the minimum); lexicographic argmin with the lowest index
+// on ties.
+constexpr int kFullPer = 4;   // centers per wave and step (8 measured slower)
+__device__ __forceinline__ void plain_dist_k(const float* __restrict__ x,
                                             const float* __restrict__ C, int j0, int k, int d,
                                             int lane, bool vec, float* p) {
-  const float* c[4];
+  const float* c[kFullPer];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) c[t] = C + (int64_t)min(j0 + t, k - 1) * d;
-  float a[4] = {0.f, 0.f, 0.f, 0.f};
+  for (int t = 0; t < kFullPer; ++t) c[t] = C + (int64_t)min(j0 + t, k - 1) * d;
+  float a[kFullPer];
+#pragma unroll
+  for (int t = 0; t < kFullPer; ++t) a[t] = 0.f;
   if (vec) {
     for (int q = lane * 4; q < d; q += 256) {
       const float4 xv = *(const float4*)(x + q);
       const float xs[4] = {xv.x, xv.y, xv.z, xv.w};
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
+      for (int t = 0; t < kFullPer; ++t) {
         const float4 u = *(const float4*)(c[t] + q);
         const float v[4] = {u.x, u.y, u.z, u.w};
 #pragma unroll
@@ -348,7 +351,7 @@ __device__ __forceinline__ void plain_dist4(const float* __restrict__ x,
     for (int q = lane; q < d; q += 64) {
       const float xq = x[q];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
+      for (int t = 0; t < kFullPer; ++t) {
         const float df = xq - c[t][q];
         a[t] = __builtin_fmaf(df, df, a[t]);
       }
@@ -357,10 +360,10 @@ __device__ __forceinline__ void plain_dist4(const float* __restrict__ x,
 #pragma unroll
   for (int m = 32; m >= 1; m >>= 1) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t) a[t] += __shfl_xor(a[t], m, 64);
+    for (int t = 0; t < kFullPer; ++t) a[t] += __shfl_xor(a[t], m, 64);
   }
 #pragma unroll
-  for (int t = 0; t < 4; ++t) p[t] = (j0 + t < k) ? a[t] : __builtin_inff();
+  for (int t = 0; t < kFullPer; ++t) p[t] = (j0 + t < k) ? a[t] : __builtin_inff();
 }
 
 __global__ __launch_bounds__(kFullWaves * 64) void recheck_full_kernel(
@@ -369,6 +372,7 @@ __global__ __launch_bounds__(kFullWaves * 64) void recheck_full_kernel(
     const LoopState* __restrict__ st, const int* __restrict__ gate, BoundsOut bo,
     float* __restrict__ d2o) {
   if (gate && *gate) return;
+  extern __shared__ float pl[];   // k plain distances of the current row
   __shared__ float redf[kFullWaves], redf2[kFullWaves];
   __shared__ int redfj[kFullWaves];
   __shared__ float redh[kFullWaves], redl[kFullWaves];
@@ -386,11 +390,12 @@ __global__ __launch_bounds__(kFullWaves * 64) void recheck_full_kernel(
     // smallest m2 (for the carried lower bound)
     float m = __builtin_inff(), m2 = __builtin_inff();
     int jm = 0x7FFFFFFF;
-    for (int j0 = 4 * wv; j0 < k; j0 += 4 * kFullWaves) {
-      float p[4];
-      plain_dist4(x, C, j0, k, d, lane, vec, p);
+    for (int j0 = kFullPer * wv; j0 < k; j0 += kFullPer * kFullWaves) {
+      float p[kFullPer];
+      plain_dist_k(x, C, j0, k, d, lane, vec, p);
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
+      for (int t = 0; t < kFullPer; ++t) {
+        if (lane == t && j0 + t < k) pl[j0 + t] = p[t];
         if (p[t] < m) { m2 = m; m = p[t]; jm = j0 + t; }
         else m2 = fminf(m2, p[t]);
       }
@@ -407,11 +412,12 @@ __global__ __launch_bounds__(kFullWaves * 64) void recheck_full_kernel(
     const float thr = m * (1.0f + gam) / (1.0f - gam) * 1.0001f + 1e-30f;
     float bh = __builtin_inff(), bl = 0.f;
     int best = 0x7FFFFFFF;
-    for (int j0 = 4 * wv; j0 < k; j0 += 4 * kFullWaves) {
-      float p[4];
-      plain_dist4(x, C, j0, k, d, lane, vec, p);
+    for (int j0 = kFullPer * wv; j0 < k; j0 += kFullPer * kFullWaves) {
+      float p[kFullPer];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
+      for (int t = 0; t < kFullPer; ++t) p[t] = (j0 + t < k) ? pl[j0 + t] : __builtin_inff();
+#pragma unroll
+      for (int t = 0; t < kFullPer; ++t) {
         if (p[t] <= thr) {   // wave-uniform
           float h, l;
           exact_dist(x, C + (int64_t)(j0 + t) * d, d, lane, h, l);
@@ -538,8 +544,9 @@ hipError_t launch_recheck(hipStream_t s, const float* X, int64_t n, int d, int64
   blocks = n;
   if (blocks > cap) blocks = cap;
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(recheck_full_kernel, dim3((unsigned)blocks), dim3(kFullWaves * 64), 0, s, X, n, d, ldx,
-                     C, k, label, d1, brute, st, gate, bo, d2);
+  hipLaunchKernelGGL(recheck_full_kernel, dim3((unsigned)blocks), dim3(kFullWaves * 64),
+                     (size_t)k * sizeof(float), s, X, n, d, ldx, C, k, label, d1, brute, st, gate,
+                     bo, d2);
   return hipGetLastError();
 }
 
@@ -661,10 +668,11 @@ __global__ __launch_bounds__(kFullWaves * 64) void recheck_full_batched_kernel(
     const float* C = I.C + (int64_t)I.koff * d;
     const bool vec = ((((uintptr_t)x) & 15) == 0) && ((((uintptr_t)C) & 15) == 0) && (d % 4 == 0);
     float m = __builtin_inff();
-    for (int j0 = 4 * wv; j0 < I.k; j0 += 4 * kFullWaves) {
-      float p[4];
-      plain_dist4(x, C, j0, I.k, d, lane, vec, p);
-      m = fminf(m, fminf(fminf(p[0], p[1]), fminf(p[2], p[3])));
+    for (int j0 = kFullPer * wv; j0 < I.k; j0 += kFullPer * kFullWaves) {
+      float p[kFullPer];
+      plain_dist_k(x, C, j0, I.k, d, lane, vec, p);
+#pragma unroll
+      for (int t = 0; t < kFullPer; ++t) m = fminf(m, p[t]);
     }
     if (lane == 0) redf[wv] = m;
     __syncthreads();
@@ -673,11 +681,11 @@ __global__ __launch_bounds__(kFullWaves * 64) void recheck_full_batched_kernel(
     const float thr = m * (1.0f + gam) / (1.0f - gam) * 1.0001f + 1e-30f;
     float bh = __builtin_inff(), bl = 0.f;
     int best = 0x7FFFFFFF;
-    for (int j0 = 4 * wv; j0 < I.k; j0 += 4 * kFullWaves) {
-      float p[4];
-      plain_dist4(x, C, j0, I.k, d, lane, vec, p);
+    for (int j0 = kFullPer * wv; j0 < I.k; j0 += kFullPer * kFullWaves) {
+      float p[kFullPer];
+      plain_dist_k(x, C, j0, I.k, d, lane, vec, p);
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
+      for (int t = 0; t < kFullPer; ++t) {
         if (p[t] <= thr) {   // wave-uniform
           float h, l;
           exact_dist(x, C + (int64_t)(j0 + t) * d, d, lane, h, l);

@@ -168,6 +168,75 @@ __device__ __forceinline__ sf32x4_t load_chunk(const float* p, int q, int d, boo
   return v;
 }
 
+// Round r's draw, by the last block of a round (every thread calls it):
+// u_r from SplitMix64, the first block whose inclusive prefix of the block
+// masses part[0 .. nb) strictly exceeds u_r M, then the first row inside it
+// (rpb rows per block); with zero mass a draw by weight among the rows not
+// chosen yet, and with no positive weight left the first row not chosen.
+// Writes row `pick` into C (row r), idx_out[r] (nullable) and chosen.
+__device__ void seed_draw(const float* __restrict__ X, int64_t n, int d, int64_t ldx,
+                          const float* __restrict__ w, int r, uint64_t seed,
+                          const double* __restrict__ D2, uint8_t* __restrict__ chosen,
+                          const double* part, int nb, int64_t rpb, float* __restrict__ C,
+                          int64_t* __restrict__ idx_out, double* sh, unsigned long long* red) {
+  const volatile double* pv = part;
+  const uint64_t z = splitmix64_at(seed, (uint64_t)r);
+  const double u = (double)(z >> 11) * 0x1.0p-53;
+  double t = 0.0;
+  for (int q = threadIdx.x; q < nb; q += 256) t += pv[q];
+  const double M = block_sum_256(t, sh);
+  int64_t pick = -1;
+  if (M > 0.0) {
+    const double target = u * M;
+    double before = 0.0;
+    int64_t qb = pick_sliced(0, nb, target, [&](int64_t q) { return pv[q]; }, sh, red, &before);
+    if (qb >= 0) {
+      const int64_t b0 = qb * rpb;
+      const int64_t b1 = min(n, b0 + rpb);
+      const double tin = target - before;
+      if (r == 0) {
+        pick = pick_sliced(b0, b1, tin, [&](int64_t i) { return w ? (double)w[i] : 1.0; }, sh,
+                           red, nullptr);
+      } else {
+        pick = pick_sliced(b0, b1, tin,
+                           [&](int64_t i) { return (w ? (double)w[i] : 1.0) * D2[i]; }, sh,
+                           red, nullptr);
+      }
+    }
+  }
+  if (pick < 0) {
+    // zero mass: draw by weight among the rows not chosen yet
+    double tt = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256)
+      tt += chosen[i] ? 0.0 : (w ? (double)w[i] : 1.0);
+    const double M2 = block_sum_256(tt, sh);
+    if (M2 > 0.0) {
+      pick = pick_linear(0, n, u * M2,
+                         [&](int64_t i) { return chosen[i] ? 0.0 : (w ? (double)w[i] : 1.0); },
+                         sh, red, nullptr);
+    }
+    if (pick < 0) {
+      // no positive weight left: the first row not chosen yet (else row 0)
+      if (threadIdx.x == 0) red[0] = ~0ull;
+      __syncthreads();
+      for (int64_t i = threadIdx.x; i < n; i += 256)
+        if (!chosen[i]) atomicMin(&red[0], (unsigned long long)i);
+      __syncthreads();
+      const unsigned long long f = red[0];
+      pick = (f == ~0ull) ? 0 : (int64_t)f;
+    }
+  }
+  __syncthreads();
+  // ---- 3. write the center (an exact copy of the row) ----
+  const float* xs = X + pick * ldx;
+  float* cr = C + (int64_t)r * d;
+  for (int q = threadIdx.x; q < d; q += 256) cr[q] = xs[q];
+  if (threadIdx.x == 0) {
+    chosen[pick] = 1;
+    if (idx_out) idx_out[r] = pick;
+  }
+}
+
 template <int G, int NV, bool VEC>
 __global__ __launch_bounds__(256) void seed_round_kernel(
     const float* __restrict__ X, int64_t n, int d, int64_t ldx, const float* __restrict__ w,
@@ -304,7 +373,6 @@ __global__ __launch_bounds__(256) void seed_round_kernel(
 
   // ---- 2. the last block draws the row ----
   __threadfence();
-  const volatile double* pv = part;
   if (r >= 1 && rows_read) {
     const volatile int* nv = nread;
     long long t_read = 0;
@@ -312,62 +380,8 @@ __global__ __launch_bounds__(256) void seed_round_kernel(
     const double tr = block_sum_256((double)t_read, sh);
     if (threadIdx.x == 0) *rows_read += (unsigned long long)tr;
   }
-  const uint64_t z = splitmix64_at(seed, (uint64_t)r);
-  const double u = (double)(z >> 11) * 0x1.0p-53;
-  double t = 0.0;
-  for (int q = threadIdx.x; q < nb; q += 256) t += pv[q];
-  const double M = block_sum_256(t, sh);
-  int64_t pick = -1;
-  if (M > 0.0) {
-    const double target = u * M;
-    double before = 0.0;
-    int64_t qb = pick_sliced(0, nb, target, [&](int64_t q) { return pv[q]; }, sh, red, &before);
-    if (qb >= 0) {
-      const int64_t b0 = qb * rpb;
-      const int64_t b1 = min(n, b0 + rpb);
-      const double tin = target - before;
-      if (r == 0) {
-        pick = pick_sliced(b0, b1, tin, [&](int64_t i) { return w ? (double)w[i] : 1.0; }, sh,
-                           red, nullptr);
-      } else {
-        pick = pick_sliced(b0, b1, tin,
-                           [&](int64_t i) { return (w ? (double)w[i] : 1.0) * D2[i]; }, sh,
-                           red, nullptr);
-      }
-    }
-  }
-  if (pick < 0) {
-    // zero mass: draw by weight among the rows not chosen yet
-    double tt = 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += 256)
-      tt += chosen[i] ? 0.0 : (w ? (double)w[i] : 1.0);
-    const double M2 = block_sum_256(tt, sh);
-    if (M2 > 0.0) {
-      pick = pick_linear(0, n, u * M2,
-                         [&](int64_t i) { return chosen[i] ? 0.0 : (w ? (double)w[i] : 1.0); },
-                         sh, red, nullptr);
-    }
-    if (pick < 0) {
-      // no positive weight left: the first row not chosen yet (else row 0)
-      if (threadIdx.x == 0) red[0] = ~0ull;
-      __syncthreads();
-      for (int64_t i = threadIdx.x; i < n; i += 256)
-        if (!chosen[i]) atomicMin(&red[0], (unsigned long long)i);
-      __syncthreads();
-      const unsigned long long f = red[0];
-      pick = (f == ~0ull) ? 0 : (int64_t)f;
-    }
-  }
-  __syncthreads();
-  // ---- 3. write the center (an exact copy of the row) ----
-  const float* xs = X + pick * ldx;
-  float* cr = C + (int64_t)r * d;
-  for (int q = threadIdx.x; q < d; q += 256) cr[q] = xs[q];
-  if (threadIdx.x == 0) {
-    chosen[pick] = 1;
-    if (idx_out) idx_out[r] = pick;
-    *ctr = 0u;
-  }
+  seed_draw(X, n, d, ldx, w, r, seed, D2, chosen, part, nb, rpb, C, idx_out, sh, red);
+  if (threadIdx.x == 0) *ctr = 0u;
 }
 
 // Squared distances from the newest center c_{r-1} to the earlier centers,
@@ -387,6 +401,148 @@ __global__ __launch_bounds__(256) void center_gap_kernel(const float* __restrict
   }
   acc = wave_sum_f64(acc);
   if (lane == 0) cc2[j] = acc * (1.0 - 1e-12);
+}
+
+// ---------------------------------------------------------------------------
+// Batched seeding: round r of every instance with k > r in one launch.
+// Instances are ordered by decreasing k, so the active ones are a prefix and
+// their blocks (kSeedRows rows each) a prefix of the block space; a block
+// finds its instance by binary search on the first block indices.  Each
+// block lowers D2 of its rows against the instance's center r - 1 (16 lanes
+// per row, FP64 sums of the FP32 differences) and writes its block mass; from
+// round 2 on a row whose closest chosen center c_a satisfies
+// ||c_{r-1} - c_a||^2 >= 4 D2 (1 + 1e-8) keeps its D2 unread (the test of
+// seed_round_kernel).  The instance's last block (its own atomic ticket)
+// draws as seed_draw does for one instance.
+// ---------------------------------------------------------------------------
+// Squared gaps of every active instance's newest center c_{r-1} to its
+// earlier centers (as center_gap_kernel): one wave per (instance, center).
+__global__ __launch_bounds__(256) void seed_batched_gap_kernel(const SeedInst* __restrict__ insts,
+                                                               int m, int r) {
+  const int lane = threadIdx.x & 63;
+  const int64_t g = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (g >= (int64_t)m * (r - 1)) return;   // uniform per wave
+  const SeedInst& I = insts[g / (r - 1)];
+  const int j = (int)(g % (r - 1));
+  const float* c = I.C + (int64_t)(r - 1) * I.d;
+  const float* cj = I.C + (int64_t)j * I.d;
+  double acc = 0.0;
+  for (int q = lane; q < I.d; q += 64) {
+    const double df = (double)c[q] - (double)cj[q];
+    acc = fma(df, df, acc);
+  }
+  acc = wave_sum_f64(acc);
+  if (lane == 0) I.cc2[j] = acc * (1.0 - 1e-12);
+}
+
+hipError_t launch_seed_batched_gaps(hipStream_t s, const SeedInst* insts, int m, int r) {
+  if (m <= 0 || r < 2) return hipSuccess;
+  const int64_t waves = (int64_t)m * (r - 1);
+  hipLaunchKernelGGL(seed_batched_gap_kernel, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s,
+                     insts, m, r);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void seed_batched_round_kernel(const SeedInst* __restrict__ insts,
+                                                                 int m, int r) {
+  __shared__ double sh[8];
+  __shared__ unsigned long long red[2];
+  __shared__ unsigned int ticket;
+  constexpr int G = 16, NG = 256 / G;
+  int lo = 0, hi = m - 1;   // last instance whose first block is <= blockIdx.x
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (insts[mid].blk0 <= (int64_t)blockIdx.x) lo = mid;
+    else hi = mid - 1;
+  }
+  const SeedInst I = insts[lo];
+  const int b = (int)((int64_t)blockIdx.x - I.blk0);
+  const int64_t rpb = kSeedRows;
+  const int64_t r0 = (int64_t)b * rpb;
+  const int64_t r1 = min(I.n, r0 + rpb);
+  const int sub = threadIdx.x & (G - 1), grp = threadIdx.x / G;
+  const float* w = I.w;
+  double macc = 0.0;
+  if (r == 0) {
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += 256) macc += w ? (double)w[i] : 1.0;
+  } else {
+    const float* c = I.C + (int64_t)(r - 1) * I.d;
+    // whole 16-byte chunks when the rows and the centers are aligned
+    const bool vec = (I.d % 4 == 0) && (I.ldx % 4 == 0) && ((((uintptr_t)I.X) & 15) == 0) &&
+                     ((((uintptr_t)I.C) & 15) == 0);
+    const int nch = (I.d + 3) >> 2;
+    for (int64_t i = r0 + grp; i < r1; i += NG) {   // uniform within a lane group
+      if (r >= 2) {
+        const double dv = I.D2[i];
+        if (I.cc2[I.sa[i]] >= 4.0 * dv * (1.0 + 1e-8)) {   // uniform within the group
+          if (sub == 0) macc += w ? (double)w[i] * dv : dv;
+          continue;
+        }
+      }
+      const float* x = I.X + i * I.ldx;
+      double acc = 0.0;
+      if (vec) {
+        // two chunks in flight per lane, four independent FMA chains
+        double a4[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int q = sub; q < nch; q += 2 * G) {
+          const bool two = q + G < nch;
+          const sf32x4_t x0 = *(const sf32x4_t*)(x + 4 * q);
+          const sf32x4_t c0 = *(const sf32x4_t*)(c + 4 * q);
+          sf32x4_t x1 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
+          if (two) {
+            x1 = *(const sf32x4_t*)(x + 4 * (q + G));
+            c1 = *(const sf32x4_t*)(c + 4 * (q + G));
+          }
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const double df = (double)x0[e] - (double)c0[e];
+            a4[e] = fma(df, df, a4[e]);
+          }
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const double df = (double)x1[e] - (double)c1[e];
+            a4[e] = fma(df, df, a4[e]);
+          }
+        }
+        acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
+      } else {
+        for (int q = sub; q < I.d; q += G) {
+          const double df = (double)x[q] - (double)c[q];
+          acc = fma(df, df, acc);
+        }
+      }
+#pragma unroll
+      for (int msk = G / 2; msk >= 1; msk >>= 1) acc += __shfl_xor(acc, msk, 64);
+      if (sub == 0) {
+        const double old = (r == 1) ? 0.0 : I.D2[i];
+        const bool closer = (r == 1) || acc < old;
+        const double dv = closer ? acc : old;
+        if (closer) I.sa[i] = r - 1;
+        I.D2[i] = dv;
+        macc += w ? (double)w[i] * dv : dv;
+      }
+    }
+  }
+  const double bsum = block_sum_256(macc, sh);
+  if (threadIdx.x == 0) {
+    I.part[b] = bsum;
+    __threadfence();
+    ticket = atomicAdd(I.ctr, 1u);
+  }
+  __syncthreads();
+  if (ticket != (unsigned)(I.nb - 1)) return;
+  __threadfence();
+  seed_draw(I.X, I.n, I.d, I.ldx, w, r, I.seed, I.D2, I.chosen, I.part, I.nb, rpb, I.C, I.idx, sh,
+            red);
+  if (threadIdx.x == 0) *I.ctr = 0u;
+}
+
+hipError_t launch_seed_batched_round(hipStream_t s, const SeedInst* insts, int m, int r,
+                                     int64_t blocks) {
+  if (m <= 0 || blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(seed_batched_round_kernel, dim3((unsigned)blocks), dim3(256), 0, s, insts, m,
+                     r);
+  return hipGetLastError();
 }
 
 hipError_t launch_seed_round(hipStream_t s, const float* X, int64_t n, int d, int64_t ldx,

@@ -1,6 +1,7 @@
 // Host side of the kmx C ABI: argument checks, the grow-only workspace, the
 // per-dataset cache and the launch sequences of seed / assign / update / cost
 // / lloyd.  All device work is enqueued on the context's stream.
+#include <algorithm>
 #include <climits>
 #include <cstdlib>
 #include <cstdint>
@@ -485,6 +486,8 @@ kmx_status kmx_destroy(kmx_ctx* ctx) {
       &ctx->bkh,
       &ctx->D2,        &ctx->chosen,   &ctx->seed_part,  &ctx->seed_ctr,   &ctx->scratch_c,
       &ctx->seed_a,    &ctx->seed_cc,  &ctx->seed_nread,
+      &ctx->bs_D2,     &ctx->bs_sa,    &ctx->bs_cc,      &ctx->bs_chosen,  &ctx->bs_part,
+      &ctx->bs_ctr,    &ctx->bs_insts,
       &ctx->hist,      &ctx->fb_rows,  &ctx->keys,       &ctx->cdist,      &ctx->nbr,
       &ctx->nbd,       &ctx->fbh,      &ctx->prop_have,  &ctx->prop_rows,      &ctx->xq8,        &ctx->sx8,        &ctx->rowstats8,
       &ctx->xstats8,   &ctx->cq8,      &ctx->ch8,        &ctx->hd8,        &ctx->cstats8,
@@ -556,6 +559,88 @@ kmx_status kmx_seed(kmx_ctx* ctx, const float* X, int64_t n, int32_t d, int64_t 
                                    P<int>(ctx->seed_nread),
                                    (unsigned long long*)(P<unsigned char>(ctx->seed_ctr) + 8)));
   }
+  return KMX_OK;
+}
+
+kmx_status kmx_seed_batched(kmx_ctx* ctx, const kmx_problem* probs, int32_t count,
+                            const uint64_t* rng_seeds, int64_t* idx_out) {
+  if (!ctx) return KMX_EINVAL;
+  ctx->err.clear();
+  if (count < 1 || !probs || !rng_seeds)
+    return fail(ctx, KMX_EINVAL, "count must be >= 1 with probs and rng_seeds given");
+  for (int i = 0; i < count; ++i) {
+    const kmx_problem& q = probs[i];
+    const kmx_status st = check_problem(ctx, q.X, q.n, q.d, q.ldx, q.k);
+    if (st != KMX_OK) return fail(ctx, st, "problem " + std::to_string(i) + ": " + ctx->err);
+    if (!q.C) return fail(ctx, KMX_EINVAL, "problem " + std::to_string(i) + ": C is NULL");
+  }
+  KMX_TRY(set_device(ctx));
+  for (int i = 0; i < count; ++i) {
+    const kmx_problem& q = probs[i];
+    const kmx_status st = check_data(ctx, q.X, q.n, q.d, q.ldx, q.w, q.k, nullptr, 0);
+    if (st != KMX_OK) return fail(ctx, st, "problem " + std::to_string(i) + ": " + ctx->err);
+  }
+  // instances by decreasing k (ties: problem order), so round r's active
+  // instances and their blocks are prefixes
+  std::vector<int> ord(count);
+  for (int i = 0; i < count; ++i) ord[i] = i;
+  std::stable_sort(ord.begin(), ord.end(),
+                   [&](int a, int b) { return probs[a].k > probs[b].k; });
+  std::vector<int64_t> koff(count + 1, 0);
+  for (int i = 0; i < count; ++i) koff[i + 1] = koff[i] + probs[i].k;
+  int64_t sn = 0, snb = 0;
+  for (int i = 0; i < count; ++i) {
+    sn += probs[i].n;
+    snb += (probs[i].n + kSeedRows - 1) / kSeedRows;
+  }
+  KMX_TRY(grow(ctx, ctx->bs_D2, (size_t)sn * sizeof(double)));
+  KMX_TRY(grow(ctx, ctx->bs_sa, (size_t)sn * sizeof(int32_t)));
+  KMX_TRY(grow(ctx, ctx->bs_cc, (size_t)koff[count] * sizeof(double)));
+  KMX_TRY(grow(ctx, ctx->bs_chosen, (size_t)sn));
+  KMX_TRY(grow(ctx, ctx->bs_part, (size_t)snb * sizeof(double)));
+  KMX_TRY(grow(ctx, ctx->bs_ctr, (size_t)count * sizeof(unsigned int)));
+  KMX_TRY(grow(ctx, ctx->bs_insts, (size_t)count * sizeof(SeedInst)));
+  std::vector<SeedInst> h(count);
+  int64_t off = 0, boff = 0;
+  for (int t = 0; t < count; ++t) {
+    const int i = ord[t];
+    const kmx_problem& q = probs[i];
+    SeedInst& I = h[t];
+    I.X = q.X;
+    I.w = q.w;
+    I.C = q.C;
+    I.idx = idx_out ? idx_out + koff[i] : nullptr;
+    I.D2 = P<double>(ctx->bs_D2) + off;
+    I.sa = P<int32_t>(ctx->bs_sa) + off;
+    I.cc2 = P<double>(ctx->bs_cc) + koff[i];
+    I.chosen = P<uint8_t>(ctx->bs_chosen) + off;
+    I.nb = (int)((q.n + kSeedRows - 1) / kSeedRows);
+    I.part = P<double>(ctx->bs_part) + boff;
+    I.ctr = P<unsigned int>(ctx->bs_ctr) + t;
+    I.n = q.n;
+    I.ldx = q.ldx;
+    I.blk0 = boff;
+    I.seed = rng_seeds[i];
+    I.d = q.d;
+    I.k = q.k;
+    off += q.n;
+    boff += I.nb;
+  }
+  Timed tm(ctx, T_SEED);
+  KMX_HIP(ctx, hipMemcpyAsync(ctx->bs_insts.p, h.data(), (size_t)count * sizeof(SeedInst),
+                              hipMemcpyHostToDevice, ctx->stream));
+  KMX_HIP(ctx, launch_fill_u8(ctx->stream, P<uint8_t>(ctx->bs_chosen), sn, 0));
+  KMX_HIP(ctx, launch_fill_i32(ctx->stream, P<int32_t>(ctx->bs_ctr), count, 0));
+  const int kmax = h[0].k;
+  int m = count;
+  for (int r = 0; r < kmax; ++r) {
+    while (m > 0 && h[m - 1].k <= r) --m;   // instances with k > r
+    const int64_t blocks = h[m - 1].blk0 + h[m - 1].nb;
+    KMX_HIP(ctx, launch_seed_batched_gaps(ctx->stream, P<SeedInst>(ctx->bs_insts), m, r));
+    KMX_HIP(ctx, launch_seed_batched_round(ctx->stream, P<SeedInst>(ctx->bs_insts), m, r, blocks));
+  }
+  // the host descriptors must outlive their copy
+  KMX_HIP(ctx, hipStreamSynchronize(ctx->stream));
   return KMX_OK;
 }
 

@@ -213,6 +213,7 @@ struct kmx_ctx {
   kmx::Buf state;
   kmx::Buf vcheck;   // argument-check counters
   kmx::Buf D2, chosen, seed_part, seed_ctr, seed_a, seed_cc, seed_nread;
+  kmx::Buf bs_D2, bs_sa, bs_cc, bs_chosen, bs_part, bs_ctr, bs_insts;   // batched seeding
   kmx::Buf scratch_c, hist;
   kmx::Buf fb_rows, keys, cdist, nbr, nbd, fbh;   // routed assignment
   kmx::Buf prop_have, prop_rows;   // bounded routed: rows with proposals, rows needing them
@@ -267,6 +268,27 @@ hipError_t launch_fill_i32(hipStream_t s, int32_t* p, int64_t n, int32_t v);
 hipError_t launch_fill_u8(hipStream_t s, uint8_t* p, int64_t n, uint8_t v);
 hipError_t launch_reset_small(hipStream_t s, CenterStats* cs, CenterStats* cs2, CenterStats* cs3,
                               LoopState* st, int reset_iter);
+
+// Batched seeding: one instance's arguments and workspace (k_seed.hip).
+struct SeedInst {
+  const float* X;
+  const float* w;      // nullable
+  float* C;            // k x d out
+  int64_t* idx;        // k out, nullable
+  double* D2;          // n
+  int32_t* sa;         // n: index of the row's closest chosen center
+  double* cc2;         // k: squared gaps of the newest center to the earlier ones
+  uint8_t* chosen;     // n
+  double* part;        // nb block masses
+  unsigned int* ctr;   // the instance's ticket
+  int64_t n, ldx, blk0;
+  uint64_t seed;
+  int d, k, nb;
+};
+hipError_t launch_seed_batched_round(hipStream_t s, const SeedInst* insts, int m, int r,
+                                     int64_t blocks);
+// the gaps of round r (r >= 2) of the first m instances
+hipError_t launch_seed_batched_gaps(hipStream_t s, const SeedInst* insts, int m, int r);
 
 // assign
 // Operand code of the last GEMM pass of the BF16 and FP8 cascades (besides

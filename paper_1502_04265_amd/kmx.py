@@ -76,6 +76,7 @@ def lib():
         "kmx_seed_stats": [_vp, _vp],
         "kmx_timing_read": [_vp, ctypes.c_int, _vp, _vp],
         "kmx_lloyd_batched": [_vp, _vp, _i32, _i32, ctypes.c_int, _vp],
+        "kmx_seed_batched": [_vp, _vp, _i32, _vp, _vp],
         "kmx_batched_autotune": [_vp, _vp, _i32, ctypes.c_int, ctypes.c_char_p, _vp],
         "kmx_batched_tiles": [_vp, _i32, _i32, _vp, _vp],
         "kmx_project": [_vp, _vp, _i64, _i32, _i64, _vp, _i32, _vp, _i64],
@@ -358,6 +359,30 @@ class Context:
         s = iters + 1
         return [(keep[i][0], keep[i][1], [hist[i * s + t] for t in range(s)])
                 for i in range(len(problems))]
+
+    def seed_batched(self, problems, rng_seeds):
+        """kmx_seed_batched: problems are dicts with X (n x d), k, optional w;
+        returns [(C, idx)] in the same order."""
+        arr = (Problem * len(problems))()
+        keep = []
+        for i, p in enumerate(problems):
+            X, k, w = p["X"], int(p["k"]), p.get("w")
+            n, d, ldx = _rows(X)
+            _vec(w, n)
+            C = torch.empty((k, d), dtype=torch.float32, device=X.device)
+            keep.append(C)
+            arr[i] = Problem(X.data_ptr(), n, d, ldx, w.data_ptr() if w is not None else None,
+                             C.data_ptr(), k, None)
+        ks = [int(p["k"]) for p in problems]
+        idx = torch.empty(sum(ks), dtype=torch.int64, device=problems[0]["X"].device)
+        seeds = (ctypes.c_uint64 * len(problems))(*[int(v) & (2 ** 64 - 1) for v in rng_seeds])
+        self._sync_stream()
+        _check(lib().kmx_seed_batched(self._p, arr, len(problems), seeds, _ptr(idx)), self._p)
+        out, o = [], 0
+        for C, k in zip(keep, ks):
+            out.append((C, idx[o:o + k]))
+            o += k
+        return out
 
     def batched_autotune(self, problems, cache_path=None, prec="bf16"):
         """Tile shapes for the batched assignment; returns True when read from the cache."""

@@ -116,3 +116,41 @@ def test_batched_autotuner(ctx, tmp_path):
     for e in lines:
         k_rep = {0: 10, 1: 50, 2: 150}[e["kclass"]]
         assert other.batched_tiles(e["d"], k_rep)[0] == e["tile"]
+
+
+def test_seed_batched_matches_oracle_and_single(ctx):
+    # k-means++ of uneven weighted instances in one batched call: every
+    # instance's indices equal the FP64 oracle's (oracle.kmeans.seed with the
+    # instance's own seed) and those of kmx_seed on it alone; the centers are
+    # exact copies of the chosen rows.  Instances include weights with zeros,
+    # no weights, n = k, k = 1, strided rows and d above the batched Lloyd's 512.
+    say("seed batched")
+    rng = np.random.default_rng(41)
+    shapes = [(1500, 16, 12, True), (3000, 40, 30, False), (777, 100, 7, True), (5, 3, 5, False),
+              (2100, 8, 1, True), (4200, 64, 25, True), (1200, 700, 4, False), (900, 33, 17, True)]
+    probs, host, seeds = [], [], []
+    for i, (n, d, k, weighted) in enumerate(shapes):
+        X, _ = synth.isotropic_mixture(n, d, max(k, 2), seed=100 + i)
+        w = synth.lognormal_weights(n, seed=100 + i) if weighted else None
+        if w is not None:
+            w[::4] = 0.0
+        Xd = _dev(X)
+        if i == 5:   # strided rows: a view into a wider buffer
+            wide = torch.zeros((n, d + 7), dtype=torch.float32, device="cuda:0")
+            wide[:, :d] = Xd
+            Xd = wide[:, :d]
+        probs.append({"X": Xd, "k": k, "w": None if w is None else _dev(w)})
+        host.append((X, w, k))
+        seeds.append(int(rng.integers(0, 2 ** 63)))
+    out = ctx.seed_batched(probs, seeds)
+    for i, ((C, idx), (X, w, k), sd) in enumerate(zip(out, host, seeds)):
+        _, idx_o, _ = ok.seed(X, w, k, sd)
+        got = idx.cpu().numpy().tolist()
+        assert got == idx_o.tolist(), (i, got, idx_o.tolist())
+        assert np.array_equal(C.cpu().numpy(), X[idx_o]), i
+        Cs, idx_s = ctx.seed(probs[i]["X"], k, w=probs[i]["w"], rng_seed=sd)
+        assert idx_s.cpu().numpy().tolist() == got, i
+    # a problem asking for more centers than rows of positive weight
+    bad = [{"X": probs[0]["X"], "k": 3, "w": torch.zeros(1500, device="cuda:0")}]
+    with pytest.raises(RuntimeError):
+        ctx.seed_batched(bad, [1])

@@ -37,6 +37,23 @@ hipError_t launch_batch_reset(hipStream_t s, const BatchInst* insts, int ninst, 
   return hipGetLastError();
 }
 
+// Per-bucket delta-update states: the change counts start every iteration
+// at zero; init also marks the carried features as not valid (a new call).
+__global__ void bucket_states_kernel(LoopState* __restrict__ bst, int nb, int init) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < nb) {
+    bst[b].dcount = 0;
+    bst[b].changed = 0;
+    if (init) bst[b].acc_valid = 0;
+  }
+}
+
+hipError_t launch_bucket_states(hipStream_t s, LoopState* bst, int nb, int init) {
+  hipLaunchKernelGGL(bucket_states_kernel, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s,
+                     bst, nb, init);
+  return hipGetLastError();
+}
+
 // Pass A, one wave per padded center of any instance (global padded index g,
 // instance cinst[g]): BF16 row of the center (zeros for padding), hd[g] =
 // ||c||^2 / 2 in FP64, norm maxima of the instance.

@@ -27,6 +27,7 @@ struct BucketPlan {
   int64_t n = 0, grow0 = 0;
   int64_t xoff = 0, xqoff = 0, coff = 0, cqoff = 0;   // offsets (elements) into bX, bXq, bC, bCq
   int kg0 = 0;
+  int64_t acc_off = 0;                               // carried features (int64) of the bucket
   std::vector<int> members;                          // internal instance indices
 };
 
@@ -43,6 +44,7 @@ struct Plan {
   int64_t N = 0, xsz = 0, xqsz = 0, csz = 0, cqsz = 0;
   int Ktot = 0, Ptot = 0;
   int64_t max_sort_counts = 0, max_n = 0, max_chunks_d = 0, max_chunks = 0;
+  int64_t acc_tot = 0;                                // int64 values of all buckets' features
   int max_K = 0;
   int gbegin[7] = {0, 0, 0, 0, 0, 0, 0};   // items of width group g: [gbegin[g], gbegin[g+1])
 };
@@ -177,6 +179,8 @@ void build_plan(const kmx_ctx* ctx, const kmx_problem* probs, int count,
       pl.max_chunks = std::max(pl.max_chunks, chunks);
       pl.max_chunks_d = std::max(pl.max_chunks_d, chunks * B.d);
       pl.max_K = std::max(pl.max_K, B.K);
+      B.acc_off = pl.acc_tot;
+      pl.acc_tot += (int64_t)B.K * B.d * 2 + 4 * (int64_t)B.K;
       pl.bk.push_back(B);
       a = b;
     }
@@ -246,6 +250,19 @@ kmx_status setup(kmx_ctx* ctx, const kmx_problem* probs, Plan& pl, int stride) {
   KMX_TRY(grow(ctx, ctx->bcf_qmax, (size_t)nb * sizeof(unsigned long long)));
   KMX_TRY(grow(ctx, ctx->bcf_wmax, (size_t)nb * sizeof(unsigned)));
   KMX_TRY(grow(ctx, ctx->bcfs, (size_t)nb * (2 * kBatchCfD + 4) * sizeof(double)));
+  // delta update: per-bucket states, previous labels and carried features;
+  // the mark / plan / scatter buffers are shared (the buckets run in order)
+  KMX_TRY(grow(ctx, ctx->bstate, (size_t)nb * sizeof(LoopState)));
+  KMX_TRY(grow(ctx, ctx->blab_prev, (size_t)pl.N * sizeof(int32_t)));
+  KMX_TRY(grow(ctx, ctx->bacc, (size_t)pl.acc_tot * sizeof(long long)));
+  KMX_TRY(grow(ctx, ctx->ecount, (size_t)(pl.max_K + 1) * sizeof(int32_t)));
+  KMX_TRY(grow(ctx, ctx->ebase, (size_t)(pl.max_K + 1) * sizeof(int32_t)));
+  KMX_TRY(grow(ctx, ctx->ecursor, (size_t)(pl.max_K + 1) * sizeof(int32_t)));
+  KMX_TRY(grow(ctx, ctx->dchunk, (size_t)(pl.max_K + 1) * sizeof(int32_t)));
+  KMX_TRY(grow(ctx, ctx->clist, (size_t)pl.max_n * sizeof(int32_t)));
+  KMX_TRY(grow(ctx, ctx->cold, (size_t)pl.max_n * sizeof(int32_t)));
+  KMX_TRY(grow(ctx, ctx->dent, (size_t)pl.max_n * sizeof(int32_t)));
+  KMX_TRY(grow(ctx, ctx->cfflag, 16));
 
   float* bX = P<float>(ctx->bX);
   float* bC = P<float>(ctx->bC);
@@ -317,6 +334,10 @@ kmx_status setup(kmx_ctx* ctx, const kmx_problem* probs, Plan& pl, int stride) {
                                   P<double>(ctx->bcfs) + (int64_t)b * (2 * kBatchCfD + 4),
                                   ctx->num_cus));
   }
+  // a new call: no carried features, every previous label unknown
+  KMX_HIP(ctx, launch_bucket_states(s, P<LoopState>(ctx->bstate), nb, 1));
+  KMX_HIP(ctx, launch_fill_i32(s, P<int32_t>(ctx->blab_prev), pl.N, -1));
+  KMX_HIP(ctx, launch_fill_i32(s, P<int32_t>(ctx->ecount), pl.max_K + 1, 0));
   return KMX_OK;
 }
 
@@ -330,6 +351,7 @@ hipError_t enqueue_iteration(kmx_ctx* ctx, const Plan& pl, hipStream_t s, int wr
   LoopState* st = ST(ctx);
   hipError_t e;
   if ((e = launch_batch_reset(s, insts, ni, st, nullptr)) != hipSuccess) return e;
+  if ((e = launch_bucket_states(s, P<LoopState>(ctx->bstate), nb, 0)) != hipSuccess) return e;
   if ((e = launch_batch_prep_centers(s, insts, P<int>(ctx->bcinst), pl.Ptot)) != hipSuccess)
     return e;
   if ((e = launch_groups(ctx, pl, s)) != hipSuccess) return e;
@@ -337,28 +359,49 @@ hipError_t enqueue_iteration(kmx_ctx* ctx, const Plan& pl, hipStream_t s, int wr
                                   P<int32_t>(ctx->blab), P<FlagEntry>(ctx->flags),
                                   P<int>(ctx->brute), st, pl.N, ctx->num_cus)) != hipSuccess)
     return e;
+  // per bucket: the delta plan (the rows whose label changed since the
+  // previous update, added to the carried features) or, on the first update
+  // of a call or when more than half of the rows changed, the full sort and
+  // reduction; both paths are decided on the device (flags), so the captured
+  // iteration replays either
+  int* flags = P<int>(ctx->cfflag);
   for (int b = 0; b < nb; ++b) {
     const BucketPlan& B = pl.bk[b];
     const int32_t* lab = P<int32_t>(ctx->blab) + B.grow0;
     float* Xb = P<float>(ctx->bX) + B.xoff;
     float* Cb = P<float>(ctx->bC) + B.coff;
+    LoopState* bst = P<LoopState>(ctx->bstate) + b;
+    const float* wb = P<float>(ctx->bw) + B.grow0;
+    const double* qb = P<double>(ctx->bcf_q) + B.grow0;
+    if ((e = launch_delta_prepare(s, lab, P<int32_t>(ctx->blab_prev) + B.grow0, B.n, B.K,
+                                  P<int32_t>(ctx->ecount), P<int32_t>(ctx->clist),
+                                  P<int32_t>(ctx->cold), P<int32_t>(ctx->ebase),
+                                  P<int32_t>(ctx->ecursor), P<int32_t>(ctx->dchunk),
+                                  P<int32_t>(ctx->dent), flags, bst, ctx->num_cus, nullptr)) !=
+        hipSuccess)
+      return e;
     if ((e = launch_sort(s, lab, nullptr, B.n, B.K, P<int32_t>(ctx->counts),
                          P<int32_t>(ctx->segsum), P<int32_t>(ctx->base),
-                         P<int32_t>(ctx->chunk_base), P<int32_t>(ctx->perm), st, 0, nullptr)) !=
+                         P<int32_t>(ctx->chunk_base), P<int32_t>(ctx->perm), st, 0, flags)) !=
         hipSuccess)
       return e;
     const double* cfs = P<double>(ctx->bcfs) + (int64_t)b * (2 * kBatchCfD + 4);
-    if ((e = launch_reduce(s, Xb, B.n, B.d, B.d, P<float>(ctx->bw) + B.grow0,
-                           P<double>(ctx->bcf_q) + B.grow0, P<int32_t>(ctx->perm),
+    if ((e = launch_reduce(s, Xb, B.n, B.d, B.d, wb, qb, P<int32_t>(ctx->perm),
                            P<int32_t>(ctx->base), P<int32_t>(ctx->chunk_base), B.K, cfs,
                            P<double>(ctx->partS), P<double>(ctx->partWQ), 0, ctx->num_cus,
-                           nullptr)) != hipSuccess)
+                           flags)) != hipSuccess)
+      return e;
+    if ((e = launch_reduce(s, Xb, B.n, B.d, B.d, wb, qb, P<int32_t>(ctx->dent),
+                           P<int32_t>(ctx->ebase), P<int32_t>(ctx->dchunk), B.K, cfs,
+                           P<double>(ctx->partS), P<double>(ctx->partWQ), 1, ctx->num_cus,
+                           flags + 1)) != hipSuccess)
       return e;
     if ((e = launch_finalize(s, P<double>(ctx->partS), P<double>(ctx->partWQ),
-                             P<int32_t>(ctx->chunk_base), nullptr, nullptr, nullptr, B.K, B.d, cfs,
-                             Cb, write_c ? Cb : nullptr, P<double>(ctx->bW) + B.kg0,
+                             P<int32_t>(ctx->chunk_base), P<int32_t>(ctx->dchunk), flags + 2,
+                             P<long long>(ctx->bacc) + B.acc_off, B.K, B.d, cfs, Cb,
+                             write_c ? Cb : nullptr, P<double>(ctx->bW) + B.kg0,
                              P<double>(ctx->btermC) + B.kg0, P<double>(ctx->btermMu) + B.kg0,
-                             write_c, nullptr, nullptr)) != hipSuccess)
+                             write_c, bst, nullptr)) != hipSuccess)
       return e;
   }
   return launch_batch_cost(s, insts, ni, P<double>(ctx->btermC), P<double>(ctx->bcost), stride,

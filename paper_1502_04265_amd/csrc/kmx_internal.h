@@ -223,6 +223,7 @@ struct kmx_ctx {
   kmx::Buf sv_om, sv_y, sv_y2, sv_z, sv_g, sv_part, sv_r, sv_v;   // range finder
   kmx::Buf bX, bXq, brs, bw, bC, bCq, bhd, bch, bcs, blab, bitems, binsts, bbuckets, bcinst, bxstats;
   kmx::Buf btermC, btermMu, bW, bcost;
+  kmx::Buf bstate, blab_prev, bacc;   // batched delta update: per-bucket states, labels, features
   kmx::Buf bcf_colmax, bcf_q, bcf_qmax, bcf_wmax, bcfs;   // per-bucket feature grids
   hipStream_t cap_stream = nullptr;                // stream graphs are captured on (batched, graphed Lloyd)
   uint64_t ws_gen = 0;                             // bumped whenever a workspace buffer moves
@@ -396,6 +397,8 @@ hipError_t launch_recheck_batched(hipStream_t s, const BatchBucket* buckets, int
                                   const BatchInst* insts, int ninst, int32_t* label,
                                   const FlagEntry* flags, const int* brute, const LoopState* st,
                                   int64_t nrows, int num_cus);
+// per-bucket delta-update states (dcount, changed; init: acc_valid too)
+hipError_t launch_bucket_states(hipStream_t s, LoopState* bst, int nb, int init);
 hipError_t launch_batch_reset(hipStream_t s, const BatchInst* insts, int ninst, LoopState* st,
                               unsigned* work_ctr);
 hipError_t launch_batch_prep_centers(hipStream_t s, const BatchInst* insts, const int* cinst,

@@ -143,6 +143,79 @@ def traffic_convert(fetch_dir, write_dir):
     return rec
 
 
+# ---------------------------------------------------------------------------
+# HBM traffic of the exact re-check on the headline path, from two counter
+# passes (FETCH_SIZE, then WRITE_SIZE) over
+#   bench.py --paths bounded_routed_fp8 --repeats 1 ...
+# with the kernel filter "reset_small_kernel|bounds_test_kernel|recheck_|
+# assign_kernel<2": every assignment begins with reset_small_kernel, so the
+# dispatches split into assignments; the bounded call is its first assignment
+# (the full-grid FP8 pass) followed by the run of assignments that hold a
+# bound test.  The counters are scaled by the copy calibration of the
+# assignment traffic record taken in the same session, and divided by the
+# entries the run's JSON line reports for that path:
+#   python bench.py --traffic-recheck <fetch_dir> <write_dir> <fetch_run_stdout> <out.json>
+# ---------------------------------------------------------------------------
+RECHECK_SOURCE = "paper_1502_04265_amd/csrc/k_recheck.hip"
+
+
+def _recheck_bytes(d):
+    rows = _traffic_rows(d)
+    rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+    segs, cur = [], None
+    for r in rows:
+        name = r["Kernel_Name"]
+        if "reset_small_kernel" in name:
+            cur = {"bounds": False, "kib": 0.0, "launches": 0}
+            segs.append(cur)
+        elif cur is not None:
+            if "bounds_test_kernel" in name:
+                cur["bounds"] = True
+            elif "recheck_" in name:
+                cur["kib"] += float(r["Counter_Value"])
+                cur["launches"] += 1
+    first = next(i for i, s in enumerate(segs) if s["bounds"])
+    last = first
+    while last + 1 < len(segs) and segs[last + 1]["bounds"]:
+        last += 1
+    call = segs[max(first - 1, 0):last + 1]
+    return sum(s["kib"] for s in call), len(call), sum(s["launches"] for s in call)
+
+
+def traffic_recheck_convert(fetch_dir, write_dir, run_stdout):
+    cal = json.load(open(os.path.join(ROOT, "profiles", "assign_traffic_n4m_d512_k1000.json")))
+    line = [l for l in open(run_stdout) if l.startswith("{")][-1]
+    rec = json.loads(line)
+    entries = rec["paths"]["bounded_routed_fp8"]["short_recheck_entries"]
+    d = rec["config"]["d"]
+    fk, nseg, nl = _recheck_bytes(fetch_dir)
+    wk, _, _ = _recheck_bytes(write_dir)
+    hbm = (fk * cal["fetch_factor"] + wk * cal["write_factor"]) * 1024.0
+    return {"kernel_source": RECHECK_SOURCE,
+            "kernel_source_sha256": hashlib.sha256(
+                open(os.path.join(ROOT, RECHECK_SOURCE), "rb").read()).hexdigest(),
+            "calibration": "fetch_factor / write_factor of assign_traffic_n4m_d512_k1000.json",
+            "fetch_kib": fk, "write_kib": wk, "assignments": nseg, "launches": nl,
+            "entries": entries, "hbm_bytes": hbm,
+            "hbm_bytes_per_entry": hbm / max(entries, 1),
+            "algorithmic_bytes_per_entry": 4.0 * d + 24}
+
+
+def measured_recheck_traffic(entries, steps):
+    """HBM bytes per step of the exact re-check from the committed counter
+    record (bytes per listed entry x entries per step); None once the kernel
+    source no longer matches the hash recorded with the counters."""
+    path = os.path.join(ROOT, "profiles", "recheck_traffic_n4m_d512_k1000.json")
+    try:
+        rec = json.load(open(path))
+        src = open(os.path.join(ROOT, rec["kernel_source"]), "rb").read()
+        if hashlib.sha256(src).hexdigest() != rec["kernel_source_sha256"]:
+            return None
+        return rec["hbm_bytes_per_entry"] * entries / steps
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def host_cpu():
     """Host CPU model and the threads the process may use."""
     model = None
@@ -753,6 +826,10 @@ def main():
     ap.add_argument("--traffic", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT_JSON"),
                     help="convert two rocprofv3 counter passes of --only assign into the traffic "
                          "record (no GPU)")
+    ap.add_argument("--traffic-recheck", nargs=4,
+                    metavar=("FETCH_DIR", "WRITE_DIR", "FETCH_RUN_STDOUT", "OUT_JSON"),
+                    help="convert two rocprofv3 counter passes of the headline path into the "
+                         "re-check traffic record (no GPU)")
     ap.add_argument("--paths", default=None,
                     help="profiling: comma-separated subset of the headline paths to run (the "
                          "full BF16 path always runs: the others are checked against it)")
@@ -772,6 +849,12 @@ def main():
     if args.traffic:
         rec = traffic_convert(args.traffic[0], args.traffic[1])
         json.dump(rec, open(args.traffic[2], "w"), indent=1)
+        print(json.dumps(rec, indent=1))
+        return
+    if args.traffic_recheck:
+        a = args.traffic_recheck
+        rec = traffic_recheck_convert(a[0], a[1], a[2])
+        json.dump(rec, open(a[3], "w"), indent=1)
         print(json.dumps(rec, indent=1))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -1037,7 +1120,9 @@ def main():
     sr_bytes = sr_entries * (4.0 * d + 24)
     sr_gbs = sr_bytes / (sr_ms_total * 1e-3) / 1e9 if sr_ms_total > 0 else 0.0
     short_roof = {"bound": "hbm", "achieved": sr_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                  "frac": sr_gbs / HBM_PEAK_GBS, "traffic": None,
+                  "frac": sr_gbs / HBM_PEAK_GBS,
+                  "traffic": (measured_recheck_traffic(sr_entries, args.steps)
+                              if args.workload == "router" else None),
                   "kernel": "recheck_pair_kernel + recheck_full_kernel (exact re-check of the "
                             "listed rows)",
                   "ms_per_step": sr_ms_total / args.steps, "entries": sr_entries,

@@ -113,12 +113,37 @@ inline const std::vector<int32_t>& kids_of(const Core& b, int32_t parent) {
 }
 
 // Closest reference among ids[from, to) (strictly closer replaces: the oldest
-// wins ties).
+// wins ties).  Eight references at a time: eight independent sums, each in
+// coordinate order as sq_dist takes it (the same bits), so the additions of
+// different references overlap instead of waiting on one chain.
 inline void scan(const Core& b, const std::vector<int32_t>& ids, size_t from, size_t to,
                  const float* x, int32_t& best, double& bd) {
-  for (size_t q = from; q < to; ++q) {
+  constexpr int L = 8;
+  const int d = b.d;
+  size_t q = from;
+  for (; q + L <= to; q += L) {
+    const float* r[L];
+    double s[L];
+    for (int i = 0; i < L; ++i) {
+      r[i] = &b.ref[(size_t)ids[q + i] * d];
+      s[i] = 0.0;
+    }
+    for (int j = 0; j < d; ++j) {
+      const double xj = (double)x[j];
+      for (int i = 0; i < L; ++i) {
+        const double t = xj - (double)r[i][j];
+        s[i] += t * t;
+      }
+    }
+    for (int i = 0; i < L; ++i)
+      if (best < 0 || s[i] < bd) {
+        best = ids[q + i];
+        bd = s[i];
+      }
+  }
+  for (; q < to; ++q) {
     const int32_t id = ids[q];
-    const double dd = sq_dist(x, &b.ref[(size_t)id * b.d], b.d);
+    const double dd = sq_dist(x, &b.ref[(size_t)id * d], d);
     if (best < 0 || dd < bd) {
       best = id;
       bd = dd;

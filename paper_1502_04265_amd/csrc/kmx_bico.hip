@@ -41,12 +41,12 @@ struct kmx_bico {
   std::vector<NodeRefs> refs;   // cached child lists, valid for one tree
   int64_t refs_rebuilds = -1;   // rebuild count the cache belongs to
   Buf dlab, dd1, dd2, dq;       // query results and a staging block
-  int64_t block = 1024;         // points per device query (adapted)
+  int64_t block = 1024;         // points per device query (adapted, 512 to 8192)
 };
 
 namespace {
 
-constexpr int64_t kBicoMinBlock = 64, kBicoMaxBlock = 8192;
+constexpr int64_t kBicoMinBlock = 512, kBicoMaxBlock = 8192;
 constexpr int64_t kRebuildBlock = 256;
 
 // The device copy of `node`'s children, uploading what was added since the

@@ -29,6 +29,8 @@
 #include <cstring>
 #include <vector>
 
+#include <immintrin.h>
+
 #pragma clang fp contract(off)
 
 namespace kmx {
@@ -112,6 +114,61 @@ inline const std::vector<int32_t>& kids_of(const Core& b, int32_t parent) {
   return parent < 0 ? b.roots : b.f[parent].kids;
 }
 
+// Squared distances of x (as doubles, xd) to eight references, each summed
+// in coordinate order exactly as sq_dist sums it: t = x_j - r_j and t * t
+// rounded as in the scalar code, the squares of four coordinates of four
+// references transposed so that each lane of an accumulator adds its own
+// reference's squares one coordinate after another (the same bits; only the
+// additions of different references overlap).  Host x86 with AVX2.
+__attribute__((target("avx2"))) inline void dist8_avx2(const double* xd, const float* const* r,
+                                                       int d, double* out) {
+  __m256d acc0 = _mm256_setzero_pd(), acc1 = _mm256_setzero_pd();
+  int j = 0;
+  for (; j + 4 <= d; j += 4) {
+    const __m256d xv = _mm256_loadu_pd(xd + j);
+    __m256d q[8];
+    for (int i = 0; i < 8; ++i) {
+      const __m256d t = _mm256_sub_pd(xv, _mm256_cvtps_pd(_mm_loadu_ps(r[i] + j)));
+      q[i] = _mm256_mul_pd(t, t);
+    }
+    for (int h = 0; h < 2; ++h) {
+      // rows q[4h + i] = squares of reference 4h + i at coordinates j .. j + 3
+      const __m256d a = q[4 * h], b = q[4 * h + 1], c = q[4 * h + 2], e = q[4 * h + 3];
+      const __m256d ab_lo = _mm256_unpacklo_pd(a, b);   // a0 b0 a2 b2
+      const __m256d ab_hi = _mm256_unpackhi_pd(a, b);   // a1 b1 a3 b3
+      const __m256d ce_lo = _mm256_unpacklo_pd(c, e);   // c0 e0 c2 e2
+      const __m256d ce_hi = _mm256_unpackhi_pd(c, e);   // c1 e1 c3 e3
+      const __m256d c0 = _mm256_permute2f128_pd(ab_lo, ce_lo, 0x20);   // a0 b0 c0 e0
+      const __m256d c1 = _mm256_permute2f128_pd(ab_hi, ce_hi, 0x20);   // a1 b1 c1 e1
+      const __m256d c2 = _mm256_permute2f128_pd(ab_lo, ce_lo, 0x31);   // a2 b2 c2 e2
+      const __m256d c3 = _mm256_permute2f128_pd(ab_hi, ce_hi, 0x31);   // a3 b3 c3 e3
+      __m256d& acc = h ? acc1 : acc0;
+      acc = _mm256_add_pd(acc, c0);
+      acc = _mm256_add_pd(acc, c1);
+      acc = _mm256_add_pd(acc, c2);
+      acc = _mm256_add_pd(acc, c3);
+    }
+  }
+  _mm256_storeu_pd(out, acc0);
+  _mm256_storeu_pd(out + 4, acc1);
+  for (; j < d; ++j)
+    for (int i = 0; i < 8; ++i) {
+      const double t = xd[j] - (double)r[i][j];
+      out[i] += t * t;
+    }
+}
+
+// Whether the scans take dist8_avx2 (KMX_BICO_SCALAR_SCAN: never, so that a
+// test build covers the portable loop, which gives the same bits).
+inline bool host_avx2() {
+#ifdef KMX_BICO_SCALAR_SCAN
+  return false;
+#else
+  static const bool ok = __builtin_cpu_supports("avx2");
+  return ok;
+#endif
+}
+
 // Closest reference among ids[from, to) (strictly closer replaces: the oldest
 // wins ties).  Eight references at a time: eight independent sums, each in
 // coordinate order as sq_dist takes it (the same bits), so the additions of
@@ -121,25 +178,32 @@ inline void scan(const Core& b, const std::vector<int32_t>& ids, size_t from, si
   constexpr int L = 8;
   const int d = b.d;
   size_t q = from;
-  for (; q + L <= to; q += L) {
-    const float* r[L];
-    double s[L];
-    for (int i = 0; i < L; ++i) {
-      r[i] = &b.ref[(size_t)ids[q + i] * d];
-      s[i] = 0.0;
-    }
-    for (int j = 0; j < d; ++j) {
-      const double xj = (double)x[j];
-      for (int i = 0; i < L; ++i) {
-        const double t = xj - (double)r[i][j];
-        s[i] += t * t;
+  if (to >= from + L) {
+    const bool avx2 = host_avx2();
+    std::vector<double> xd(avx2 ? d : 0);
+    for (int j = 0; j < (int)xd.size(); ++j) xd[j] = (double)x[j];
+    for (; q + L <= to; q += L) {
+      const float* r[L];
+      double s[L];
+      for (int i = 0; i < L; ++i) r[i] = &b.ref[(size_t)ids[q + i] * d];
+      if (avx2) {
+        dist8_avx2(xd.data(), r, d, s);
+      } else {
+        for (int i = 0; i < L; ++i) s[i] = 0.0;
+        for (int j = 0; j < d; ++j) {
+          const double xj = (double)x[j];
+          for (int i = 0; i < L; ++i) {
+            const double t = xj - (double)r[i][j];
+            s[i] += t * t;
+          }
+        }
       }
+      for (int i = 0; i < L; ++i)
+        if (best < 0 || s[i] < bd) {
+          best = ids[q + i];
+          bd = s[i];
+        }
     }
-    for (int i = 0; i < L; ++i)
-      if (best < 0 || s[i] < bd) {
-        best = ids[q + i];
-        bd = s[i];
-      }
   }
   for (; q < to; ++q) {
     const int32_t id = ids[q];

@@ -19,7 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 
 
-def _build(tmp_path_factory, big_kids):
+def _build(tmp_path_factory, big_kids, scalar_scan=False):
     gxx = shutil.which("g++")
     if gxx is None:
         pytest.skip("no g++")
@@ -27,6 +27,7 @@ def _build(tmp_path_factory, big_kids):
     cmd = [gxx, "-std=c++17", "-O1", "-g", "-ffp-contract=off", "-Wno-unknown-pragmas",
            "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
            f"-DKMX_BICO_BIG_KIDS={big_kids}",
+           *(["-DKMX_BICO_SCALAR_SCAN"] if scalar_scan else []),
            "-I", os.path.join(ROOT, "paper_1502_04265_amd", "csrc"),
            os.path.join(HERE, "bico_host_main.cpp"), "-o", exe]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -38,6 +39,12 @@ def _build(tmp_path_factory, big_kids):
 @pytest.fixture(scope="module")
 def harness(tmp_path_factory):
     return _build(tmp_path_factory, 32)
+
+
+@pytest.fixture(scope="module")
+def harness_scalar(tmp_path_factory):
+    # the portable scan loop (the default build takes AVX2 where the host has it)
+    return _build(tmp_path_factory, 32, scalar_scan=True)
 
 
 @pytest.fixture(scope="module")
@@ -76,10 +83,22 @@ def _mixture(n, d, seed, sigma):
     return (means[rng.integers(0, 8, n)] + sigma * rng.normal(size=(n, d))).astype(np.float32)
 
 
-@pytest.mark.parametrize("n,d,m,T0,block,wkind,sigma", [
-    (2000, 6, 50, 1e-3, 64, None, 1.0), (1500, 4, 30, 0.5, 33, "int", 0.05),
-    (1200, 17, 80, 1e-2, 128, "lognormal", 0.5), (900, 3, 120, 1e-2, 5, "zeros", 0.3)])
+CASES = [(2000, 6, 50, 1e-3, 64, None, 1.0), (1500, 4, 30, 0.5, 33, "int", 0.05),
+         (1200, 17, 80, 1e-2, 128, "lognormal", 0.5), (900, 3, 120, 1e-2, 5, "zeros", 0.3)]
+
+
+@pytest.mark.parametrize("n,d,m,T0,block,wkind,sigma", CASES)
 def test_host_bico_matches_oracle(harness, tmp_path, n, d, m, T0, block, wkind, sigma):
+    _check_case(harness, tmp_path, n, d, m, T0, block, wkind, sigma)
+
+
+@pytest.mark.parametrize("n,d,m,T0,block,wkind,sigma", CASES[:3])
+def test_host_bico_scalar_scan_matches_oracle(harness_scalar, tmp_path, n, d, m, T0, block,
+                                              wkind, sigma):
+    _check_case(harness_scalar, tmp_path, n, d, m, T0, block, wkind, sigma)
+
+
+def _check_case(harness, tmp_path, n, d, m, T0, block, wkind, sigma):
     X = _mixture(n, d, n + d, sigma)
     rng = np.random.default_rng(d)
     w = None

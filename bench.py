@@ -455,6 +455,9 @@ def batched_main(args):
                      "algorithmic_bytes": it_bytes},
         "assign_flops_per_iteration": flops,
         "whole_iteration_tflops": flops / (wall / args.steps) / 1e12,
+        "prepared_inputs": "the timed call reuses the grouped rows, weights and row statistics "
+                           "the warm-up call made for the same problems (one by one, each call "
+                           "prepares its own copy: the context keeps one X)",
         "tiles": tiles, "seed_s": seed_s, "seed_one_by_one_s": seed_single_s,
         "seed_identical_to_one_by_one": seed_same, "autotune_s": tune_s,
     }

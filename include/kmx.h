@@ -333,7 +333,11 @@ typedef struct {
  *   prec      KMX_BF16.
  *   cost_hist host, count x (iters + 1) doubles, row i = problem i:
  *             cost_hist[i][t] = cost of problem i at C_t.
- * Synchronizes.  Inputs are copied once per call into a grouped layout. */
+ * Synchronizes.  X and w are copied into a grouped layout (with their row
+ * statistics and feature grids) when the problems differ from those of the
+ * previous batched call on ctx (X and w pointers, sizes, order); otherwise
+ * those copies are reused, so call kmx_invalidate after changing the contents
+ * of any X or w.  C is read on every call. */
 kmx_status kmx_lloyd_batched(kmx_ctx* ctx, const kmx_problem* probs, int32_t count,
                              int32_t iters, kmx_prec prec, double* cost_hist);
 

@@ -524,6 +524,7 @@ kmx_status kmx_invalidate(kmx_ctx* ctx, const float* X) {
   if (X == nullptr || ctx->cache_X == X) ctx->cache_valid = false;
   if (X == nullptr || ctx->cache8_X == X) ctx->cache8_valid = false;
   if (X == nullptr || ctx->cf_X == X) ctx->cf_valid = false;
+  ctx->batch_key.clear();   // the batched path's grouped copies of any problem
   return KMX_OK;
 }
 

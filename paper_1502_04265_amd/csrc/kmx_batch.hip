@@ -294,6 +294,29 @@ kmx_status setup(kmx_ctx* ctx, const kmx_problem* probs, Plan& pl, int stride) {
     I.C = bC + B.coff;
     I.xq_max = xst + I.bucket;
   }
+  // The grouped rows, weights, row statistics and feature grids depend only
+  // on the problems' X and w (pointers, sizes; contents as the caller
+  // promises until kmx_invalidate) and on the layout: a call with the same
+  // key as the previous one reuses them.
+  std::vector<int64_t> key;
+  key.push_back(ni);
+  key.push_back(nb);
+  for (int b = 0; b < nb; ++b) {
+    const BucketPlan& B = pl.bk[b];
+    for (int64_t v : {(int64_t)B.d, (int64_t)B.dp, B.n, B.grow0, B.xoff, B.xqoff}) key.push_back(v);
+  }
+  for (int i = 0; i < ni; ++i) {
+    const BatchInst& I = pl.insts[i];
+    const kmx_problem& q = probs[pl.user_of[i]];
+    for (int64_t v : {(int64_t)(uintptr_t)q.X, q.n, (int64_t)q.d, q.ldx, (int64_t)(uintptr_t)q.w,
+                      (int64_t)I.bucket, I.row0, I.grow0})
+      key.push_back(v);
+  }
+  for (const Buf* b : {&ctx->bX, &ctx->bXq, &ctx->brs, &ctx->bw, &ctx->bxstats, &ctx->bcf_colmax,
+                       &ctx->bcf_q, &ctx->bcf_qmax, &ctx->bcf_wmax, &ctx->bcfs})
+    key.push_back((int64_t)(uintptr_t)b->p);
+  const bool reuse = (key == ctx->batch_key);
+  ctx->batch_key.clear();   // set again once the buffers hold these problems
   hipStream_t s = ctx->stream;
   KMX_HIP(ctx, hipMemcpy(ctx->binsts.p, pl.insts.data(), (size_t)ni * sizeof(BatchInst),
                          hipMemcpyHostToDevice));
@@ -307,19 +330,22 @@ kmx_status setup(kmx_ctx* ctx, const kmx_problem* probs, Plan& pl, int stride) {
     const BatchInst& I = pl.insts[i];
     const BucketPlan& B = pl.bk[I.bucket];
     const kmx_problem& q = probs[pl.user_of[i]];
-    KMX_HIP(ctx, hipMemcpy2DAsync(bX + B.xoff + I.row0 * I.d, (size_t)I.d * sizeof(float), q.X,
-                                  (size_t)q.ldx * sizeof(float), (size_t)I.d * sizeof(float),
-                                  (size_t)I.n, hipMemcpyDeviceToDevice, s));
-    float* w = P<float>(ctx->bw) + I.grow0;
-    if (q.w)
-      KMX_HIP(ctx, hipMemcpyAsync(w, q.w, (size_t)I.n * sizeof(float), hipMemcpyDeviceToDevice, s));
-    else
-      KMX_HIP(ctx, launch_fill_i32(s, (int32_t*)w, I.n, 0x3F800000));   // 1.0f
+    if (!reuse) {
+      KMX_HIP(ctx, hipMemcpy2DAsync(bX + B.xoff + I.row0 * I.d, (size_t)I.d * sizeof(float), q.X,
+                                    (size_t)q.ldx * sizeof(float), (size_t)I.d * sizeof(float),
+                                    (size_t)I.n, hipMemcpyDeviceToDevice, s));
+      float* w = P<float>(ctx->bw) + I.grow0;
+      if (q.w)
+        KMX_HIP(ctx, hipMemcpyAsync(w, q.w, (size_t)I.n * sizeof(float), hipMemcpyDeviceToDevice,
+                                    s));
+      else
+        KMX_HIP(ctx, launch_fill_i32(s, (int32_t*)w, I.n, 0x3F800000));   // 1.0f
+    }
     KMX_HIP(ctx, hipMemcpyAsync(bC + B.coff + (int64_t)I.koff * I.d, q.C,
                                 (size_t)I.k * I.d * sizeof(float), hipMemcpyDeviceToDevice, s));
   }
-  KMX_HIP(ctx, launch_fill_i32(s, (int32_t*)xst, nb, 0));
-  for (int b = 0; b < nb; ++b) {
+  if (!reuse) KMX_HIP(ctx, launch_fill_i32(s, (int32_t*)xst, nb, 0));
+  for (int b = 0; b < nb && !reuse; ++b) {
     const BucketPlan& B = pl.bk[b];
     Timed tm(ctx, T_PREP);
     KMX_HIP(ctx, launch_prep_rows(s, bX + B.xoff, B.n, B.d, B.d, B.dp, bXq + B.xqoff,
@@ -338,6 +364,7 @@ kmx_status setup(kmx_ctx* ctx, const kmx_problem* probs, Plan& pl, int stride) {
   KMX_HIP(ctx, launch_bucket_states(s, P<LoopState>(ctx->bstate), nb, 1));
   KMX_HIP(ctx, launch_fill_i32(s, P<int32_t>(ctx->blab_prev), pl.N, -1));
   KMX_HIP(ctx, launch_fill_i32(s, P<int32_t>(ctx->ecount), pl.max_K + 1, 0));
+  ctx->batch_key = std::move(key);
   return KMX_OK;
 }
 

@@ -180,6 +180,9 @@ struct kmx_ctx {
   bool validate = false;   // KMX_VALIDATE=1: scan X and C for non-finite values
   void* na_scratch = nullptr;   // device address of this device's static scratch array
   std::string err;
+  // the problems whose rows, weights, row statistics and feature grids the
+  // batched path's grouped buffers hold (empty: none; kmx_invalidate clears)
+  std::vector<int64_t> batch_key;
 
   // cached per-dataset data
   const float* cache_X = nullptr;

@@ -62,6 +62,32 @@ def test_batched_matches_single_runs(ctx):
         np.testing.assert_allclose(histb, hist, rtol=1e-12, err_msg=str(i))
 
 
+def test_batched_reuses_grouped_copies_until_invalidated(ctx):
+    # a second call on the same problems reuses the grouped rows, weights and
+    # row statistics; after new contents at the same addresses and
+    # kmx_invalidate, the results are those of a fresh context
+    from paper_1502_04265_amd import kmx
+    iters = 3
+    descs, probs = _instances(ctx, 8, seed=5)
+    r1 = ctx.lloyd_batched(probs, iters)
+    r2 = ctx.lloyd_batched(probs, iters)
+    for a, b in zip(r1, r2):
+        assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+        np.testing.assert_array_equal(a[2], b[2])
+    for p in probs:
+        p["X"].mul_(1.5)
+        p["w"].add_(0.25)
+    ctx.invalidate()
+    r3 = ctx.lloyd_batched(probs, iters)
+    r4 = kmx.Context(0).lloyd_batched(probs, iters)
+    changed = 0
+    for a, b, c in zip(r3, r4, r1):
+        assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+        np.testing.assert_array_equal(a[2], b[2])
+        changed += int(not torch.equal(a[0], c[0]))
+    assert changed == len(probs)
+
+
 def test_batched_matches_oracle(ctx):
     iters = 4
     descs, probs = _instances(ctx, 6, seed=2, n_range=(300, 3000), k_range=(3, 40))

@@ -80,7 +80,9 @@ typedef enum {
 kmx_status kmx_create(kmx_ctx** out, int device, void* hip_stream);
 kmx_status kmx_destroy(kmx_ctx* ctx);
 kmx_status kmx_set_stream(kmx_ctx* ctx, void* hip_stream);
-/* Drop cached derived data of X (call after X's contents change). */
+/* Drop cached derived data of X (call after X's contents change; X == NULL:
+ * of every X).  Every call also drops the grouped copies of the batched
+ * path (call it after changing any batched problem's X or w). */
 kmx_status kmx_invalidate(kmx_ctx* ctx, const float* X);
 /* Message of the last failed call on ctx ("" if none).  Valid until the next
  * call on ctx.  kmx_last_error(NULL) reports failures of kmx_create. */

@@ -340,6 +340,9 @@ class Context:
             n, d, ldx = _rows(X)
             k = _centers(C0, d)
             _vec(w, n)
+            self._fresh(X)
+            if w is not None:
+                self._fresh(w)
             C = C0 if inplace else C0.clone()
             lab = torch.empty(n, dtype=torch.int32, device=X.device) if labels else None
             keep.append((C, lab))

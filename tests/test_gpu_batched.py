@@ -64,8 +64,9 @@ def test_batched_matches_single_runs(ctx):
 
 def test_batched_reuses_grouped_copies_until_invalidated(ctx):
     # a second call on the same problems reuses the grouped rows, weights and
-    # row statistics; after new contents at the same addresses and
-    # kmx_invalidate, the results are those of a fresh context
+    # row statistics; after new contents at the same addresses (which the
+    # binding notices from the tensors' version counters and reports with
+    # kmx_invalidate), the results are those of a fresh context
     from paper_1502_04265_amd import kmx
     iters = 3
     descs, probs = _instances(ctx, 8, seed=5)
@@ -77,7 +78,6 @@ def test_batched_reuses_grouped_copies_until_invalidated(ctx):
     for p in probs:
         p["X"].mul_(1.5)
         p["w"].add_(0.25)
-    ctx.invalidate()
     r3 = ctx.lloyd_batched(probs, iters)
     r4 = kmx.Context(0).lloyd_batched(probs, iters)
     changed = 0
